@@ -1,0 +1,471 @@
+"""Two-level overlapping Schwarz preconditioner M_EH+Rot (and M_EH).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Everything here works on the free degrees of freedom F (the complement of
+the clamped set Gamma_D): the state system is K_FF u_F = f_F.
+
+Readings taken where the paper is silent or garbled (each is listed with its
+justification in the design notes of the repository):
+
+* overlapping subdomains (Section 2): box mode extends each coarse block
+  D_i by ``overlap`` element layers in the max-norm, clipped to the mesh;
+  vertex mode uses the coarse neighbourhoods omega_l of the coarse nodes
+  that are not clamped (the paper's experiments).  R_i selects the free DOFs
+  of the nodes strictly inside D'_i, plus nodes on the physical boundary
+  inside its closure, so K_i = R_i K R_i^T is the principal submatrix;
+* partition of unity chi_l: the coarse bilinear / trilinear hat functions;
+* heat eigenproblem (Section 4.1): -div(kappa grad psi) = lambda kappa psi
+  on omega_l with kappa = E, Neumann on the boundary of omega_l except at
+  clamped nodes, which are removed; consistent kappa-weighted mass matrix;
+* automatic threshold: keep lambda with lambda * H^2 < tau in ascending
+  order, at most kmax of them, H the coarse block edge (longest axis);
+* rotation enrichment (Section 4.2): add chi_l times each infinitesimal
+  rotation about the coarse node (1 in 2D, 3 in 3D, scaled by 1/H) when the
+  neighbourhood selected at least one heat mode; clamped DOFs are zeroed.
+"""
+from __future__ import annotations
+
+import dataclasses
+import itertools
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .fem import assemble_scalar, assemble_stiffness, heat_element, simp_modulus
+
+# omega with at most this many nodes is solved with a dense LAPACK eigh
+DENSE_EIG_MAX = 1600
+
+
+# --------------------------------------------------------------------------
+# geometry
+# --------------------------------------------------------------------------
+
+def _blocks_per_axis(desc):
+    nb = []
+    for n, s in zip(desc["nel"], desc["sub_nel"]):
+        if s <= 0 or n % s:
+            raise ValueError("mesh size must be a multiple of the block size")
+        nb.append(n // s)
+    return nb
+
+
+def coarse_node_grid(desc):
+    """Multi-indices of the coarse nodes (block corners), x fastest."""
+    nb = _blocks_per_axis(desc)
+    ranges = [range(b + 1) for b in nb]
+    return [tuple(reversed(t)) for t in itertools.product(*reversed(ranges))]
+
+
+def _node_box_from_elements(e_lo, e_hi, nel):
+    """Included node range [lo, hi] for the element range [e_lo, e_hi):
+    strictly interior nodes plus nodes on the physical boundary."""
+    lo = e_lo if e_lo == 0 else e_lo + 1
+    hi = e_hi if e_hi == nel else e_hi - 1
+    return lo, hi
+
+
+def _node_ids_of_box(desc, box):
+    nel = desc["nel"]
+    axes = [np.arange(lo, hi + 1) for lo, hi in box]
+    g = np.meshgrid(*axes, indexing="ij")
+    flat = [np.ascontiguousarray(a.transpose()).ravel() for a in g]
+    ids = np.zeros_like(flat[0])
+    stride = 1
+    for d in range(desc["dim"]):
+        ids += flat[d] * stride
+        stride *= nel[d] + 1
+    return ids, flat
+
+
+def _node_is_clamped(desc, fixed, ijk):
+    dim = desc["dim"]
+    nel = desc["nel"]
+    p = 0
+    stride = 1
+    for d in range(dim):
+        p += ijk[d] * stride
+        stride *= nel[d] + 1
+    return bool(np.all(fixed[dim * p:dim * p + dim] == 1))
+
+
+def subdomain_node_boxes(desc, fixed):
+    """Inclusive node boxes of the overlapping subdomains D'_i (Section 2)."""
+    dim = desc["dim"]
+    nel = desc["nel"]
+    S = desc["sub_nel"]
+    nb = _blocks_per_axis(desc)
+    delta = desc["overlap"]
+    boxes = []
+    if desc["sub_mode"] == 0:
+        for b in itertools.product(*[range(v) for v in reversed(nb)]):
+            b = tuple(reversed(b))
+            box = []
+            for d in range(dim):
+                e_lo = max(0, b[d] * S[d] - delta)
+                e_hi = min(nel[d], (b[d] + 1) * S[d] + delta)
+                box.append(_node_box_from_elements(e_lo, e_hi, nel[d]))
+            boxes.append(tuple(box))
+    else:
+        for c in coarse_node_grid(desc):
+            pos = tuple(c[d] * S[d] for d in range(dim))
+            if _node_is_clamped(desc, fixed, pos):
+                continue
+            box = []
+            for d in range(dim):
+                e_lo = max(0, (c[d] - 1) * S[d])
+                e_hi = min(nel[d], (c[d] + 1) * S[d])
+                box.append(_node_box_from_elements(e_lo, e_hi, nel[d]))
+            boxes.append(tuple(box))
+    return boxes
+
+
+def neighbourhood(desc, c):
+    """omega_l of coarse node ``c``: (element box, closed node box)."""
+    nel = desc["nel"]
+    S = desc["sub_nel"]
+    ebox, nbox = [], []
+    for d in range(desc["dim"]):
+        e_lo = max(0, (c[d] - 1) * S[d])
+        e_hi = min(nel[d], (c[d] + 1) * S[d])
+        ebox.append((e_lo, e_hi))
+        nbox.append((e_lo, e_hi))
+    return tuple(ebox), tuple(nbox)
+
+
+def partition_of_unity(desc, c, node_xyz):
+    """chi_l: coarse multilinear hat of coarse node ``c`` at integer node
+    coordinates ``node_xyz`` (list of per-axis arrays)."""
+    S = desc["sub_nel"]
+    chi = np.ones_like(node_xyz[0], dtype=np.float64)
+    for d in range(desc["dim"]):
+        chi *= np.maximum(0.0, 1.0 - np.abs(node_xyz[d] - c[d] * S[d]) / S[d])
+    return chi
+
+
+def coarse_H(desc):
+    return max(desc["sub_nel"]) * desc["h"]
+
+
+# --------------------------------------------------------------------------
+# heat eigenproblems and the automatic threshold
+# --------------------------------------------------------------------------
+
+def heat_pencil(desc, E, c, dirichlet_nodes=None):
+    """(A_l, M_l, node ids) of the heat pencil on omega_l (Section 4.1).
+
+    A_l = sum_e E_e int grad N grad N, M_l = sum_e E_e int N N over the
+    elements of omega_l; nodes listed in ``dirichlet_nodes`` (global ids)
+    are removed.  Returned node ids are global, in omega's x-fastest order.
+    """
+    dim = desc["dim"]
+    nel = desc["nel"]
+    ebox, nbox = neighbourhood(desc, c)
+    Ae, Me = heat_element(dim, desc["h"])
+    node_ids, _ = _node_ids_of_box(desc, nbox)
+    shape = [hi - lo + 1 for lo, hi in nbox]
+    # local element -> local node map
+    eaxes = [np.arange(lo, hi) for lo, hi in ebox]
+    g = np.meshgrid(*eaxes, indexing="ij")
+    ecoord = [np.ascontiguousarray(a.transpose()).ravel() for a in g]
+    estride = [1]
+    for d in range(dim - 1):
+        estride.append(estride[-1] * nel[d])
+    eid = sum(ecoord[d] * estride[d] for d in range(dim))
+    lstride = [1]
+    for d in range(dim - 1):
+        lstride.append(lstride[-1] * shape[d])
+    lbase = sum((ecoord[d] - nbox[d][0]) * lstride[d] for d in range(dim))
+    loc = np.empty((len(eid), 2 ** dim), dtype=np.int64)
+    for a in range(2 ** dim):
+        loc[:, a] = lbase + sum(((a >> d) & 1) * lstride[d] for d in range(dim))
+    kappa = np.asarray(E)[eid]
+    n = len(node_ids)
+    A = assemble_scalar(loc, kappa, Ae, n)
+    M = assemble_scalar(loc, kappa, Me, n)
+    keep = np.ones(n, dtype=bool)
+    if dirichlet_nodes is not None and len(dirichlet_nodes):
+        keep &= ~np.isin(node_ids, dirichlet_nodes)
+    idx = np.nonzero(keep)[0]
+    return A[idx][:, idx].tocsc(), M[idx][:, idx].tocsc(), node_ids[idx]
+
+
+@dataclasses.dataclass
+class HeatModes:
+    lam: np.ndarray        # selected eigenvalues, ascending
+    vecs: np.ndarray       # (n, k) M-orthonormal eigenvectors
+    lam_seen: np.ndarray   # all eigenvalues computed (ascending)
+    cap_hit: bool          # more than kmax eigenvalues lie below threshold
+
+
+def heat_modes(A, M, tau, H, kmax):
+    """Eigenpairs of A psi = lambda M psi with lambda * H^2 < tau, ascending,
+    at most kmax (the automatic threshold of Sections 2.1 and 4.1).
+
+    Small pencils use LAPACK's dense symmetric-definite solver; larger ones
+    use ARPACK in shift-invert mode about a point just below zero for the
+    kmax + 1 eigenvalues of smallest magnitude, which is enough to decide
+    both the selection and whether the cap was hit.
+    """
+    n = A.shape[0]
+    if n == 0:
+        return HeatModes(np.zeros(0), np.zeros((0, 0)), np.zeros(0), False)
+    lim = tau / (H * H)
+    if n <= DENSE_EIG_MAX:
+        lam, vec = sla.eigh(A.toarray(), M.toarray())
+    else:
+        k = min(kmax + 1, n - 1)
+        sigma = -1e-3 / (H * H)
+        rng = np.random.default_rng(12345)
+        lam, vec = spla.eigsh(A, k=k, M=M, sigma=sigma, which="LM", tol=0.0,
+                              v0=rng.standard_normal(n), maxiter=100000)
+        order = np.argsort(lam)
+        lam, vec = lam[order], vec[:, order]
+    below = np.nonzero(lam < lim)[0]
+    cap_hit = len(below) > kmax
+    sel = below[:kmax]
+    vec = vec[:, sel]
+    # M-orthonormalise (eigh / eigsh already are, up to rounding)
+    if vec.shape[1]:
+        G = vec.T @ (M @ vec)
+        L = np.linalg.cholesky(0.5 * (G + G.T))
+        vec = np.linalg.solve(L, vec.T).T
+    return HeatModes(lam[sel], vec, lam, cap_hit)
+
+
+def _rotations(desc, c, node_flat):
+    """Infinitesimal rotations about coarse node ``c`` scaled by 1/H, as a
+    list of (n_nodes, dim) arrays (rigid body rotations of Section 2.1)."""
+    dim = desc["dim"]
+    S = desc["sub_nel"]
+    h = desc["h"]
+    H = coarse_H(desc)
+    rel = [(node_flat[d] - c[d] * S[d]) * h / H for d in range(dim)]
+    z = np.zeros_like(rel[0])
+    if dim == 2:
+        return [np.stack([-rel[1], rel[0]], axis=1)]
+    x, y, w = rel
+    return [np.stack([z, -w, y], axis=1), np.stack([w, z, -x], axis=1),
+            np.stack([-y, x, z], axis=1)]
+
+
+@dataclasses.dataclass
+class CoarseSpace:
+    Phi: sp.csc_matrix            # (n, N_c) coarse basis on all DOFs
+    n_modes: np.ndarray           # (n_coarse_nodes, dim) selected heat modes
+    n_rot: np.ndarray             # (n_coarse_nodes,) rotation columns added
+    eigvals: list                 # per coarse node: list over components
+    lam_seen: list                # per coarse node: list over components
+    cap_hits: int
+    coarse_nodes: list
+
+
+def build_coarse_basis(desc, E, fixed, rot=None):
+    """R_0^T = [Phi_1 ... Phi_Nc] of M_EH(+Rot) (Sections 2.1, 4.1, 4.2).
+
+    Column order: coarse nodes x-fastest; per node, for each component c the
+    selected heat modes chi_l psi_j e_c in ascending eigenvalue order, then
+    the rotations chi_l r_k.
+    """
+    dim = desc["dim"]
+    rot = desc["rot_enrich"] if rot is None else rot
+    H = coarse_H(desc)
+    tau, kmax = desc["eig_tau"], desc["eig_kmax"]
+    n = len(fixed)
+    nodes = coarse_node_grid(desc)
+    rows, cols, vals = [], [], []
+    n_modes = np.zeros((len(nodes), dim), dtype=np.int64)
+    n_rot = np.zeros(len(nodes), dtype=np.int64)
+    eigvals, seen = [], []
+    cap_hits = 0
+    col = 0
+    fixed = np.asarray(fixed)
+    for li, c in enumerate(nodes):
+        _, nbox = neighbourhood(desc, c)
+        node_ids, flat = _node_ids_of_box(desc, nbox)
+        chi = partition_of_unity(desc, c, flat)
+        cache = {}
+        ev_l, seen_l, modes_l = [], [], []
+        for comp in range(dim):
+            dn = node_ids[fixed[dim * node_ids + comp] == 1]
+            key = tuple(dn.tolist())
+            if key not in cache:
+                A, M, kept = heat_pencil(desc, E, c, dn)
+                cache[key] = (heat_modes(A, M, tau, H, kmax), kept)
+            hm, kept = cache[key]
+            ev_l.append(hm.lam)
+            seen_l.append(hm.lam_seen)
+            modes_l.append((hm, kept))
+            n_modes[li, comp] = len(hm.lam)
+            cap_hits += int(hm.cap_hit)
+        eigvals.append(ev_l)
+        seen.append(seen_l)
+        pos = {int(g): i for i, g in enumerate(node_ids)}
+        for comp in range(dim):
+            hm, kept = modes_l[comp]
+            kidx = np.array([pos[int(g)] for g in kept], dtype=np.int64)
+            for j in range(hm.vecs.shape[1]):
+                v = chi[kidx] * hm.vecs[:, j]
+                nz = v != 0.0
+                rows.append(dim * kept[nz] + comp)
+                cols.append(np.full(int(nz.sum()), col))
+                vals.append(v[nz])
+                col += 1
+        if rot and n_modes[li].max() >= 1:
+            for r in _rotations(desc, c, flat):
+                v = (chi[:, None] * r)
+                dofs = (dim * node_ids[:, None] + np.arange(dim)[None, :])
+                v = v.ravel()
+                dofs = dofs.ravel()
+                keep = (fixed[dofs] == 0) & (v != 0.0)
+                rows.append(dofs[keep])
+                cols.append(np.full(int(keep.sum()), col))
+                vals.append(v[keep])
+                col += 1
+                n_rot[li] += 1
+    if col:
+        Phi = sp.csc_matrix((np.concatenate(vals),
+                             (np.concatenate(rows), np.concatenate(cols))),
+                            shape=(n, col))
+    else:
+        Phi = sp.csc_matrix((n, 0))
+    return CoarseSpace(Phi, n_modes, n_rot, eigvals, seen, cap_hits, nodes)
+
+
+# --------------------------------------------------------------------------
+# the preconditioner
+# --------------------------------------------------------------------------
+
+# relative cut below which a scaled coarse eigenvalue counts as zero
+K0_RCOND = 1e-12
+
+
+def coarse_pseudo_inverse(K0):
+    """Moore-Penrose inverse of K_0 = R_0 K R_0^T after symmetric scaling to
+    unit diagonal, eigenvalues below K0_RCOND * lambda_max dropped.
+
+    The coarse columns can be linearly dependent or vanish on the free
+    DOFs: when every coarse node
+    carries a rotation, sum_l chi_l r_l = 0 because the coarse hats reproduce
+    linear functions.  R_0^T G R_0 is the same operator (the K-orthogonal
+    projection onto span R_0^T composed with K^{-1}) for every generalized
+    inverse G of K_0, so the pseudo-inverse is the natural reading of
+    K_0^{-1} in Section 2.  Returns (pinv, numerical rank).
+    """
+    d = np.diag(K0).copy()
+    if np.any(d < 0.0):
+        raise np.linalg.LinAlgError("coarse matrix has a negative diagonal")
+    # a column with zero energy (e.g. a mode living only where chi_l = 0)
+    # spans nothing: its scale is set to zero, which drops it
+    s = np.zeros_like(d)
+    s[d > 0.0] = 1.0 / np.sqrt(d[d > 0.0])
+    K0s = K0 * s[:, None] * s[None, :]
+    w, V = np.linalg.eigh(K0s)
+    if w[0] < -1e-8 * w[-1]:
+        raise np.linalg.LinAlgError("coarse matrix is not positive semidefinite")
+    keep = w > K0_RCOND * w[-1]
+    Vk = V[:, keep]
+    P = (Vk / w[keep][None, :]) @ Vk.T
+    return P * s[:, None] * s[None, :], int(keep.sum())
+
+
+class TwoLevelSchwarz:
+    """M^{-1} r = sum_i R_i^T K_i^{-1} R_i r + R_0^T K_0^{-1} R_0 r on the
+    free DOFs (Section 2, two-level additive Schwarz; Section 4.3 for the
+    heat coarse space with rotations).  ``level`` selects 'both', 'one' or
+    'coarse'."""
+
+    def __init__(self, K_FF, sub_idx, Phi_F, level="both"):
+        self.n = K_FF.shape[0]
+        self.level = level
+        self.sub_idx = sub_idx
+        self.factors = []
+        if level in ("both", "one"):
+            for idx in sub_idx:
+                Ki = K_FF[idx][:, idx].tocsc()
+                self.factors.append(spla.splu(Ki))
+        self.Phi = Phi_F
+        self.K0 = None
+        if level in ("both", "coarse") and Phi_F.shape[1] > 0:
+            KPhi = K_FF @ Phi_F
+            K0 = (Phi_F.T @ KPhi)
+            K0 = K0.toarray() if sp.issparse(K0) else np.asarray(K0)
+            self.K0 = 0.5 * (K0 + K0.T)
+            self.K0_pinv, self.K0_rank = coarse_pseudo_inverse(self.K0)
+
+    def level1(self, r):
+        z = np.zeros(self.n)
+        for idx, lu in zip(self.sub_idx, self.factors):
+            z[idx] += lu.solve(r[idx])
+        return z
+
+    def coarse(self, r):
+        if self.K0 is None:
+            return np.zeros(self.n)
+        c = self.Phi.T @ r
+        return self.Phi @ (self.K0_pinv @ c)
+
+    def __call__(self, r):
+        z = np.zeros(self.n)
+        if self.level in ("both", "one"):
+            z += self.level1(r)
+        if self.level in ("both", "coarse"):
+            z += self.coarse(r)
+        return z
+
+
+@dataclasses.dataclass
+class Hierarchy:
+    desc: dict
+    E: np.ndarray
+    fixed: np.ndarray
+    free: np.ndarray
+    K: sp.csr_matrix
+    K_FF: sp.csr_matrix
+    sub_boxes: list
+    sub_idx: list           # free-numbering indices per subdomain
+    coarse: CoarseSpace
+    M: TwoLevelSchwarz
+
+
+def subdomain_free_indices(desc, fixed, boxes):
+    dim = desc["dim"]
+    n = len(fixed)
+    fmap = -np.ones(n, dtype=np.int64)
+    free = np.nonzero(np.asarray(fixed) == 0)[0]
+    fmap[free] = np.arange(len(free))
+    out = []
+    covered = np.zeros(len(free), dtype=bool)
+    for box in boxes:
+        ids, _ = _node_ids_of_box(desc, box)
+        dofs = (dim * ids[:, None] + np.arange(dim)[None, :]).ravel()
+        loc = fmap[dofs]
+        loc = loc[loc >= 0]
+        out.append(loc)
+        covered[loc] = True
+    if not covered.all():
+        raise ValueError("the overlapping subdomains do not cover every free DOF")
+    return out
+
+
+def build_preconditioner(desc, rho, fixed, level="both", rot=None):
+    """Assemble K(rho) and build M_EH+Rot (rot=1) or M_EH (rot=0)."""
+    fixed = np.asarray(fixed, dtype=np.uint8)
+    E = simp_modulus(rho, desc["E0"], desc["Emin"], desc["penal"])
+    K = assemble_stiffness(desc, E)
+    free = np.nonzero(fixed == 0)[0]
+    K_FF = K[free][:, free].tocsr()
+    boxes = subdomain_node_boxes(desc, fixed)
+    sub_idx = subdomain_free_indices(desc, fixed, boxes)
+    if level in ("both", "coarse"):
+        cs = build_coarse_basis(desc, E, fixed, rot)
+    else:
+        cs = CoarseSpace(sp.csc_matrix((len(fixed), 0)),
+                         np.zeros((0, desc["dim"]), np.int64),
+                         np.zeros(0, np.int64), [], [], 0, [])
+    Phi_F = cs.Phi[free, :].tocsc()
+    M = TwoLevelSchwarz(K_FF, sub_idx, Phi_F, level)
+    return Hierarchy(desc, E, fixed, free, K, K_FF, boxes, sub_idx, cs, M)
