@@ -1,0 +1,189 @@
+/*
+ * msp.h -- C ABI of libmsp: the PCG state solve K(rho) u = f of SIMP
+ * linear elasticity, preconditioned by the two-level overlapping additive
+ * Schwarz method M_EH+Rot of Zambrano, Serrano, Lazarov and Galvis,
+ * "Fast multiscale contrast independent preconditioners for linear elastic
+ * topology optimization problems" (arXiv:2006.13387).
+ *
+ * All work runs on one AMD MI355X (gfx950) in hand-written HIP kernels.
+ * Pointers marked _dev are device pointers (any HIP allocation, e.g. the
+ * data_ptr() of a torch tensor); _host pointers are host memory.  Every
+ * call enqueues on the caller's stream and returns after its results are
+ * complete on that stream unless stated otherwise.
+ *
+ * Numbering (the same in every argument):
+ *   node (i,j[,k])          id = i + (nx+1)*(j + (ny+1)*k)
+ *   DOF c of node p         id = dim*p + c          (interleaved)
+ *   element (i,j[,k])       id = i + nx*(j + ny*k)
+ *
+ * Status codes: 0 success, > 0 a warning with valid outputs, < 0 an error
+ * that leaves every output untouched.  msp_last_error() gives the text.
+ */
+#ifndef MSP_H
+#define MSP_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MSP_OK = 0,
+  MSP_NOT_CONVERGED = 1,   /* maxit reached: u holds the last iterate     */
+  MSP_E_INVALID = -1,      /* bad argument or unsupported problem shape   */
+  MSP_E_NOMEM = -2,        /* device allocation failed                   */
+  MSP_E_DEVICE = -3,       /* a HIP call failed                          */
+  MSP_E_NOT_SPD = -4,      /* a local or coarse pivot was not positive   */
+  MSP_E_BREAKDOWN = -5,    /* p^T K p <= 0 or a non-finite CG scalar     */
+  MSP_E_STATE = -7         /* call out of order (e.g. solve before rho)  */
+} msp_status;
+
+/*
+ * Problem statement (paper Section 1: SIMP law and Navier-Cauchy problem;
+ * Section 2: coarse blocks D_i and overlapping subdomains D'_i; Section 4.1:
+ * heat eigenproblem and its automatic threshold; Section 4.2: rotations).
+ *
+ *  dim        2 (bilinear Q1, plane stress) or 3 (trilinear H8)
+ *  nel        elements per axis (nel[2] ignored in 2D)
+ *  h          element edge length
+ *  E0, Emin   SIMP moduli: E_e = Emin + rho_e^penal (E0 - Emin), 0<Emin<=E0
+ *  nu         Poisson ratio in (-1, 0.5)
+ *  penal      SIMP exponent, >= 1
+ *  sub_nel    coarse block edge S in elements per axis (must divide nel)
+ *  overlap    delta: element layers added around each block (0 <= delta < S)
+ *  sub_mode   0: subdomains are the blocks extended by delta (max-norm);
+ *             1: subdomains are the coarse-vertex neighbourhoods of the
+ *                coarse nodes that are not clamped (the paper's experiments)
+ *  eig_tau    keep heat eigenvalues with lambda * H^2 < eig_tau, H = S*h
+ *  eig_kmax   at most this many modes per neighbourhood (1..24)
+ *  rot_enrich 1: add chi_l times the rotations (M_EH+Rot); 0: M_EH
+ *  precision  0: FP64 local solves; 1: local inverses stored, applied and
+ *             accumulated in FP32 inside the FP64 outer CG (flexible beta)
+ */
+typedef struct {
+  int32_t dim;
+  int32_t nel[3];
+  double h, E0, Emin, nu, penal;
+  int32_t sub_nel[3];
+  int32_t overlap;
+  int32_t sub_mode;
+  double eig_tau;
+  int32_t eig_kmax;
+  int32_t rot_enrich;
+  int32_t precision;
+} msp_problem_desc;
+
+typedef struct {
+  int32_t status;          /* msp_status of the solve                        */
+  int32_t iters;           /* PCG iterations (all restarts included)         */
+  int32_t converged;       /* 1 if the true residual met rtol                */
+  int32_t restarts;        /* restarts from the true residual                */
+  int32_t n_coarse;        /* coarse dimension N_c (columns of R_0^T)         */
+  int32_t coarse_rank;     /* numerical rank of K_0                          */
+  int32_t cap_hits;        /* neighbourhoods with more than kmax modes below  */
+  int32_t pad_;
+  double relres_true;      /* ||f - K u|| / ||f|| over free DOFs             */
+  double relres_rec;       /* recursively updated residual at exit           */
+  double compliance;       /* f^T u                                          */
+  double cond_est;         /* Lanczos estimate of cond(M^-1 K) (Section 5)   */
+  double t_setup_ms;       /* setup run inside this call (0 if none)         */
+  double t_solve_ms;       /* PCG wall time of this call                     */
+} msp_solve_info;
+
+typedef struct msp_handle msp_handle;
+
+/*
+ * Create a solver for one mesh.  fixed_mask_host holds n = dim*(#nodes)
+ * bytes, 1 = that displacement DOF is clamped to zero (Gamma_D).  The mask
+ * is copied.  In 2D the block row of a subdomain (2 * nodes per row) and
+ * of a neighbourhood (nodes per row) must not exceed 72.
+ * Errors: MSP_E_INVALID (see the field ranges above), MSP_E_NOMEM.
+ */
+msp_status msp_create(const msp_problem_desc* desc,
+                      const uint8_t* fixed_mask_host, msp_handle** out);
+
+/* Free every device buffer of the handle.  Accepts NULL. */
+msp_status msp_destroy(msp_handle* h);
+
+/* Text of the last error on this handle (static storage if h is NULL). */
+const char* msp_last_error(const msp_handle* h);
+
+/*
+ * Element densities rho_dev (nel doubles in [0,1]) for the next setup.
+ * Computes E_e by the SIMP law on the device and marks the setup dirty.
+ * Non-finite or out-of-range densities give MSP_E_INVALID.
+ */
+msp_status msp_set_densities(msp_handle* h, const double* rho_dev,
+                             hipStream_t stream);
+
+/*
+ * Build the preconditioner for the current densities (Section 2 and 4):
+ * local factors of K_i = R_i K R_i^T, heat eigenpairs on every coarse
+ * neighbourhood with the threshold, coarse basis and K_0^+.  One
+ * device-to-host read of the selected mode counts.  MSP_E_NOT_SPD if a
+ * local pivot is not positive.
+ */
+msp_status msp_setup(msp_handle* h, hipStream_t stream);
+
+/*
+ * Solve K_FF u = f by PCG with M_EH+Rot (or M_EH) to ||f - K u|| <=
+ * rtol ||f|| over the free DOFs (Section 2; Section 5 for the stopping
+ * test and the Lanczos estimate).  f_dev and u_dev hold nrhs right-hand
+ * sides of n doubles each, one after another; with warm != 0 u_dev holds
+ * the initial guesses.  Entries of f at clamped DOFs are ignored and u is
+ * 0 there.  Runs msp_setup first if the densities changed.  info_host (may
+ * be NULL) receives the statistics of the last right-hand side.
+ */
+msp_status msp_solve(msp_handle* h, const double* f_dev, double* u_dev,
+                     int32_t nrhs, int32_t warm, double rtol, int32_t maxit,
+                     hipStream_t stream, msp_solve_info* info_host);
+
+/* ---- single steps of the hot path, for parity checks and profiling ---- */
+
+/* y = K_FF x (Section 1.1 discretisation): y = 0 at clamped DOFs, entries
+ * of x at clamped DOFs are treated as 0.  Needs densities. */
+msp_status msp_apply_K(msp_handle* h, const double* x_dev, double* y_dev,
+                       hipStream_t stream);
+
+/* z = sum_i R_i^T K_i^{-1} R_i r  (first level, Section 2).  Needs setup. */
+msp_status msp_apply_level1(msp_handle* h, const double* r_dev, double* z_dev,
+                            hipStream_t stream);
+
+/* z = R_0^T K_0^+ R_0 r  (coarse level, Sections 2 and 4.3). */
+msp_status msp_apply_coarse(msp_handle* h, const double* r_dev, double* z_dev,
+                            hipStream_t stream);
+
+/* z = M^{-1} r = level 1 + coarse level. */
+msp_status msp_apply_prec(msp_handle* h, const double* r_dev, double* z_dev,
+                          hipStream_t stream);
+
+/*
+ * Coarse-space statistics after setup.  n_modes_host: one int per coarse
+ * node (x fastest) = heat modes selected; eigvals_host: eig_kmax doubles
+ * per coarse node (selected eigenvalues ascending, rest NaN).  Either
+ * pointer may be NULL.  n_coarse_nodes receives the coarse node count.
+ */
+msp_status msp_coarse_info(msp_handle* h, int32_t* n_modes_host,
+                           double* eigvals_host, int32_t* n_coarse_nodes,
+                           int32_t* n_coarse, int32_t* cap_hits);
+
+/* Write the coarse basis R_0^T as a dense n x N_c column-major matrix to
+ * phi_dev (caller allocates n*N_c doubles).  For checks on small meshes. */
+msp_status msp_coarse_basis(msp_handle* h, double* phi_dev, hipStream_t stream);
+
+/* out_host[0] = x . y over n doubles with the library's two-stage
+ * wavefront reduction (the reduction used by the CG dot products). */
+msp_status msp_vec_dot(int64_t n, const double* x_dev, const double* y_dev,
+                       hipStream_t stream, double* out_host);
+
+/* Sizes: [0] n DOFs, [1] elements, [2] subdomains, [3] coarse nodes,
+ * [4] coarse dimension after setup, [5] largest local system,
+ * [6] bytes of local factor storage, [7] bytes of coarse basis storage. */
+msp_status msp_query(msp_handle* h, int64_t* sizes8);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSP_H */

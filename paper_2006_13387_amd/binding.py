@@ -1,0 +1,238 @@
+"""ctypes binding of libmsp (include/msp.h).
+
+Argument marshalling only: every step of the solve runs in the library's
+HIP kernels.  Device arrays are torch tensors on the GPU; only their
+data_ptr() crosses the boundary, with torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmsp.so")
+
+MSP_OK = 0
+MSP_NOT_CONVERGED = 1
+STATUS_NAMES = {0: "MSP_OK", 1: "MSP_NOT_CONVERGED", -1: "MSP_E_INVALID",
+                -2: "MSP_E_NOMEM", -3: "MSP_E_DEVICE", -4: "MSP_E_NOT_SPD",
+                -5: "MSP_E_BREAKDOWN", -7: "MSP_E_STATE"}
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("nel", ctypes.c_int32 * 3),
+                ("h", ctypes.c_double), ("E0", ctypes.c_double),
+                ("Emin", ctypes.c_double), ("nu", ctypes.c_double),
+                ("penal", ctypes.c_double), ("sub_nel", ctypes.c_int32 * 3),
+                ("overlap", ctypes.c_int32), ("sub_mode", ctypes.c_int32),
+                ("eig_tau", ctypes.c_double), ("eig_kmax", ctypes.c_int32),
+                ("rot_enrich", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("n_coarse", ctypes.c_int32), ("coarse_rank", ctypes.c_int32),
+                ("cap_hits", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("relres_true", ctypes.c_double),
+                ("relres_rec", ctypes.c_double),
+                ("compliance", ctypes.c_double), ("cond_est", ctypes.c_double),
+                ("t_setup_ms", ctypes.c_double),
+                ("t_solve_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+
+
+EXPORTS = ["msp_create", "msp_destroy", "msp_last_error", "msp_set_densities",
+           "msp_setup", "msp_solve", "msp_apply_K", "msp_apply_level1",
+           "msp_apply_coarse", "msp_apply_prec", "msp_coarse_info",
+           "msp_coarse_basis", "msp_vec_dot", "msp_query"]
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libmsp.so; raises if it is missing (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"libmsp.so not found at {path}: build it with "
+            "`python -m paper_2006_13387_amd.build` (no CPU fallback exists)")
+    L = ctypes.CDLL(path)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    L.msp_create.argtypes = [ctypes.POINTER(ProblemDesc), vp, ctypes.POINTER(vp)]
+    L.msp_destroy.argtypes = [vp]
+    L.msp_last_error.argtypes = [vp]
+    L.msp_last_error.restype = ctypes.c_char_p
+    L.msp_set_densities.argtypes = [vp, vp, vp]
+    L.msp_setup.argtypes = [vp, vp]
+    L.msp_solve.argtypes = [vp, vp, vp, i32, i32, dbl, i32, vp,
+                            ctypes.POINTER(SolveInfo)]
+    for name in ("msp_apply_K", "msp_apply_level1", "msp_apply_coarse",
+                 "msp_apply_prec"):
+        getattr(L, name).argtypes = [vp, vp, vp, vp]
+    L.msp_coarse_info.argtypes = [vp, vp, vp, ctypes.POINTER(i32),
+                                  ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.msp_coarse_basis.argtypes = [vp, vp, vp]
+    L.msp_vec_dot.argtypes = [ctypes.c_int64, vp, vp, vp,
+                              ctypes.POINTER(ctypes.c_double)]
+    L.msp_query.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    for name in EXPORTS:
+        if name != "msp_last_error":
+            getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+class MspError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) torch tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_desc(d):
+    pd = ProblemDesc()
+    pd.dim = d["dim"]
+    nel = list(d["nel"]) + [1] * (3 - len(d["nel"]))
+    sub = list(d["sub_nel"]) + [1] * (3 - len(d["sub_nel"]))
+    pd.nel = (ctypes.c_int32 * 3)(*nel)
+    pd.sub_nel = (ctypes.c_int32 * 3)(*sub)
+    pd.h, pd.E0, pd.Emin = d["h"], d["E0"], d["Emin"]
+    pd.nu, pd.penal = d["nu"], d["penal"]
+    pd.overlap, pd.sub_mode = d["overlap"], d["sub_mode"]
+    pd.eig_tau, pd.eig_kmax = d["eig_tau"], d["eig_kmax"]
+    pd.rot_enrich, pd.precision = d["rot_enrich"], d["precision"]
+    return pd
+
+
+class Solver:
+    """One mesh, one set of boundary conditions (a msp_handle)."""
+
+    def __init__(self, desc, fixed):
+        self.L = load_library()
+        self.desc = dict(desc)
+        self._pd = make_desc(desc)
+        mask = np.ascontiguousarray(np.asarray(fixed, dtype=np.uint8))
+        self._mask = mask
+        h = ctypes.c_void_p()
+        st = self.L.msp_create(ctypes.byref(self._pd),
+                               mask.ctypes.data_as(ctypes.c_void_p),
+                               ctypes.byref(h))
+        if st != 0:
+            raise MspError(st, self.L.msp_last_error(None).decode())
+        self.h = h
+        q = (ctypes.c_int64 * 8)()
+        self.L.msp_query(self.h, q)
+        self.n = int(q[0])
+
+    def _check(self, st, ok=(0,)):
+        if st not in ok:
+            raise MspError(st, self.L.msp_last_error(self.h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.msp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_densities(self, rho):
+        self._check(self.L.msp_set_densities(self.h, _ptr(rho), _stream()))
+
+    def setup(self):
+        self._check(self.L.msp_setup(self.h, _stream()))
+
+    def solve(self, f, u=None, warm=False, rtol=1e-8, maxit=5000):
+        import torch
+        nrhs = f.numel() // self.n
+        if u is None:
+            u = torch.zeros_like(f)
+        info = SolveInfo()
+        st = self.L.msp_solve(self.h, _ptr(f), _ptr(u), nrhs, int(bool(warm)),
+                              float(rtol), int(maxit), _stream(),
+                              ctypes.byref(info))
+        self._check(st, ok=(0, 1))
+        return u, info.as_dict()
+
+    def _apply(self, fn, x):
+        import torch
+        y = torch.empty_like(x)
+        self._check(fn(self.h, _ptr(x), _ptr(y), _stream()))
+        return y
+
+    def apply_K(self, x):
+        return self._apply(self.L.msp_apply_K, x)
+
+    def apply_level1(self, r):
+        return self._apply(self.L.msp_apply_level1, r)
+
+    def apply_coarse(self, r):
+        return self._apply(self.L.msp_apply_coarse, r)
+
+    def apply_prec(self, r):
+        return self._apply(self.L.msp_apply_prec, r)
+
+    def coarse_info(self):
+        q = (ctypes.c_int64 * 8)()
+        self.L.msp_query(self.h, q)
+        ncn = int(q[3])
+        kmax = self.desc["eig_kmax"]
+        nm = np.zeros(ncn, np.int32)
+        ev = np.zeros(ncn * kmax, np.float64)
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.L.msp_coarse_info(
+            self.h, nm.ctypes.data_as(ctypes.c_void_p),
+            ev.ctypes.data_as(ctypes.c_void_p), ctypes.byref(a),
+            ctypes.byref(b), ctypes.byref(c)))
+        return {"n_modes": nm, "eigvals": ev.reshape(ncn, kmax),
+                "n_coarse": b.value, "cap_hits": c.value}
+
+    def coarse_basis(self):
+        import torch
+        nc = self.coarse_info()["n_coarse"]
+        phi = torch.zeros((max(nc, 1), self.n), dtype=torch.float64,
+                          device="cuda")
+        self._check(self.L.msp_coarse_basis(self.h, _ptr(phi), _stream()))
+        return phi[:nc].T
+
+    def query(self):
+        q = (ctypes.c_int64 * 8)()
+        self._check(self.L.msp_query(self.h, q))
+        keys = ["n_dofs", "n_elems", "n_subdomains", "n_coarse_nodes",
+                "n_coarse", "max_local", "local_factor_bytes",
+                "coarse_basis_bytes"]
+        return dict(zip(keys, [int(v) for v in q]))
+
+
+def vec_dot(x, y):
+    L = load_library()
+    out = ctypes.c_double()
+    st = L.msp_vec_dot(x.numel(), _ptr(x), _ptr(y), _stream(),
+                       ctypes.byref(out))
+    if st != 0:
+        raise MspError(st, L.msp_last_error(None).decode())
+    return out.value

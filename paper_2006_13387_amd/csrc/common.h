@@ -1,0 +1,82 @@
+// Shared host/device definitions of libmsp (2D Q1 path).
+//
+// Layout conventions (all device arrays, interleaved DOFs):
+//   vectors   : n_dofs doubles, DOF 2*node + c
+//   E         : n_elems doubles (SIMP moduli), element i + nx*j
+//   mask      : n_dofs bytes, 1 = clamped
+//   local systems (subdomains D'_i and neighbourhoods omega_l) are node
+//   boxes [x0, x0+nxb) x [y0, y0+nyb); their block rows are node rows, so
+//   each system is block tridiagonal with nyb blocks of bs = ndof*nxb.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msp {
+
+constexpr int MAXBS = 72;      // largest block row (DOFs) of a local system
+constexpr int MAXM = 32;       // largest eigen subspace block
+constexpr int RED_THREADS = 256;
+
+// One block-tridiagonal local system.
+struct SysDesc {
+  int x0, y0;          // first node of the box
+  int nxb, nyb;        // nodes per row, rows
+  int ex0, ex1;        // elements that contribute: [ex0, ex1) x [ey0, ey1)
+  int ey0, ey1;
+  long long foff;      // offset (entries) of the inverse Schur blocks
+  long long voff;      // offset (entries) of the local vector
+};
+
+// Coarse node record (2D): neighbourhood box and column layout.
+struct CoarseNode {
+  int cx, cy;          // coarse grid index
+  int x0, y0;          // omega node box origin (closed box)
+  int nxw, nyw;        // omega node box size
+  int nmodes;          // selected heat modes
+  int nrot;            // rotation columns (0 or 1)
+  int col0;            // first coarse column (mode j of component c at
+                       // col0 + c*nmodes + j; rotation at col0 + 2*nmodes)
+  int sys;             // index of this omega in the eigen system table
+  long long psi_off;   // offset of psi_j (nmodes x nxw*nyw doubles)
+  long long w_off;     // offset of K Phi columns (ncols x 2*nxw*nyw)
+};
+
+// Device scalars of one PCG run.
+struct CGScalars {
+  double rz, rz_old, pq, alpha, beta, rr, ff, zq, fx, rr0;
+  double tol2;
+  int iter, done, status, maxit;
+  int flexible, pad0, pad1, pad2;
+};
+
+enum : int { DONE_RUNNING = 0, DONE_CONVERGED = 1, DONE_MAXIT = 2,
+             DONE_BREAKDOWN = 3 };
+
+// Error bits raised by kernels.
+enum : int { ERR_NOT_SPD = 1, ERR_NONFINITE = 2, ERR_RANGE = 4,
+             ERR_EIG = 8 };
+
+// Arguments of the kernel that forms z = M^{-1} r at every node.
+struct CombineArgs {
+  const SysDesc* sys;
+  const int* sub_grid;       // grid cell -> subdomain index or -1
+  int ngx, ngy;              // extent of that grid
+  int sub_vertex;            // 1: grid = coarse nodes, 0: blocks
+  const void* lsol;          // local solutions (double or float)
+  int lsol_fp32;
+  const CoarseNode* cnodes;
+  const double* psi;
+  const double* c0;
+  double invH;
+  int use_l1, use_coarse;
+};
+
+struct Geom {
+  int nx, ny;          // elements
+  int nnx, nny;        // nodes
+  int sx, sy;          // coarse block edge S (elements)
+  int ncx, ncy;        // coarse nodes per axis
+  double h;
+};
+
+}  // namespace msp

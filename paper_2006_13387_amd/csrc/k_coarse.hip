@@ -1,0 +1,627 @@
+// Coarse level of M_EH+Rot (paper Sections 2, 4.1-4.3) and the kernel that
+// assembles z = M^{-1} r.
+//
+// Coarse basis (implicit): for coarse node l with heat modes psi_j on its
+// neighbourhood omega_l, columns chi_l psi_j e_c (c = 0, 1) and, when at
+// least one mode was selected, chi_l r_l with r_l the rotation about the
+// coarse node scaled by 1/H.  chi_l is the coarse bilinear hat, evaluated
+// analytically; only psi is stored.  Entries at clamped DOFs are zero.
+//
+// K_0 = R_0 K R_0^T is assembled from W = K Phi per column and the
+// products Phi_a^T W_b over overlapping neighbourhoods, scaled to unit
+// diagonal and inverted by blocked Gauss-Jordan with zero-pivot dropping.
+// Dropping a (numerically) dependent direction gives a generalized inverse
+// G of K_0, and R_0^T G R_0 does not depend on which one: it is the
+// K-orthogonal projection onto the coarse space composed with K^{-1}.
+#include "common.h"
+#include "dev.h"
+
+namespace msp {
+
+constexpr int CK_NT = 256;
+constexpr int GJB = 64;           // Gauss-Jordan block
+
+__device__ __forceinline__ double chi_at(const Geom& g, int cx, int cy, int x,
+                                         int y) {
+  const double ax = 1.0 - fabs((double)(x - cx * g.sx)) / g.sx;
+  const double ay = 1.0 - fabs((double)(y - cy * g.sy)) / g.sy;
+  return (ax > 0.0 && ay > 0.0) ? ax * ay : 0.0;
+}
+
+// Value of coarse column lc of coarse node cn at node (x, y) (2 comps).
+__device__ __forceinline__ double2 phi_at(const Geom& g, const CoarseNode& cn,
+                                          const double* __restrict__ psi,
+                                          const uint8_t* __restrict__ mask,
+                                          int lc, int x, int y, double invH) {
+  if (x < cn.x0 || x >= cn.x0 + cn.nxw || y < cn.y0 || y >= cn.y0 + cn.nyw)
+    return make_double2(0.0, 0.0);
+  const double chi = chi_at(g, cn.cx, cn.cy, x, y);
+  if (chi == 0.0) return make_double2(0.0, 0.0);
+  const long long node = (long long)y * g.nnx + x;
+  const uchar2 m = reinterpret_cast<const uchar2*>(mask)[node];
+  const int nw = cn.nxw * cn.nyw;
+  const int loc = (y - cn.y0) * cn.nxw + (x - cn.x0);
+  double vx = 0.0, vy = 0.0;
+  if (lc < 2 * cn.nmodes) {
+    const int comp = lc / cn.nmodes, j = lc - comp * cn.nmodes;
+    const double v = chi * psi[cn.psi_off + (long long)j * nw + loc];
+    if (comp == 0) vx = v; else vy = v;
+  } else {
+    const double rx = (x - cn.cx * g.sx) * g.h * invH;
+    const double ry = (y - cn.cy * g.sy) * g.h * invH;
+    vx = -chi * ry;
+    vy = chi * rx;
+  }
+  return make_double2(m.x ? 0.0 : vx, m.y ? 0.0 : vy);
+}
+
+// W_col = K Phi_col on the closed box of omega_l (zero at clamped DOFs).
+__global__ void __launch_bounds__(CK_NT)
+k_coarse_kphi(Geom g, const CoarseNode* __restrict__ cnodes,
+              const int* __restrict__ col_node, const double* __restrict__ Ke,
+              const double* __restrict__ E, const uint8_t* __restrict__ mask,
+              const double* __restrict__ psi, double* __restrict__ W,
+              double invH) {
+  __shared__ double ks[64];
+  const int col = blockIdx.x;
+  const int l = col_node[col];
+  const CoarseNode cn = cnodes[l];
+  const int lc = col - cn.col0;
+  if (threadIdx.x < 64) ks[threadIdx.x] = Ke[threadIdx.x];
+  __syncthreads();
+  const int nw = cn.nxw * cn.nyw;
+  double* out = W + cn.w_off + (long long)lc * 2 * nw;
+  for (int loc = threadIdx.x; loc < nw; loc += CK_NT) {
+    const int x = cn.x0 + loc % cn.nxw, y = cn.y0 + loc / cn.nxw;
+    double y0 = 0.0, y1 = 0.0;
+    for (int ey = max(y - 1, 0); ey <= min(y, g.ny - 1); ++ey)
+      for (int ex = max(x - 1, 0); ex <= min(x, g.nx - 1); ++ex) {
+        const int a = (x - ex) + 2 * (y - ey);
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const double2 u = phi_at(g, cn, psi, mask, lc, ex + (b & 1), ey + (b >> 1), invH);
+          s0 += ks[(2 * a) * 8 + 2 * b] * u.x + ks[(2 * a) * 8 + 2 * b + 1] * u.y;
+          s1 += ks[(2 * a + 1) * 8 + 2 * b] * u.x + ks[(2 * a + 1) * 8 + 2 * b + 1] * u.y;
+        }
+        const double ee = E[(long long)ey * g.nx + ex];
+        y0 += ee * s0;
+        y1 += ee * s1;
+      }
+    const uchar2 m = reinterpret_cast<const uchar2*>(mask)[(long long)y * g.nnx + x];
+    out[2 * loc] = m.x ? 0.0 : y0;
+    out[2 * loc + 1] = m.y ? 0.0 : y1;
+  }
+}
+
+// K_0 block of coarse nodes (l, l2): K0[a][b] = Phi_a^T W_b over the
+// intersection of omega_l and omega_l2.  One workgroup per ordered pair.
+constexpr int K0_CH = 32;      // nodes per LDS chunk
+constexpr int MAXCOL = 2 * 24 + 1;
+
+__global__ void __launch_bounds__(CK_NT)
+k_coarse_k0(Geom g, const CoarseNode* __restrict__ cnodes,
+            const int2* __restrict__ pairs, const uint8_t* __restrict__ mask,
+            const double* __restrict__ psi, const double* __restrict__ W,
+            double* __restrict__ K0, int ldk, double invH) {
+  __shared__ double pa[MAXCOL * K0_CH * 2];
+  __shared__ double wb[MAXCOL * K0_CH * 2];
+  const int2 pr = pairs[blockIdx.x];
+  const CoarseNode A = cnodes[pr.x];
+  const CoarseNode B = cnodes[pr.y];
+  const int na = 2 * A.nmodes + A.nrot;
+  const int nbc = 2 * B.nmodes + B.nrot;
+  if (na == 0 || nbc == 0) return;
+  const int xlo = max(A.x0, B.x0), xhi = min(A.x0 + A.nxw, B.x0 + B.nxw);
+  const int ylo = max(A.y0, B.y0), yhi = min(A.y0 + A.nyw, B.y0 + B.nyw);
+  const int nxi = max(0, xhi - xlo), nyi = max(0, yhi - ylo);
+  const int ni = nxi * nyi;
+  const int nwB = B.nxw * B.nyw;
+  double acc[(MAXCOL * MAXCOL + CK_NT - 1) / CK_NT];
+#pragma unroll
+  for (int e = 0; e < (MAXCOL * MAXCOL + CK_NT - 1) / CK_NT; ++e) acc[e] = 0.0;
+  for (int c0 = 0; c0 < ni; c0 += K0_CH) {
+    const int cn = min(K0_CH, ni - c0);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < na * K0_CH; idx += CK_NT) {
+      const int a = idx / K0_CH, t = idx - a * K0_CH;
+      double2 v = make_double2(0.0, 0.0);
+      if (t < cn) {
+        const int q = c0 + t;
+        const int x = xlo + q % nxi, y = ylo + q / nxi;
+        v = phi_at(g, A, psi, mask, a, x, y, invH);
+      }
+      pa[(a * K0_CH + t) * 2] = v.x;
+      pa[(a * K0_CH + t) * 2 + 1] = v.y;
+    }
+    for (int idx = threadIdx.x; idx < nbc * K0_CH; idx += CK_NT) {
+      const int b = idx / K0_CH, t = idx - b * K0_CH;
+      double vx = 0.0, vy = 0.0;
+      if (t < cn) {
+        const int q = c0 + t;
+        const int x = xlo + q % nxi, y = ylo + q / nxi;
+        const int loc = (y - B.y0) * B.nxw + (x - B.x0);
+        const double* wcol = W + B.w_off + (long long)b * 2 * nwB;
+        vx = wcol[2 * loc];
+        vy = wcol[2 * loc + 1];
+      }
+      wb[(b * K0_CH + t) * 2] = vx;
+      wb[(b * K0_CH + t) * 2 + 1] = vy;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < (MAXCOL * MAXCOL + CK_NT - 1) / CK_NT; ++e) {
+      const int idx = threadIdx.x + e * CK_NT;
+      if (idx < na * nbc) {
+        const int a = idx / nbc, b = idx - (idx / nbc) * nbc;
+        double s = 0.0;
+        for (int t = 0; t < 2 * K0_CH; ++t) s += pa[a * 2 * K0_CH + t] * wb[b * 2 * K0_CH + t];
+        acc[e] += s;
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < (MAXCOL * MAXCOL + CK_NT - 1) / CK_NT; ++e) {
+    const int idx = threadIdx.x + e * CK_NT;
+    if (idx < na * nbc) {
+      const int a = idx / nbc, b = idx - (idx / nbc) * nbc;
+      K0[(long long)(A.col0 + a) * ldk + (B.col0 + b)] = acc[e];
+    }
+  }
+}
+
+// Symmetrise, scale to unit diagonal (s_j = 1/sqrt(K0_jj), 0 for empty
+// columns and padding).  One thread per entry.
+__global__ void k_k0_scale_factors(const double* __restrict__ K0, int ldk,
+                                   int nc, double* __restrict__ sdiag) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ldk) return;
+  double s = 0.0;
+  if (j < nc) {
+    const double d = K0[(long long)j * ldk + j];
+    if (d > 0.0 && finite(d)) s = 1.0 / sqrt(d);
+  }
+  sdiag[j] = s;
+}
+
+__global__ void k_k0_scale(double* __restrict__ K0, int ldk,
+                           const double* __restrict__ sdiag) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long n2 = (long long)ldk * ldk;
+  if (idx >= n2) return;
+  const int i = (int)(idx / ldk), j = (int)(idx - (idx / ldk) * ldk);
+  if (j < i) return;
+  const double v = 0.5 * (K0[(long long)i * ldk + j] + K0[(long long)j * ldk + i]) * sdiag[i] * sdiag[j];
+  K0[(long long)i * ldk + j] = v;
+  K0[(long long)j * ldk + i] = v;
+}
+
+// Blocked Gauss-Jordan on the scaled K_0, block k: invert the 64 x 64
+// diagonal block in LDS, dropping pivots <= tol (row and column zeroed).
+__global__ void __launch_bounds__(CK_NT)
+k_gj_pivot(double* __restrict__ A, int ld, int kb, double* __restrict__ P,
+           double tol, int* __restrict__ dropped) {
+  __shared__ double S[GJB * (GJB + 1)];
+  __shared__ double rowv[GJB], colv[GJB];
+  const int tid = threadIdx.x;
+  const long long base = (long long)kb * GJB;
+  for (int idx = tid; idx < GJB * GJB; idx += CK_NT) {
+    const int i = idx / GJB, j = idx - i * GJB;
+    S[i * (GJB + 1) + j] = A[(base + i) * ld + base + j];
+  }
+  __syncthreads();
+  for (int p = 0; p < GJB; ++p) {
+    for (int i = tid; i < GJB; i += CK_NT) {
+      colv[i] = S[i * (GJB + 1) + p];
+      rowv[i] = S[p * (GJB + 1) + i];
+    }
+    __syncthreads();
+    const double piv = colv[p];
+    const bool drop = !(piv > tol) || !finite(piv);
+    if (drop && tid == 0) atomicAdd(dropped, 1);
+    const double ip = drop ? 0.0 : 1.0 / piv;
+    for (int idx = tid; idx < GJB * GJB; idx += CK_NT) {
+      const int i = idx / GJB, j = idx - i * GJB;
+      double v;
+      if (drop) {
+        v = (i == p || j == p) ? 0.0 : S[i * (GJB + 1) + j];
+      } else if (i == p) {
+        v = (j == p) ? ip : rowv[j] * ip;
+      } else if (j == p) {
+        v = -colv[i] * ip;
+      } else {
+        v = S[i * (GJB + 1) + j] - colv[i] * rowv[j] * ip;
+      }
+      S[i * (GJB + 1) + j] = v;
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < GJB * GJB; idx += CK_NT) {
+    const int i = idx / GJB, j = idx - i * GJB;
+    P[idx] = S[i * (GJB + 1) + j];
+  }
+}
+
+// Panels of block k: Lp_i = A_ik P (for every block row i != k) and
+// Rp_j = A_kj (copy).  Grid: nblk workgroups, block index = i (or j).
+__global__ void __launch_bounds__(CK_NT)
+k_gj_panel(const double* __restrict__ A, int ld, int kb,
+           const double* __restrict__ P, double* __restrict__ Lp,
+           double* __restrict__ Rp) {
+  __shared__ double Ps[GJB * GJB];
+  __shared__ double As[GJB * (GJB + 1)];
+  const int ib = blockIdx.x;
+  const int tid = threadIdx.x;
+  const long long kbase = (long long)kb * GJB, ibase = (long long)ib * GJB;
+  for (int idx = tid; idx < GJB * GJB; idx += CK_NT) {
+    Ps[idx] = P[idx];
+    const int i = idx / GJB, j = idx - i * GJB;
+    As[i * (GJB + 1) + j] = A[(ibase + i) * ld + kbase + j];     // A_ik
+    Rp[(long long)i * ld + ibase + j] = A[(kbase + i) * ld + ibase + j];   // A_kj, j-block ib
+  }
+  __syncthreads();
+  for (int idx = tid; idx < GJB * GJB; idx += CK_NT) {
+    const int i = idx / GJB, j = idx - i * GJB;
+    double s = 0.0;
+    for (int t = 0; t < GJB; ++t) s += As[i * (GJB + 1) + t] * Ps[t * GJB + j];
+    Lp[(ibase + i) * GJB + j] = s;
+  }
+}
+
+// Tile update of block step k.  Grid (nblk, nblk) of 64 x 64 tiles.
+__global__ void __launch_bounds__(CK_NT)
+k_gj_update(double* __restrict__ A, int ld, int kb,
+            const double* __restrict__ P, const double* __restrict__ Lp,
+            const double* __restrict__ Rp) {
+  __shared__ double Ls[GJB * (GJB + 1)];
+  __shared__ double Rs[GJB * (GJB + 1)];
+  const int ib = blockIdx.y, jb = blockIdx.x;
+  const int tid = threadIdx.x;
+  const long long ibase = (long long)ib * GJB, jbase = (long long)jb * GJB;
+  if (ib == kb && jb == kb) {
+    for (int idx = tid; idx < GJB * GJB; idx += CK_NT) {
+      const int i = idx / GJB, j = idx - i * GJB;
+      A[(ibase + i) * ld + jbase + j] = P[idx];
+    }
+    return;
+  }
+  if (jb == kb) {
+    for (int idx = tid; idx < GJB * GJB; idx += CK_NT) {
+      const int i = idx / GJB, j = idx - i * GJB;
+      A[(ibase + i) * ld + jbase + j] = -Lp[(ibase + i) * GJB + j];
+    }
+    return;
+  }
+  // Ls = (ib == kb) ? P : Lp_i ; Rs = Rp_j
+  for (int idx = tid; idx < GJB * GJB; idx += CK_NT) {
+    const int i = idx / GJB, j = idx - i * GJB;
+    Ls[i * (GJB + 1) + j] = (ib == kb) ? P[idx] : Lp[(ibase + i) * GJB + j];
+    Rs[i * (GJB + 1) + j] = Rp[(long long)i * ld + jbase + j];
+  }
+  __syncthreads();
+  // each thread: 4 rows x 4 cols of the tile
+  const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int t = 0; t < GJB; ++t) {
+    double lv[4], rv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) lv[a] = Ls[(tr + a) * (GJB + 1) + t];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) rv[b] = Rs[t * (GJB + 1) + tc + b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] += lv[a] * rv[b];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      double* dst = &A[(ibase + tr + a) * ld + jbase + tc + b];
+      if (ib == kb) *dst = acc[a][b];              // P A_kj
+      else *dst = *dst - acc[a][b];                // A_ij - Lp_i A_kj
+    }
+}
+
+// K0p = S A S (undo the scaling), symmetrised.
+__global__ void k_k0_unscale(double* __restrict__ K0, int ldk,
+                             const double* __restrict__ sdiag) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long n2 = (long long)ldk * ldk;
+  if (idx >= n2) return;
+  const int i = (int)(idx / ldk), j = (int)(idx - (idx / ldk) * ldk);
+  if (j < i) return;
+  const double v = 0.5 * (K0[(long long)i * ldk + j] + K0[(long long)j * ldk + i]) * sdiag[i] * sdiag[j];
+  K0[(long long)i * ldk + j] = v;
+  K0[(long long)j * ldk + i] = v;
+}
+
+// ---------------------------------------------------------------------
+// Restriction c = R_0 r: one workgroup per coarse node; wave w takes the
+// columns j = w, w+4, ...; its lanes stride over the neighbourhood's nodes
+// (coalesced psi and r reads) and the column sum is a wavefront butterfly.
+__global__ void __launch_bounds__(CK_NT)
+k_restrict(Geom g, const CoarseNode* __restrict__ cnodes,
+           const uint8_t* __restrict__ mask, const double* __restrict__ psi,
+           const double* __restrict__ r, double* __restrict__ c, double invH,
+           const CGScalars* __restrict__ sc) {
+  if (sc != nullptr && sc->done) return;
+  const CoarseNode cn = cnodes[blockIdx.x];
+  const int ncol = 2 * cn.nmodes + cn.nrot;
+  const int nw = cn.nxw * cn.nyw;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int j = w; j < ncol; j += CK_NT / 64) {
+    double acc = 0.0;
+    for (int loc = lane; loc < nw; loc += 64) {
+      const int x = cn.x0 + loc % cn.nxw, y = cn.y0 + loc / cn.nxw;
+      const double chi = chi_at(g, cn.cx, cn.cy, x, y);
+      const long long node = (long long)y * g.nnx + x;
+      const double2 rv = reinterpret_cast<const double2*>(r)[node];
+      const uchar2 m = reinterpret_cast<const uchar2*>(mask)[node];
+      const double r0 = m.x ? 0.0 : rv.x, r1 = m.y ? 0.0 : rv.y;
+      if (j < 2 * cn.nmodes) {
+        const int comp = j / cn.nmodes, jm = j - comp * cn.nmodes;
+        const double ps = chi * psi[cn.psi_off + (long long)jm * nw + loc];
+        acc += ps * (comp == 0 ? r0 : r1);
+      } else {
+        const double rx = (x - cn.cx * g.sx) * g.h * invH;
+        const double ry = (y - cn.cy * g.sy) * g.h * invH;
+        acc += chi * (-ry * r0 + rx * r1);
+      }
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) c[cn.col0 + j] = acc;
+  }
+}
+
+// c0 = K0p c : one wavefront per row (K0p symmetric, row-major).
+__global__ void __launch_bounds__(256)
+k_coarse_gemv(const double* __restrict__ K0, int ldk, int nc,
+              const double* __restrict__ c, double* __restrict__ c0,
+              const CGScalars* __restrict__ sc) {
+  if (sc != nullptr && sc->done) return;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= nc) return;
+  const double* a = K0 + (long long)row * ldk;
+  double s = 0.0;
+  for (int j = lane; j < nc; j += 64) s += a[j] * c[j];
+  s = wave_sum(s);
+  if (lane == 0) c0[row] = s;
+}
+
+// z = [sum_i R_i^T x_i] + [R_0^T c0] at every node; optional dot products
+// (r.z and z.q) with the beta of Fletcher-Reeves or, flexible, Polak-Ribiere
+// (beta = -alpha (z.q) / (r.z)_old since r_new - r_old = -alpha q).
+
+
+template <int MODE>   // 0: plain apply, 1: CG iteration, 2: CG start
+__global__ void __launch_bounds__(256)
+k_combine(Geom g, CombineArgs ca, const uint8_t* __restrict__ mask,
+          const double* __restrict__ r, const double* __restrict__ q,
+          double* __restrict__ z, CGScalars* __restrict__ sc,
+          double* __restrict__ beta_hist, double* __restrict__ part,
+          unsigned int* __restrict__ counter) {
+  __shared__ double red[256 / 64 + 1];
+  __shared__ unsigned int ticket;
+  if (MODE != 0 && sc->done) return;
+  const long long node = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long nn = (long long)g.nnx * g.nny;
+  double d_rz = 0.0, d_zq = 0.0;
+  if (node < nn) {
+    const int x = (int)(node % g.nnx), y = (int)(node / g.nnx);
+    double z0 = 0.0, z1 = 0.0;
+    if (ca.use_l1) {
+      const int gx0 = x / g.sx, gy0 = y / g.sy;
+      for (int gy = gy0 - 1; gy <= gy0 + 1; ++gy) {
+        if (gy < 0 || gy >= ca.ngy) continue;
+        for (int gx = gx0 - 1; gx <= gx0 + 1; ++gx) {
+          if (gx < 0 || gx >= ca.ngx) continue;
+          const int sid = ca.sub_grid[gy * ca.ngx + gx];
+          if (sid < 0) continue;
+          const SysDesc s = ca.sys[sid];
+          if (x < s.x0 || x >= s.x0 + s.nxb || y < s.y0 || y >= s.y0 + s.nyb) continue;
+          const long long li = s.voff + 2 * ((long long)(y - s.y0) * s.nxb + (x - s.x0));
+          if (ca.lsol_fp32) {
+            const float* ls = (const float*)ca.lsol;
+            z0 += (double)ls[li];
+            z1 += (double)ls[li + 1];
+          } else {
+            const double* ls = (const double*)ca.lsol;
+            z0 += ls[li];
+            z1 += ls[li + 1];
+          }
+        }
+      }
+    }
+    if (ca.use_coarse) {
+      const int cx0 = x / g.sx, cy0 = y / g.sy;
+      for (int cy = cy0; cy <= cy0 + 1; ++cy) {
+        if (cy >= g.ncy) continue;
+        for (int cx = cx0; cx <= cx0 + 1; ++cx) {
+          if (cx >= g.ncx) continue;
+          const CoarseNode cn = ca.cnodes[cy * g.ncx + cx];
+          const int ncol = 2 * cn.nmodes + cn.nrot;
+          if (ncol == 0) continue;
+          const double chi = chi_at(g, cx, cy, x, y);
+          if (chi == 0.0) continue;
+          const int nw = cn.nxw * cn.nyw;
+          const int loc = (y - cn.y0) * cn.nxw + (x - cn.x0);
+          double s0 = 0.0, s1 = 0.0;
+          for (int j = 0; j < cn.nmodes; ++j) {
+            const double ps = ca.psi[cn.psi_off + (long long)j * nw + loc];
+            s0 += ps * ca.c0[cn.col0 + j];
+            s1 += ps * ca.c0[cn.col0 + cn.nmodes + j];
+          }
+          s0 *= chi;
+          s1 *= chi;
+          if (cn.nrot) {
+            const double rx = (x - cx * g.sx) * g.h * ca.invH;
+            const double ry = (y - cy * g.sy) * g.h * ca.invH;
+            const double cr = ca.c0[cn.col0 + 2 * cn.nmodes];
+            s0 += -chi * ry * cr;
+            s1 += chi * rx * cr;
+          }
+          z0 += s0;
+          z1 += s1;
+        }
+      }
+    }
+    const uchar2 m = reinterpret_cast<const uchar2*>(mask)[node];
+    if (m.x) z0 = 0.0;
+    if (m.y) z1 = 0.0;
+    reinterpret_cast<double2*>(z)[node] = make_double2(z0, z1);
+    if (MODE != 0) {
+      const double2 rv = reinterpret_cast<const double2*>(r)[node];
+      d_rz = rv.x * z0 + rv.y * z1;
+      if (MODE == 1 && sc->flexible) {
+        const double2 qv = reinterpret_cast<const double2*>(q)[node];
+        d_zq = qv.x * z0 + qv.y * z1;
+      }
+    }
+  }
+  if (MODE == 0) return;
+  const unsigned int nb = gridDim.x;
+  const double s_rz = block_sum<256>(d_rz, red);
+  const double s_zq = block_sum<256>(d_zq, red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s_rz;
+    part[nb + blockIdx.x] = s_zq;
+  }
+  if (!last_block(counter, nb, &ticket)) return;
+  const double rz = reduce_partials<256>(part, nb, 1, red);
+  const double zq = reduce_partials<256>(part + nb, nb, 1, red);
+  if (threadIdx.x == 0) {
+    if (MODE == 2) {
+      sc->rz = rz;
+      sc->beta = 0.0;
+    } else {
+      const double rz_old = sc->rz;
+      double beta = sc->flexible ? (-sc->alpha * zq / rz_old) : (rz / rz_old);
+      if (!finite(beta)) {
+        sc->done = DONE_BREAKDOWN;
+        sc->status = -5;
+        beta = 0.0;
+      }
+      sc->zq = zq;
+      sc->rz_old = rz_old;
+      sc->rz = rz;
+      sc->beta = beta;
+      const int it = sc->iter;
+      if (it >= 1 && it <= sc->maxit) beta_hist[it - 1] = beta;
+    }
+    *counter = 0u;
+  }
+}
+
+// Dense export of the coarse basis (column-major n x Nc).
+__global__ void __launch_bounds__(CK_NT)
+k_export_basis(Geom g, const CoarseNode* __restrict__ cnodes,
+               const int* __restrict__ col_node,
+               const uint8_t* __restrict__ mask, const double* __restrict__ psi,
+               double* __restrict__ out, double invH) {
+  const int col = blockIdx.y;
+  const int l = col_node[col];
+  const CoarseNode cn = cnodes[l];
+  const int lc = col - cn.col0;
+  const long long nn = (long long)g.nnx * g.nny;
+  const long long node = (long long)blockIdx.x * CK_NT + threadIdx.x;
+  if (node >= nn) return;
+  const int x = (int)(node % g.nnx), y = (int)(node / g.nnx);
+  const double2 v = phi_at(g, cn, psi, mask, lc, x, y, invH);
+  out[(long long)col * 2 * nn + 2 * node] = v.x;
+  out[(long long)col * 2 * nn + 2 * node + 1] = v.y;
+}
+
+// ---------------------------------------------------------------- launchers
+
+void launch_coarse_kphi(const Geom& g, const CoarseNode* cn, const int* col_node,
+                        int ncols, const double* Ke, const double* E,
+                        const uint8_t* mask, const double* psi, double* W,
+                        double invH, hipStream_t s) {
+  if (ncols <= 0) return;
+  hipLaunchKernelGGL(k_coarse_kphi, dim3(ncols), dim3(CK_NT), 0, s, g, cn,
+                     col_node, Ke, E, mask, psi, W, invH);
+}
+
+void launch_coarse_k0(const Geom& g, const CoarseNode* cn, const int2* pairs,
+                      int npairs, const uint8_t* mask, const double* psi,
+                      const double* W, double* K0, int ldk, double invH,
+                      hipStream_t s) {
+  if (npairs <= 0) return;
+  hipLaunchKernelGGL(k_coarse_k0, dim3(npairs), dim3(CK_NT), 0, s, g, cn, pairs,
+                     mask, psi, W, K0, ldk, invH);
+}
+
+void launch_k0_pinv(double* K0, int ldk, int nc, double* sdiag, double* P,
+                    double* Lp, double* Rp, double tol, int* dropped,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_k0_scale_factors, dim3((ldk + 255) / 256), dim3(256), 0,
+                     s, K0, ldk, nc, sdiag);
+  const long long n2 = (long long)ldk * ldk;
+  hipLaunchKernelGGL(k_k0_scale, dim3((unsigned)((n2 + 255) / 256)), dim3(256),
+                     0, s, K0, ldk, sdiag);
+  const int nblk = ldk / GJB;
+  for (int kb = 0; kb < nblk; ++kb) {
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(CK_NT), 0, s, K0, ldk, kb, P,
+                       tol, dropped);
+    hipLaunchKernelGGL(k_gj_panel, dim3(nblk), dim3(CK_NT), 0, s, K0, ldk, kb,
+                       P, Lp, Rp);
+    hipLaunchKernelGGL(k_gj_update, dim3(nblk, nblk), dim3(CK_NT), 0, s, K0,
+                       ldk, kb, P, Lp, Rp);
+  }
+  hipLaunchKernelGGL(k_k0_unscale, dim3((unsigned)((n2 + 255) / 256)),
+                     dim3(256), 0, s, K0, ldk, sdiag);
+}
+
+void launch_restrict(const Geom& g, const CoarseNode* cn, int ncn,
+                     const uint8_t* mask, const double* psi, const double* r,
+                     double* c, double invH, const CGScalars* sc,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_restrict, dim3(ncn), dim3(CK_NT), 0, s, g, cn, mask, psi,
+                     r, c, invH, sc);
+}
+
+void launch_coarse_gemv(const double* K0, int ldk, int nc, const double* c,
+                        double* c0, const CGScalars* sc, hipStream_t s) {
+  if (nc <= 0) return;
+  hipLaunchKernelGGL(k_coarse_gemv, dim3((nc + 3) / 4), dim3(256), 0, s, K0,
+                     ldk, nc, c, c0, sc);
+}
+
+int combine_blocks(const Geom& g) {
+  return (int)(((long long)g.nnx * g.nny + 255) / 256);
+}
+
+void launch_combine(int mode, const Geom& g, const CombineArgs& ca,
+                    const uint8_t* mask, const double* r, const double* q,
+                    double* z, CGScalars* sc, double* beta_hist, double* part,
+                    unsigned int* counter, hipStream_t s) {
+  const dim3 grid(combine_blocks(g));
+  if (mode == 0)
+    hipLaunchKernelGGL(k_combine<0>, grid, dim3(256), 0, s, g, ca, mask, r, q, z,
+                       sc, beta_hist, part, counter);
+  else if (mode == 1)
+    hipLaunchKernelGGL(k_combine<1>, grid, dim3(256), 0, s, g, ca, mask, r, q, z,
+                       sc, beta_hist, part, counter);
+  else
+    hipLaunchKernelGGL(k_combine<2>, grid, dim3(256), 0, s, g, ca, mask, r, q, z,
+                       sc, beta_hist, part, counter);
+}
+
+void launch_export_basis(const Geom& g, const CoarseNode* cn,
+                         const int* col_node, int ncols, const uint8_t* mask,
+                         const double* psi, double* out, double invH,
+                         hipStream_t s) {
+  if (ncols <= 0) return;
+  const long long nn = (long long)g.nnx * g.nny;
+  hipLaunchKernelGGL(k_export_basis,
+                     dim3((unsigned)((nn + CK_NT - 1) / CK_NT), ncols),
+                     dim3(CK_NT), 0, s, g, cn, col_node, mask, psi, out, invH);
+}
+
+}  // namespace msp

@@ -1,0 +1,980 @@
+// Host runtime of libmsp: problem geometry, device memory, the setup
+// pipeline of the preconditioner and the PCG driver behind the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "msp.h"
+
+namespace msp {
+// k_vec.hip
+void launch_simp(const double*, double*, int, double, double, double, int*,
+                 hipStream_t);
+int matvec_blocks(const Geom&);
+void launch_apply_K(const Geom&, const double*, const double*, const uint8_t*,
+                    const double*, double*, hipStream_t);
+void launch_cg_matvec(const Geom&, const double*, const double*,
+                      const uint8_t*, const double*, const double*, double*,
+                      double*, CGScalars*, double*, unsigned int*, hipStream_t);
+void launch_residual(const Geom&, const double*, const double*, const uint8_t*,
+                     const double*, const double*, double*, CGScalars*, double*,
+                     unsigned int*, int, hipStream_t);
+int update_blocks(long long);
+void launch_update(long long, double*, double*, const double*, const double*,
+                   CGScalars*, double*, double*, unsigned int*, hipStream_t);
+void launch_dot(long long, const double*, const double*, double*,
+                unsigned int*, double*, hipStream_t);
+void launch_mask(long long, const uint8_t*, double*, hipStream_t);
+// k_local.hip
+void launch_factor_elastic(const Geom&, const SysDesc*, int, const double*,
+                           const uint8_t*, const double*, void*, bool, int*,
+                           hipStream_t);
+void launch_factor_heat(const Geom&, const SysDesc*, int, const double*,
+                        const uint8_t*, const double*, double*, int*,
+                        hipStream_t);
+void launch_level1(const Geom&, const SysDesc*, int, const double*,
+                   const uint8_t*, const double*, const void*, const double*,
+                   void*, bool, const CGScalars*, hipStream_t);
+void launch_heat_eigen(const Geom&, const SysDesc*, int, const double*,
+                       const uint8_t*, const double*, const double*,
+                       const double*, const double*, double*, double*, double*,
+                       int, int, int, int, double, double, double*, double*,
+                       int*, int*, int*, hipStream_t);
+// k_coarse.hip
+
+void launch_coarse_kphi(const Geom&, const CoarseNode*, const int*, int,
+                        const double*, const double*, const uint8_t*,
+                        const double*, double*, double, hipStream_t);
+void launch_coarse_k0(const Geom&, const CoarseNode*, const int2*, int,
+                      const uint8_t*, const double*, const double*, double*,
+                      int, double, hipStream_t);
+void launch_k0_pinv(double*, int, int, double*, double*, double*, double*,
+                    double, int*, hipStream_t);
+void launch_restrict(const Geom&, const CoarseNode*, int, const uint8_t*,
+                     const double*, const double*, double*, double,
+                     const CGScalars*, hipStream_t);
+void launch_coarse_gemv(const double*, int, int, const double*, double*,
+                        const CGScalars*, hipStream_t);
+int combine_blocks(const Geom&);
+void launch_combine(int, const Geom&, const CombineArgs&, const uint8_t*,
+                    const double*, const double*, double*, CGScalars*, double*,
+                    double*, unsigned int*, hipStream_t);
+void launch_export_basis(const Geom&, const CoarseNode*, const int*, int,
+                         const uint8_t*, const double*, double*, double,
+                         hipStream_t);
+// elements.cpp
+void q1_element_matrices(double nu, double h, double* Ke, double* Ae,
+                         double* Me);
+}  // namespace msp
+
+using namespace msp;
+
+namespace {
+
+// Tunables of the heat eigen setup.
+constexpr double kShift = 0.05;      // sigma = kShift / H^2 in C = A + sigma M
+constexpr int kEigExtra = 8;         // subspace block m = kmax + kEigExtra
+constexpr int kEigMaxIt = 48;
+constexpr int kEigRR = 4;
+constexpr double kEigTol = 1e-10;
+constexpr double kPivotDrop = 1e-12; // scaled K_0 pivots at or below: dropped
+constexpr int kChunk = 16;           // PCG iterations between host checks
+constexpr int kMaxRestarts = 3;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct msp_handle {
+  msp_problem_desc desc;
+  Geom g;
+  std::string err;
+  long long n_dofs = 0, n_nodes = 0, n_elems = 0;
+  double H = 1.0, invH = 1.0;
+  bool fp32 = false;
+
+  std::vector<uint8_t> mask_h;
+  std::vector<SysDesc> subs, omegas;
+  std::vector<int> sub_grid;
+  int ngx = 0, ngy = 0;
+  std::vector<CoarseNode> cn_h;
+  long long l1_entries = 0, l1_vec = 0, om_entries = 0, om_vec = 0;
+
+  double Ke[64], Ae[16], Me[16], Ce[16];
+
+  // device
+  double *d_elem = nullptr;             // Ke | Ae | Me | Ce
+  uint8_t *d_mask = nullptr, *d_dflag = nullptr;
+  double* d_E = nullptr;
+  SysDesc *d_subs = nullptr, *d_omegas = nullptr;
+  int* d_sub_grid = nullptr;
+  void* d_Sinv = nullptr;
+  void* d_lsol = nullptr;
+  double* d_Som = nullptr;
+  double *d_X = nullptr, *d_Y = nullptr, *d_Z = nullptr;
+  double *d_psi = nullptr, *d_lam = nullptr;
+  int *d_nsel = nullptr, *d_cap = nullptr;
+  CoarseNode* d_cn = nullptr;
+  int* d_col_node = nullptr;
+  int2* d_pairs = nullptr;
+  size_t col_cap = 0, pair_cap = 0;
+  double* d_W = nullptr;
+  size_t w_cap = 0;
+  double* d_K0 = nullptr;
+  int ldk_cap = 0;
+  double *d_sdiag = nullptr, *d_P = nullptr, *d_Lp = nullptr, *d_Rp = nullptr;
+  int* d_dropped = nullptr;
+  double *d_c = nullptr, *d_c0 = nullptr;
+  double *d_x = nullptr, *d_r = nullptr, *d_p0 = nullptr, *d_p1 = nullptr,
+         *d_q = nullptr, *d_z = nullptr, *d_tmp = nullptr;
+  CGScalars* d_sc = nullptr;
+  double *d_ahist = nullptr, *d_bhist = nullptr;
+  int hist_cap = 0;
+  double* d_part = nullptr;
+  unsigned int* d_cnt = nullptr;   // 8 counters
+  int* d_err = nullptr;
+  // pinned host
+  CGScalars* h_sc = nullptr;
+  int* h_int = nullptr;            // scratch ints
+  double* h_dbl = nullptr;
+
+  bool have_E = false, setup_ok = false;
+  int nc = 0, ldk = 0, rank = 0, cap_hits = 0;
+  std::vector<int> nsel_h;
+  std::vector<double> lam_h;
+  double t_setup_ms = 0.0;
+};
+
+namespace {
+
+thread_local std::string g_static_err;
+
+msp_status fail(msp_handle* h, msp_status st, const std::string& msg) {
+  if (h) h->err = msg; else g_static_err = msg;
+  return st;
+}
+
+#define HIPCHK(h, call)                                                    \
+  do {                                                                     \
+    hipError_t e_ = (call);                                                \
+    if (e_ != hipSuccess)                                                  \
+      return fail((h), MSP_E_DEVICE,                                       \
+                  std::string(#call " failed: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void**)p, count * sizeof(T));
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+// Subdomain node box along one axis for element range [e_lo, e_hi):
+// strictly interior nodes plus nodes on the physical boundary.
+void node_range(int e_lo, int e_hi, int nel, int* lo, int* hi) {
+  *lo = (e_lo == 0) ? 0 : e_lo + 1;
+  *hi = (e_hi == nel) ? nel : e_hi - 1;
+}
+
+bool node_clamped(const msp_handle* h, int x, int y) {
+  const long long p = (long long)y * h->g.nnx + x;
+  return h->mask_h[2 * p] && h->mask_h[2 * p + 1];
+}
+
+msp_status build_geometry(msp_handle* h) {
+  const Geom& g = h->g;
+  const int S = g.sx, Sy = g.sy, delta = h->desc.overlap;
+  const int nbx = g.nx / S, nby = g.ny / Sy;
+  // subdomains
+  h->subs.clear();
+  long long foff = 0, voff = 0;
+  auto add_sub = [&](int elx0, int elx1, int ely0, int ely1) -> int {
+    SysDesc s{};
+    int xlo, xhi, ylo, yhi;
+    node_range(elx0, elx1, g.nx, &xlo, &xhi);
+    node_range(ely0, ely1, g.ny, &ylo, &yhi);
+    s.x0 = xlo;
+    s.y0 = ylo;
+    s.nxb = xhi - xlo + 1;
+    s.nyb = yhi - ylo + 1;
+    s.ex0 = 0;
+    s.ex1 = g.nx;
+    s.ey0 = 0;
+    s.ey1 = g.ny;
+    s.foff = foff;
+    s.voff = voff;
+    const long long bs = 2LL * s.nxb;
+    foff += (long long)s.nyb * bs * bs;
+    voff += (long long)s.nyb * bs;
+    h->subs.push_back(s);
+    return (int)h->subs.size() - 1;
+  };
+  if (h->desc.sub_mode == 0) {
+    h->ngx = nbx;
+    h->ngy = nby;
+    h->sub_grid.assign((size_t)nbx * nby, -1);
+    for (int by = 0; by < nby; ++by)
+      for (int bx = 0; bx < nbx; ++bx) {
+        const int id = add_sub(std::max(0, bx * S - delta),
+                               std::min(g.nx, (bx + 1) * S + delta),
+                               std::max(0, by * Sy - delta),
+                               std::min(g.ny, (by + 1) * Sy + delta));
+        h->sub_grid[by * nbx + bx] = id;
+      }
+  } else {
+    h->ngx = g.ncx;
+    h->ngy = g.ncy;
+    h->sub_grid.assign((size_t)g.ncx * g.ncy, -1);
+    for (int cy = 0; cy < g.ncy; ++cy)
+      for (int cx = 0; cx < g.ncx; ++cx) {
+        if (node_clamped(h, cx * S, cy * Sy)) continue;
+        const int id = add_sub(std::max(0, (cx - 1) * S),
+                               std::min(g.nx, (cx + 1) * S),
+                               std::max(0, (cy - 1) * Sy),
+                               std::min(g.ny, (cy + 1) * Sy));
+        h->sub_grid[cy * g.ncx + cx] = id;
+      }
+  }
+  h->l1_entries = foff;
+  h->l1_vec = voff;
+  for (const SysDesc& s : h->subs) {
+    if (2 * s.nxb > MAXBS)
+      return fail(h, MSP_E_INVALID, "subdomain row exceeds 72 DOFs (reduce sub_nel + 2*overlap)");
+    if ((long long)s.nyb * 2 * s.nxb > MAXBS * 40)
+      return fail(h, MSP_E_INVALID, "subdomain exceeds 2880 DOFs");
+    if (s.nxb <= 0 || s.nyb <= 0)
+      return fail(h, MSP_E_INVALID, "empty subdomain");
+  }
+  // coverage of every free DOF
+  {
+    std::vector<uint8_t> cov((size_t)g.nnx * g.nny, 0);
+    for (const SysDesc& s : h->subs)
+      for (int y = s.y0; y < s.y0 + s.nyb; ++y)
+        for (int x = s.x0; x < s.x0 + s.nxb; ++x) cov[(size_t)y * g.nnx + x] = 1;
+    for (long long p = 0; p < (long long)g.nnx * g.nny; ++p)
+      if (!cov[p] && (!h->mask_h[2 * p] || !h->mask_h[2 * p + 1]))
+        return fail(h, MSP_E_INVALID, "subdomains do not cover every free DOF (overlap too small)");
+  }
+  // coarse neighbourhoods omega_l
+  h->omegas.clear();
+  h->cn_h.clear();
+  foff = 0;
+  voff = 0;
+  for (int cy = 0; cy < g.ncy; ++cy)
+    for (int cx = 0; cx < g.ncx; ++cx) {
+      SysDesc s{};
+      const int ex0 = std::max(0, (cx - 1) * S), ex1 = std::min(g.nx, (cx + 1) * S);
+      const int ey0 = std::max(0, (cy - 1) * Sy), ey1 = std::min(g.ny, (cy + 1) * Sy);
+      s.x0 = ex0;
+      s.y0 = ey0;
+      s.nxb = ex1 - ex0 + 1;
+      s.nyb = ey1 - ey0 + 1;
+      s.ex0 = ex0;
+      s.ex1 = ex1;
+      s.ey0 = ey0;
+      s.ey1 = ey1;
+      s.foff = foff;
+      s.voff = voff;
+      foff += (long long)s.nyb * s.nxb * s.nxb;
+      voff += (long long)s.nxb * s.nyb;
+      if (s.nxb > MAXBS)
+        return fail(h, MSP_E_INVALID, "coarse neighbourhood row exceeds 72 nodes (sub_nel too large)");
+      h->omegas.push_back(s);
+      CoarseNode c{};
+      c.cx = cx;
+      c.cy = cy;
+      c.x0 = s.x0;
+      c.y0 = s.y0;
+      c.nxw = s.nxb;
+      c.nyw = s.nyb;
+      c.sys = (int)h->omegas.size() - 1;
+      h->cn_h.push_back(c);
+    }
+  h->om_entries = foff;
+  h->om_vec = voff;
+  return MSP_OK;
+}
+
+// Eigenvalues of a symmetric tridiagonal matrix (bisection with Sturm
+// counts): smallest and largest.
+void tridiag_extremes(const std::vector<double>& d, const std::vector<double>& e,
+                      double* lo, double* hi) {
+  const int n = (int)d.size();
+  double gl = d[0], gu = d[0];
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i < n - 1 ? std::fabs(e[i]) : 0.0);
+    gl = std::min(gl, d[i] - r);
+    gu = std::max(gu, d[i] + r);
+  }
+  auto count_below = [&](double x) {
+    int c = 0;
+    double q = d[0] - x;
+    if (q < 0) ++c;
+    for (int i = 1; i < n; ++i) {
+      if (q == 0.0) q = 1e-300;
+      q = d[i] - x - e[i - 1] * e[i - 1] / q;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  auto kth = [&](int k) {   // k-th smallest (0-based)
+    double a = gl, b = gu;
+    for (int it = 0; it < 200; ++it) {
+      const double m = 0.5 * (a + b);
+      if (count_below(m) > k) b = m; else a = m;
+      if (b - a <= 1e-15 * std::max(std::fabs(a), std::fabs(b))) break;
+    }
+    return 0.5 * (a + b);
+  };
+  *lo = kth(0);
+  *hi = kth(n - 1);
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------- API
+
+extern "C" const char* msp_last_error(const msp_handle* h) {
+  return h ? h->err.c_str() : g_static_err.c_str();
+}
+
+extern "C" msp_status msp_destroy(msp_handle* h) {
+  if (!h) return MSP_OK;
+  void* bufs[] = {h->d_elem, h->d_mask, h->d_dflag, h->d_E, h->d_subs,
+                  h->d_omegas, h->d_sub_grid, h->d_Sinv, h->d_lsol, h->d_Som,
+                  h->d_X, h->d_Y, h->d_Z, h->d_psi, h->d_lam, h->d_nsel,
+                  h->d_cap, h->d_cn, h->d_col_node, h->d_pairs, h->d_W,
+                  h->d_K0, h->d_sdiag, h->d_P, h->d_Lp, h->d_Rp, h->d_dropped,
+                  h->d_c, h->d_c0, h->d_x, h->d_r, h->d_p0, h->d_p1, h->d_q,
+                  h->d_z, h->d_tmp, h->d_sc, h->d_ahist, h->d_bhist,
+                  h->d_part, h->d_cnt, h->d_err};
+  for (void* p : bufs) dfree(p);
+  if (h->h_sc) (void)hipHostFree(h->h_sc);
+  if (h->h_int) (void)hipHostFree(h->h_int);
+  if (h->h_dbl) (void)hipHostFree(h->h_dbl);
+  delete h;
+  return MSP_OK;
+}
+
+extern "C" msp_status msp_create(const msp_problem_desc* d,
+                                 const uint8_t* fixed_mask_host,
+                                 msp_handle** out) {
+  if (!d || !out || !fixed_mask_host)
+    return fail(nullptr, MSP_E_INVALID, "null argument");
+  *out = nullptr;
+  if (d->dim != 2)
+    return fail(nullptr, MSP_E_INVALID, "only dim = 2 (Q1 plane stress) is built in this library");
+  if (d->nel[0] <= 0 || d->nel[1] <= 0 || d->sub_nel[0] <= 0 || d->sub_nel[1] <= 0)
+    return fail(nullptr, MSP_E_INVALID, "mesh and block sizes must be positive");
+  if (d->nel[0] % d->sub_nel[0] || d->nel[1] % d->sub_nel[1])
+    return fail(nullptr, MSP_E_INVALID, "nel must be a multiple of sub_nel");
+  if (d->overlap < 0 || d->overlap >= std::min(d->sub_nel[0], d->sub_nel[1]))
+    return fail(nullptr, MSP_E_INVALID, "overlap must satisfy 0 <= overlap < sub_nel");
+  if (!(d->Emin > 0.0) || !(d->E0 >= d->Emin) || !std::isfinite(d->E0))
+    return fail(nullptr, MSP_E_INVALID, "need 0 < Emin <= E0");
+  if (!(d->nu > -1.0 && d->nu < 0.5))
+    return fail(nullptr, MSP_E_INVALID, "nu must lie in (-1, 0.5)");
+  if (!(d->penal >= 1.0)) return fail(nullptr, MSP_E_INVALID, "penal must be >= 1");
+  if (!(d->h > 0.0)) return fail(nullptr, MSP_E_INVALID, "h must be positive");
+  if (!(d->eig_tau > 0.0)) return fail(nullptr, MSP_E_INVALID, "eig_tau must be positive");
+  if (d->eig_kmax < 1 || d->eig_kmax > 24)
+    return fail(nullptr, MSP_E_INVALID, "eig_kmax must lie in 1..24");
+  if (d->sub_mode != 0 && d->sub_mode != 1)
+    return fail(nullptr, MSP_E_INVALID, "sub_mode must be 0 or 1");
+  if (d->precision != 0 && d->precision != 1)
+    return fail(nullptr, MSP_E_INVALID, "precision must be 0 or 1");
+
+  msp_handle* h = new msp_handle();
+  h->desc = *d;
+  Geom& g = h->g;
+  g.nx = d->nel[0];
+  g.ny = d->nel[1];
+  g.nnx = g.nx + 1;
+  g.nny = g.ny + 1;
+  g.sx = d->sub_nel[0];
+  g.sy = d->sub_nel[1];
+  g.ncx = g.nx / g.sx + 1;
+  g.ncy = g.ny / g.sy + 1;
+  g.h = d->h;
+  h->n_nodes = (long long)g.nnx * g.nny;
+  h->n_dofs = 2 * h->n_nodes;
+  h->n_elems = (long long)g.nx * g.ny;
+  h->H = std::max(g.sx, g.sy) * d->h;
+  h->invH = 1.0 / h->H;
+  h->fp32 = d->precision == 1;
+  h->mask_h.assign(fixed_mask_host, fixed_mask_host + h->n_dofs);
+  for (auto& m : h->mask_h) m = m ? 1 : 0;
+  // the GPU heat pencils use one Dirichlet set per node: a node is either
+  // fully clamped or free in every component
+  for (long long p = 0; p < h->n_nodes; ++p)
+    if (h->mask_h[2 * p] != h->mask_h[2 * p + 1]) {
+      msp_destroy(h);
+      return fail(nullptr, MSP_E_INVALID, "partially clamped nodes are not supported");
+    }
+  msp_status st = build_geometry(h);
+  if (st != MSP_OK) {
+    g_static_err = h->err;
+    msp_destroy(h);
+    return st;
+  }
+  q1_element_matrices(d->nu, d->h, h->Ke, h->Ae, h->Me);
+  const double sigma = kShift / (h->H * h->H);
+  for (int i = 0; i < 16; ++i) h->Ce[i] = h->Ae[i] + sigma * h->Me[i];
+
+  const long long nd = h->n_dofs, nn = h->n_nodes;
+  const int m = std::min(d->eig_kmax + kEigExtra, MAXM);
+  const size_t esz = h->fp32 ? sizeof(float) : sizeof(double);
+  const int nparts = std::max(std::max(matvec_blocks(g), update_blocks(nd)),
+                              std::max(combine_blocks(g), 1024)) * 3 + 16;
+  bool ok = true;
+  auto A = [&](hipError_t e) { if (e != hipSuccess) ok = false; };
+  A(dalloc(&h->d_elem, 64 + 16 * 3));
+  A(dalloc(&h->d_mask, nd));
+  A(dalloc(&h->d_dflag, nn));
+  A(dalloc(&h->d_E, h->n_elems));
+  A(dalloc(&h->d_subs, h->subs.size()));
+  A(dalloc(&h->d_omegas, h->omegas.size()));
+  A(dalloc(&h->d_sub_grid, h->sub_grid.size()));
+  A(hipMalloc(&h->d_Sinv, std::max<size_t>(1, h->l1_entries * esz)));
+  A(hipMalloc(&h->d_lsol, std::max<size_t>(1, h->l1_vec * esz)));
+  A(dalloc(&h->d_Som, h->om_entries));
+  A(dalloc(&h->d_X, h->om_vec * m));
+  A(dalloc(&h->d_Y, h->om_vec * m));
+  A(dalloc(&h->d_Z, h->om_vec * m));
+  A(dalloc(&h->d_psi, h->om_vec * d->eig_kmax));
+  A(dalloc(&h->d_lam, h->omegas.size() * d->eig_kmax));
+  A(dalloc(&h->d_nsel, h->omegas.size()));
+  A(dalloc(&h->d_cap, h->omegas.size()));
+  A(dalloc(&h->d_cn, h->cn_h.size()));
+  A(dalloc(&h->d_x, nd));
+  A(dalloc(&h->d_r, nd));
+  A(dalloc(&h->d_p0, nd));
+  A(dalloc(&h->d_p1, nd));
+  A(dalloc(&h->d_q, nd));
+  A(dalloc(&h->d_z, nd));
+  A(dalloc(&h->d_tmp, nd));
+  A(dalloc(&h->d_sc, 1));
+  A(dalloc(&h->d_part, nparts));
+  A(dalloc(&h->d_cnt, 8));
+  A(dalloc(&h->d_err, 4));
+  A(dalloc(&h->d_dropped, 1));
+  A(hipHostMalloc((void**)&h->h_sc, sizeof(CGScalars)));
+  A(hipHostMalloc((void**)&h->h_int, 64 * sizeof(int)));
+  A(hipHostMalloc((void**)&h->h_dbl, 64 * sizeof(double)));
+  if (!ok) {
+    msp_destroy(h);
+    return fail(nullptr, MSP_E_NOMEM, "device allocation failed");
+  }
+  std::vector<double> elem(64 + 48);
+  std::memcpy(elem.data(), h->Ke, 64 * sizeof(double));
+  std::memcpy(elem.data() + 64, h->Ae, 16 * sizeof(double));
+  std::memcpy(elem.data() + 80, h->Me, 16 * sizeof(double));
+  std::memcpy(elem.data() + 96, h->Ce, 16 * sizeof(double));
+  std::vector<uint8_t> dflag(nn);
+  for (long long p = 0; p < nn; ++p) dflag[p] = h->mask_h[2 * p] & h->mask_h[2 * p + 1];
+  hipError_t e = hipSuccess;
+  auto C = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
+  C(hipMemcpy(h->d_elem, elem.data(), elem.size() * sizeof(double), hipMemcpyHostToDevice));
+  C(hipMemcpy(h->d_mask, h->mask_h.data(), nd, hipMemcpyHostToDevice));
+  C(hipMemcpy(h->d_dflag, dflag.data(), nn, hipMemcpyHostToDevice));
+  C(hipMemcpy(h->d_subs, h->subs.data(), h->subs.size() * sizeof(SysDesc), hipMemcpyHostToDevice));
+  C(hipMemcpy(h->d_omegas, h->omegas.data(), h->omegas.size() * sizeof(SysDesc), hipMemcpyHostToDevice));
+  C(hipMemcpy(h->d_sub_grid, h->sub_grid.data(), h->sub_grid.size() * sizeof(int), hipMemcpyHostToDevice));
+  C(hipMemset(h->d_cnt, 0, 8 * sizeof(unsigned int)));
+  C(hipMemset(h->d_err, 0, 4 * sizeof(int)));
+  if (e != hipSuccess) {
+    std::string msg = std::string("device copy failed: ") + hipGetErrorString(e);
+    msp_destroy(h);
+    return fail(nullptr, MSP_E_DEVICE, msg);
+  }
+  *out = h;
+  return MSP_OK;
+}
+
+extern "C" msp_status msp_set_densities(msp_handle* h, const double* rho,
+                                        hipStream_t s) {
+  if (!h || !rho) return fail(h, MSP_E_INVALID, "null argument");
+  HIPCHK(h, hipMemsetAsync(h->d_err, 0, sizeof(int), s));
+  launch_simp(rho, h->d_E, (int)h->n_elems, h->desc.E0, h->desc.Emin,
+              h->desc.penal, h->d_err, s);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(h->h_int, h->d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  if (h->h_int[0] & ERR_RANGE) {
+    h->have_E = false;
+    h->setup_ok = false;
+    return fail(h, MSP_E_INVALID, "densities must be finite and lie in [0, 1]");
+  }
+  h->have_E = true;
+  h->setup_ok = false;
+  return MSP_OK;
+}
+
+static msp_status ensure_coarse_buffers(msp_handle* h, size_t ncols,
+                                        size_t npairs, size_t wsize, int ldk) {
+  if (ncols > h->col_cap) {
+    dfree(h->d_col_node);
+    HIPCHK(h, dalloc(&h->d_col_node, ncols + 64));
+    dfree(h->d_c);
+    dfree(h->d_c0);
+    HIPCHK(h, dalloc(&h->d_c, ncols + 64));
+    HIPCHK(h, dalloc(&h->d_c0, ncols + 64));
+    h->col_cap = ncols + 64;
+  }
+  if (npairs > h->pair_cap) {
+    dfree(h->d_pairs);
+    HIPCHK(h, dalloc(&h->d_pairs, npairs));
+    h->pair_cap = npairs;
+  }
+  if (wsize > h->w_cap) {
+    dfree(h->d_W);
+    HIPCHK(h, dalloc(&h->d_W, wsize));
+    h->w_cap = wsize;
+  }
+  if (ldk > h->ldk_cap) {
+    dfree(h->d_K0);
+    dfree(h->d_sdiag);
+    dfree(h->d_Lp);
+    dfree(h->d_Rp);
+    if (!h->d_P) HIPCHK(h, dalloc(&h->d_P, 64 * 64));
+    HIPCHK(h, dalloc(&h->d_K0, (size_t)ldk * ldk));
+    HIPCHK(h, dalloc(&h->d_sdiag, ldk));
+    HIPCHK(h, dalloc(&h->d_Lp, (size_t)ldk * 64));
+    HIPCHK(h, dalloc(&h->d_Rp, (size_t)ldk * 64));
+    h->ldk_cap = ldk;
+  }
+  return MSP_OK;
+}
+
+extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
+  if (!h) return fail(h, MSP_E_INVALID, "null handle");
+  if (!h->have_E) return fail(h, MSP_E_STATE, "msp_set_densities must come first");
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  HIPCHK(h, hipEventRecord(e0, s));
+  const Geom& g = h->g;
+  const double* Ke = h->d_elem;
+  const double* Ae = h->d_elem + 64;
+  const double* Me = h->d_elem + 80;
+  const double* Ce = h->d_elem + 96;
+  const int kmax = h->desc.eig_kmax;
+  const int m = std::min(kmax + kEigExtra, MAXM);
+  HIPCHK(h, hipMemsetAsync(h->d_err, 0, sizeof(int), s));
+  launch_factor_elastic(g, h->d_subs, (int)h->subs.size(), h->d_E, h->d_mask,
+                        Ke, h->d_Sinv, h->fp32, h->d_err, s);
+  launch_factor_heat(g, h->d_omegas, (int)h->omegas.size(), h->d_E,
+                     h->d_dflag, Ce, h->d_Som, h->d_err, s);
+  launch_heat_eigen(g, h->d_omegas, (int)h->omegas.size(), h->d_E, h->d_dflag,
+                    Ae, Me, Ce, h->d_Som, h->d_X, h->d_Y, h->d_Z, m, kmax,
+                    kEigMaxIt, kEigRR, h->desc.eig_tau / (h->H * h->H), kEigTol,
+                    h->d_psi, h->d_lam, h->d_nsel, h->d_cap, h->d_err, s);
+  HIPCHK(h, hipGetLastError());
+  const size_t nom = h->omegas.size();
+  h->nsel_h.resize(nom);
+  std::vector<int> cap(nom);
+  h->lam_h.resize(nom * kmax);
+  HIPCHK(h, hipMemcpyAsync(h->h_int, h->d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  HIPCHK(h, hipMemcpy(h->nsel_h.data(), h->d_nsel, nom * sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(h, hipMemcpy(cap.data(), h->d_cap, nom * sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(h, hipMemcpy(h->lam_h.data(), h->d_lam, nom * kmax * sizeof(double), hipMemcpyDeviceToHost));
+  const int kerr = h->h_int[0];
+  if (kerr & ERR_NOT_SPD) {
+    h->setup_ok = false;
+    return fail(h, MSP_E_NOT_SPD, "a local pivot was not positive (floating region with Emin too small?)");
+  }
+  if (kerr & ERR_EIG) {
+    h->setup_ok = false;
+    return fail(h, MSP_E_NOT_SPD, "heat eigen setup lost positive definiteness of the subspace Gram matrix");
+  }
+  // coarse column layout
+  const int rot = h->desc.rot_enrich ? 1 : 0;
+  int col = 0;
+  long long woff = 0;
+  std::vector<int> col_node;
+  h->cap_hits = 0;
+  for (size_t l = 0; l < h->cn_h.size(); ++l) {
+    CoarseNode& c = h->cn_h[l];
+    const SysDesc& s_ = h->omegas[c.sys];
+    c.nmodes = h->nsel_h[c.sys];
+    c.nrot = (rot && c.nmodes >= 1) ? 1 : 0;
+    c.col0 = col;
+    c.psi_off = s_.voff * (long long)kmax;
+    c.w_off = woff;
+    const int ncol = 2 * c.nmodes + c.nrot;
+    for (int j = 0; j < ncol; ++j) col_node.push_back((int)l);
+    col += ncol;
+    woff += (long long)ncol * 2 * c.nxw * c.nyw;
+    h->cap_hits += cap[c.sys];
+  }
+  h->nc = col;
+  h->ldk = std::max(64, ((col + 63) / 64) * 64);
+  std::vector<int2> pairs;
+  for (size_t l = 0; l < h->cn_h.size(); ++l)
+    for (size_t l2 = 0; l2 < h->cn_h.size(); ++l2) {
+      const CoarseNode &a = h->cn_h[l], &b = h->cn_h[l2];
+      if (std::abs(a.cx - b.cx) <= 1 && std::abs(a.cy - b.cy) <= 1 &&
+          2 * a.nmodes + a.nrot > 0 && 2 * b.nmodes + b.nrot > 0)
+        pairs.push_back(make_int2((int)l, (int)l2));
+    }
+  msp_status st = ensure_coarse_buffers(h, col_node.size(), pairs.size(),
+                                        (size_t)std::max<long long>(woff, 1), h->ldk);
+  if (st != MSP_OK) return st;
+  HIPCHK(h, hipMemcpyAsync(h->d_cn, h->cn_h.data(), h->cn_h.size() * sizeof(CoarseNode), hipMemcpyHostToDevice, s));
+  if (!col_node.empty())
+    HIPCHK(h, hipMemcpyAsync(h->d_col_node, col_node.data(), col_node.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  if (!pairs.empty())
+    HIPCHK(h, hipMemcpyAsync(h->d_pairs, pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+  launch_coarse_kphi(g, h->d_cn, h->d_col_node, col, Ke, h->d_E, h->d_mask,
+                     h->d_psi, h->d_W, h->invH, s);
+  HIPCHK(h, hipMemsetAsync(h->d_K0, 0, (size_t)h->ldk * h->ldk * sizeof(double), s));
+  launch_coarse_k0(g, h->d_cn, h->d_pairs, (int)pairs.size(), h->d_mask,
+                   h->d_psi, h->d_W, h->d_K0, h->ldk, h->invH, s);
+  HIPCHK(h, hipMemsetAsync(h->d_dropped, 0, sizeof(int), s));
+  launch_k0_pinv(h->d_K0, h->ldk, h->nc, h->d_sdiag, h->d_P, h->d_Lp, h->d_Rp,
+                 kPivotDrop, h->d_dropped, s);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(h->h_int + 1, h->d_dropped, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipEventRecord(e1, s));
+  HIPCHK(h, hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->t_setup_ms = ms;
+  h->rank = h->ldk - h->h_int[1];
+  h->setup_ok = true;
+  return MSP_OK;
+}
+
+static CombineArgs combine_args(msp_handle* h, bool l1, bool coarse) {
+  CombineArgs ca;
+  ca.sys = h->d_subs;
+  ca.sub_grid = h->d_sub_grid;
+  ca.ngx = h->ngx;
+  ca.ngy = h->ngy;
+  ca.sub_vertex = h->desc.sub_mode;
+  ca.lsol = h->d_lsol;
+  ca.lsol_fp32 = h->fp32 ? 1 : 0;
+  ca.cnodes = h->d_cn;
+  ca.psi = h->d_psi;
+  ca.c0 = h->d_c0;
+  ca.invH = h->invH;
+  ca.use_l1 = l1 ? 1 : 0;
+  ca.use_coarse = (coarse && h->nc > 0) ? 1 : 0;
+  return ca;
+}
+
+// z = M^{-1} r with the CG scalars (mode 1: iteration, 2: start) or plain.
+static void enqueue_prec(msp_handle* h, int mode, const double* r,
+                         const double* q, double* z, bool l1, bool coarse,
+                         bool use_sc, hipStream_t s) {
+  const Geom& g = h->g;
+  const CGScalars* sc = use_sc ? h->d_sc : nullptr;
+  if (l1)
+    launch_level1(g, h->d_subs, (int)h->subs.size(), h->d_E, h->d_mask,
+                  h->d_elem, h->d_Sinv, r, h->d_lsol, h->fp32, sc, s);
+  if (coarse && h->nc > 0) {
+    launch_restrict(g, h->d_cn, (int)h->cn_h.size(), h->d_mask, h->d_psi, r,
+                    h->d_c, h->invH, sc, s);
+    launch_coarse_gemv(h->d_K0, h->ldk, h->nc, h->d_c, h->d_c0, sc, s);
+  }
+  const CombineArgs ca = combine_args(h, l1, coarse);
+  launch_combine(mode, g, ca, h->d_mask, r, q, z, h->d_sc, h->d_bhist,
+                 h->d_part, h->d_cnt + 2, s);
+}
+
+static msp_status check_ready(msp_handle* h, hipStream_t s) {
+  if (!h) return fail(h, MSP_E_INVALID, "null handle");
+  if (!h->have_E) return fail(h, MSP_E_STATE, "msp_set_densities must come first");
+  if (!h->setup_ok) return msp_setup(h, s);
+  return MSP_OK;
+}
+
+extern "C" msp_status msp_apply_K(msp_handle* h, const double* x, double* y,
+                                  hipStream_t s) {
+  if (!h || !x || !y) return fail(h, MSP_E_INVALID, "null argument");
+  if (!h->have_E) return fail(h, MSP_E_STATE, "msp_set_densities must come first");
+  if (x == y) return fail(h, MSP_E_INVALID, "x and y must not alias");
+  launch_apply_K(h->g, h->d_elem, h->d_E, h->d_mask, x, y, s);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(s));
+  return MSP_OK;
+}
+
+static msp_status apply_parts(msp_handle* h, const double* r, double* z,
+                              bool l1, bool coarse, hipStream_t s) {
+  if (!r || !z) return fail(h, MSP_E_INVALID, "null argument");
+  msp_status st = check_ready(h, s);
+  if (st != MSP_OK) return st;
+  enqueue_prec(h, 0, r, nullptr, z, l1, coarse, false, s);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(s));
+  return MSP_OK;
+}
+
+extern "C" msp_status msp_apply_level1(msp_handle* h, const double* r,
+                                       double* z, hipStream_t s) {
+  return apply_parts(h, r, z, true, false, s);
+}
+extern "C" msp_status msp_apply_coarse(msp_handle* h, const double* r,
+                                       double* z, hipStream_t s) {
+  return apply_parts(h, r, z, false, true, s);
+}
+extern "C" msp_status msp_apply_prec(msp_handle* h, const double* r, double* z,
+                                     hipStream_t s) {
+  return apply_parts(h, r, z, true, true, s);
+}
+
+static msp_status solve_one(msp_handle* h, const double* f, double* u,
+                            int warm, double rtol, int maxit, hipStream_t s,
+                            msp_solve_info* info) {
+  const Geom& g = h->g;
+  const long long nd = h->n_dofs;
+  if (maxit > h->hist_cap) {
+    dfree(h->d_ahist);
+    dfree(h->d_bhist);
+    HIPCHK(h, dalloc(&h->d_ahist, maxit + 8));
+    HIPCHK(h, dalloc(&h->d_bhist, maxit + 8));
+    h->hist_cap = maxit;
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  HIPCHK(h, hipEventRecord(e0, s));
+  if (warm) {
+    HIPCHK(h, hipMemcpyAsync(h->d_x, u, nd * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_mask(nd, h->d_mask, h->d_x, s);      // u = 0 at clamped DOFs
+  } else {
+    HIPCHK(h, hipMemsetAsync(h->d_x, 0, nd * sizeof(double), s));
+  }
+  CGScalars init{};
+  init.tol2 = rtol * rtol;
+  init.maxit = maxit;
+  init.flexible = h->fp32 ? 1 : 0;
+  int total_iters = 0, restarts = 0;
+  int status = MSP_OK;
+  double relres_true = 0.0, relres_rec = 0.0, comp = 0.0;
+  std::vector<double> ah, bh;
+  int seg_iters = 0;
+  for (;;) {
+    // fresh segment: iteration count and histories restart at 0
+    CGScalars seg = init;
+    seg.maxit = std::max(1, maxit - total_iters);
+    *h->h_sc = seg;
+    HIPCHK(h, hipMemcpyAsync(h->d_sc, h->h_sc, sizeof(CGScalars), hipMemcpyHostToDevice, s));
+    // r = f - K x ; ||f|| ; then z = M^{-1} r, p_old = 0
+    launch_residual(g, h->d_elem, h->d_E, h->d_mask, h->d_x, f, h->d_r,
+                    h->d_sc, h->d_part, h->d_cnt + 0, 0, s);
+    HIPCHK(h, hipMemsetAsync(h->d_p0, 0, nd * sizeof(double), s));
+    enqueue_prec(h, 2, h->d_r, nullptr, h->d_z, true, true, true, s);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(CGScalars), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (h->h_sc->ff == 0.0) {
+      HIPCHK(h, hipMemsetAsync(h->d_x, 0, nd * sizeof(double), s));
+      break;
+    }
+    if (h->h_sc->rr <= init.tol2 * h->h_sc->ff) {
+      h->h_sc->done = DONE_CONVERGED;
+    } else {
+      int cur = 0;
+      for (;;) {
+        for (int it = 0; it < kChunk; ++it) {
+          double* pold = cur ? h->d_p1 : h->d_p0;
+          double* pnew = cur ? h->d_p0 : h->d_p1;
+          launch_cg_matvec(g, h->d_elem, h->d_E, h->d_mask, h->d_z, pold, pnew,
+                           h->d_q, h->d_sc, h->d_part, h->d_cnt + 1, s);
+          launch_update(nd, h->d_x, h->d_r, pnew, h->d_q, h->d_sc, h->d_ahist,
+                        h->d_part, h->d_cnt + 3, s);
+          enqueue_prec(h, 1, h->d_r, h->d_q, h->d_z, true, true, true, s);
+          cur ^= 1;
+        }
+        HIPCHK(h, hipGetLastError());
+        HIPCHK(h, hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(CGScalars), hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        if (h->h_sc->done) break;
+      }
+    }
+    const CGScalars fin = *h->h_sc;
+    seg_iters = fin.iter;
+    total_iters += fin.iter;
+    relres_rec = fin.ff > 0 ? std::sqrt(fin.rr / fin.ff) : 0.0;
+    if (fin.iter > 0) {
+      ah.resize(fin.iter);
+      bh.resize(fin.iter);
+      HIPCHK(h, hipMemcpy(ah.data(), h->d_ahist, fin.iter * sizeof(double), hipMemcpyDeviceToHost));
+      HIPCHK(h, hipMemcpy(bh.data(), h->d_bhist, fin.iter * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    if (fin.done == DONE_BREAKDOWN) {
+      status = MSP_E_BREAKDOWN;
+      break;
+    }
+    // true residual and compliance
+    launch_residual(g, h->d_elem, h->d_E, h->d_mask, h->d_x, f, h->d_tmp,
+                    h->d_sc, h->d_part, h->d_cnt + 0, 1, s);
+    HIPCHK(h, hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(CGScalars), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    relres_true = std::sqrt(h->h_sc->rr0 / h->h_sc->ff);
+    comp = h->h_sc->fx;
+    if (relres_true <= rtol) break;
+    if (fin.done == DONE_MAXIT || total_iters >= maxit) {
+      status = MSP_NOT_CONVERGED;
+      break;
+    }
+    if (restarts >= kMaxRestarts) {
+      status = MSP_NOT_CONVERGED;
+      break;
+    }
+    ++restarts;
+  }
+  HIPCHK(h, hipMemcpyAsync(u, h->d_x, nd * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipEventRecord(e1, s));
+  HIPCHK(h, hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  double cond = NAN;
+  if (seg_iters >= 1 && (int)ah.size() >= seg_iters) {
+    std::vector<double> d(seg_iters), e(std::max(0, seg_iters - 1));
+    for (int j = 0; j < seg_iters; ++j) {
+      d[j] = 1.0 / ah[j];
+      if (j > 0) d[j] += bh[j - 1] / ah[j - 1];
+      if (j < seg_iters - 1) e[j] = std::sqrt(std::fabs(bh[j])) / ah[j];
+    }
+    double lo, hi;
+    tridiag_extremes(d, e, &lo, &hi);
+    cond = hi / lo;
+  }
+  if (info) {
+    info->status = status;
+    info->iters = total_iters;
+    info->converged = (status == MSP_OK) ? 1 : 0;
+    info->restarts = restarts;
+    info->n_coarse = h->nc;
+    info->coarse_rank = h->rank;
+    info->cap_hits = h->cap_hits;
+    info->relres_true = relres_true;
+    info->relres_rec = relres_rec;
+    info->compliance = comp;
+    info->cond_est = cond;
+    info->t_solve_ms = ms;
+  }
+  if (status == MSP_E_BREAKDOWN) return fail(h, MSP_E_BREAKDOWN, "PCG breakdown (p^T K p <= 0 or non-finite)");
+  return (msp_status)status;
+}
+
+extern "C" msp_status msp_solve(msp_handle* h, const double* f, double* u,
+                                int32_t nrhs, int32_t warm, double rtol,
+                                int32_t maxit, hipStream_t s,
+                                msp_solve_info* info) {
+  if (!h || !f || !u) return fail(h, MSP_E_INVALID, "null argument");
+  if (nrhs < 1 || maxit < 1 || !(rtol > 0.0))
+    return fail(h, MSP_E_INVALID, "need nrhs >= 1, maxit >= 1, rtol > 0");
+  double t_setup = 0.0;
+  if (!h->have_E) return fail(h, MSP_E_STATE, "msp_set_densities must come first");
+  if (!h->setup_ok) {
+    msp_status st = msp_setup(h, s);
+    if (st != MSP_OK) return st;
+    t_setup = h->t_setup_ms;
+  }
+  msp_status last = MSP_OK;
+  for (int k = 0; k < nrhs; ++k) {
+    msp_status st = solve_one(h, f + (long long)k * h->n_dofs,
+                              u + (long long)k * h->n_dofs, warm, rtol, maxit,
+                              s, info);
+    if (st < 0) return st;
+    if (st != MSP_OK) last = st;
+  }
+  if (info) info->t_setup_ms = t_setup;
+  return last;
+}
+
+extern "C" msp_status msp_coarse_info(msp_handle* h, int32_t* n_modes,
+                                      double* eigvals, int32_t* n_cnodes,
+                                      int32_t* n_coarse, int32_t* cap_hits) {
+  if (!h) return fail(h, MSP_E_INVALID, "null handle");
+  if (!h->setup_ok) return fail(h, MSP_E_STATE, "no setup");
+  const int kmax = h->desc.eig_kmax;
+  for (size_t l = 0; l < h->cn_h.size(); ++l) {
+    const int sys = h->cn_h[l].sys;
+    if (n_modes) n_modes[l] = h->nsel_h[sys];
+    if (eigvals)
+      for (int j = 0; j < kmax; ++j) eigvals[l * kmax + j] = h->lam_h[(size_t)sys * kmax + j];
+  }
+  if (n_cnodes) *n_cnodes = (int32_t)h->cn_h.size();
+  if (n_coarse) *n_coarse = h->nc;
+  if (cap_hits) *cap_hits = h->cap_hits;
+  return MSP_OK;
+}
+
+extern "C" msp_status msp_coarse_basis(msp_handle* h, double* phi,
+                                       hipStream_t s) {
+  if (!h || !phi) return fail(h, MSP_E_INVALID, "null argument");
+  if (!h->setup_ok) return fail(h, MSP_E_STATE, "no setup");
+  launch_export_basis(h->g, h->d_cn, h->d_col_node, h->nc, h->d_mask, h->d_psi,
+                      phi, h->invH, s);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(s));
+  return MSP_OK;
+}
+
+extern "C" msp_status msp_vec_dot(int64_t n, const double* x, const double* y,
+                                  hipStream_t s, double* out) {
+  if (!x || !y || !out || n < 0) return fail(nullptr, MSP_E_INVALID, "bad argument");
+  double* part = nullptr;
+  unsigned int* cnt = nullptr;
+  double* d_out = nullptr;
+  if (dalloc(&part, 1024) != hipSuccess || dalloc(&cnt, 1) != hipSuccess ||
+      dalloc(&d_out, 1) != hipSuccess) {
+    dfree(part);
+    dfree(cnt);
+    dfree(d_out);
+    return fail(nullptr, MSP_E_NOMEM, "allocation failed");
+  }
+  hipError_t e = hipMemsetAsync(cnt, 0, sizeof(unsigned int), s);
+  if (e == hipSuccess) {
+    launch_dot(n, x, y, part, cnt, d_out, s);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dfree(part);
+  dfree(cnt);
+  dfree(d_out);
+  if (e != hipSuccess) return fail(nullptr, MSP_E_DEVICE, hipGetErrorString(e));
+  return MSP_OK;
+}
+
+extern "C" msp_status msp_query(msp_handle* h, int64_t* q) {
+  if (!h || !q) return fail(h, MSP_E_INVALID, "null argument");
+  long long maxsys = 0;
+  for (const SysDesc& s : h->subs) maxsys = std::max(maxsys, 2LL * s.nxb * s.nyb);
+  q[0] = h->n_dofs;
+  q[1] = h->n_elems;
+  q[2] = (int64_t)h->subs.size();
+  q[3] = (int64_t)h->cn_h.size();
+  q[4] = h->nc;
+  q[5] = maxsys;
+  q[6] = h->l1_entries * (h->fp32 ? 4 : 8);
+  long long psi_bytes = 0;
+  for (const CoarseNode& c : h->cn_h) psi_bytes += (long long)c.nmodes * c.nxw * c.nyw * 8;
+  q[7] = psi_bytes;
+  return MSP_OK;
+}

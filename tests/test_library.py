@@ -1,0 +1,67 @@
+"""Host-side checks of the C-ABI library: it loads and exports every entry
+point that include/msp.h declares (no device call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2006_13387_amd as msp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "msp.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(msp_[A-Za-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_exports():
+    assert sorted(msp.EXPORTS) == _declared()
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(msp.LIB_PATH):
+        pytest.skip("libmsp.so not built (run python -m paper_2006_13387_amd.build)")
+    lib = ctypes.CDLL(msp.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts_match_header():
+    # msp_problem_desc: natural alignment as in C
+    assert ctypes.sizeof(msp.ProblemDesc) == 104
+    assert msp.ProblemDesc.h.offset == 16
+    assert msp.ProblemDesc.eig_tau.offset == 80
+    assert ctypes.sizeof(msp.SolveInfo) == 32 + 6 * 8
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    from paper_2006_13387_amd import binding
+    saved = binding._lib
+    binding._lib = None
+    try:
+        with pytest.raises(RuntimeError, match="not found"):
+            binding.load_library(str(tmp_path / "nope.so"))
+    finally:
+        binding._lib = saved
+
+
+def test_create_rejects_invalid_desc_without_touching_gpu():
+    if not os.path.exists(msp.LIB_PATH):
+        pytest.skip("libmsp.so not built")
+    import inputs
+    L = msp.load_library()
+    bad = inputs.problem_desc(2, (64, 32), sub_nel=10, overlap=2)   # 64 % 10
+    pd = msp.make_desc(bad)
+    mask = (ctypes.c_uint8 * (2 * 65 * 33))()
+    h = ctypes.c_void_p()
+    st = L.msp_create(ctypes.byref(pd), ctypes.cast(mask, ctypes.c_void_p),
+                      ctypes.byref(h))
+    assert st == -1
+    assert b"multiple" in L.msp_last_error(None)
+    bad3 = inputs.problem_desc(3, (4, 4, 4), sub_nel=2, overlap=1)
+    st = L.msp_create(ctypes.byref(msp.make_desc(bad3)),
+                      ctypes.cast(mask, ctypes.c_void_p), ctypes.byref(h))
+    assert st == -1
