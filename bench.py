@@ -1,0 +1,339 @@
+#!/usr/bin/env python3
+"""Benchmark: state solves/s to a relative residual of 1e-8 on one MI355X.
+
+Workload (the 512 x 256 Q1 plane-stress cantilever, 263,682 DOFs): seeded
+two-scale random-field densities with 40 bars, left edge clamped, unit
+point load at the right-mid node, 16 x 8 subdomains of 32 x 32 elements
+with overlap 2, the same densities at Emin = 1e-3, 1e-6 and 1e-9.
+
+One step = for each of the three contrasts: SIMP moduli from the densities,
+the whole preconditioner setup (local factors, heat eigenproblems with the
+threshold, coarse basis and K_0^+), and one PCG solve to relres 1e-8
+(true residual verified).  The FP32-local ("mixed") path is the headline
+value; the FP64 path is timed the same way beside it.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+CONTRASTS = (1e-3, 1e-6, 1e-9)
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0,
+                    help="seconds of oracle work in the CPU baseline sample")
+    ap.add_argument("--quick", action="store_true",
+                    help="one contrast, no FP64 leg (for profiler runs)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_solvers(probs, precision):
+    import paper_2006_13387_amd as msp
+    return [msp.Solver(dict(p.desc, precision=precision), p.fixed) for p in probs]
+
+
+def run_steps(torch, solvers, rho, f, nsteps, lat, infos):
+    for _ in range(nsteps):
+        for s in solvers:
+            t0 = time.perf_counter()
+            s.set_densities(rho)
+            s.setup()
+            _, info = s.solve(f, rtol=1e-8)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t0)
+            infos.append(info)
+            if info["relres_true"] > 1e-8:
+                raise RuntimeError(f"solve missed relres 1e-8: {info}")
+
+
+def timed(torch, solvers, rho, f, steps):
+    lat, infos = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_steps(torch, solvers, rho, f, steps, lat, infos)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, lat, infos
+
+
+def solve_only(torch, solvers, rho, f, reps):
+    """Solves/s with the preconditioner already built (setup excluded)."""
+    for s in solvers:
+        s.set_densities(rho)
+        s.setup()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = 0
+    for _ in range(reps):
+        for s in solvers:
+            s.solve(f, rtol=1e-8)
+            n += 1
+    torch.cuda.synchronize()
+    return n / (time.perf_counter() - t0)
+
+
+def level1_bytes(q, fp32):
+    """Algorithmic HBM bytes of one first-level launch: every inverse
+    Schur block read twice (forward and backward sweeps), the local
+    right-hand sides read (FP64) and the local solutions written."""
+    tsz = 4 if fp32 else 8
+    return 2 * q["local_factor_bytes"] + q["local_vec_entries"] * (8 + tsz)
+
+
+def cpu_baseline(budget_s, gpu_iters):
+    """Time the CPU oracle on a bounded sample of the same workload and
+    scale it to seconds per solve (setup + PCG).
+
+    Sample (the Emin = 1e-6 densities): assembly of K(rho); sparse
+    factorisation of every 8th local system (scaled by 8); the heat
+    eigenproblems of every 8th coarse neighbourhood, and the coarse columns
+    chi psi / chi r they give (scaled to the GPU's coarse dimension) for
+    K Phi, Phi^T K Phi and the restriction / prolongation; the coarse
+    pseudo-inverse at the GPU's coarse dimension; one PCG iteration = K_FF x
+    + the sampled local solves (scaled) + the coarse parts, times the
+    iteration count of the same algorithm at each contrast.
+    """
+    import numpy as np
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+
+    import inputs
+    import oracle
+    from oracle import dd
+
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        blas_threads = 1
+    T = time.perf_counter
+    t_start = T()
+    p = inputs.config(1, Emin=1e-6)
+    d = p.desc
+    t0 = T()
+    E = oracle.simp_modulus(p.rho, d["E0"], d["Emin"], d["penal"])
+    K = oracle.assemble_stiffness(d, E)
+    free = np.nonzero(p.fixed == 0)[0]
+    K_FF = K[free][:, free].tocsr()
+    t_asm = T() - t0
+    boxes = dd.subdomain_node_boxes(d, p.fixed)
+    idx = dd.subdomain_free_indices(d, p.fixed, boxes)
+    sample = idx[::8]
+    t0 = T()
+    lus = [spla.splu(K_FF[i][:, i].tocsc()) for i in sample]
+    t_fact = (T() - t0) * len(idx) / len(sample)
+    nodes = dd.coarse_node_grid(d)
+    cs_sample = nodes[::8]
+    H = dd.coarse_H(d)
+    fmap = -np.ones(len(p.fixed), np.int64)
+    fmap[free] = np.arange(len(free))
+    rows, cols, vals = [], [], []
+    ncol = 0
+    t_eig = 0.0
+    for c in cs_sample:
+        t0 = T()
+        _, nbox = dd.neighbourhood(d, c)
+        ids, flat = dd._node_ids_of_box(d, nbox)
+        dn = ids[p.fixed[2 * ids] == 1]
+        A, M, kept = dd.heat_pencil(d, E, c, dn)
+        hm = dd.heat_modes(A, M, d["eig_tau"], H, d["eig_kmax"])
+        t_eig += T() - t0
+        chi = dd.partition_of_unity(d, c, flat)
+        pos = {int(g): i for i, g in enumerate(ids)}
+        kidx = np.array([pos[int(g)] for g in kept], np.int64)
+        for comp in range(2):
+            for j in range(hm.vecs.shape[1]):
+                dof = fmap[2 * kept + comp]
+                v = chi[kidx] * hm.vecs[:, j]
+                ok = (dof >= 0) & (v != 0)
+                rows.append(dof[ok]); cols.append(np.full(ok.sum(), ncol)); vals.append(v[ok])
+                ncol += 1
+    t_eig *= len(nodes) / len(cs_sample)
+    Phi = sp.csc_matrix((np.concatenate(vals),
+                         (np.concatenate(rows), np.concatenate(cols))),
+                        shape=(len(free), max(ncol, 1)))
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(len(free))
+    res = []
+    for Emin, iters, nc in gpu_iters:
+        scale = nc / max(ncol, 1)
+        t0 = T()
+        KPhi = K_FF @ Phi
+        t_kphi = (T() - t0) * scale
+        t0 = T()
+        G = (Phi.T @ KPhi)
+        # the sampled neighbourhoods do not overlap; each column of the full
+        # space meets the columns of 9 neighbourhoods
+        t_k0 = t_kphi + (T() - t0) * scale * 9
+        B = rng.standard_normal((nc, nc))
+        A0 = B @ B.T / nc + np.eye(nc)
+        t0 = T()
+        P0, _ = dd.coarse_pseudo_inverse(A0)
+        t_pinv = T() - t0
+        t0 = T()
+        for _ in range(3):
+            y = K_FF @ x
+        t_mv = (T() - t0) / 3
+        t0 = T()
+        for lu, i in zip(lus, sample):
+            lu.solve(x[i])
+        t_l1 = (T() - t0) * len(idx) / len(sample)
+        t0 = T()
+        cvec = Phi.T @ x
+        z = Phi @ cvec
+        t_cp = (T() - t0) * scale
+        t0 = T()
+        c0 = P0 @ rng.standard_normal(nc)
+        t_cs = T() - t0
+        t_setup = t_asm + t_fact + t_eig + t_k0 + t_pinv
+        t_iter = t_mv + t_l1 + t_cp + t_cs
+        res.append(t_setup + iters * t_iter)
+        if T() - t_start > budget_s:
+            break
+    sec = statistics.mean(res)
+    return {"value": 1.0 / sec, "unit": "solves/s", "cores": int(blas_threads),
+            "kind": "oracle",
+            "sample": ("512x256 cantilever (Emin 1e-6 densities): assembly, "
+                       "1/8 of the local factorisations and of the heat "
+                       "eigenproblems with their coarse columns (scaled), "
+                       "the coarse pseudo-inverse at the GPU's coarse "
+                       "dimension, one PCG iteration's parts times the "
+                       "iteration count at Emin " +
+                       "/".join(f"{e:g}" for e, _, _ in gpu_iters[:len(res)]) +
+                       f"; sampled work {T() - t_start:.1f} s"),
+            "sec_per_solve": sec}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this solver has no "
+              "multi-GPU path (sharding is described in DESIGN.md); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import inputs
+    import paper_2006_13387_amd as msp
+    msp.load_library()
+    contrasts = CONTRASTS[1:2] if args.quick else CONTRASTS
+    probs = [inputs.config(1, Emin=e) for e in contrasts]
+    rho = torch.tensor(probs[0].rho, device="cuda")
+    f = torch.tensor(probs[0].f, device="cuda")
+    log(f"[bench] workload {probs[0].name} n={len(probs[0].f)} "
+        f"contrasts={contrasts}")
+    mixed = make_solvers(probs, 1)
+    fp64 = [] if args.quick else make_solvers(probs, 0)
+    for _ in range(args.warmup):
+        run_steps(torch, mixed, rho, f, 1, [], [])
+        if fp64:
+            run_steps(torch, fp64, rho, f, 1, [], [])
+    log("[bench] warmup done")
+    # headline: mixed path, level-1 kernel timed with events in the region
+    for s in mixed:
+        s.kernel_timing(enable=1)          # bit 0: first-level apply
+    t_mixed, lat_mixed, inf_mixed = timed(torch, mixed, rho, f, args.steps)
+    l1 = [s.kernel_timing(enable=0)["level1_apply"] for s in mixed]
+    log(f"[bench] mixed: {t_mixed:.3f} s for {args.steps} steps")
+    res = {}
+    if fp64:
+        t_fp64, lat_fp64, inf_fp64 = timed(torch, fp64, rho, f, args.steps)
+        log(f"[bench] fp64: {t_fp64:.3f} s")
+    # per-kernel breakdown on one extra pass (not in the timed region)
+    for s in mixed:
+        s.kernel_timing(enable=True)
+    run_steps(torch, mixed, rho, f, 1, [], [])
+    kt = {}
+    for s in mixed:
+        for k, (c, t) in s.kernel_timing(enable=0).items():
+            a, b = kt.get(k, (0, 0.0))
+            kt[k] = (a + c, b + t)
+    so_mixed = solve_only(torch, mixed, rho, f, 1)
+    so_fp64 = solve_only(torch, fp64, rho, f, 1) if fp64 else None
+    nsolves = args.steps * len(mixed)
+    value = nsolves / t_mixed
+    q = mixed[0].query()
+    launches = sum(c for c, _ in l1)
+    l1_ms = sum(t for _, t in l1) / max(launches, 1)
+    l1_bytes = level1_bytes(q, True)
+    achieved = l1_bytes / (l1_ms * 1e-3) / 1e9
+    lat_sorted = sorted(lat_mixed)
+    pct = lambda a, x: a[min(len(a) - 1, int(round(x * (len(a) - 1))))]
+    out = {
+        "metric": "state solves/s to relres 1e-8 (setup + solve per solve; "
+                  "FP32-local mixed path)",
+        "value": round(value, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t_mixed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (FP32 local inverses)",
+        "data": "synthetic",
+        "config": {"workload": "cantilever2d_512x256_q1 (263682 DOFs), "
+                               "16x8 subdomains S=32 overlap 2, M_EH+Rot, "
+                               "tau=2, kmax=16, Emin " +
+                               "/".join(f"{e:g}" for e in contrasts),
+                   "solves_per_step": len(mixed),
+                   "rtol": 1e-8},
+        "latency_ms": {"p50": round(1e3 * pct(lat_sorted, 0.5), 3),
+                       "p99": round(1e3 * pct(lat_sorted, 0.99), 3)},
+        "iterations": {f"{e:g}": i["iters"] for e, i in zip(contrasts, inf_mixed)},
+        "coarse_dim": {f"{e:g}": i["n_coarse"] for e, i in zip(contrasts, inf_mixed)},
+        "relres_true_max": max(i["relres_true"] for i in inf_mixed),
+        "solve_only_solves_per_s": round(so_mixed, 3),
+        "kernel_ms": {k: round(t / max(c, 1), 4) for k, (c, t) in kt.items()},
+        "kernel_ms_per_step_total": {k: round(t, 3) for k, (c, t) in kt.items()},
+        "roofline": {"kernel": "level1_apply (FP32 inverse blocks)",
+                     "bound": "hbm", "achieved": round(achieved, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None,
+                     "bytes_per_launch": int(l1_bytes),
+                     "avg_launch_ms": round(l1_ms, 5),
+                     "launches_timed": int(launches)},
+    }
+    if fp64:
+        v64 = nsolves / t_fp64
+        out["fp64_path"] = {
+            "value": round(v64, 4),
+            "solve_only_solves_per_s": round(so_fp64, 3),
+            "iterations": {f"{e:g}": i["iters"] for e, i in zip(contrasts, inf_fp64)},
+            "latency_ms_p50": round(1e3 * statistics.median(lat_fp64), 3)}
+        out["mixed_over_fp64"] = round(value / v64, 4)
+        out["mixed_over_fp64_solve_only"] = round(so_mixed / so_fp64, 4)
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle sample)")
+        gi = [(e, i["iters"], i["n_coarse"]) for e, i in zip(contrasts, inf_mixed)]
+        cb = cpu_baseline(args.cpu_budget, gi)
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores",
+                                                  "kind", "sample")}
+        out["cpu_baseline"]["value"] = round(cb["value"], 6)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -60,7 +60,10 @@ typedef enum {
  *  eig_kmax   at most this many modes per neighbourhood (1..24)
  *  rot_enrich 1: add chi_l times the rotations (M_EH+Rot); 0: M_EH
  *  precision  0: FP64 local solves; 1: local inverses stored, applied and
- *             accumulated in FP32 inside the FP64 outer CG (flexible beta)
+ *             accumulated in FP32 inside the FP64 outer CG (flexible beta),
+ *             except in subdomains whose amplification metric (see
+ *             msp_solve_info.fp64_subdomains) shows stiff islands floating
+ *             in soft material, which keep FP64 blocks
  */
 typedef struct {
   int32_t dim;
@@ -83,7 +86,7 @@ typedef struct {
   int32_t n_coarse;        /* coarse dimension N_c (columns of R_0^T)         */
   int32_t coarse_rank;     /* numerical rank of K_0                          */
   int32_t cap_hits;        /* neighbourhoods with more than kmax modes below  */
-  int32_t pad_;
+  int32_t fp64_subdomains; /* subdomains applied with FP64 inverse blocks     */
   double relres_true;      /* ||f - K u|| / ||f|| over free DOFs             */
   double relres_rec;       /* recursively updated residual at exit           */
   double compliance;       /* f^T u                                          */
@@ -178,10 +181,26 @@ msp_status msp_coarse_basis(msp_handle* h, double* phi_dev, hipStream_t stream);
 msp_status msp_vec_dot(int64_t n, const double* x_dev, const double* y_dev,
                        hipStream_t stream, double* out_host);
 
-/* Sizes: [0] n DOFs, [1] elements, [2] subdomains, [3] coarse nodes,
- * [4] coarse dimension after setup, [5] largest local system,
- * [6] bytes of local factor storage, [7] bytes of coarse basis storage. */
-msp_status msp_query(msp_handle* h, int64_t* sizes8);
+/* Sizes (12 int64): [0] n DOFs, [1] elements, [2] subdomains, [3] coarse
+ * nodes, [4] coarse dimension after setup, [5] largest local system,
+ * [6] bytes of local inverse blocks, [7] bytes of stored heat modes psi,
+ * [8] sum of local system sizes, [9] sum of neighbourhood sizes,
+ * [10] bytes of the neighbourhood inverse blocks, [11] padded K_0 order. */
+msp_status msp_query(msp_handle* h, int64_t* sizes12);
+
+/*
+ * Per-kernel event timing for measurement.  enable >= 0 is a bit mask of
+ * the tracked kernels below: from now on the library records a hipEvent
+ * pair around every launch of each selected kernel on the caller's stream
+ * (0 stops timing, -1 leaves the state unchanged).
+ * Before changing the state the call returns, for kernel k < n, the number
+ * of timed launches and their summed duration in ms since the last reset:
+ * k = 0 first-level apply, 1 CG stiffness product, 2 heat eigen setup,
+ * 3 combine (z = M^-1 r), 4 coarse restriction, 5 local factorisation.
+ */
+msp_status msp_kernel_timing(msp_handle* h, int32_t enable,
+                             int64_t* launches_host, double* total_ms_host,
+                             int32_t n);
 
 #ifdef __cplusplus
 }

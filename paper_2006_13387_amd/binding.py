@@ -35,7 +35,8 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
                 ("converged", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("n_coarse", ctypes.c_int32), ("coarse_rank", ctypes.c_int32),
-                ("cap_hits", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("cap_hits", ctypes.c_int32),
+                ("fp64_subdomains", ctypes.c_int32),
                 ("relres_true", ctypes.c_double),
                 ("relres_rec", ctypes.c_double),
                 ("compliance", ctypes.c_double), ("cond_est", ctypes.c_double),
@@ -43,13 +44,17 @@ class SolveInfo(ctypes.Structure):
                 ("t_solve_ms", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 EXPORTS = ["msp_create", "msp_destroy", "msp_last_error", "msp_set_densities",
            "msp_setup", "msp_solve", "msp_apply_K", "msp_apply_level1",
            "msp_apply_coarse", "msp_apply_prec", "msp_coarse_info",
-           "msp_coarse_basis", "msp_vec_dot", "msp_query"]
+           "msp_coarse_basis", "msp_vec_dot", "msp_query",
+           "msp_kernel_timing"]
+
+KERNEL_NAMES = ["level1_apply", "cg_matvec", "heat_eigen", "combine",
+                "coarse_restrict", "local_factor"]
 
 _lib = None
 
@@ -82,6 +87,7 @@ def load_library(path=LIB_PATH):
     L.msp_vec_dot.argtypes = [ctypes.c_int64, vp, vp, vp,
                               ctypes.POINTER(ctypes.c_double)]
     L.msp_query.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    L.msp_kernel_timing.argtypes = [vp, i32, vp, vp, i32]
     for name in EXPORTS:
         if name != "msp_last_error":
             getattr(L, name).restype = i32
@@ -140,7 +146,7 @@ class Solver:
         if st != 0:
             raise MspError(st, self.L.msp_last_error(None).decode())
         self.h = h
-        q = (ctypes.c_int64 * 8)()
+        q = (ctypes.c_int64 * 12)()
         self.L.msp_query(self.h, q)
         self.n = int(q[0])
 
@@ -197,7 +203,7 @@ class Solver:
         return self._apply(self.L.msp_apply_prec, r)
 
     def coarse_info(self):
-        q = (ctypes.c_int64 * 8)()
+        q = (ctypes.c_int64 * 12)()
         self.L.msp_query(self.h, q)
         ncn = int(q[3])
         kmax = self.desc["eig_kmax"]
@@ -219,12 +225,27 @@ class Solver:
         self._check(self.L.msp_coarse_basis(self.h, _ptr(phi), _stream()))
         return phi[:nc].T
 
+    def kernel_timing(self, enable=-1):
+        """Launch counts and summed event times (ms) of the tracked kernels
+        since the last reset; enable (a bit mask over KERNEL_NAMES, or True
+        for all) resets and switches timing, -1 only reads."""
+        if enable is True:
+            enable = (1 << len(KERNEL_NAMES)) - 1
+        n = len(KERNEL_NAMES)
+        cnt = np.zeros(n, np.int64)
+        tot = np.zeros(n, np.float64)
+        self._check(self.L.msp_kernel_timing(
+            self.h, int(enable), cnt.ctypes.data_as(ctypes.c_void_p),
+            tot.ctypes.data_as(ctypes.c_void_p), n))
+        return {k: (int(c), float(t)) for k, c, t in zip(KERNEL_NAMES, cnt, tot)}
+
     def query(self):
-        q = (ctypes.c_int64 * 8)()
+        q = (ctypes.c_int64 * 12)()
         self._check(self.L.msp_query(self.h, q))
         keys = ["n_dofs", "n_elems", "n_subdomains", "n_coarse_nodes",
                 "n_coarse", "max_local", "local_factor_bytes",
-                "coarse_basis_bytes"]
+                "coarse_basis_bytes", "local_vec_entries",
+                "omega_vec_entries", "omega_factor_bytes", "ldk"]
         return dict(zip(keys, [int(v) for v in q]))
 
 

@@ -341,40 +341,71 @@ __global__ void k_k0_unscale(double* __restrict__ K0, int ldk,
 }
 
 // ---------------------------------------------------------------------
-// Restriction c = R_0 r: one workgroup per coarse node; wave w takes the
-// columns j = w, w+4, ...; its lanes stride over the neighbourhood's nodes
-// (coalesced psi and r reads) and the column sum is a wavefront butterfly.
-__global__ void __launch_bounds__(CK_NT)
+// Restriction c = R_0 r: one workgroup per coarse node.  Each thread takes
+// nodes of the neighbourhood (coalesced psi and r reads), reads r, the mask
+// and chi once per node and accumulates every column of the node in
+// registers; the column sums are a wavefront butterfly and a fixed-order
+// sum over the waves.
+constexpr int RS_NT = 256;
+constexpr int KMAXD = 24;
+
+__global__ void __launch_bounds__(RS_NT)
 k_restrict(Geom g, const CoarseNode* __restrict__ cnodes,
            const uint8_t* __restrict__ mask, const double* __restrict__ psi,
            const double* __restrict__ r, double* __restrict__ c, double invH,
            const CGScalars* __restrict__ sc) {
+  __shared__ double red[(2 * KMAXD + 1) * (RS_NT / 64)];
   if (sc != nullptr && sc->done) return;
   const CoarseNode cn = cnodes[blockIdx.x];
-  const int ncol = 2 * cn.nmodes + cn.nrot;
+  const int nm = cn.nmodes;
+  const int ncol = 2 * nm + cn.nrot;
+  if (ncol == 0) return;
   const int nw = cn.nxw * cn.nyw;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int j = w; j < ncol; j += CK_NT / 64) {
-    double acc = 0.0;
-    for (int loc = lane; loc < nw; loc += 64) {
-      const int x = cn.x0 + loc % cn.nxw, y = cn.y0 + loc / cn.nxw;
-      const double chi = chi_at(g, cn.cx, cn.cy, x, y);
-      const long long node = (long long)y * g.nnx + x;
-      const double2 rv = reinterpret_cast<const double2*>(r)[node];
-      const uchar2 m = reinterpret_cast<const uchar2*>(mask)[node];
-      const double r0 = m.x ? 0.0 : rv.x, r1 = m.y ? 0.0 : rv.y;
-      if (j < 2 * cn.nmodes) {
-        const int comp = j / cn.nmodes, jm = j - comp * cn.nmodes;
-        const double ps = chi * psi[cn.psi_off + (long long)jm * nw + loc];
-        acc += ps * (comp == 0 ? r0 : r1);
-      } else {
-        const double rx = (x - cn.cx * g.sx) * g.h * invH;
-        const double ry = (y - cn.cy * g.sy) * g.h * invH;
-        acc += chi * (-ry * r0 + rx * r1);
+  const double* ps = psi + cn.psi_off;
+  double ax[KMAXD], ay[KMAXD], ar = 0.0;
+#pragma unroll
+  for (int j = 0; j < KMAXD; ++j) ax[j] = ay[j] = 0.0;
+  for (int loc = threadIdx.x; loc < nw; loc += RS_NT) {
+    const int x = cn.x0 + loc % cn.nxw, y = cn.y0 + loc / cn.nxw;
+    const double chi = chi_at(g, cn.cx, cn.cy, x, y);
+    const long long node = (long long)y * g.nnx + x;
+    const double2 rv = reinterpret_cast<const double2*>(r)[node];
+    const uchar2 m = reinterpret_cast<const uchar2*>(mask)[node];
+    const double r0 = m.x ? 0.0 : chi * rv.x, r1 = m.y ? 0.0 : chi * rv.y;
+#pragma unroll
+    for (int j = 0; j < KMAXD; ++j) {
+      if (j < nm) {
+        const double pv = ps[(long long)j * nw + loc];
+        ax[j] += pv * r0;
+        ay[j] += pv * r1;
       }
     }
-    acc = wave_sum(acc);
-    if (lane == 0) c[cn.col0 + j] = acc;
+    const double rx = (x - cn.cx * g.sx) * g.h * invH;
+    const double ry = (y - cn.cy * g.sy) * g.h * invH;
+    ar += -ry * r0 + rx * r1;
+  }
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < KMAXD; ++j) {
+    if (j < nm) {
+      const double sx = wave_sum(ax[j]);
+      const double sy = wave_sum(ay[j]);
+      if ((threadIdx.x & 63) == 0) {
+        red[j * (RS_NT / 64) + w] = sx;
+        red[(nm + j) * (RS_NT / 64) + w] = sy;
+      }
+    }
+  }
+  if (cn.nrot) {
+    const double sr = wave_sum(ar);
+    if ((threadIdx.x & 63) == 0) red[(2 * nm) * (RS_NT / 64) + w] = sr;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < ncol; j += RS_NT) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < RS_NT / 64; ++q) t += red[j * (RS_NT / 64) + q];
+    c[cn.col0 + j] = t;
   }
 }
 
@@ -582,7 +613,7 @@ void launch_restrict(const Geom& g, const CoarseNode* cn, int ncn,
                      const uint8_t* mask, const double* psi, const double* r,
                      double* c, double invH, const CGScalars* sc,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_restrict, dim3(ncn), dim3(CK_NT), 0, s, g, cn, mask, psi,
+  hipLaunchKernelGGL(k_restrict, dim3(ncn), dim3(RS_NT), 0, s, g, cn, mask, psi,
                      r, c, invH, sc);
 }
 

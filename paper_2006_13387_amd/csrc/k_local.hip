@@ -18,7 +18,7 @@
 namespace msp {
 
 constexpr int FT_NT = 256;    // factorisation workgroup
-constexpr int AP_NT = 512;    // first-level apply workgroup
+constexpr int AP_NT = 256;    // first-level apply workgroup
 constexpr int EG_NT = 512;    // eigen workgroup
 constexpr int LDSTR = MAXBS + 1;   // LDS row stride of a dense block
 
@@ -83,17 +83,28 @@ __device__ void gj_invert(double* S, int bs, double* rowv, double* colv,
   }
 }
 
-// Factorise every system: one workgroup per system.  TOUT is double (FP64
-// local solves) or float (inverse blocks rounded for the FP32 path).
-template <int NDOF, typename TOUT>
+// Factorise every system: one workgroup per system.
+//
+// out64 receives the FP64 inverse blocks; out32 (may be null) a rounded FP32
+// copy.  metric (may be null) receives per system max_i (S_k^-1)_ii (D_k)_ii
+// over all blocks: about 1 for DOFs held by stiff material and up to the
+// contrast E0/Emin for DOFs of stiff islands that float in soft material,
+// whose rigid motions then have amplitudes ~E0/Emin.  FP32 rounding of such
+// values leaves spurious strains in the stiff phase, so the runtime keeps
+// FP64 blocks for systems whose metric exceeds a bound.
+template <int NDOF>
 __global__ void __launch_bounds__(FT_NT)
 k_factor(Geom g, const SysDesc* __restrict__ systems,
          const double* __restrict__ E, const uint8_t* __restrict__ flag,
-         const double* __restrict__ Kel, TOUT* __restrict__ out,
+         const double* __restrict__ Kel, double* __restrict__ out64,
+         float* __restrict__ out32, double* __restrict__ metric,
          int* __restrict__ err) {
   __shared__ double buf[3][MAXBS * LDSTR];
   __shared__ double Bv[MAXBS * 3 * NDOF];
   __shared__ double rowv[MAXBS], colv[MAXBS];
+  __shared__ double ddiag[MAXBS];
+  __shared__ double red[FT_NT / 64 + 1];
+  double mloc = 0.0;
   const SysDesc s = systems[blockIdx.x];
   const int tid = threadIdx.x;
   const int bs = NDOF * s.nxb;
@@ -115,6 +126,7 @@ k_factor(Geom g, const SysDesc* __restrict__ systems,
         v = coupling<NDOF>(g, s, E, Kel, s.x0 + ia, y, ca, s.x0 + ib, y, cb);
       }
       S[a * LDSTR + b] = v;
+      if (a == b) ddiag[a] = v;
     }
     if (k > 0) {
       // B_{k-1}: rows a in node row y, columns in node row y-1, banded
@@ -161,136 +173,254 @@ k_factor(Geom g, const SysDesc* __restrict__ systems,
     }
     __syncthreads();
     gj_invert<FT_NT>(S, bs, rowv, colv, err);
-    TOUT* o = out + s.foff + (long long)k * bs * bs;
+    double* o = out64 + s.foff + (long long)k * bs * bs;
     for (int idx = tid; idx < bs * bs; idx += FT_NT) {
       const int j = idx / bs, i = idx - (idx / bs) * bs;
-      o[idx] = (TOUT)S[i * LDSTR + j];      // column j contiguous
+      o[idx] = S[i * LDSTR + j];      // column j contiguous
     }
+    if (out32 != nullptr) {
+      float* o32 = out32 + s.foff + (long long)k * bs * bs;
+      for (int idx = tid; idx < bs * bs; idx += FT_NT) {
+        const int j = idx / bs, i = idx - (idx / bs) * bs;
+        o32[idx] = (float)S[i * LDSTR + j];
+      }
+    }
+    for (int a = tid; a < bs; a += FT_NT) mloc = fmax(mloc, S[a * LDSTR + a] * ddiag[a]);
     __syncthreads();
     const int t = prev;
     prev = cur;
     cur = t;
   }
+  if (metric != nullptr) {
+    // workgroup max (fixed order)
+    double v = mloc;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+      double mm = 0.0;
+      for (int i = 0; i < FT_NT / 64; ++i) mm = fmax(mm, red[i]);
+      metric[blockIdx.x] = mm;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------
 // First level: z_i = K_i^{-1} R_i r for every subdomain (2D elasticity).
-// One workgroup per subdomain; the local vector stays in LDS.  Threads are
-// grouped NG = AP_NT / bs ways over the columns of each inverse block; a
-// group's lanes read consecutive entries of a column (coalesced).
+//
+// One workgroup per subdomain.  At kernel start the subdomain's element
+// moduli, element matrix, mask and right-hand side go to LDS; the sweep is
+// then a chain of nyb-1 + nyb steps.  In each step threads 0..bs-1 form the
+// block right-hand side and multiply it by the inverse block held in LDS
+// (thread i owns row i: no cross-thread reduction), while the remaining
+// threads build the next step's coupling coefficients from the LDS moduli
+// and every thread streams its share of the next inverse block from HBM
+// into registers, stored to the second LDS buffer at the end of the step.
+// Two barriers per step; HBM latency overlaps the arithmetic.
+constexpr int L1_EBOX = 3072;      // element moduli of one subdomain box
+constexpr int L1_PF = (MAXBS * MAXBS + AP_NT - 1) / AP_NT;
+
 template <typename T>
-__global__ void __launch_bounds__(AP_NT)
-k_level1(Geom g, const SysDesc* __restrict__ systems,
-         const double* __restrict__ E, const uint8_t* __restrict__ mask,
-         const double* __restrict__ Kel, const T* __restrict__ Sinv,
-         const double* __restrict__ r, T* __restrict__ lsol,
-         const CGScalars* __restrict__ sc) {
-  __shared__ T v[MAXBS * 40];          // whole local vector (nyb*bs <= 2880)
-  __shared__ T tmp[MAXBS];
-  __shared__ T part[AP_NT];
-  __shared__ double Bc[MAXBS * 6];     // coupling coefficients of one row
-  if (sc != nullptr && sc->done) return;
-  const SysDesc s = systems[blockIdx.x];
+struct L1Lds {
+  T SL[2][MAXBS * MAXBS];
+  T v[MAXBS * 40];
+  T tmp[MAXBS];
+  T Bc[2][MAXBS * 6];
+  double Es[L1_EBOX];
+  double Ks[64];
+  uint8_t mk[MAXBS * 40];
+};
+
+// coupling of DOF (ia, ca) of node row ya with DOF (ib, cb) of row yb =
+// ya -+ 1, from the moduli in LDS (box origin x0-1, y0-1, width nxb+1)
+__device__ __forceinline__ double l1_coupling(const Geom& g, const SysDesc& s,
+                                              const double* Es,
+                                              const double* Ks, int ia, int ya,
+                                              int ca, int ib, int yb, int cb) {
+  const int xa = s.x0 + ia, xb = s.x0 + ib;
+  const int ey = min(ya, yb);                      // element row between them
+  double v = 0.0;
+  for (int ex = max(xa, xb) - 1; ex <= min(xa, xb); ++ex) {
+    if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny) continue;
+    const int va = (xa - ex) + 2 * (ya - ey);
+    const int vb = (xb - ex) + 2 * (yb - ey);
+    const double e = Es[(ey - (s.y0 - 1)) * (s.nxb + 1) + (ex - (s.x0 - 1))];
+    v += e * Ks[(2 * va + ca) * 8 + 2 * vb + cb];
+  }
+  return v;
+}
+
+// couplings of every DOF of local row k with its 3 neighbour nodes in
+// row k + dir (dir = -1 forward, +1 backward), zero for clamped DOFs
+template <typename T>
+__device__ __forceinline__ void l1_row_couplings(const Geom& g,
+                                                 const SysDesc& s,
+                                                 L1Lds<T>& L, int k, int dir,
+                                                 T* out, int t0, int nthr) {
+  const int bs = 2 * s.nxb;
+  for (int idx = t0; idx < bs * 6; idx += nthr) {
+    const int a = idx / 6, t = idx - a * 6;
+    const int ia = a >> 1, ca = a & 1;
+    const int ib = ia + t / 2 - 1, cb = t & 1;
+    double cv = 0.0;
+    if (ib >= 0 && ib < s.nxb && !L.mk[k * bs + a] &&
+        !L.mk[(k + dir) * bs + 2 * ib + cb])
+      cv = l1_coupling(g, s, L.Es, L.Ks, ia, s.y0 + k, ca, ib, s.y0 + k + dir, cb);
+    out[idx] = (T)cv;
+  }
+}
+
+template <typename T>
+__device__ void level1_body(const Geom& g, const SysDesc& s,
+                            const double* __restrict__ E,
+                            const uint8_t* __restrict__ mask,
+                            const double* __restrict__ Kel,
+                            const T* __restrict__ Sinv,
+                            const double* __restrict__ r,
+                            double* __restrict__ lsol, unsigned char* lds) {
+  L1Lds<T>& L = *reinterpret_cast<L1Lds<T>*>(lds);
   const int tid = threadIdx.x;
   const int bs = 2 * s.nxb;
   const int nb = s.nyb;
-  const int NG = AP_NT / bs;
-  const int grp = tid / bs, li = tid - (tid / bs) * bs;
+  const int bs2 = bs * bs;
+  const int ew = s.nxb + 1;
+  const T* base = Sinv + s.foff;
 
+  if (tid < 64) L.Ks[tid] = Kel[tid];
+  for (int idx = tid; idx < ew * (nb + 1); idx += AP_NT) {
+    const int ex = s.x0 - 1 + idx % ew, ey = s.y0 - 1 + idx / ew;
+    L.Es[idx] = (ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny)
+                    ? E[(long long)ey * g.nx + ex] : 0.0;
+  }
   for (int idx = tid; idx < nb * bs; idx += AP_NT) {
     const int k = idx / bs, a = idx - (idx / bs) * bs;
-    const int x = s.x0 + a / 2, y = s.y0 + k, c = a & 1;
-    const long long d = 2 * ((long long)y * g.nnx + x) + c;
-    v[idx] = mask[d] ? (T)0 : (T)r[d];
+    const long long d = 2 * ((long long)(s.y0 + k) * g.nnx + s.x0 + a / 2) + (a & 1);
+    const uint8_t m = mask[d];
+    L.mk[idx] = m;
+    L.v[idx] = m ? (T)0 : (T)r[d];
   }
+  for (int idx = tid; idx < bs2; idx += AP_NT) L.SL[0][idx] = base[idx];
   __syncthreads();
 
-  // forward sweep
+  T pf[L1_PF];
+  int cur = 0, bcur = 0;
+  // forward sweep: step k uses block k; prefetch block k+1 (or, in the last
+  // step, block nb-2 for the backward sweep)
   for (int k = 0; k < nb; ++k) {
-    const int y = s.y0 + k;
-    if (k > 0) {
-      // coupling of row y (a) with row y-1 (i + di)
-      for (int idx = tid; idx < bs * 6; idx += AP_NT) {
-        const int a = idx / 6, t = idx - a * 6;
-        const int ia = a >> 1, ca = a & 1;
-        const int ib = ia + t / 2 - 1, cb = t & 1;
-        double cv = 0.0;
-        if (ib >= 0 && ib < s.nxb && !mask[2 * ((long long)y * g.nnx + s.x0 + ia) + ca] &&
-            !mask[2 * ((long long)(y - 1) * g.nnx + s.x0 + ib) + cb])
-          cv = coupling<2>(g, s, E, Kel, s.x0 + ia, y, ca, s.x0 + ib, y - 1, cb);
-        Bc[idx] = cv;
+    const int knext = (k + 1 < nb) ? k + 1 : nb - 2;
+    const bool has_next = knext >= 0;
+    if (has_next) {
+      const T* src = base + (long long)knext * bs2;
+#pragma unroll
+      for (int q = 0; q < L1_PF; ++q) {
+        const int idx = tid + q * AP_NT;
+        if (idx < bs2) pf[q] = src[idx];
       }
-      __syncthreads();
-      for (int a = tid; a < bs; a += AP_NT) {
-        const int ia = a >> 1;
-        T acc = v[k * bs + a];
+    }
+    if (tid < bs) {
+      T w = L.v[k * bs + tid];
+      if (k > 0) {
+        const int ia = tid >> 1;
+        const T* bc = L.Bc[bcur ^ 1] + tid * 6;
 #pragma unroll
         for (int t = 0; t < 6; ++t) {
           const int col = 2 * (ia + t / 2 - 1) + (t & 1);
-          if (col >= 0 && col < bs) acc -= (T)Bc[a * 6 + t] * v[(k - 1) * bs + col];
+          if (col >= 0 && col < bs) w -= bc[t] * L.v[(k - 1) * bs + col];
         }
-        tmp[a] = acc;
       }
+      L.tmp[tid] = w;
+    }
+    __syncthreads();
+    if (tid < bs) {
+      const T* S = L.SL[cur];
+      T acc = 0;
+      for (int j = 0; j < bs; ++j) acc += S[j * bs + tid] * L.tmp[j];
+      L.v[k * bs + tid] = acc;
     } else {
-      for (int a = tid; a < bs; a += AP_NT) tmp[a] = v[a];
+      // couplings for the next step: row k+1 with row k (forward), or, after
+      // the last forward step, row nb-2 with row nb-1 (first backward step)
+      if (k + 1 < nb)
+        l1_row_couplings<T>(g, s, L, k + 1, -1, L.Bc[bcur], tid - bs, AP_NT - bs);
+      else if (nb >= 2)
+        l1_row_couplings<T>(g, s, L, nb - 2, +1, L.Bc[bcur], tid - bs, AP_NT - bs);
+    }
+    if (has_next) {
+#pragma unroll
+      for (int q = 0; q < L1_PF; ++q) {
+        const int idx = tid + q * AP_NT;
+        if (idx < bs2) L.SL[cur ^ 1][idx] = pf[q];
+      }
     }
     __syncthreads();
-    const T* Sk = Sinv + s.foff + (long long)k * bs * bs;
-    if (grp < NG) {
-      T acc = 0;
-      for (int j = grp; j < bs; j += NG) acc += Sk[(long long)j * bs + li] * tmp[j];
-      part[grp * bs + li] = acc;
-    }
-    __syncthreads();
-    for (int a = tid; a < bs; a += AP_NT) {
-      T acc = 0;
-      for (int q = 0; q < NG; ++q) acc += part[q * bs + a];
-      v[k * bs + a] = acc;
-    }
-    __syncthreads();
+    cur ^= 1;
+    bcur ^= 1;
   }
-  // backward sweep
+  // backward sweep: step k uses block k and couplings of row k with k+1
   for (int k = nb - 2; k >= 0; --k) {
-    const int y = s.y0 + k;
-    // (B_k^T x_{k+1})[b], b in row y, neighbours (i+di) in row y+1
-    for (int idx = tid; idx < bs * 6; idx += AP_NT) {
-      const int b = idx / 6, t = idx - b * 6;
-      const int ib = b >> 1, cb = b & 1;
-      const int ia = ib + t / 2 - 1, ca = t & 1;
-      double cv = 0.0;
-      if (ia >= 0 && ia < s.nxb && !mask[2 * ((long long)y * g.nnx + s.x0 + ib) + cb] &&
-          !mask[2 * ((long long)(y + 1) * g.nnx + s.x0 + ia) + ca])
-        cv = coupling<2>(g, s, E, Kel, s.x0 + ib, y, cb, s.x0 + ia, y + 1, ca);
-      Bc[idx] = cv;
+    const int knext = k - 1;
+    if (knext >= 0) {
+      const T* src = base + (long long)knext * bs2;
+#pragma unroll
+      for (int q = 0; q < L1_PF; ++q) {
+        const int idx = tid + q * AP_NT;
+        if (idx < bs2) pf[q] = src[idx];
+      }
     }
-    __syncthreads();
-    for (int b = tid; b < bs; b += AP_NT) {
-      const int ib = b >> 1;
-      T acc = 0;
+    if (tid < bs) {
+      const int ib = tid >> 1;
+      const T* bc = L.Bc[bcur ^ 1] + tid * 6;
+      T w = 0;
 #pragma unroll
       for (int t = 0; t < 6; ++t) {
         const int col = 2 * (ib + t / 2 - 1) + (t & 1);
-        if (col >= 0 && col < bs) acc += (T)Bc[b * 6 + t] * v[(k + 1) * bs + col];
+        if (col >= 0 && col < bs) w += bc[t] * L.v[(k + 1) * bs + col];
       }
-      tmp[b] = acc;
+      L.tmp[tid] = w;
     }
     __syncthreads();
-    const T* Sk = Sinv + s.foff + (long long)k * bs * bs;
-    if (grp < NG) {
+    if (tid < bs) {
+      const T* S = L.SL[cur];
       T acc = 0;
-      for (int j = grp; j < bs; j += NG) acc += Sk[(long long)j * bs + li] * tmp[j];
-      part[grp * bs + li] = acc;
+      for (int j = 0; j < bs; ++j) acc += S[j * bs + tid] * L.tmp[j];
+      L.v[k * bs + tid] -= acc;
+    } else if (k >= 1) {
+      // couplings for the next backward step: row k-1 with row k
+      l1_row_couplings<T>(g, s, L, k - 1, +1, L.Bc[bcur], tid - bs, AP_NT - bs);
+    }
+    if (knext >= 0) {
+#pragma unroll
+      for (int q = 0; q < L1_PF; ++q) {
+        const int idx = tid + q * AP_NT;
+        if (idx < bs2) L.SL[cur ^ 1][idx] = pf[q];
+      }
     }
     __syncthreads();
-    for (int a = tid; a < bs; a += AP_NT) {
-      T acc = 0;
-      for (int q = 0; q < NG; ++q) acc += part[q * bs + a];
-      v[k * bs + a] -= acc;
-    }
-    __syncthreads();
+    cur ^= 1;
+    bcur ^= 1;
   }
-  T* o = lsol + s.voff;
-  for (int idx = tid; idx < nb * bs; idx += AP_NT) o[idx] = v[idx];
+  double* o = lsol + s.voff;
+  for (int idx = tid; idx < nb * bs; idx += AP_NT) o[idx] = (double)L.v[idx];
+}
+
+constexpr size_t L1_LDS_BYTES = sizeof(L1Lds<double>);
+
+// use64[i] != 0 (or use64 == null) selects the FP64 inverse blocks of
+// system i, else its FP32 copy (applied and accumulated in FP32).
+__global__ void __launch_bounds__(AP_NT)
+k_level1(Geom g, const SysDesc* __restrict__ systems,
+         const double* __restrict__ E, const uint8_t* __restrict__ mask,
+         const double* __restrict__ Kel, const double* __restrict__ S64,
+         const float* __restrict__ S32, const uint8_t* __restrict__ use64,
+         const double* __restrict__ r, double* __restrict__ lsol,
+         const CGScalars* __restrict__ sc) {
+  __shared__ __align__(16) unsigned char lds[L1_LDS_BYTES];
+  if (sc != nullptr && sc->done) return;
+  const SysDesc s = systems[blockIdx.x];
+  if (S32 == nullptr || use64 == nullptr || use64[blockIdx.x])
+    level1_body<double>(g, s, E, mask, Kel, S64, r, lsol, lds);
+  else
+    level1_body<float>(g, s, E, mask, Kel, S32, r, lsol, lds);
 }
 
 // ---------------------------------------------------------------------
@@ -322,31 +452,49 @@ __device__ __forceinline__ double hash_unit(unsigned long long a) {
 }
 
 // out[j][node] = sum_e kappa_e (Kel in)[node] over omega's elements for the
-// first m columns; Dirichlet rows are 0.
+// first m columns; Dirichlet rows are 0.  One node per thread, the element
+// moduli of its (up to) four elements read once for all m columns.
 __device__ void omega_stencil(const Geom& g, const SysDesc& s,
                               const double* __restrict__ E,
                               const uint8_t* __restrict__ dflag,
                               const double* __restrict__ Kel4,
                               const double* in, double* out, int n, int m) {
-  for (int idx = threadIdx.x; idx < n * m; idx += EG_NT) {
-    const int j = idx / n, node = idx - (idx / n) * n;
+  for (int node = threadIdx.x; node < n; node += EG_NT) {
     const int i = node % s.nxb, k = node / s.nxb;
     const int x = s.x0 + i, y = s.y0 + k;
-    double acc = 0.0;
-    if (!dflag[(long long)y * g.nnx + x]) {
-      for (int ey = max(y - 1, s.ey0); ey <= min(y, s.ey1 - 1); ++ey)
-        for (int ex = max(x - 1, s.ex0); ex <= min(x, s.ex1 - 1); ++ex) {
-          const int va = (x - ex) + 2 * (y - ey);
-          double t = 0.0;
-#pragma unroll
-          for (int vb = 0; vb < 4; ++vb) {
-            const int xb = ex + (vb & 1), yb = ey + (vb >> 1);
-            t += Kel4[va * 4 + vb] * in[(long long)j * n + (yb - s.y0) * s.nxb + (xb - s.x0)];
-          }
-          acc += E[(long long)ey * g.nx + ex] * t;
-        }
+    if (dflag[(long long)y * g.nnx + x]) {
+      for (int j = 0; j < m; ++j) out[(long long)j * n + node] = 0.0;
+      continue;
     }
-    out[(long long)j * n + node] = acc;
+    // weights w[dy][dx][vb] = kappa_e * Kel[va][vb] for the four elements
+    double wgt[2][2][4];
+    int base[2][2];
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) {
+        const int ex = x - 1 + dx, ey = y - 1 + dy;
+        const bool ok = ex >= s.ex0 && ex < s.ex1 && ey >= s.ey0 && ey < s.ey1;
+        const double ke = ok ? E[(long long)ey * g.nx + ex] : 0.0;
+        const int va = (x - ex) + 2 * (y - ey);
+#pragma unroll
+        for (int vb = 0; vb < 4; ++vb) wgt[dy][dx][vb] = ke * Kel4[va * 4 + vb];
+        base[dy][dx] = ok ? (ey - s.y0) * s.nxb + (ex - s.x0) : -1;
+      }
+    for (int j = 0; j < m; ++j) {
+      const double* col = in + (long long)j * n;
+      double acc = 0.0;
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+          const int b0 = base[dy][dx];
+          if (b0 < 0) continue;
+          acc += wgt[dy][dx][0] * col[b0] + wgt[dy][dx][1] * col[b0 + 1] +
+                 wgt[dy][dx][2] * col[b0 + s.nxb] + wgt[dy][dx][3] * col[b0 + s.nxb + 1];
+        }
+      out[(long long)j * n + node] = acc;
+    }
   }
 }
 
@@ -545,6 +693,8 @@ k_heat_eigen(Geom g, const SysDesc* __restrict__ systems,
              int* __restrict__ nsel_out, int* __restrict__ cap_out,
              int* __restrict__ err) {
   __shared__ double lbuf[3 * MAXBS * MAXM];   // solve rows / gram staging
+  __shared__ double SkL[MAXBS * MAXBS];        // one inverse block
+  __shared__ double cpl[MAXBS * 3];            // couplings of one row
   __shared__ double G[MAXM * MAXM];
   __shared__ double V[MAXM * MAXM];
   __shared__ double theta[MAXM], theta_old[MAXM];
@@ -584,27 +734,36 @@ k_heat_eigen(Geom g, const SysDesc* __restrict__ systems,
     // Y = C^{-1} Z : forward
     for (int k = 0; k < nb; ++k) {
       const int y = s.y0 + k;
+      const double* Sk = Sinv + s.foff + (long long)k * bs * bs;
+      for (int idx = tid; idx < bs * bs; idx += EG_NT) SkL[idx] = Sk[idx];
+      if (k > 0)
+        for (int idx = tid; idx < bs * 3; idx += EG_NT) {
+          const int a = idx / 3, t = idx - a * 3;
+          const int b = a + t - 1, x = s.x0 + a;
+          double cv = 0.0;
+          if (b >= 0 && b < bs && !dflag[(long long)y * g.nnx + x] &&
+              !dflag[(long long)(y - 1) * g.nnx + s.x0 + b])
+            cv = coupling<1>(g, s, E, Cel, x, y, 0, s.x0 + b, y - 1, 0);
+          cpl[idx] = cv;
+        }
+      __syncthreads();
       for (int idx = tid; idx < bs * m; idx += EG_NT) {
         const int a = idx / m, j = idx - (idx / m) * m;
-        const int x = s.x0 + a;
         double w = Z[(long long)j * n + k * bs + a];
-        if (k > 0 && !dflag[(long long)y * g.nnx + x]) {
-          for (int di = -1; di <= 1; ++di) {
-            const int b = a + di;
-            if (b < 0 || b >= bs) continue;
-            if (dflag[(long long)(y - 1) * g.nnx + s.x0 + b]) continue;
-            const double cv = coupling<1>(g, s, E, Cel, x, y, 0, s.x0 + b, y - 1, 0);
-            w -= cv * Tp[b * MAXM + j];
+        if (k > 0) {
+#pragma unroll
+          for (int t = 0; t < 3; ++t) {
+            const int b = a + t - 1;
+            if (b >= 0 && b < bs) w -= cpl[a * 3 + t] * Tp[b * MAXM + j];
           }
         }
         Wl[a * MAXM + j] = w;
       }
       __syncthreads();
-      const double* Sk = Sinv + s.foff + (long long)k * bs * bs;
       for (int idx = tid; idx < bs * m; idx += EG_NT) {
         const int i = idx % bs, j = idx / bs;
         double acc = 0.0;
-        for (int b = 0; b < bs; ++b) acc += Sk[(long long)b * bs + i] * Wl[b * MAXM + j];
+        for (int b = 0; b < bs; ++b) acc += SkL[b * bs + i] * Wl[b * MAXM + j];
         Tc[i * MAXM + j] = acc;
         Y[(long long)j * n + k * bs + i] = acc;
       }
@@ -614,27 +773,33 @@ k_heat_eigen(Geom g, const SysDesc* __restrict__ systems,
     // backward: Tp holds row nb-1 (final)
     for (int k = nb - 2; k >= 0; --k) {
       const int y = s.y0 + k;
+      const double* Sk = Sinv + s.foff + (long long)k * bs * bs;
+      for (int idx = tid; idx < bs * bs; idx += EG_NT) SkL[idx] = Sk[idx];
+      for (int idx = tid; idx < bs * 3; idx += EG_NT) {
+        const int b = idx / 3, t = idx - b * 3;
+        const int a = b + t - 1, x = s.x0 + b;
+        double cv = 0.0;
+        if (a >= 0 && a < bs && !dflag[(long long)y * g.nnx + x] &&
+            !dflag[(long long)(y + 1) * g.nnx + s.x0 + a])
+          cv = coupling<1>(g, s, E, Cel, x, y, 0, s.x0 + a, y + 1, 0);
+        cpl[idx] = cv;
+      }
+      __syncthreads();
       for (int idx = tid; idx < bs * m; idx += EG_NT) {
         const int b = idx / m, j = idx - (idx / m) * m;
-        const int x = s.x0 + b;
         double w = 0.0;
-        if (!dflag[(long long)y * g.nnx + x]) {
-          for (int di = -1; di <= 1; ++di) {
-            const int a = b + di;
-            if (a < 0 || a >= bs) continue;
-            if (dflag[(long long)(y + 1) * g.nnx + s.x0 + a]) continue;
-            const double cv = coupling<1>(g, s, E, Cel, x, y, 0, s.x0 + a, y + 1, 0);
-            w += cv * Tp[a * MAXM + j];
-          }
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const int a = b + t - 1;
+          if (a >= 0 && a < bs) w += cpl[b * 3 + t] * Tp[a * MAXM + j];
         }
         Wl[b * MAXM + j] = w;
       }
       __syncthreads();
-      const double* Sk = Sinv + s.foff + (long long)k * bs * bs;
       for (int idx = tid; idx < bs * m; idx += EG_NT) {
         const int i = idx % bs, j = idx / bs;
         double acc = 0.0;
-        for (int b = 0; b < bs; ++b) acc += Sk[(long long)b * bs + i] * Wl[b * MAXM + j];
+        for (int b = 0; b < bs; ++b) acc += SkL[b * bs + i] * Wl[b * MAXM + j];
         const double val = Y[(long long)j * n + k * bs + i] - acc;
         Tc[i * MAXM + j] = val;
         Y[(long long)j * n + k * bs + i] = val;
@@ -642,15 +807,15 @@ k_heat_eigen(Geom g, const SysDesc* __restrict__ systems,
       __syncthreads();
       double* t = Tp; Tp = Tc; Tc = t;
     }
-    // M-orthonormalise Y twice (Cholesky QR)
-    for (int pass = 0; pass < 2; ++pass) {
+    const bool do_rr = ((it + 1) % prm.rr_every == 0) || (it + 1 == prm.maxit);
+    // M-orthonormalise Y by Cholesky QR (twice before a Rayleigh-Ritz step)
+    for (int pass = 0; pass < (do_rr ? 2 : 1); ++pass) {
       omega_stencil(g, s, E, dflag, Me, Y, Z, n, m);
       __syncthreads();
       gram(Y, Z, n, m, G, lbuf);
       chol_small(G, m, err);
       apply_linvT(Y, n, m, G);
     }
-    const bool do_rr = ((it + 1) % prm.rr_every == 0) || (it + 1 == prm.maxit);
     if (do_rr) {
       omega_stencil(g, s, E, dflag, Ae, Y, Z, n, m);
       __syncthreads();
@@ -668,16 +833,20 @@ k_heat_eigen(Geom g, const SysDesc* __restrict__ systems,
           }
           order[j + 1] = oi;
         }
-        double dmax = 0.0;
-        const int nchk = min(m, prm.kmax + 1);
-        for (int i = 0; i < nchk; ++i) {
-          const double th = G[order[i] * m + order[i]];
-          const double rel = fabs(th - theta_old[i]) / (fabs(th) + prm.lim);
-          dmax = fmax(dmax, rel);
-          theta[i] = th;
-          theta_old[i] = th;
+        // converge the Ritz values that decide the selection: those below
+        // the threshold (at most kmax) and the next one
+        int nbelow = 0;
+        for (int i = 0; i < m; ++i) {
+          theta[i] = G[order[i] * m + order[i]];
+          if (theta[i] < prm.lim) ++nbelow;
         }
-        for (int i = nchk; i < m; ++i) theta[i] = G[order[i] * m + order[i]];
+        const int nchk = min(m - 1, min(nbelow, prm.kmax) + 1);
+        double dmax = 0.0;
+        for (int i = 0; i < nchk; ++i) {
+          const double rel = fabs(theta[i] - theta_old[i]) / (fabs(theta[i]) + prm.lim);
+          dmax = fmax(dmax, rel);
+        }
+        for (int i = 0; i < m; ++i) theta_old[i] = theta[i];
         converged = (it > 0 && dmax < prm.tol) ? 1 : 0;
       }
       __syncthreads();
@@ -723,34 +892,27 @@ k_heat_eigen(Geom g, const SysDesc* __restrict__ systems,
 
 void launch_factor_elastic(const Geom& g, const SysDesc* sys, int nsys,
                            const double* E, const uint8_t* mask,
-                           const double* Ke, void* out, bool fp32, int* err,
-                           hipStream_t s) {
-  if (fp32)
-    hipLaunchKernelGGL((k_factor<2, float>), dim3(nsys), dim3(FT_NT), 0, s, g,
-                       sys, E, mask, Ke, (float*)out, err);
-  else
-    hipLaunchKernelGGL((k_factor<2, double>), dim3(nsys), dim3(FT_NT), 0, s, g,
-                       sys, E, mask, Ke, (double*)out, err);
+                           const double* Ke, double* out64, float* out32,
+                           double* metric, int* err, hipStream_t s) {
+  hipLaunchKernelGGL(k_factor<2>, dim3(nsys), dim3(FT_NT), 0, s, g, sys, E,
+                     mask, Ke, out64, out32, metric, err);
 }
 
 void launch_factor_heat(const Geom& g, const SysDesc* sys, int nsys,
                         const double* E, const uint8_t* dflag,
                         const double* Cel, double* out, int* err,
                         hipStream_t s) {
-  hipLaunchKernelGGL((k_factor<1, double>), dim3(nsys), dim3(FT_NT), 0, s, g,
-                     sys, E, dflag, Cel, out, err);
+  hipLaunchKernelGGL(k_factor<1>, dim3(nsys), dim3(FT_NT), 0, s, g, sys, E,
+                     dflag, Cel, out, (float*)nullptr, (double*)nullptr, err);
 }
 
 void launch_level1(const Geom& g, const SysDesc* sys, int nsys,
                    const double* E, const uint8_t* mask, const double* Ke,
-                   const void* Sinv, const double* r, void* lsol, bool fp32,
-                   const CGScalars* sc, hipStream_t s) {
-  if (fp32)
-    hipLaunchKernelGGL(k_level1<float>, dim3(nsys), dim3(AP_NT), 0, s, g, sys,
-                       E, mask, Ke, (const float*)Sinv, r, (float*)lsol, sc);
-  else
-    hipLaunchKernelGGL(k_level1<double>, dim3(nsys), dim3(AP_NT), 0, s, g, sys,
-                       E, mask, Ke, (const double*)Sinv, r, (double*)lsol, sc);
+                   const double* S64, const float* S32, const uint8_t* use64,
+                   const double* r, double* lsol, const CGScalars* sc,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_level1, dim3(nsys), dim3(AP_NT), 0, s, g, sys, E, mask,
+                     Ke, S64, S32, use64, r, lsol, sc);
 }
 
 void launch_heat_eigen(const Geom& g, const SysDesc* sys, int nsys,

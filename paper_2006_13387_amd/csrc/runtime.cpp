@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -34,14 +35,15 @@ void launch_dot(long long, const double*, const double*, double*,
 void launch_mask(long long, const uint8_t*, double*, hipStream_t);
 // k_local.hip
 void launch_factor_elastic(const Geom&, const SysDesc*, int, const double*,
-                           const uint8_t*, const double*, void*, bool, int*,
-                           hipStream_t);
+                           const uint8_t*, const double*, double*, float*,
+                           double*, int*, hipStream_t);
 void launch_factor_heat(const Geom&, const SysDesc*, int, const double*,
                         const uint8_t*, const double*, double*, int*,
                         hipStream_t);
 void launch_level1(const Geom&, const SysDesc*, int, const double*,
-                   const uint8_t*, const double*, const void*, const double*,
-                   void*, bool, const CGScalars*, hipStream_t);
+                   const uint8_t*, const double*, const double*, const float*,
+                   const uint8_t*, const double*, double*, const CGScalars*,
+                   hipStream_t);
 void launch_heat_eigen(const Geom&, const SysDesc*, int, const double*,
                        const uint8_t*, const double*, const double*,
                        const double*, const double*, double*, double*, double*,
@@ -87,6 +89,11 @@ constexpr double kEigTol = 1e-10;
 constexpr double kPivotDrop = 1e-12; // scaled K_0 pivots at or below: dropped
 constexpr int kChunk = 16;           // PCG iterations between host checks
 constexpr int kMaxRestarts = 3;
+// FP32 inverse blocks are used for a subdomain only if its amplification
+// metric max_i (S_k^-1)_ii (D_k)_ii stays at or below this bound (see
+// k_factor); above it, FP32 rounding of floating stiff islands' rigid
+// motions (amplitude ~ metric) pollutes the stiff phase.
+constexpr double kFp32MetricMax = 1e6;
 
 struct DevBuf {
   void* p = nullptr;
@@ -95,8 +102,23 @@ struct DevBuf {
 
 }  // namespace
 
+// Event pairs around the launches of selected kernels, for the
+// per-kernel average durations reported by msp_kernel_timing.
+struct KernelTimer {
+  std::vector<hipEvent_t> ev;
+  int used = 0;
+  long long launches = 0;
+  double total_ms = 0.0;
+};
+
+enum { KT_LEVEL1 = 0, KT_MATVEC = 1, KT_EIGEN = 2, KT_COMBINE = 3,
+       KT_RESTRICT = 4, KT_FACTOR = 5, KT_COUNT = 6 };
+
 struct msp_handle {
   msp_problem_desc desc;
+  bool timing = false;
+  int timing_mask = 0;
+  KernelTimer kt[KT_COUNT];
   Geom g;
   std::string err;
   long long n_dofs = 0, n_nodes = 0, n_elems = 0;
@@ -118,8 +140,15 @@ struct msp_handle {
   double* d_E = nullptr;
   SysDesc *d_subs = nullptr, *d_omegas = nullptr;
   int* d_sub_grid = nullptr;
-  void* d_Sinv = nullptr;
-  void* d_lsol = nullptr;
+  double* d_S64 = nullptr;         // FP64 inverse blocks (always)
+  float* d_S32 = nullptr;          // FP32 copy (precision 1)
+  double* d_metric = nullptr;      // per-subdomain amplification metric
+  uint8_t* d_use64 = nullptr;      // per-subdomain: 1 = apply in FP64
+  std::vector<double> metric_h;
+  std::vector<uint8_t> use64_h;
+  int n_fp64_subs = 0;
+  double fp32_metric_max = kFp32MetricMax;
+  double* d_lsol = nullptr;
   double* d_Som = nullptr;
   double *d_X = nullptr, *d_Y = nullptr, *d_Z = nullptr;
   double *d_psi = nullptr, *d_lam = nullptr;
@@ -256,6 +285,8 @@ msp_status build_geometry(msp_handle* h) {
       return fail(h, MSP_E_INVALID, "subdomain row exceeds 72 DOFs (reduce sub_nel + 2*overlap)");
     if ((long long)s.nyb * 2 * s.nxb > MAXBS * 40)
       return fail(h, MSP_E_INVALID, "subdomain exceeds 2880 DOFs");
+    if ((long long)(s.nxb + 1) * (s.nyb + 1) > 3072)
+      return fail(h, MSP_E_INVALID, "subdomain element box exceeds 3072 elements");
     if (s.nxb <= 0 || s.nyb <= 0)
       return fail(h, MSP_E_INVALID, "empty subdomain");
   }
@@ -346,6 +377,42 @@ void tridiag_extremes(const std::vector<double>& d, const std::vector<double>& e
 
 }  // namespace
 
+static int timer_begin(msp_handle* h, int kind, hipStream_t s) {
+  if (!h->timing || !(h->timing_mask & (1 << kind))) return -1;
+  KernelTimer& t = h->kt[kind];
+  if (t.used * 2 + 2 > (int)t.ev.size()) {
+    for (int i = 0; i < 32; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return -1;
+      t.ev.push_back(e);
+    }
+  }
+  const int i = t.used++;
+  (void)hipEventRecord(t.ev[2 * i], s);
+  return i;
+}
+
+static void timer_end(msp_handle* h, int kind, int i, hipStream_t s) {
+  if (i < 0) return;
+  (void)hipEventRecord(h->kt[kind].ev[2 * i + 1], s);
+}
+
+// After a stream synchronisation: fold the recorded pairs into the totals.
+static void timer_flush(msp_handle* h) {
+  if (!h->timing) return;
+  for (int k = 0; k < KT_COUNT; ++k) {
+    KernelTimer& t = h->kt[k];
+    for (int i = 0; i < t.used; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, t.ev[2 * i], t.ev[2 * i + 1]) == hipSuccess) {
+        t.total_ms += ms;
+        t.launches += 1;
+      }
+    }
+    t.used = 0;
+  }
+}
+
 // --------------------------------------------------------------------- API
 
 extern "C" const char* msp_last_error(const msp_handle* h) {
@@ -355,7 +422,8 @@ extern "C" const char* msp_last_error(const msp_handle* h) {
 extern "C" msp_status msp_destroy(msp_handle* h) {
   if (!h) return MSP_OK;
   void* bufs[] = {h->d_elem, h->d_mask, h->d_dflag, h->d_E, h->d_subs,
-                  h->d_omegas, h->d_sub_grid, h->d_Sinv, h->d_lsol, h->d_Som,
+                  h->d_omegas, h->d_sub_grid, h->d_S64, h->d_S32, h->d_metric,
+                  h->d_use64, h->d_lsol, h->d_Som,
                   h->d_X, h->d_Y, h->d_Z, h->d_psi, h->d_lam, h->d_nsel,
                   h->d_cap, h->d_cn, h->d_col_node, h->d_pairs, h->d_W,
                   h->d_K0, h->d_sdiag, h->d_P, h->d_Lp, h->d_Rp, h->d_dropped,
@@ -363,6 +431,8 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
                   h->d_z, h->d_tmp, h->d_sc, h->d_ahist, h->d_bhist,
                   h->d_part, h->d_cnt, h->d_err};
   for (void* p : bufs) dfree(p);
+  for (int k = 0; k < KT_COUNT; ++k)
+    for (hipEvent_t e : h->kt[k].ev) (void)hipEventDestroy(e);
   if (h->h_sc) (void)hipHostFree(h->h_sc);
   if (h->h_int) (void)hipHostFree(h->h_int);
   if (h->h_dbl) (void)hipHostFree(h->h_dbl);
@@ -416,6 +486,7 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
   h->H = std::max(g.sx, g.sy) * d->h;
   h->invH = 1.0 / h->H;
   h->fp32 = d->precision == 1;
+  if (const char* ev = std::getenv("MSP_FP32_METRIC_MAX")) h->fp32_metric_max = std::atof(ev);
   h->mask_h.assign(fixed_mask_host, fixed_mask_host + h->n_dofs);
   for (auto& m : h->mask_h) m = m ? 1 : 0;
   // the GPU heat pencils use one Dirichlet set per node: a node is either
@@ -437,7 +508,6 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
 
   const long long nd = h->n_dofs, nn = h->n_nodes;
   const int m = std::min(d->eig_kmax + kEigExtra, MAXM);
-  const size_t esz = h->fp32 ? sizeof(float) : sizeof(double);
   const int nparts = std::max(std::max(matvec_blocks(g), update_blocks(nd)),
                               std::max(combine_blocks(g), 1024)) * 3 + 16;
   bool ok = true;
@@ -449,8 +519,11 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
   A(dalloc(&h->d_subs, h->subs.size()));
   A(dalloc(&h->d_omegas, h->omegas.size()));
   A(dalloc(&h->d_sub_grid, h->sub_grid.size()));
-  A(hipMalloc(&h->d_Sinv, std::max<size_t>(1, h->l1_entries * esz)));
-  A(hipMalloc(&h->d_lsol, std::max<size_t>(1, h->l1_vec * esz)));
+  A(dalloc(&h->d_S64, h->l1_entries));
+  if (h->fp32) A(dalloc(&h->d_S32, h->l1_entries));
+  A(dalloc(&h->d_metric, h->subs.size()));
+  A(dalloc(&h->d_use64, h->subs.size()));
+  A(dalloc(&h->d_lsol, h->l1_vec));
   A(dalloc(&h->d_Som, h->om_entries));
   A(dalloc(&h->d_X, h->om_vec * m));
   A(dalloc(&h->d_Y, h->om_vec * m));
@@ -575,14 +648,19 @@ extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
   const int kmax = h->desc.eig_kmax;
   const int m = std::min(kmax + kEigExtra, MAXM);
   HIPCHK(h, hipMemsetAsync(h->d_err, 0, sizeof(int), s));
+  int tk = timer_begin(h, KT_FACTOR, s);
   launch_factor_elastic(g, h->d_subs, (int)h->subs.size(), h->d_E, h->d_mask,
-                        Ke, h->d_Sinv, h->fp32, h->d_err, s);
+                        Ke, h->d_S64, h->fp32 ? h->d_S32 : nullptr,
+                        h->d_metric, h->d_err, s);
+  timer_end(h, KT_FACTOR, tk, s);
   launch_factor_heat(g, h->d_omegas, (int)h->omegas.size(), h->d_E,
                      h->d_dflag, Ce, h->d_Som, h->d_err, s);
+  tk = timer_begin(h, KT_EIGEN, s);
   launch_heat_eigen(g, h->d_omegas, (int)h->omegas.size(), h->d_E, h->d_dflag,
                     Ae, Me, Ce, h->d_Som, h->d_X, h->d_Y, h->d_Z, m, kmax,
                     kEigMaxIt, kEigRR, h->desc.eig_tau / (h->H * h->H), kEigTol,
                     h->d_psi, h->d_lam, h->d_nsel, h->d_cap, h->d_err, s);
+  timer_end(h, KT_EIGEN, tk, s);
   HIPCHK(h, hipGetLastError());
   const size_t nom = h->omegas.size();
   h->nsel_h.resize(nom);
@@ -590,9 +668,24 @@ extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
   h->lam_h.resize(nom * kmax);
   HIPCHK(h, hipMemcpyAsync(h->h_int, h->d_err, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
+  timer_flush(h);
   HIPCHK(h, hipMemcpy(h->nsel_h.data(), h->d_nsel, nom * sizeof(int), hipMemcpyDeviceToHost));
   HIPCHK(h, hipMemcpy(cap.data(), h->d_cap, nom * sizeof(int), hipMemcpyDeviceToHost));
   HIPCHK(h, hipMemcpy(h->lam_h.data(), h->d_lam, nom * kmax * sizeof(double), hipMemcpyDeviceToHost));
+  const size_t nsub = h->subs.size();
+  h->metric_h.resize(nsub);
+  h->use64_h.assign(nsub, 1);
+  HIPCHK(h, hipMemcpy(h->metric_h.data(), h->d_metric, nsub * sizeof(double), hipMemcpyDeviceToHost));
+  h->n_fp64_subs = (int)nsub;
+  if (h->fp32) {
+    h->n_fp64_subs = 0;
+    for (size_t i = 0; i < nsub; ++i) {
+      const double mtr = h->metric_h[i];
+      h->use64_h[i] = (!(mtr <= h->fp32_metric_max)) ? 1 : 0;
+      h->n_fp64_subs += h->use64_h[i];
+    }
+  }
+  HIPCHK(h, hipMemcpyAsync(h->d_use64, h->use64_h.data(), nsub, hipMemcpyHostToDevice, s));
   const int kerr = h->h_int[0];
   if (kerr & ERR_NOT_SPD) {
     h->setup_ok = false;
@@ -670,7 +763,7 @@ static CombineArgs combine_args(msp_handle* h, bool l1, bool coarse) {
   ca.ngy = h->ngy;
   ca.sub_vertex = h->desc.sub_mode;
   ca.lsol = h->d_lsol;
-  ca.lsol_fp32 = h->fp32 ? 1 : 0;
+  ca.lsol_fp32 = 0;
   ca.cnodes = h->d_cn;
   ca.psi = h->d_psi;
   ca.c0 = h->d_c0;
@@ -686,17 +779,25 @@ static void enqueue_prec(msp_handle* h, int mode, const double* r,
                          bool use_sc, hipStream_t s) {
   const Geom& g = h->g;
   const CGScalars* sc = use_sc ? h->d_sc : nullptr;
-  if (l1)
+  if (l1) {
+    const int t = timer_begin(h, KT_LEVEL1, s);
     launch_level1(g, h->d_subs, (int)h->subs.size(), h->d_E, h->d_mask,
-                  h->d_elem, h->d_Sinv, r, h->d_lsol, h->fp32, sc, s);
+                  h->d_elem, h->d_S64, h->fp32 ? h->d_S32 : nullptr,
+                  h->fp32 ? h->d_use64 : nullptr, r, h->d_lsol, sc, s);
+    timer_end(h, KT_LEVEL1, t, s);
+  }
   if (coarse && h->nc > 0) {
+    const int t = timer_begin(h, KT_RESTRICT, s);
     launch_restrict(g, h->d_cn, (int)h->cn_h.size(), h->d_mask, h->d_psi, r,
                     h->d_c, h->invH, sc, s);
+    timer_end(h, KT_RESTRICT, t, s);
     launch_coarse_gemv(h->d_K0, h->ldk, h->nc, h->d_c, h->d_c0, sc, s);
   }
   const CombineArgs ca = combine_args(h, l1, coarse);
+  const int t = timer_begin(h, KT_COMBINE, s);
   launch_combine(mode, g, ca, h->d_mask, r, q, z, h->d_sc, h->d_bhist,
                  h->d_part, h->d_cnt + 2, s);
+  timer_end(h, KT_COMBINE, t, s);
 }
 
 static msp_status check_ready(msp_handle* h, hipStream_t s) {
@@ -725,6 +826,7 @@ static msp_status apply_parts(msp_handle* h, const double* r, double* z,
   enqueue_prec(h, 0, r, nullptr, z, l1, coarse, false, s);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(s));
+  timer_flush(h);
   return MSP_OK;
 }
 
@@ -786,6 +888,7 @@ static msp_status solve_one(msp_handle* h, const double* f, double* u,
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(CGScalars), hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
+    timer_flush(h);
     if (h->h_sc->ff == 0.0) {
       HIPCHK(h, hipMemsetAsync(h->d_x, 0, nd * sizeof(double), s));
       break;
@@ -798,8 +901,10 @@ static msp_status solve_one(msp_handle* h, const double* f, double* u,
         for (int it = 0; it < kChunk; ++it) {
           double* pold = cur ? h->d_p1 : h->d_p0;
           double* pnew = cur ? h->d_p0 : h->d_p1;
+          const int tm = timer_begin(h, KT_MATVEC, s);
           launch_cg_matvec(g, h->d_elem, h->d_E, h->d_mask, h->d_z, pold, pnew,
                            h->d_q, h->d_sc, h->d_part, h->d_cnt + 1, s);
+          timer_end(h, KT_MATVEC, tm, s);
           launch_update(nd, h->d_x, h->d_r, pnew, h->d_q, h->d_sc, h->d_ahist,
                         h->d_part, h->d_cnt + 3, s);
           enqueue_prec(h, 1, h->d_r, h->d_q, h->d_z, true, true, true, s);
@@ -808,6 +913,7 @@ static msp_status solve_one(msp_handle* h, const double* f, double* u,
         HIPCHK(h, hipGetLastError());
         HIPCHK(h, hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(CGScalars), hipMemcpyDeviceToHost, s));
         HIPCHK(h, hipStreamSynchronize(s));
+        timer_flush(h);
         if (h->h_sc->done) break;
       }
     }
@@ -870,6 +976,7 @@ static msp_status solve_one(msp_handle* h, const double* f, double* u,
     info->n_coarse = h->nc;
     info->coarse_rank = h->rank;
     info->cap_hits = h->cap_hits;
+    info->fp64_subdomains = h->n_fp64_subs;
     info->relres_true = relres_true;
     info->relres_rec = relres_rec;
     info->compliance = comp;
@@ -972,9 +1079,41 @@ extern "C" msp_status msp_query(msp_handle* h, int64_t* q) {
   q[3] = (int64_t)h->cn_h.size();
   q[4] = h->nc;
   q[5] = maxsys;
-  q[6] = h->l1_entries * (h->fp32 ? 4 : 8);
+  long long l1_bytes = 0;
+  for (size_t i = 0; i < h->subs.size(); ++i) {
+    const SysDesc& s = h->subs[i];
+    const long long ent = (long long)s.nyb * 4LL * s.nxb * s.nxb;
+    const bool f64 = !h->fp32 || (i < h->use64_h.size() ? h->use64_h[i] != 0 : true);
+    l1_bytes += ent * (f64 ? 8 : 4);
+  }
+  q[6] = l1_bytes;
   long long psi_bytes = 0;
   for (const CoarseNode& c : h->cn_h) psi_bytes += (long long)c.nmodes * c.nxw * c.nyw * 8;
   q[7] = psi_bytes;
+  q[8] = h->l1_vec;
+  q[9] = h->om_vec;
+  q[10] = h->om_entries * 8;
+  q[11] = h->ldk;
+  return MSP_OK;
+}
+
+extern "C" msp_status msp_kernel_timing(msp_handle* h, int32_t enable,
+                                        int64_t* launches, double* total_ms,
+                                        int32_t n) {
+  if (!h) return fail(h, MSP_E_INVALID, "null handle");
+  timer_flush(h);
+  for (int k = 0; k < std::min<int>(n, KT_COUNT); ++k) {
+    if (launches) launches[k] = h->kt[k].launches;
+    if (total_ms) total_ms[k] = h->kt[k].total_ms;
+  }
+  if (enable >= 0) {
+    h->timing = enable != 0;
+    h->timing_mask = enable;
+    for (int k = 0; k < KT_COUNT; ++k) {
+      h->kt[k].launches = 0;
+      h->kt[k].total_ms = 0.0;
+      h->kt[k].used = 0;
+    }
+  }
   return MSP_OK;
 }
