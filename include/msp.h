@@ -183,7 +183,9 @@ msp_status msp_vec_dot(int64_t n, const double* x_dev, const double* y_dev,
 
 /* Sizes (12 int64): [0] n DOFs, [1] elements, [2] subdomains, [3] coarse
  * nodes, [4] coarse dimension after setup, [5] largest local system,
- * [6] bytes of local inverse blocks, [7] bytes of stored heat modes psi,
+ * [6] bytes of first-level factor records (inverse Schur blocks and row
+ * couplings, in the precision selected per subdomain) that one first-level
+ * application reads, [7] bytes of stored heat modes psi,
  * [8] sum of local system sizes, [9] sum of neighbourhood sizes,
  * [10] bytes of the neighbourhood inverse blocks, [11] padded K_0 order. */
 msp_status msp_query(msp_handle* h, int64_t* sizes12);

@@ -243,7 +243,7 @@ class Solver:
         q = (ctypes.c_int64 * 12)()
         self._check(self.L.msp_query(self.h, q))
         keys = ["n_dofs", "n_elems", "n_subdomains", "n_coarse_nodes",
-                "n_coarse", "max_local", "local_factor_bytes",
+                "n_coarse", "max_local", "level1_record_bytes",
                 "coarse_basis_bytes", "local_vec_entries",
                 "omega_vec_entries", "omega_factor_bytes", "ldk"]
         return dict(zip(keys, [int(v) for v in q]))

@@ -73,4 +73,47 @@ __device__ __forceinline__ bool finite(double v) {
   return __builtin_isfinite(v);
 }
 
+// Block-uniform read of the CG "done" word (another workgroup of the same
+// kernel may write it while this one runs; the value is read once by thread
+// 0 and broadcast through LDS so that every thread takes the same branch).
+__device__ __forceinline__ int block_read_done(const CGScalars* sc, int* sh) {
+  if (threadIdx.x == 0)
+    *sh = __hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const int d = *sh;
+  __syncthreads();
+  return d;
+}
+
+// Convergence test after the update x += alpha p, r -= alpha q: every
+// workgroup sums the update kernel's partials of r.r in the same fixed
+// order; workgroup 0 records the outcome.  Returns true when the iteration
+// is over (converged, iteration limit or non-finite residual).
+template <int NT>
+__device__ bool cg_check_done(CGScalars* sc, const double* part_upd, int nb_upd,
+                              double* red, int* sh) {
+  if (block_read_done(sc, sh)) return true;
+  const double rr = reduce_partials<NT>(part_upd, nb_upd, 1, red);
+  // the decision is taken by thread 0 and broadcast, so that it is uniform
+  // in the workgroup even if workgroup 0 updates the counters meanwhile
+  if (threadIdx.x == 0) {
+    const int it1 = sc->iter + 1;
+    int d = DONE_RUNNING;
+    if (!finite(rr)) d = DONE_BREAKDOWN;
+    else if (rr <= sc->tol2 * sc->ff) d = DONE_CONVERGED;
+    else if (it1 >= sc->maxit) d = DONE_MAXIT;
+    if (d != DONE_RUNNING && blockIdx.x == 0) {
+      sc->rr = rr;
+      sc->iter = it1;
+      if (d == DONE_BREAKDOWN) sc->status = -5;
+      __hip_atomic_store(&sc->done, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    *sh = d;
+  }
+  __syncthreads();
+  const bool over = *sh != DONE_RUNNING;
+  __syncthreads();
+  return over;
+}
+
 }  // namespace msp

@@ -341,31 +341,44 @@ __global__ void k_k0_unscale(double* __restrict__ K0, int ldk,
 }
 
 // ---------------------------------------------------------------------
-// Restriction c = R_0 r: one workgroup per coarse node.  Each thread takes
-// nodes of the neighbourhood (coalesced psi and r reads), reads r, the mask
-// and chi once per node and accumulates every column of the node in
-// registers; the column sums are a wavefront butterfly and a fixed-order
-// sum over the waves.
+// Restriction c = R_0 r: RS_CH workgroups per coarse node, each over a
+// band of rows of the neighbourhood.  A thread reads r, the mask and chi
+// once per node and accumulates every column of the node in registers
+// (coalesced psi reads); column sums are a wavefront butterfly and a
+// fixed-order sum over the waves, written per band to cpart[band][col].
 constexpr int RS_NT = 256;
+constexpr int RS_CH = 4;
 constexpr int KMAXD = 24;
 
 __global__ void __launch_bounds__(RS_NT)
 k_restrict(Geom g, const CoarseNode* __restrict__ cnodes,
            const uint8_t* __restrict__ mask, const double* __restrict__ psi,
-           const double* __restrict__ r, double* __restrict__ c, double invH,
-           const CGScalars* __restrict__ sc) {
+           const double* __restrict__ r, double* __restrict__ cpart, int ldc,
+           double invH, CGScalars* __restrict__ sc,
+           const double* __restrict__ part_upd, int nb_upd, int check) {
   __shared__ double red[(2 * KMAXD + 1) * (RS_NT / 64)];
-  if (sc != nullptr && sc->done) return;
-  const CoarseNode cn = cnodes[blockIdx.x];
+  __shared__ double redc[RS_NT / 64 + 1];
+  __shared__ int shi;
+  if (sc != nullptr) {
+    if (check) {
+      if (cg_check_done<RS_NT>(sc, part_upd, nb_upd, redc, &shi)) return;
+    } else if (block_read_done(sc, &shi)) {
+      return;
+    }
+  }
+  const CoarseNode cn = cnodes[blockIdx.x / RS_CH];
+  const int band = blockIdx.x % RS_CH;
   const int nm = cn.nmodes;
   const int ncol = 2 * nm + cn.nrot;
   if (ncol == 0) return;
   const int nw = cn.nxw * cn.nyw;
+  const int r0w = (band * cn.nyw) / RS_CH, r1w = ((band + 1) * cn.nyw) / RS_CH;
+  const int lo = r0w * cn.nxw, hi = r1w * cn.nxw;
   const double* ps = psi + cn.psi_off;
   double ax[KMAXD], ay[KMAXD], ar = 0.0;
 #pragma unroll
   for (int j = 0; j < KMAXD; ++j) ax[j] = ay[j] = 0.0;
-  for (int loc = threadIdx.x; loc < nw; loc += RS_NT) {
+  for (int loc = lo + threadIdx.x; loc < hi; loc += RS_NT) {
     const int x = cn.x0 + loc % cn.nxw, y = cn.y0 + loc / cn.nxw;
     const double chi = chi_at(g, cn.cx, cn.cy, x, y);
     const long long node = (long long)y * g.nnx + x;
@@ -405,41 +418,56 @@ k_restrict(Geom g, const CoarseNode* __restrict__ cnodes,
     double t = 0.0;
 #pragma unroll
     for (int q = 0; q < RS_NT / 64; ++q) t += red[j * (RS_NT / 64) + q];
-    c[cn.col0 + j] = t;
+    cpart[(long long)band * ldc + cn.col0 + j] = t;
   }
 }
 
-// c0 = K0p c : one wavefront per row (K0p symmetric, row-major).
-__global__ void __launch_bounds__(256)
+// c0 = K0p c with c = sum over bands of cpart: each workgroup (16 waves)
+// sums the bands into LDS once, then every wave forms 4 rows (K0p
+// symmetric, row-major, coalesced along the row).
+constexpr int GV_NT = 1024;
+constexpr int GV_ROWS = 64;
+constexpr int GV_MAXC = 12288;
+
+__global__ void __launch_bounds__(GV_NT)
 k_coarse_gemv(const double* __restrict__ K0, int ldk, int nc,
-              const double* __restrict__ c, double* __restrict__ c0,
-              const CGScalars* __restrict__ sc) {
-  if (sc != nullptr && sc->done) return;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (row >= nc) return;
-  const double* a = K0 + (long long)row * ldk;
-  double s = 0.0;
-  for (int j = lane; j < nc; j += 64) s += a[j] * c[j];
-  s = wave_sum(s);
-  if (lane == 0) c0[row] = s;
+              const double* __restrict__ cpart, int ldc,
+              double* __restrict__ c0, const CGScalars* __restrict__ sc) {
+  __shared__ double cl[GV_MAXC];
+  __shared__ int shi;
+  if (sc != nullptr && block_read_done(sc, &shi)) return;
+  for (int j = threadIdx.x; j < nc; j += GV_NT) {
+    double t = 0.0;
+#pragma unroll
+    for (int b = 0; b < RS_CH; ++b) t += cpart[(long long)b * ldc + j];
+    cl[j] = t;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int rr = 0; rr < GV_ROWS / (GV_NT / 64); ++rr) {
+    const int row = blockIdx.x * GV_ROWS + wave * (GV_ROWS / (GV_NT / 64)) + rr;
+    if (row >= nc) break;
+    const double* a = K0 + (long long)row * ldk;
+    double s = 0.0;
+    for (int j = lane; j < nc; j += 64) s += a[j] * cl[j];
+    s = wave_sum(s);
+    if (lane == 0) c0[row] = s;
+  }
 }
 
-// z = [sum_i R_i^T x_i] + [R_0^T c0] at every node; optional dot products
-// (r.z and z.q) with the beta of Fletcher-Reeves or, flexible, Polak-Ribiere
-// (beta = -alpha (z.q) / (r.z)_old since r_new - r_old = -alpha q).
-
-
-template <int MODE>   // 0: plain apply, 1: CG iteration, 2: CG start
+// MODE 0: plain apply.  MODE 1 (CG iteration) and 2 (CG start): also the
+// partial sums of r.z and, flexible, z.q per workgroup, read by the next
+// iteration's stiffness and update kernels; in MODE 1 workgroup 0 advances
+// the iteration counter.
+template <int MODE>
 __global__ void __launch_bounds__(256)
 k_combine(Geom g, CombineArgs ca, const uint8_t* __restrict__ mask,
           const double* __restrict__ r, const double* __restrict__ q,
           double* __restrict__ z, CGScalars* __restrict__ sc,
-          double* __restrict__ beta_hist, double* __restrict__ part,
-          unsigned int* __restrict__ counter) {
+          double* __restrict__ part) {
   __shared__ double red[256 / 64 + 1];
-  __shared__ unsigned int ticket;
-  if (MODE != 0 && sc->done) return;
+  __shared__ int shi;
+  if (MODE != 0 && block_read_done(sc, &shi)) return;
   const long long node = (long long)blockIdx.x * 256 + threadIdx.x;
   const long long nn = (long long)g.nnx * g.nny;
   double d_rz = 0.0, d_zq = 0.0;
@@ -457,15 +485,9 @@ k_combine(Geom g, CombineArgs ca, const uint8_t* __restrict__ mask,
           const SysDesc s = ca.sys[sid];
           if (x < s.x0 || x >= s.x0 + s.nxb || y < s.y0 || y >= s.y0 + s.nyb) continue;
           const long long li = s.voff + 2 * ((long long)(y - s.y0) * s.nxb + (x - s.x0));
-          if (ca.lsol_fp32) {
-            const float* ls = (const float*)ca.lsol;
-            z0 += (double)ls[li];
-            z1 += (double)ls[li + 1];
-          } else {
-            const double* ls = (const double*)ca.lsol;
-            z0 += ls[li];
-            z1 += ls[li + 1];
-          }
+          const double* ls = (const double*)ca.lsol;
+          z0 += ls[li];
+          z1 += ls[li + 1];
         }
       }
     }
@@ -516,36 +538,12 @@ k_combine(Geom g, CombineArgs ca, const uint8_t* __restrict__ mask,
     }
   }
   if (MODE == 0) return;
-  const unsigned int nb = gridDim.x;
   const double s_rz = block_sum<256>(d_rz, red);
   const double s_zq = block_sum<256>(d_zq, red);
   if (threadIdx.x == 0) {
     part[blockIdx.x] = s_rz;
-    part[nb + blockIdx.x] = s_zq;
-  }
-  if (!last_block(counter, nb, &ticket)) return;
-  const double rz = reduce_partials<256>(part, nb, 1, red);
-  const double zq = reduce_partials<256>(part + nb, nb, 1, red);
-  if (threadIdx.x == 0) {
-    if (MODE == 2) {
-      sc->rz = rz;
-      sc->beta = 0.0;
-    } else {
-      const double rz_old = sc->rz;
-      double beta = sc->flexible ? (-sc->alpha * zq / rz_old) : (rz / rz_old);
-      if (!finite(beta)) {
-        sc->done = DONE_BREAKDOWN;
-        sc->status = -5;
-        beta = 0.0;
-      }
-      sc->zq = zq;
-      sc->rz_old = rz_old;
-      sc->rz = rz;
-      sc->beta = beta;
-      const int it = sc->iter;
-      if (it >= 1 && it <= sc->maxit) beta_hist[it - 1] = beta;
-    }
-    *counter = 0u;
+    part[gridDim.x + blockIdx.x] = s_zq;
+    if (MODE == 1 && blockIdx.x == 0) sc->iter = sc->iter + 1;
   }
 }
 
@@ -611,17 +609,22 @@ void launch_k0_pinv(double* K0, int ldk, int nc, double* sdiag, double* P,
 
 void launch_restrict(const Geom& g, const CoarseNode* cn, int ncn,
                      const uint8_t* mask, const double* psi, const double* r,
-                     double* c, double invH, const CGScalars* sc,
+                     double* cpart, int ldc, double invH, CGScalars* sc,
+                     const double* part_upd, int nb_upd, int check,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_restrict, dim3(ncn), dim3(RS_NT), 0, s, g, cn, mask, psi,
-                     r, c, invH, sc);
+  hipLaunchKernelGGL(k_restrict, dim3(ncn * RS_CH), dim3(RS_NT), 0, s, g, cn,
+                     mask, psi, r, cpart, ldc, invH, sc, part_upd, nb_upd,
+                     check);
 }
 
-void launch_coarse_gemv(const double* K0, int ldk, int nc, const double* c,
-                        double* c0, const CGScalars* sc, hipStream_t s) {
+int restrict_bands() { return RS_CH; }
+
+void launch_coarse_gemv(const double* K0, int ldk, int nc, const double* cpart,
+                        int ldc, double* c0, const CGScalars* sc,
+                        hipStream_t s) {
   if (nc <= 0) return;
-  hipLaunchKernelGGL(k_coarse_gemv, dim3((nc + 3) / 4), dim3(256), 0, s, K0,
-                     ldk, nc, c, c0, sc);
+  hipLaunchKernelGGL(k_coarse_gemv, dim3((nc + GV_ROWS - 1) / GV_ROWS),
+                     dim3(GV_NT), 0, s, K0, ldk, nc, cpart, ldc, c0, sc);
 }
 
 int combine_blocks(const Geom& g) {
@@ -630,18 +633,17 @@ int combine_blocks(const Geom& g) {
 
 void launch_combine(int mode, const Geom& g, const CombineArgs& ca,
                     const uint8_t* mask, const double* r, const double* q,
-                    double* z, CGScalars* sc, double* beta_hist, double* part,
-                    unsigned int* counter, hipStream_t s) {
+                    double* z, CGScalars* sc, double* part, hipStream_t s) {
   const dim3 grid(combine_blocks(g));
   if (mode == 0)
     hipLaunchKernelGGL(k_combine<0>, grid, dim3(256), 0, s, g, ca, mask, r, q, z,
-                       sc, beta_hist, part, counter);
+                       sc, part);
   else if (mode == 1)
     hipLaunchKernelGGL(k_combine<1>, grid, dim3(256), 0, s, g, ca, mask, r, q, z,
-                       sc, beta_hist, part, counter);
+                       sc, part);
   else
     hipLaunchKernelGGL(k_combine<2>, grid, dim3(256), 0, s, g, ca, mask, r, q, z,
-                       sc, beta_hist, part, counter);
+                       sc, part);
 }
 
 void launch_export_basis(const Geom& g, const CoarseNode* cn,

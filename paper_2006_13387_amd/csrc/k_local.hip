@@ -18,7 +18,7 @@
 namespace msp {
 
 constexpr int FT_NT = 256;    // factorisation workgroup
-constexpr int AP_NT = 256;    // first-level apply workgroup
+constexpr int AP_NT = 512;    // first-level apply workgroup
 constexpr int EG_NT = 512;    // eigen workgroup
 constexpr int LDSTR = MAXBS + 1;   // LDS row stride of a dense block
 
@@ -173,17 +173,27 @@ k_factor(Geom g, const SysDesc* __restrict__ systems,
     }
     __syncthreads();
     gj_invert<FT_NT>(S, bs, rowv, colv, err);
-    double* o = out64 + s.foff + (long long)k * bs * bs;
+    // record of row k: the inverse block (column j contiguous) and, for the
+    // elasticity systems, the couplings F(k) of row k with row k-1 (zero
+    // for k = 0) that the first-level apply streams with it
+    const long long rec = (long long)bs * bs + (NDOF == 2 ? 6LL * bs : 0LL);
+    double* o = out64 + s.foff + (long long)k * rec;
     for (int idx = tid; idx < bs * bs; idx += FT_NT) {
       const int j = idx / bs, i = idx - (idx / bs) * bs;
-      o[idx] = S[i * LDSTR + j];      // column j contiguous
+      o[idx] = S[i * LDSTR + j];
     }
+    if (NDOF == 2)
+      for (int idx = tid; idx < bs * 6; idx += FT_NT)
+        o[bs * bs + idx] = (k > 0) ? Bv[idx] : 0.0;
     if (out32 != nullptr) {
-      float* o32 = out32 + s.foff + (long long)k * bs * bs;
+      float* o32 = out32 + s.foff + (long long)k * rec;
       for (int idx = tid; idx < bs * bs; idx += FT_NT) {
         const int j = idx / bs, i = idx - (idx / bs) * bs;
         o32[idx] = (float)S[i * LDSTR + j];
       }
+      if (NDOF == 2)
+        for (int idx = tid; idx < bs * 6; idx += FT_NT)
+          o32[bs * bs + idx] = (k > 0) ? (float)Bv[idx] : 0.0f;
     }
     for (int a = tid; a < bs; a += FT_NT) mloc = fmax(mloc, S[a * LDSTR + a] * ddiag[a]);
     __syncthreads();
@@ -209,218 +219,362 @@ k_factor(Geom g, const SysDesc* __restrict__ systems,
 // ---------------------------------------------------------------------
 // First level: z_i = K_i^{-1} R_i r for every subdomain (2D elasticity).
 //
-// One workgroup per subdomain.  At kernel start the subdomain's element
-// moduli, element matrix, mask and right-hand side go to LDS; the sweep is
-// then a chain of nyb-1 + nyb steps.  In each step threads 0..bs-1 form the
-// block right-hand side and multiply it by the inverse block held in LDS
-// (thread i owns row i: no cross-thread reduction), while the remaining
-// threads build the next step's coupling coefficients from the LDS moduli
-// and every thread streams its share of the next inverse block from HBM
-// into registers, stored to the second LDS buffer at the end of the step.
-// Two barriers per step; HBM latency overlaps the arithmetic.
-constexpr int L1_EBOX = 3072;      // element moduli of one subdomain box
-constexpr int L1_PF = (MAXBS * MAXBS + AP_NT - 1) / AP_NT;
+// One workgroup of 8 waves per subdomain; the local vector stays in LDS.
+// Each node row k has a record in HBM: its inverse Schur block S_k^{-1}
+// (column-major) followed by the couplings F(k) of row k with row k-1,
+// written by the factorisation.  The sweep is a chain of nyb forward and
+// nyb-1 backward steps; step c uses the record of row k(c).
+//  * waves 4-7 ("loaders") copy records straight from HBM into a ring of R
+//    LDS slots with direct-to-LDS loads (global_load_lds, 16 bytes a lane),
+//    R-1 steps ahead, and wait with an explicit vmcnt for the record of the
+//    next step only: the HBM latency of a record overlaps R-1 steps;
+//  * waves 0-3 ("compute") only read and write LDS, so they never wait on
+//    memory.  Phase 1 forms the block right-hand side w from the
+//    neighbouring row (forward: F(k) of this record; backward: F(k+1), kept
+//    from the previous step, read transposed); phase 2 multiplies w by the
+//    inverse block, split over L1_NS column groups (thread (q, i) sums
+//    row i over group q).  The group partial sums are added up where they
+//    are next used, in the following step's phase 1, which also retires
+//    the finished row into v.
+// Two barriers per step.
+constexpr int L1_NS = 3;                   // column groups of the block GEMV
+constexpr int L1_GMAX = (MAXBS + L1_NS - 1) / L1_NS;   // columns per group
+constexpr int L1_COMPUTE = 256;            // threads of the compute waves
+constexpr int L1_NLW = (AP_NT - L1_COMPUTE) / 64;   // loader waves
+constexpr int L1_CHUNK = 1024;             // bytes of one wave's DMA load
+constexpr int L1_LDS = 160 * 1024 - 256;   // LDS of the apply kernel
+static_assert(L1_NS * MAXBS <= L1_COMPUTE, "GEMV threads exceed the compute waves");
 
-template <typename T>
-struct L1Lds {
-  T SL[2][MAXBS * MAXBS];
-  T v[MAXBS * 40];
-  T tmp[MAXBS];
-  T Bc[2][MAXBS * 6];
-  double Es[L1_EBOX];
-  double Ks[64];
-  uint8_t mk[MAXBS * 40];
+// ring geometry of one subdomain: R slots of nch 1 KiB chunks; chunk q is
+// copied by loader wave q % L1_NLW
+struct L1Ring {
+  int rec;       // record elements (bs^2 + 6 bs)
+  int nch;       // chunks per record
+  int slot;      // slot bytes
+  int R;         // ring depth, 2..8
 };
 
-// coupling of DOF (ia, ca) of node row ya with DOF (ib, cb) of row yb =
-// ya -+ 1, from the moduli in LDS (box origin x0-1, y0-1, width nxb+1)
-__device__ __forceinline__ double l1_coupling(const Geom& g, const SysDesc& s,
-                                              const double* Es,
-                                              const double* Ks, int ia, int ya,
-                                              int ca, int ib, int yb, int cb) {
-  const int xa = s.x0 + ia, xb = s.x0 + ib;
-  const int ey = min(ya, yb);                      // element row between them
-  double v = 0.0;
-  for (int ex = max(xa, xb) - 1; ex <= min(xa, xb); ++ex) {
-    if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny) continue;
-    const int va = (xa - ex) + 2 * (ya - ey);
-    const int vb = (xb - ex) + 2 * (yb - ey);
-    const double e = Es[(ey - (s.y0 - 1)) * (s.nxb + 1) + (ex - (s.x0 - 1))];
-    v += e * Ks[(2 * va + ca) * 8 + 2 * vb + cb];
-  }
-  return v;
+// LDS elements beside the ring: v (nb*bs), w (bs), partial sums
+// (2 step parities x L1_NS groups x MAXBS)
+__host__ __device__ inline int l1_vec_elems(int bs, int nb) {
+  return nb * bs + bs + 2 * L1_NS * MAXBS;
 }
 
-// couplings of every DOF of local row k with its 3 neighbour nodes in
-// row k + dir (dir = -1 forward, +1 backward), zero for clamped DOFs
 template <typename T>
-__device__ __forceinline__ void l1_row_couplings(const Geom& g,
-                                                 const SysDesc& s,
-                                                 L1Lds<T>& L, int k, int dir,
-                                                 T* out, int t0, int nthr) {
-  const int bs = 2 * s.nxb;
-  for (int idx = t0; idx < bs * 6; idx += nthr) {
-    const int a = idx / 6, t = idx - a * 6;
-    const int ia = a >> 1, ca = a & 1;
-    const int ib = ia + t / 2 - 1, cb = t & 1;
-    double cv = 0.0;
-    if (ib >= 0 && ib < s.nxb && !L.mk[k * bs + a] &&
-        !L.mk[(k + dir) * bs + 2 * ib + cb])
-      cv = l1_coupling(g, s, L.Es, L.Ks, ia, s.y0 + k, ca, ib, s.y0 + k + dir, cb);
-    out[idx] = (T)cv;
+__host__ __device__ inline L1Ring l1_ring(int bs, int nb) {
+  L1Ring g;
+  g.rec = bs * bs + 6 * bs;
+  g.nch = (g.rec * (int)sizeof(T) + L1_CHUNK - 1) / L1_CHUNK;
+  g.slot = g.nch * L1_CHUNK;
+  const int vbytes = l1_vec_elems(bs, nb) * (int)sizeof(T);
+  const int per_wave = (g.nch + L1_NLW - 1) / L1_NLW;
+  g.R = 2;
+  // deeper rings while they fit and the vmcnt wait stays within 63
+  while (g.R < 8 && (g.R + 1) * g.slot + vbytes <= L1_LDS &&
+         (g.R - 1) * per_wave <= 63)
+    ++g.R;
+  return g;
+}
+
+template <typename T>
+__host__ __device__ inline bool l1_fits(int bs, int nb) {
+  const L1Ring g = l1_ring<T>(bs, nb);
+  return g.R * g.slot + l1_vec_elems(bs, nb) * (int)sizeof(T) <= L1_LDS;
+}
+
+// s_waitcnt vmcnt(n) for a wave-uniform n in 0..63 (larger n waits for 63)
+__device__ __forceinline__ void wait_vmcnt(int n) {
+  switch (n) {
+    case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+    case 1: asm volatile("s_waitcnt vmcnt(1)" ::: "memory"); break;
+    case 2: asm volatile("s_waitcnt vmcnt(2)" ::: "memory"); break;
+    case 3: asm volatile("s_waitcnt vmcnt(3)" ::: "memory"); break;
+    case 4: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
+    case 5: asm volatile("s_waitcnt vmcnt(5)" ::: "memory"); break;
+    case 6: asm volatile("s_waitcnt vmcnt(6)" ::: "memory"); break;
+    case 7: asm volatile("s_waitcnt vmcnt(7)" ::: "memory"); break;
+    case 8: asm volatile("s_waitcnt vmcnt(8)" ::: "memory"); break;
+    case 9: asm volatile("s_waitcnt vmcnt(9)" ::: "memory"); break;
+    case 10: asm volatile("s_waitcnt vmcnt(10)" ::: "memory"); break;
+    case 11: asm volatile("s_waitcnt vmcnt(11)" ::: "memory"); break;
+    case 12: asm volatile("s_waitcnt vmcnt(12)" ::: "memory"); break;
+    case 13: asm volatile("s_waitcnt vmcnt(13)" ::: "memory"); break;
+    case 14: asm volatile("s_waitcnt vmcnt(14)" ::: "memory"); break;
+    case 15: asm volatile("s_waitcnt vmcnt(15)" ::: "memory"); break;
+    case 16: asm volatile("s_waitcnt vmcnt(16)" ::: "memory"); break;
+    case 17: asm volatile("s_waitcnt vmcnt(17)" ::: "memory"); break;
+    case 18: asm volatile("s_waitcnt vmcnt(18)" ::: "memory"); break;
+    case 19: asm volatile("s_waitcnt vmcnt(19)" ::: "memory"); break;
+    case 20: asm volatile("s_waitcnt vmcnt(20)" ::: "memory"); break;
+    case 21: asm volatile("s_waitcnt vmcnt(21)" ::: "memory"); break;
+    case 22: asm volatile("s_waitcnt vmcnt(22)" ::: "memory"); break;
+    case 23: asm volatile("s_waitcnt vmcnt(23)" ::: "memory"); break;
+    case 24: asm volatile("s_waitcnt vmcnt(24)" ::: "memory"); break;
+    case 25: asm volatile("s_waitcnt vmcnt(25)" ::: "memory"); break;
+    case 26: asm volatile("s_waitcnt vmcnt(26)" ::: "memory"); break;
+    case 27: asm volatile("s_waitcnt vmcnt(27)" ::: "memory"); break;
+    case 28: asm volatile("s_waitcnt vmcnt(28)" ::: "memory"); break;
+    case 29: asm volatile("s_waitcnt vmcnt(29)" ::: "memory"); break;
+    case 30: asm volatile("s_waitcnt vmcnt(30)" ::: "memory"); break;
+    case 31: asm volatile("s_waitcnt vmcnt(31)" ::: "memory"); break;
+    case 32: asm volatile("s_waitcnt vmcnt(32)" ::: "memory"); break;
+    case 33: asm volatile("s_waitcnt vmcnt(33)" ::: "memory"); break;
+    case 34: asm volatile("s_waitcnt vmcnt(34)" ::: "memory"); break;
+    case 35: asm volatile("s_waitcnt vmcnt(35)" ::: "memory"); break;
+    case 36: asm volatile("s_waitcnt vmcnt(36)" ::: "memory"); break;
+    case 37: asm volatile("s_waitcnt vmcnt(37)" ::: "memory"); break;
+    case 38: asm volatile("s_waitcnt vmcnt(38)" ::: "memory"); break;
+    case 39: asm volatile("s_waitcnt vmcnt(39)" ::: "memory"); break;
+    case 40: asm volatile("s_waitcnt vmcnt(40)" ::: "memory"); break;
+    case 41: asm volatile("s_waitcnt vmcnt(41)" ::: "memory"); break;
+    case 42: asm volatile("s_waitcnt vmcnt(42)" ::: "memory"); break;
+    case 43: asm volatile("s_waitcnt vmcnt(43)" ::: "memory"); break;
+    case 44: asm volatile("s_waitcnt vmcnt(44)" ::: "memory"); break;
+    case 45: asm volatile("s_waitcnt vmcnt(45)" ::: "memory"); break;
+    case 46: asm volatile("s_waitcnt vmcnt(46)" ::: "memory"); break;
+    case 47: asm volatile("s_waitcnt vmcnt(47)" ::: "memory"); break;
+    case 48: asm volatile("s_waitcnt vmcnt(48)" ::: "memory"); break;
+    case 49: asm volatile("s_waitcnt vmcnt(49)" ::: "memory"); break;
+    case 50: asm volatile("s_waitcnt vmcnt(50)" ::: "memory"); break;
+    case 51: asm volatile("s_waitcnt vmcnt(51)" ::: "memory"); break;
+    case 52: asm volatile("s_waitcnt vmcnt(52)" ::: "memory"); break;
+    case 53: asm volatile("s_waitcnt vmcnt(53)" ::: "memory"); break;
+    case 54: asm volatile("s_waitcnt vmcnt(54)" ::: "memory"); break;
+    case 55: asm volatile("s_waitcnt vmcnt(55)" ::: "memory"); break;
+    case 56: asm volatile("s_waitcnt vmcnt(56)" ::: "memory"); break;
+    case 57: asm volatile("s_waitcnt vmcnt(57)" ::: "memory"); break;
+    case 58: asm volatile("s_waitcnt vmcnt(58)" ::: "memory"); break;
+    case 59: asm volatile("s_waitcnt vmcnt(59)" ::: "memory"); break;
+    case 60: asm volatile("s_waitcnt vmcnt(60)" ::: "memory"); break;
+    case 61: asm volatile("s_waitcnt vmcnt(61)" ::: "memory"); break;
+    case 62: asm volatile("s_waitcnt vmcnt(62)" ::: "memory"); break;
+    default: asm volatile("s_waitcnt vmcnt(63)" ::: "memory"); break;
   }
+}
+
+// GEMV of one column group: sum over j < n of S[j*ld + i] * w[j], n <= NJ,
+// fully unrolled with every LDS read issued before the first use; columns
+// j >= n read a valid entry (column 0 of the group) and weigh it by 0.
+// Four accumulators in a fixed order.
+template <typename T, int NJ>
+__device__ __forceinline__ T lds_gemv_group(const T* S, int ld, int i,
+                                            const T* w, int n) {
+  T s[NJ], x[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int jc = j < n ? j : 0;
+    s[j] = S[jc * ld + i];
+    x[j] = w[jc];
+  }
+  T a[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) a[j & 3] += s[j] * (j < n ? x[j] : (T)0);
+  return (a[0] + a[1]) + (a[2] + a[3]);
+}
+
+// block index used at sweep step c (forward steps 0..nb-1, then backward
+// steps nb..2nb-2 on blocks nb-2..0)
+__device__ __forceinline__ int l1_block_of_step(int c, int nb) {
+  return c < nb ? c : 2 * nb - 2 - c;
+}
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// loader wave lw: DMA its chunks of the record of row k into the LDS slot
+template <typename T>
+__device__ __forceinline__ void l1_dma(const T* base, int rec, int k,
+                                       unsigned char* slot, int nch,
+                                       int lw, int lane) {
+  const unsigned char* src =
+      reinterpret_cast<const unsigned char*>(base + (long long)k * rec);
+  for (int q = lw; q < nch; q += L1_NLW) {
+    const int off = q * L1_CHUNK;
+    __builtin_amdgcn_global_load_lds((const void*)(src + off + 16 * lane),
+                                     (lds_void*)(slot + off), 16, 0, 0);
+  }
+}
+
+// Workgroup barrier ordering LDS accesses only.  __syncthreads(), and any
+// release fence that covers LDS, makes every wave wait for all of its
+// loads in flight, the direct-to-LDS record loads included; the ring waits
+// for those itself with an explicit vmcnt before it reaches the barrier.
+// The asm's memory clobber keeps the compiler from moving memory accesses
+// across it.
+__device__ __forceinline__ void l1_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
 template <typename T>
 __device__ void level1_body(const Geom& g, const SysDesc& s,
-                            const double* __restrict__ E,
                             const uint8_t* __restrict__ mask,
-                            const double* __restrict__ Kel,
                             const T* __restrict__ Sinv,
                             const double* __restrict__ r,
                             double* __restrict__ lsol, unsigned char* lds) {
-  L1Lds<T>& L = *reinterpret_cast<L1Lds<T>*>(lds);
   const int tid = threadIdx.x;
   const int bs = 2 * s.nxb;
   const int nb = s.nyb;
   const int bs2 = bs * bs;
-  const int ew = s.nxb + 1;
+  const int nsteps = 2 * nb - 1;
+  const L1Ring ring = l1_ring<T>(bs, nb);
+  const int R = ring.R;
   const T* base = Sinv + s.foff;
+  T* v = reinterpret_cast<T*>(lds + R * ring.slot);
+  T* w = v + nb * bs;
+  T* P = w + bs;                              // P[parity][group][MAXBS]
+  const bool loader = tid >= L1_COMPUTE;
+  const int lw = __builtin_amdgcn_readfirstlane((tid - L1_COMPUTE) >> 6);
+  const int lane = tid & 63;
+  // loads this wave issues per record, and after the record it waits for
+  const int cw = lw < ring.nch ? (ring.nch - lw + L1_NLW - 1) / L1_NLW : 0;
+  const int younger = (R - 2) * cw;
+  // GEMV role: column group q, row i
+  const int cs = (bs + L1_NS - 1) / L1_NS;
+  const int gq = tid / bs, gi = tid - (tid / bs) * bs;
+  const int j0 = gq * cs;
+  const int jn = min(bs, j0 + cs) - j0;
+  const bool gemv = tid < L1_NS * bs;
+  // phase-1 role: row entry tid, its node and component
+  const int ia = tid >> 1, ca = tid & 1;
 
-  if (tid < 64) L.Ks[tid] = Kel[tid];
-  for (int idx = tid; idx < ew * (nb + 1); idx += AP_NT) {
-    const int ex = s.x0 - 1 + idx % ew, ey = s.y0 - 1 + idx / ew;
-    L.Es[idx] = (ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny)
-                    ? E[(long long)ey * g.nx + ex] : 0.0;
+  if (loader) {
+    for (int c = 0; c < R - 1; ++c) {
+      const int st = c < nsteps ? c : nsteps - 1;
+      l1_dma<T>(base, ring.rec, l1_block_of_step(st, nb), lds + (c % R) * ring.slot,
+                ring.nch, lw, lane);
+    }
   }
   for (int idx = tid; idx < nb * bs; idx += AP_NT) {
     const int k = idx / bs, a = idx - (idx / bs) * bs;
     const long long d = 2 * ((long long)(s.y0 + k) * g.nnx + s.x0 + a / 2) + (a & 1);
-    const uint8_t m = mask[d];
-    L.mk[idx] = m;
-    L.v[idx] = m ? (T)0 : (T)r[d];
+    v[idx] = mask[d] ? (T)0 : (T)r[d];
   }
-  for (int idx = tid; idx < bs2; idx += AP_NT) L.SL[0][idx] = base[idx];
-  __syncthreads();
+  if (loader) wait_vmcnt(younger);      // record of step 0 is in its slot
+  l1_barrier();
 
-  T pf[L1_PF];
-  int cur = 0, bcur = 0;
-  // forward sweep: step k uses block k; prefetch block k+1 (or, in the last
-  // step, block nb-2 for the backward sweep)
-  for (int k = 0; k < nb; ++k) {
-    const int knext = (k + 1 < nb) ? k + 1 : nb - 2;
-    const bool has_next = knext >= 0;
-    if (has_next) {
-      const T* src = base + (long long)knext * bs2;
+  // Row kp, finished at the previous step (parity pp), at entry col: the
+  // sum of the group partial sums (forward steps produce the row, backward
+  // steps subtract it from y_kp).  fin_load issues the LDS reads, fin_value
+  // combines them, so that callers can issue all reads before the first use
+  // (the compiler otherwise waits for each read in turn).
+  struct Fin {
+    T p[L1_NS];
+    T y;
+  };
+  auto fin_load = [&](int kp, int pp, int col) -> Fin {
+    Fin r;
+    const T* pr = P + pp * (L1_NS * MAXBS) + col;
 #pragma unroll
-      for (int q = 0; q < L1_PF; ++q) {
-        const int idx = tid + q * AP_NT;
-        if (idx < bs2) pf[q] = src[idx];
-      }
-    }
+    for (int q = 0; q < L1_NS; ++q) r.p[q] = pr[q * MAXBS];
+    r.y = v[kp * bs + col];
+    return r;
+  };
+  auto fin_value = [&](const Fin& r, bool pfwd) -> T {
+    T acc = r.p[0];
+#pragma unroll
+    for (int q = 1; q < L1_NS; ++q) acc += r.p[q];
+    return pfwd ? acc : r.y - acc;
+  };
+
+  for (int c = 0; c < nsteps; ++c) {
+    const bool fwd = c < nb;
+    const int k = l1_block_of_step(c, nb);
+    const int cur = c % R;
+    const int prev = (c + R - 1) % R;
+    const int pp = (c + 1) & 1;               // parity of step c-1
+    const bool pfwd = (c - 1) < nb;
+    const int kp = fwd ? k - 1 : k + 1;       // row finished at step c-1
+    // phase 1: w = right-hand side of the step
     if (tid < bs) {
-      T w = L.v[k * bs + tid];
-      if (k > 0) {
-        const int ia = tid >> 1;
-        const T* bc = L.Bc[bcur ^ 1] + tid * 6;
+      T wv;
+      if (c == 0) {
+        wv = v[tid];
+      } else {
+        // forward: F(k) (couplings of row k with row k-1, this step's
+        // record), zero towards nodes outside the row, so a clamped index
+        // contributes nothing; backward: F(k+1) (couplings of row k+1 with
+        // row k, in the previous step's slot) read transposed, entries
+        // outside the row masked
+        const T* F = fwd ? reinterpret_cast<const T*>(lds + cur * ring.slot) + bs2 + tid * 6
+                         : reinterpret_cast<const T*>(lds + prev * ring.slot) + bs2;
+        T f[6];
+        Fin y[6];
+        bool ok[6];
 #pragma unroll
         for (int t = 0; t < 6; ++t) {
-          const int col = 2 * (ia + t / 2 - 1) + (t & 1);
-          if (col >= 0 && col < bs) w -= bc[t] * L.v[(k - 1) * bs + col];
+          const int di = t / 2 - 1, cc = t & 1;
+          const int a = 2 * (ia + di) + cc;
+          ok[t] = a >= 0 && a < bs;
+          const int ac = min(max(a, 0), bs - 1);
+          f[t] = fwd ? F[t] : F[ac * 6 + (1 - di) * 2 + ca];
+          y[t] = fin_load(kp, pp, ac);
         }
-      }
-      L.tmp[tid] = w;
-    }
-    __syncthreads();
-    if (tid < bs) {
-      const T* S = L.SL[cur];
-      T acc = 0;
-      for (int j = 0; j < bs; ++j) acc += S[j * bs + tid] * L.tmp[j];
-      L.v[k * bs + tid] = acc;
-    } else {
-      // couplings for the next step: row k+1 with row k (forward), or, after
-      // the last forward step, row nb-2 with row nb-1 (first backward step)
-      if (k + 1 < nb)
-        l1_row_couplings<T>(g, s, L, k + 1, -1, L.Bc[bcur], tid - bs, AP_NT - bs);
-      else if (nb >= 2)
-        l1_row_couplings<T>(g, s, L, nb - 2, +1, L.Bc[bcur], tid - bs, AP_NT - bs);
-    }
-    if (has_next) {
+        const T rk = v[k * bs + tid];
+        __builtin_amdgcn_sched_barrier(0);
+        T acc = 0;
 #pragma unroll
-      for (int q = 0; q < L1_PF; ++q) {
-        const int idx = tid + q * AP_NT;
-        if (idx < bs2) L.SL[cur ^ 1][idx] = pf[q];
+        for (int t = 0; t < 6; ++t) acc += (ok[t] ? f[t] : (T)0) * fin_value(y[t], pfwd);
+        wv = fwd ? rk - acc : acc;
       }
+      w[tid] = wv;
     }
-    __syncthreads();
-    cur ^= 1;
-    bcur ^= 1;
+    l1_barrier();
+    // phase 2: retire row kp into v (phase 1 may read y_kp there, so not
+    // before the barrier); partial block GEMV; loaders fetch the record of
+    // step c+R-1 into the slot freed by step c-1 and wait for the record of
+    // step c+1
+    if (gemv) {
+      if (c > 0 && tid < bs) v[kp * bs + tid] = fin_value(fin_load(kp, pp, tid), pfwd);
+      const T* S = reinterpret_cast<const T*>(lds + cur * ring.slot) + j0 * bs;
+      P[(c & 1) * (L1_NS * MAXBS) + gq * MAXBS + gi] =
+          lds_gemv_group<T, L1_GMAX>(S, bs, gi, w + j0, jn);
+    } else if (loader) {
+      const int cn = c + R - 1;
+      const int st = cn < nsteps ? cn : nsteps - 1;
+      l1_dma<T>(base, ring.rec, l1_block_of_step(st, nb), lds + prev * ring.slot,
+                ring.nch, lw, lane);
+      wait_vmcnt(younger);
+    }
+    l1_barrier();
   }
-  // backward sweep: step k uses block k and couplings of row k with k+1
-  for (int k = nb - 2; k >= 0; --k) {
-    const int knext = k - 1;
-    if (knext >= 0) {
-      const T* src = base + (long long)knext * bs2;
-#pragma unroll
-      for (int q = 0; q < L1_PF; ++q) {
-        const int idx = tid + q * AP_NT;
-        if (idx < bs2) pf[q] = src[idx];
-      }
-    }
+  // retire the row of the last step
+  {
+    const int c = nsteps;
+    const int kl = l1_block_of_step(c - 1, nb);
     if (tid < bs) {
-      const int ib = tid >> 1;
-      const T* bc = L.Bc[bcur ^ 1] + tid * 6;
-      T w = 0;
-#pragma unroll
-      for (int t = 0; t < 6; ++t) {
-        const int col = 2 * (ib + t / 2 - 1) + (t & 1);
-        if (col >= 0 && col < bs) w += bc[t] * L.v[(k + 1) * bs + col];
-      }
-      L.tmp[tid] = w;
+      v[kl * bs + tid] = fin_value(fin_load(kl, (c + 1) & 1, tid), (c - 1) < nb);
     }
-    __syncthreads();
-    if (tid < bs) {
-      const T* S = L.SL[cur];
-      T acc = 0;
-      for (int j = 0; j < bs; ++j) acc += S[j * bs + tid] * L.tmp[j];
-      L.v[k * bs + tid] -= acc;
-    } else if (k >= 1) {
-      // couplings for the next backward step: row k-1 with row k
-      l1_row_couplings<T>(g, s, L, k - 1, +1, L.Bc[bcur], tid - bs, AP_NT - bs);
-    }
-    if (knext >= 0) {
-#pragma unroll
-      for (int q = 0; q < L1_PF; ++q) {
-        const int idx = tid + q * AP_NT;
-        if (idx < bs2) L.SL[cur ^ 1][idx] = pf[q];
-      }
-    }
-    __syncthreads();
-    cur ^= 1;
-    bcur ^= 1;
   }
+  l1_barrier();
   double* o = lsol + s.voff;
-  for (int idx = tid; idx < nb * bs; idx += AP_NT) o[idx] = (double)L.v[idx];
+  for (int idx = tid; idx < nb * bs; idx += AP_NT) o[idx] = (double)v[idx];
 }
 
-constexpr size_t L1_LDS_BYTES = sizeof(L1Lds<double>);
-
-// use64[i] != 0 (or use64 == null) selects the FP64 inverse blocks of
-// system i, else its FP32 copy (applied and accumulated in FP32).
+// use64[i] != 0 (or use64 == null) selects the FP64 records of system i,
+// else its FP32 copy (applied and accumulated in FP32).  With sc given,
+// every workgroup first runs the CG convergence test on the update
+// kernel's partials (check = 1) or reads the done word (check = 0).
 __global__ void __launch_bounds__(AP_NT)
 k_level1(Geom g, const SysDesc* __restrict__ systems,
-         const double* __restrict__ E, const uint8_t* __restrict__ mask,
-         const double* __restrict__ Kel, const double* __restrict__ S64,
+         const uint8_t* __restrict__ mask, const double* __restrict__ S64,
          const float* __restrict__ S32, const uint8_t* __restrict__ use64,
          const double* __restrict__ r, double* __restrict__ lsol,
-         const CGScalars* __restrict__ sc) {
-  __shared__ __align__(16) unsigned char lds[L1_LDS_BYTES];
-  if (sc != nullptr && sc->done) return;
+         CGScalars* __restrict__ sc, const double* __restrict__ part_upd,
+         int nb_upd, int check) {
+  __shared__ __align__(1024) unsigned char lds[L1_LDS];
+  __shared__ double red[AP_NT / 64 + 1];
+  __shared__ int shi;
+  if (sc != nullptr) {
+    if (check) {
+      if (cg_check_done<AP_NT>(sc, part_upd, nb_upd, red, &shi)) return;
+    } else if (block_read_done(sc, &shi)) {
+      return;
+    }
+  }
   const SysDesc s = systems[blockIdx.x];
   if (S32 == nullptr || use64 == nullptr || use64[blockIdx.x])
-    level1_body<double>(g, s, E, mask, Kel, S64, r, lsol, lds);
+    level1_body<double>(g, s, mask, S64, r, lsol, lds);
   else
-    level1_body<float>(g, s, E, mask, Kel, S32, r, lsol, lds);
+    level1_body<float>(g, s, mask, S32, r, lsol, lds);
 }
 
 // ---------------------------------------------------------------------
@@ -441,6 +595,22 @@ struct EigParams {
   double lim;        // select lambda < lim (= tau / H^2)
   double tol;        // relative convergence of the Ritz values
 };
+
+// sum_b S[b*ld + i] * w[b*MAXM] for b < n (4 independent accumulators)
+__device__ __forceinline__ double eig_dot(const double* S, int ld, int i,
+                                          const double* w, int n) {
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  int b = 0;
+#pragma unroll 2
+  for (; b + 4 <= n; b += 4) {
+    a0 += S[(b + 0) * ld + i] * w[(b + 0) * MAXM];
+    a1 += S[(b + 1) * ld + i] * w[(b + 1) * MAXM];
+    a2 += S[(b + 2) * ld + i] * w[(b + 2) * MAXM];
+    a3 += S[(b + 3) * ld + i] * w[(b + 3) * MAXM];
+  }
+  for (; b < n; ++b) a0 += S[b * ld + i] * w[b * MAXM];
+  return (a0 + a1) + (a2 + a3);
+}
 
 __device__ __forceinline__ double hash_unit(unsigned long long a) {
   // splitmix64 finaliser -> uniform in [-1, 1)
@@ -762,8 +932,7 @@ k_heat_eigen(Geom g, const SysDesc* __restrict__ systems,
       __syncthreads();
       for (int idx = tid; idx < bs * m; idx += EG_NT) {
         const int i = idx % bs, j = idx / bs;
-        double acc = 0.0;
-        for (int b = 0; b < bs; ++b) acc += SkL[b * bs + i] * Wl[b * MAXM + j];
+        const double acc = eig_dot(SkL, bs, i, Wl + j, bs);
         Tc[i * MAXM + j] = acc;
         Y[(long long)j * n + k * bs + i] = acc;
       }
@@ -798,8 +967,7 @@ k_heat_eigen(Geom g, const SysDesc* __restrict__ systems,
       __syncthreads();
       for (int idx = tid; idx < bs * m; idx += EG_NT) {
         const int i = idx % bs, j = idx / bs;
-        double acc = 0.0;
-        for (int b = 0; b < bs; ++b) acc += SkL[b * bs + i] * Wl[b * MAXM + j];
+        const double acc = eig_dot(SkL, bs, i, Wl + j, bs);
         const double val = Y[(long long)j * n + k * bs + i] - acc;
         Tc[i * MAXM + j] = val;
         Y[(long long)j * n + k * bs + i] = val;
@@ -907,12 +1075,16 @@ void launch_factor_heat(const Geom& g, const SysDesc* sys, int nsys,
 }
 
 void launch_level1(const Geom& g, const SysDesc* sys, int nsys,
-                   const double* E, const uint8_t* mask, const double* Ke,
-                   const double* S64, const float* S32, const uint8_t* use64,
-                   const double* r, double* lsol, const CGScalars* sc,
+                   const uint8_t* mask, const double* S64, const float* S32,
+                   const uint8_t* use64, const double* r, double* lsol,
+                   CGScalars* sc, const double* part_upd, int nb_upd, int check,
                    hipStream_t s) {
-  hipLaunchKernelGGL(k_level1, dim3(nsys), dim3(AP_NT), 0, s, g, sys, E, mask,
-                     Ke, S64, S32, use64, r, lsol, sc);
+  hipLaunchKernelGGL(k_level1, dim3(nsys), dim3(AP_NT), 0, s, g, sys, mask, S64,
+                     S32, use64, r, lsol, sc, part_upd, nb_upd, check);
+}
+
+bool level1_fits(int bs, int nb, bool fp32) {
+  return l1_fits<double>(bs, nb) && (!fp32 || l1_fits<float>(bs, nb));
 }
 
 void launch_heat_eigen(const Geom& g, const SysDesc* sys, int nsys,

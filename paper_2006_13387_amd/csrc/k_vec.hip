@@ -33,12 +33,16 @@ k_simp(const double* __restrict__ rho, double* __restrict__ E, int n,
 }
 
 // MODE MV_APPLY : y = K x with x treated as 0 at clamped DOFs.
-// MODE MV_CG    : p_new = z + beta p_old (beta in sc), q = K p_new, sum
-//                 p_new.q; the last workgroup forms alpha = (r.z)/(p.q).
+// MODE MV_CG    : p_new = z + beta p_old, q = K p_new, partial sums of
+//                 p_new.q.  beta comes from the previous combine kernel's
+//                 partials of r.z (and z.q), summed here by every
+//                 workgroup in the same order: Fletcher-Reeves
+//                 (r.z)_new/(r.z)_old, or, flexible, Polak-Ribiere
+//                 -alpha (z.q)/(r.z)_old.  Workgroup 0 records beta.
 //                 p_old and p_new are different buffers: neighbouring tiles
 //                 read p_old in their halos while this tile writes p_new.
-// MODE MV_RESID : r = f - K x (x is already 0 at clamped DOFs);
-//                 sums r.r, f.f and f.x over free DOFs.
+// MODE MV_RESID : r = f - K x (x is already 0 at clamped DOFs); partial
+//                 sums of r.r, f.f and f.x over free DOFs.
 template <int MODE>
 __global__ void __launch_bounds__(MV_NT)
 k_matvec(Geom g, const double* __restrict__ Ke, const double* __restrict__ E,
@@ -49,21 +53,42 @@ k_matvec(Geom g, const double* __restrict__ Ke, const double* __restrict__ E,
          double* __restrict__ yout,          // APPLY: y, CG: q, RESID: r
          const double* __restrict__ f,       // RESID: f
          CGScalars* __restrict__ sc, double* __restrict__ part,
-         unsigned int* __restrict__ counter, int resid_slot) {
+         const double* __restrict__ part_comb, int nb_comb,
+         double* __restrict__ beta_hist) {
   __shared__ double2 xs[(MV_TY + 2) * (MV_TX + 2)];
   __shared__ double es[(MV_TY + 1) * (MV_TX + 1)];
   __shared__ double ks[64];
   __shared__ double red[MV_NT / 64 + 1];
-  __shared__ unsigned int ticket;
+  __shared__ int shi;
+  __shared__ double sh_beta;
 
-  if (MODE == MV_CG) {
-    if (sc->done) return;
-  }
   const int tid = threadIdx.x;
+  double beta = 0.0;
+  if (MODE == MV_CG) {
+    if (block_read_done(sc, &shi)) return;
+    const int it = sc->iter;                 // not written by this kernel
+    if (it > 0) {
+      const double rz = reduce_partials<MV_NT>(part_comb, nb_comb, 1, red);
+      const double zq = sc->flexible ? reduce_partials<MV_NT>(part_comb + nb_comb, nb_comb, 1, red) : 0.0;
+      if (tid == 0) {
+        const double b = sc->flexible ? (-sc->alpha * zq / sc->rz) : (rz / sc->rz);
+        sh_beta = b;
+        if (blockIdx.x == 0 && blockIdx.y == 0) {
+          sc->beta = b;
+          if (it <= sc->maxit) beta_hist[it - 1] = b;
+          if (!finite(b)) {
+            sc->status = -5;
+            __hip_atomic_store(&sc->done, (int)DONE_BREAKDOWN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+        }
+      }
+      __syncthreads();
+      beta = sh_beta;
+      if (!finite(beta)) return;
+    }
+  }
   const int bx0 = blockIdx.x * MV_TX - 1;   // node x of xs column 0
   const int by0 = blockIdx.y * MV_TY - 1;
-  double beta = 0.0;
-  if (MODE == MV_CG) beta = sc->beta;
   if (tid < 64) ks[tid] = Ke[tid];
 
   for (int t = tid; t < (MV_TY + 2) * (MV_TX + 2); t += MV_NT) {
@@ -156,50 +181,65 @@ k_matvec(Geom g, const double* __restrict__ Ke, const double* __restrict__ E,
       part[2 * nb + bid] = s2;
     }
   }
-  if (!last_block(counter, nb, &ticket)) return;
-  if (MODE == MV_CG) {
-    const double pq = reduce_partials<MV_NT>(part, nb, 1, red);
-    if (tid == 0) {
-      sc->pq = pq;
-      if (!(pq > 0.0) || !finite(pq) || !finite(sc->rz)) {
-        sc->done = DONE_BREAKDOWN;
-        sc->status = -5;
-        sc->alpha = 0.0;
-      } else {
-        sc->alpha = sc->rz / pq;
-      }
-      *counter = 0u;
-    }
-  } else {
-    const double rr = reduce_partials<MV_NT>(part, nb, 1, red);
-    const double ff = reduce_partials<MV_NT>(part + nb, nb, 1, red);
-    const double fx = reduce_partials<MV_NT>(part + 2 * nb, nb, 1, red);
-    if (tid == 0) {
-      if (resid_slot == 0) {     // start of a (re)start: r0 and ||f||
-        sc->rr = rr;
-        sc->rr0 = rr;
-        sc->ff = ff;
-      } else {                   // true residual at exit
-        sc->rr0 = rr;
-        sc->ff = ff;
-        sc->fx = fx;
-      }
-      *counter = 0u;
+}
+
+// One workgroup: sum the residual kernel's partials (r.r, f.f, f.x).
+// slot 0 (start of a CG segment): rr, rr0 and ff; slot 1 (true residual at
+// exit): rr0 = true r.r, ff and fx.
+__global__ void __launch_bounds__(256)
+k_resid_finish(CGScalars* __restrict__ sc, const double* __restrict__ part,
+               int nb, int slot) {
+  __shared__ double red[256 / 64 + 1];
+  const double rr = reduce_partials<256>(part, nb, 1, red);
+  const double ff = reduce_partials<256>(part + nb, nb, 1, red);
+  const double fx = reduce_partials<256>(part + 2 * nb, nb, 1, red);
+  if (threadIdx.x == 0) {
+    if (slot == 0) {
+      sc->rr = rr;
+      sc->rr0 = rr;
+      sc->ff = ff;
+    } else {
+      sc->rr0 = rr;
+      sc->ff = ff;
+      sc->fx = fx;
     }
   }
 }
 
-// x += alpha p ; r -= alpha q ; sum r.r ; the last workgroup advances the
-// iteration counter, records alpha and tests ||r|| <= tol ||f||.
+// x += alpha p ; r -= alpha q ; partial sums of r.r.  alpha = (r.z)/(p.q)
+// from the partials of the combine and stiffness kernels, summed by every
+// workgroup in the same order; workgroup 0 records alpha and r.z.
 __global__ void __launch_bounds__(256)
 k_update(long long n2, double* __restrict__ x, double* __restrict__ r,
          const double* __restrict__ p, const double* __restrict__ q,
          CGScalars* __restrict__ sc, double* __restrict__ alpha_hist,
-         double* __restrict__ part, unsigned int* __restrict__ counter) {
+         double* __restrict__ part, const double* __restrict__ part_mv,
+         int nb_mv, const double* __restrict__ part_comb, int nb_comb) {
   __shared__ double red[256 / 64 + 1];
-  __shared__ unsigned int ticket;
-  if (sc->done) return;
-  const double alpha = sc->alpha;
+  __shared__ int shi;
+  __shared__ double sh_alpha;
+  if (block_read_done(sc, &shi)) return;
+  const double pq = reduce_partials<256>(part_mv, nb_mv, 1, red);
+  const double rz = reduce_partials<256>(part_comb, nb_comb, 1, red);
+  if (threadIdx.x == 0) {
+    const bool bad = !(pq > 0.0) || !finite(pq) || !finite(rz);
+    const double alpha = bad ? 0.0 : rz / pq;
+    sh_alpha = bad ? __builtin_nan("") : alpha;
+    if (blockIdx.x == 0) {
+      const int it = sc->iter;
+      sc->pq = pq;
+      sc->alpha = alpha;
+      sc->rz = rz;
+      if (it < sc->maxit) alpha_hist[it] = alpha;
+      if (bad) {
+        sc->status = -5;
+        __hip_atomic_store(&sc->done, (int)DONE_BREAKDOWN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+  __syncthreads();
+  const double alpha = sh_alpha;
+  if (!finite(alpha)) return;
   double acc = 0.0;
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   if (i < n2) {
@@ -217,23 +257,6 @@ k_update(long long n2, double* __restrict__ x, double* __restrict__ r,
   }
   const double s = block_sum<256>(acc, red);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
-  if (!last_block(counter, gridDim.x, &ticket)) return;
-  const double rrs = reduce_partials<256>(part, gridDim.x, 1, red);
-  if (threadIdx.x == 0) {
-    sc->rr = rrs;
-    const int it = sc->iter;
-    if (it < sc->maxit) alpha_hist[it] = alpha;
-    sc->iter = it + 1;
-    if (!finite(rrs)) {
-      sc->done = DONE_BREAKDOWN;
-      sc->status = -5;
-    } else if (rrs <= sc->tol2 * sc->ff) {
-      sc->done = DONE_CONVERGED;
-    } else if (it + 1 >= sc->maxit) {
-      sc->done = DONE_MAXIT;
-    }
-    *counter = 0u;
-  }
 }
 
 __global__ void __launch_bounds__(256)
@@ -290,34 +313,40 @@ void launch_apply_K(const Geom& g, const double* Ke, const double* E,
   hipLaunchKernelGGL(k_matvec<MV_APPLY>, mv_grid(g), dim3(MV_NT), 0, s, g, Ke,
                      E, mask, x, (const double*)nullptr, (double*)nullptr, y,
                      (const double*)nullptr, (CGScalars*)nullptr,
-                     (double*)nullptr, (unsigned int*)nullptr, 0);
+                     (double*)nullptr, (const double*)nullptr, 0,
+                     (double*)nullptr);
 }
 
 void launch_cg_matvec(const Geom& g, const double* Ke, const double* E,
                       const uint8_t* mask, const double* z, const double* p_old,
-                      double* p_new, double* q, CGScalars* sc, double* part,
-                      unsigned int* counter, hipStream_t s) {
+                      double* p_new, double* q, CGScalars* sc, double* part_mv,
+                      const double* part_comb, int nb_comb, double* beta_hist,
+                      hipStream_t s) {
   hipLaunchKernelGGL(k_matvec<MV_CG>, mv_grid(g), dim3(MV_NT), 0, s, g, Ke, E,
-                     mask, z, p_old, p_new, q, (const double*)nullptr, sc, part,
-                     counter, 0);
+                     mask, z, p_old, p_new, q, (const double*)nullptr, sc,
+                     part_mv, part_comb, nb_comb, beta_hist);
 }
 
 void launch_residual(const Geom& g, const double* Ke, const double* E,
                      const uint8_t* mask, const double* x, const double* f,
-                     double* r, CGScalars* sc, double* part,
-                     unsigned int* counter, int slot, hipStream_t s) {
+                     double* r, CGScalars* sc, double* part, int slot,
+                     hipStream_t s) {
   hipLaunchKernelGGL(k_matvec<MV_RESID>, mv_grid(g), dim3(MV_NT), 0, s, g, Ke,
                      E, mask, x, (const double*)nullptr, (double*)nullptr, r, f,
-                     sc, part, counter, slot);
+                     sc, part, (const double*)nullptr, 0, (double*)nullptr);
+  hipLaunchKernelGGL(k_resid_finish, dim3(1), dim3(256), 0, s, sc, part,
+                     matvec_blocks(g), slot);
 }
 
 int update_blocks(long long n) { return (int)((n / 2 + 255) / 256); }
 
 void launch_update(long long n, double* x, double* r, const double* p,
                    const double* q, CGScalars* sc, double* alpha_hist,
-                   double* part, unsigned int* counter, hipStream_t s) {
+                   double* part_upd, const double* part_mv, int nb_mv,
+                   const double* part_comb, int nb_comb, hipStream_t s) {
   hipLaunchKernelGGL(k_update, dim3(update_blocks(n)), dim3(256), 0, s, n / 2,
-                     x, r, p, q, sc, alpha_hist, part, counter);
+                     x, r, p, q, sc, alpha_hist, part_upd, part_mv, nb_mv,
+                     part_comb, nb_comb);
 }
 
 void launch_dot(long long n, const double* x, const double* y, double* part,

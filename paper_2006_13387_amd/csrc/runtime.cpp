@@ -23,13 +23,15 @@ void launch_apply_K(const Geom&, const double*, const double*, const uint8_t*,
                     const double*, double*, hipStream_t);
 void launch_cg_matvec(const Geom&, const double*, const double*,
                       const uint8_t*, const double*, const double*, double*,
-                      double*, CGScalars*, double*, unsigned int*, hipStream_t);
+                      double*, CGScalars*, double*, const double*, int, double*,
+                      hipStream_t);
 void launch_residual(const Geom&, const double*, const double*, const uint8_t*,
                      const double*, const double*, double*, CGScalars*, double*,
-                     unsigned int*, int, hipStream_t);
+                     int, hipStream_t);
 int update_blocks(long long);
 void launch_update(long long, double*, double*, const double*, const double*,
-                   CGScalars*, double*, double*, unsigned int*, hipStream_t);
+                   CGScalars*, double*, double*, const double*, int,
+                   const double*, int, hipStream_t);
 void launch_dot(long long, const double*, const double*, double*,
                 unsigned int*, double*, hipStream_t);
 void launch_mask(long long, const uint8_t*, double*, hipStream_t);
@@ -40,10 +42,10 @@ void launch_factor_elastic(const Geom&, const SysDesc*, int, const double*,
 void launch_factor_heat(const Geom&, const SysDesc*, int, const double*,
                         const uint8_t*, const double*, double*, int*,
                         hipStream_t);
-void launch_level1(const Geom&, const SysDesc*, int, const double*,
-                   const uint8_t*, const double*, const double*, const float*,
-                   const uint8_t*, const double*, double*, const CGScalars*,
-                   hipStream_t);
+void launch_level1(const Geom&, const SysDesc*, int, const uint8_t*,
+                   const double*, const float*, const uint8_t*, const double*,
+                   double*, CGScalars*, const double*, int, int, hipStream_t);
+bool level1_fits(int bs, int nb, bool fp32);
 void launch_heat_eigen(const Geom&, const SysDesc*, int, const double*,
                        const uint8_t*, const double*, const double*,
                        const double*, const double*, double*, double*, double*,
@@ -60,14 +62,15 @@ void launch_coarse_k0(const Geom&, const CoarseNode*, const int2*, int,
 void launch_k0_pinv(double*, int, int, double*, double*, double*, double*,
                     double, int*, hipStream_t);
 void launch_restrict(const Geom&, const CoarseNode*, int, const uint8_t*,
-                     const double*, const double*, double*, double,
-                     const CGScalars*, hipStream_t);
-void launch_coarse_gemv(const double*, int, int, const double*, double*,
+                     const double*, const double*, double*, int, double,
+                     CGScalars*, const double*, int, int, hipStream_t);
+int restrict_bands();
+void launch_coarse_gemv(const double*, int, int, const double*, int, double*,
                         const CGScalars*, hipStream_t);
 int combine_blocks(const Geom&);
 void launch_combine(int, const Geom&, const CombineArgs&, const uint8_t*,
                     const double*, const double*, double*, CGScalars*, double*,
-                    double*, unsigned int*, hipStream_t);
+                    hipStream_t);
 void launch_export_basis(const Geom&, const CoarseNode*, const int*, int,
                          const uint8_t*, const double*, double*, double,
                          hipStream_t);
@@ -156,7 +159,7 @@ struct msp_handle {
   CoarseNode* d_cn = nullptr;
   int* d_col_node = nullptr;
   int2* d_pairs = nullptr;
-  size_t col_cap = 0, pair_cap = 0;
+  size_t col_cap = 0, pair_cap = 0, c_cap = 0;
   double* d_W = nullptr;
   size_t w_cap = 0;
   double* d_K0 = nullptr;
@@ -169,8 +172,11 @@ struct msp_handle {
   CGScalars* d_sc = nullptr;
   double *d_ahist = nullptr, *d_bhist = nullptr;
   int hist_cap = 0;
-  double* d_part = nullptr;
-  unsigned int* d_cnt = nullptr;   // 8 counters
+  double* d_part = nullptr;        // partial sums, see part_* below
+  double *part_mv = nullptr, *part_upd = nullptr, *part_comb = nullptr,
+         *part_res = nullptr;
+  int nb_mv = 0, nb_upd = 0, nb_comb = 0;
+  unsigned int* d_cnt = nullptr;   // counters of msp_vec_dot
   int* d_err = nullptr;
   // pinned host
   CGScalars* h_sc = nullptr;
@@ -247,7 +253,7 @@ msp_status build_geometry(msp_handle* h) {
     s.foff = foff;
     s.voff = voff;
     const long long bs = 2LL * s.nxb;
-    foff += (long long)s.nyb * bs * bs;
+    foff += (long long)s.nyb * (bs * bs + 6 * bs);   // records: S^-1 | F
     voff += (long long)s.nyb * bs;
     h->subs.push_back(s);
     return (int)h->subs.size() - 1;
@@ -285,8 +291,8 @@ msp_status build_geometry(msp_handle* h) {
       return fail(h, MSP_E_INVALID, "subdomain row exceeds 72 DOFs (reduce sub_nel + 2*overlap)");
     if ((long long)s.nyb * 2 * s.nxb > MAXBS * 40)
       return fail(h, MSP_E_INVALID, "subdomain exceeds 2880 DOFs");
-    if ((long long)(s.nxb + 1) * (s.nyb + 1) > 3072)
-      return fail(h, MSP_E_INVALID, "subdomain element box exceeds 3072 elements");
+    if (!level1_fits(2 * s.nxb, s.nyb, h->desc.precision == 1))
+      return fail(h, MSP_E_INVALID, "subdomain too large for the first-level kernel's LDS ring");
     if (s.nxb <= 0 || s.nyb <= 0)
       return fail(h, MSP_E_INVALID, "empty subdomain");
   }
@@ -508,8 +514,10 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
 
   const long long nd = h->n_dofs, nn = h->n_nodes;
   const int m = std::min(d->eig_kmax + kEigExtra, MAXM);
-  const int nparts = std::max(std::max(matvec_blocks(g), update_blocks(nd)),
-                              std::max(combine_blocks(g), 1024)) * 3 + 16;
+  h->nb_mv = matvec_blocks(g);
+  h->nb_upd = update_blocks(nd);
+  h->nb_comb = combine_blocks(g);
+  const int nparts = h->nb_mv + h->nb_upd + 2 * h->nb_comb + 3 * h->nb_mv + 64;
   bool ok = true;
   auto A = [&](hipError_t e) { if (e != hipSuccess) ok = false; };
   A(dalloc(&h->d_elem, 64 + 16 * 3));
@@ -519,8 +527,10 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
   A(dalloc(&h->d_subs, h->subs.size()));
   A(dalloc(&h->d_omegas, h->omegas.size()));
   A(dalloc(&h->d_sub_grid, h->sub_grid.size()));
-  A(dalloc(&h->d_S64, h->l1_entries));
-  if (h->fp32) A(dalloc(&h->d_S32, h->l1_entries));
+  // slack: the first-level kernel copies records in whole 1 KiB chunks and
+  // reads less than 1 KiB past the last record
+  A(dalloc(&h->d_S64, h->l1_entries + 1024));
+  if (h->fp32) A(dalloc(&h->d_S32, h->l1_entries + 1024));
   A(dalloc(&h->d_metric, h->subs.size()));
   A(dalloc(&h->d_use64, h->subs.size()));
   A(dalloc(&h->d_lsol, h->l1_vec));
@@ -542,6 +552,12 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
   A(dalloc(&h->d_tmp, nd));
   A(dalloc(&h->d_sc, 1));
   A(dalloc(&h->d_part, nparts));
+  if (h->d_part) {
+    h->part_mv = h->d_part;
+    h->part_upd = h->part_mv + h->nb_mv;
+    h->part_comb = h->part_upd + h->nb_upd;
+    h->part_res = h->part_comb + 2 * h->nb_comb;
+  }
   A(dalloc(&h->d_cnt, 8));
   A(dalloc(&h->d_err, 4));
   A(dalloc(&h->d_dropped, 1));
@@ -599,14 +615,15 @@ extern "C" msp_status msp_set_densities(msp_handle* h, const double* rho,
 
 static msp_status ensure_coarse_buffers(msp_handle* h, size_t ncols,
                                         size_t npairs, size_t wsize, int ldk) {
-  if (ncols > h->col_cap) {
+  if (ncols > h->col_cap || (size_t)ldk > h->c_cap) {
     dfree(h->d_col_node);
     HIPCHK(h, dalloc(&h->d_col_node, ncols + 64));
     dfree(h->d_c);
     dfree(h->d_c0);
-    HIPCHK(h, dalloc(&h->d_c, ncols + 64));
-    HIPCHK(h, dalloc(&h->d_c0, ncols + 64));
+    HIPCHK(h, dalloc(&h->d_c, (size_t)restrict_bands() * ldk));
+    HIPCHK(h, dalloc(&h->d_c0, ldk));
     h->col_cap = ncols + 64;
+    h->c_cap = ldk;
   }
   if (npairs > h->pair_cap) {
     dfree(h->d_pairs);
@@ -717,6 +734,10 @@ extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
   }
   h->nc = col;
   h->ldk = std::max(64, ((col + 63) / 64) * 64);
+  if (h->ldk > 12288) {
+    h->setup_ok = false;
+    return fail(h, MSP_E_INVALID, "coarse dimension exceeds 12288 (reduce eig_kmax or refine the coarse grid)");
+  }
   std::vector<int2> pairs;
   for (size_t l = 0; l < h->cn_h.size(); ++l)
     for (size_t l2 = 0; l2 < h->cn_h.size(); ++l2) {
@@ -778,25 +799,26 @@ static void enqueue_prec(msp_handle* h, int mode, const double* r,
                          const double* q, double* z, bool l1, bool coarse,
                          bool use_sc, hipStream_t s) {
   const Geom& g = h->g;
-  const CGScalars* sc = use_sc ? h->d_sc : nullptr;
+  CGScalars* sc = use_sc ? h->d_sc : nullptr;
+  const int check = (mode == 1) ? 1 : 0;   // convergence test after update
   if (l1) {
     const int t = timer_begin(h, KT_LEVEL1, s);
-    launch_level1(g, h->d_subs, (int)h->subs.size(), h->d_E, h->d_mask,
-                  h->d_elem, h->d_S64, h->fp32 ? h->d_S32 : nullptr,
-                  h->fp32 ? h->d_use64 : nullptr, r, h->d_lsol, sc, s);
+    launch_level1(g, h->d_subs, (int)h->subs.size(), h->d_mask, h->d_S64,
+                  h->fp32 ? h->d_S32 : nullptr, h->fp32 ? h->d_use64 : nullptr,
+                  r, h->d_lsol, sc, h->part_upd, h->nb_upd, check, s);
     timer_end(h, KT_LEVEL1, t, s);
   }
   if (coarse && h->nc > 0) {
     const int t = timer_begin(h, KT_RESTRICT, s);
     launch_restrict(g, h->d_cn, (int)h->cn_h.size(), h->d_mask, h->d_psi, r,
-                    h->d_c, h->invH, sc, s);
+                    h->d_c, h->ldk, h->invH, sc, h->part_upd, h->nb_upd, check,
+                    s);
     timer_end(h, KT_RESTRICT, t, s);
-    launch_coarse_gemv(h->d_K0, h->ldk, h->nc, h->d_c, h->d_c0, sc, s);
+    launch_coarse_gemv(h->d_K0, h->ldk, h->nc, h->d_c, h->ldk, h->d_c0, sc, s);
   }
   const CombineArgs ca = combine_args(h, l1, coarse);
   const int t = timer_begin(h, KT_COMBINE, s);
-  launch_combine(mode, g, ca, h->d_mask, r, q, z, h->d_sc, h->d_bhist,
-                 h->d_part, h->d_cnt + 2, s);
+  launch_combine(mode, g, ca, h->d_mask, r, q, z, h->d_sc, h->part_comb, s);
   timer_end(h, KT_COMBINE, t, s);
 }
 
@@ -882,7 +904,7 @@ static msp_status solve_one(msp_handle* h, const double* f, double* u,
     HIPCHK(h, hipMemcpyAsync(h->d_sc, h->h_sc, sizeof(CGScalars), hipMemcpyHostToDevice, s));
     // r = f - K x ; ||f|| ; then z = M^{-1} r, p_old = 0
     launch_residual(g, h->d_elem, h->d_E, h->d_mask, h->d_x, f, h->d_r,
-                    h->d_sc, h->d_part, h->d_cnt + 0, 0, s);
+                    h->d_sc, h->part_res, 0, s);
     HIPCHK(h, hipMemsetAsync(h->d_p0, 0, nd * sizeof(double), s));
     enqueue_prec(h, 2, h->d_r, nullptr, h->d_z, true, true, true, s);
     HIPCHK(h, hipGetLastError());
@@ -903,10 +925,12 @@ static msp_status solve_one(msp_handle* h, const double* f, double* u,
           double* pnew = cur ? h->d_p0 : h->d_p1;
           const int tm = timer_begin(h, KT_MATVEC, s);
           launch_cg_matvec(g, h->d_elem, h->d_E, h->d_mask, h->d_z, pold, pnew,
-                           h->d_q, h->d_sc, h->d_part, h->d_cnt + 1, s);
+                           h->d_q, h->d_sc, h->part_mv, h->part_comb,
+                           h->nb_comb, h->d_bhist, s);
           timer_end(h, KT_MATVEC, tm, s);
           launch_update(nd, h->d_x, h->d_r, pnew, h->d_q, h->d_sc, h->d_ahist,
-                        h->d_part, h->d_cnt + 3, s);
+                        h->part_upd, h->part_mv, h->nb_mv, h->part_comb,
+                        h->nb_comb, s);
           enqueue_prec(h, 1, h->d_r, h->d_q, h->d_z, true, true, true, s);
           cur ^= 1;
         }
@@ -933,7 +957,7 @@ static msp_status solve_one(msp_handle* h, const double* f, double* u,
     }
     // true residual and compliance
     launch_residual(g, h->d_elem, h->d_E, h->d_mask, h->d_x, f, h->d_tmp,
-                    h->d_sc, h->d_part, h->d_cnt + 0, 1, s);
+                    h->d_sc, h->part_res, 1, s);
     HIPCHK(h, hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(CGScalars), hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
     relres_true = std::sqrt(h->h_sc->rr0 / h->h_sc->ff);
@@ -1082,7 +1106,9 @@ extern "C" msp_status msp_query(msp_handle* h, int64_t* q) {
   long long l1_bytes = 0;
   for (size_t i = 0; i < h->subs.size(); ++i) {
     const SysDesc& s = h->subs[i];
-    const long long ent = (long long)s.nyb * 4LL * s.nxb * s.nxb;
+    // one application reads the record of every row in the forward sweep
+    // and all but the last row's again in the backward sweep
+    const long long ent = (2LL * s.nyb - 1) * (4LL * s.nxb * s.nxb + 12LL * s.nxb);
     const bool f64 = !h->fp32 || (i < h->use64_h.size() ? h->use64_h[i] != 0 : true);
     l1_bytes += ent * (f64 ? 8 : 4);
   }
