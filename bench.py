@@ -28,6 +28,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 CONTRASTS = (1e-3, 1e-6, 1e-9)
+CPU_STRIDE = 2          # the CPU baseline samples every 2nd local problem
 HBM_PEAK_GBS = 8000.0
 
 
@@ -41,7 +42,117 @@ def parse():
                     help="seconds of oracle work in the CPU baseline sample")
     ap.add_argument("--quick", action="store_true",
                     help="one contrast, no FP64 leg (for profiler runs)")
+    ap.add_argument("--no-matvec-probe", action="store_true",
+                    help="skip the HBM-sized stiffness-product probe")
+    ap.add_argument("--kernel-probe", action="store_true",
+                    help="only launch the profiled kernels: first-level "
+                         "applies (Emin 1e-6, FP32 path), stiffness products "
+                         "on the probe mesh and a plain 1 GiB device copy "
+                         "(the byte-counter calibration); prints their sizes")
     return ap.parse_args()
+
+
+# Stiffness-product probe: a mesh well beyond the 256 MB last-level cache,
+# so the matvec streams from HBM.
+PROBE_NEL = (8192, 4096)
+
+
+def matvec_bytes(nel):
+    """Algorithmic HBM bytes of one stiffness product y = K x (2D Q1): x
+    read and y written (FP64, two DOFs a node), the element moduli read
+    (FP64) and the clamped-DOF mask read (one byte a DOF)."""
+    nn = (nel[0] + 1) * (nel[1] + 1)
+    n = 2 * nn
+    return 8 * 2 * n + 8 * nel[0] * nel[1] + n
+
+
+def matvec_probe(torch, launches=20):
+    """Average event-timed duration of the stiffness product on PROBE_NEL."""
+    import numpy as np
+    import inputs
+    import paper_2006_13387_amd as msp
+    desc = inputs.problem_desc(2, PROBE_NEL, sub_nel=32, overlap=2)
+    fixed = inputs.clamp_face_mask(desc, axis=0, side=0)
+    rng = np.random.default_rng(7)
+    s = msp.Solver(desc, fixed)
+    s.set_densities(torch.tensor(rng.random(PROBE_NEL[0] * PROBE_NEL[1]),
+                                 device="cuda"))
+    x = torch.randn(s.n, device="cuda", dtype=torch.float64)
+    for _ in range(3):
+        s.apply_K(x)
+    s.kernel_timing(enable=2)              # bit 1: stiffness product
+    for _ in range(launches):
+        s.apply_K(x)
+    c, t = s.kernel_timing(enable=0)["cg_matvec"]
+    s.close()
+    ms = t / max(c, 1)
+    b = matvec_bytes(PROBE_NEL)
+    gbs = b / (ms * 1e-3) / 1e9
+    return {"mesh": f"{PROBE_NEL[0]}x{PROBE_NEL[1]} Q1 ({s.n} DOFs)",
+            "bytes_per_launch": int(b), "avg_launch_ms": round(ms, 5),
+            "achieved_GBs": round(gbs, 1),
+            "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "launches": int(c)}
+
+
+COUNTERS = os.path.join(ROOT, "profiles", "level1_apply_hbm_counters.json")
+LEVEL1_SOURCES = ("paper_2006_13387_amd/csrc/k_local.hip",
+                  "paper_2006_13387_amd/csrc/dev.h",
+                  "paper_2006_13387_amd/csrc/common.h")
+
+
+def level1_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in LEVEL1_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def level1_traffic(launches_by_contrast):
+    """HBM bytes per first-level launch from the committed FETCH_SIZE /
+    WRITE_SIZE counters, weighted like the timed launches; None when the
+    kernel's sources changed since the counters were taken."""
+    try:
+        with open(COUNTERS) as fh:
+            c = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if c.get("source_sha256") != level1_source_hash():
+        return None
+    per = c["traffic_bytes_per_launch"]
+    tot = sum(n for n in launches_by_contrast.values())
+    if tot == 0 or any(k not in per for k in launches_by_contrast):
+        return None
+    return sum(n * per[k] for k, n in launches_by_contrast.items()) / tot
+
+
+def kernel_probe(torch):
+    """Launch only the kernels whose HBM counters are collected."""
+    import inputs
+    import paper_2006_13387_amd as msp
+    l1 = {}
+    for e in CONTRASTS:                     # 10 launches per contrast, in order
+        p = inputs.config(1, Emin=e)
+        s = msp.Solver(dict(p.desc, precision=1), p.fixed)
+        s.set_densities(torch.tensor(p.rho, device="cuda"))
+        s.setup()
+        r = torch.randn(s.n, device="cuda", dtype=torch.float64)
+        for _ in range(10):
+            s.apply_level1(r)
+        torch.cuda.synchronize()
+        l1[f"{e:g}"] = int(level1_bytes(s.query()))
+        s.close()
+    mv = matvec_probe(torch, launches=10)
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 8, device="cuda", dtype=torch.float64).fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"level1_bytes_per_launch": l1,
+                      "matvec_bytes_per_launch": mv["bytes_per_launch"],
+                      "copy_bytes_read": nbytes, "copy_bytes_written": nbytes}))
 
 
 def log(msg):
@@ -106,8 +217,8 @@ def cpu_baseline(budget_s, gpu_iters):
     scale it to seconds per solve (setup + PCG).
 
     Sample (the Emin = 1e-6 densities): assembly of K(rho); sparse
-    factorisation of every 8th local system (scaled by 8); the heat
-    eigenproblems of every 8th coarse neighbourhood, and the coarse columns
+    factorisation of every 2nd local system (scaled by 2); the heat
+    eigenproblems of every 2nd coarse neighbourhood, and the coarse columns
     chi psi / chi r they give (scaled to the GPU's coarse dimension) for
     K Phi, Phi^T K Phi and the restriction / prolongation; the coarse
     pseudo-inverse at the GPU's coarse dimension; one PCG iteration = K_FF x
@@ -139,12 +250,12 @@ def cpu_baseline(budget_s, gpu_iters):
     t_asm = T() - t0
     boxes = dd.subdomain_node_boxes(d, p.fixed)
     idx = dd.subdomain_free_indices(d, p.fixed, boxes)
-    sample = idx[::8]
+    sample = idx[::CPU_STRIDE]
     t0 = T()
     lus = [spla.splu(K_FF[i][:, i].tocsc()) for i in sample]
     t_fact = (T() - t0) * len(idx) / len(sample)
     nodes = dd.coarse_node_grid(d)
-    cs_sample = nodes[::8]
+    cs_sample = nodes[::CPU_STRIDE]
     H = dd.coarse_H(d)
     fmap = -np.ones(len(p.fixed), np.int64)
     fmap[free] = np.arange(len(free))
@@ -215,7 +326,7 @@ def cpu_baseline(budget_s, gpu_iters):
     return {"value": 1.0 / sec, "unit": "solves/s", "cores": int(blas_threads),
             "kind": "oracle",
             "sample": ("512x256 cantilever (Emin 1e-6 densities): assembly, "
-                       "1/8 of the local factorisations and of the heat "
+                       f"1/{CPU_STRIDE} of the local factorisations and of the heat "
                        "eigenproblems with their coarse columns (scaled), "
                        "the coarse pseudo-inverse at the GPU's coarse "
                        "dimension, one PCG iteration's parts times the "
@@ -237,6 +348,9 @@ def main():
     import inputs
     import paper_2006_13387_amd as msp
     msp.load_library()
+    if args.kernel_probe:
+        kernel_probe(torch)
+        return
     contrasts = CONTRASTS[1:2] if args.quick else CONTRASTS
     probs = [inputs.config(1, Emin=e) for e in contrasts]
     rho = torch.tensor(probs[0].rho, device="cuda")
@@ -280,6 +394,9 @@ def main():
     # its launches
     l1_tot_bytes = sum(c * level1_bytes(s.query()) for (c, _), s in zip(l1, mixed))
     l1_bytes = l1_tot_bytes / max(launches, 1)
+    traffic = level1_traffic({f"{e:g}": c for e, (c, _) in zip(contrasts, l1)})
+    if traffic is not None:
+        traffic = int(traffic)
     achieved = l1_bytes / (l1_ms * 1e-3) / 1e9
     lat_sorted = sorted(lat_mixed)
     pct = lambda a, x: a[min(len(a) - 1, int(round(x * (len(a) - 1))))]
@@ -315,7 +432,7 @@ def main():
                      "bound": "hbm", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None,
+                     "traffic": traffic,
                      "bytes_per_launch": int(l1_bytes),
                      "avg_launch_ms": round(l1_ms, 5),
                      "launches_timed": int(launches)},
@@ -329,6 +446,9 @@ def main():
             "latency_ms_p50": round(1e3 * statistics.median(lat_fp64), 3)}
         out["mixed_over_fp64"] = round(value / v64, 4)
         out["mixed_over_fp64_solve_only"] = round(so_mixed / so_fp64, 4)
+    if not args.no_matvec_probe:
+        log("[bench] matvec probe")
+        out["matvec_probe"] = matvec_probe(torch)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         gi = [(e, i["iters"], i["n_coarse"]) for e, i in zip(contrasts, inf_mixed)]

@@ -197,7 +197,8 @@ msp_status msp_query(msp_handle* h, int64_t* sizes12);
  * (0 stops timing, -1 leaves the state unchanged).
  * Before changing the state the call returns, for kernel k < n, the number
  * of timed launches and their summed duration in ms since the last reset:
- * k = 0 first-level apply, 1 CG stiffness product, 2 heat eigen setup,
+ * k = 0 first-level apply, 1 stiffness product (in the CG and in
+ * msp_apply_K), 2 heat eigen setup,
  * 3 combine (z = M^-1 r), 4 coarse restriction, 5 local factorisation.
  */
 msp_status msp_kernel_timing(msp_handle* h, int32_t enable,

@@ -12,11 +12,11 @@ Numbering used throughout (the same at the C boundary):
 * element ``(i, j[, k])`` has id ``i + nx*(j + ny*k)``.
 
 Densities follow the paper's setting of a design field bounded in [0, 1]
-with void = 0 and solid = 1 (Introduction, before eq. (1.3)).  The material
+with void = 0 and solid = 1 (Section 1, the SIMP interpolation law).  The material
 maps of the paper's experiments exist only as figures that are not available,
 so the fields here are stand-ins for their *structure*: stiff channels and
 inclusions that cross coarse-block boundaries at high contrast, with loads
-applied on solid material (Section 6, experiment description).
+applied on solid material (Section 5, description of the experiments).
 """
 from __future__ import annotations
 

@@ -347,7 +347,8 @@ __global__ void k_k0_unscale(double* __restrict__ K0, int ldk,
 // (coalesced psi reads); column sums are a wavefront butterfly and a
 // fixed-order sum over the waves, written per band to cpart[band][col].
 constexpr int RS_NT = 256;
-constexpr int RS_CH = 4;
+constexpr int RS_CH = 4;       // bands of neighbourhood rows per coarse node
+constexpr int RS_NPT = 8;      // band nodes per thread (band <= RS_NT*RS_NPT)
 constexpr int KMAXD = 24;
 
 __global__ void __launch_bounds__(RS_NT)
@@ -375,27 +376,41 @@ k_restrict(Geom g, const CoarseNode* __restrict__ cnodes,
   const int r0w = (band * cn.nyw) / RS_CH, r1w = ((band + 1) * cn.nyw) / RS_CH;
   const int lo = r0w * cn.nxw, hi = r1w * cn.nxw;
   const double* ps = psi + cn.psi_off;
-  double ax[KMAXD], ay[KMAXD], ar = 0.0;
+  // this thread's nodes of the band: masked chi*r in registers first, so
+  // that the loads of one mode (below) are independent of each other
+  int locs[RS_NPT];
+  double r0[RS_NPT], r1[RS_NPT];
+  double ar = 0.0;
 #pragma unroll
-  for (int j = 0; j < KMAXD; ++j) ax[j] = ay[j] = 0.0;
-  for (int loc = lo + threadIdx.x; loc < hi; loc += RS_NT) {
-    const int x = cn.x0 + loc % cn.nxw, y = cn.y0 + loc / cn.nxw;
+  for (int p = 0; p < RS_NPT; ++p) {
+    const int loc = lo + threadIdx.x + p * RS_NT;
+    const bool ok = loc < hi;
+    locs[p] = ok ? loc : lo;
+    const int x = cn.x0 + locs[p] % cn.nxw, y = cn.y0 + locs[p] / cn.nxw;
     const double chi = chi_at(g, cn.cx, cn.cy, x, y);
     const long long node = (long long)y * g.nnx + x;
     const double2 rv = reinterpret_cast<const double2*>(r)[node];
     const uchar2 m = reinterpret_cast<const uchar2*>(mask)[node];
-    const double r0 = m.x ? 0.0 : chi * rv.x, r1 = m.y ? 0.0 : chi * rv.y;
-#pragma unroll
-    for (int j = 0; j < KMAXD; ++j) {
-      if (j < nm) {
-        const double pv = ps[(long long)j * nw + loc];
-        ax[j] += pv * r0;
-        ay[j] += pv * r1;
-      }
-    }
+    r0[p] = (!ok || m.x) ? 0.0 : chi * rv.x;
+    r1[p] = (!ok || m.y) ? 0.0 : chi * rv.y;
     const double rx = (x - cn.cx * g.sx) * g.h * invH;
     const double ry = (y - cn.cy * g.sy) * g.h * invH;
-    ar += -ry * r0 + rx * r1;
+    ar += -ry * r0[p] + rx * r1[p];
+  }
+  double ax[KMAXD], ay[KMAXD];
+#pragma unroll
+  for (int j = 0; j < KMAXD; ++j) {
+    ax[j] = ay[j] = 0.0;
+    if (j < nm) {
+      double pv[RS_NPT];
+#pragma unroll
+      for (int p = 0; p < RS_NPT; ++p) pv[p] = ps[(long long)j * nw + locs[p]];
+#pragma unroll
+      for (int p = 0; p < RS_NPT; ++p) {
+        ax[j] += pv[p] * r0[p];
+        ay[j] += pv[p] * r1[p];
+      }
+    }
   }
   const int w = threadIdx.x >> 6;
 #pragma unroll
@@ -422,11 +437,13 @@ k_restrict(Geom g, const CoarseNode* __restrict__ cnodes,
   }
 }
 
-// c0 = K0p c with c = sum over bands of cpart: each workgroup (16 waves)
-// sums the bands into LDS once, then every wave forms 4 rows (K0p
-// symmetric, row-major, coalesced along the row).
-constexpr int GV_NT = 1024;
-constexpr int GV_ROWS = 64;
+// c0 = K_0^+ c with c the sum of the restriction's band partials.  Rows of
+// K_0^+ are split over many small workgroups so that every CU streams a few
+// rows; each workgroup first sums the bands into LDS (fixed order).  One
+// wave per GV_RPW rows, four independent accumulators per lane.
+constexpr int GV_NT = 256;
+constexpr int GV_RPW = 2;                               // rows per wave
+constexpr int GV_ROWS = (GV_NT / 64) * GV_RPW;          // rows per workgroup
 constexpr int GV_MAXC = 12288;
 
 __global__ void __launch_bounds__(GV_NT)
@@ -444,13 +461,21 @@ k_coarse_gemv(const double* __restrict__ K0, int ldk, int nc,
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int rr = 0; rr < GV_ROWS / (GV_NT / 64); ++rr) {
-    const int row = blockIdx.x * GV_ROWS + wave * (GV_ROWS / (GV_NT / 64)) + rr;
+#pragma unroll
+  for (int rr = 0; rr < GV_RPW; ++rr) {
+    const int row = blockIdx.x * GV_ROWS + wave * GV_RPW + rr;
     if (row >= nc) break;
     const double* a = K0 + (long long)row * ldk;
-    double s = 0.0;
-    for (int j = lane; j < nc; j += 64) s += a[j] * cl[j];
-    s = wave_sum(s);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int j = lane;
+    for (; j + 192 < nc; j += 256) {
+      s0 += a[j] * cl[j];
+      s1 += a[j + 64] * cl[j + 64];
+      s2 += a[j + 128] * cl[j + 128];
+      s3 += a[j + 192] * cl[j + 192];
+    }
+    for (; j < nc; j += 64) s0 += a[j] * cl[j];
+    const double s = wave_sum((s0 + s1) + (s2 + s3));
     if (lane == 0) c0[row] = s;
   }
 }
@@ -505,10 +530,24 @@ k_combine(Geom g, CombineArgs ca, const uint8_t* __restrict__ mask,
           const int nw = cn.nxw * cn.nyw;
           const int loc = (y - cn.y0) * cn.nxw + (x - cn.x0);
           double s0 = 0.0, s1 = 0.0;
-          for (int j = 0; j < cn.nmodes; ++j) {
-            const double ps = ca.psi[cn.psi_off + (long long)j * nw + loc];
-            s0 += ps * ca.c0[cn.col0 + j];
-            s1 += ps * ca.c0[cn.col0 + cn.nmodes + j];
+          const double* pp = ca.psi + cn.psi_off + loc;
+          const double* cc = ca.c0 + cn.col0;
+          // modes in chunks of 4: the loads of a chunk are independent
+          for (int j0 = 0; j0 < cn.nmodes; j0 += 4) {
+            double pv[4], ca0[4], ca1[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const int j = min(j0 + t, cn.nmodes - 1);
+              pv[t] = pp[(long long)j * nw];
+              ca0[t] = cc[j];
+              ca1[t] = cc[cn.nmodes + j];
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const double w = (j0 + t < cn.nmodes) ? pv[t] : 0.0;
+              s0 += w * ca0[t];
+              s1 += w * ca1[t];
+            }
           }
           s0 *= chi;
           s1 *= chi;
@@ -618,6 +657,7 @@ void launch_restrict(const Geom& g, const CoarseNode* cn, int ncn,
 }
 
 int restrict_bands() { return RS_CH; }
+int restrict_max_band_nodes() { return RS_NT * RS_NPT; }
 
 void launch_coarse_gemv(const double* K0, int ldk, int nc, const double* cpart,
                         int ldc, double* c0, const CGScalars* sc,

@@ -65,6 +65,7 @@ void launch_restrict(const Geom&, const CoarseNode*, int, const uint8_t*,
                      const double*, const double*, double*, int, double,
                      CGScalars*, const double*, int, int, hipStream_t);
 int restrict_bands();
+int restrict_max_band_nodes();
 void launch_coarse_gemv(const double*, int, int, const double*, int, double*,
                         const CGScalars*, hipStream_t);
 int combine_blocks(const Geom&);
@@ -330,6 +331,9 @@ msp_status build_geometry(msp_handle* h) {
       voff += (long long)s.nxb * s.nyb;
       if (s.nxb > MAXBS)
         return fail(h, MSP_E_INVALID, "coarse neighbourhood row exceeds 72 nodes (sub_nel too large)");
+      if ((long long)s.nxb * ((s.nyb + restrict_bands() - 1) / restrict_bands()) >
+          restrict_max_band_nodes())
+        return fail(h, MSP_E_INVALID, "coarse neighbourhood too large for the restriction kernel");
       h->omegas.push_back(s);
       CoarseNode c{};
       c.cx = cx;
@@ -527,22 +531,7 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
   A(dalloc(&h->d_subs, h->subs.size()));
   A(dalloc(&h->d_omegas, h->omegas.size()));
   A(dalloc(&h->d_sub_grid, h->sub_grid.size()));
-  // slack: the first-level kernel copies records in whole 1 KiB chunks and
-  // reads less than 1 KiB past the last record
-  A(dalloc(&h->d_S64, h->l1_entries + 1024));
-  if (h->fp32) A(dalloc(&h->d_S32, h->l1_entries + 1024));
-  A(dalloc(&h->d_metric, h->subs.size()));
-  A(dalloc(&h->d_use64, h->subs.size()));
-  A(dalloc(&h->d_lsol, h->l1_vec));
-  A(dalloc(&h->d_Som, h->om_entries));
-  A(dalloc(&h->d_X, h->om_vec * m));
-  A(dalloc(&h->d_Y, h->om_vec * m));
-  A(dalloc(&h->d_Z, h->om_vec * m));
-  A(dalloc(&h->d_psi, h->om_vec * d->eig_kmax));
-  A(dalloc(&h->d_lam, h->omegas.size() * d->eig_kmax));
-  A(dalloc(&h->d_nsel, h->omegas.size()));
-  A(dalloc(&h->d_cap, h->omegas.size()));
-  A(dalloc(&h->d_cn, h->cn_h.size()));
+  (void)m;   // the preconditioner's buffers are allocated by the first setup
   A(dalloc(&h->d_x, nd));
   A(dalloc(&h->d_r, nd));
   A(dalloc(&h->d_p0, nd));
@@ -613,6 +602,46 @@ extern "C" msp_status msp_set_densities(msp_handle* h, const double* rho,
   return MSP_OK;
 }
 
+// Buffers of the preconditioner (local factor records, neighbourhood
+// factors and eigen workspaces, heat modes), allocated by the first setup so
+// that a handle used only for stiffness products holds just its vectors.
+static msp_status ensure_setup_buffers(msp_handle* h) {
+  if (h->d_S64 != nullptr) return MSP_OK;
+  const int m = std::min(h->desc.eig_kmax + kEigExtra, MAXM);
+  bool ok = true;
+  auto A = [&](hipError_t e) { if (e != hipSuccess) ok = false; };
+  // slack: the first-level kernel copies records in whole 1 KiB chunks and
+  // reads less than 1 KiB past the last record
+  A(dalloc(&h->d_S64, h->l1_entries + 1024));
+  if (h->fp32) A(dalloc(&h->d_S32, h->l1_entries + 1024));
+  A(dalloc(&h->d_metric, h->subs.size()));
+  A(dalloc(&h->d_use64, h->subs.size()));
+  A(dalloc(&h->d_lsol, h->l1_vec));
+  A(dalloc(&h->d_Som, h->om_entries));
+  A(dalloc(&h->d_X, h->om_vec * m));
+  A(dalloc(&h->d_Y, h->om_vec * m));
+  A(dalloc(&h->d_Z, h->om_vec * m));
+  A(dalloc(&h->d_psi, h->om_vec * h->desc.eig_kmax));
+  A(dalloc(&h->d_lam, h->omegas.size() * h->desc.eig_kmax));
+  A(dalloc(&h->d_nsel, h->omegas.size()));
+  A(dalloc(&h->d_cap, h->omegas.size()));
+  A(dalloc(&h->d_cn, h->cn_h.size()));
+  if (!ok) {
+    // leave none of them behind, so that a later setup tries again
+    void** bufs[] = {(void**)&h->d_S64, (void**)&h->d_S32, (void**)&h->d_metric,
+                     (void**)&h->d_use64, (void**)&h->d_lsol, (void**)&h->d_Som,
+                     (void**)&h->d_X, (void**)&h->d_Y, (void**)&h->d_Z,
+                     (void**)&h->d_psi, (void**)&h->d_lam, (void**)&h->d_nsel,
+                     (void**)&h->d_cap, (void**)&h->d_cn};
+    for (void** b : bufs) {
+      dfree(*b);
+      *b = nullptr;
+    }
+    return fail(h, MSP_E_NOMEM, "device allocation of the preconditioner failed");
+  }
+  return MSP_OK;
+}
+
 static msp_status ensure_coarse_buffers(msp_handle* h, size_t ncols,
                                         size_t npairs, size_t wsize, int ldk) {
   if (ncols > h->col_cap || (size_t)ldk > h->c_cap) {
@@ -653,6 +682,10 @@ static msp_status ensure_coarse_buffers(msp_handle* h, size_t ncols,
 extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
   if (!h) return fail(h, MSP_E_INVALID, "null handle");
   if (!h->have_E) return fail(h, MSP_E_STATE, "msp_set_densities must come first");
+  {
+    const msp_status st = ensure_setup_buffers(h);
+    if (st != MSP_OK) return st;
+  }
   hipEvent_t e0, e1;
   HIPCHK(h, hipEventCreate(&e0));
   HIPCHK(h, hipEventCreate(&e1));
@@ -834,9 +867,12 @@ extern "C" msp_status msp_apply_K(msp_handle* h, const double* x, double* y,
   if (!h || !x || !y) return fail(h, MSP_E_INVALID, "null argument");
   if (!h->have_E) return fail(h, MSP_E_STATE, "msp_set_densities must come first");
   if (x == y) return fail(h, MSP_E_INVALID, "x and y must not alias");
+  const int tm = timer_begin(h, KT_MATVEC, s);
   launch_apply_K(h->g, h->d_elem, h->d_E, h->d_mask, x, y, s);
+  timer_end(h, KT_MATVEC, tm, s);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(s));
+  timer_flush(h);
   return MSP_OK;
 }
 
