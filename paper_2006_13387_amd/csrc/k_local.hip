@@ -53,34 +53,135 @@ __device__ __forceinline__ bool is_fixed(const Geom& g,
   return flag[NDOF * node + c] != 0;
 }
 
-// In-place Gauss-Jordan inversion of an SPD block in LDS (no pivoting is
-// needed for SPD matrices).  rowv/colv: scratch vectors of MAXBS.
-template <int NT>
-__device__ void gj_invert(double* S, int bs, double* rowv, double* colv,
-                          int* __restrict__ err) {
-  const int tid = threadIdx.x;
-  for (int p = 0; p < bs; ++p) {
-    for (int i = tid; i < bs; i += NT) {
-      colv[i] = S[i * LDSTR + p];
-      rowv[i] = S[p * LDSTR + i];
+// In-place Gauss-Jordan inversion of an SPD block (no pivoting is needed
+// for SPD matrices).  The block sits in LDS (row stride LDSTR) before and
+// after; during the inversion each of the 16 x 16 threads holds a 5 x 5
+// tile in registers (rows ti + 16u, columns tj + 16w), and only the pivot
+// row and column go through LDS, double-buffered by pivot parity so that
+// one barrier per pivot suffices.  pv: LDS scratch of 4 * MAXBS doubles.
+constexpr int GJ_T = 5;                      // tile edge: 16 * 5 >= MAXBS
+static_assert(16 * GJ_T >= MAXBS, "Gauss-Jordan tiles do not cover a block");
+static_assert(GJ_T == 5, "gj_invert unrolls five tile rows of pivots");
+
+// One Gauss-Jordan pivot p = 16 PU + pt.  PU is a compile-time constant,
+// so the pivot's tile row and column are static register indices and only
+// the entries of that tile row / column need a select.
+template <int PU>
+__device__ __forceinline__ void gj_pivot_step(double (&a)[GJ_T][GJ_T], int p,
+                                              int pt, int ti, int tj, int bs,
+                                              double* pv, bool& bad) {
+  double* rowv = pv + (p & 1) * 2 * MAXBS;
+  double* colv = rowv + MAXBS;
+  // the owners publish the current pivot row and column
+  if (ti == pt) {
+#pragma unroll
+    for (int w = 0; w < GJ_T; ++w) {
+      const int j = tj + 16 * w;
+      if (j < bs) rowv[j] = a[PU][w];
     }
-    __syncthreads();
-    double piv = colv[p];
-    if (!(piv > 0.0) || !finite(piv)) {
-      if (tid == 0) atomicOr(err, ERR_NOT_SPD);
-      piv = 1.0;
-    }
-    const double ip = 1.0 / piv;
-    for (int idx = tid; idx < bs * bs; idx += NT) {
-      const int i = idx / bs, j = idx - (idx / bs) * bs;
-      double v;
-      if (i == p) v = (j == p) ? ip : rowv[j] * ip;
-      else if (j == p) v = -colv[i] * ip;
-      else v = S[i * LDSTR + j] - colv[i] * rowv[j] * ip;
-      S[i * LDSTR + j] = v;
-    }
-    __syncthreads();
   }
+  if (tj == pt) {
+#pragma unroll
+    for (int u = 0; u < GJ_T; ++u) {
+      const int i = ti + 16 * u;
+      if (i < bs) colv[i] = a[u][PU];
+    }
+  }
+  __syncthreads();
+  double piv = colv[p];
+  if (!(piv > 0.0) || !finite(piv)) {
+    bad = true;
+    piv = 1.0;
+  }
+  const double ip = 1.0 / piv;
+  double cv[GJ_T], rv[GJ_T];
+#pragma unroll
+  for (int u = 0; u < GJ_T; ++u) {
+    const int i = ti + 16 * u;
+    cv[u] = (i < bs) ? colv[i] : 0.0;
+  }
+#pragma unroll
+  for (int w = 0; w < GJ_T; ++w) {
+    const int j = tj + 16 * w;
+    rv[w] = ((j < bs) ? rowv[j] : 0.0) * ip;
+  }
+  const bool prow = ti == pt, pcol = tj == pt;
+#pragma unroll
+  for (int u = 0; u < GJ_T; ++u)
+#pragma unroll
+    for (int w = 0; w < GJ_T; ++w) {
+      const double upd = a[u][w] - cv[u] * rv[w];
+      if (u == PU && w == PU)
+        a[u][w] = prow ? (pcol ? ip : rv[w]) : (pcol ? -cv[u] * ip : upd);
+      else if (u == PU)
+        a[u][w] = prow ? rv[w] : upd;
+      else if (w == PU)
+        a[u][w] = pcol ? -cv[u] * ip : upd;
+      else
+        a[u][w] = upd;
+    }
+}
+
+template <int PU>
+__device__ __forceinline__ void gj_pivot_tile(double (&a)[GJ_T][GJ_T], int ti,
+                                              int tj, int bs, double* pv,
+                                              bool& bad) {
+  for (int pt = 0; pt < 16; ++pt) {
+    const int p = 16 * PU + pt;
+    if (p >= bs) break;                       // uniform: bs is per system
+    gj_pivot_step<PU>(a, p, pt, ti, tj, bs, pv, bad);
+  }
+}
+
+__device__ __forceinline__ void gj_invert(double* S, int bs, double* pv,
+                                          int* __restrict__ err) {
+  static_assert(FT_NT == 256, "the Gauss-Jordan tiling assumes 256 threads");
+  const int tid = threadIdx.x;
+  const int ti = tid & 15, tj = tid >> 4;
+  double a[GJ_T][GJ_T];
+#pragma unroll
+  for (int u = 0; u < GJ_T; ++u)
+#pragma unroll
+    for (int w = 0; w < GJ_T; ++w) {
+      const int i = ti + 16 * u, j = tj + 16 * w;
+      a[u][w] = (i < bs && j < bs) ? S[i * LDSTR + j] : 0.0;
+    }
+  bool bad = false;
+  gj_pivot_tile<0>(a, ti, tj, bs, pv, bad);
+  gj_pivot_tile<1>(a, ti, tj, bs, pv, bad);
+  gj_pivot_tile<2>(a, ti, tj, bs, pv, bad);
+  gj_pivot_tile<3>(a, ti, tj, bs, pv, bad);
+  gj_pivot_tile<4>(a, ti, tj, bs, pv, bad);
+  if (bad && tid == 0) atomicOr(err, ERR_NOT_SPD);
+#pragma unroll
+  for (int u = 0; u < GJ_T; ++u)
+#pragma unroll
+    for (int w = 0; w < GJ_T; ++w) {
+      const int i = ti + 16 * u, j = tj + 16 * w;
+      if (i < bs && j < bs) S[i * LDSTR + j] = a[u][w];
+    }
+  __syncthreads();
+}
+
+// K entry between DOF (ia, ca) of node row ra and DOF (ib, cb) of node row
+// rb of the two rows staged in LDS (r = 0: row y-1, r = 1: row y), from
+// the staged element moduli er[e][t] of element rows y-1 (e = 0) and y
+// (e = 1), element column x0 - 1 + t (zero outside the system's element
+// box), and the element matrix Kl.
+template <int NDOF>
+__device__ __forceinline__ double coupling_l(const double (*er)[MAXBS + 2],
+                                             const double* Kl, int ia, int ra,
+                                             int ca, int ib, int rb, int cb) {
+  double v = 0.0;
+  const int tlo = max(ia, ib), thi = min(ia, ib) + 1;   // element columns t
+  const int elo = max(ra, rb) - 1, ehi = min(ra, rb);   // element rows e
+  for (int e = max(elo, 0); e <= ehi; ++e)
+    for (int t = tlo; t <= thi; ++t) {
+      const int va = (ia + 1 - t) + 2 * (ra - e);
+      const int vb = (ib + 1 - t) + 2 * (rb - e);
+      v += er[e][t] * Kl[(NDOF * va + ca) * (4 * NDOF) + NDOF * vb + cb];
+    }
+  return v;
 }
 
 // Factorise every system: one workgroup per system.
@@ -101,29 +202,46 @@ k_factor(Geom g, const SysDesc* __restrict__ systems,
          int* __restrict__ err) {
   __shared__ double buf[3][MAXBS * LDSTR];
   __shared__ double Bv[MAXBS * 3 * NDOF];
-  __shared__ double rowv[MAXBS], colv[MAXBS];
+  __shared__ double pv[4 * MAXBS];
   __shared__ double ddiag[MAXBS];
+  __shared__ double er[2][MAXBS + 2];          // element moduli, rows y-1, y
+  __shared__ uint8_t fr[2][MAXBS];             // clamp flags, node rows y-1, y
+  __shared__ double Kl[16 * NDOF * NDOF];
   __shared__ double red[FT_NT / 64 + 1];
   double mloc = 0.0;
   const SysDesc s = systems[blockIdx.x];
   const int tid = threadIdx.x;
   const int bs = NDOF * s.nxb;
+  for (int i = tid; i < 16 * NDOF * NDOF; i += FT_NT) Kl[i] = Kel[i];
   int cur = 0, prev = 1, wb = 2;
   for (int k = 0; k < s.nyb; ++k) {
     const int y = s.y0 + k;
     double* S = buf[cur];
+    // stage the moduli of element rows y-1, y (element columns x0-1 ..
+    // x0+nxb-1; zero outside the element box) and the clamp flags of node
+    // rows y-1, y (row -1 does not exist: flagged)
+    for (int idx = tid; idx < 2 * (s.nxb + 1); idx += FT_NT) {
+      const int e = idx / (s.nxb + 1), t = idx - e * (s.nxb + 1);
+      const int ex = s.x0 - 1 + t, ey = y - 1 + e;
+      const bool in = ex >= s.ex0 && ex < s.ex1 && ey >= s.ey0 && ey < s.ey1;
+      er[e][t] = in ? E[(long long)ey * g.nx + ex] : 0.0;
+    }
+    for (int idx = tid; idx < 2 * bs; idx += FT_NT) {
+      const int r = idx / bs, a = idx - r * bs;
+      const int yy = y - 1 + r;
+      fr[r][a] = (yy >= 0) ? flag[NDOF * ((long long)yy * g.nnx + s.x0) + a] : 1;
+    }
+    __syncthreads();
     // D_k
     for (int idx = tid; idx < bs * bs; idx += FT_NT) {
       const int a = idx / bs, b = idx - (idx / bs) * bs;
       const int ia = a / NDOF, ca = a - ia * NDOF;
       const int ib = b / NDOF, cb = b - ib * NDOF;
       double v = 0.0;
-      const bool fa = is_fixed<NDOF>(g, flag, s.x0 + ia, y, ca);
-      const bool fb = is_fixed<NDOF>(g, flag, s.x0 + ib, y, cb);
-      if (fa || fb) {
+      if (fr[1][a] || fr[1][b]) {
         v = (a == b) ? 1.0 : 0.0;
       } else if (abs(ia - ib) <= 1) {
-        v = coupling<NDOF>(g, s, E, Kel, s.x0 + ia, y, ca, s.x0 + ib, y, cb);
+        v = coupling_l<NDOF>(er, Kl, ia, 1, ca, ib, 1, cb);
       }
       S[a * LDSTR + b] = v;
       if (a == b) ddiag[a] = v;
@@ -136,10 +254,8 @@ k_factor(Geom g, const SysDesc* __restrict__ systems,
         const int di = t / NDOF - 1, cb = t - (t / NDOF) * NDOF;
         const int ib = ia + di;
         double v = 0.0;
-        if (ib >= 0 && ib < s.nxb &&
-            !is_fixed<NDOF>(g, flag, s.x0 + ia, y, ca) &&
-            !is_fixed<NDOF>(g, flag, s.x0 + ib, y - 1, cb))
-          v = coupling<NDOF>(g, s, E, Kel, s.x0 + ia, y, ca, s.x0 + ib, y - 1, cb);
+        if (ib >= 0 && ib < s.nxb && !fr[1][a] && !fr[0][NDOF * ib + cb])
+          v = coupling_l<NDOF>(er, Kl, ia, 1, ca, ib, 0, cb);
         Bv[idx] = v;
       }
       __syncthreads();
@@ -172,28 +288,26 @@ k_factor(Geom g, const SysDesc* __restrict__ systems,
       }
     }
     __syncthreads();
-    gj_invert<FT_NT>(S, bs, rowv, colv, err);
-    // record of row k: the inverse block (column j contiguous) and, for the
-    // elasticity systems, the couplings F(k) of row k with row k-1 (zero
-    // for k = 0) that the first-level apply streams with it
-    const long long rec = (long long)bs * bs + (NDOF == 2 ? 6LL * bs : 0LL);
+    gj_invert(S, bs, pv, err);
+    // record of row k: the inverse block (column j contiguous) and the
+    // couplings F(k) of row k with row k-1 (zero for k = 0), which the
+    // first-level apply and the heat eigen sweeps stream with it
+    const long long rec = (long long)bs * bs + 3LL * NDOF * bs;
     double* o = out64 + s.foff + (long long)k * rec;
     for (int idx = tid; idx < bs * bs; idx += FT_NT) {
       const int j = idx / bs, i = idx - (idx / bs) * bs;
       o[idx] = S[i * LDSTR + j];
     }
-    if (NDOF == 2)
-      for (int idx = tid; idx < bs * 6; idx += FT_NT)
-        o[bs * bs + idx] = (k > 0) ? Bv[idx] : 0.0;
+    for (int idx = tid; idx < bs * 3 * NDOF; idx += FT_NT)
+      o[bs * bs + idx] = (k > 0) ? Bv[idx] : 0.0;
     if (out32 != nullptr) {
       float* o32 = out32 + s.foff + (long long)k * rec;
       for (int idx = tid; idx < bs * bs; idx += FT_NT) {
         const int j = idx / bs, i = idx - (idx / bs) * bs;
         o32[idx] = (float)S[i * LDSTR + j];
       }
-      if (NDOF == 2)
-        for (int idx = tid; idx < bs * 6; idx += FT_NT)
-          o32[bs * bs + idx] = (k > 0) ? (float)Bv[idx] : 0.0f;
+      for (int idx = tid; idx < bs * 3 * NDOF; idx += FT_NT)
+        o32[bs * bs + idx] = (k > 0) ? (float)Bv[idx] : 0.0f;
     }
     for (int a = tid; a < bs; a += FT_NT) mloc = fmax(mloc, S[a * LDSTR + a] * ddiag[a]);
     __syncthreads();
@@ -852,6 +966,59 @@ __device__ void jacobi_small(double* A, double* V, int m, double* rc,
   __syncthreads();
 }
 
+// X[:, c] = Y V[:, order[c]] (the Ritz vectors, ascending); one node per
+// thread.
+__device__ void ritz_vectors(const double* Y, double* X,
+                                          const double* V, const int* order,
+                                          int n, int m) {
+  for (int node = threadIdx.x; node < n; node += EG_NT) {
+    double yv[MAXM];
+#pragma unroll
+    for (int j = 0; j < MAXM; ++j)
+      if (j < m) yv[j] = Y[(long long)j * n + node];
+    for (int c = 0; c < m; ++c) {
+      const int oc = order[c];
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < MAXM; ++j)
+        if (j < m) acc += yv[j] * V[j * m + oc];
+      X[(long long)c * n + node] = acc;
+    }
+  }
+}
+
+// Sweep of the shift-invert solve Y = C^{-1} Z by node rows: nb forward and
+// nb-1 backward steps, step c on row k(c) (as in the first-level apply).
+// Each row k has a record [S_k^{-1} (bs x bs, column-major) | F(k) (bs x
+// 3: couplings of row k with row k-1)] written by the factorisation.  While
+// step c runs, every thread holds its share of step c+1's record and vector
+// row (Z forward, the forward Y backward) in registers; they are stored to
+// the other LDS slot at the end of the step, so the loads overlap the block
+// GEMM.  The GEMM gives each thread one row i and up to EG_NC columns.
+constexpr int EG_PFR = (MAXBS * MAXBS + 3 * MAXBS + EG_NT - 1) / EG_NT;   // record regs
+constexpr int EG_PFZ = (MAXBS * MAXM + EG_NT - 1) / EG_NT;               // row regs
+constexpr int EG_NC = 5;                                                 // GEMM columns
+constexpr int EG_RAW = 18176;              // doubles of the kernel's carved LDS
+
+// LDS doubles the sweep needs for bs, m (2 record slots, 2 vector rows,
+// the right-hand side and the result rows)
+__host__ __device__ inline int eig_sweep_doubles(int bs, int m) {
+  const int rec = bs * bs + 3 * bs;
+  return 2 * ((rec + 1) & ~1) + 4 * bs * m;
+}
+
+// the block size m fits the kernel for rows of bs nodes
+__host__ __device__ inline bool eig_fits(int bs, int m) {
+  const int ngrp = min(EG_NT / bs, m);
+  return m <= MAXM && bs <= MAXBS && eig_sweep_doubles(bs, m) <= EG_RAW &&
+         (m + ngrp - 1) / ngrp <= EG_NC && 2 * MAXM * 64 <= EG_RAW;
+}
+
+// LDS-only workgroup barrier (the register prefetch stays in flight)
+__device__ __forceinline__ void eg_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 __global__ void __launch_bounds__(EG_NT)
 k_heat_eigen(Geom g, const SysDesc* __restrict__ systems,
              const double* __restrict__ E, const uint8_t* __restrict__ dflag,
@@ -862,9 +1029,7 @@ k_heat_eigen(Geom g, const SysDesc* __restrict__ systems,
              double* __restrict__ psi_out, double* __restrict__ lam_out,
              int* __restrict__ nsel_out, int* __restrict__ cap_out,
              int* __restrict__ err) {
-  __shared__ double lbuf[3 * MAXBS * MAXM];   // solve rows / gram staging
-  __shared__ double SkL[MAXBS * MAXBS];        // one inverse block
-  __shared__ double cpl[MAXBS * 3];            // couplings of one row
+  __shared__ __align__(16) double raw[EG_RAW];   // sweep rows / gram staging
   __shared__ double G[MAXM * MAXM];
   __shared__ double V[MAXM * MAXM];
   __shared__ double theta[MAXM], theta_old[MAXM];
@@ -880,6 +1045,7 @@ k_heat_eigen(Geom g, const SysDesc* __restrict__ systems,
   double* X = Xw + wo;
   double* Y = Yw + wo;
   double* Z = Zw + wo;
+  (void)Cel;
 
   for (int idx = tid; idx < n * m; idx += EG_NT) {
     const int j = idx / n, node = idx - (idx / n) * n;
@@ -893,101 +1059,150 @@ k_heat_eigen(Geom g, const SysDesc* __restrict__ systems,
   if (tid == 0) converged = 0;
   __syncthreads();
 
-  double* Wl = lbuf;                    // bs x m
-  double* Tp = lbuf + MAXBS * MAXM;     // previous row result
-  double* Tc = lbuf + 2 * MAXBS * MAXM; // current row result
+  // carve the sweep buffers
+  const int rec = bs * bs + 3 * bs;
+  const int recp = (rec + 1) & ~1;
+  double* slot[2] = {raw, raw + recp};
+  double* Zs[2] = {raw + 2 * recp, raw + 2 * recp + bs * m};
+  double* Wl = raw + 2 * recp + 2 * bs * m;      // [a][j], stride m
+  double* T = Wl + bs * m;                       // [a][j], stride m
+  const double* recs = Sinv + s.foff;
+  const int nsteps = 2 * nb - 1;
+  // GEMM role
+  const int ngrp = min(EG_NT / bs, m);
+  const int gi = tid % bs, gj = tid / bs;
+  const bool gact = gj < ngrp;
+  const int bm = bs * m;
 
   for (int it = 0; it < prm.maxit; ++it) {
     // Z = M X
     omega_stencil(g, s, E, dflag, Me, X, Z, n, m);
     __syncthreads();
-    // Y = C^{-1} Z : forward
-    for (int k = 0; k < nb; ++k) {
-      const int y = s.y0 + k;
-      const double* Sk = Sinv + s.foff + (long long)k * bs * bs;
-      for (int idx = tid; idx < bs * bs; idx += EG_NT) SkL[idx] = Sk[idx];
-      if (k > 0)
-        for (int idx = tid; idx < bs * 3; idx += EG_NT) {
-          const int a = idx / 3, t = idx - a * 3;
-          const int b = a + t - 1, x = s.x0 + a;
-          double cv = 0.0;
-          if (b >= 0 && b < bs && !dflag[(long long)y * g.nnx + x] &&
-              !dflag[(long long)(y - 1) * g.nnx + s.x0 + b])
-            cv = coupling<1>(g, s, E, Cel, x, y, 0, s.x0 + b, y - 1, 0);
-          cpl[idx] = cv;
-        }
+    // Y = C^{-1} Z
+    {
+      for (int q = tid; q < rec; q += EG_NT) slot[0][q] = recs[q];
+      for (int q = tid; q < bm; q += EG_NT) {
+        const int j = q / bs, a = q - (q / bs) * bs;
+        Zs[0][q] = Z[(long long)j * n + a];
+      }
       __syncthreads();
-      for (int idx = tid; idx < bs * m; idx += EG_NT) {
-        const int a = idx / m, j = idx - (idx / m) * m;
-        double w = Z[(long long)j * n + k * bs + a];
-        if (k > 0) {
+    }
+    for (int c = 0; c < nsteps; ++c) {
+      const bool fwd = c < nb;
+      const int k = c < nb ? c : 2 * nb - 2 - c;
+      const int cur = c & 1;
+      if (c == nb - 1) __syncthreads();    // forward rows of Y visible to the
+                                           // backward prefetch below
+      // prefetch step c+1: record and vector row (Z forward, Y backward)
+      double pr[EG_PFR], pz[EG_PFZ];
+      const bool pf = c + 1 < nsteps;
+      if (pf) {
+        const int k1 = (c + 1) < nb ? c + 1 : 2 * nb - 3 - c;
+        const double* rsrc = recs + (long long)k1 * rec;
 #pragma unroll
-          for (int t = 0; t < 3; ++t) {
-            const int b = a + t - 1;
-            if (b >= 0 && b < bs) w -= cpl[a * 3 + t] * Tp[b * MAXM + j];
+        for (int u = 0; u < EG_PFR; ++u) {
+          const int q = tid + u * EG_NT;
+          pr[u] = q < rec ? rsrc[q] : 0.0;
+        }
+        const double* vsrc = ((c + 1) < nb ? Z : Y) + (long long)k1 * bs;
+#pragma unroll
+        for (int u = 0; u < EG_PFZ; ++u) {
+          const int q = tid + u * EG_NT;
+          const int j = q / bs, a = q - (q / bs) * bs;
+          pz[u] = q < bm ? vsrc[(long long)j * n + a] : 0.0;
+        }
+      }
+      // phase A: right-hand side of the row
+      {
+        const double* F = slot[cur] + bs * bs;            // F(k), forward
+        const double* Fp = slot[cur ^ 1] + bs * bs;       // F(k+1), backward
+        for (int idx = tid; idx < bm; idx += EG_NT) {
+          const int j = idx / bs, a = idx - (idx / bs) * bs;
+          double w;
+          if (fwd) {
+            w = Zs[cur][idx];
+            if (k > 0) {
+#pragma unroll
+              for (int t = 0; t < 3; ++t) {
+                const int b = a + t - 1;
+                if (b >= 0 && b < bs) w -= F[a * 3 + t] * T[b * m + j];
+              }
+            }
+          } else {
+            w = 0.0;
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+              const int b = a + t - 1;      // node of row k+1
+              if (b >= 0 && b < bs) w += Fp[b * 3 + (2 - t)] * T[b * m + j];
+            }
+          }
+          Wl[a * m + j] = w;
+        }
+      }
+      eg_barrier();
+      // phase B: rows of C^{-1}: T = S_k^{-1} Wl (backward: Y_k - that)
+      if (gact) {
+        const double* S = slot[cur];
+        double acc[EG_NC];
+#pragma unroll
+        for (int u = 0; u < EG_NC; ++u) acc[u] = 0.0;
+        int b = 0;
+        for (; b + 2 <= bs; b += 2) {
+          const double s0 = S[b * bs + gi], s1 = S[(b + 1) * bs + gi];
+#pragma unroll
+          for (int u = 0; u < EG_NC; ++u) {
+            const int j = gj + u * ngrp;
+            if (j < m) acc[u] += s0 * Wl[b * m + j] + s1 * Wl[(b + 1) * m + j];
           }
         }
-        Wl[a * MAXM + j] = w;
-      }
-      __syncthreads();
-      for (int idx = tid; idx < bs * m; idx += EG_NT) {
-        const int i = idx % bs, j = idx / bs;
-        const double acc = eig_dot(SkL, bs, i, Wl + j, bs);
-        Tc[i * MAXM + j] = acc;
-        Y[(long long)j * n + k * bs + i] = acc;
-      }
-      __syncthreads();
-      double* t = Tp; Tp = Tc; Tc = t;
-    }
-    // backward: Tp holds row nb-1 (final)
-    for (int k = nb - 2; k >= 0; --k) {
-      const int y = s.y0 + k;
-      const double* Sk = Sinv + s.foff + (long long)k * bs * bs;
-      for (int idx = tid; idx < bs * bs; idx += EG_NT) SkL[idx] = Sk[idx];
-      for (int idx = tid; idx < bs * 3; idx += EG_NT) {
-        const int b = idx / 3, t = idx - b * 3;
-        const int a = b + t - 1, x = s.x0 + b;
-        double cv = 0.0;
-        if (a >= 0 && a < bs && !dflag[(long long)y * g.nnx + x] &&
-            !dflag[(long long)(y + 1) * g.nnx + s.x0 + a])
-          cv = coupling<1>(g, s, E, Cel, x, y, 0, s.x0 + a, y + 1, 0);
-        cpl[idx] = cv;
-      }
-      __syncthreads();
-      for (int idx = tid; idx < bs * m; idx += EG_NT) {
-        const int b = idx / m, j = idx - (idx / m) * m;
-        double w = 0.0;
+        for (; b < bs; ++b) {
+          const double s0 = S[b * bs + gi];
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-          const int a = b + t - 1;
-          if (a >= 0 && a < bs) w += cpl[b * 3 + t] * Tp[a * MAXM + j];
+          for (int u = 0; u < EG_NC; ++u) {
+            const int j = gj + u * ngrp;
+            if (j < m) acc[u] += s0 * Wl[b * m + j];
+          }
         }
-        Wl[b * MAXM + j] = w;
+#pragma unroll
+        for (int u = 0; u < EG_NC; ++u) {
+          const int j = gj + u * ngrp;
+          if (j < m) {
+            const double val = fwd ? acc[u] : Zs[cur][j * bs + gi] - acc[u];
+            T[gi * m + j] = val;
+            Y[(long long)j * n + k * bs + gi] = val;
+          }
+        }
       }
-      __syncthreads();
-      for (int idx = tid; idx < bs * m; idx += EG_NT) {
-        const int i = idx % bs, j = idx / bs;
-        const double acc = eig_dot(SkL, bs, i, Wl + j, bs);
-        const double val = Y[(long long)j * n + k * bs + i] - acc;
-        Tc[i * MAXM + j] = val;
-        Y[(long long)j * n + k * bs + i] = val;
+      if (pf) {
+        double* ds = slot[cur ^ 1];
+#pragma unroll
+        for (int u = 0; u < EG_PFR; ++u) {
+          const int q = tid + u * EG_NT;
+          if (q < rec) ds[q] = pr[u];
+        }
+        double* dz = Zs[cur ^ 1];
+#pragma unroll
+        for (int u = 0; u < EG_PFZ; ++u) {
+          const int q = tid + u * EG_NT;
+          if (q < bm) dz[q] = pz[u];
+        }
       }
-      __syncthreads();
-      double* t = Tp; Tp = Tc; Tc = t;
+      eg_barrier();
     }
+    __syncthreads();
     const bool do_rr = ((it + 1) % prm.rr_every == 0) || (it + 1 == prm.maxit);
     // M-orthonormalise Y by Cholesky QR (twice before a Rayleigh-Ritz step)
     for (int pass = 0; pass < (do_rr ? 2 : 1); ++pass) {
       omega_stencil(g, s, E, dflag, Me, Y, Z, n, m);
       __syncthreads();
-      gram(Y, Z, n, m, G, lbuf);
+      gram(Y, Z, n, m, G, raw);
       chol_small(G, m, err);
       apply_linvT(Y, n, m, G);
     }
     if (do_rr) {
       omega_stencil(g, s, E, dflag, Ae, Y, Z, n, m);
       __syncthreads();
-      gram(Y, Z, n, m, G, lbuf);
+      gram(Y, Z, n, m, G, raw);
       jacobi_small(G, V, m, rc, rs, rp, rq);
       if (tid == 0) {
         for (int i = 0; i < m; ++i) order[i] = i;
@@ -1019,20 +1234,7 @@ k_heat_eigen(Geom g, const SysDesc* __restrict__ systems,
       }
       __syncthreads();
       // X = Y V (columns sorted ascending)
-      for (int node = tid; node < n; node += EG_NT) {
-        double yv[MAXM];
-#pragma unroll
-        for (int j = 0; j < MAXM; ++j)
-          if (j < m) yv[j] = Y[(long long)j * n + node];
-        for (int c = 0; c < m; ++c) {
-          const int oc = order[c];
-          double acc = 0.0;
-#pragma unroll
-          for (int j = 0; j < MAXM; ++j)
-            if (j < m) acc += yv[j] * V[j * m + oc];
-          X[(long long)c * n + node] = acc;
-        }
-      }
+      ritz_vectors(Y, X, V, order, n, m);
       __syncthreads();
       if (converged) break;
     } else {
@@ -1082,6 +1284,8 @@ void launch_level1(const Geom& g, const SysDesc* sys, int nsys,
   hipLaunchKernelGGL(k_level1, dim3(nsys), dim3(AP_NT), 0, s, g, sys, mask, S64,
                      S32, use64, r, lsol, sc, part_upd, nb_upd, check);
 }
+
+bool eig_fits_host(int bs, int m) { return eig_fits(bs, m); }
 
 bool level1_fits(int bs, int nb, bool fp32) {
   return l1_fits<double>(bs, nb) && (!fp32 || l1_fits<float>(bs, nb));

@@ -65,6 +65,7 @@ void launch_restrict(const Geom&, const CoarseNode*, int, const uint8_t*,
                      const double*, const double*, double*, int, double,
                      CGScalars*, const double*, int, int, hipStream_t);
 int restrict_bands();
+bool eig_fits_host(int bs, int m);
 int restrict_max_band_nodes();
 void launch_coarse_gemv(const double*, int, int, const double*, int, double*,
                         const CGScalars*, hipStream_t);
@@ -135,6 +136,7 @@ struct msp_handle {
   int ngx = 0, ngy = 0;
   std::vector<CoarseNode> cn_h;
   long long l1_entries = 0, l1_vec = 0, om_entries = 0, om_vec = 0;
+  int eig_m = 0;             // subspace block of the heat eigen iteration
 
   double Ke[64], Ae[16], Me[16], Ce[16];
 
@@ -327,7 +329,7 @@ msp_status build_geometry(msp_handle* h) {
       s.ey1 = ey1;
       s.foff = foff;
       s.voff = voff;
-      foff += (long long)s.nyb * s.nxb * s.nxb;
+      foff += (long long)s.nyb * (s.nxb * s.nxb + 3 * s.nxb);   // records: S^-1 | F
       voff += (long long)s.nxb * s.nyb;
       if (s.nxb > MAXBS)
         return fail(h, MSP_E_INVALID, "coarse neighbourhood row exceeds 72 nodes (sub_nel too large)");
@@ -347,6 +349,18 @@ msp_status build_geometry(msp_handle* h) {
     }
   h->om_entries = foff;
   h->om_vec = voff;
+  // subspace block: kmax + kEigExtra vectors, fewer if the eigen kernel's
+  // LDS cannot hold the sweep rows of the widest neighbourhood, but at
+  // least kmax + 2
+  {
+    int maxw = 1;
+    for (const SysDesc& o : h->omegas) maxw = std::max(maxw, o.nxb);
+    int m = std::min(h->desc.eig_kmax + kEigExtra, MAXM);
+    while (m > h->desc.eig_kmax + 2 && !eig_fits_host(maxw, m)) --m;
+    if (!eig_fits_host(maxw, m))
+      return fail(h, MSP_E_INVALID, "eig_kmax too large for the coarse neighbourhood size");
+    h->eig_m = m;
+  }
   return MSP_OK;
 }
 
@@ -517,7 +531,6 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
   for (int i = 0; i < 16; ++i) h->Ce[i] = h->Ae[i] + sigma * h->Me[i];
 
   const long long nd = h->n_dofs, nn = h->n_nodes;
-  const int m = std::min(d->eig_kmax + kEigExtra, MAXM);
   h->nb_mv = matvec_blocks(g);
   h->nb_upd = update_blocks(nd);
   h->nb_comb = combine_blocks(g);
@@ -531,7 +544,7 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
   A(dalloc(&h->d_subs, h->subs.size()));
   A(dalloc(&h->d_omegas, h->omegas.size()));
   A(dalloc(&h->d_sub_grid, h->sub_grid.size()));
-  (void)m;   // the preconditioner's buffers are allocated by the first setup
+  // the preconditioner's buffers are allocated by the first setup
   A(dalloc(&h->d_x, nd));
   A(dalloc(&h->d_r, nd));
   A(dalloc(&h->d_p0, nd));
@@ -607,7 +620,7 @@ extern "C" msp_status msp_set_densities(msp_handle* h, const double* rho,
 // that a handle used only for stiffness products holds just its vectors.
 static msp_status ensure_setup_buffers(msp_handle* h) {
   if (h->d_S64 != nullptr) return MSP_OK;
-  const int m = std::min(h->desc.eig_kmax + kEigExtra, MAXM);
+  const int m = h->eig_m;
   bool ok = true;
   auto A = [&](hipError_t e) { if (e != hipSuccess) ok = false; };
   // slack: the first-level kernel copies records in whole 1 KiB chunks and
@@ -696,7 +709,7 @@ extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
   const double* Me = h->d_elem + 80;
   const double* Ce = h->d_elem + 96;
   const int kmax = h->desc.eig_kmax;
-  const int m = std::min(kmax + kEigExtra, MAXM);
+  const int m = h->eig_m;
   HIPCHK(h, hipMemsetAsync(h->d_err, 0, sizeof(int), s));
   int tk = timer_begin(h, KT_FACTOR, s);
   launch_factor_elastic(g, h->d_subs, (int)h->subs.size(), h->d_E, h->d_mask,
