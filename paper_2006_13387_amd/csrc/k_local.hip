@@ -736,13 +736,16 @@ __device__ __forceinline__ double hash_unit(unsigned long long a) {
 }
 
 // out[j][node] = sum_e kappa_e (Kel in)[node] over omega's elements for the
-// first m columns; Dirichlet rows are 0.  One node per thread, the element
-// moduli of its (up to) four elements read once for all m columns.
+// first m columns; Dirichlet rows are 0.  One node per thread: its nine
+// neighbour weights are formed once from the (up to) four elements around
+// it, then the columns are done four at a time with all their loads issued
+// before the stores.
 __device__ void omega_stencil(const Geom& g, const SysDesc& s,
                               const double* __restrict__ E,
                               const uint8_t* __restrict__ dflag,
                               const double* __restrict__ Kel4,
-                              const double* in, double* out, int n, int m) {
+                              const double* __restrict__ in,
+                              double* __restrict__ out, int n, int m) {
   for (int node = threadIdx.x; node < n; node += EG_NT) {
     const int i = node % s.nxb, k = node / s.nxb;
     const int x = s.x0 + i, y = s.y0 + k;
@@ -750,34 +753,47 @@ __device__ void omega_stencil(const Geom& g, const SysDesc& s,
       for (int j = 0; j < m; ++j) out[(long long)j * n + node] = 0.0;
       continue;
     }
-    // weights w[dy][dx][vb] = kappa_e * Kel[va][vb] for the four elements
-    double wgt[2][2][4];
-    int base[2][2];
+    // w9[(dy+1)*3 + (dx+1)]: weight of neighbour (x+dx, y+dy)
+    double w9[9];
 #pragma unroll
-    for (int dy = 0; dy < 2; ++dy)
+    for (int t = 0; t < 9; ++t) w9[t] = 0.0;
 #pragma unroll
-      for (int dx = 0; dx < 2; ++dx) {
-        const int ex = x - 1 + dx, ey = y - 1 + dy;
+    for (int ey_ = 0; ey_ < 2; ++ey_)
+#pragma unroll
+      for (int ex_ = 0; ex_ < 2; ++ex_) {
+        const int ex = x - 1 + ex_, ey = y - 1 + ey_;
         const bool ok = ex >= s.ex0 && ex < s.ex1 && ey >= s.ey0 && ey < s.ey1;
         const double ke = ok ? E[(long long)ey * g.nx + ex] : 0.0;
-        const int va = (x - ex) + 2 * (y - ey);
+        const int va = (1 - ex_) + 2 * (1 - ey_);
 #pragma unroll
-        for (int vb = 0; vb < 4; ++vb) wgt[dy][dx][vb] = ke * Kel4[va * 4 + vb];
-        base[dy][dx] = ok ? (ey - s.y0) * s.nxb + (ex - s.x0) : -1;
-      }
-    for (int j = 0; j < m; ++j) {
-      const double* col = in + (long long)j * n;
-      double acc = 0.0;
-#pragma unroll
-      for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 2; ++dx) {
-          const int b0 = base[dy][dx];
-          if (b0 < 0) continue;
-          acc += wgt[dy][dx][0] * col[b0] + wgt[dy][dx][1] * col[b0 + 1] +
-                 wgt[dy][dx][2] * col[b0 + s.nxb] + wgt[dy][dx][3] * col[b0 + s.nxb + 1];
+        for (int vb = 0; vb < 4; ++vb) {
+          const int ddx = ex_ - 1 + (vb & 1), ddy = ey_ - 1 + (vb >> 1);
+          w9[(ddy + 1) * 3 + (ddx + 1)] += ke * Kel4[va * 4 + vb];
         }
-      out[(long long)j * n + node] = acc;
+      }
+    int off9[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int ddx = t % 3 - 1, ddy = t / 3 - 1;
+      const bool in_box = i + ddx >= 0 && i + ddx < s.nxb && k + ddy >= 0 && k + ddy < s.nyb;
+      off9[t] = in_box ? node + ddy * s.nxb + ddx : node;
+      if (!in_box) w9[t] = 0.0;
+    }
+    for (int j0 = 0; j0 < m; j0 += 4) {
+      double v[4][9];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const double* col = in + (long long)min(j0 + jj, m - 1) * n;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) v[jj][t] = col[off9[t]];
+      }
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc += w9[t] * v[jj][t];
+        if (j0 + jj < m) out[(long long)(j0 + jj) * n + node] = acc;
+      }
     }
   }
 }
@@ -856,12 +872,13 @@ __device__ void chol_small(double* G, int m, int* __restrict__ err) {
 }
 
 // Y <- Y L^{-T} (each node's row of m values solved with L).
-__device__ void apply_linvT(double* Y, int n, int m, const double* L) {
+__device__ void apply_linvT(const double* Yin, double* Y, int n, int m,
+                            const double* L) {
   for (int node = threadIdx.x; node < n; node += EG_NT) {
     double yv[MAXM];
 #pragma unroll
     for (int j = 0; j < MAXM; ++j)
-      if (j < m) yv[j] = Y[(long long)j * n + node];
+      if (j < m) yv[j] = Yin[(long long)j * n + node];
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       if (i < m) {
@@ -994,10 +1011,9 @@ __device__ void ritz_vectors(const double* Y, double* X,
 // step c runs, every thread holds its share of step c+1's record and vector
 // row (Z forward, the forward Y backward) in registers; they are stored to
 // the other LDS slot at the end of the step, so the loads overlap the block
-// GEMM.  The GEMM gives each thread one row i and up to EG_NC columns.
+// GEMM, which gives each thread two rows and four columns.
 constexpr int EG_PFR = (MAXBS * MAXBS + 3 * MAXBS + EG_NT - 1) / EG_NT;   // record regs
 constexpr int EG_PFZ = (MAXBS * MAXM + EG_NT - 1) / EG_NT;               // row regs
-constexpr int EG_NC = 5;                                                 // GEMM columns
 constexpr int EG_RAW = 18176;              // doubles of the kernel's carved LDS
 
 // LDS doubles the sweep needs for bs, m (2 record slots, 2 vector rows,
@@ -1009,9 +1025,8 @@ __host__ __device__ inline int eig_sweep_doubles(int bs, int m) {
 
 // the block size m fits the kernel for rows of bs nodes
 __host__ __device__ inline bool eig_fits(int bs, int m) {
-  const int ngrp = min(EG_NT / bs, m);
-  return m <= MAXM && bs <= MAXBS && eig_sweep_doubles(bs, m) <= EG_RAW &&
-         (m + ngrp - 1) / ngrp <= EG_NC && 2 * MAXM * 64 <= EG_RAW;
+  return m >= 4 && m <= MAXM && bs <= MAXBS && eig_sweep_doubles(bs, m) <= EG_RAW &&
+         ((bs + 1) / 2) * ((m + 3) / 4) <= EG_NT && 2 * MAXM * 64 <= EG_RAW;
 }
 
 // LDS-only workgroup barrier (the register prefetch stays in flight)
@@ -1019,34 +1034,27 @@ __device__ __forceinline__ void eg_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// Per-neighbourhood state of the subspace iteration, kept in device memory
+// between the iteration's kernels.
+struct EigState {
+  int done;                  // converged (or failed): later launches skip it
+  int pad;
+  double theta[MAXM];        // Ritz values of the last Rayleigh-Ritz step
+  double theta_old[MAXM];
+};
+
+size_t eig_state_bytes() { return sizeof(EigState); }
+
+// X = random start block (a counter-based hash of neighbourhood, column and
+// node: the same on every run), zero on Dirichlet nodes; state reset.
 __global__ void __launch_bounds__(EG_NT)
-k_heat_eigen(Geom g, const SysDesc* __restrict__ systems,
-             const double* __restrict__ E, const uint8_t* __restrict__ dflag,
-             const double* __restrict__ Ae, const double* __restrict__ Me,
-             const double* __restrict__ Cel, const double* __restrict__ Sinv,
-             double* __restrict__ Xw, double* __restrict__ Yw,
-             double* __restrict__ Zw, EigParams prm,
-             double* __restrict__ psi_out, double* __restrict__ lam_out,
-             int* __restrict__ nsel_out, int* __restrict__ cap_out,
-             int* __restrict__ err) {
-  __shared__ __align__(16) double raw[EG_RAW];   // sweep rows / gram staging
-  __shared__ double G[MAXM * MAXM];
-  __shared__ double V[MAXM * MAXM];
-  __shared__ double theta[MAXM], theta_old[MAXM];
-  __shared__ double rc[MAXM], rs[MAXM];
-  __shared__ int rp[MAXM], rq[MAXM], order[MAXM];
-  __shared__ int converged;
+k_eig_start(Geom g, const SysDesc* __restrict__ systems,
+            const uint8_t* __restrict__ dflag, double* __restrict__ Xw,
+            int m, EigState* __restrict__ st) {
   const SysDesc s = systems[blockIdx.x];
   const int tid = threadIdx.x;
   const int n = s.nxb * s.nyb;
-  const int bs = s.nxb, nb = s.nyb;
-  const int m = prm.m;
-  const long long wo = s.voff * (long long)m;
-  double* X = Xw + wo;
-  double* Y = Yw + wo;
-  double* Z = Zw + wo;
-  (void)Cel;
-
+  double* X = Xw + s.voff * (long long)m;
   for (int idx = tid; idx < n * m; idx += EG_NT) {
     const int j = idx / n, node = idx - (idx / n) * n;
     const int x = s.x0 + node % s.nxb, y = s.y0 + node / s.nxb;
@@ -1055,203 +1063,265 @@ k_heat_eigen(Geom g, const SysDesc* __restrict__ systems,
         ((unsigned long long)blockIdx.x << 40) ^ ((unsigned long long)j << 24) ^ (unsigned long long)node;
     X[idx] = d ? 0.0 : hash_unit(key);
   }
-  if (tid < MAXM) theta_old[tid] = 0.0;
-  if (tid == 0) converged = 0;
-  __syncthreads();
+  EigState& e = st[blockIdx.x];
+  if (tid == 0) e.done = 0;
+  if (tid < MAXM) e.theta_old[tid] = 0.0;
+}
 
-  // carve the sweep buffers
+// One shift-invert step of every neighbourhood still iterating:
+// Z = M X, then Y = C^{-1} Z by the row sweep.
+__global__ void __launch_bounds__(EG_NT)
+k_eig_sweep(Geom g, const SysDesc* __restrict__ systems,
+            const double* __restrict__ E, const uint8_t* __restrict__ dflag,
+            const double* __restrict__ Me, const double* __restrict__ Sinv,
+            const double* __restrict__ Xw, double* __restrict__ Yw,
+            double* __restrict__ Zw, int m, const EigState* __restrict__ st) {
+  __shared__ __align__(16) double raw[EG_RAW];
+  if (st[blockIdx.x].done) return;
+  const SysDesc s = systems[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int n = s.nxb * s.nyb;
+  const int bs = s.nxb, nb = s.nyb;
+  const long long wo = s.voff * (long long)m;
+  const double* X = Xw + wo;
+  double* Y = Yw + wo;
+  double* Z = Zw + wo;
+  // sweep buffers in LDS, addressed by offsets into raw (so that every
+  // access stays an LDS access): two record slots, two vector rows, the
+  // right-hand side Wl and the result rows T ([a][j], stride m)
   const int rec = bs * bs + 3 * bs;
   const int recp = (rec + 1) & ~1;
-  double* slot[2] = {raw, raw + recp};
-  double* Zs[2] = {raw + 2 * recp, raw + 2 * recp + bs * m};
-  double* Wl = raw + 2 * recp + 2 * bs * m;      // [a][j], stride m
-  double* T = Wl + bs * m;                       // [a][j], stride m
+  const int bm = bs * m;
+  const int o_z = 2 * recp, o_w = 2 * recp + 2 * bm, o_t = o_w + bm;
   const double* recs = Sinv + s.foff;
   const int nsteps = 2 * nb - 1;
-  // GEMM role
-  const int ngrp = min(EG_NT / bs, m);
-  const int gi = tid % bs, gj = tid / bs;
-  const bool gact = gj < ngrp;
-  const int bm = bs * m;
-
-  for (int it = 0; it < prm.maxit; ++it) {
-    // Z = M X
-    omega_stencil(g, s, E, dflag, Me, X, Z, n, m);
-    __syncthreads();
-    // Y = C^{-1} Z
-    {
-      for (int q = tid; q < rec; q += EG_NT) slot[0][q] = recs[q];
-      for (int q = tid; q < bm; q += EG_NT) {
-        const int j = q / bs, a = q - (q / bs) * bs;
-        Zs[0][q] = Z[(long long)j * n + a];
-      }
-      __syncthreads();
-    }
-    for (int c = 0; c < nsteps; ++c) {
-      const bool fwd = c < nb;
-      const int k = c < nb ? c : 2 * nb - 2 - c;
-      const int cur = c & 1;
-      if (c == nb - 1) __syncthreads();    // forward rows of Y visible to the
-                                           // backward prefetch below
-      // prefetch step c+1: record and vector row (Z forward, Y backward)
-      double pr[EG_PFR], pz[EG_PFZ];
-      const bool pf = c + 1 < nsteps;
-      if (pf) {
-        const int k1 = (c + 1) < nb ? c + 1 : 2 * nb - 3 - c;
-        const double* rsrc = recs + (long long)k1 * rec;
+  // GEMM role: row pair gr, column group gc (four columns)
+  const int nrp = (bs + 1) / 2, ncg = (m + 3) / 4;
+  const int gr = tid % nrp, gc = tid / nrp;
+  const bool gact = gc < ncg;
+  // vector-row role: entries q = tid + u * EG_NT, q = j * bs + a
+  int qa[EG_PFZ], qj[EG_PFZ];
 #pragma unroll
-        for (int u = 0; u < EG_PFR; ++u) {
-          const int q = tid + u * EG_NT;
-          pr[u] = q < rec ? rsrc[q] : 0.0;
-        }
-        const double* vsrc = ((c + 1) < nb ? Z : Y) + (long long)k1 * bs;
-#pragma unroll
-        for (int u = 0; u < EG_PFZ; ++u) {
-          const int q = tid + u * EG_NT;
-          const int j = q / bs, a = q - (q / bs) * bs;
-          pz[u] = q < bm ? vsrc[(long long)j * n + a] : 0.0;
-        }
-      }
-      // phase A: right-hand side of the row
-      {
-        const double* F = slot[cur] + bs * bs;            // F(k), forward
-        const double* Fp = slot[cur ^ 1] + bs * bs;       // F(k+1), backward
-        for (int idx = tid; idx < bm; idx += EG_NT) {
-          const int j = idx / bs, a = idx - (idx / bs) * bs;
-          double w;
-          if (fwd) {
-            w = Zs[cur][idx];
-            if (k > 0) {
-#pragma unroll
-              for (int t = 0; t < 3; ++t) {
-                const int b = a + t - 1;
-                if (b >= 0 && b < bs) w -= F[a * 3 + t] * T[b * m + j];
-              }
-            }
-          } else {
-            w = 0.0;
-#pragma unroll
-            for (int t = 0; t < 3; ++t) {
-              const int b = a + t - 1;      // node of row k+1
-              if (b >= 0 && b < bs) w += Fp[b * 3 + (2 - t)] * T[b * m + j];
-            }
-          }
-          Wl[a * m + j] = w;
-        }
-      }
-      eg_barrier();
-      // phase B: rows of C^{-1}: T = S_k^{-1} Wl (backward: Y_k - that)
-      if (gact) {
-        const double* S = slot[cur];
-        double acc[EG_NC];
-#pragma unroll
-        for (int u = 0; u < EG_NC; ++u) acc[u] = 0.0;
-        int b = 0;
-        for (; b + 2 <= bs; b += 2) {
-          const double s0 = S[b * bs + gi], s1 = S[(b + 1) * bs + gi];
-#pragma unroll
-          for (int u = 0; u < EG_NC; ++u) {
-            const int j = gj + u * ngrp;
-            if (j < m) acc[u] += s0 * Wl[b * m + j] + s1 * Wl[(b + 1) * m + j];
-          }
-        }
-        for (; b < bs; ++b) {
-          const double s0 = S[b * bs + gi];
-#pragma unroll
-          for (int u = 0; u < EG_NC; ++u) {
-            const int j = gj + u * ngrp;
-            if (j < m) acc[u] += s0 * Wl[b * m + j];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < EG_NC; ++u) {
-          const int j = gj + u * ngrp;
-          if (j < m) {
-            const double val = fwd ? acc[u] : Zs[cur][j * bs + gi] - acc[u];
-            T[gi * m + j] = val;
-            Y[(long long)j * n + k * bs + gi] = val;
-          }
-        }
-      }
-      if (pf) {
-        double* ds = slot[cur ^ 1];
-#pragma unroll
-        for (int u = 0; u < EG_PFR; ++u) {
-          const int q = tid + u * EG_NT;
-          if (q < rec) ds[q] = pr[u];
-        }
-        double* dz = Zs[cur ^ 1];
-#pragma unroll
-        for (int u = 0; u < EG_PFZ; ++u) {
-          const int q = tid + u * EG_NT;
-          if (q < bm) dz[q] = pz[u];
-        }
-      }
-      eg_barrier();
-    }
-    __syncthreads();
-    const bool do_rr = ((it + 1) % prm.rr_every == 0) || (it + 1 == prm.maxit);
-    // M-orthonormalise Y by Cholesky QR (twice before a Rayleigh-Ritz step)
-    for (int pass = 0; pass < (do_rr ? 2 : 1); ++pass) {
-      omega_stencil(g, s, E, dflag, Me, Y, Z, n, m);
-      __syncthreads();
-      gram(Y, Z, n, m, G, raw);
-      chol_small(G, m, err);
-      apply_linvT(Y, n, m, G);
-    }
-    if (do_rr) {
-      omega_stencil(g, s, E, dflag, Ae, Y, Z, n, m);
-      __syncthreads();
-      gram(Y, Z, n, m, G, raw);
-      jacobi_small(G, V, m, rc, rs, rp, rq);
-      if (tid == 0) {
-        for (int i = 0; i < m; ++i) order[i] = i;
-        for (int i = 1; i < m; ++i) {       // insertion sort by eigenvalue
-          const int oi = order[i];
-          const double key = G[oi * m + oi];
-          int j = i - 1;
-          while (j >= 0 && G[order[j] * m + order[j]] > key) {
-            order[j + 1] = order[j];
-            --j;
-          }
-          order[j + 1] = oi;
-        }
-        // converge the Ritz values that decide the selection: those below
-        // the threshold (at most kmax) and the next one
-        int nbelow = 0;
-        for (int i = 0; i < m; ++i) {
-          theta[i] = G[order[i] * m + order[i]];
-          if (theta[i] < prm.lim) ++nbelow;
-        }
-        const int nchk = min(m - 1, min(nbelow, prm.kmax) + 1);
-        double dmax = 0.0;
-        for (int i = 0; i < nchk; ++i) {
-          const double rel = fabs(theta[i] - theta_old[i]) / (fabs(theta[i]) + prm.lim);
-          dmax = fmax(dmax, rel);
-        }
-        for (int i = 0; i < m; ++i) theta_old[i] = theta[i];
-        converged = (it > 0 && dmax < prm.tol) ? 1 : 0;
-      }
-      __syncthreads();
-      // X = Y V (columns sorted ascending)
-      ritz_vectors(Y, X, V, order, n, m);
-      __syncthreads();
-      if (converged) break;
-    } else {
-      double* t = X; X = Y; Y = t;
-    }
+  for (int u = 0; u < EG_PFZ; ++u) {
+    const int q = tid + u * EG_NT;
+    qj[u] = q < bm ? q / bs : -1;
+    qa[u] = q < bm ? q - (q / bs) * bs : 0;
   }
-  // X holds the Ritz vectors (ascending).  Select lambda < lim, <= kmax.
+
+  omega_stencil(g, s, E, dflag, Me, X, Z, n, m);
+  __syncthreads();
+  // Y = C^{-1} Z
+  for (int q = tid; q < rec; q += EG_NT) raw[q] = recs[q];
+#pragma unroll
+  for (int u = 0; u < EG_PFZ; ++u)
+    if (qj[u] >= 0) raw[o_z + tid + u * EG_NT] = Z[(long long)qj[u] * n + qa[u]];
+  __syncthreads();
+  for (int c = 0; c < nsteps; ++c) {
+    const bool fwd = c < nb;
+    const int k = c < nb ? c : 2 * nb - 2 - c;
+    const int cur = c & 1;
+    const int o_s = cur ? recp : 0, o_sn = cur ? 0 : recp;     // this / other slot
+    const int o_zc = o_z + (cur ? bm : 0), o_zn = o_z + (cur ? 0 : bm);
+    if (c == nb - 1) __syncthreads();    // forward rows of Y visible to the
+                                         // backward prefetch below
+    // prefetch step c+1: record and vector row (Z forward, Y backward)
+    double pr[EG_PFR], pz[EG_PFZ];
+    const bool pf = c + 1 < nsteps;
+    if (pf) {
+      const int k1 = (c + 1) < nb ? c + 1 : 2 * nb - 3 - c;
+      const double* rsrc = recs + (long long)k1 * rec;
+      // unconditional loads at clamped indices (entries past the end are
+      // not stored below)
+#pragma unroll
+      for (int u = 0; u < EG_PFR; ++u) pr[u] = rsrc[min(tid + u * EG_NT, rec - 1)];
+      const double* vsrc = ((c + 1) < nb ? Z : Y) + (long long)k1 * bs;
+#pragma unroll
+      for (int u = 0; u < EG_PFZ; ++u) pz[u] = vsrc[(long long)max(qj[u], 0) * n + qa[u]];
+    }
+    // phase A: right-hand side of the row (forward: F(k) of this record;
+    // backward: F(k+1) of the previous step's record, read transposed)
+    {
+      const int o_f = (fwd ? o_s : o_sn) + bs * bs;
+#pragma unroll
+      for (int u = 0; u < EG_PFZ; ++u) {
+        const int j = qj[u], a = qa[u];
+        if (j < 0) continue;
+        double f[3], tv[3];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const int b = min(max(a + t - 1, 0), bs - 1);
+          const bool ok = (a + t - 1) >= 0 && (a + t - 1) < bs;
+          const double fv = fwd ? raw[o_f + a * 3 + t] : raw[o_f + b * 3 + (2 - t)];
+          f[t] = (ok && (!fwd || k > 0)) ? fv : 0.0;
+          tv[t] = raw[o_t + b * m + j];
+        }
+        const double zv = raw[o_zc + tid + u * EG_NT];
+        double w = fwd ? zv : 0.0;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) w = fwd ? w - f[t] * tv[t] : w + f[t] * tv[t];
+        raw[o_w + a * m + j] = w;
+      }
+    }
+    eg_barrier();
+    // phase B: rows of C^{-1}: T = S_k^{-1} Wl (backward: Y_k - that).
+    // Thread (row pair r, column group cg) forms rows 2r, 2r+1 and columns
+    // 4cg .. 4cg+3 (clamped at the block edge; the extra ones are dropped).
+    if (gact) {
+      double acc[2][4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[a][u] = 0.0;
+      const int i0 = min(2 * gr, bs - 1), i1 = min(2 * gr + 1, bs - 1);
+      const int jc0 = min(4 * gc, m - 4);          // m >= 4 (host check)
+#pragma unroll 4
+      for (int b = 0; b < bs; ++b) {
+        const double s0 = raw[o_s + b * bs + i0], s1 = raw[o_s + b * bs + i1];
+        const double* wr = raw + o_w + b * m + jc0;
+        const double w0 = wr[0], w1 = wr[1], w2 = wr[2], w3 = wr[3];
+        acc[0][0] += s0 * w0; acc[0][1] += s0 * w1; acc[0][2] += s0 * w2; acc[0][3] += s0 * w3;
+        acc[1][0] += s1 * w0; acc[1][1] += s1 * w1; acc[1][2] += s1 * w2; acc[1][3] += s1 * w3;
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int i = 2 * gr + a;
+        if (i >= bs) continue;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = jc0 + u;
+          if (j < 4 * gc) continue;               // column of the previous group
+          const double val = fwd ? acc[a][u] : raw[o_zc + j * bs + i] - acc[a][u];
+          raw[o_t + i * m + j] = val;
+          Y[(long long)j * n + k * bs + i] = val;
+        }
+      }
+    }
+    if (pf) {
+#pragma unroll
+      for (int u = 0; u < EG_PFR; ++u) {
+        const int q = tid + u * EG_NT;
+        if (q < rec) raw[o_sn + q] = pr[u];
+      }
+#pragma unroll
+      for (int u = 0; u < EG_PFZ; ++u)
+        if (qj[u] >= 0) raw[o_zn + tid + u * EG_NT] = pz[u];
+    }
+    eg_barrier();
+  }
+  __syncthreads();
+}
+
+// M-orthonormalise Y by Cholesky QR into X; with rr, orthonormalise again
+// and replace X by the Ritz vectors of the pencil (A, M) on span(X),
+// ascending, then test convergence of the Ritz values that decide the
+// selection (those below the threshold, at most kmax, and the next one).
+__global__ void __launch_bounds__(EG_NT)
+k_eig_orth(Geom g, const SysDesc* __restrict__ systems,
+           const double* __restrict__ E, const uint8_t* __restrict__ dflag,
+           const double* __restrict__ Ae, const double* __restrict__ Me,
+           double* __restrict__ Xw, double* __restrict__ Yw,
+           double* __restrict__ Zw, EigParams prm, int rr, int first_rr,
+           EigState* __restrict__ st, int* __restrict__ err) {
+  __shared__ __align__(16) double raw[2 * MAXM * 64];   // gram staging
+  __shared__ double G[MAXM * MAXM];
+  __shared__ double V[MAXM * MAXM];
+  __shared__ double rc[MAXM], rs[MAXM];
+  __shared__ int rp[MAXM], rq[MAXM], order[MAXM];
+  __shared__ int converged;
+  EigState& es = st[blockIdx.x];
+  if (es.done) return;
+  const SysDesc s = systems[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int n = s.nxb * s.nyb;
+  const int m = prm.m;
+  const long long wo = s.voff * (long long)m;
+  double* X = Xw + wo;
+  double* Y = Yw + wo;
+  double* Z = Zw + wo;
+  // pass 1: X = Y L^-T with L L^T = Y^T M Y
+  omega_stencil(g, s, E, dflag, Me, Y, Z, n, m);
+  __syncthreads();
+  gram(Y, Z, n, m, G, raw);
+  chol_small(G, m, err);
+  apply_linvT(Y, X, n, m, G);
+  if (!rr) return;
+  // pass 2 (in place)
+  omega_stencil(g, s, E, dflag, Me, X, Z, n, m);
+  __syncthreads();
+  gram(X, Z, n, m, G, raw);
+  chol_small(G, m, err);
+  apply_linvT(X, X, n, m, G);
+  // Rayleigh-Ritz with A
+  omega_stencil(g, s, E, dflag, Ae, X, Z, n, m);
+  __syncthreads();
+  gram(X, Z, n, m, G, raw);
+  jacobi_small(G, V, m, rc, rs, rp, rq);
+  if (tid == 0) {
+    for (int i = 0; i < m; ++i) order[i] = i;
+    for (int i = 1; i < m; ++i) {       // insertion sort by eigenvalue
+      const int oi = order[i];
+      const double key = G[oi * m + oi];
+      int j = i - 1;
+      while (j >= 0 && G[order[j] * m + order[j]] > key) {
+        order[j + 1] = order[j];
+        --j;
+      }
+      order[j + 1] = oi;
+    }
+    int nbelow = 0;
+    for (int i = 0; i < m; ++i) {
+      es.theta[i] = G[order[i] * m + order[i]];
+      if (es.theta[i] < prm.lim) ++nbelow;
+    }
+    const int nchk = min(m - 1, min(nbelow, prm.kmax) + 1);
+    double dmax = 0.0;
+    for (int i = 0; i < nchk; ++i) {
+      const double rel = fabs(es.theta[i] - es.theta_old[i]) / (fabs(es.theta[i]) + prm.lim);
+      dmax = fmax(dmax, rel);
+    }
+    for (int i = 0; i < m; ++i) es.theta_old[i] = es.theta[i];
+    converged = (!first_rr && dmax < prm.tol) ? 1 : 0;
+  }
+  __syncthreads();
+  // X = X V (columns sorted ascending), in place node by node
+  ritz_vectors(X, X, V, order, n, m);
+  if (tid == 0 && converged) es.done = 1;
+}
+
+// Number of neighbourhoods still iterating, into *count (one workgroup).
+__global__ void __launch_bounds__(256)
+k_eig_count(const EigState* __restrict__ st, int nsys, int* __restrict__ count) {
+  __shared__ int c;
+  if (threadIdx.x == 0) c = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int i = threadIdx.x; i < nsys; i += 256) mine += st[i].done ? 0 : 1;
+  if (mine) atomicAdd(&c, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) *count = c;
+}
+
+// X holds the Ritz vectors (ascending): select lambda < lim, at most kmax.
+__global__ void __launch_bounds__(EG_NT)
+k_eig_select(const SysDesc* __restrict__ systems, const double* __restrict__ Xw,
+             EigParams prm, const EigState* __restrict__ st,
+             double* __restrict__ psi_out, double* __restrict__ lam_out,
+             int* __restrict__ nsel_out, int* __restrict__ cap_out) {
   __shared__ int nsel;
+  const SysDesc s = systems[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int n = s.nxb * s.nyb;
+  const EigState& es = st[blockIdx.x];
+  const double* X = Xw + s.voff * (long long)prm.m;
   if (tid == 0) {
     int cnt = 0;
-    for (int i = 0; i < m; ++i)
-      if (theta[i] < prm.lim) ++cnt;
+    for (int i = 0; i < prm.m; ++i)
+      if (es.theta[i] < prm.lim) ++cnt;
     nsel = min(cnt, prm.kmax);
     nsel_out[blockIdx.x] = nsel;
     cap_out[blockIdx.x] = (cnt > prm.kmax) ? 1 : 0;
     for (int i = 0; i < prm.kmax; ++i)
-      lam_out[(long long)blockIdx.x * prm.kmax + i] = (i < nsel) ? theta[i] : __builtin_nan("");
+      lam_out[(long long)blockIdx.x * prm.kmax + i] = (i < nsel) ? es.theta[i] : __builtin_nan("");
   }
   __syncthreads();
   double* po = psi_out + s.voff * (long long)prm.kmax;
@@ -1293,15 +1363,33 @@ bool level1_fits(int bs, int nb, bool fp32) {
 
 void launch_heat_eigen(const Geom& g, const SysDesc* sys, int nsys,
                        const double* E, const uint8_t* dflag, const double* Ae,
-                       const double* Me, const double* Cel, const double* Sinv,
-                       double* X, double* Y, double* Z, int m, int kmax,
-                       int maxit, int rr_every, double lim, double tol,
-                       double* psi, double* lam, int* nsel, int* cap, int* err,
-                       hipStream_t s) {
+                       const double* Me, const double* Sinv, double* X,
+                       double* Y, double* Z, int m, int kmax, int maxit,
+                       int rr_every, double lim, double tol, void* state,
+                       int* d_count, int* h_count, double* psi, double* lam,
+                       int* nsel, int* cap, int* err, hipStream_t s) {
   EigParams p{m, kmax, maxit, rr_every, lim, tol};
-  hipLaunchKernelGGL(k_heat_eigen, dim3(nsys), dim3(EG_NT), 0, s, g, sys, E,
-                     dflag, Ae, Me, Cel, Sinv, X, Y, Z, p, psi, lam, nsel, cap,
-                     err);
+  EigState* st = static_cast<EigState*>(state);
+  hipLaunchKernelGGL(k_eig_start, dim3(nsys), dim3(EG_NT), 0, s, g, sys, dflag, X, m, st);
+  bool first_rr = true;
+  for (int it = 0; it < maxit; ++it) {
+    hipLaunchKernelGGL(k_eig_sweep, dim3(nsys), dim3(EG_NT), 0, s, g, sys, E,
+                       dflag, Me, Sinv, X, Y, Z, m, st);
+    const bool rr = ((it + 1) % rr_every == 0) || (it + 1 == maxit);
+    hipLaunchKernelGGL(k_eig_orth, dim3(nsys), dim3(EG_NT), 0, s, g, sys, E,
+                       dflag, Ae, Me, X, Y, Z, p, rr ? 1 : 0, first_rr ? 1 : 0,
+                       st, err);
+    if (rr) {
+      first_rr = false;
+      hipLaunchKernelGGL(k_eig_count, dim3(1), dim3(256), 0, s, st, nsys, d_count);
+      if (hipMemcpyAsync(h_count, d_count, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        break;
+      if (*h_count == 0) break;
+    }
+  }
+  hipLaunchKernelGGL(k_eig_select, dim3(nsys), dim3(EG_NT), 0, s, sys, X, p, st,
+                     psi, lam, nsel, cap);
 }
 
 }  // namespace msp

@@ -48,9 +48,10 @@ void launch_level1(const Geom&, const SysDesc*, int, const uint8_t*,
 bool level1_fits(int bs, int nb, bool fp32);
 void launch_heat_eigen(const Geom&, const SysDesc*, int, const double*,
                        const uint8_t*, const double*, const double*,
-                       const double*, const double*, double*, double*, double*,
-                       int, int, int, int, double, double, double*, double*,
+                       const double*, double*, double*, double*, int, int, int,
+                       int, double, double, void*, int*, int*, double*, double*,
                        int*, int*, int*, hipStream_t);
+size_t eig_state_bytes();
 // k_coarse.hip
 
 void launch_coarse_kphi(const Geom&, const CoarseNode*, const int*, int,
@@ -158,6 +159,7 @@ struct msp_handle {
   double* d_Som = nullptr;
   double *d_X = nullptr, *d_Y = nullptr, *d_Z = nullptr;
   double *d_psi = nullptr, *d_lam = nullptr;
+  void* d_eig_state = nullptr;     // per-neighbourhood subspace-iteration state
   int *d_nsel = nullptr, *d_cap = nullptr;
   CoarseNode* d_cn = nullptr;
   int* d_col_node = nullptr;
@@ -453,7 +455,7 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
                   h->d_K0, h->d_sdiag, h->d_P, h->d_Lp, h->d_Rp, h->d_dropped,
                   h->d_c, h->d_c0, h->d_x, h->d_r, h->d_p0, h->d_p1, h->d_q,
                   h->d_z, h->d_tmp, h->d_sc, h->d_ahist, h->d_bhist,
-                  h->d_part, h->d_cnt, h->d_err};
+                  h->d_part, h->d_cnt, h->d_err, h->d_eig_state};
   for (void* p : bufs) dfree(p);
   for (int k = 0; k < KT_COUNT; ++k)
     for (hipEvent_t e : h->kt[k].ev) (void)hipEventDestroy(e);
@@ -639,13 +641,14 @@ static msp_status ensure_setup_buffers(msp_handle* h) {
   A(dalloc(&h->d_nsel, h->omegas.size()));
   A(dalloc(&h->d_cap, h->omegas.size()));
   A(dalloc(&h->d_cn, h->cn_h.size()));
+  A(hipMalloc(&h->d_eig_state, h->omegas.size() * eig_state_bytes()));
   if (!ok) {
     // leave none of them behind, so that a later setup tries again
     void** bufs[] = {(void**)&h->d_S64, (void**)&h->d_S32, (void**)&h->d_metric,
                      (void**)&h->d_use64, (void**)&h->d_lsol, (void**)&h->d_Som,
                      (void**)&h->d_X, (void**)&h->d_Y, (void**)&h->d_Z,
                      (void**)&h->d_psi, (void**)&h->d_lam, (void**)&h->d_nsel,
-                     (void**)&h->d_cap, (void**)&h->d_cn};
+                     (void**)&h->d_cap, (void**)&h->d_cn, &h->d_eig_state};
     for (void** b : bufs) {
       dfree(*b);
       *b = nullptr;
@@ -720,8 +723,9 @@ extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
                      h->d_dflag, Ce, h->d_Som, h->d_err, s);
   tk = timer_begin(h, KT_EIGEN, s);
   launch_heat_eigen(g, h->d_omegas, (int)h->omegas.size(), h->d_E, h->d_dflag,
-                    Ae, Me, Ce, h->d_Som, h->d_X, h->d_Y, h->d_Z, m, kmax,
+                    Ae, Me, h->d_Som, h->d_X, h->d_Y, h->d_Z, m, kmax,
                     kEigMaxIt, kEigRR, h->desc.eig_tau / (h->H * h->H), kEigTol,
+                    h->d_eig_state, (int*)h->d_cnt + 4, h->h_int + 8,
                     h->d_psi, h->d_lam, h->d_nsel, h->d_cap, h->d_err, s);
   timer_end(h, KT_EIGEN, tk, s);
   HIPCHK(h, hipGetLastError());
