@@ -205,6 +205,40 @@ msp_status msp_kernel_timing(msp_handle* h, int32_t enable,
                              int64_t* launches_host, double* total_ms_host,
                              int32_t n);
 
+/* ---- batches: the PCG solves of many problems in lockstep ---- */
+
+typedef struct msp_batch msp_batch;
+
+/* Create / destroy a batch context (device tables and a captured graph,
+ * reused while the same handles are solved together). */
+msp_status msp_batch_create(msp_batch** out);
+msp_status msp_batch_destroy(msp_batch* b);
+const char* msp_batch_last_error(const msp_batch* b);
+
+/*
+ * Solve problem e = 0..n-1 on its own handle hs[e] (all distinct, densities
+ * set): K_e u_e = f_e to rtol as msp_solve does, with warm[e] (may be NULL)
+ * selecting a warm start from u_e.  Setups run first where the densities
+ * changed.  Every PCG iteration then launches each iteration kernel once
+ * for all problems still iterating (the first-level solves of all of them
+ * in one persistent launch of one workgroup per CU); with use_graph != 0 a
+ * chunk of 16 iterations is captured once as a HIP graph and replayed.
+ * Each problem's arithmetic is that of msp_solve on its handle, so every
+ * result is bitwise the one it would have alone.  infos_host (may be NULL)
+ * receives n statistics records.  A negative status of any entry makes the
+ * call return an error; MSP_NOT_CONVERGED if some entry did not converge.
+ */
+msp_status msp_batch_solve(msp_batch* b, msp_handle* const* handles,
+                           const double* const* f_dev, double* const* u_dev,
+                           const int32_t* warm_host, int32_t n, double rtol,
+                           int32_t maxit, int32_t use_graph, hipStream_t stream,
+                           msp_solve_info* infos_host);
+
+/* Chunks of 16 lockstep iterations run by this batch context, and how many
+ * of them were graph replays. */
+msp_status msp_batch_stats(const msp_batch* b, int64_t* chunks,
+                           int64_t* graph_chunks);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,7 +51,8 @@ EXPORTS = ["msp_create", "msp_destroy", "msp_last_error", "msp_set_densities",
            "msp_setup", "msp_solve", "msp_apply_K", "msp_apply_level1",
            "msp_apply_coarse", "msp_apply_prec", "msp_coarse_info",
            "msp_coarse_basis", "msp_vec_dot", "msp_query",
-           "msp_kernel_timing"]
+           "msp_kernel_timing", "msp_batch_create", "msp_batch_destroy",
+           "msp_batch_last_error", "msp_batch_solve", "msp_batch_stats"]
 
 KERNEL_NAMES = ["level1_apply", "cg_matvec", "heat_eigen", "combine",
                 "coarse_restrict", "local_factor"]
@@ -88,8 +89,16 @@ def load_library(path=LIB_PATH):
                               ctypes.POINTER(ctypes.c_double)]
     L.msp_query.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     L.msp_kernel_timing.argtypes = [vp, i32, vp, vp, i32]
+    L.msp_batch_create.argtypes = [ctypes.POINTER(vp)]
+    L.msp_batch_destroy.argtypes = [vp]
+    L.msp_batch_last_error.argtypes = [vp]
+    L.msp_batch_last_error.restype = ctypes.c_char_p
+    L.msp_batch_solve.argtypes = [vp, vp, vp, vp, vp, i32, dbl, i32, i32, vp,
+                                  ctypes.POINTER(SolveInfo)]
+    L.msp_batch_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTS:
-        if name != "msp_last_error":
+        if name not in ("msp_last_error", "msp_batch_last_error"):
             getattr(L, name).restype = i32
     _lib = L
     return L
@@ -247,6 +256,56 @@ class Solver:
                 "coarse_basis_bytes", "local_vec_entries",
                 "omega_vec_entries", "omega_factor_bytes", "ldk"]
         return dict(zip(keys, [int(v) for v in q]))
+
+
+class Batch:
+    """A batch context: the PCG solves of several Solvers in lockstep."""
+
+    def __init__(self):
+        self.L = load_library()
+        b = ctypes.c_void_p()
+        st = self.L.msp_batch_create(ctypes.byref(b))
+        if st != 0:
+            raise MspError(st, self.L.msp_batch_last_error(None).decode())
+        self.b = b
+
+    def close(self):
+        if getattr(self, "b", None):
+            self.L.msp_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, solvers, fs, us=None, warm=None, rtol=1e-8, maxit=5000,
+              use_graph=True):
+        """Solve solvers[e] with right-hand side fs[e] (device float64
+        tensors); returns (us, infos) like Solver.solve per entry."""
+        import torch
+        n = len(solvers)
+        if us is None:
+            us = [torch.zeros_like(f) for f in fs]
+        H = (ctypes.c_void_p * n)(*[s.h.value for s in solvers])
+        F = (ctypes.c_void_p * n)(*[_ptr(f).value for f in fs])
+        U = (ctypes.c_void_p * n)(*[_ptr(u).value for u in us])
+        W = None
+        if warm is not None:
+            W = (ctypes.c_int32 * n)(*[int(bool(w)) for w in warm])
+        infos = (SolveInfo * n)()
+        st = self.L.msp_batch_solve(self.b, H, F, U, W, n, float(rtol),
+                                    int(maxit), int(bool(use_graph)),
+                                    _stream(), infos)
+        if st not in (0, 1):
+            raise MspError(st, self.L.msp_batch_last_error(self.b).decode())
+        return us, [i.as_dict() for i in infos]
+
+    def stats(self):
+        c, g = ctypes.c_int64(), ctypes.c_int64()
+        self.L.msp_batch_stats(self.b, ctypes.byref(c), ctypes.byref(g))
+        return {"chunks": c.value, "graph_chunks": g.value}
 
 
 def vec_dot(x, y):

@@ -79,4 +79,104 @@ struct Geom {
   double h;
 };
 
+// Arguments of one problem's PCG-iteration kernels.  A single solve passes
+// them by value; a batched launch passes a device table with one entry per
+// problem and a prefix table of workgroup offsets (start[e] .. start[e+1]
+// are problem e's workgroups).
+struct MatvecArgs {
+  Geom g;
+  const double* Ke;
+  const double* E;
+  const uint8_t* mask;
+  const double* xin;         // APPLY: x, CG: z, RESID: x
+  const double* pin;         // CG: p_old
+  double* pout;              // CG: p_new
+  double* yout;              // APPLY: y, CG: q, RESID: r
+  const double* f;           // RESID: f
+  CGScalars* sc;
+  double* part;
+  const double* part_comb;
+  int nb_comb;
+  int ty;                    // node rows per tile (4, 8 or 16)
+  double* beta_hist;
+};
+
+struct UpdateArgs {
+  long long n2;              // nodes (DOF pairs)
+  double* x;
+  double* r;
+  const double* p;
+  const double* q;
+  CGScalars* sc;
+  double* alpha_hist;
+  double* part;
+  const double* part_mv;
+  int nb_mv;
+  const double* part_comb;
+  int nb_comb;
+};
+
+struct Level1Args {
+  Geom g;
+  const SysDesc* sys;
+  const uint8_t* mask;
+  const double* S64;
+  const float* S32;
+  const uint8_t* use64;
+  const double* r;
+  double* lsol;
+  CGScalars* sc;
+  const double* part_upd;
+  int nb_upd;
+  int check;
+};
+
+struct RestrictArgs {
+  Geom g;
+  const CoarseNode* cn;
+  const uint8_t* mask;
+  const double* psi;
+  const double* r;
+  double* cpart;
+  int ldc;
+  double invH;
+  CGScalars* sc;
+  const double* part_upd;
+  int nb_upd;
+  int check;
+};
+
+struct GemvArgs {
+  const double* K0;
+  int ldk, nc;
+  const double* cpart;
+  int ldc;
+  double* c0;
+  const CGScalars* sc;
+};
+
+struct CombineCall {
+  Geom g;
+  CombineArgs ca;
+  const uint8_t* mask;
+  const double* r;
+  const double* q;
+  double* z;
+  CGScalars* sc;
+  double* part;
+};
+
+// Problem of workgroup b in a batched launch: the last e with start[e] <= b
+// (start has nent + 1 entries, start[0] = 0).  Uniform per workgroup.
+__device__ __forceinline__ int batch_entry(const int* __restrict__ start,
+                                           int nent, int b) {
+  int lo = 0, hi = nent - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 }  // namespace msp

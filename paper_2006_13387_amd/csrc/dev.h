@@ -87,11 +87,12 @@ __device__ __forceinline__ int block_read_done(const CGScalars* sc, int* sh) {
 
 // Convergence test after the update x += alpha p, r -= alpha q: every
 // workgroup sums the update kernel's partials of r.r in the same fixed
-// order; workgroup 0 records the outcome.  Returns true when the iteration
-// is over (converged, iteration limit or non-finite residual).
+// order; the leader (the problem's workgroup 0) records the outcome.
+// Returns true when the iteration is over (converged, iteration limit or
+// non-finite residual).
 template <int NT>
 __device__ bool cg_check_done(CGScalars* sc, const double* part_upd, int nb_upd,
-                              double* red, int* sh) {
+                              double* red, int* sh, bool leader) {
   if (block_read_done(sc, sh)) return true;
   const double rr = reduce_partials<NT>(part_upd, nb_upd, 1, red);
   // the decision is taken by thread 0 and broadcast, so that it is uniform
@@ -102,7 +103,7 @@ __device__ bool cg_check_done(CGScalars* sc, const double* part_upd, int nb_upd,
     if (!finite(rr)) d = DONE_BREAKDOWN;
     else if (rr <= sc->tol2 * sc->ff) d = DONE_CONVERGED;
     else if (it1 >= sc->maxit) d = DONE_MAXIT;
-    if (d != DONE_RUNNING && blockIdx.x == 0) {
+    if (d != DONE_RUNNING && leader) {
       sc->rr = rr;
       sc->iter = it1;
       if (d == DONE_BREAKDOWN) sc->status = -5;

@@ -351,31 +351,36 @@ constexpr int RS_CH = 4;       // bands of neighbourhood rows per coarse node
 constexpr int RS_NPT = 8;      // band nodes per thread (band <= RS_NT*RS_NPT)
 constexpr int KMAXD = 24;
 
-__global__ void __launch_bounds__(RS_NT)
-k_restrict(Geom g, const CoarseNode* __restrict__ cnodes,
-           const uint8_t* __restrict__ mask, const double* __restrict__ psi,
-           const double* __restrict__ r, double* __restrict__ cpart, int ldc,
-           double invH, CGScalars* __restrict__ sc,
-           const double* __restrict__ part_upd, int nb_upd, int check) {
-  __shared__ double red[(2 * KMAXD + 1) * (RS_NT / 64)];
-  __shared__ double redc[RS_NT / 64 + 1];
-  __shared__ int shi;
-  if (sc != nullptr) {
-    if (check) {
-      if (cg_check_done<RS_NT>(sc, part_upd, nb_upd, redc, &shi)) return;
-    } else if (block_read_done(sc, &shi)) {
+struct RsLds {
+  double red[(2 * KMAXD + 1) * (RS_NT / 64)];
+  double redc[RS_NT / 64 + 1];
+  int shi;
+};
+
+// Workgroup bid = (coarse node, band): partial restriction of r.
+__device__ __forceinline__ void restrict_body(const RestrictArgs& a, int bid,
+                                              RsLds& L) {
+  const Geom& g = a.g;
+  const uint8_t* __restrict__ mask = a.mask;
+  const double* __restrict__ r = a.r;
+  const double invH = a.invH;
+  double* red = L.red;
+  if (a.sc != nullptr) {
+    if (a.check) {
+      if (cg_check_done<RS_NT>(a.sc, a.part_upd, a.nb_upd, L.redc, &L.shi, bid == 0)) return;
+    } else if (block_read_done(a.sc, &L.shi)) {
       return;
     }
   }
-  const CoarseNode cn = cnodes[blockIdx.x / RS_CH];
-  const int band = blockIdx.x % RS_CH;
+  const CoarseNode cn = a.cn[bid / RS_CH];
+  const int band = bid % RS_CH;
   const int nm = cn.nmodes;
   const int ncol = 2 * nm + cn.nrot;
   if (ncol == 0) return;
   const int nw = cn.nxw * cn.nyw;
   const int r0w = (band * cn.nyw) / RS_CH, r1w = ((band + 1) * cn.nyw) / RS_CH;
   const int lo = r0w * cn.nxw, hi = r1w * cn.nxw;
-  const double* ps = psi + cn.psi_off;
+  const double* ps = a.psi + cn.psi_off;
   // this thread's nodes of the band: masked chi*r in registers first, so
   // that the loads of one mode (below) are independent of each other
   int locs[RS_NPT];
@@ -433,8 +438,21 @@ k_restrict(Geom g, const CoarseNode* __restrict__ cnodes,
     double t = 0.0;
 #pragma unroll
     for (int q = 0; q < RS_NT / 64; ++q) t += red[j * (RS_NT / 64) + q];
-    cpart[(long long)band * ldc + cn.col0 + j] = t;
+    a.cpart[(long long)band * a.ldc + cn.col0 + j] = t;
   }
+}
+
+__global__ void __launch_bounds__(RS_NT) k_restrict(RestrictArgs a) {
+  __shared__ RsLds L;
+  restrict_body(a, blockIdx.x, L);
+}
+
+__global__ void __launch_bounds__(RS_NT)
+k_restrict_batch(const RestrictArgs* __restrict__ tab, const int* __restrict__ start,
+                 int nent) {
+  __shared__ RsLds L;
+  const int e = batch_entry(start, nent, blockIdx.x);
+  restrict_body(tab[e], blockIdx.x - start[e], L);
 }
 
 // c0 = K_0^+ c with c the sum of the restriction's band partials.  Rows of
@@ -446,13 +464,17 @@ constexpr int GV_RPW = 2;                               // rows per wave
 constexpr int GV_ROWS = (GV_NT / 64) * GV_RPW;          // rows per workgroup
 constexpr int GV_MAXC = 12288;
 
-__global__ void __launch_bounds__(GV_NT)
-k_coarse_gemv(const double* __restrict__ K0, int ldk, int nc,
-              const double* __restrict__ cpart, int ldc,
-              double* __restrict__ c0, const CGScalars* __restrict__ sc) {
-  __shared__ double cl[GV_MAXC];
-  __shared__ int shi;
-  if (sc != nullptr && block_read_done(sc, &shi)) return;
+struct GvLds {
+  double cl[GV_MAXC];
+  int shi;
+};
+
+__device__ __forceinline__ void gemv_body(const GemvArgs& a, int bid, GvLds& L) {
+  const double* __restrict__ K0 = a.K0;
+  const int ldk = a.ldk, nc = a.nc, ldc = a.ldc;
+  const double* __restrict__ cpart = a.cpart;
+  double* cl = L.cl;
+  if (a.sc != nullptr && block_read_done(a.sc, &L.shi)) return;
   for (int j = threadIdx.x; j < nc; j += GV_NT) {
     double t = 0.0;
 #pragma unroll
@@ -463,37 +485,55 @@ k_coarse_gemv(const double* __restrict__ K0, int ldk, int nc,
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
   for (int rr = 0; rr < GV_RPW; ++rr) {
-    const int row = blockIdx.x * GV_ROWS + wave * GV_RPW + rr;
+    const int row = bid * GV_ROWS + wave * GV_RPW + rr;
     if (row >= nc) break;
-    const double* a = K0 + (long long)row * ldk;
+    const double* kr = K0 + (long long)row * ldk;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int j = lane;
     for (; j + 192 < nc; j += 256) {
-      s0 += a[j] * cl[j];
-      s1 += a[j + 64] * cl[j + 64];
-      s2 += a[j + 128] * cl[j + 128];
-      s3 += a[j + 192] * cl[j + 192];
+      s0 += kr[j] * cl[j];
+      s1 += kr[j + 64] * cl[j + 64];
+      s2 += kr[j + 128] * cl[j + 128];
+      s3 += kr[j + 192] * cl[j + 192];
     }
-    for (; j < nc; j += 64) s0 += a[j] * cl[j];
+    for (; j < nc; j += 64) s0 += kr[j] * cl[j];
     const double s = wave_sum((s0 + s1) + (s2 + s3));
-    if (lane == 0) c0[row] = s;
+    if (lane == 0) a.c0[row] = s;
   }
+}
+
+__global__ void __launch_bounds__(GV_NT) k_coarse_gemv(GemvArgs a) {
+  __shared__ GvLds L;
+  gemv_body(a, blockIdx.x, L);
+}
+
+__global__ void __launch_bounds__(GV_NT)
+k_coarse_gemv_batch(const GemvArgs* __restrict__ tab, const int* __restrict__ start,
+                    int nent) {
+  __shared__ GvLds L;
+  const int e = batch_entry(start, nent, blockIdx.x);
+  gemv_body(tab[e], blockIdx.x - start[e], L);
 }
 
 // MODE 0: plain apply.  MODE 1 (CG iteration) and 2 (CG start): also the
 // partial sums of r.z and, flexible, z.q per workgroup, read by the next
 // iteration's stiffness and update kernels; in MODE 1 workgroup 0 advances
 // the iteration counter.
+struct CbLds {
+  double red[256 / 64 + 1];
+  int shi;
+};
+
 template <int MODE>
-__global__ void __launch_bounds__(256)
-k_combine(Geom g, CombineArgs ca, const uint8_t* __restrict__ mask,
-          const double* __restrict__ r, const double* __restrict__ q,
-          double* __restrict__ z, CGScalars* __restrict__ sc,
-          double* __restrict__ part) {
-  __shared__ double red[256 / 64 + 1];
-  __shared__ int shi;
-  if (MODE != 0 && block_read_done(sc, &shi)) return;
-  const long long node = (long long)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void combine_body(const CombineCall& a, int bid,
+                                             int nblk, CbLds& L) {
+  const Geom& g = a.g;
+  const CombineArgs& ca = a.ca;
+  const uint8_t* __restrict__ mask = a.mask;
+  CGScalars* sc = a.sc;
+  double* red = L.red;
+  if (MODE != 0 && block_read_done(sc, &L.shi)) return;
+  const long long node = (long long)bid * 256 + threadIdx.x;
   const long long nn = (long long)g.nnx * g.nny;
   double d_rz = 0.0, d_zq = 0.0;
   if (node < nn) {
@@ -566,12 +606,12 @@ k_combine(Geom g, CombineArgs ca, const uint8_t* __restrict__ mask,
     const uchar2 m = reinterpret_cast<const uchar2*>(mask)[node];
     if (m.x) z0 = 0.0;
     if (m.y) z1 = 0.0;
-    reinterpret_cast<double2*>(z)[node] = make_double2(z0, z1);
+    reinterpret_cast<double2*>(a.z)[node] = make_double2(z0, z1);
     if (MODE != 0) {
-      const double2 rv = reinterpret_cast<const double2*>(r)[node];
+      const double2 rv = reinterpret_cast<const double2*>(a.r)[node];
       d_rz = rv.x * z0 + rv.y * z1;
       if (MODE == 1 && sc->flexible) {
-        const double2 qv = reinterpret_cast<const double2*>(q)[node];
+        const double2 qv = reinterpret_cast<const double2*>(a.q)[node];
         d_zq = qv.x * z0 + qv.y * z1;
       }
     }
@@ -580,10 +620,24 @@ k_combine(Geom g, CombineArgs ca, const uint8_t* __restrict__ mask,
   const double s_rz = block_sum<256>(d_rz, red);
   const double s_zq = block_sum<256>(d_zq, red);
   if (threadIdx.x == 0) {
-    part[blockIdx.x] = s_rz;
-    part[gridDim.x + blockIdx.x] = s_zq;
-    if (MODE == 1 && blockIdx.x == 0) sc->iter = sc->iter + 1;
+    a.part[bid] = s_rz;
+    a.part[nblk + bid] = s_zq;
+    if (MODE == 1 && bid == 0) sc->iter = sc->iter + 1;
   }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) k_combine(CombineCall a) {
+  __shared__ CbLds L;
+  combine_body<MODE>(a, blockIdx.x, gridDim.x, L);
+}
+
+__global__ void __launch_bounds__(256)
+k_combine_cg_batch(const CombineCall* __restrict__ tab, const int* __restrict__ start,
+                   int nent) {
+  __shared__ CbLds L;
+  const int e = batch_entry(start, nent, blockIdx.x);
+  combine_body<1>(tab[e], blockIdx.x - start[e], start[e + 1] - start[e], L);
 }
 
 // Dense export of the coarse basis (column-major n x Nc).
@@ -646,44 +700,48 @@ void launch_k0_pinv(double* K0, int ldk, int nc, double* sdiag, double* P,
                      dim3(256), 0, s, K0, ldk, sdiag);
 }
 
-void launch_restrict(const Geom& g, const CoarseNode* cn, int ncn,
-                     const uint8_t* mask, const double* psi, const double* r,
-                     double* cpart, int ldc, double invH, CGScalars* sc,
-                     const double* part_upd, int nb_upd, int check,
-                     hipStream_t s) {
-  hipLaunchKernelGGL(k_restrict, dim3(ncn * RS_CH), dim3(RS_NT), 0, s, g, cn,
-                     mask, psi, r, cpart, ldc, invH, sc, part_upd, nb_upd,
-                     check);
+void launch_restrict(const RestrictArgs& a, int ncn, hipStream_t s) {
+  hipLaunchKernelGGL(k_restrict, dim3(ncn * RS_CH), dim3(RS_NT), 0, s, a);
+}
+
+void launch_restrict_batch(const RestrictArgs* tab, const int* start, int nent,
+                           int total, hipStream_t s) {
+  hipLaunchKernelGGL(k_restrict_batch, dim3(total), dim3(RS_NT), 0, s, tab, start, nent);
 }
 
 int restrict_bands() { return RS_CH; }
 int restrict_max_band_nodes() { return RS_NT * RS_NPT; }
 
-void launch_coarse_gemv(const double* K0, int ldk, int nc, const double* cpart,
-                        int ldc, double* c0, const CGScalars* sc,
-                        hipStream_t s) {
-  if (nc <= 0) return;
-  hipLaunchKernelGGL(k_coarse_gemv, dim3((nc + GV_ROWS - 1) / GV_ROWS),
-                     dim3(GV_NT), 0, s, K0, ldk, nc, cpart, ldc, c0, sc);
+int gemv_blocks(int nc) { return nc > 0 ? (nc + GV_ROWS - 1) / GV_ROWS : 0; }
+
+void launch_coarse_gemv(const GemvArgs& a, hipStream_t s) {
+  if (a.nc <= 0) return;
+  hipLaunchKernelGGL(k_coarse_gemv, dim3(gemv_blocks(a.nc)), dim3(GV_NT), 0, s, a);
+}
+
+void launch_coarse_gemv_batch(const GemvArgs* tab, const int* start, int nent,
+                              int total, hipStream_t s) {
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_coarse_gemv_batch, dim3(total), dim3(GV_NT), 0, s, tab, start, nent);
 }
 
 int combine_blocks(const Geom& g) {
   return (int)(((long long)g.nnx * g.nny + 255) / 256);
 }
 
-void launch_combine(int mode, const Geom& g, const CombineArgs& ca,
-                    const uint8_t* mask, const double* r, const double* q,
-                    double* z, CGScalars* sc, double* part, hipStream_t s) {
-  const dim3 grid(combine_blocks(g));
+void launch_combine(int mode, const CombineCall& a, hipStream_t s) {
+  const dim3 grid(combine_blocks(a.g));
   if (mode == 0)
-    hipLaunchKernelGGL(k_combine<0>, grid, dim3(256), 0, s, g, ca, mask, r, q, z,
-                       sc, part);
+    hipLaunchKernelGGL(k_combine<0>, grid, dim3(256), 0, s, a);
   else if (mode == 1)
-    hipLaunchKernelGGL(k_combine<1>, grid, dim3(256), 0, s, g, ca, mask, r, q, z,
-                       sc, part);
+    hipLaunchKernelGGL(k_combine<1>, grid, dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL(k_combine<2>, grid, dim3(256), 0, s, g, ca, mask, r, q, z,
-                       sc, part);
+    hipLaunchKernelGGL(k_combine<2>, grid, dim3(256), 0, s, a);
+}
+
+void launch_combine_cg_batch(const CombineCall* tab, const int* start, int nent,
+                             int total, hipStream_t s) {
+  hipLaunchKernelGGL(k_combine_cg_batch, dim3(total), dim3(256), 0, s, tab, start, nent);
 }
 
 void launch_export_basis(const Geom& g, const CoarseNode* cn,

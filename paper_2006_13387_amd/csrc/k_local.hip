@@ -650,7 +650,8 @@ __device__ void level1_body(const Geom& g, const SysDesc& s,
     }
     l1_barrier();
   }
-  // retire the row of the last step
+  // retire the row of the last step; the loaders drain their last
+  // (unused) record loads so that no copy into LDS outlives this system
   {
     const int c = nsteps;
     const int kl = l1_block_of_step(c - 1, nb);
@@ -658,6 +659,7 @@ __device__ void level1_body(const Geom& g, const SysDesc& s,
       v[kl * bs + tid] = fin_value(fin_load(kl, (c + 1) & 1, tid), (c - 1) < nb);
     }
   }
+  if (loader) wait_vmcnt(0);
   l1_barrier();
   double* o = lsol + s.voff;
   for (int idx = tid; idx < nb * bs; idx += AP_NT) o[idx] = (double)v[idx];
@@ -667,28 +669,51 @@ __device__ void level1_body(const Geom& g, const SysDesc& s,
 // else its FP32 copy (applied and accumulated in FP32).  With sc given,
 // every workgroup first runs the CG convergence test on the update
 // kernel's partials (check = 1) or reads the done word (check = 0).
-__global__ void __launch_bounds__(AP_NT)
-k_level1(Geom g, const SysDesc* __restrict__ systems,
-         const uint8_t* __restrict__ mask, const double* __restrict__ S64,
-         const float* __restrict__ S32, const uint8_t* __restrict__ use64,
-         const double* __restrict__ r, double* __restrict__ lsol,
-         CGScalars* __restrict__ sc, const double* __restrict__ part_upd,
-         int nb_upd, int check) {
-  __shared__ __align__(1024) unsigned char lds[L1_LDS];
-  __shared__ double red[AP_NT / 64 + 1];
-  __shared__ int shi;
-  if (sc != nullptr) {
-    if (check) {
-      if (cg_check_done<AP_NT>(sc, part_upd, nb_upd, red, &shi)) return;
-    } else if (block_read_done(sc, &shi)) {
+struct L1Shared {
+  double red[AP_NT / 64 + 1];
+  int shi;
+};
+
+// First-level solve of system bid of one problem.  With a.sc set, the CG
+// convergence test on the update kernel's partials (check = 1) or the done
+// word (check = 0) comes first.
+__device__ __forceinline__ void level1_item(const Level1Args& a, int bid,
+                                            unsigned char* lds, L1Shared& L) {
+  if (a.sc != nullptr) {
+    if (a.check) {
+      if (cg_check_done<AP_NT>(a.sc, a.part_upd, a.nb_upd, L.red, &L.shi, bid == 0)) return;
+    } else if (block_read_done(a.sc, &L.shi)) {
       return;
     }
   }
-  const SysDesc s = systems[blockIdx.x];
-  if (S32 == nullptr || use64 == nullptr || use64[blockIdx.x])
-    level1_body<double>(g, s, mask, S64, r, lsol, lds);
+  const SysDesc s = a.sys[bid];
+  if (a.S32 == nullptr || a.use64 == nullptr || a.use64[bid])
+    level1_body<double>(a.g, s, a.mask, a.S64, a.r, a.lsol, lds);
   else
-    level1_body<float>(g, s, mask, S32, r, lsol, lds);
+    level1_body<float>(a.g, s, a.mask, a.S32, a.r, a.lsol, lds);
+}
+
+// use64[i] != 0 (or use64 == null) selects the FP64 records of system i,
+// else its FP32 copy (applied and accumulated in FP32).
+__global__ void __launch_bounds__(AP_NT) k_level1(Level1Args a) {
+  __shared__ __align__(1024) unsigned char lds[L1_LDS];
+  __shared__ L1Shared L;
+  level1_item(a, blockIdx.x, lds, L);
+}
+
+// The first-level solves of several problems in one persistent launch:
+// workgroup w takes systems w, w + grid, w + 2 grid, ... of the concatenated
+// list (problem by problem), so a grid of a few per CU covers any batch.
+__global__ void __launch_bounds__(AP_NT)
+k_level1_batch(const Level1Args* __restrict__ tab, const int* __restrict__ start,
+               int nent, int total) {
+  __shared__ __align__(1024) unsigned char lds[L1_LDS];
+  __shared__ L1Shared L;
+  for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+    const int e = batch_entry(start, nent, vb);
+    level1_item(tab[e], vb - start[e], lds, L);
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------
@@ -1346,13 +1371,14 @@ void launch_factor_heat(const Geom& g, const SysDesc* sys, int nsys,
                      dflag, Cel, out, (float*)nullptr, (double*)nullptr, err);
 }
 
-void launch_level1(const Geom& g, const SysDesc* sys, int nsys,
-                   const uint8_t* mask, const double* S64, const float* S32,
-                   const uint8_t* use64, const double* r, double* lsol,
-                   CGScalars* sc, const double* part_upd, int nb_upd, int check,
-                   hipStream_t s) {
-  hipLaunchKernelGGL(k_level1, dim3(nsys), dim3(AP_NT), 0, s, g, sys, mask, S64,
-                     S32, use64, r, lsol, sc, part_upd, nb_upd, check);
+void launch_level1(const Level1Args& a, int nsys, hipStream_t s) {
+  hipLaunchKernelGGL(k_level1, dim3(nsys), dim3(AP_NT), 0, s, a);
+}
+
+void launch_level1_batch(const Level1Args* tab, const int* start, int nent,
+                         int total, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_level1_batch, dim3(grid), dim3(AP_NT), 0, s, tab, start,
+                     nent, total);
 }
 
 bool eig_fits_host(int bs, int m) { return eig_fits(bs, m); }

@@ -3,18 +3,20 @@
 //
 // Stiffness product (paper Section 1.1: K = sum_e E_e P_e^T K^_e P_e with
 // the SIMP modulus E_e): node-centric gather, so every output is written
-// once and no atomics are needed.  A 64 x 4 tile of nodes stages its
+// once and no atomics are needed.  A tile of 64 x TY nodes stages its
 // displacements (one-node halo) and the surrounding element moduli in LDS;
 // each thread then sums the contributions of the four elements that share
-// its node.  Rows of clamped DOFs are zero.
+// its node.  Rows of clamped DOFs are zero.  The tile height (4, 8 or 16
+// node rows, 256 threads) is chosen per mesh by a short timing at the first
+// densities: taller tiles re-read fewer halo nodes and moduli.
 #include "common.h"
 #include "dev.h"
 
 namespace msp {
 
-constexpr int MV_TX = 64;
-constexpr int MV_TY = 4;
-constexpr int MV_NT = MV_TX * MV_TY;
+constexpr int MV_TX = 64;        // nodes per tile row
+constexpr int MV_NT = 256;       // threads: tile rows are processed 4 at a time
+constexpr int MV_TYMAX = 16;     // tallest tile (rows of nodes)
 
 enum : int { MV_APPLY = 0, MV_CG = 1, MV_RESID = 2 };
 
@@ -32,155 +34,183 @@ k_simp(const double* __restrict__ rho, double* __restrict__ E, int n,
   E[i] = Emin + pow(r, penal) * (E0 - Emin);
 }
 
+// LDS of one stiffness-product tile (sized for the tallest tile)
+struct MvLds {
+  double2 xs[(MV_TYMAX + 2) * (MV_TX + 2)];
+  double es[(MV_TYMAX + 1) * (MV_TX + 1)];
+  double ks[64];
+  double red[MV_NT / 64 + 1];
+  int shi;
+  double beta;
+};
+
+// Tile (bx, by) of a gx x gy grid of 64 x TY node tiles.
 // MODE MV_APPLY : y = K x with x treated as 0 at clamped DOFs.
 // MODE MV_CG    : p_new = z + beta p_old, q = K p_new, partial sums of
 //                 p_new.q.  beta comes from the previous combine kernel's
 //                 partials of r.z (and z.q), summed here by every
 //                 workgroup in the same order: Fletcher-Reeves
 //                 (r.z)_new/(r.z)_old, or, flexible, Polak-Ribiere
-//                 -alpha (z.q)/(r.z)_old.  Workgroup 0 records beta.
+//                 -alpha (z.q)/(r.z)_old.  Tile 0 records beta.
 //                 p_old and p_new are different buffers: neighbouring tiles
 //                 read p_old in their halos while this tile writes p_new.
 // MODE MV_RESID : r = f - K x (x is already 0 at clamped DOFs); partial
 //                 sums of r.r, f.f and f.x over free DOFs.
-template <int MODE>
-__global__ void __launch_bounds__(MV_NT)
-k_matvec(Geom g, const double* __restrict__ Ke, const double* __restrict__ E,
-         const uint8_t* __restrict__ mask,
-         const double* __restrict__ xin,     // APPLY: x, CG: z, RESID: x
-         const double* __restrict__ pin,     // CG: p_old
-         double* __restrict__ pout,          // CG: p_new
-         double* __restrict__ yout,          // APPLY: y, CG: q, RESID: r
-         const double* __restrict__ f,       // RESID: f
-         CGScalars* __restrict__ sc, double* __restrict__ part,
-         const double* __restrict__ part_comb, int nb_comb,
-         double* __restrict__ beta_hist) {
-  __shared__ double2 xs[(MV_TY + 2) * (MV_TX + 2)];
-  __shared__ double es[(MV_TY + 1) * (MV_TX + 1)];
-  __shared__ double ks[64];
-  __shared__ double red[MV_NT / 64 + 1];
-  __shared__ int shi;
-  __shared__ double sh_beta;
-
+template <int MODE, int TY>
+__device__ __forceinline__ void matvec_body(const MatvecArgs& a, int bx, int by,
+                                            int gx, int gy, MvLds& L) {
+  static_assert(TY % 4 == 0 && TY <= MV_TYMAX, "tile height");
+  constexpr int RPT = TY / 4;                // rows per thread
+  const Geom& g = a.g;
   const int tid = threadIdx.x;
   double beta = 0.0;
   if (MODE == MV_CG) {
-    if (block_read_done(sc, &shi)) return;
-    const int it = sc->iter;                 // not written by this kernel
+    if (block_read_done(a.sc, &L.shi)) return;
+    const int it = a.sc->iter;               // not written by this kernel
     if (it > 0) {
-      const double rz = reduce_partials<MV_NT>(part_comb, nb_comb, 1, red);
-      const double zq = sc->flexible ? reduce_partials<MV_NT>(part_comb + nb_comb, nb_comb, 1, red) : 0.0;
+      const double rz = reduce_partials<MV_NT>(a.part_comb, a.nb_comb, 1, L.red);
+      const double zq = a.sc->flexible ? reduce_partials<MV_NT>(a.part_comb + a.nb_comb, a.nb_comb, 1, L.red) : 0.0;
       if (tid == 0) {
-        const double b = sc->flexible ? (-sc->alpha * zq / sc->rz) : (rz / sc->rz);
-        sh_beta = b;
-        if (blockIdx.x == 0 && blockIdx.y == 0) {
-          sc->beta = b;
-          if (it <= sc->maxit) beta_hist[it - 1] = b;
+        const double b = a.sc->flexible ? (-a.sc->alpha * zq / a.sc->rz) : (rz / a.sc->rz);
+        L.beta = b;
+        if (bx == 0 && by == 0) {
+          a.sc->beta = b;
+          if (it <= a.sc->maxit) a.beta_hist[it - 1] = b;
           if (!finite(b)) {
-            sc->status = -5;
-            __hip_atomic_store(&sc->done, (int)DONE_BREAKDOWN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            a.sc->status = -5;
+            __hip_atomic_store(&a.sc->done, (int)DONE_BREAKDOWN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
         }
       }
       __syncthreads();
-      beta = sh_beta;
+      beta = L.beta;
       if (!finite(beta)) return;
     }
   }
-  const int bx0 = blockIdx.x * MV_TX - 1;   // node x of xs column 0
-  const int by0 = blockIdx.y * MV_TY - 1;
-  if (tid < 64) ks[tid] = Ke[tid];
+  const int bx0 = bx * MV_TX - 1;   // node x of xs column 0
+  const int by0 = by * TY - 1;
+  if (tid < 64) L.ks[tid] = a.Ke[tid];
 
-  for (int t = tid; t < (MV_TY + 2) * (MV_TX + 2); t += MV_NT) {
+  for (int t = tid; t < (TY + 2) * (MV_TX + 2); t += MV_NT) {
     const int ii = t % (MV_TX + 2), jj = t / (MV_TX + 2);
     const int x = bx0 + ii, y = by0 + jj;
     double2 v = make_double2(0.0, 0.0);
     if (x >= 0 && x < g.nnx && y >= 0 && y < g.nny) {
       const long long node = (long long)y * g.nnx + x;
-      const double2 a = reinterpret_cast<const double2*>(xin)[node];
+      const double2 u = reinterpret_cast<const double2*>(a.xin)[node];
       if (MODE == MV_CG) {
-        const double2 po = reinterpret_cast<const double2*>(pin)[node];
-        v = make_double2(a.x + beta * po.x, a.y + beta * po.y);
+        const double2 po = reinterpret_cast<const double2*>(a.pin)[node];
+        v = make_double2(u.x + beta * po.x, u.y + beta * po.y);
       } else if (MODE == MV_APPLY) {
-        const uchar2 m = reinterpret_cast<const uchar2*>(mask)[node];
-        v = make_double2(m.x ? 0.0 : a.x, m.y ? 0.0 : a.y);
+        const uchar2 m = reinterpret_cast<const uchar2*>(a.mask)[node];
+        v = make_double2(m.x ? 0.0 : u.x, m.y ? 0.0 : u.y);
       } else {
-        v = a;
+        v = u;
       }
     }
-    xs[t] = v;
+    L.xs[t] = v;
   }
-  for (int t = tid; t < (MV_TY + 1) * (MV_TX + 1); t += MV_NT) {
+  for (int t = tid; t < (TY + 1) * (MV_TX + 1); t += MV_NT) {
     const int ii = t % (MV_TX + 1), jj = t / (MV_TX + 1);
     const int ex = bx0 + ii, ey = by0 + jj;
     double v = 0.0;
-    if (ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny) v = E[(long long)ey * g.nx + ex];
-    es[t] = v;
+    if (ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny) v = a.E[(long long)ey * g.nx + ex];
+    L.es[t] = v;
   }
   __syncthreads();
 
-  const int i = tid % MV_TX, j = tid / MV_TX;
-  const int x = blockIdx.x * MV_TX + i, y = blockIdx.y * MV_TY + j;
-  const bool own = (x < g.nnx && y < g.nny);
-  double y0 = 0.0, y1 = 0.0;
-#pragma unroll
-  for (int dy = 0; dy < 2; ++dy) {
-#pragma unroll
-    for (int dx = 0; dx < 2; ++dx) {
-      const double ee = es[(j + dy) * (MV_TX + 1) + (i + dx)];
-      const int a = (1 - dx) + 2 * (1 - dy);
-      double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const double2 u = xs[(j + dy + (b >> 1)) * (MV_TX + 2) + (i + dx + (b & 1))];
-        s0 += ks[(2 * a) * 8 + 2 * b] * u.x + ks[(2 * a) * 8 + 2 * b + 1] * u.y;
-        s1 += ks[(2 * a + 1) * 8 + 2 * b] * u.x + ks[(2 * a + 1) * 8 + 2 * b + 1] * u.y;
-      }
-      y0 += ee * s0;
-      y1 += ee * s1;
-    }
-  }
-
+  const int i = tid % MV_TX;
   double d0 = 0.0, d1 = 0.0, d2 = 0.0;
-  if (own) {
-    const long long node = (long long)y * g.nnx + x;
-    const uchar2 m = reinterpret_cast<const uchar2*>(mask)[node];
-    if (m.x) y0 = 0.0;
-    if (m.y) y1 = 0.0;
-    if (MODE == MV_APPLY) {
-      reinterpret_cast<double2*>(yout)[node] = make_double2(y0, y1);
-    } else if (MODE == MV_CG) {
-      const double2 pn = xs[(j + 1) * (MV_TX + 2) + (i + 1)];
-      reinterpret_cast<double2*>(pout)[node] = pn;
-      reinterpret_cast<double2*>(yout)[node] = make_double2(y0, y1);
-      d0 = pn.x * y0 + pn.y * y1;
-    } else {
-      const double2 ff = reinterpret_cast<const double2*>(f)[node];
-      const double f0 = m.x ? 0.0 : ff.x, f1 = m.y ? 0.0 : ff.y;
-      const double r0 = m.x ? 0.0 : f0 - y0, r1 = m.y ? 0.0 : f1 - y1;
-      reinterpret_cast<double2*>(yout)[node] = make_double2(r0, r1);
-      const double2 xx = xs[(j + 1) * (MV_TX + 2) + (i + 1)];
-      d0 = r0 * r0 + r1 * r1;
-      d1 = f0 * f0 + f1 * f1;
-      d2 = f0 * xx.x + f1 * xx.y;
+#pragma unroll
+  for (int rr = 0; rr < RPT; ++rr) {
+    const int j = tid / MV_TX + 4 * rr;
+    const int x = bx * MV_TX + i, y = by * TY + j;
+    const bool own = (x < g.nnx && y < g.nny);
+    double y0 = 0.0, y1 = 0.0;
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy) {
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) {
+        const double ee = L.es[(j + dy) * (MV_TX + 1) + (i + dx)];
+        const int av = (1 - dx) + 2 * (1 - dy);
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const double2 u = L.xs[(j + dy + (b >> 1)) * (MV_TX + 2) + (i + dx + (b & 1))];
+          s0 += L.ks[(2 * av) * 8 + 2 * b] * u.x + L.ks[(2 * av) * 8 + 2 * b + 1] * u.y;
+          s1 += L.ks[(2 * av + 1) * 8 + 2 * b] * u.x + L.ks[(2 * av + 1) * 8 + 2 * b + 1] * u.y;
+        }
+        y0 += ee * s0;
+        y1 += ee * s1;
+      }
+    }
+    if (own) {
+      const long long node = (long long)y * g.nnx + x;
+      const uchar2 m = reinterpret_cast<const uchar2*>(a.mask)[node];
+      if (m.x) y0 = 0.0;
+      if (m.y) y1 = 0.0;
+      if (MODE == MV_APPLY) {
+        reinterpret_cast<double2*>(a.yout)[node] = make_double2(y0, y1);
+      } else if (MODE == MV_CG) {
+        const double2 pn = L.xs[(j + 1) * (MV_TX + 2) + (i + 1)];
+        reinterpret_cast<double2*>(a.pout)[node] = pn;
+        reinterpret_cast<double2*>(a.yout)[node] = make_double2(y0, y1);
+        d0 += pn.x * y0 + pn.y * y1;
+      } else {
+        const double2 ff = reinterpret_cast<const double2*>(a.f)[node];
+        const double f0 = m.x ? 0.0 : ff.x, f1 = m.y ? 0.0 : ff.y;
+        const double r0 = m.x ? 0.0 : f0 - y0, r1 = m.y ? 0.0 : f1 - y1;
+        reinterpret_cast<double2*>(a.yout)[node] = make_double2(r0, r1);
+        const double2 xx = L.xs[(j + 1) * (MV_TX + 2) + (i + 1)];
+        d0 += r0 * r0 + r1 * r1;
+        d1 += f0 * f0 + f1 * f1;
+        d2 += f0 * xx.x + f1 * xx.y;
+      }
     }
   }
   if (MODE == MV_APPLY) return;
 
-  const unsigned int nb = gridDim.x * gridDim.y;
-  const unsigned int bid = blockIdx.y * gridDim.x + blockIdx.x;
-  const double s0 = block_sum<MV_NT>(d0, red);
+  const int nb = gx * gy;
+  const int bid = by * gx + bx;
+  const double s0 = block_sum<MV_NT>(d0, L.red);
   if (MODE == MV_CG) {
-    if (tid == 0) part[bid] = s0;
+    if (tid == 0) a.part[bid] = s0;
   } else {
-    const double s1 = block_sum<MV_NT>(d1, red);
-    const double s2 = block_sum<MV_NT>(d2, red);
+    const double s1 = block_sum<MV_NT>(d1, L.red);
+    const double s2 = block_sum<MV_NT>(d2, L.red);
     if (tid == 0) {
-      part[bid] = s0;
-      part[nb + bid] = s1;
-      part[2 * nb + bid] = s2;
+      a.part[bid] = s0;
+      a.part[nb + bid] = s1;
+      a.part[2 * nb + bid] = s2;
     }
   }
+}
+
+template <int MODE>
+__device__ __forceinline__ void matvec_dispatch(const MatvecArgs& a, int bx,
+                                                int by, int gx, int gy, MvLds& L) {
+  if (a.ty == 4) matvec_body<MODE, 4>(a, bx, by, gx, gy, L);
+  else if (a.ty == 8) matvec_body<MODE, 8>(a, bx, by, gx, gy, L);
+  else matvec_body<MODE, 16>(a, bx, by, gx, gy, L);
+}
+
+template <int MODE, int TY>
+__global__ void __launch_bounds__(MV_NT) k_matvec(MatvecArgs a) {
+  __shared__ MvLds L;
+  matvec_body<MODE, TY>(a, blockIdx.x, blockIdx.y, gridDim.x, gridDim.y, L);
+}
+
+// The CG stiffness products of several problems in one launch.
+__global__ void __launch_bounds__(MV_NT)
+k_matvec_cg_batch(const MatvecArgs* __restrict__ tab, const int* __restrict__ start,
+                  int nent) {
+  __shared__ MvLds L;
+  const int e = batch_entry(start, nent, blockIdx.x);
+  const MatvecArgs a = tab[e];
+  const int gx = (a.g.nnx + MV_TX - 1) / MV_TX;
+  const int gy = (a.g.nny + a.ty - 1) / a.ty;
+  const int lb = blockIdx.x - start[e];
+  matvec_dispatch<MV_CG>(a, lb % gx, lb / gx, gx, gy, L);
 }
 
 // One workgroup: sum the residual kernel's partials (r.r, f.f, f.x).
@@ -206,57 +236,68 @@ k_resid_finish(CGScalars* __restrict__ sc, const double* __restrict__ part,
   }
 }
 
+struct UpLds {
+  double red[256 / 64 + 1];
+  int shi;
+  double alpha;
+};
+
 // x += alpha p ; r -= alpha q ; partial sums of r.r.  alpha = (r.z)/(p.q)
 // from the partials of the combine and stiffness kernels, summed by every
 // workgroup in the same order; workgroup 0 records alpha and r.z.
-__global__ void __launch_bounds__(256)
-k_update(long long n2, double* __restrict__ x, double* __restrict__ r,
-         const double* __restrict__ p, const double* __restrict__ q,
-         CGScalars* __restrict__ sc, double* __restrict__ alpha_hist,
-         double* __restrict__ part, const double* __restrict__ part_mv,
-         int nb_mv, const double* __restrict__ part_comb, int nb_comb) {
-  __shared__ double red[256 / 64 + 1];
-  __shared__ int shi;
-  __shared__ double sh_alpha;
-  if (block_read_done(sc, &shi)) return;
-  const double pq = reduce_partials<256>(part_mv, nb_mv, 1, red);
-  const double rz = reduce_partials<256>(part_comb, nb_comb, 1, red);
+__device__ __forceinline__ void update_body(const UpdateArgs& a, int bid, UpLds& L) {
+  if (block_read_done(a.sc, &L.shi)) return;
+  const double pq = reduce_partials<256>(a.part_mv, a.nb_mv, 1, L.red);
+  const double rz = reduce_partials<256>(a.part_comb, a.nb_comb, 1, L.red);
   if (threadIdx.x == 0) {
     const bool bad = !(pq > 0.0) || !finite(pq) || !finite(rz);
     const double alpha = bad ? 0.0 : rz / pq;
-    sh_alpha = bad ? __builtin_nan("") : alpha;
-    if (blockIdx.x == 0) {
-      const int it = sc->iter;
-      sc->pq = pq;
-      sc->alpha = alpha;
-      sc->rz = rz;
-      if (it < sc->maxit) alpha_hist[it] = alpha;
+    L.alpha = bad ? __builtin_nan("") : alpha;
+    if (bid == 0) {
+      const int it = a.sc->iter;
+      a.sc->pq = pq;
+      a.sc->alpha = alpha;
+      a.sc->rz = rz;
+      if (it < a.sc->maxit) a.alpha_hist[it] = alpha;
       if (bad) {
-        sc->status = -5;
-        __hip_atomic_store(&sc->done, (int)DONE_BREAKDOWN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a.sc->status = -5;
+        __hip_atomic_store(&a.sc->done, (int)DONE_BREAKDOWN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
   }
   __syncthreads();
-  const double alpha = sh_alpha;
+  const double alpha = L.alpha;
   if (!finite(alpha)) return;
   double acc = 0.0;
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (i < n2) {
-    double2 xx = reinterpret_cast<double2*>(x)[i];
-    double2 rr = reinterpret_cast<double2*>(r)[i];
-    const double2 pp = reinterpret_cast<const double2*>(p)[i];
-    const double2 qq = reinterpret_cast<const double2*>(q)[i];
+  const long long i = (long long)bid * 256 + threadIdx.x;
+  if (i < a.n2) {
+    double2 xx = reinterpret_cast<double2*>(a.x)[i];
+    double2 rr = reinterpret_cast<double2*>(a.r)[i];
+    const double2 pp = reinterpret_cast<const double2*>(a.p)[i];
+    const double2 qq = reinterpret_cast<const double2*>(a.q)[i];
     xx.x += alpha * pp.x;
     xx.y += alpha * pp.y;
     rr.x -= alpha * qq.x;
     rr.y -= alpha * qq.y;
-    reinterpret_cast<double2*>(x)[i] = xx;
-    reinterpret_cast<double2*>(r)[i] = rr;
+    reinterpret_cast<double2*>(a.x)[i] = xx;
+    reinterpret_cast<double2*>(a.r)[i] = rr;
     acc = rr.x * rr.x + rr.y * rr.y;
   }
-  const double s = block_sum<256>(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  const double s = block_sum<256>(acc, L.red);
+  if (threadIdx.x == 0) a.part[bid] = s;
+}
+
+__global__ void __launch_bounds__(256) k_update(UpdateArgs a) {
+  __shared__ UpLds L;
+  update_body(a, blockIdx.x, L);
+}
+
+__global__ void __launch_bounds__(256)
+k_update_batch(const UpdateArgs* __restrict__ tab, const int* __restrict__ start,
+               int nent) {
+  __shared__ UpLds L;
+  const int e = batch_entry(start, nent, blockIdx.x);
+  update_body(tab[e], blockIdx.x - start[e], L);
 }
 
 __global__ void __launch_bounds__(256)
@@ -298,55 +339,114 @@ void launch_simp(const double* rho, double* E, int n, double E0, double Emin,
                      E0, Emin, penal, err);
 }
 
-static dim3 mv_grid(const Geom& g) {
-  return dim3((g.nnx + MV_TX - 1) / MV_TX, (g.nny + MV_TY - 1) / MV_TY);
+static dim3 mv_grid(const Geom& g, int ty) {
+  return dim3((g.nnx + MV_TX - 1) / MV_TX, (g.nny + ty - 1) / ty);
 }
 
-int matvec_blocks(const Geom& g) {
-  const dim3 gr = mv_grid(g);
+int matvec_blocks(const Geom& g, int ty) {
+  const dim3 gr = mv_grid(g, ty);
   return gr.x * gr.y;
 }
 
-void launch_apply_K(const Geom& g, const double* Ke, const double* E,
+template <int MODE>
+static void launch_mv(const MatvecArgs& a, hipStream_t s) {
+  const dim3 gr = mv_grid(a.g, a.ty);
+  if (a.ty == 4) hipLaunchKernelGGL((k_matvec<MODE, 4>), gr, dim3(MV_NT), 0, s, a);
+  else if (a.ty == 8) hipLaunchKernelGGL((k_matvec<MODE, 8>), gr, dim3(MV_NT), 0, s, a);
+  else hipLaunchKernelGGL((k_matvec<MODE, 16>), gr, dim3(MV_NT), 0, s, a);
+}
+
+static MatvecArgs mv_args(const Geom& g, int ty, const double* Ke, const double* E,
+                          const uint8_t* mask) {
+  MatvecArgs a{};
+  a.g = g;
+  a.ty = ty;
+  a.Ke = Ke;
+  a.E = E;
+  a.mask = mask;
+  return a;
+}
+
+void launch_apply_K(const Geom& g, int ty, const double* Ke, const double* E,
                     const uint8_t* mask, const double* x, double* y,
                     hipStream_t s) {
-  hipLaunchKernelGGL(k_matvec<MV_APPLY>, mv_grid(g), dim3(MV_NT), 0, s, g, Ke,
-                     E, mask, x, (const double*)nullptr, (double*)nullptr, y,
-                     (const double*)nullptr, (CGScalars*)nullptr,
-                     (double*)nullptr, (const double*)nullptr, 0,
-                     (double*)nullptr);
+  MatvecArgs a = mv_args(g, ty, Ke, E, mask);
+  a.xin = x;
+  a.yout = y;
+  launch_mv<MV_APPLY>(a, s);
 }
 
-void launch_cg_matvec(const Geom& g, const double* Ke, const double* E,
-                      const uint8_t* mask, const double* z, const double* p_old,
-                      double* p_new, double* q, CGScalars* sc, double* part_mv,
-                      const double* part_comb, int nb_comb, double* beta_hist,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(k_matvec<MV_CG>, mv_grid(g), dim3(MV_NT), 0, s, g, Ke, E,
-                     mask, z, p_old, p_new, q, (const double*)nullptr, sc,
-                     part_mv, part_comb, nb_comb, beta_hist);
+MatvecArgs cg_matvec_args(const Geom& g, int ty, const double* Ke,
+                          const double* E, const uint8_t* mask, const double* z,
+                          const double* p_old, double* p_new, double* q,
+                          CGScalars* sc, double* part_mv,
+                          const double* part_comb, int nb_comb,
+                          double* beta_hist) {
+  MatvecArgs a = mv_args(g, ty, Ke, E, mask);
+  a.xin = z;
+  a.pin = p_old;
+  a.pout = p_new;
+  a.yout = q;
+  a.sc = sc;
+  a.part = part_mv;
+  a.part_comb = part_comb;
+  a.nb_comb = nb_comb;
+  a.beta_hist = beta_hist;
+  return a;
 }
 
-void launch_residual(const Geom& g, const double* Ke, const double* E,
+void launch_cg_matvec(const MatvecArgs& a, hipStream_t s) { launch_mv<MV_CG>(a, s); }
+
+void launch_cg_matvec_batch(const MatvecArgs* tab, const int* start, int nent,
+                            int total, hipStream_t s) {
+  hipLaunchKernelGGL(k_matvec_cg_batch, dim3(total), dim3(MV_NT), 0, s, tab,
+                     start, nent);
+}
+
+void launch_residual(const Geom& g, int ty, const double* Ke, const double* E,
                      const uint8_t* mask, const double* x, const double* f,
                      double* r, CGScalars* sc, double* part, int slot,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_matvec<MV_RESID>, mv_grid(g), dim3(MV_NT), 0, s, g, Ke,
-                     E, mask, x, (const double*)nullptr, (double*)nullptr, r, f,
-                     sc, part, (const double*)nullptr, 0, (double*)nullptr);
+  MatvecArgs a = mv_args(g, ty, Ke, E, mask);
+  a.xin = x;
+  a.yout = r;
+  a.f = f;
+  a.sc = sc;
+  a.part = part;
+  launch_mv<MV_RESID>(a, s);
   hipLaunchKernelGGL(k_resid_finish, dim3(1), dim3(256), 0, s, sc, part,
-                     matvec_blocks(g), slot);
+                     matvec_blocks(g, ty), slot);
 }
 
 int update_blocks(long long n) { return (int)((n / 2 + 255) / 256); }
 
-void launch_update(long long n, double* x, double* r, const double* p,
-                   const double* q, CGScalars* sc, double* alpha_hist,
-                   double* part_upd, const double* part_mv, int nb_mv,
-                   const double* part_comb, int nb_comb, hipStream_t s) {
-  hipLaunchKernelGGL(k_update, dim3(update_blocks(n)), dim3(256), 0, s, n / 2,
-                     x, r, p, q, sc, alpha_hist, part_upd, part_mv, nb_mv,
-                     part_comb, nb_comb);
+UpdateArgs update_args(long long n, double* x, double* r, const double* p,
+                       const double* q, CGScalars* sc, double* alpha_hist,
+                       double* part_upd, const double* part_mv, int nb_mv,
+                       const double* part_comb, int nb_comb) {
+  UpdateArgs a{};
+  a.n2 = n / 2;
+  a.x = x;
+  a.r = r;
+  a.p = p;
+  a.q = q;
+  a.sc = sc;
+  a.alpha_hist = alpha_hist;
+  a.part = part_upd;
+  a.part_mv = part_mv;
+  a.nb_mv = nb_mv;
+  a.part_comb = part_comb;
+  a.nb_comb = nb_comb;
+  return a;
+}
+
+void launch_update(const UpdateArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_update, dim3(update_blocks(2 * a.n2)), dim3(256), 0, s, a);
+}
+
+void launch_update_batch(const UpdateArgs* tab, const int* start, int nent,
+                         int total, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_batch, dim3(total), dim3(256), 0, s, tab, start, nent);
 }
 
 void launch_dot(long long n, const double* x, const double* y, double* part,

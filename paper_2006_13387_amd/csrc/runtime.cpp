@@ -18,20 +18,24 @@ namespace msp {
 // k_vec.hip
 void launch_simp(const double*, double*, int, double, double, double, int*,
                  hipStream_t);
-int matvec_blocks(const Geom&);
-void launch_apply_K(const Geom&, const double*, const double*, const uint8_t*,
-                    const double*, double*, hipStream_t);
-void launch_cg_matvec(const Geom&, const double*, const double*,
-                      const uint8_t*, const double*, const double*, double*,
-                      double*, CGScalars*, double*, const double*, int, double*,
-                      hipStream_t);
-void launch_residual(const Geom&, const double*, const double*, const uint8_t*,
-                     const double*, const double*, double*, CGScalars*, double*,
-                     int, hipStream_t);
+int matvec_blocks(const Geom&, int ty);
+void launch_apply_K(const Geom&, int ty, const double*, const double*,
+                    const uint8_t*, const double*, double*, hipStream_t);
+MatvecArgs cg_matvec_args(const Geom&, int ty, const double*, const double*,
+                          const uint8_t*, const double*, const double*, double*,
+                          double*, CGScalars*, double*, const double*, int,
+                          double*);
+void launch_cg_matvec(const MatvecArgs&, hipStream_t);
+void launch_cg_matvec_batch(const MatvecArgs*, const int*, int, int, hipStream_t);
+void launch_residual(const Geom&, int ty, const double*, const double*,
+                     const uint8_t*, const double*, const double*, double*,
+                     CGScalars*, double*, int, hipStream_t);
 int update_blocks(long long);
-void launch_update(long long, double*, double*, const double*, const double*,
-                   CGScalars*, double*, double*, const double*, int,
-                   const double*, int, hipStream_t);
+UpdateArgs update_args(long long, double*, double*, const double*,
+                       const double*, CGScalars*, double*, double*,
+                       const double*, int, const double*, int);
+void launch_update(const UpdateArgs&, hipStream_t);
+void launch_update_batch(const UpdateArgs*, const int*, int, int, hipStream_t);
 void launch_dot(long long, const double*, const double*, double*,
                 unsigned int*, double*, hipStream_t);
 void launch_mask(long long, const uint8_t*, double*, hipStream_t);
@@ -42,9 +46,8 @@ void launch_factor_elastic(const Geom&, const SysDesc*, int, const double*,
 void launch_factor_heat(const Geom&, const SysDesc*, int, const double*,
                         const uint8_t*, const double*, double*, int*,
                         hipStream_t);
-void launch_level1(const Geom&, const SysDesc*, int, const uint8_t*,
-                   const double*, const float*, const uint8_t*, const double*,
-                   double*, CGScalars*, const double*, int, int, hipStream_t);
+void launch_level1(const Level1Args&, int nsys, hipStream_t);
+void launch_level1_batch(const Level1Args*, const int*, int, int, int, hipStream_t);
 bool level1_fits(int bs, int nb, bool fp32);
 void launch_heat_eigen(const Geom&, const SysDesc*, int, const double*,
                        const uint8_t*, const double*, const double*,
@@ -62,18 +65,17 @@ void launch_coarse_k0(const Geom&, const CoarseNode*, const int2*, int,
                       int, double, hipStream_t);
 void launch_k0_pinv(double*, int, int, double*, double*, double*, double*,
                     double, int*, hipStream_t);
-void launch_restrict(const Geom&, const CoarseNode*, int, const uint8_t*,
-                     const double*, const double*, double*, int, double,
-                     CGScalars*, const double*, int, int, hipStream_t);
+void launch_restrict(const RestrictArgs&, int ncn, hipStream_t);
+void launch_restrict_batch(const RestrictArgs*, const int*, int, int, hipStream_t);
 int restrict_bands();
 bool eig_fits_host(int bs, int m);
 int restrict_max_band_nodes();
-void launch_coarse_gemv(const double*, int, int, const double*, int, double*,
-                        const CGScalars*, hipStream_t);
+int gemv_blocks(int nc);
+void launch_coarse_gemv(const GemvArgs&, hipStream_t);
+void launch_coarse_gemv_batch(const GemvArgs*, const int*, int, int, hipStream_t);
 int combine_blocks(const Geom&);
-void launch_combine(int, const Geom&, const CombineArgs&, const uint8_t*,
-                    const double*, const double*, double*, CGScalars*, double*,
-                    hipStream_t);
+void launch_combine(int, const CombineCall&, hipStream_t);
+void launch_combine_cg_batch(const CombineCall*, const int*, int, int, hipStream_t);
 void launch_export_basis(const Geom&, const CoarseNode*, const int*, int,
                          const uint8_t*, const double*, double*, double,
                          hipStream_t);
@@ -100,6 +102,7 @@ constexpr int kMaxRestarts = 3;
 // k_factor); above it, FP32 rounding of floating stiff islands' rigid
 // motions (amplitude ~ metric) pollutes the stiff phase.
 constexpr double kFp32MetricMax = 1e6;
+constexpr int kNumCUs = 256;           // MI355X compute units
 
 struct DevBuf {
   void* p = nullptr;
@@ -181,6 +184,9 @@ struct msp_handle {
   double *part_mv = nullptr, *part_upd = nullptr, *part_comb = nullptr,
          *part_res = nullptr;
   int nb_mv = 0, nb_upd = 0, nb_comb = 0;
+  int nb_mv_max = 0;         // stiffness-product tiles of the smallest tile
+  int mv_ty = 8;             // node rows per stiffness-product tile
+  bool mv_tuned = false;
   unsigned int* d_cnt = nullptr;   // counters of msp_vec_dot
   int* d_err = nullptr;
   // pinned host
@@ -533,10 +539,12 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
   for (int i = 0; i < 16; ++i) h->Ce[i] = h->Ae[i] + sigma * h->Me[i];
 
   const long long nd = h->n_dofs, nn = h->n_nodes;
-  h->nb_mv = matvec_blocks(g);
+  h->mv_ty = 8;                           // until the first densities
+  h->nb_mv_max = matvec_blocks(g, 4);     // partial buffers fit any tile
+  h->nb_mv = matvec_blocks(g, h->mv_ty);
   h->nb_upd = update_blocks(nd);
   h->nb_comb = combine_blocks(g);
-  const int nparts = h->nb_mv + h->nb_upd + 2 * h->nb_comb + 3 * h->nb_mv + 64;
+  const int nparts = h->nb_mv_max + h->nb_upd + 2 * h->nb_comb + 3 * h->nb_mv_max + 64;
   bool ok = true;
   auto A = [&](hipError_t e) { if (e != hipSuccess) ok = false; };
   A(dalloc(&h->d_elem, 64 + 16 * 3));
@@ -558,7 +566,7 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
   A(dalloc(&h->d_part, nparts));
   if (h->d_part) {
     h->part_mv = h->d_part;
-    h->part_upd = h->part_mv + h->nb_mv;
+    h->part_upd = h->part_mv + h->nb_mv_max;
     h->part_comb = h->part_upd + h->nb_upd;
     h->part_res = h->part_comb + 2 * h->nb_comb;
   }
@@ -598,6 +606,48 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
   return MSP_OK;
 }
 
+// Stiffness-product tile height for this mesh: MSP_MV_TILE (4, 8 or 16)
+// if set, else the fastest over ten timed products of the tiles that still
+// give at least two workgroups per CU (4 always qualifies).  Once per
+// handle, at the first densities; every later product of the handle, alone
+// or batched, uses the same tile and therefore the same sums.
+static msp_status tune_matvec(msp_handle* h, hipStream_t s) {
+  int best = 8;
+  const char* env = std::getenv("MSP_MV_TILE");
+  if (env && (std::atoi(env) == 4 || std::atoi(env) == 8 || std::atoi(env) == 16)) {
+    best = std::atoi(env);
+  } else {
+    const long long nd = h->n_dofs;
+    HIPCHK(h, hipMemsetAsync(h->d_x, 0, nd * sizeof(double), s));
+    hipEvent_t e0, e1;
+    HIPCHK(h, hipEventCreate(&e0));
+    HIPCHK(h, hipEventCreate(&e1));
+    float best_ms = 0.f;
+    const int cand[3] = {4, 8, 16};
+    for (int c = 0; c < 3; ++c) {
+      if (cand[c] != 4 && matvec_blocks(h->g, cand[c]) < 2 * kNumCUs) continue;
+      launch_apply_K(h->g, cand[c], h->d_elem, h->d_E, h->d_mask, h->d_x, h->d_tmp, s);
+      HIPCHK(h, hipEventRecord(e0, s));
+      for (int r = 0; r < 10; ++r)
+        launch_apply_K(h->g, cand[c], h->d_elem, h->d_E, h->d_mask, h->d_x, h->d_tmp, s);
+      HIPCHK(h, hipEventRecord(e1, s));
+      HIPCHK(h, hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+      if (c == 0 || ms < best_ms) {
+        best_ms = ms;
+        best = cand[c];
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  h->mv_ty = best;
+  h->nb_mv = matvec_blocks(h->g, best);
+  h->mv_tuned = true;
+  return MSP_OK;
+}
+
 extern "C" msp_status msp_set_densities(msp_handle* h, const double* rho,
                                         hipStream_t s) {
   if (!h || !rho) return fail(h, MSP_E_INVALID, "null argument");
@@ -614,6 +664,10 @@ extern "C" msp_status msp_set_densities(msp_handle* h, const double* rho,
   }
   h->have_E = true;
   h->setup_ok = false;
+  if (!h->mv_tuned) {
+    const msp_status st = tune_matvec(h, s);
+    if (st != MSP_OK) return st;
+  }
   return MSP_OK;
 }
 
@@ -844,31 +898,104 @@ static CombineArgs combine_args(msp_handle* h, bool l1, bool coarse) {
   return ca;
 }
 
+// Arguments of one handle's iteration kernels (also the entries of a batch).
+// check = 1: the first-level and restriction kernels first run the CG
+// convergence test on the update kernel's partials.
+static Level1Args l1_args(msp_handle* h, const double* r, CGScalars* sc, int check) {
+  Level1Args a{};
+  a.g = h->g;
+  a.sys = h->d_subs;
+  a.mask = h->d_mask;
+  a.S64 = h->d_S64;
+  a.S32 = h->fp32 ? h->d_S32 : nullptr;
+  a.use64 = h->fp32 ? h->d_use64 : nullptr;
+  a.r = r;
+  a.lsol = h->d_lsol;
+  a.sc = sc;
+  a.part_upd = h->part_upd;
+  a.nb_upd = h->nb_upd;
+  a.check = check;
+  return a;
+}
+
+static RestrictArgs rs_args(msp_handle* h, const double* r, CGScalars* sc, int check) {
+  RestrictArgs a{};
+  a.g = h->g;
+  a.cn = h->d_cn;
+  a.mask = h->d_mask;
+  a.psi = h->d_psi;
+  a.r = r;
+  a.cpart = h->d_c;
+  a.ldc = h->ldk;
+  a.invH = h->invH;
+  a.sc = sc;
+  a.part_upd = h->part_upd;
+  a.nb_upd = h->nb_upd;
+  a.check = check;
+  return a;
+}
+
+static GemvArgs gv_args(msp_handle* h, const CGScalars* sc) {
+  GemvArgs a{};
+  a.K0 = h->d_K0;
+  a.ldk = h->ldk;
+  a.nc = h->nc;
+  a.cpart = h->d_c;
+  a.ldc = h->ldk;
+  a.c0 = h->d_c0;
+  a.sc = sc;
+  return a;
+}
+
+static CombineCall cb_args(msp_handle* h, bool l1, bool coarse, const double* r,
+                           const double* q, double* z) {
+  CombineCall a{};
+  a.g = h->g;
+  a.ca = combine_args(h, l1, coarse);
+  a.mask = h->d_mask;
+  a.r = r;
+  a.q = q;
+  a.z = z;
+  a.sc = h->d_sc;
+  a.part = h->part_comb;
+  return a;
+}
+
+// CG stiffness product of iteration parity cur (p_old / p_new swap).
+static MatvecArgs mv_cg_args(msp_handle* h, int cur) {
+  double* pold = cur ? h->d_p1 : h->d_p0;
+  double* pnew = cur ? h->d_p0 : h->d_p1;
+  return cg_matvec_args(h->g, h->mv_ty, h->d_elem, h->d_E, h->d_mask, h->d_z,
+                        pold, pnew, h->d_q, h->d_sc, h->part_mv, h->part_comb,
+                        h->nb_comb, h->d_bhist);
+}
+
+static UpdateArgs up_args(msp_handle* h, int cur) {
+  double* pnew = cur ? h->d_p0 : h->d_p1;
+  return update_args(h->n_dofs, h->d_x, h->d_r, pnew, h->d_q, h->d_sc,
+                     h->d_ahist, h->part_upd, h->part_mv, h->nb_mv,
+                     h->part_comb, h->nb_comb);
+}
+
 // z = M^{-1} r with the CG scalars (mode 1: iteration, 2: start) or plain.
 static void enqueue_prec(msp_handle* h, int mode, const double* r,
                          const double* q, double* z, bool l1, bool coarse,
                          bool use_sc, hipStream_t s) {
-  const Geom& g = h->g;
   CGScalars* sc = use_sc ? h->d_sc : nullptr;
   const int check = (mode == 1) ? 1 : 0;   // convergence test after update
   if (l1) {
     const int t = timer_begin(h, KT_LEVEL1, s);
-    launch_level1(g, h->d_subs, (int)h->subs.size(), h->d_mask, h->d_S64,
-                  h->fp32 ? h->d_S32 : nullptr, h->fp32 ? h->d_use64 : nullptr,
-                  r, h->d_lsol, sc, h->part_upd, h->nb_upd, check, s);
+    launch_level1(l1_args(h, r, sc, check), (int)h->subs.size(), s);
     timer_end(h, KT_LEVEL1, t, s);
   }
   if (coarse && h->nc > 0) {
     const int t = timer_begin(h, KT_RESTRICT, s);
-    launch_restrict(g, h->d_cn, (int)h->cn_h.size(), h->d_mask, h->d_psi, r,
-                    h->d_c, h->ldk, h->invH, sc, h->part_upd, h->nb_upd, check,
-                    s);
+    launch_restrict(rs_args(h, r, sc, check), (int)h->cn_h.size(), s);
     timer_end(h, KT_RESTRICT, t, s);
-    launch_coarse_gemv(h->d_K0, h->ldk, h->nc, h->d_c, h->ldk, h->d_c0, sc, s);
+    launch_coarse_gemv(gv_args(h, sc), s);
   }
-  const CombineArgs ca = combine_args(h, l1, coarse);
   const int t = timer_begin(h, KT_COMBINE, s);
-  launch_combine(mode, g, ca, h->d_mask, r, q, z, h->d_sc, h->part_comb, s);
+  launch_combine(mode, cb_args(h, l1, coarse, r, q, z), s);
   timer_end(h, KT_COMBINE, t, s);
 }
 
@@ -885,7 +1012,7 @@ extern "C" msp_status msp_apply_K(msp_handle* h, const double* x, double* y,
   if (!h->have_E) return fail(h, MSP_E_STATE, "msp_set_densities must come first");
   if (x == y) return fail(h, MSP_E_INVALID, "x and y must not alias");
   const int tm = timer_begin(h, KT_MATVEC, s);
-  launch_apply_K(h->g, h->d_elem, h->d_E, h->d_mask, x, y, s);
+  launch_apply_K(h->g, h->mv_ty, h->d_elem, h->d_E, h->d_mask, x, y, s);
   timer_end(h, KT_MATVEC, tm, s);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(s));
@@ -918,150 +1045,218 @@ extern "C" msp_status msp_apply_prec(msp_handle* h, const double* r, double* z,
   return apply_parts(h, r, z, true, true, s);
 }
 
-static msp_status solve_one(msp_handle* h, const double* f, double* u,
-                            int warm, double rtol, int maxit, hipStream_t s,
-                            msp_solve_info* info) {
-  const Geom& g = h->g;
+// One right-hand side's PCG run, in phases shared by msp_solve (one
+// problem) and msp_batch_solve (many problems in lockstep):
+//   run_begin, then per segment seg_launch / seg_started (after a sync),
+//   iteration chunks until the device marks the segment done,
+//   seg_finish (true residual: finished, or restart with a new segment),
+//   and run_end.
+struct SolveRun {
+  msp_handle* h = nullptr;
+  const double* f = nullptr;
+  double* u = nullptr;
+  double rtol = 0.0;
+  int maxit = 0;
+  CGScalars init{};
+  int total_iters = 0, restarts = 0, status = MSP_OK, seg_iters = 0;
+  double relres_true = 0.0, relres_rec = 0.0, comp = 0.0;
+  std::vector<double> ah, bh;
+  bool iterating = false;     // the current segment needs iterations
+  bool finished = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+
+static msp_status run_begin(SolveRun& R, int warm, hipStream_t s) {
+  msp_handle* h = R.h;
   const long long nd = h->n_dofs;
-  if (maxit > h->hist_cap) {
+  if (R.maxit > h->hist_cap) {
     dfree(h->d_ahist);
     dfree(h->d_bhist);
-    HIPCHK(h, dalloc(&h->d_ahist, maxit + 8));
-    HIPCHK(h, dalloc(&h->d_bhist, maxit + 8));
-    h->hist_cap = maxit;
+    HIPCHK(h, dalloc(&h->d_ahist, R.maxit + 8));
+    HIPCHK(h, dalloc(&h->d_bhist, R.maxit + 8));
+    h->hist_cap = R.maxit;
   }
-  hipEvent_t e0, e1;
-  HIPCHK(h, hipEventCreate(&e0));
-  HIPCHK(h, hipEventCreate(&e1));
-  HIPCHK(h, hipEventRecord(e0, s));
+  HIPCHK(h, hipEventCreate(&R.e0));
+  HIPCHK(h, hipEventCreate(&R.e1));
+  HIPCHK(h, hipEventRecord(R.e0, s));
   if (warm) {
-    HIPCHK(h, hipMemcpyAsync(h->d_x, u, nd * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->d_x, R.u, nd * sizeof(double), hipMemcpyDeviceToDevice, s));
     launch_mask(nd, h->d_mask, h->d_x, s);      // u = 0 at clamped DOFs
   } else {
     HIPCHK(h, hipMemsetAsync(h->d_x, 0, nd * sizeof(double), s));
   }
-  CGScalars init{};
-  init.tol2 = rtol * rtol;
-  init.maxit = maxit;
-  init.flexible = h->fp32 ? 1 : 0;
-  int total_iters = 0, restarts = 0;
-  int status = MSP_OK;
-  double relres_true = 0.0, relres_rec = 0.0, comp = 0.0;
-  std::vector<double> ah, bh;
-  int seg_iters = 0;
-  for (;;) {
-    // fresh segment: iteration count and histories restart at 0
-    CGScalars seg = init;
-    seg.maxit = std::max(1, maxit - total_iters);
-    *h->h_sc = seg;
-    HIPCHK(h, hipMemcpyAsync(h->d_sc, h->h_sc, sizeof(CGScalars), hipMemcpyHostToDevice, s));
-    // r = f - K x ; ||f|| ; then z = M^{-1} r, p_old = 0
-    launch_residual(g, h->d_elem, h->d_E, h->d_mask, h->d_x, f, h->d_r,
-                    h->d_sc, h->part_res, 0, s);
-    HIPCHK(h, hipMemsetAsync(h->d_p0, 0, nd * sizeof(double), s));
-    enqueue_prec(h, 2, h->d_r, nullptr, h->d_z, true, true, true, s);
-    HIPCHK(h, hipGetLastError());
-    HIPCHK(h, hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(CGScalars), hipMemcpyDeviceToHost, s));
-    HIPCHK(h, hipStreamSynchronize(s));
-    timer_flush(h);
-    if (h->h_sc->ff == 0.0) {
-      HIPCHK(h, hipMemsetAsync(h->d_x, 0, nd * sizeof(double), s));
-      break;
-    }
-    if (h->h_sc->rr <= init.tol2 * h->h_sc->ff) {
-      h->h_sc->done = DONE_CONVERGED;
-    } else {
-      int cur = 0;
-      for (;;) {
-        for (int it = 0; it < kChunk; ++it) {
-          double* pold = cur ? h->d_p1 : h->d_p0;
-          double* pnew = cur ? h->d_p0 : h->d_p1;
-          const int tm = timer_begin(h, KT_MATVEC, s);
-          launch_cg_matvec(g, h->d_elem, h->d_E, h->d_mask, h->d_z, pold, pnew,
-                           h->d_q, h->d_sc, h->part_mv, h->part_comb,
-                           h->nb_comb, h->d_bhist, s);
-          timer_end(h, KT_MATVEC, tm, s);
-          launch_update(nd, h->d_x, h->d_r, pnew, h->d_q, h->d_sc, h->d_ahist,
-                        h->part_upd, h->part_mv, h->nb_mv, h->part_comb,
-                        h->nb_comb, s);
-          enqueue_prec(h, 1, h->d_r, h->d_q, h->d_z, true, true, true, s);
-          cur ^= 1;
-        }
-        HIPCHK(h, hipGetLastError());
-        HIPCHK(h, hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(CGScalars), hipMemcpyDeviceToHost, s));
-        HIPCHK(h, hipStreamSynchronize(s));
-        timer_flush(h);
-        if (h->h_sc->done) break;
-      }
-    }
-    const CGScalars fin = *h->h_sc;
-    seg_iters = fin.iter;
-    total_iters += fin.iter;
-    relres_rec = fin.ff > 0 ? std::sqrt(fin.rr / fin.ff) : 0.0;
-    if (fin.iter > 0) {
-      ah.resize(fin.iter);
-      bh.resize(fin.iter);
-      HIPCHK(h, hipMemcpy(ah.data(), h->d_ahist, fin.iter * sizeof(double), hipMemcpyDeviceToHost));
-      HIPCHK(h, hipMemcpy(bh.data(), h->d_bhist, fin.iter * sizeof(double), hipMemcpyDeviceToHost));
-    }
-    if (fin.done == DONE_BREAKDOWN) {
-      status = MSP_E_BREAKDOWN;
-      break;
-    }
-    // true residual and compliance
-    launch_residual(g, h->d_elem, h->d_E, h->d_mask, h->d_x, f, h->d_tmp,
-                    h->d_sc, h->part_res, 1, s);
-    HIPCHK(h, hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(CGScalars), hipMemcpyDeviceToHost, s));
-    HIPCHK(h, hipStreamSynchronize(s));
-    relres_true = std::sqrt(h->h_sc->rr0 / h->h_sc->ff);
-    comp = h->h_sc->fx;
-    if (relres_true <= rtol) break;
-    if (fin.done == DONE_MAXIT || total_iters >= maxit) {
-      status = MSP_NOT_CONVERGED;
-      break;
-    }
-    if (restarts >= kMaxRestarts) {
-      status = MSP_NOT_CONVERGED;
-      break;
-    }
-    ++restarts;
+  R.init = CGScalars{};
+  R.init.tol2 = R.rtol * R.rtol;
+  R.init.maxit = R.maxit;
+  R.init.flexible = h->fp32 ? 1 : 0;
+  return MSP_OK;
+}
+
+// Fresh segment: iteration count and histories restart at 0;
+// r = f - K x, ||f||, z = M^{-1} r, p_old = 0; the scalars are copied back.
+static msp_status seg_launch(SolveRun& R, hipStream_t s) {
+  msp_handle* h = R.h;
+  CGScalars seg = R.init;
+  seg.maxit = std::max(1, R.maxit - R.total_iters);
+  *h->h_sc = seg;
+  HIPCHK(h, hipMemcpyAsync(h->d_sc, h->h_sc, sizeof(CGScalars), hipMemcpyHostToDevice, s));
+  launch_residual(h->g, h->mv_ty, h->d_elem, h->d_E, h->d_mask, h->d_x, R.f,
+                  h->d_r, h->d_sc, h->part_res, 0, s);
+  HIPCHK(h, hipMemsetAsync(h->d_p0, 0, h->n_dofs * sizeof(double), s));
+  enqueue_prec(h, 2, h->d_r, nullptr, h->d_z, true, true, true, s);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(CGScalars), hipMemcpyDeviceToHost, s));
+  return MSP_OK;
+}
+
+// After the stream synchronised: a zero right-hand side or a start that
+// already meets the tolerance needs no iteration (the device scalars are
+// then marked done, so batched iterations skip this run).
+static msp_status seg_started(SolveRun& R, hipStream_t s) {
+  msp_handle* h = R.h;
+  timer_flush(h);
+  R.iterating = false;
+  if (h->h_sc->ff == 0.0) {
+    HIPCHK(h, hipMemsetAsync(h->d_x, 0, h->n_dofs * sizeof(double), s));
+  } else if (!(h->h_sc->rr <= R.init.tol2 * h->h_sc->ff)) {
+    R.iterating = true;
+    return MSP_OK;
   }
-  HIPCHK(h, hipMemcpyAsync(u, h->d_x, nd * sizeof(double), hipMemcpyDeviceToDevice, s));
-  HIPCHK(h, hipEventRecord(e1, s));
-  HIPCHK(h, hipEventSynchronize(e1));
+  h->h_sc->done = DONE_CONVERGED;
+  HIPCHK(h, hipMemcpyAsync(h->d_sc, h->h_sc, sizeof(CGScalars), hipMemcpyHostToDevice, s));
+  return MSP_OK;
+}
+
+// The segment is over (h_sc read back after a sync): histories, true
+// residual, compliance; either the run is finished or a new segment starts
+// (*restart).
+static msp_status seg_finish(SolveRun& R, hipStream_t s, bool* restart) {
+  msp_handle* h = R.h;
+  *restart = false;
+  const CGScalars fin = *h->h_sc;
+  R.seg_iters = fin.iter;
+  R.total_iters += fin.iter;
+  R.relres_rec = fin.ff > 0 ? std::sqrt(fin.rr / fin.ff) : 0.0;
+  if (fin.iter > 0) {
+    R.ah.resize(fin.iter);
+    R.bh.resize(fin.iter);
+    HIPCHK(h, hipMemcpyAsync(R.ah.data(), h->d_ahist, fin.iter * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(R.bh.data(), h->d_bhist, fin.iter * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  if (fin.done == DONE_BREAKDOWN) {
+    HIPCHK(h, hipStreamSynchronize(s));
+    R.status = MSP_E_BREAKDOWN;
+    R.finished = true;
+    return MSP_OK;
+  }
+  if (fin.ff == 0.0) {                      // zero right-hand side
+    HIPCHK(h, hipStreamSynchronize(s));
+    R.relres_true = 0.0;
+    R.comp = 0.0;
+    R.finished = true;
+    return MSP_OK;
+  }
+  launch_residual(h->g, h->mv_ty, h->d_elem, h->d_E, h->d_mask, h->d_x, R.f,
+                  h->d_tmp, h->d_sc, h->part_res, 1, s);
+  HIPCHK(h, hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(CGScalars), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  R.relres_true = std::sqrt(h->h_sc->rr0 / h->h_sc->ff);
+  R.comp = h->h_sc->fx;
+  if (R.relres_true <= R.rtol) {
+    R.finished = true;
+  } else if (fin.done == DONE_MAXIT || R.total_iters >= R.maxit || R.restarts >= kMaxRestarts) {
+    R.status = MSP_NOT_CONVERGED;
+    R.finished = true;
+  } else {
+    ++R.restarts;
+    *restart = true;
+  }
+  return MSP_OK;
+}
+
+static msp_status run_end(SolveRun& R, hipStream_t s, msp_solve_info* info) {
+  msp_handle* h = R.h;
+  HIPCHK(h, hipMemcpyAsync(R.u, h->d_x, h->n_dofs * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipEventRecord(R.e1, s));
+  HIPCHK(h, hipEventSynchronize(R.e1));
   float ms = 0.f;
-  HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  HIPCHK(h, hipEventElapsedTime(&ms, R.e0, R.e1));
+  (void)hipEventDestroy(R.e0);
+  (void)hipEventDestroy(R.e1);
+  R.e0 = R.e1 = nullptr;
+  const int si = R.seg_iters;
   double cond = NAN;
-  if (seg_iters >= 1 && (int)ah.size() >= seg_iters) {
-    std::vector<double> d(seg_iters), e(std::max(0, seg_iters - 1));
-    for (int j = 0; j < seg_iters; ++j) {
-      d[j] = 1.0 / ah[j];
-      if (j > 0) d[j] += bh[j - 1] / ah[j - 1];
-      if (j < seg_iters - 1) e[j] = std::sqrt(std::fabs(bh[j])) / ah[j];
+  if (si >= 1 && (int)R.ah.size() >= si) {
+    std::vector<double> d(si), e(std::max(0, si - 1));
+    for (int j = 0; j < si; ++j) {
+      d[j] = 1.0 / R.ah[j];
+      if (j > 0) d[j] += R.bh[j - 1] / R.ah[j - 1];
+      if (j < si - 1) e[j] = std::sqrt(std::fabs(R.bh[j])) / R.ah[j];
     }
     double lo, hi;
     tridiag_extremes(d, e, &lo, &hi);
     cond = hi / lo;
   }
   if (info) {
-    info->status = status;
-    info->iters = total_iters;
-    info->converged = (status == MSP_OK) ? 1 : 0;
-    info->restarts = restarts;
+    info->status = R.status;
+    info->iters = R.total_iters;
+    info->converged = (R.status == MSP_OK) ? 1 : 0;
+    info->restarts = R.restarts;
     info->n_coarse = h->nc;
     info->coarse_rank = h->rank;
     info->cap_hits = h->cap_hits;
     info->fp64_subdomains = h->n_fp64_subs;
-    info->relres_true = relres_true;
-    info->relres_rec = relres_rec;
-    info->compliance = comp;
+    info->relres_true = R.relres_true;
+    info->relres_rec = R.relres_rec;
+    info->compliance = R.comp;
     info->cond_est = cond;
     info->t_solve_ms = ms;
   }
-  if (status == MSP_E_BREAKDOWN) return fail(h, MSP_E_BREAKDOWN, "PCG breakdown (p^T K p <= 0 or non-finite)");
-  return (msp_status)status;
+  if (R.status == MSP_E_BREAKDOWN) return fail(h, MSP_E_BREAKDOWN, "PCG breakdown (p^T K p <= 0 or non-finite)");
+  return (msp_status)R.status;
+}
+
+// kChunk CG iterations of one problem (each kernel returns at once when the
+// device has marked the segment done).
+static void chunk_single(msp_handle* h, hipStream_t s) {
+  for (int it = 0; it < kChunk; ++it) {
+    const int cur = it & 1;
+    const int tm = timer_begin(h, KT_MATVEC, s);
+    launch_cg_matvec(mv_cg_args(h, cur), s);
+    timer_end(h, KT_MATVEC, tm, s);
+    launch_update(up_args(h, cur), s);
+    enqueue_prec(h, 1, h->d_r, h->d_q, h->d_z, true, true, true, s);
+  }
+}
+
+static msp_status solve_one(msp_handle* h, const double* f, double* u,
+                            int warm, double rtol, int maxit, hipStream_t s,
+                            msp_solve_info* info) {
+  static_assert(kChunk % 2 == 0, "chunks keep the p parity");
+  SolveRun R;
+  R.h = h;
+  R.f = f;
+  R.u = u;
+  R.rtol = rtol;
+  R.maxit = maxit;
+  msp_status st = run_begin(R, warm, s);
+  if (st != MSP_OK) return st;
+  while (!R.finished) {
+    if ((st = seg_launch(R, s)) != MSP_OK) return st;
+    HIPCHK(h, hipStreamSynchronize(s));
+    if ((st = seg_started(R, s)) != MSP_OK) return st;
+    while (R.iterating) {
+      chunk_single(h, s);
+      HIPCHK(h, hipGetLastError());
+      HIPCHK(h, hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(CGScalars), hipMemcpyDeviceToHost, s));
+      HIPCHK(h, hipStreamSynchronize(s));
+      timer_flush(h);
+      if (h->h_sc->done) break;
+    }
+    bool restart = false;
+    if ((st = seg_finish(R, s, &restart)) != MSP_OK) return st;
+  }
+  return run_end(R, s, info);
 }
 
 extern "C" msp_status msp_solve(msp_handle* h, const double* f, double* u,
@@ -1088,6 +1283,301 @@ extern "C" msp_status msp_solve(msp_handle* h, const double* f, double* u,
   }
   if (info) info->t_setup_ms = t_setup;
   return last;
+}
+
+// ------------------------------------------------------------------ batches
+
+struct msp_batch {
+  std::string err;
+  int cap = 0;                            // entries the device tables hold
+  MatvecArgs* d_mv[2] = {nullptr, nullptr};
+  UpdateArgs* d_up[2] = {nullptr, nullptr};
+  Level1Args* d_l1 = nullptr;
+  RestrictArgs* d_rs = nullptr;
+  GemvArgs* d_gv = nullptr;
+  CombineCall* d_cb = nullptr;
+  int* d_start = nullptr;                 // 6 prefix tables of cap + 1 ints
+  int tot[6] = {0, 0, 0, 0, 0, 0};
+  int n = 0;
+  hipGraphExec_t gexec = nullptr;         // captured chunk of kChunk iterations
+  std::vector<unsigned char> gkey;        // tables the graph was captured with
+  long long chunks = 0, graph_chunks = 0;
+};
+
+enum { BT_MV = 0, BT_UP, BT_L1, BT_RS, BT_GV, BT_CB };
+
+static msp_status bfail(msp_batch* b, msp_status st, const std::string& msg) {
+  if (b) b->err = msg;
+  g_static_err = msg;
+  return st;
+}
+
+static void batch_free_tables(msp_batch* b) {
+  void* bufs[] = {b->d_mv[0], b->d_mv[1], b->d_up[0], b->d_up[1], b->d_l1,
+                  b->d_rs, b->d_gv, b->d_cb, b->d_start};
+  for (void* p : bufs) dfree(p);
+  b->d_mv[0] = b->d_mv[1] = nullptr;
+  b->d_up[0] = b->d_up[1] = nullptr;
+  b->d_l1 = nullptr;
+  b->d_rs = nullptr;
+  b->d_gv = nullptr;
+  b->d_cb = nullptr;
+  b->d_start = nullptr;
+  b->cap = 0;
+}
+
+extern "C" msp_status msp_batch_create(msp_batch** out) {
+  if (!out) return bfail(nullptr, MSP_E_INVALID, "null argument");
+  *out = new msp_batch();
+  return MSP_OK;
+}
+
+extern "C" msp_status msp_batch_destroy(msp_batch* b) {
+  if (!b) return MSP_OK;
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  batch_free_tables(b);
+  delete b;
+  return MSP_OK;
+}
+
+extern "C" const char* msp_batch_last_error(const msp_batch* b) {
+  return b ? b->err.c_str() : g_static_err.c_str();
+}
+
+// Device tables of the batch's iteration kernels (one entry per problem,
+// two parities for the p_old / p_new swap) and the workgroup prefix tables.
+static msp_status batch_tables(msp_batch* b, const std::vector<msp_handle*>& hs,
+                               hipStream_t s, std::vector<unsigned char>* key) {
+  const int n = (int)hs.size();
+  if (n > b->cap) {
+    batch_free_tables(b);
+    const int cap = std::max(n, 8);
+    bool ok = true;
+    auto A = [&](hipError_t e) { if (e != hipSuccess) ok = false; };
+    for (int c = 0; c < 2; ++c) {
+      A(dalloc(&b->d_mv[c], cap));
+      A(dalloc(&b->d_up[c], cap));
+    }
+    A(dalloc(&b->d_l1, cap));
+    A(dalloc(&b->d_rs, cap));
+    A(dalloc(&b->d_gv, cap));
+    A(dalloc(&b->d_cb, cap));
+    A(dalloc(&b->d_start, 6 * (cap + 1)));
+    if (!ok) {
+      batch_free_tables(b);
+      return bfail(b, MSP_E_NOMEM, "device allocation of the batch tables failed");
+    }
+    b->cap = cap;
+  }
+  std::vector<MatvecArgs> mv[2];
+  std::vector<UpdateArgs> up[2];
+  std::vector<Level1Args> l1;
+  std::vector<RestrictArgs> rs;
+  std::vector<GemvArgs> gv;
+  std::vector<CombineCall> cb;
+  std::vector<int> start(6 * (b->cap + 1), 0);
+  for (int e = 0; e < n; ++e) {
+    msp_handle* h = hs[e];
+    for (int c = 0; c < 2; ++c) {
+      mv[c].push_back(mv_cg_args(h, c));
+      up[c].push_back(up_args(h, c));
+    }
+    l1.push_back(l1_args(h, h->d_r, h->d_sc, 1));
+    rs.push_back(rs_args(h, h->d_r, h->d_sc, 1));
+    gv.push_back(gv_args(h, h->d_sc));
+    cb.push_back(cb_args(h, true, true, h->d_r, h->d_q, h->d_z));
+    const int nblk[6] = {matvec_blocks(h->g, h->mv_ty), update_blocks(h->n_dofs),
+                         (int)h->subs.size(),
+                         h->nc > 0 ? (int)h->cn_h.size() * restrict_bands() : 0,
+                         gemv_blocks(h->nc), combine_blocks(h->g)};
+    for (int k = 0; k < 6; ++k)
+      start[k * (b->cap + 1) + e + 1] = start[k * (b->cap + 1) + e] + nblk[k];
+  }
+  for (int k = 0; k < 6; ++k) b->tot[k] = start[k * (b->cap + 1) + n];
+  b->n = n;
+  auto up_copy = [&](void* d, const void* hsrc, size_t bytes) {
+    return hipMemcpyAsync(d, hsrc, bytes, hipMemcpyHostToDevice, s);
+  };
+  hipError_t e = hipSuccess;
+  auto C = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
+  for (int c = 0; c < 2; ++c) {
+    C(up_copy(b->d_mv[c], mv[c].data(), n * sizeof(MatvecArgs)));
+    C(up_copy(b->d_up[c], up[c].data(), n * sizeof(UpdateArgs)));
+  }
+  C(up_copy(b->d_l1, l1.data(), n * sizeof(Level1Args)));
+  C(up_copy(b->d_rs, rs.data(), n * sizeof(RestrictArgs)));
+  C(up_copy(b->d_gv, gv.data(), n * sizeof(GemvArgs)));
+  C(up_copy(b->d_cb, cb.data(), n * sizeof(CombineCall)));
+  C(up_copy(b->d_start, start.data(), start.size() * sizeof(int)));
+  C(hipStreamSynchronize(s));               // host tables go out of scope
+  if (e != hipSuccess) return bfail(b, MSP_E_DEVICE, std::string("batch table upload failed: ") + hipGetErrorString(e));
+  // the graph depends on the table contents and the grid sizes
+  key->clear();
+  auto add = [&](const void* p, size_t bytes) {
+    const unsigned char* c = (const unsigned char*)p;
+    key->insert(key->end(), c, c + bytes);
+  };
+  add(&n, sizeof(n));
+  add(b->tot, sizeof(b->tot));
+  const void* ptrs[9] = {b->d_mv[0], b->d_mv[1], b->d_up[0], b->d_up[1], b->d_l1,
+                         b->d_rs, b->d_gv, b->d_cb, b->d_start};
+  add(ptrs, sizeof(ptrs));
+  for (int c = 0; c < 2; ++c) {
+    add(mv[c].data(), n * sizeof(MatvecArgs));
+    add(up[c].data(), n * sizeof(UpdateArgs));
+  }
+  add(l1.data(), n * sizeof(Level1Args));
+  add(rs.data(), n * sizeof(RestrictArgs));
+  add(gv.data(), n * sizeof(GemvArgs));
+  add(cb.data(), n * sizeof(CombineCall));
+  return MSP_OK;
+}
+
+// kChunk lockstep iterations of every problem of the batch: each kernel is
+// launched once for all problems (problems whose segment is done return at
+// once); the first-level solves of all problems in one persistent launch of
+// one workgroup per CU.
+static void chunk_batch(msp_batch* b, hipStream_t s) {
+  const int cp = b->cap + 1;
+  const int* st = b->d_start;
+  const int l1_grid = std::max(1, std::min(b->tot[BT_L1], kNumCUs));
+  for (int it = 0; it < kChunk; ++it) {
+    const int cur = it & 1;
+    launch_cg_matvec_batch(b->d_mv[cur], st + BT_MV * cp, b->n, b->tot[BT_MV], s);
+    launch_update_batch(b->d_up[cur], st + BT_UP * cp, b->n, b->tot[BT_UP], s);
+    launch_level1_batch(b->d_l1, st + BT_L1 * cp, b->n, b->tot[BT_L1], l1_grid, s);
+    if (b->tot[BT_RS] > 0) {
+      launch_restrict_batch(b->d_rs, st + BT_RS * cp, b->n, b->tot[BT_RS], s);
+      launch_coarse_gemv_batch(b->d_gv, st + BT_GV * cp, b->n, b->tot[BT_GV], s);
+    }
+    launch_combine_cg_batch(b->d_cb, st + BT_CB * cp, b->n, b->tot[BT_CB], s);
+  }
+}
+
+extern "C" msp_status msp_batch_solve(msp_batch* b, msp_handle* const* hs_in,
+                                      const double* const* f,
+                                      double* const* u, const int32_t* warm,
+                                      int32_t n, double rtol, int32_t maxit,
+                                      int32_t use_graph, hipStream_t s,
+                                      msp_solve_info* infos) {
+  if (!b || !hs_in || !f || !u || n < 1)
+    return bfail(b, MSP_E_INVALID, "null argument or empty batch");
+  if (maxit < 1 || !(rtol > 0.0))
+    return bfail(b, MSP_E_INVALID, "need maxit >= 1, rtol > 0");
+  std::vector<msp_handle*> hs(hs_in, hs_in + n);
+  for (int e = 0; e < n; ++e) {
+    if (!hs[e] || !f[e] || !u[e]) return bfail(b, MSP_E_INVALID, "null handle or vector in the batch");
+    for (int k = 0; k < e; ++k)
+      if (hs[k] == hs[e]) return bfail(b, MSP_E_INVALID, "a handle appears twice in the batch");
+    if (!hs[e]->have_E) return bfail(b, MSP_E_STATE, "msp_set_densities must come first");
+  }
+  // setups (those whose densities changed)
+  std::vector<double> t_setup(n, 0.0);
+  for (int e = 0; e < n; ++e) {
+    if (hs[e]->setup_ok) continue;
+    const msp_status st = msp_setup(hs[e], s);
+    if (st != MSP_OK) return bfail(b, st, std::string("setup of batch entry failed: ") + hs[e]->err);
+    t_setup[e] = hs[e]->t_setup_ms;
+  }
+  msp_status st = MSP_OK;
+  std::vector<SolveRun> R(n);
+  for (int e = 0; e < n; ++e) {
+    R[e].h = hs[e];
+    R[e].f = f[e];
+    R[e].u = u[e];
+    R[e].rtol = rtol;
+    R[e].maxit = maxit;
+    if ((st = run_begin(R[e], warm ? warm[e] : 0, s)) != MSP_OK) return bfail(b, st, hs[e]->err);
+  }
+  // after run_begin: the tables hold the (possibly reallocated) histories
+  std::vector<unsigned char> key;
+  if ((st = batch_tables(b, hs, s, &key)) != MSP_OK) return st;
+  for (int e = 0; e < n; ++e)
+    if ((st = seg_launch(R[e], s)) != MSP_OK) return bfail(b, st, hs[e]->err);
+  if (hipStreamSynchronize(s) != hipSuccess) return bfail(b, MSP_E_DEVICE, "stream synchronisation failed");
+  for (int e = 0; e < n; ++e)
+    if ((st = seg_started(R[e], s)) != MSP_OK) return bfail(b, st, hs[e]->err);
+  // capture one chunk when asked for and the tables changed
+  bool graph_ready = false;
+  if (use_graph) {
+    if (b->gexec && b->gkey == key) {
+      graph_ready = true;
+    } else {
+      if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+      b->gexec = nullptr;
+      hipStream_t cs;
+      hipGraph_t gr = nullptr;
+      if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess) {
+        bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) chunk_batch(b, cs);
+        ok = (hipStreamEndCapture(cs, &gr) == hipSuccess) && ok && gr != nullptr;
+        if (ok) ok = hipGraphInstantiate(&b->gexec, gr, nullptr, nullptr, 0) == hipSuccess;
+        if (gr) (void)hipGraphDestroy(gr);
+        (void)hipStreamDestroy(cs);
+        if (ok) {
+          b->gkey = key;
+          graph_ready = true;
+        } else {
+          b->gexec = nullptr;
+        }
+      }
+    }
+  }
+  for (;;) {
+    bool any = false;
+    for (int e = 0; e < n; ++e) any = any || (!R[e].finished && R[e].iterating);
+    if (!any) {
+      // every run is between segments or finished: finish / restart them
+      bool more = false;
+      for (int e = 0; e < n; ++e) {
+        if (R[e].finished) continue;
+        bool restart = false;
+        if ((st = seg_finish(R[e], s, &restart)) != MSP_OK) return bfail(b, st, hs[e]->err);
+        if (restart) {
+          if ((st = seg_launch(R[e], s)) != MSP_OK) return bfail(b, st, hs[e]->err);
+          if (hipStreamSynchronize(s) != hipSuccess) return bfail(b, MSP_E_DEVICE, "stream synchronisation failed");
+          if ((st = seg_started(R[e], s)) != MSP_OK) return bfail(b, st, hs[e]->err);
+          more = true;
+        }
+      }
+      if (!more) break;
+      continue;
+    }
+    if (graph_ready) {
+      if (hipGraphLaunch(b->gexec, s) != hipSuccess) return bfail(b, MSP_E_DEVICE, "graph launch failed");
+      ++b->graph_chunks;
+    } else {
+      chunk_batch(b, s);
+    }
+    ++b->chunks;
+    if (hipGetLastError() != hipSuccess) return bfail(b, MSP_E_DEVICE, "batched iteration launch failed");
+    for (int e = 0; e < n; ++e)
+      if (!R[e].finished && R[e].iterating)
+        (void)hipMemcpyAsync(hs[e]->h_sc, hs[e]->d_sc, sizeof(CGScalars), hipMemcpyDeviceToHost, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return bfail(b, MSP_E_DEVICE, "stream synchronisation failed");
+    for (int e = 0; e < n; ++e) {
+      if (R[e].finished || !R[e].iterating || !hs[e]->h_sc->done) continue;
+      R[e].iterating = false;               // segment over: finished below
+    }
+  }
+  msp_status worst = MSP_OK;
+  for (int e = 0; e < n; ++e) {
+    msp_solve_info* inf = infos ? &infos[e] : nullptr;
+    const msp_status se = run_end(R[e], s, inf);
+    if (inf) inf->t_setup_ms = t_setup[e];
+    if (se < 0 && worst >= 0) worst = se;
+    else if (se > 0 && worst == MSP_OK) worst = se;
+  }
+  if (worst < 0) return bfail(b, worst, "a batch entry failed (see its msp_solve_info.status)");
+  return worst;
+}
+
+extern "C" msp_status msp_batch_stats(const msp_batch* b, int64_t* chunks,
+                                      int64_t* graph_chunks) {
+  if (!b) return MSP_E_INVALID;
+  if (chunks) *chunks = b->chunks;
+  if (graph_chunks) *graph_chunks = b->graph_chunks;
+  return MSP_OK;
 }
 
 extern "C" msp_status msp_coarse_info(msp_handle* h, int32_t* n_modes,
