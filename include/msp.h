@@ -239,6 +239,65 @@ msp_status msp_batch_solve(msp_batch* b, msp_handle* const* handles,
 msp_status msp_batch_stats(const msp_batch* b, int64_t* chunks,
                            int64_t* graph_chunks);
 
+/* ---- serving: continuous batching of state and adjoint solves ---- */
+
+typedef struct msp_server msp_server;
+
+/*
+ * A request loop for many topology-optimisation runs.  A run is a mesh with
+ * its clamped DOFs; its handle (setup) and its last state and adjoint
+ * solutions stay resident while the projected device memory of all resident
+ * runs fits hbm_budget_bytes (idle runs' setups are evicted least recently
+ * used first; their warm-start vectors stay).  At most max_active requests
+ * are in progress.  The serving layer is not in the paper; the solves are.
+ */
+msp_status msp_server_create(int64_t hbm_budget_bytes, int32_t max_active,
+                             msp_server** out);
+msp_status msp_server_destroy(msp_server* sv);
+const char* msp_server_last_error(const msp_server* sv);
+
+/* Register a run (validated like msp_create; no device memory yet). */
+msp_status msp_server_add_run(msp_server* sv, const msp_problem_desc* desc,
+                              const uint8_t* fixed_mask_host, int32_t* run_id);
+
+/*
+ * Queue a request of a run: new densities, a state load and optionally an
+ * adjoint load (f_adj_dev and u_adj_dev both NULL for none).  The solutions
+ * are written to u_state_dev / u_adj_dev when the request completes; each
+ * solve warm-starts from the run's previous solution of its kind.  The
+ * caller keeps all five device arrays alive until then.  Requests of one
+ * run are served in submission order.
+ */
+msp_status msp_server_submit(msp_server* sv, int32_t run_id,
+                             const double* rho_dev, const double* f_state_dev,
+                             const double* f_adj_dev, double* u_state_dev,
+                             double* u_adj_dev, double rtol, int32_t maxit,
+                             int32_t* ticket);
+
+/*
+ * One scheduling step on the caller's stream: one chunk of 16 lockstep PCG
+ * iterations for every solve in progress (a batched launch per iteration
+ * kernel, as msp_batch_solve), while queued requests are admitted as slots
+ * and memory allow, their densities and setup running on a second stream
+ * at the same time; then finished solves move on (state -> adjoint ->
+ * done).  n_completed receives the requests completed by this step.  Each
+ * solve's arithmetic is that of msp_solve on its run's handle with the
+ * same warm start, whatever else is in progress.
+ */
+msp_status msp_server_step(msp_server* sv, hipStream_t stream,
+                           int32_t* n_completed);
+
+/* Result of a completed request: two msp_solve_info records (state,
+ * adjoint) and the latency from submission to completion in ms.
+ * MSP_E_STATE while the request is still queued or in progress. */
+msp_status msp_server_result(msp_server* sv, int32_t ticket,
+                             msp_solve_info* info2_host, double* latency_ms);
+
+/* 8 doubles: completed requests, p50 and p99 latency (ms), solves per
+ * second (state and adjoint solves, first submission to last completion),
+ * projected device bytes of resident runs, queued, active, chunks run. */
+msp_status msp_server_stats(const msp_server* sv, double* stats8_host);
+
 #ifdef __cplusplus
 }
 #endif

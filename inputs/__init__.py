@@ -34,6 +34,7 @@ __all__ = [
     "clamp_all_mask", "point_load", "face_patch_load", "force_solid_disk",
     "connect_load_path",
     "config", "config_p", "batch_configs", "perturb", "perturb_seed",
+    "output_dof_load",
 ]
 
 
@@ -443,6 +444,26 @@ def config_p(Emin=1.0, rho=None):
     f = point_load(desc, (80, 80), 0, -1.0, f)
     return Problem("square2d_100x100", desc, np.asarray(rho, np.float64),
                    fixed, f, tol=1e-6)
+
+
+def output_dof_load(desc, rho, fixed, seed):
+    """Adjoint load of a compliant-mechanism style output: a unit load on a
+    seeded free DOF whose node touches solid material (rho >= 0.5)."""
+    rng = np.random.default_rng(seed)
+    dim = desc["dim"]
+    nel = desc["nel"]
+    shape = tuple(nel)
+    solid = (np.asarray(rho).reshape(shape[::-1]).transpose() >= 0.5)
+    node_solid = np.zeros(tuple(n + 1 for n in shape), dtype=bool)
+    for corner in np.ndindex(*(2,) * dim):
+        sl = tuple(slice(c, c + n) for c, n in zip(corner, shape))
+        node_solid[sl] |= solid
+    flat = np.ascontiguousarray(node_solid.transpose()).ravel()
+    cand = [dim * p + c for p in np.nonzero(flat)[0] for c in range(dim)
+            if fixed[dim * p + c] == 0]
+    f = np.zeros(n_dofs(desc))
+    f[cand[int(rng.integers(len(cand)))]] = 1.0
+    return f
 
 
 def perturb_seed(run, t):

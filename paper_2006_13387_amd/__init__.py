@@ -5,7 +5,9 @@ The compute path is the HIP library libmsp.so built from csrc/ for gfx950;
 this package only marshals arguments (see binding.py).
 """
 from .binding import (EXPORTS, LIB_PATH, Batch, MspError, ProblemDesc,
-                      SolveInfo, Solver, load_library, make_desc, vec_dot)
+                      Server, SolveInfo, Solver, load_library, make_desc,
+                      vec_dot)
 
 __all__ = ["EXPORTS", "LIB_PATH", "Batch", "MspError", "ProblemDesc",
-           "SolveInfo", "Solver", "load_library", "make_desc", "vec_dot"]
+           "Server", "SolveInfo", "Solver", "load_library", "make_desc",
+           "vec_dot"]

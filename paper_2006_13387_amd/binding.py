@@ -52,7 +52,10 @@ EXPORTS = ["msp_create", "msp_destroy", "msp_last_error", "msp_set_densities",
            "msp_apply_coarse", "msp_apply_prec", "msp_coarse_info",
            "msp_coarse_basis", "msp_vec_dot", "msp_query",
            "msp_kernel_timing", "msp_batch_create", "msp_batch_destroy",
-           "msp_batch_last_error", "msp_batch_solve", "msp_batch_stats"]
+           "msp_batch_last_error", "msp_batch_solve", "msp_batch_stats",
+           "msp_server_create", "msp_server_destroy", "msp_server_last_error",
+           "msp_server_add_run", "msp_server_submit", "msp_server_step",
+           "msp_server_result", "msp_server_stats"]
 
 KERNEL_NAMES = ["level1_apply", "cg_matvec", "heat_eigen", "combine",
                 "coarse_restrict", "local_factor"]
@@ -97,8 +100,21 @@ def load_library(path=LIB_PATH):
                                   ctypes.POINTER(SolveInfo)]
     L.msp_batch_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(ctypes.c_int64)]
+    L.msp_server_create.argtypes = [ctypes.c_int64, i32, ctypes.POINTER(vp)]
+    L.msp_server_destroy.argtypes = [vp]
+    L.msp_server_last_error.argtypes = [vp]
+    L.msp_server_last_error.restype = ctypes.c_char_p
+    L.msp_server_add_run.argtypes = [vp, ctypes.POINTER(ProblemDesc), vp,
+                                     ctypes.POINTER(i32)]
+    L.msp_server_submit.argtypes = [vp, i32, vp, vp, vp, vp, vp, dbl, i32,
+                                    ctypes.POINTER(i32)]
+    L.msp_server_step.argtypes = [vp, vp, ctypes.POINTER(i32)]
+    L.msp_server_result.argtypes = [vp, i32, ctypes.POINTER(SolveInfo),
+                                    ctypes.POINTER(ctypes.c_double)]
+    L.msp_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     for name in EXPORTS:
-        if name not in ("msp_last_error", "msp_batch_last_error"):
+        if name not in ("msp_last_error", "msp_batch_last_error",
+                        "msp_server_last_error"):
             getattr(L, name).restype = i32
     _lib = L
     return L
@@ -306,6 +322,84 @@ class Batch:
         c, g = ctypes.c_int64(), ctypes.c_int64()
         self.L.msp_batch_stats(self.b, ctypes.byref(c), ctypes.byref(g))
         return {"chunks": c.value, "graph_chunks": g.value}
+
+
+class Server:
+    """Continuous batching of state and adjoint solves of many runs."""
+
+    def __init__(self, hbm_budget_bytes, max_active):
+        self.L = load_library()
+        sv = ctypes.c_void_p()
+        st = self.L.msp_server_create(int(hbm_budget_bytes), int(max_active),
+                                      ctypes.byref(sv))
+        if st != 0:
+            raise MspError(st, self.L.msp_server_last_error(None).decode())
+        self.sv = sv
+        self._keep = {}          # tensors the server reads or writes
+
+    def _check(self, st, ok=(0,)):
+        if st not in ok:
+            raise MspError(st, self.L.msp_server_last_error(self.sv).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "sv", None):
+            self.L.msp_server_destroy(self.sv)
+            self.sv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_run(self, desc, fixed):
+        pd = make_desc(desc)
+        mask = np.ascontiguousarray(np.asarray(fixed, dtype=np.uint8))
+        rid = ctypes.c_int32()
+        self._check(self.L.msp_server_add_run(
+            self.sv, ctypes.byref(pd), mask.ctypes.data_as(ctypes.c_void_p),
+            ctypes.byref(rid)))
+        return rid.value
+
+    def submit(self, run, rho, f_state, f_adj=None, rtol=1e-8, maxit=5000):
+        """Queue a request; returns (ticket, u_state, u_adj) with the output
+        tensors filled when the request completes."""
+        import torch
+        us = torch.zeros_like(f_state)
+        ua = torch.zeros_like(f_adj) if f_adj is not None else None
+        t = ctypes.c_int32()
+        self._check(self.L.msp_server_submit(
+            self.sv, int(run), _ptr(rho), _ptr(f_state),
+            _ptr(f_adj) if f_adj is not None else None, _ptr(us),
+            _ptr(ua) if ua is not None else None, float(rtol), int(maxit),
+            ctypes.byref(t)))
+        self._keep[t.value] = (rho, f_state, f_adj, us, ua)
+        return t.value, us, ua
+
+    def step(self):
+        n = ctypes.c_int32()
+        self._check(self.L.msp_server_step(self.sv, _stream(), ctypes.byref(n)))
+        return n.value
+
+    def result(self, ticket):
+        """(state info, adjoint info, latency ms) or None while pending."""
+        infos = (SolveInfo * 2)()
+        lat = ctypes.c_double()
+        st = self.L.msp_server_result(self.sv, int(ticket), infos,
+                                      ctypes.byref(lat))
+        if st == -7:
+            return None
+        self._check(st, ok=(0, 1))
+        self._keep.pop(ticket, None)
+        return infos[0].as_dict(), infos[1].as_dict(), lat.value
+
+    def stats(self):
+        v = (ctypes.c_double * 8)()
+        self._check(self.L.msp_server_stats(self.sv, v))
+        keys = ["completed", "p50_ms", "p99_ms", "solves_per_s", "hbm_bytes",
+                "queued", "active", "chunks"]
+        return dict(zip(keys, list(v)))
 
 
 def vec_dot(x, y):

@@ -1580,6 +1580,409 @@ extern "C" msp_status msp_batch_stats(const msp_batch* b, int64_t* chunks,
   return MSP_OK;
 }
 
+// ------------------------------------------------------------------ serving
+
+// Projected device bytes of a handle after its setup (vectors, local factor
+// records, eigen workspaces and modes, coarse matrices at the largest
+// coarse dimension kmax allows).
+static long long handle_projected_bytes(const msp_handle* h) {
+  const long long nd = h->n_dofs, nn = h->n_nodes, ne = h->n_elems;
+  const int kmax = h->desc.eig_kmax;
+  long long ldk = 0;
+  ldk = (long long)h->cn_h.size() * (2 * kmax + 1);
+  long long b = 10 * nd * 8 + nd + nn + ne * 8;
+  b += h->l1_entries * (8 + (h->fp32 ? 4 : 0)) + h->l1_vec * 8;
+  b += h->om_entries * 8 + h->om_vec * (long long)h->eig_m * 8 * 3 + h->om_vec * kmax * 8;
+  b += 3 * ldk * ldk * 8 + 4 * ldk * 8;
+  return b;
+}
+
+struct SvRun {
+  msp_problem_desc desc{};
+  std::vector<uint8_t> mask;
+  msp_handle* h = nullptr;
+  double* d_us = nullptr;      // last state solution (warm start)
+  double* d_ua = nullptr;      // last adjoint solution
+  bool have_us = false, have_ua = false;
+  long long bytes = 0;         // projected handle bytes
+  long long last_use = 0;
+  bool busy = false;           // a request of this run is admitted
+};
+
+struct SvReq {
+  int run = -1;
+  const double* rho = nullptr;
+  const double* fs = nullptr;
+  const double* fa = nullptr;
+  double* us_out = nullptr;
+  double* ua_out = nullptr;
+  double rtol = 1e-8;
+  int maxit = 5000;
+  int phase = 0;               // 0 queued, 2 state, 3 adjoint, 4 done, -1 failed
+  SolveRun R;
+  msp_solve_info info[2]{};
+  double t_sub = 0.0, t_done = 0.0;
+  msp_status status = MSP_OK;
+};
+
+struct msp_server {
+  long long budget = 0;
+  int max_active = 0;
+  std::vector<SvRun> runs;
+  std::vector<SvReq> reqs;
+  std::vector<int> queue;      // request ids, arrival order
+  std::vector<int> active;     // admitted, not finished
+  hipStream_t s_setup = nullptr;
+  msp_batch batch;
+  std::vector<msp_handle*> batch_hs;   // handles the batch tables hold
+  long long clock = 0;
+  std::vector<double> lat_ms;
+  long long solves = 0;
+  double t_first = -1.0, t_last = 0.0;
+  std::string err;
+};
+
+static double sv_now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+static msp_status sfail(msp_server* sv, msp_status st, const std::string& msg) {
+  if (sv) sv->err = msg;
+  g_static_err = msg;
+  return st;
+}
+
+extern "C" msp_status msp_server_create(int64_t hbm_budget_bytes, int32_t max_active,
+                                        msp_server** out) {
+  if (!out || hbm_budget_bytes <= 0 || max_active < 1)
+    return sfail(nullptr, MSP_E_INVALID, "need a positive budget and max_active >= 1");
+  msp_server* sv = new msp_server();
+  sv->budget = hbm_budget_bytes;
+  sv->max_active = max_active;
+  if (hipStreamCreateWithFlags(&sv->s_setup, hipStreamNonBlocking) != hipSuccess) {
+    delete sv;
+    return sfail(nullptr, MSP_E_DEVICE, "stream creation failed");
+  }
+  *out = sv;
+  return MSP_OK;
+}
+
+extern "C" msp_status msp_server_destroy(msp_server* sv) {
+  if (!sv) return MSP_OK;
+  if (sv->s_setup) (void)hipStreamSynchronize(sv->s_setup);
+  for (SvRun& r : sv->runs) {
+    msp_destroy(r.h);
+    dfree(r.d_us);
+    dfree(r.d_ua);
+  }
+  if (sv->batch.gexec) (void)hipGraphExecDestroy(sv->batch.gexec);
+  batch_free_tables(&sv->batch);
+  sv->batch.gexec = nullptr;
+  if (sv->s_setup) (void)hipStreamDestroy(sv->s_setup);
+  delete sv;
+  return MSP_OK;
+}
+
+extern "C" const char* msp_server_last_error(const msp_server* sv) {
+  return sv ? sv->err.c_str() : g_static_err.c_str();
+}
+
+extern "C" msp_status msp_server_add_run(msp_server* sv, const msp_problem_desc* d,
+                                         const uint8_t* fixed_mask_host,
+                                         int32_t* run_id) {
+  if (!sv || !d || !fixed_mask_host || !run_id)
+    return sfail(sv, MSP_E_INVALID, "null argument");
+  // validate by building the geometry once (no device memory is kept)
+  msp_handle* probe = nullptr;
+  msp_status st = msp_create(d, fixed_mask_host, &probe);
+  if (st != MSP_OK) return sfail(sv, st, g_static_err);
+  SvRun r;
+  r.desc = *d;
+  r.mask.assign(fixed_mask_host, fixed_mask_host + probe->n_dofs);
+  r.bytes = handle_projected_bytes(probe) + 2 * probe->n_dofs * 8;
+  msp_destroy(probe);
+  sv->runs.push_back(std::move(r));
+  *run_id = (int32_t)sv->runs.size() - 1;
+  return MSP_OK;
+}
+
+extern "C" msp_status msp_server_submit(msp_server* sv, int32_t run_id,
+                                        const double* rho_dev,
+                                        const double* f_state_dev,
+                                        const double* f_adj_dev,
+                                        double* u_state_dev, double* u_adj_dev,
+                                        double rtol, int32_t maxit,
+                                        int32_t* ticket) {
+  if (!sv || !rho_dev || !f_state_dev || !u_state_dev || !ticket)
+    return sfail(sv, MSP_E_INVALID, "null argument");
+  if (run_id < 0 || run_id >= (int)sv->runs.size())
+    return sfail(sv, MSP_E_INVALID, "unknown run");
+  if ((f_adj_dev == nullptr) != (u_adj_dev == nullptr))
+    return sfail(sv, MSP_E_INVALID, "adjoint load and output go together");
+  if (maxit < 1 || !(rtol > 0.0)) return sfail(sv, MSP_E_INVALID, "need maxit >= 1, rtol > 0");
+  SvReq q;
+  q.run = run_id;
+  q.rho = rho_dev;
+  q.fs = f_state_dev;
+  q.fa = f_adj_dev;
+  q.us_out = u_state_dev;
+  q.ua_out = u_adj_dev;
+  q.rtol = rtol;
+  q.maxit = maxit;
+  q.t_sub = sv_now_ms();
+  if (sv->t_first < 0) sv->t_first = q.t_sub;
+  sv->reqs.push_back(q);
+  *ticket = (int32_t)sv->reqs.size() - 1;
+  sv->queue.push_back(*ticket);
+  return MSP_OK;
+}
+
+static long long sv_in_use(const msp_server* sv) {
+  long long b = 0;
+  for (const SvRun& r : sv->runs)
+    if (r.h) b += r.bytes;
+  return b;
+}
+
+// Room for run r's handle: evict the setups of idle runs, least recently
+// used first (their warm-start vectors stay).
+static bool sv_make_room(msp_server* sv, int r) {
+  const long long need = sv->runs[r].bytes;
+  while (sv_in_use(sv) + need > sv->budget) {
+    int victim = -1;
+    for (int k = 0; k < (int)sv->runs.size(); ++k) {
+      const SvRun& v = sv->runs[k];
+      if (k == r || !v.h || v.busy) continue;
+      if (victim < 0 || v.last_use < sv->runs[victim].last_use) victim = k;
+    }
+    if (victim < 0) return false;
+    // the batch tables may still point into the victim
+    msp_destroy(sv->runs[victim].h);
+    sv->runs[victim].h = nullptr;
+    sv->batch_hs.clear();
+  }
+  return true;
+}
+
+// Start solve (state or adjoint) of request q on its run's handle: a first
+// segment on stream s, synchronised; R.iterating tells whether it iterates.
+static msp_status sv_start_solve(msp_server* sv, SvReq& q, bool adjoint, hipStream_t s) {
+  SvRun& r = sv->runs[q.run];
+  sv->batch_hs.clear();          // run_begin may reallocate the histories
+  q.R = SolveRun();
+  q.R.h = r.h;
+  q.R.f = adjoint ? q.fa : q.fs;
+  q.R.u = adjoint ? r.d_ua : r.d_us;
+  q.R.rtol = q.rtol;
+  q.R.maxit = q.maxit;
+  msp_status st = run_begin(q.R, adjoint ? r.have_ua : r.have_us, s);
+  if (st == MSP_OK) st = seg_launch(q.R, s);
+  if (st == MSP_OK && hipStreamSynchronize(s) != hipSuccess) st = MSP_E_DEVICE;
+  if (st == MSP_OK) st = seg_started(q.R, s);
+  q.phase = adjoint ? 3 : 2;
+  return st;
+}
+
+// Admit queued requests (arrival order, one request per run at a time) while
+// the active slots and the HBM budget allow: densities and setup on the
+// setup stream, then the first segment of the state solve.
+static msp_status sv_admit(msp_server* sv) {
+  for (size_t qi = 0; qi < sv->queue.size();) {
+    if ((int)sv->active.size() >= sv->max_active) break;
+    const int id = sv->queue[qi];
+    SvReq& q = sv->reqs[id];
+    SvRun& r = sv->runs[q.run];
+    if (r.busy) {
+      ++qi;
+      continue;
+    }
+    if (!r.h) {
+      if (!sv_make_room(sv, q.run)) break;          // wait for memory
+      msp_status st = msp_create(&r.desc, r.mask.data(), &r.h);
+      if (st != MSP_OK) return sfail(sv, st, g_static_err);
+      if (!r.d_us) {
+        const long long nd = r.h->n_dofs;
+        if (dalloc(&r.d_us, nd) != hipSuccess || dalloc(&r.d_ua, nd) != hipSuccess)
+          return sfail(sv, MSP_E_NOMEM, "warm-start vectors");
+      }
+    }
+    r.busy = true;
+    r.last_use = ++sv->clock;
+    sv->queue.erase(sv->queue.begin() + qi);
+    sv->active.push_back(id);
+    msp_status st = msp_set_densities(r.h, q.rho, sv->s_setup);
+    if (st == MSP_OK) st = msp_setup(r.h, sv->s_setup);
+    if (st == MSP_OK) st = sv_start_solve(sv, q, false, sv->s_setup);
+    if (st != MSP_OK) {
+      q.status = st;
+      q.phase = -1;
+    }
+  }
+  return MSP_OK;
+}
+
+// The run of q finished its current solve: state -> adjoint, adjoint -> done.
+static void sv_solve_finished(msp_server* sv, SvReq& q, hipStream_t s) {
+  SvRun& r = sv->runs[q.run];
+  const bool adjoint = q.phase == 3;
+  msp_solve_info& inf = q.info[adjoint ? 1 : 0];
+  const msp_status st = run_end(q.R, s, &inf);
+  inf.t_setup_ms = adjoint ? 0.0 : r.h->t_setup_ms;
+  if (st < 0) {
+    q.status = st;
+    q.phase = -1;
+    return;
+  }
+  if (st > 0 && q.status == MSP_OK) q.status = st;
+  ++sv->solves;
+  const long long nd = r.h->n_dofs;
+  if (!adjoint) {
+    r.have_us = true;
+    (void)hipMemcpyAsync(q.us_out, r.d_us, nd * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (q.fa) {
+      const msp_status s2 = sv_start_solve(sv, q, true, s);
+      if (s2 != MSP_OK) {
+        q.status = s2;
+        q.phase = -1;
+      }
+      return;
+    }
+  } else {
+    r.have_ua = true;
+    (void)hipMemcpyAsync(q.ua_out, r.d_ua, nd * sizeof(double), hipMemcpyDeviceToDevice, s);
+  }
+  q.phase = 4;
+}
+
+extern "C" msp_status msp_server_step(msp_server* sv, hipStream_t s,
+                                      int32_t* n_completed) {
+  if (!sv) return sfail(sv, MSP_E_INVALID, "null server");
+  if (n_completed) *n_completed = 0;
+  // 1. one chunk of lockstep iterations for every solve that iterates
+  std::vector<int> it_ids;
+  std::vector<msp_handle*> hs;
+  for (int id : sv->active) {
+    SvReq& q = sv->reqs[id];
+    if ((q.phase == 2 || q.phase == 3) && !q.R.finished && q.R.iterating) {
+      it_ids.push_back(id);
+      hs.push_back(q.R.h);
+    }
+  }
+  if (!hs.empty()) {
+    if (hs != sv->batch_hs) {
+      std::vector<unsigned char> key;
+      const msp_status st = batch_tables(&sv->batch, hs, s, &key);
+      if (st != MSP_OK) return sfail(sv, st, sv->batch.err);
+      sv->batch_hs = hs;
+    }
+    chunk_batch(&sv->batch, s);
+    ++sv->batch.chunks;
+    for (int id : it_ids) {
+      msp_handle* h = sv->reqs[id].R.h;
+      (void)hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(CGScalars), hipMemcpyDeviceToHost, s);
+    }
+  }
+  // 2. admissions: their setups run on the setup stream while the chunk
+  //    runs on s
+  msp_status st = sv_admit(sv);
+  if (st != MSP_OK) return st;
+  if (hipStreamSynchronize(s) != hipSuccess || hipStreamSynchronize(sv->s_setup) != hipSuccess)
+    return sfail(sv, MSP_E_DEVICE, "stream synchronisation failed");
+  for (int id : it_ids) {
+    SvReq& q = sv->reqs[id];
+    if (q.R.h->h_sc->done) q.R.iterating = false;
+  }
+  // 3. segments that ended: finish, restart, or move on to the next solve
+  for (int id : sv->active) {
+    SvReq& q = sv->reqs[id];
+    for (int guard = 0; guard < 8; ++guard) {
+      if (!(q.phase == 2 || q.phase == 3) || q.R.iterating) break;
+      bool restart = false;
+      if (!q.R.finished) {
+        st = seg_finish(q.R, s, &restart);
+        if (st != MSP_OK) {
+          q.status = st;
+          q.phase = -1;
+          break;
+        }
+      }
+      if (restart) {
+        st = seg_launch(q.R, s);
+        if (st == MSP_OK && hipStreamSynchronize(s) != hipSuccess) st = MSP_E_DEVICE;
+        if (st == MSP_OK) st = seg_started(q.R, s);
+        if (st != MSP_OK) {
+          q.status = st;
+          q.phase = -1;
+        }
+        continue;
+      }
+      if (q.R.finished) sv_solve_finished(sv, q, s);   // may start the adjoint
+    }
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return sfail(sv, MSP_E_DEVICE, "stream synchronisation failed");
+  // 4. retire finished requests
+  int done = 0;
+  std::vector<int> keep;
+  for (int id : sv->active) {
+    SvReq& q = sv->reqs[id];
+    if (q.phase == 4 || q.phase == -1) {
+      q.t_done = sv_now_ms();
+      sv->runs[q.run].busy = false;
+      if (q.phase == 4) {
+        sv->lat_ms.push_back(q.t_done - q.t_sub);
+        sv->t_last = q.t_done;
+      }
+      ++done;
+    } else {
+      keep.push_back(id);
+    }
+  }
+  sv->active.swap(keep);
+  if (n_completed) *n_completed = done;
+  return MSP_OK;
+}
+
+extern "C" msp_status msp_server_result(msp_server* sv, int32_t ticket,
+                                        msp_solve_info* info2_host,
+                                        double* latency_ms) {
+  if (!sv || ticket < 0 || ticket >= (int)sv->reqs.size())
+    return sfail(sv, MSP_E_INVALID, "unknown ticket");
+  const SvReq& q = sv->reqs[ticket];
+  if (q.phase != 4 && q.phase != -1) return MSP_E_STATE;
+  if (info2_host) {
+    info2_host[0] = q.info[0];
+    info2_host[1] = q.info[1];
+  }
+  if (latency_ms) *latency_ms = q.t_done - q.t_sub;
+  return q.phase == 4 ? q.status : (q.status < 0 ? q.status : MSP_E_DEVICE);
+}
+
+// stats (8 doubles): completed requests, p50 and p99 latency (ms), solves/s
+// (state and adjoint solves completed per second of wall time from the
+// first submission to the last completion), projected HBM in use (bytes),
+// queued, active, batched chunks run.
+extern "C" msp_status msp_server_stats(const msp_server* sv, double* out8) {
+  if (!sv || !out8) return MSP_E_INVALID;
+  std::vector<double> l = sv->lat_ms;
+  std::sort(l.begin(), l.end());
+  auto pct = [&](double p) {
+    if (l.empty()) return 0.0;
+    const size_t i = std::min(l.size() - 1, (size_t)std::llround(p * (l.size() - 1)));
+    return l[i];
+  };
+  const double span = (sv->t_first >= 0 && sv->t_last > sv->t_first) ? (sv->t_last - sv->t_first) : 0.0;
+  out8[0] = (double)l.size();
+  out8[1] = pct(0.5);
+  out8[2] = pct(0.99);
+  out8[3] = span > 0 ? sv->solves / (span * 1e-3) : 0.0;
+  out8[4] = (double)sv_in_use(sv);
+  out8[5] = (double)sv->queue.size();
+  out8[6] = (double)sv->active.size();
+  out8[7] = (double)sv->batch.chunks;
+  return MSP_OK;
+}
+
 extern "C" msp_status msp_coarse_info(msp_handle* h, int32_t* n_modes,
                                       double* eigvals, int32_t* n_cnodes,
                                       int32_t* n_coarse, int32_t* cap_hits) {

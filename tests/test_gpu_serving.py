@@ -1,0 +1,123 @@
+"""GPU: the serving loop (continuous batching) against each run served alone.
+
+Three runs of uneven size submit requests (new densities, a state load and
+an adjoint load) in two waves, so later requests are admitted while earlier
+ones iterate.  Every solve keeps the arithmetic of msp_solve on its run's
+handle with its warm start, so each result must be bitwise the one the run
+gets when it is served alone; a second server whose memory budget holds one
+run's setup at a time (evictions and rebuilt setups) must give the same
+bits again.
+"""
+import numpy as np
+import pytest
+
+import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _msp():
+    import paper_2006_13387_amd as msp
+    return msp
+
+
+def _runs():
+    return [inputs.config(0),
+            inputs.scaled_cantilever_2d((64, 32), 4001, sub=16, precision=1),
+            inputs.scaled_cantilever_2d((96, 32), 4002, sub=16, precision=1)]
+
+
+def _requests(p, r, nreq):
+    out = []
+    rho = p.rho
+    for t in range(nreq):
+        rho = inputs.perturb(rho, p.desc["nel"], inputs.perturb_seed(4000 + r, t))
+        fa = inputs.output_dof_load(p.desc, rho, p.fixed, 7000 + 10 * r + t)
+        out.append((torch.tensor(rho, device="cuda"),
+                    torch.tensor(p.f, device="cuda"),
+                    torch.tensor(fa, device="cuda")))
+    return out
+
+
+def _serve(server, runs, reqs, order):
+    """Submit the requests of (run, t) in order, two waves, step to the end;
+    return {(run, t): (u_state, u_adj, infos)}."""
+    rid = {r: server.add_run(runs[r].desc, runs[r].fixed) for r in sorted({r for r, _ in order})}
+    tickets = {}
+    half = len(order) // 2
+    for k, (r, t) in enumerate(order):
+        rho, fs, fa = reqs[r][t]
+        tickets[(r, t)] = server.submit(rid[r], rho, fs, fa, rtol=1e-8)
+        if k == half:
+            for _ in range(2):
+                server.step()            # first wave in flight
+    for _ in range(10000):
+        if all(server.result(tk[0]) is not None for tk in tickets.values()):
+            break
+        server.step()
+    out = {}
+    for key, (tk, us, ua) in tickets.items():
+        res = server.result(tk)
+        assert res is not None, key
+        out[key] = (us.clone(), ua.clone(), res)
+    return out
+
+
+def test_serving_results_alone_equal_mixed_and_under_eviction():
+    msp = _msp()
+    runs = _runs()
+    nreq = 2
+    reqs = [_requests(p, r, nreq) for r, p in enumerate(runs)]
+    order = [(r, t) for t in range(nreq) for r in range(len(runs))]
+    mixed = _serve(msp.Server(1 << 40, 3), runs, reqs, order)
+    for r in range(len(runs)):
+        alone = _serve(msp.Server(1 << 40, 1), runs, reqs, [(r, t) for t in range(nreq)])
+        for t in range(nreq):
+            um, am, (i0, i1, _) = mixed[(r, t)]
+            ua_, aa, (j0, j1, _) = alone[(r, t)]
+            print(f"[serve] run {r} req {t}: iters {i0['iters']}/{i1['iters']} "
+                  f"relres {i0['relres_true']:.1e}/{i1['relres_true']:.1e}", flush=True)
+            assert torch.equal(um, ua_), (r, t)
+            assert torch.equal(am, aa), (r, t)
+            assert i0["iters"] == j0["iters"] and i1["iters"] == j1["iters"]
+            assert i0["relres_true"] <= 1e-7 and i1["relres_true"] <= 1e-7
+    # a budget that holds one run's setup at a time: evictions, same bits
+    one = max(_projected(runs))
+    tight = _serve(msp.Server(int(one * 1.2), 3), runs, reqs, order)
+    for key in mixed:
+        assert torch.equal(tight[key][0], mixed[key][0]), key
+        assert torch.equal(tight[key][1], mixed[key][1]), key
+
+
+def _projected(runs):
+    """Projected bytes per run, read back from a server's stats."""
+    msp = _msp()
+    out = []
+    for p in runs:
+        sv = msp.Server(1 << 40, 1)
+        rid = sv.add_run(p.desc, p.fixed)
+        rho = torch.tensor(p.rho, device="cuda")
+        f = torch.tensor(p.f, device="cuda")
+        tk, _, _ = sv.submit(rid, rho, f, rtol=1e-6)
+        sv.step()
+        out.append(sv.stats()["hbm_bytes"])
+        for _ in range(1000):
+            if sv.result(tk) is not None:
+                break
+            sv.step()
+        sv.close()
+    return out
+
+
+def test_serving_latency_stats():
+    msp = _msp()
+    runs = _runs()[:2]
+    reqs = [_requests(p, r, 2) for r, p in enumerate(runs)]
+    sv = msp.Server(1 << 40, 2)
+    _serve(sv, runs, reqs, [(r, t) for t in range(2) for r in range(2)])
+    st = sv.stats()
+    print(f"[serve] stats {st}", flush=True)
+    assert st["completed"] == 4
+    assert 0 < st["p50_ms"] <= st["p99_ms"]
+    assert st["solves_per_s"] > 0
