@@ -44,6 +44,16 @@ def parse():
                     help="one contrast, no FP64 leg (for profiler runs)")
     ap.add_argument("--no-matvec-probe", action="store_true",
                     help="skip the HBM-sized stiffness-product probe")
+    ap.add_argument("--workload", choices=("cantilever", "batch", "serving"),
+                    default="cantilever",
+                    help="cantilever: the 512x256 benchmark (default line); "
+                         "batch: 64 uneven cantilevers solved in lockstep; "
+                         "serving: Poisson stream of state+adjoint requests")
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--serve-runs", type=int, default=32)
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-rate", type=float, default=200.0,
+                    help="mean arrival rate (requests/s)")
     ap.add_argument("--kernel-probe", action="store_true",
                     help="only launch the profiled kernels: first-level "
                          "applies (Emin 1e-6, FP32 path), stiffness products "
@@ -125,6 +135,134 @@ def level1_traffic(launches_by_contrast):
     if tot == 0 or any(k not in per for k in launches_by_contrast):
         return None
     return sum(n * per[k] for k, n in launches_by_contrast.items()) / tot
+
+
+def batch_workload(torch, args):
+    """64 independent 2D cantilevers of uneven size (128x64 .. 768x384,
+    config-1 style densities at Emin 1e-6, FP32 local solves): setups, then
+    the PCG solves of all of them in lockstep (one launch per iteration
+    kernel, graph-captured chunks), against the same solves one at a time."""
+    import inputs
+    import paper_2006_13387_amd as msp
+    t0 = time.perf_counter()
+    probs = inputs.batch_configs(count=args.batch_count)
+    log(f"[batch] {len(probs)} problems generated in {time.perf_counter() - t0:.1f} s; "
+        f"{sum(len(p.f) for p in probs)} DOFs")
+    solvers = [msp.Solver(p.desc, p.fixed) for p in probs]
+    fs = [torch.tensor(p.f, device="cuda") for p in probs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, p in zip(solvers, probs):
+        s.set_densities(torch.tensor(p.rho, device="cuda"))
+        s.setup()
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    b = msp.Batch()
+    b.solve(solvers, fs, use_graph=True)           # warm-up, graph capture
+    res = {}
+    for name, graph in (("batched_graph", True), ("batched_eager", False)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        us, infos = b.solve(solvers, fs, use_graph=graph)
+        torch.cuda.synchronize()
+        res[name] = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = [s.solve(f)[1] for s, f in zip(solvers, fs)]
+    torch.cuda.synchronize()
+    res["one_at_a_time"] = time.perf_counter() - t0
+    n = len(probs)
+    conv = sum(1 for i in infos if i["relres_true"] <= 1e-8)
+    out = {
+        "metric": "batched state solves/s to relres 1e-8 (solve only, setups before)",
+        "value": round(n / res["batched_graph"], 3), "unit": "solves/s",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "f64 (FP32 local inverses)",
+        "data": "synthetic",
+        "config": {"workload": f"{n} 2D cantilevers, sizes 128x64..768x384 Q1, "
+                               "Emin 1e-6, S=32 overlap 2, FP32 local",
+                   "dofs_total": int(sum(len(p.f) for p in probs))},
+        "seconds": {k: round(v, 4) for k, v in res.items()},
+        "setup_seconds_one_at_a_time": round(t_setup, 4),
+        "speedup_batched_over_one_at_a_time": round(res["one_at_a_time"] / res["batched_graph"], 3),
+        "iterations_max": max(i["iters"] for i in infos),
+        "iterations_mean": round(sum(i["iters"] for i in infos) / n, 1),
+        "converged_to_1e-8": conv,
+        "relres_true_max": max(i["relres_true"] for i in infos),
+        "same_as_one_at_a_time": all(i["iters"] == j["iters"] for i, j in zip(infos, seq)),
+        "batch_stats": b.stats(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def serving_workload(torch, args):
+    """Poisson stream of state + adjoint requests from concurrent 2D runs
+    (256x128 .. 1024x512 Q1, Emin 1e-6 / 1e-9, FP32 local solves): each
+    request perturbs its run's densities (setup rebuilt) and warm-starts
+    from the run's previous solutions."""
+    import numpy as np
+    import inputs
+    import paper_2006_13387_amd as msp
+    rng = np.random.default_rng(4)
+    sizes = ((256, 128), (512, 256), (768, 384), (1024, 512))
+    runs = []
+    t0 = time.perf_counter()
+    for r in range(args.serve_runs):
+        nel = sizes[int(rng.integers(len(sizes)))]
+        emin = (1e-6, 1e-9)[int(rng.integers(2))]
+        runs.append(inputs.scaled_cantilever_2d(nel, 4000 + r, Emin=emin, precision=1))
+    log(f"[serve] {len(runs)} runs generated in {time.perf_counter() - t0:.1f} s")
+    # requests: run r's t-th request perturbs its densities
+    order = [int(rng.integers(len(runs))) for _ in range(args.serve_requests)]
+    count = [0] * len(runs)
+    rho_now = [p.rho.copy() for p in runs]
+    reqs = []
+    for r in order:
+        t = count[r]
+        count[r] += 1
+        p = runs[r]
+        rho_now[r] = inputs.perturb(rho_now[r], p.desc["nel"], inputs.perturb_seed(4000 + r, t))
+        fa = inputs.output_dof_load(p.desc, rho_now[r], p.fixed, 5000 + 100 * r + t)
+        reqs.append((r, torch.tensor(rho_now[r], device="cuda"),
+                     torch.tensor(p.f, device="cuda"), torch.tensor(fa, device="cuda")))
+    arrivals = np.cumsum(rng.exponential(1.0 / args.serve_rate, len(reqs)))
+    sv = msp.Server(250 << 30, 16)
+    rid = [sv.add_run(p.desc, p.fixed) for p in runs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nxt = 0
+    tickets = []
+    while True:
+        now = time.perf_counter() - t0
+        while nxt < len(reqs) and arrivals[nxt] <= now:
+            r, rho, fs, fa = reqs[nxt]
+            tickets.append(sv.submit(rid[r], rho, fs, fa)[0])
+            nxt += 1
+        st = sv.stats()
+        if nxt == len(reqs) and st["completed"] == len(reqs):
+            break
+        if st["active"] == 0 and st["queued"] == 0 and nxt < len(reqs):
+            time.sleep(max(0.0, arrivals[nxt] - now))
+            continue
+        sv.step()
+    wall = time.perf_counter() - t0
+    st = sv.stats()
+    infos = [sv.result(t) for t in tickets]
+    conv = sum(1 for a, b, _ in infos if a["relres_true"] <= 1e-8 and b["relres_true"] <= 1e-8)
+    out = {
+        "metric": "served state+adjoint solves/s and p50/p99 request latency",
+        "value": round(st["solves_per_s"], 3), "unit": "solves/s",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "f64 (FP32 local inverses)",
+        "data": "synthetic",
+        "config": {"workload": f"{len(runs)} 2D runs (256x128..1024x512 Q1, Emin 1e-6/1e-9), "
+                               f"{len(reqs)} requests, Poisson {args.serve_rate:g}/s, "
+                               "perturbed densities (amplitude 0.05), warm starts",
+                   "max_active": 16, "hbm_budget_gib": 250},
+        "latency_ms": {"p50": round(st["p50_ms"], 2), "p99": round(st["p99_ms"], 2)},
+        "wall_seconds": round(wall, 3),
+        "requests_converged_to_1e-8": conv,
+        "chunks": int(st["chunks"]),
+    }
+    print(json.dumps(out), flush=True)
 
 
 def kernel_probe(torch):
@@ -350,6 +488,12 @@ def main():
     msp.load_library()
     if args.kernel_probe:
         kernel_probe(torch)
+        return
+    if args.workload == "batch":
+        batch_workload(torch, args)
+        return
+    if args.workload == "serving":
+        serving_workload(torch, args)
         return
     contrasts = CONTRASTS[1:2] if args.quick else CONTRASTS
     probs = [inputs.config(1, Emin=e) for e in contrasts]
