@@ -28,7 +28,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 CONTRASTS = (1e-3, 1e-6, 1e-9)
-CPU_STRIDE = 2          # the CPU baseline samples every 2nd local problem
+CPU_STRIDE = 1          # the CPU baseline times every local problem
 HBM_PEAK_GBS = 8000.0
 
 

@@ -823,45 +823,90 @@ __device__ void omega_stencil(const Geom& g, const SysDesc& s,
   }
 }
 
-// G = Y^T Z (m x m) into LDS G[MAXM*MAXM]; stage is LDS scratch of
-// 2*MAXM*64 doubles.
-__device__ void gram(const double* Y, const double* Z, int n, int m,
-                     double* G, double* stage) {
+// G = Y^T Z (m x m, symmetrised) into LDS G[MAXM*MAXM].  Chunks of
+// GR_NC nodes of Y and Z are staged in LDS (stage: 2*MAXM*GR_NC doubles;
+// the next chunk is loaded into registers while the current one is used).
+// Thread t = 32 sb + grp accumulates the 8 x 8 block sb of G over the
+// chunk nodes grp, grp + 32; the 32 partial blocks of a block are then
+// summed across the lanes (fixed butterfly order).
+constexpr int GR_NC = 64;                       // nodes per chunk
+constexpr int GR_PF = (2 * MAXM * GR_NC + EG_NT - 1) / EG_NT;   // prefetch regs
+__device__ void gram(const double* __restrict__ Y, const double* __restrict__ Z,
+                     int n, int m, double* G, double* stage) {
+  static_assert(EG_NT == 512, "gram: 16 blocks of 32 lanes");
   const int tid = threadIdx.x;
-  double acc0 = 0.0, acc1 = 0.0;
-  const int e0 = tid, e1 = tid + EG_NT;
-  for (int c0 = 0; c0 < n; c0 += 64) {
-    const int cn = min(64, n - c0);
-    for (int idx = tid; idx < m * 64; idx += EG_NT) {
-      const int j = idx / 64, t = idx - j * 64;
-      stage[j * 64 + t] = (t < cn) ? Y[(long long)j * n + c0 + t] : 0.0;
-      stage[MAXM * 64 + j * 64 + t] = (t < cn) ? Z[(long long)j * n + c0 + t] : 0.0;
+  const int sb = tid >> 5, grp = tid & 31;
+  const int nbk = (m + 7) / 8;                 // 8 x 8 blocks per dimension
+  const bool act = sb < nbk * nbk;
+  const int a0 = (sb / max(nbk, 1)) * 8, b0 = (sb % max(nbk, 1)) * 8;
+  double acc[8][8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
+  const int per = m * GR_NC;                   // doubles of Y (or Z) per chunk
+  auto load = [&](int c0, double (&pf)[GR_PF]) {
+#pragma unroll
+    for (int u = 0; u < GR_PF; ++u) {
+      const int q = tid + u * EG_NT;           // q < per: Y, else Z
+      const int qq = q < per ? q : q - per;
+      const int j = qq / GR_NC, t = qq - (qq / GR_NC) * GR_NC;
+      const int node = min(c0 + t, n - 1);
+      const double* src = q < per ? Y : Z;
+      pf[u] = (q < 2 * per && c0 + t < n && j < m) ? src[(long long)j * n + node] : 0.0;
+    }
+  };
+  double pf[GR_PF];
+  load(0, pf);
+  for (int c0 = 0; c0 < n; c0 += GR_NC) {
+    __syncthreads();                           // previous chunk consumed
+#pragma unroll
+    for (int u = 0; u < GR_PF; ++u) {
+      const int q = tid + u * EG_NT;
+      if (q < 2 * per) stage[q] = pf[u];
     }
     __syncthreads();
-    if (e0 < m * m) {
-      const int a = e0 / m, b = e0 - (e0 / m) * m;
-      for (int t = 0; t < 64; ++t) acc0 += stage[a * 64 + t] * stage[MAXM * 64 + b * 64 + t];
+    if (c0 + GR_NC < n) load(c0 + GR_NC, pf);
+    if (act) {
+      const double* ys = stage;
+      const double* zs = stage + per;
+#pragma unroll
+      for (int h = 0; h < GR_NC / 32; ++h) {
+        const int t = grp + 32 * h;
+        double yv[8], zv[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          yv[i] = (a0 + i < m) ? ys[(a0 + i) * GR_NC + t] : 0.0;
+          zv[i] = (b0 + i < m) ? zs[(b0 + i) * GR_NC + t] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) acc[i][j] += yv[i] * zv[j];
+      }
     }
-    if (e1 < m * m) {
-      const int a = e1 / m, b = e1 - (e1 / m) * m;
-      for (int t = 0; t < 64; ++t) acc1 += stage[a * 64 + t] * stage[MAXM * 64 + b * 64 + t];
-    }
-    __syncthreads();
   }
-  if (e0 < m * m) G[e0] = acc0;
-  if (e1 < m * m) G[e1] = acc1;
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      double v = acc[i][j];
+#pragma unroll
+      for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      acc[i][j] = v;
+    }
+  __syncthreads();
+  if (act && grp == 0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (a0 + i < m && b0 + j < m) G[(a0 + i) * m + b0 + j] = acc[i][j];
+  }
   __syncthreads();
   // symmetrise
-  if (e0 < m * m) {
-    const int a = e0 / m, b = e0 - (e0 / m) * m;
-    if (a < b) {
-      const double v = 0.5 * (G[a * m + b] + G[b * m + a]);
-      G[a * m + b] = v;
-      G[b * m + a] = v;
-    }
-  }
-  if (e1 < m * m) {
-    const int a = e1 / m, b = e1 - (e1 / m) * m;
+  for (int e = tid; e < m * m; e += EG_NT) {
+    const int a = e / m, b = e - (e / m) * m;
     if (a < b) {
       const double v = 0.5 * (G[a * m + b] + G[b * m + a]);
       G[a * m + b] = v;
@@ -871,7 +916,6 @@ __device__ void gram(const double* Y, const double* Z, int n, int m,
   __syncthreads();
 }
 
-// In-place lower Cholesky of the m x m matrix G (row-major, stride m).
 __device__ void chol_small(double* G, int m, int* __restrict__ err) {
   const int tid = threadIdx.x;
   for (int p = 0; p < m; ++p) {
@@ -933,22 +977,19 @@ __device__ void jacobi_small(double* A, double* V, int m, double* rc,
     V[idx] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
+  __shared__ double jred[EG_NT / 64 + 1];
   for (int sweep = 0; sweep < 30; ++sweep) {
-    // convergence test
-    __shared__ double offn, diagn;
-    if (tid == 0) {
-      double o = 0.0, d = 0.0;
-      for (int i = 0; i < m; ++i)
-        for (int j = 0; j < m; ++j) {
-          const double a = A[i * m + j];
-          if (i == j) d += a * a; else o += a * a;
-        }
-      offn = o;
-      diagn = d;
+    // convergence test: off-diagonal and diagonal squares, summed by the
+    // whole workgroup (fixed order)
+    double o = 0.0, d = 0.0;
+    for (int idx = tid; idx < m * m; idx += EG_NT) {
+      const int i = idx / m, j = idx - (idx / m) * m;
+      const double a = A[idx];
+      if (i == j) d += a * a; else o += a * a;
     }
-    __syncthreads();
+    const double offn = block_sum<EG_NT>(o, jred);
+    const double diagn = block_sum<EG_NT>(d, jred);
     if (offn <= 1e-30 * diagn || offn == 0.0) break;
-    __syncthreads();
     for (int r = 0; r < me - 1; ++r) {
       if (tid < me / 2) {
         int p, q;
