@@ -198,48 +198,85 @@ __global__ void k_k0_scale(double* __restrict__ K0, int ldk,
 
 // Blocked Gauss-Jordan on the scaled K_0, block k: invert the 64 x 64
 // diagonal block in LDS, dropping pivots <= tol (row and column zeroed).
+// One pivot p = 16 PU + pt of the 64 x 64 diagonal block held as 4 x 4
+// register tiles by 16 x 16 threads (rows ti + 16u, columns tj + 16w); PU is
+// a compile-time constant, so the pivot's tile row and column are static.
+// A pivot at or below tol (scaled matrix) is dropped: its row and column
+// become zero, the rest is unchanged (a generalised inverse).
+template <int PU>
+__device__ __forceinline__ void gjp_pivot(double (&a)[4][4], int pt, int ti,
+                                          int tj, double tol, double* pv,
+                                          int* __restrict__ dropped) {
+  const int p = 16 * PU + pt;
+  double* rowv = pv + (p & 1) * 2 * GJB;
+  double* colv = rowv + GJB;
+  if (ti == pt) {
+#pragma unroll
+    for (int w = 0; w < 4; ++w) rowv[tj + 16 * w] = a[PU][w];
+  }
+  if (tj == pt) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) colv[ti + 16 * u] = a[u][PU];
+  }
+  __syncthreads();
+  const double piv = colv[p];
+  const bool drop = !(piv > tol) || !finite(piv);
+  if (drop && threadIdx.x == 0) atomicAdd(dropped, 1);
+  const double ip = drop ? 0.0 : 1.0 / piv;
+  double cv[4], rv[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) cv[u] = colv[ti + 16 * u];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) rv[w] = rowv[tj + 16 * w] * ip;
+  const bool prow = ti == pt, pcol = tj == pt;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const double upd = a[u][w] - cv[u] * rv[w];   // drop: rv = 0, unchanged
+      if (u == PU && w == PU)
+        a[u][w] = prow ? (pcol ? ip : (drop ? 0.0 : rv[w]))
+                       : (pcol ? (drop ? 0.0 : -cv[u] * ip) : upd);
+      else if (u == PU)
+        a[u][w] = prow ? (drop ? 0.0 : rv[w]) : upd;
+      else if (w == PU)
+        a[u][w] = pcol ? (drop ? 0.0 : -cv[u] * ip) : upd;
+      else
+        a[u][w] = upd;
+    }
+}
+
+template <int PU>
+__device__ __forceinline__ void gjp_tile(double (&a)[4][4], int ti, int tj,
+                                         double tol, double* pv,
+                                         int* __restrict__ dropped) {
+  for (int pt = 0; pt < 16; ++pt) gjp_pivot<PU>(a, pt, ti, tj, tol, pv, dropped);
+}
+
+// P = GJ inverse (generalised) of the diagonal block kb of A.
 __global__ void __launch_bounds__(CK_NT)
 k_gj_pivot(double* __restrict__ A, int ld, int kb, double* __restrict__ P,
            double tol, int* __restrict__ dropped) {
-  __shared__ double S[GJB * (GJB + 1)];
-  __shared__ double rowv[GJB], colv[GJB];
+  static_assert(GJB == 64 && CK_NT == 256, "pivot tiling: 16 x 16 threads, 4 x 4 tiles");
+  __shared__ double pv[4 * GJB];
   const int tid = threadIdx.x;
+  const int tj = tid & 15, ti = tid >> 4;
   const long long base = (long long)kb * GJB;
-  for (int idx = tid; idx < GJB * GJB; idx += CK_NT) {
-    const int i = idx / GJB, j = idx - i * GJB;
-    S[i * (GJB + 1) + j] = A[(base + i) * ld + base + j];
-  }
-  __syncthreads();
-  for (int p = 0; p < GJB; ++p) {
-    for (int i = tid; i < GJB; i += CK_NT) {
-      colv[i] = S[i * (GJB + 1) + p];
-      rowv[i] = S[p * (GJB + 1) + i];
-    }
-    __syncthreads();
-    const double piv = colv[p];
-    const bool drop = !(piv > tol) || !finite(piv);
-    if (drop && tid == 0) atomicAdd(dropped, 1);
-    const double ip = drop ? 0.0 : 1.0 / piv;
-    for (int idx = tid; idx < GJB * GJB; idx += CK_NT) {
-      const int i = idx / GJB, j = idx - i * GJB;
-      double v;
-      if (drop) {
-        v = (i == p || j == p) ? 0.0 : S[i * (GJB + 1) + j];
-      } else if (i == p) {
-        v = (j == p) ? ip : rowv[j] * ip;
-      } else if (j == p) {
-        v = -colv[i] * ip;
-      } else {
-        v = S[i * (GJB + 1) + j] - colv[i] * rowv[j] * ip;
-      }
-      S[i * (GJB + 1) + j] = v;
-    }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < GJB * GJB; idx += CK_NT) {
-    const int i = idx / GJB, j = idx - i * GJB;
-    P[idx] = S[i * (GJB + 1) + j];
-  }
+  double a[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+      a[u][w] = A[(base + ti + 16 * u) * ld + base + tj + 16 * w];
+  gjp_tile<0>(a, ti, tj, tol, pv, dropped);
+  gjp_tile<1>(a, ti, tj, tol, pv, dropped);
+  gjp_tile<2>(a, ti, tj, tol, pv, dropped);
+  gjp_tile<3>(a, ti, tj, tol, pv, dropped);
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+      P[(ti + 16 * u) * GJB + tj + 16 * w] = a[u][w];
 }
 
 // Panels of block k: Lp_i = A_ik P (for every block row i != k) and
