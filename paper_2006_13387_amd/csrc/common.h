@@ -125,6 +125,7 @@ struct Level1Args {
   const uint8_t* use64;
   const double* r;
   double* lsol;
+  double* gmid;        // per system 2 x MAXBS: each chain's coupling into the middle row
   CGScalars* sc;
   const double* part_upd;
   int nb_upd;

@@ -8,8 +8,12 @@
 // S_{k+1} = D_{k+1} - B_k S_k^{-1} B_k^T, a solve is
 //   forward  t_k = S_k^{-1} (r_k - B_{k-1} t_{k-1})
 //   backward x_k = t_k - S_k^{-1} B_k^T x_{k+1}.
-// Only the blocks S_k^{-1} are stored; B_k is rebuilt from the element
-// moduli on the fly, so one solve reads 2 * nyb * bs^2 stored values.
+// The elasticity systems use the twisted form of the same elimination: rows
+// 0..m-1 are eliminated top-down and rows nyb-1..m+1 bottom-up, both into
+// the middle row m = (nyb-1)/2, so that each solve is two independent
+// chains of half the length that meet at the middle row.
+// Only the blocks S_k^{-1} and compressed couplings are stored, one record
+// per row and chain, so one solve reads about 2 * nyb * bs^2 stored values.
 // Clamped (Dirichlet) DOFs become identity rows with zero couplings, which
 // keeps the principal submatrix of the free DOFs exact.
 #include "common.h"
@@ -164,10 +168,10 @@ __device__ __forceinline__ void gj_invert(double* S, int bs, double* pv,
 }
 
 // K entry between DOF (ia, ca) of node row ra and DOF (ib, cb) of node row
-// rb of the two rows staged in LDS (r = 0: row y-1, r = 1: row y), from
-// the staged element moduli er[e][t] of element rows y-1 (e = 0) and y
-// (e = 1), element column x0 - 1 + t (zero outside the system's element
-// box), and the element matrix Kl.
+// rb of the rows staged in LDS (r = 0, 1, 2: node rows y-1, y, y+1), from
+// the staged element moduli er[e][t] of element row y-1+e, element column
+// x0 - 1 + t (zero outside the system's element box), and the element
+// matrix Kl.
 template <int NDOF>
 __device__ __forceinline__ double coupling_l(const double (*er)[MAXBS + 2],
                                              const double* Kl, int ia, int ra,
@@ -184,9 +188,202 @@ __device__ __forceinline__ double coupling_l(const double (*er)[MAXBS + 2],
   return v;
 }
 
-// Factorise every system: one workgroup per system.
+// LDS of the factorisation: three dense blocks (the current row's S, the
+// previous inverse P and W = P B^T), the banded coupling B of the row with
+// the previous row of the chain, and the staged element moduli of element
+// rows y-1, y, y+1 and clamp flags of node rows y-1, y, y+1.
+struct FactorLds {
+  double buf[3][MAXBS * LDSTR];
+  double Bv[MAXBS * 6];
+  double pv[4 * MAXBS];
+  double ddiag[MAXBS];
+  double er[3][MAXBS + 2];
+  uint8_t fr[3][MAXBS];
+  double Kl[64];
+  double red[FT_NT / 64 + 1];
+};
+
+// Stage element rows y-1, y, y+1 (element columns x0-1 .. x0+nxb-1, zero
+// outside the element box) and node rows y-1, y, y+1 (rows outside the mesh
+// are flagged).
+template <int NDOF>
+__device__ __forceinline__ void fac_stage(const Geom& g, const SysDesc& s, int y,
+                                          const double* __restrict__ E,
+                                          const uint8_t* __restrict__ flag,
+                                          FactorLds& L) {
+  const int tid = threadIdx.x;
+  const int bs = NDOF * s.nxb;
+  for (int idx = tid; idx < 3 * (s.nxb + 1); idx += FT_NT) {
+    const int e = idx / (s.nxb + 1), t = idx - e * (s.nxb + 1);
+    const int ex = s.x0 - 1 + t, ey = y - 1 + e;
+    const bool in = ex >= s.ex0 && ex < s.ex1 && ey >= s.ey0 && ey < s.ey1;
+    L.er[e][t] = in ? E[(long long)ey * g.nx + ex] : 0.0;
+  }
+  for (int idx = tid; idx < 3 * bs; idx += FT_NT) {
+    const int r = idx / bs, a = idx - r * bs;
+    const int yy = y - 1 + r;
+    L.fr[r][a] = (yy >= 0 && yy < g.nny) ? flag[NDOF * ((long long)yy * g.nnx + s.x0) + a] : 1;
+  }
+}
+
+// D of the staged node row into S (row stride LDSTR), its diagonal into
+// ddiag; clamped DOFs become identity rows and columns.
+template <int NDOF>
+__device__ __forceinline__ void fac_diag(int bs, double* S, FactorLds& L) {
+  for (int idx = threadIdx.x; idx < bs * bs; idx += FT_NT) {
+    const int a = idx / bs, b = idx - (idx / bs) * bs;
+    const int ia = a / NDOF, ca = a - ia * NDOF;
+    const int ib = b / NDOF, cb = b - ib * NDOF;
+    double v = 0.0;
+    if (L.fr[1][a] || L.fr[1][b]) {
+      v = (a == b) ? 1.0 : 0.0;
+    } else if (abs(ia - ib) <= 1) {
+      v = coupling_l<NDOF>(L.er, L.Kl, ia, 1, ca, ib, 1, cb);
+    }
+    S[a * LDSTR + b] = v;
+    if (a == b) L.ddiag[a] = v;
+  }
+}
+
+// Banded couplings of the staged node row with node row rb (0: the row
+// above, 2: the row below): Bv[a][t] couples DOF a with DOF
+// NDOF (ia + t / NDOF - 1) + t % NDOF of that row (zero outside the row and
+// at clamped DOFs).
+template <int NDOF>
+__device__ __forceinline__ void fac_coupling(int nxb, int rb, FactorLds& L) {
+  const int bs = NDOF * nxb;
+  for (int idx = threadIdx.x; idx < bs * 3 * NDOF; idx += FT_NT) {
+    const int a = idx / (3 * NDOF), t = idx - a * (3 * NDOF);
+    const int ia = a / NDOF, ca = a - ia * NDOF;
+    const int di = t / NDOF - 1, cb = t - (t / NDOF) * NDOF;
+    const int ib = ia + di;
+    double v = 0.0;
+    if (ib >= 0 && ib < nxb && !L.fr[1][a] && !L.fr[rb][NDOF * ib + cb])
+      v = coupling_l<NDOF>(L.er, L.Kl, ia, 1, ca, ib, rb, cb);
+    L.Bv[idx] = v;
+  }
+}
+
+// S -= B P B^T for the coupling in Bv and the inverse P of the eliminated
+// row (both in LDS); W = P B^T is scratch.
+template <int NDOF>
+__device__ __forceinline__ void fac_schur(int bs, const double* P, double* W,
+                                          double* S, const FactorLds& L) {
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < bs * bs; idx += FT_NT) {
+    const int b = idx / bs, a = idx - (idx / bs) * bs;
+    const int ia = a / NDOF;
+    double v = 0.0;
+#pragma unroll
+    for (int t = 0; t < 3 * NDOF; ++t) {
+      const int col = NDOF * (ia + t / NDOF - 1) + (t % NDOF);
+      if (col >= 0 && col < bs) v += P[b * LDSTR + col] * L.Bv[a * 3 * NDOF + t];
+    }
+    W[b * LDSTR + a] = v;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < bs * bs; idx += FT_NT) {
+    const int a = idx / bs, a2 = idx - (idx / bs) * bs;
+    const int ia = a / NDOF;
+    double v = 0.0;
+#pragma unroll
+    for (int t = 0; t < 3 * NDOF; ++t) {
+      const int row = NDOF * (ia + t / NDOF - 1) + (t % NDOF);
+      if (row >= 0 && row < bs) v += L.Bv[a * 3 * NDOF + t] * W[row * LDSTR + a2];
+    }
+    S[a * LDSTR + a2] -= v;
+  }
+}
+
+// Record elements of one node row: S^{-1} (bs^2) and F (bs x 3 NDOF).
+__host__ __device__ inline long long fac_rec(int ndof, int nxb) {
+  const long long bs = (long long)ndof * nxb;
+  return bs * bs + 3LL * ndof * bs;
+}
+
+// Inverse block of a record: column j contiguous.
+__device__ __forceinline__ void fac_write_inverse(int bs, const double* S,
+                                                  double* o64, float* o32) {
+  for (int idx = threadIdx.x; idx < bs * bs; idx += FT_NT) {
+    const int j = idx / bs, i = idx - (idx / bs) * bs;
+    const double v = S[i * LDSTR + j];
+    o64[idx] = v;
+    if (o32 != nullptr) o32[idx] = (float)v;
+  }
+}
+
+// Coupling part F of a record (Bv, or zero for the first row of a chain).
+template <int NDOF>
+__device__ __forceinline__ void fac_write_coupling(int bs, bool coupled,
+                                                   const FactorLds& L,
+                                                   double* o64, float* o32) {
+  for (int idx = threadIdx.x; idx < bs * 3 * NDOF; idx += FT_NT) {
+    const double v = coupled ? L.Bv[idx] : 0.0;
+    o64[bs * bs + idx] = v;
+    if (o32 != nullptr) o32[bs * bs + idx] = (float)v;
+  }
+}
+
+// max over the workgroup of v (fixed order); thread 0 holds the result
+__device__ __forceinline__ double fac_wg_max(double v, FactorLds& L) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0) L.red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double mm = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < FT_NT / 64; ++i) mm = fmax(mm, L.red[i]);
+  return mm;
+}
+
+// Factorise one chain of node rows of system s: count rows starting at
+// node row row0 (relative to the box) in direction dir (+1 downwards in row
+// index, -1 upwards), each eliminating the previous row of the chain, with
+// chain position j's record at record index rec0 + j.  Returns this
+// thread's share of max_i (S^-1)_ii (D)_ii.
+template <int NDOF>
+__device__ double factor_chain(const Geom& g, const SysDesc& s, int row0,
+                               int dir, int count, int rec0,
+                               const double* __restrict__ E,
+                               const uint8_t* __restrict__ flag,
+                               double* __restrict__ out64,
+                               float* __restrict__ out32, int* err,
+                               FactorLds& L) {
+  const int tid = threadIdx.x;
+  const int bs = NDOF * s.nxb;
+  const int rb = 1 - dir;              // staged node row of the previous row
+  const long long rec = fac_rec(NDOF, s.nxb);
+  double mloc = 0.0;
+  int cur = 0, prev = 1, wb = 2;
+  for (int j = 0; j < count; ++j) {
+    const int y = s.y0 + row0 + dir * j;
+    double* S = L.buf[cur];
+    fac_stage<NDOF>(g, s, y, E, flag, L);
+    __syncthreads();
+    fac_diag<NDOF>(bs, S, L);
+    if (j > 0) {
+      fac_coupling<NDOF>(s.nxb, rb, L);
+      __syncthreads();
+      fac_schur<NDOF>(bs, L.buf[prev], L.buf[wb], S, L);
+    }
+    __syncthreads();
+    gj_invert(S, bs, L.pv, err);
+    const long long off = s.foff + (long long)(rec0 + j) * rec;
+    fac_write_inverse(bs, S, out64 + off, out32 ? out32 + off : nullptr);
+    fac_write_coupling<NDOF>(bs, j > 0, L, out64 + off, out32 ? out32 + off : nullptr);
+    for (int a = tid; a < bs; a += FT_NT) mloc = fmax(mloc, S[a * LDSTR + a] * L.ddiag[a]);
+    __syncthreads();
+    const int t = prev;
+    prev = cur;
+    cur = t;
+  }
+  return mloc;
+}
+
+// Factorise every system top-down: one workgroup per system, records of
+// rows 0..nyb-1 in order (the heat pencils of the coarse space).
 //
-// out64 receives the FP64 inverse blocks; out32 (may be null) a rounded FP32
+// out64 receives the FP64 records; out32 (may be null) a rounded FP32
 // copy.  metric (may be null) receives per system max_i (S_k^-1)_ii (D_k)_ii
 // over all blocks: about 1 for DOFs held by stiff material and up to the
 // contrast E0/Emin for DOFs of stiff islands that float in soft material,
@@ -200,156 +397,128 @@ k_factor(Geom g, const SysDesc* __restrict__ systems,
          const double* __restrict__ Kel, double* __restrict__ out64,
          float* __restrict__ out32, double* __restrict__ metric,
          int* __restrict__ err) {
-  __shared__ double buf[3][MAXBS * LDSTR];
-  __shared__ double Bv[MAXBS * 3 * NDOF];
-  __shared__ double pv[4 * MAXBS];
-  __shared__ double ddiag[MAXBS];
-  __shared__ double er[2][MAXBS + 2];          // element moduli, rows y-1, y
-  __shared__ uint8_t fr[2][MAXBS];             // clamp flags, node rows y-1, y
-  __shared__ double Kl[16 * NDOF * NDOF];
-  __shared__ double red[FT_NT / 64 + 1];
-  double mloc = 0.0;
+  __shared__ FactorLds L;
+  const SysDesc s = systems[blockIdx.x];
+  for (int i = threadIdx.x; i < 16 * NDOF * NDOF; i += FT_NT) L.Kl[i] = Kel[i];
+  const double mloc = factor_chain<NDOF>(g, s, 0, 1, s.nyb, 0, E, flag, out64,
+                                         out32, err, L);
+  const double mm = fac_wg_max(mloc, L);
+  if (metric != nullptr && threadIdx.x == 0) metric[blockIdx.x] = mm;
+}
+
+// Twisted factorisation, both outer parts: workgroup 2 i + h factorises
+// system i's chain h: h = 0 eliminates rows 0..m-1 top-down (records
+// 0..m-1), h = 1 rows nyb-1..m+1 bottom-up (records m+1..nyb-1), with
+// m = (nyb - 1) / 2 the middle row.  Part metrics go to
+// metric[nsys + 2 i + h].
+template <int NDOF>
+__global__ void __launch_bounds__(FT_NT)
+k_factor_twisted(Geom g, const SysDesc* __restrict__ systems, int nsys,
+                 const double* __restrict__ E, const uint8_t* __restrict__ flag,
+                 const double* __restrict__ Kel, double* __restrict__ out64,
+                 float* __restrict__ out32, double* __restrict__ metric,
+                 int* __restrict__ err) {
+  __shared__ FactorLds L;
+  const int sys = blockIdx.x >> 1, half = blockIdx.x & 1;
+  const SysDesc s = systems[sys];
+  for (int i = threadIdx.x; i < 16 * NDOF * NDOF; i += FT_NT) L.Kl[i] = Kel[i];
+  const int m = (s.nyb - 1) >> 1;
+  const double mloc =
+      half == 0 ? factor_chain<NDOF>(g, s, 0, 1, m, 0, E, flag, out64, out32, err, L)
+                : factor_chain<NDOF>(g, s, s.nyb - 1, -1, s.nyb - 1 - m, m + 1, E,
+                                     flag, out64, out32, err, L);
+  const double mm = fac_wg_max(mloc, L);
+  if (threadIdx.x == 0) metric[nsys + blockIdx.x] = mm;
+}
+
+// Load the inverse block of a record into LDS (row stride LDSTR).
+__device__ __forceinline__ void fac_load_inverse(int bs, const double* __restrict__ o,
+                                                 double* P) {
+  for (int idx = threadIdx.x; idx < bs * bs; idx += FT_NT) {
+    const int j = idx / bs, i = idx - (idx / bs) * bs;
+    P[i * LDSTR + j] = o[idx];
+  }
+}
+
+// Twisted factorisation, the middle row m of system i (one workgroup each):
+// S_m = D_m - B S_{m-1}^{-1} B^T - C S'_{m+1}^{-1} C^T with B, C the
+// couplings of row m with rows m-1 and m+1, inverted.  Its inverse ends
+// both chains: record m (top chain, with F = B) and record nyb (bottom
+// chain, with F = C).  metric[i] = max over the system.
+template <int NDOF>
+__global__ void __launch_bounds__(FT_NT)
+k_factor_middle(Geom g, const SysDesc* __restrict__ systems, int nsys,
+                const double* __restrict__ E, const uint8_t* __restrict__ flag,
+                const double* __restrict__ Kel, double* __restrict__ out64,
+                float* __restrict__ out32, double* __restrict__ metric,
+                int* __restrict__ err) {
+  __shared__ FactorLds L;
   const SysDesc s = systems[blockIdx.x];
   const int tid = threadIdx.x;
   const int bs = NDOF * s.nxb;
-  for (int i = tid; i < 16 * NDOF * NDOF; i += FT_NT) Kl[i] = Kel[i];
-  int cur = 0, prev = 1, wb = 2;
-  for (int k = 0; k < s.nyb; ++k) {
-    const int y = s.y0 + k;
-    double* S = buf[cur];
-    // stage the moduli of element rows y-1, y (element columns x0-1 ..
-    // x0+nxb-1; zero outside the element box) and the clamp flags of node
-    // rows y-1, y (row -1 does not exist: flagged)
-    for (int idx = tid; idx < 2 * (s.nxb + 1); idx += FT_NT) {
-      const int e = idx / (s.nxb + 1), t = idx - e * (s.nxb + 1);
-      const int ex = s.x0 - 1 + t, ey = y - 1 + e;
-      const bool in = ex >= s.ex0 && ex < s.ex1 && ey >= s.ey0 && ey < s.ey1;
-      er[e][t] = in ? E[(long long)ey * g.nx + ex] : 0.0;
-    }
-    for (int idx = tid; idx < 2 * bs; idx += FT_NT) {
-      const int r = idx / bs, a = idx - r * bs;
-      const int yy = y - 1 + r;
-      fr[r][a] = (yy >= 0) ? flag[NDOF * ((long long)yy * g.nnx + s.x0) + a] : 1;
-    }
+  const int m = (s.nyb - 1) >> 1;
+  const long long rec = fac_rec(NDOF, s.nxb);
+  for (int i = tid; i < 16 * NDOF * NDOF; i += FT_NT) L.Kl[i] = Kel[i];
+  double* S = L.buf[0];
+  fac_stage<NDOF>(g, s, s.y0 + m, E, flag, L);
+  __syncthreads();
+  fac_diag<NDOF>(bs, S, L);
+  const long long otop = s.foff + (long long)m * rec;
+  const long long obot = s.foff + (long long)s.nyb * rec;
+  // top part: row m-1 eliminated
+  if (m > 0) {
+    fac_coupling<NDOF>(s.nxb, 0, L);
+    fac_load_inverse(bs, out64 + s.foff + (long long)(m - 1) * rec, L.buf[1]);
     __syncthreads();
-    // D_k
-    for (int idx = tid; idx < bs * bs; idx += FT_NT) {
-      const int a = idx / bs, b = idx - (idx / bs) * bs;
-      const int ia = a / NDOF, ca = a - ia * NDOF;
-      const int ib = b / NDOF, cb = b - ib * NDOF;
-      double v = 0.0;
-      if (fr[1][a] || fr[1][b]) {
-        v = (a == b) ? 1.0 : 0.0;
-      } else if (abs(ia - ib) <= 1) {
-        v = coupling_l<NDOF>(er, Kl, ia, 1, ca, ib, 1, cb);
-      }
-      S[a * LDSTR + b] = v;
-      if (a == b) ddiag[a] = v;
-    }
-    if (k > 0) {
-      // B_{k-1}: rows a in node row y, columns in node row y-1, banded
-      for (int idx = tid; idx < bs * 3 * NDOF; idx += FT_NT) {
-        const int a = idx / (3 * NDOF), t = idx - a * (3 * NDOF);
-        const int ia = a / NDOF, ca = a - ia * NDOF;
-        const int di = t / NDOF - 1, cb = t - (t / NDOF) * NDOF;
-        const int ib = ia + di;
-        double v = 0.0;
-        if (ib >= 0 && ib < s.nxb && !fr[1][a] && !fr[0][NDOF * ib + cb])
-          v = coupling_l<NDOF>(er, Kl, ia, 1, ca, ib, 0, cb);
-        Bv[idx] = v;
-      }
-      __syncthreads();
-      // W = S_{k-1}^{-1} B_{k-1}^T : W[b][a]
-      const double* P = buf[prev];
-      double* W = buf[wb];
-      for (int idx = tid; idx < bs * bs; idx += FT_NT) {
-        const int b = idx / bs, a = idx - (idx / bs) * bs;
-        const int ia = a / NDOF;
-        double v = 0.0;
-#pragma unroll
-        for (int t = 0; t < 3 * NDOF; ++t) {
-          const int col = NDOF * (ia + t / NDOF - 1) + (t % NDOF);
-          if (col >= 0 && col < bs) v += P[b * LDSTR + col] * Bv[a * 3 * NDOF + t];
-        }
-        W[b * LDSTR + a] = v;
-      }
-      __syncthreads();
-      // S -= B W
-      for (int idx = tid; idx < bs * bs; idx += FT_NT) {
-        const int a = idx / bs, a2 = idx - (idx / bs) * bs;
-        const int ia = a / NDOF;
-        double v = 0.0;
-#pragma unroll
-        for (int t = 0; t < 3 * NDOF; ++t) {
-          const int row = NDOF * (ia + t / NDOF - 1) + (t % NDOF);
-          if (row >= 0 && row < bs) v += Bv[a * 3 * NDOF + t] * W[row * LDSTR + a2];
-        }
-        S[a * LDSTR + a2] -= v;
-      }
-    }
+    fac_schur<NDOF>(bs, L.buf[1], L.buf[2], S, L);
     __syncthreads();
-    gj_invert(S, bs, pv, err);
-    // record of row k: the inverse block (column j contiguous) and the
-    // couplings F(k) of row k with row k-1 (zero for k = 0), which the
-    // first-level apply and the heat eigen sweeps stream with it
-    const long long rec = (long long)bs * bs + 3LL * NDOF * bs;
-    double* o = out64 + s.foff + (long long)k * rec;
-    for (int idx = tid; idx < bs * bs; idx += FT_NT) {
-      const int j = idx / bs, i = idx - (idx / bs) * bs;
-      o[idx] = S[i * LDSTR + j];
-    }
-    for (int idx = tid; idx < bs * 3 * NDOF; idx += FT_NT)
-      o[bs * bs + idx] = (k > 0) ? Bv[idx] : 0.0;
-    if (out32 != nullptr) {
-      float* o32 = out32 + s.foff + (long long)k * rec;
-      for (int idx = tid; idx < bs * bs; idx += FT_NT) {
-        const int j = idx / bs, i = idx - (idx / bs) * bs;
-        o32[idx] = (float)S[i * LDSTR + j];
-      }
-      for (int idx = tid; idx < bs * 3 * NDOF; idx += FT_NT)
-        o32[bs * bs + idx] = (k > 0) ? (float)Bv[idx] : 0.0f;
-    }
-    for (int a = tid; a < bs; a += FT_NT) mloc = fmax(mloc, S[a * LDSTR + a] * ddiag[a]);
-    __syncthreads();
-    const int t = prev;
-    prev = cur;
-    cur = t;
   }
-  if (metric != nullptr) {
-    // workgroup max (fixed order)
-    double v = mloc;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    if ((tid & 63) == 0) red[tid >> 6] = v;
+  fac_write_coupling<NDOF>(bs, m > 0, L, out64 + otop, out32 ? out32 + otop : nullptr);
+  __syncthreads();
+  // bottom part: row m+1 eliminated (its record is the bottom chain's
+  // record nyb-1)
+  if (m + 1 < s.nyb) {
+    fac_coupling<NDOF>(s.nxb, 2, L);
+    fac_load_inverse(bs, out64 + s.foff + (long long)(s.nyb - 1) * rec, L.buf[1]);
     __syncthreads();
-    if (tid == 0) {
-      double mm = 0.0;
-      for (int i = 0; i < FT_NT / 64; ++i) mm = fmax(mm, red[i]);
-      metric[blockIdx.x] = mm;
-    }
+    fac_schur<NDOF>(bs, L.buf[1], L.buf[2], S, L);
+    __syncthreads();
   }
+  fac_write_coupling<NDOF>(bs, m + 1 < s.nyb, L, out64 + obot, out32 ? out32 + obot : nullptr);
+  __syncthreads();
+  gj_invert(S, bs, L.pv, err);
+  fac_write_inverse(bs, S, out64 + otop, out32 ? out32 + otop : nullptr);
+  fac_write_inverse(bs, S, out64 + obot, out32 ? out32 + obot : nullptr);
+  double mloc = 0.0;
+  for (int a = tid; a < bs; a += FT_NT) mloc = fmax(mloc, S[a * LDSTR + a] * L.ddiag[a]);
+  const double mm = fac_wg_max(mloc, L);
+  if (tid == 0)
+    metric[blockIdx.x] = fmax(mm, fmax(metric[nsys + 2 * blockIdx.x],
+                                       metric[nsys + 2 * blockIdx.x + 1]));
 }
 
 // ---------------------------------------------------------------------
 // First level: z_i = K_i^{-1} R_i r for every subdomain (2D elasticity).
 //
-// One workgroup of 8 waves per subdomain; the local vector stays in LDS.
-// Each node row k has a record in HBM: its inverse Schur block S_k^{-1}
-// (column-major) followed by the couplings F(k) of row k with row k-1,
-// written by the factorisation.  The sweep is a chain of nyb forward and
-// nyb-1 backward steps; step c uses the record of row k(c).
+// Two passes (forward, backward) of two workgroups of 8 waves per
+// subdomain, one per chain of the twisted factorisation; the chain's part
+// of the local vector stays in LDS within a pass and goes through lsol
+// between the passes.  Each chain position has a record in HBM: its inverse
+// Schur block (column-major) followed by the couplings F of its row with
+// the previous row of the chain, written by the factorisation.  Step c of a
+// pass uses the record of one chain position:
 //  * waves 4-7 ("loaders") copy records straight from HBM into a ring of R
 //    LDS slots with direct-to-LDS loads (global_load_lds, 16 bytes a lane),
 //    R-1 steps ahead, and wait with an explicit vmcnt for the record of the
 //    next step only: the HBM latency of a record overlaps R-1 steps;
 //  * waves 0-3 ("compute") only read and write LDS, so they never wait on
 //    memory.  Phase 1 forms the block right-hand side w from the
-//    neighbouring row (forward: F(k) of this record; backward: F(k+1), kept
-//    from the previous step, read transposed); phase 2 multiplies w by the
+//    neighbouring position (forward: F of this record; backward: F of the
+//    previous step's record, read transposed); phase 2 multiplies w by the
 //    inverse block, split over L1_NS column groups (thread (q, i) sums
 //    row i over group q).  The group partial sums are added up where they
 //    are next used, in the following step's phase 1, which also retires
-//    the finished row into v.
+//    the finished position into v.
 // Two barriers per step.
 constexpr int L1_NS = 3;                   // column groups of the block GEMV
 constexpr int L1_GMAX = (MAXBS + L1_NS - 1) / L1_NS;   // columns per group
@@ -518,22 +687,46 @@ __device__ __forceinline__ void l1_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-template <typename T>
-__device__ void level1_body(const Geom& g, const SysDesc& s,
+// First-level solve of one system by the twisted factorisation: chain h
+// (0: node rows 0..m from the top, 1: node rows nyb-1..m from the bottom,
+// m = (nyb - 1) / 2) has L positions, the last being the middle row; its
+// position j is node row j (h = 0) or nyb-1-j (h = 1) with record rec0 + j.
+//  * forward (BWD = false): t_j = S_j^{-1} (r_j - F_j t_{j-1}) for
+//    j = 0..L-2 into lsol, then the middle row's coupling to this chain,
+//    g_h = F_{L-1} t_{L-2}, into gm[h];
+//  * backward (BWD = true): x_m = S_m^{-1} (r_m - g_0 - g_1), then
+//    x_j = t_j - S_j^{-1} F_{j+1}^T x_{j+1} for j = L-2..0, into lsol
+//    (the middle row by chain 0 only).
+// Step c of the sweep uses the record of position j(c) (forward j = c,
+// backward j = L-1-c).
+template <typename T, bool BWD>
+__device__ void level1_half(const Geom& g, const SysDesc& s, int half,
                             const uint8_t* __restrict__ mask,
                             const T* __restrict__ Sinv,
                             const double* __restrict__ r,
-                            double* __restrict__ lsol, unsigned char* lds) {
+                            double* __restrict__ lsol, double* __restrict__ gm,
+                            unsigned char* lds) {
   const int tid = threadIdx.x;
   const int bs = 2 * s.nxb;
   const int nb = s.nyb;
   const int bs2 = bs * bs;
-  const int nsteps = 2 * nb - 1;
-  const L1Ring ring = l1_ring<T>(bs, nb);
+  const int mid = (nb - 1) >> 1;
+  const int L = half ? nb - mid : mid + 1;
+  const int rec0 = half ? mid + 1 : 0;
+  const int nsteps = BWD ? L : L - 1;
+  const L1Ring ring = l1_ring<T>(bs, L);
   const int R = ring.R;
-  const T* base = Sinv + s.foff;
+  const T* base = Sinv + s.foff + (long long)rec0 * ring.rec;
+  double* o = lsol + s.voff;
+  auto row_of = [&](int j) { return half ? nb - 1 - j : j; };
+  auto pos_of = [&](int c) { return BWD ? L - 1 - c : c; };
+  if (!BWD && L == 1) {
+    // no row before the middle on this side
+    for (int a = tid; a < bs; a += AP_NT) gm[half * MAXBS + a] = 0.0;
+    return;
+  }
   T* v = reinterpret_cast<T*>(lds + R * ring.slot);
-  T* w = v + nb * bs;
+  T* w = v + L * bs;
   T* P = w + bs;                              // P[parity][group][MAXBS]
   const bool loader = tid >= L1_COMPUTE;
   const int lw = __builtin_amdgcn_readfirstlane((tid - L1_COMPUTE) >> 6);
@@ -553,157 +746,183 @@ __device__ void level1_body(const Geom& g, const SysDesc& s,
   if (loader) {
     for (int c = 0; c < R - 1; ++c) {
       const int st = c < nsteps ? c : nsteps - 1;
-      l1_dma<T>(base, ring.rec, l1_block_of_step(st, nb), lds + (c % R) * ring.slot,
+      l1_dma<T>(base, ring.rec, pos_of(st), lds + (c % R) * ring.slot,
                 ring.nch, lw, lane);
     }
   }
-  for (int idx = tid; idx < nb * bs; idx += AP_NT) {
-    const int k = idx / bs, a = idx - (idx / bs) * bs;
-    const long long d = 2 * ((long long)(s.y0 + k) * g.nnx + s.x0 + a / 2) + (a & 1);
-    v[idx] = mask[d] ? (T)0 : (T)r[d];
+  // local vector: forward, r at the chain's rows before the middle;
+  // backward, the forward results t_j and the middle row's right-hand side
+  for (int idx = tid; idx < (L - 1) * bs; idx += AP_NT) {
+    const int j = idx / bs, a = idx - (idx / bs) * bs;
+    const int k = row_of(j);
+    if (!BWD) {
+      const long long d = 2 * ((long long)(s.y0 + k) * g.nnx + s.x0 + a / 2) + (a & 1);
+      v[idx] = mask[d] ? (T)0 : (T)r[d];
+    } else {
+      v[idx] = (T)o[k * bs + a];
+    }
+  }
+  if (BWD && tid < bs) {
+    const long long d = 2 * ((long long)(s.y0 + mid) * g.nnx + s.x0 + tid / 2) + (tid & 1);
+    w[tid] = mask[d] ? (T)0 : (T)r[d] - ((T)gm[tid] + (T)gm[MAXBS + tid]);
   }
   if (loader) wait_vmcnt(younger);      // record of step 0 is in its slot
   l1_barrier();
 
-  // Row kp, finished at the previous step (parity pp), at entry col: the
-  // sum of the group partial sums (forward steps produce the row, backward
-  // steps subtract it from y_kp).  fin_load issues the LDS reads, fin_value
-  // combines them, so that callers can issue all reads before the first use
-  // (the compiler otherwise waits for each read in turn).
+  // Position jp, finished at the previous step (parity pp), at entry col:
+  // the sum of the group partial sums (forward-type steps produce the row,
+  // backward steps subtract it from t_jp).  fin_load issues the LDS reads,
+  // fin_value combines them, so that callers can issue all reads before
+  // the first use (the compiler otherwise waits for each read in turn).
   struct Fin {
     T p[L1_NS];
     T y;
   };
-  auto fin_load = [&](int kp, int pp, int col) -> Fin {
-    Fin r;
+  auto fin_load = [&](int jp, int pp, int col) -> Fin {
+    Fin f;
     const T* pr = P + pp * (L1_NS * MAXBS) + col;
 #pragma unroll
-    for (int q = 0; q < L1_NS; ++q) r.p[q] = pr[q * MAXBS];
-    r.y = v[kp * bs + col];
-    return r;
+    for (int q = 0; q < L1_NS; ++q) f.p[q] = pr[q * MAXBS];
+    f.y = v[jp * bs + col];
+    return f;
   };
-  auto fin_value = [&](const Fin& r, bool pfwd) -> T {
-    T acc = r.p[0];
+  auto fin_value = [&](const Fin& f, bool pfwd) -> T {
+    T acc = f.p[0];
 #pragma unroll
-    for (int q = 1; q < L1_NS; ++q) acc += r.p[q];
-    return pfwd ? acc : r.y - acc;
+    for (int q = 1; q < L1_NS; ++q) acc += f.p[q];
+    return pfwd ? acc : f.y - acc;
   };
 
   for (int c = 0; c < nsteps; ++c) {
-    const bool fwd = c < nb;
-    const int k = l1_block_of_step(c, nb);
+    const int j = pos_of(c);
     const int cur = c % R;
     const int prev = (c + R - 1) % R;
     const int pp = (c + 1) & 1;               // parity of step c-1
-    const bool pfwd = (c - 1) < nb;
-    const int kp = fwd ? k - 1 : k + 1;       // row finished at step c-1
+    const bool pfwd = !BWD || c == 1;         // step c-1 produced its row
+    const int jp = BWD ? j + 1 : j - 1;       // position finished at step c-1
     // phase 1: w = right-hand side of the step
-    if (tid < bs) {
-      T wv;
-      if (c == 0) {
-        wv = v[tid];
-      } else {
-        // forward: F(k) (couplings of row k with row k-1, this step's
-        // record), zero towards nodes outside the row, so a clamped index
-        // contributes nothing; backward: F(k+1) (couplings of row k+1 with
-        // row k, in the previous step's slot) read transposed, entries
-        // outside the row masked
-        const T* F = fwd ? reinterpret_cast<const T*>(lds + cur * ring.slot) + bs2 + tid * 6
-                         : reinterpret_cast<const T*>(lds + prev * ring.slot) + bs2;
-        T f[6];
-        Fin y[6];
-        bool ok[6];
+    if (tid < bs && c > 0) {
+      // forward: F_j (couplings of position j with j-1, this step's
+      // record), zero towards nodes outside the row, so a clamped index
+      // contributes nothing; backward: F_{j+1} (couplings of position j+1
+      // with j, in the previous step's slot) read transposed, entries
+      // outside the row masked
+      const T* F = !BWD ? reinterpret_cast<const T*>(lds + cur * ring.slot) + bs2 + tid * 6
+                        : reinterpret_cast<const T*>(lds + prev * ring.slot) + bs2;
+      T f[6];
+      Fin y[6];
+      bool ok[6];
 #pragma unroll
-        for (int t = 0; t < 6; ++t) {
-          const int di = t / 2 - 1, cc = t & 1;
-          const int a = 2 * (ia + di) + cc;
-          ok[t] = a >= 0 && a < bs;
-          const int ac = min(max(a, 0), bs - 1);
-          f[t] = fwd ? F[t] : F[ac * 6 + (1 - di) * 2 + ca];
-          y[t] = fin_load(kp, pp, ac);
-        }
-        const T rk = v[k * bs + tid];
-        __builtin_amdgcn_sched_barrier(0);
-        T acc = 0;
-#pragma unroll
-        for (int t = 0; t < 6; ++t) acc += (ok[t] ? f[t] : (T)0) * fin_value(y[t], pfwd);
-        wv = fwd ? rk - acc : acc;
+      for (int t = 0; t < 6; ++t) {
+        const int di = t / 2 - 1, cc = t & 1;
+        const int a = 2 * (ia + di) + cc;
+        ok[t] = a >= 0 && a < bs;
+        const int ac = min(max(a, 0), bs - 1);
+        f[t] = !BWD ? F[t] : F[ac * 6 + (1 - di) * 2 + ca];
+        y[t] = fin_load(jp, pp, ac);
       }
-      w[tid] = wv;
+      const T rk = v[j * bs + tid];
+      __builtin_amdgcn_sched_barrier(0);
+      T acc = 0;
+#pragma unroll
+      for (int t = 0; t < 6; ++t) acc += (ok[t] ? f[t] : (T)0) * fin_value(y[t], pfwd);
+      w[tid] = !BWD ? rk - acc : acc;
+    } else if (!BWD && tid < bs) {
+      w[tid] = v[tid];
     }
     l1_barrier();
-    // phase 2: retire row kp into v (phase 1 may read y_kp there, so not
-    // before the barrier); partial block GEMV; loaders fetch the record of
-    // step c+R-1 into the slot freed by step c-1 and wait for the record of
-    // step c+1
+    // phase 2: retire position jp into v (phase 1 may read t_jp there, so
+    // not before the barrier); partial block GEMV; loaders fetch the record
+    // of step c+R-1 into the slot freed by step c-1 and wait for the record
+    // of step c+1
     if (gemv) {
-      if (c > 0 && tid < bs) v[kp * bs + tid] = fin_value(fin_load(kp, pp, tid), pfwd);
+      if (c > 0 && tid < bs) v[jp * bs + tid] = fin_value(fin_load(jp, pp, tid), pfwd);
       const T* S = reinterpret_cast<const T*>(lds + cur * ring.slot) + j0 * bs;
       P[(c & 1) * (L1_NS * MAXBS) + gq * MAXBS + gi] =
           lds_gemv_group<T, L1_GMAX>(S, bs, gi, w + j0, jn);
     } else if (loader) {
       const int cn = c + R - 1;
       const int st = cn < nsteps ? cn : nsteps - 1;
-      l1_dma<T>(base, ring.rec, l1_block_of_step(st, nb), lds + prev * ring.slot,
-                ring.nch, lw, lane);
+      l1_dma<T>(base, ring.rec, pos_of(st), lds + prev * ring.slot, ring.nch,
+                lw, lane);
       wait_vmcnt(younger);
     }
     l1_barrier();
   }
-  // retire the row of the last step; the loaders drain their last
+  // retire the position of the last step; the loaders drain their last
   // (unused) record loads so that no copy into LDS outlives this system
   {
     const int c = nsteps;
-    const int kl = l1_block_of_step(c - 1, nb);
-    if (tid < bs) {
-      v[kl * bs + tid] = fin_value(fin_load(kl, (c + 1) & 1, tid), (c - 1) < nb);
-    }
+    const int jl = pos_of(c - 1);
+    if (tid < bs) v[jl * bs + tid] = fin_value(fin_load(jl, (c + 1) & 1, tid), !BWD || c == 1);
   }
   if (loader) wait_vmcnt(0);
   l1_barrier();
-  double* o = lsol + s.voff;
-  for (int idx = tid; idx < nb * bs; idx += AP_NT) o[idx] = (double)v[idx];
+  if (!BWD) {
+    // g = F_{L-1} t_{L-2}, F_{L-1} from the middle row's record in HBM
+    if (tid < bs) {
+      const T* F = base + (long long)(L - 1) * ring.rec + bs2 + tid * 6;
+      T acc = 0;
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        const int di = t / 2 - 1, cc = t & 1;
+        const int a = 2 * (ia + di) + cc;
+        if (a >= 0 && a < bs) acc += F[t] * v[(L - 2) * bs + a];
+      }
+      gm[half * MAXBS + tid] = (double)acc;
+    }
+  }
+  const int nout = (BWD && half == 0) ? L : L - 1;
+  for (int idx = tid; idx < nout * bs; idx += AP_NT) {
+    const int j = idx / bs, a = idx - (idx / bs) * bs;
+    o[row_of(j) * bs + a] = (double)v[idx];
+  }
 }
 
 // use64[i] != 0 (or use64 == null) selects the FP64 records of system i,
-// else its FP32 copy (applied and accumulated in FP32).  With sc given,
-// every workgroup first runs the CG convergence test on the update
-// kernel's partials (check = 1) or reads the done word (check = 0).
+// else its FP32 copy (applied and accumulated in FP32).
 struct L1Shared {
   double red[AP_NT / 64 + 1];
   int shi;
 };
 
-// First-level solve of system bid of one problem.  With a.sc set, the CG
-// convergence test on the update kernel's partials (check = 1) or the done
-// word (check = 0) comes first.
-__device__ __forceinline__ void level1_item(const Level1Args& a, int bid,
+// Workgroup vb of one problem's first-level pass: system vb / 2, chain
+// vb % 2.  With a.sc set, the forward pass first runs the CG convergence
+// test on the update kernel's partials (check = 1) or reads the done word
+// (check = 0); the backward pass reads the done word.
+template <bool BWD>
+__device__ __forceinline__ void level1_item(const Level1Args& a, int vb,
                                             unsigned char* lds, L1Shared& L) {
   if (a.sc != nullptr) {
-    if (a.check) {
-      if (cg_check_done<AP_NT>(a.sc, a.part_upd, a.nb_upd, L.red, &L.shi, bid == 0)) return;
+    if (!BWD && a.check) {
+      if (cg_check_done<AP_NT>(a.sc, a.part_upd, a.nb_upd, L.red, &L.shi, vb == 0)) return;
     } else if (block_read_done(a.sc, &L.shi)) {
       return;
     }
   }
+  const int bid = vb >> 1, half = vb & 1;
   const SysDesc s = a.sys[bid];
+  double* gm = a.gmid + (long long)bid * 2 * MAXBS;
   if (a.S32 == nullptr || a.use64 == nullptr || a.use64[bid])
-    level1_body<double>(a.g, s, a.mask, a.S64, a.r, a.lsol, lds);
+    level1_half<double, BWD>(a.g, s, half, a.mask, a.S64, a.r, a.lsol, gm, lds);
   else
-    level1_body<float>(a.g, s, a.mask, a.S32, a.r, a.lsol, lds);
+    level1_half<float, BWD>(a.g, s, half, a.mask, a.S32, a.r, a.lsol, gm, lds);
 }
 
-// use64[i] != 0 (or use64 == null) selects the FP64 records of system i,
-// else its FP32 copy (applied and accumulated in FP32).
+// One pass (forward or backward) of the first-level solves: two workgroups
+// per system.
+template <bool BWD>
 __global__ void __launch_bounds__(AP_NT) k_level1(Level1Args a) {
   __shared__ __align__(1024) unsigned char lds[L1_LDS];
   __shared__ L1Shared L;
-  level1_item(a, blockIdx.x, lds, L);
+  level1_item<BWD>(a, blockIdx.x, lds, L);
 }
 
-// The first-level solves of several problems in one persistent launch:
-// workgroup w takes systems w, w + grid, w + 2 grid, ... of the concatenated
-// list (problem by problem), so a grid of a few per CU covers any batch.
+// One pass of the first-level solves of several problems in one persistent
+// launch: workgroup w takes items w, w + grid, w + 2 grid, ... of the
+// concatenated list (problem by problem, two per system), so a grid of one
+// per CU covers any batch.
+template <bool BWD>
 __global__ void __launch_bounds__(AP_NT)
 k_level1_batch(const Level1Args* __restrict__ tab, const int* __restrict__ start,
                int nent, int total) {
@@ -711,7 +930,7 @@ k_level1_batch(const Level1Args* __restrict__ tab, const int* __restrict__ start
   __shared__ L1Shared L;
   for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
     const int e = batch_entry(start, nent, vb);
-    level1_item(tab[e], vb - start[e], lds, L);
+    level1_item<BWD>(tab[e], vb - start[e], lds, L);
     __syncthreads();
   }
 }
@@ -1400,8 +1619,10 @@ void launch_factor_elastic(const Geom& g, const SysDesc* sys, int nsys,
                            const double* E, const uint8_t* mask,
                            const double* Ke, double* out64, float* out32,
                            double* metric, int* err, hipStream_t s) {
-  hipLaunchKernelGGL(k_factor<2>, dim3(nsys), dim3(FT_NT), 0, s, g, sys, E,
-                     mask, Ke, out64, out32, metric, err);
+  hipLaunchKernelGGL(k_factor_twisted<2>, dim3(2 * nsys), dim3(FT_NT), 0, s, g,
+                     sys, nsys, E, mask, Ke, out64, out32, metric, err);
+  hipLaunchKernelGGL(k_factor_middle<2>, dim3(nsys), dim3(FT_NT), 0, s, g, sys,
+                     nsys, E, mask, Ke, out64, out32, metric, err);
 }
 
 void launch_factor_heat(const Geom& g, const SysDesc* sys, int nsys,
@@ -1413,19 +1634,23 @@ void launch_factor_heat(const Geom& g, const SysDesc* sys, int nsys,
 }
 
 void launch_level1(const Level1Args& a, int nsys, hipStream_t s) {
-  hipLaunchKernelGGL(k_level1, dim3(nsys), dim3(AP_NT), 0, s, a);
+  hipLaunchKernelGGL(k_level1<false>, dim3(2 * nsys), dim3(AP_NT), 0, s, a);
+  hipLaunchKernelGGL(k_level1<true>, dim3(2 * nsys), dim3(AP_NT), 0, s, a);
 }
 
 void launch_level1_batch(const Level1Args* tab, const int* start, int nent,
                          int total, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_level1_batch, dim3(grid), dim3(AP_NT), 0, s, tab, start,
-                     nent, total);
+  hipLaunchKernelGGL(k_level1_batch<false>, dim3(grid), dim3(AP_NT), 0, s, tab,
+                     start, nent, total);
+  hipLaunchKernelGGL(k_level1_batch<true>, dim3(grid), dim3(AP_NT), 0, s, tab,
+                     start, nent, total);
 }
 
 bool eig_fits_host(int bs, int m) { return eig_fits(bs, m); }
 
 bool level1_fits(int bs, int nb, bool fp32) {
-  return l1_fits<double>(bs, nb) && (!fp32 || l1_fits<float>(bs, nb));
+  const int L = nb - (nb - 1) / 2;     // the longer chain of the twisted sweep
+  return l1_fits<double>(bs, L) && (!fp32 || l1_fits<float>(bs, L));
 }
 
 void launch_heat_eigen(const Geom& g, const SysDesc* sys, int nsys,

@@ -159,6 +159,7 @@ struct msp_handle {
   int n_fp64_subs = 0;
   double fp32_metric_max = kFp32MetricMax;
   double* d_lsol = nullptr;
+  double* d_gmid = nullptr;        // first level: chain couplings into the middle rows
   double* d_Som = nullptr;
   double *d_X = nullptr, *d_Y = nullptr, *d_Z = nullptr;
   double *d_psi = nullptr, *d_lam = nullptr;
@@ -264,7 +265,9 @@ msp_status build_geometry(msp_handle* h) {
     s.foff = foff;
     s.voff = voff;
     const long long bs = 2LL * s.nxb;
-    foff += (long long)s.nyb * (bs * bs + 6 * bs);   // records: S^-1 | F
+    // records S^-1 | F of the twisted factorisation: node rows 0..m from the
+    // top, nyb-1..m from the bottom (the middle row m twice)
+    foff += (long long)(s.nyb + 1) * (bs * bs + 6 * bs);
     voff += (long long)s.nyb * bs;
     h->subs.push_back(s);
     return (int)h->subs.size() - 1;
@@ -455,7 +458,7 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
   if (!h) return MSP_OK;
   void* bufs[] = {h->d_elem, h->d_mask, h->d_dflag, h->d_E, h->d_subs,
                   h->d_omegas, h->d_sub_grid, h->d_S64, h->d_S32, h->d_metric,
-                  h->d_use64, h->d_lsol, h->d_Som,
+                  h->d_use64, h->d_lsol, h->d_gmid, h->d_Som,
                   h->d_X, h->d_Y, h->d_Z, h->d_psi, h->d_lam, h->d_nsel,
                   h->d_cap, h->d_cn, h->d_col_node, h->d_pairs, h->d_W,
                   h->d_K0, h->d_sdiag, h->d_P, h->d_Lp, h->d_Rp, h->d_dropped,
@@ -683,7 +686,9 @@ static msp_status ensure_setup_buffers(msp_handle* h) {
   // reads less than 1 KiB past the last record
   A(dalloc(&h->d_S64, h->l1_entries + 1024));
   if (h->fp32) A(dalloc(&h->d_S32, h->l1_entries + 1024));
-  A(dalloc(&h->d_metric, h->subs.size()));
+  // per system, then the two chain parts of the twisted factorisation
+  A(dalloc(&h->d_metric, 3 * h->subs.size()));
+  A(dalloc(&h->d_gmid, 2 * (long long)MAXBS * h->subs.size()));
   A(dalloc(&h->d_use64, h->subs.size()));
   A(dalloc(&h->d_lsol, h->l1_vec));
   A(dalloc(&h->d_Som, h->om_entries));
@@ -699,7 +704,8 @@ static msp_status ensure_setup_buffers(msp_handle* h) {
   if (!ok) {
     // leave none of them behind, so that a later setup tries again
     void** bufs[] = {(void**)&h->d_S64, (void**)&h->d_S32, (void**)&h->d_metric,
-                     (void**)&h->d_use64, (void**)&h->d_lsol, (void**)&h->d_Som,
+                     (void**)&h->d_use64, (void**)&h->d_lsol, (void**)&h->d_gmid,
+                     (void**)&h->d_Som,
                      (void**)&h->d_X, (void**)&h->d_Y, (void**)&h->d_Z,
                      (void**)&h->d_psi, (void**)&h->d_lam, (void**)&h->d_nsel,
                      (void**)&h->d_cap, (void**)&h->d_cn, &h->d_eig_state};
@@ -911,6 +917,7 @@ static Level1Args l1_args(msp_handle* h, const double* r, CGScalars* sc, int che
   a.use64 = h->fp32 ? h->d_use64 : nullptr;
   a.r = r;
   a.lsol = h->d_lsol;
+  a.gmid = h->d_gmid;
   a.sc = sc;
   a.part_upd = h->part_upd;
   a.nb_upd = h->nb_upd;
@@ -1387,7 +1394,7 @@ static msp_status batch_tables(msp_batch* b, const std::vector<msp_handle*>& hs,
     gv.push_back(gv_args(h, h->d_sc));
     cb.push_back(cb_args(h, true, true, h->d_r, h->d_q, h->d_z));
     const int nblk[6] = {matvec_blocks(h->g, h->mv_ty), update_blocks(h->n_dofs),
-                         (int)h->subs.size(),
+                         2 * (int)h->subs.size(),
                          h->nc > 0 ? (int)h->cn_h.size() * restrict_bands() : 0,
                          gemv_blocks(h->nc), combine_blocks(h->g)};
     for (int k = 0; k < 6; ++k)
@@ -2052,9 +2059,10 @@ extern "C" msp_status msp_query(msp_handle* h, int64_t* q) {
   long long l1_bytes = 0;
   for (size_t i = 0; i < h->subs.size(); ++i) {
     const SysDesc& s = h->subs[i];
-    // one application reads the record of every row in the forward sweep
-    // and all but the last row's again in the backward sweep
-    const long long ent = (2LL * s.nyb - 1) * (4LL * s.nxb * s.nxb + 12LL * s.nxb);
+    // one application of the twisted sweep reads every row's record twice
+    // (the middle row's once per chain) and each chain's middle coupling
+    // once more
+    const long long ent = 2LL * s.nyb * (4LL * s.nxb * s.nxb + 12LL * s.nxb) + 24LL * s.nxb;
     const bool f64 = !h->fp32 || (i < h->use64_h.size() ? h->use64_h[i] != 0 : true);
     l1_bytes += ent * (f64 ? 8 : 4);
   }
