@@ -383,10 +383,16 @@ __global__ void k_k0_unscale(double* __restrict__ K0, int ldk,
 // once per node and accumulates every column of the node in registers
 // (coalesced psi reads); column sums are a wavefront butterfly and a
 // fixed-order sum over the waves, written per band to cpart[band][col].
+// The psi loads of RS_JC modes at all of a thread's nodes are issued
+// together (indices clamped into the valid range, extra modes dropped), and
+// the first chunk together with the loads of r, so that a workgroup waits
+// for HBM about once per chunk rather than once per mode.
 constexpr int RS_NT = 256;
 constexpr int RS_CH = 4;       // bands of neighbourhood rows per coarse node
-constexpr int RS_NPT = 8;      // band nodes per thread (band <= RS_NT*RS_NPT)
+constexpr int RS_NPT = 6;      // band nodes per thread (band <= RS_NT*RS_NPT)
+constexpr int RS_JC = 8;       // modes per load chunk
 constexpr int KMAXD = 24;
+static_assert(KMAXD % RS_JC == 0, "mode chunks must tile the mode cap");
 
 struct RsLds {
   double red[(2 * KMAXD + 1) * (RS_NT / 64)];
@@ -418,51 +424,68 @@ __device__ __forceinline__ void restrict_body(const RestrictArgs& a, int bid,
   const int r0w = (band * cn.nyw) / RS_CH, r1w = ((band + 1) * cn.nyw) / RS_CH;
   const int lo = r0w * cn.nxw, hi = r1w * cn.nxw;
   const double* ps = a.psi + cn.psi_off;
-  // this thread's nodes of the band: masked chi*r in registers first, so
-  // that the loads of one mode (below) are independent of each other
+  // this thread's nodes of the band (past the band's end: its first node,
+  // weighted 0)
   int locs[RS_NPT];
+  bool okp[RS_NPT];
+#pragma unroll
+  for (int p = 0; p < RS_NPT; ++p) {
+    const int loc = lo + threadIdx.x + p * RS_NT;
+    okp[p] = loc < hi;
+    locs[p] = okp[p] ? loc : lo;
+  }
+  double pv[RS_JC][RS_NPT];
+  auto load_chunk = [&](int j0) {
+#pragma unroll
+    for (int u = 0; u < RS_JC; ++u) {
+      const long long j = min(j0 + u, nm - 1);
+#pragma unroll
+      for (int p = 0; p < RS_NPT; ++p) pv[u][p] = ps[j * nw + locs[p]];
+    }
+  };
+  load_chunk(0);
+  // masked chi*r at the nodes, and the rotation column's partial sum
   double r0[RS_NPT], r1[RS_NPT];
   double ar = 0.0;
 #pragma unroll
   for (int p = 0; p < RS_NPT; ++p) {
-    const int loc = lo + threadIdx.x + p * RS_NT;
-    const bool ok = loc < hi;
-    locs[p] = ok ? loc : lo;
     const int x = cn.x0 + locs[p] % cn.nxw, y = cn.y0 + locs[p] / cn.nxw;
     const double chi = chi_at(g, cn.cx, cn.cy, x, y);
     const long long node = (long long)y * g.nnx + x;
     const double2 rv = reinterpret_cast<const double2*>(r)[node];
     const uchar2 m = reinterpret_cast<const uchar2*>(mask)[node];
-    r0[p] = (!ok || m.x) ? 0.0 : chi * rv.x;
-    r1[p] = (!ok || m.y) ? 0.0 : chi * rv.y;
+    r0[p] = (!okp[p] || m.x) ? 0.0 : chi * rv.x;
+    r1[p] = (!okp[p] || m.y) ? 0.0 : chi * rv.y;
     const double rx = (x - cn.cx * g.sx) * g.h * invH;
     const double ry = (y - cn.cy * g.sy) * g.h * invH;
     ar += -ry * r0[p] + rx * r1[p];
   }
-  double ax[KMAXD], ay[KMAXD];
-#pragma unroll
-  for (int j = 0; j < KMAXD; ++j) {
-    ax[j] = ay[j] = 0.0;
-    if (j < nm) {
-      double pv[RS_NPT];
-#pragma unroll
-      for (int p = 0; p < RS_NPT; ++p) pv[p] = ps[(long long)j * nw + locs[p]];
-#pragma unroll
-      for (int p = 0; p < RS_NPT; ++p) {
-        ax[j] += pv[p] * r0[p];
-        ay[j] += pv[p] * r1[p];
-      }
-    }
-  }
   const int w = threadIdx.x >> 6;
 #pragma unroll
-  for (int j = 0; j < KMAXD; ++j) {
-    if (j < nm) {
-      const double sx = wave_sum(ax[j]);
-      const double sy = wave_sum(ay[j]);
-      if ((threadIdx.x & 63) == 0) {
-        red[j * (RS_NT / 64) + w] = sx;
-        red[(nm + j) * (RS_NT / 64) + w] = sy;
+  for (int c = 0; c < KMAXD / RS_JC; ++c) {
+    const int j0 = c * RS_JC;
+    if (j0 >= nm) break;
+    if (c > 0) load_chunk(j0);
+    double ax[RS_JC], ay[RS_JC];
+#pragma unroll
+    for (int u = 0; u < RS_JC; ++u) {
+      ax[u] = ay[u] = 0.0;
+#pragma unroll
+      for (int p = 0; p < RS_NPT; ++p) {
+        ax[u] += pv[u][p] * r0[p];
+        ay[u] += pv[u][p] * r1[p];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RS_JC; ++u) {
+      const int j = j0 + u;
+      if (j < nm) {
+        const double sx = wave_sum(ax[u]);
+        const double sy = wave_sum(ay[u]);
+        if ((threadIdx.x & 63) == 0) {
+          red[j * (RS_NT / 64) + w] = sx;
+          red[(nm + j) * (RS_NT / 64) + w] = sy;
+        }
       }
     }
   }
@@ -556,10 +579,34 @@ k_coarse_gemv_batch(const GemvArgs* __restrict__ tab, const int* __restrict__ st
 // partial sums of r.z and, flexible, z.q per workgroup, read by the next
 // iteration's stiffness and update kernels; in MODE 1 workgroup 0 advances
 // the iteration counter.
+// Combination z = (first-level part + coarse part) on free DOFs, with the
+// CG partials.  One workgroup per (coarse cell, band of the cell's node
+// rows): cell (cx, cy) owns the nodes x in [cx S, cx S + S) (the last cell
+// column also x = nx), likewise in y.  Everything that can touch those
+// nodes is the same for the whole workgroup and is staged in LDS first: the
+// subdomains of the 3 x 3 block of subdomain-grid cells around the cell
+// (a node lies in at most 4 of them) and the cell's four corner coarse
+// nodes with their coefficients c0.  The per-node loads (local solutions,
+// psi of every corner's modes, r, q) then go out together.
+constexpr int CB_NT = 256;
+constexpr int CB_JC = 8;                      // modes per load chunk
+constexpr int CB_NCOL = 2 * KMAXD + 1;        // columns of one coarse node
+
 struct CbLds {
-  double red[256 / 64 + 1];
+  double red[CB_NT / 64 + 1];
+  double c0[4][CB_NCOL];
+  long long svoff[9];
+  long long cpsi[4];
+  int sx0[9], sy0[9], snx[9], sny[9];
+  int cx0[4], cy0[4], cnxw[4], cnw[4], cnm[4], crot[4], ccol[4];
   int shi;
 };
+
+// rows of a cell per workgroup, and bands per cell
+__host__ __device__ inline int cb_rows(const Geom& g) { return CB_NT / (g.sx + 1); }
+__host__ __device__ inline int cb_bands(const Geom& g) {
+  return (g.sy + 1 + cb_rows(g) - 1) / cb_rows(g);
+}
 
 template <int MODE>
 __device__ __forceinline__ void combine_body(const CombineCall& a, int bid,
@@ -568,95 +615,151 @@ __device__ __forceinline__ void combine_body(const CombineCall& a, int bid,
   const CombineArgs& ca = a.ca;
   const uint8_t* __restrict__ mask = a.mask;
   CGScalars* sc = a.sc;
-  double* red = L.red;
+  const int tid = threadIdx.x;
   if (MODE != 0 && block_read_done(sc, &L.shi)) return;
-  const long long node = (long long)bid * 256 + threadIdx.x;
-  const long long nn = (long long)g.nnx * g.nny;
-  double d_rz = 0.0, d_zq = 0.0;
-  if (node < nn) {
-    const int x = (int)(node % g.nnx), y = (int)(node / g.nnx);
-    double z0 = 0.0, z1 = 0.0;
-    if (ca.use_l1) {
-      const int gx0 = x / g.sx, gy0 = y / g.sy;
-      for (int gy = gy0 - 1; gy <= gy0 + 1; ++gy) {
-        if (gy < 0 || gy >= ca.ngy) continue;
-        for (int gx = gx0 - 1; gx <= gx0 + 1; ++gx) {
-          if (gx < 0 || gx >= ca.ngx) continue;
-          const int sid = ca.sub_grid[gy * ca.ngx + gx];
-          if (sid < 0) continue;
-          const SysDesc s = ca.sys[sid];
-          if (x < s.x0 || x >= s.x0 + s.nxb || y < s.y0 || y >= s.y0 + s.nyb) continue;
-          const long long li = s.voff + 2 * ((long long)(y - s.y0) * s.nxb + (x - s.x0));
-          const double* ls = (const double*)ca.lsol;
-          z0 += ls[li];
-          z1 += ls[li + 1];
-        }
-      }
-    }
-    if (ca.use_coarse) {
-      const int cx0 = x / g.sx, cy0 = y / g.sy;
-      for (int cy = cy0; cy <= cy0 + 1; ++cy) {
-        if (cy >= g.ncy) continue;
-        for (int cx = cx0; cx <= cx0 + 1; ++cx) {
-          if (cx >= g.ncx) continue;
-          const CoarseNode cn = ca.cnodes[cy * g.ncx + cx];
-          const int ncol = 2 * cn.nmodes + cn.nrot;
-          if (ncol == 0) continue;
-          const double chi = chi_at(g, cx, cy, x, y);
-          if (chi == 0.0) continue;
-          const int nw = cn.nxw * cn.nyw;
-          const int loc = (y - cn.y0) * cn.nxw + (x - cn.x0);
-          double s0 = 0.0, s1 = 0.0;
-          const double* pp = ca.psi + cn.psi_off + loc;
-          const double* cc = ca.c0 + cn.col0;
-          // modes in chunks of 4: the loads of a chunk are independent
-          for (int j0 = 0; j0 < cn.nmodes; j0 += 4) {
-            double pv[4], ca0[4], ca1[4];
+  const int ncellx = g.nx / g.sx, ncelly = g.ny / g.sy;
+  const int nbands = cb_bands(g), rpb = cb_rows(g);
+  const int cell = bid / nbands, band = bid - (bid / nbands) * nbands;
+  const int cx = cell % ncellx, cy = cell / ncellx;
+  const int wx = g.sx + (cx == ncellx - 1 ? 1 : 0);
+  const int wy = g.sy + (cy == ncelly - 1 ? 1 : 0);
+  const int ty = band * rpb + tid / wx, tx = tid - (tid / wx) * wx;
+  const bool act = tid < rpb * wx && ty < wy;
+  // idle threads stand on the cell's first node (valid addresses, no output)
+  const int x = cx * g.sx + (act ? tx : 0), y = cy * g.sy + (act ? ty : 0);
+  const long long node = (long long)y * g.nnx + x;
+  // stage the candidates (empty boxes / no modes where there are none)
+  if (tid < 9) {
+    const int gy = cy - 1 + tid / 3, gx = cx - 1 + tid % 3;
+    int sid = -1;
+    if (ca.use_l1 && gx >= 0 && gx < ca.ngx && gy >= 0 && gy < ca.ngy)
+      sid = ca.sub_grid[gy * ca.ngx + gx];
+    SysDesc sd{};
+    if (sid >= 0) sd = ca.sys[sid];
+    L.sx0[tid] = sd.x0;
+    L.sy0[tid] = sd.y0;
+    L.snx[tid] = sid >= 0 ? sd.nxb : 0;
+    L.sny[tid] = sid >= 0 ? sd.nyb : 0;
+    L.svoff[tid] = sid >= 0 ? sd.voff : 0;
+  } else if (tid >= 64 && tid < 68) {
+    const int k = tid - 64;
+    CoarseNode cn{};
+    if (ca.use_coarse) cn = ca.cnodes[(cy + (k >> 1)) * g.ncx + cx + (k & 1)];
+    const bool on = ca.use_coarse && (2 * cn.nmodes + cn.nrot) > 0;
+    L.cx0[k] = cn.x0;
+    L.cy0[k] = cn.y0;
+    L.cnxw[k] = cn.nxw;
+    L.cnw[k] = cn.nxw * cn.nyw;
+    L.cnm[k] = on ? cn.nmodes : 0;
+    L.crot[k] = on ? cn.nrot : 0;
+    L.ccol[k] = cn.col0;
+    L.cpsi[k] = cn.psi_off;
+  }
+  // loads that need no candidate
+  uchar2 mk = reinterpret_cast<const uchar2*>(mask)[node];
+  double2 rv = make_double2(0.0, 0.0), qv = make_double2(0.0, 0.0);
+  if (MODE != 0) {
+    rv = reinterpret_cast<const double2*>(a.r)[node];
+    if (MODE == 1 && sc->flexible) qv = reinterpret_cast<const double2*>(a.q)[node];
+  }
+  __syncthreads();
+  for (int idx = tid; idx < 4 * CB_NCOL; idx += CB_NT) {
+    const int k = idx / CB_NCOL, j = idx - (idx / CB_NCOL) * CB_NCOL;
+    if (j < 2 * L.cnm[k] + L.crot[k]) L.c0[k][j] = ca.c0[L.ccol[k] + j];
+  }
+  // first level: the subdomains that contain the node, in candidate order
+  // (at most four: the geometry guarantees it)
+  long long li0 = 0, li1 = 0, li2 = 0, li3 = 0;
+  int nh = 0;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-              const int j = min(j0 + t, cn.nmodes - 1);
-              pv[t] = pp[(long long)j * nw];
-              ca0[t] = cc[j];
-              ca1[t] = cc[cn.nmodes + j];
-            }
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-              const double w = (j0 + t < cn.nmodes) ? pv[t] : 0.0;
-              s0 += w * ca0[t];
-              s1 += w * ca1[t];
-            }
-          }
-          s0 *= chi;
-          s1 *= chi;
-          if (cn.nrot) {
-            const double rx = (x - cx * g.sx) * g.h * ca.invH;
-            const double ry = (y - cy * g.sy) * g.h * ca.invH;
-            const double cr = ca.c0[cn.col0 + 2 * cn.nmodes];
-            s0 += -chi * ry * cr;
-            s1 += chi * rx * cr;
-          }
-          z0 += s0;
-          z1 += s1;
-        }
-      }
-    }
-    const uchar2 m = reinterpret_cast<const uchar2*>(mask)[node];
-    if (m.x) z0 = 0.0;
-    if (m.y) z1 = 0.0;
-    reinterpret_cast<double2*>(a.z)[node] = make_double2(z0, z1);
-    if (MODE != 0) {
-      const double2 rv = reinterpret_cast<const double2*>(a.r)[node];
-      d_rz = rv.x * z0 + rv.y * z1;
-      if (MODE == 1 && sc->flexible) {
-        const double2 qv = reinterpret_cast<const double2*>(a.q)[node];
-        d_zq = qv.x * z0 + qv.y * z1;
-      }
+  for (int k = 0; k < 9; ++k) {
+    const int sx = L.sx0[k], sy = L.sy0[k];
+    if (x >= sx && x < sx + L.snx[k] && y >= sy && y < sy + L.sny[k]) {
+      const long long li = L.svoff[k] + 2 * ((long long)(y - sy) * L.snx[k] + (x - sx));
+      li0 = nh == 0 ? li : li0;
+      li1 = nh == 1 ? li : li1;
+      li2 = nh == 2 ? li : li2;
+      li3 = nh == 3 ? li : li3;
+      ++nh;
     }
   }
+  const double2* ls = reinterpret_cast<const double2*>(ca.lsol);
+  double2 lv0 = make_double2(0.0, 0.0), lv1 = lv0, lv2 = lv0, lv3 = lv0;
+  if (nh > 0) lv0 = ls[li0 >> 1];
+  if (nh > 1) lv1 = ls[li1 >> 1];
+  if (nh > 2) lv2 = ls[li2 >> 1];
+  if (nh > 3) lv3 = ls[li3 >> 1];
+  // coarse part: the first chunk of every corner's modes at this node
+  double pv[4][CB_JC];
+  const double* pp[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int nm = L.cnm[k];
+    pp[k] = ca.psi + L.cpsi[k] + (long long)(y - L.cy0[k]) * L.cnxw[k] + (x - L.cx0[k]);
+    if (nm > 0) {
+#pragma unroll
+      for (int u = 0; u < CB_JC; ++u) pv[k][u] = pp[k][(long long)min(u, nm - 1) * L.cnw[k]];
+    }
+  }
+  __syncthreads();
+  double z0 = 0.0, z1 = 0.0;
+  z0 += lv0.x;
+  z1 += lv0.y;
+  z0 += lv1.x;
+  z1 += lv1.y;
+  z0 += lv2.x;
+  z1 += lv2.y;
+  z0 += lv3.x;
+  z1 += lv3.y;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int nm = L.cnm[k];
+    if (nm == 0) continue;
+    const int ccx = cx + (k & 1), ccy = cy + (k >> 1);
+    const double chi = chi_at(g, ccx, ccy, x, y);
+    const double* c = L.c0[k];
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int u = 0; u < CB_JC; ++u) {
+      const double w = u < nm ? pv[k][u] : 0.0;
+      s0 += w * c[min(u, nm - 1)];
+      s1 += w * c[nm + min(u, nm - 1)];
+    }
+    for (int j0 = CB_JC; j0 < nm; j0 += CB_JC) {
+#pragma unroll
+      for (int u = 0; u < CB_JC; ++u)
+        pv[k][u] = pp[k][(long long)min(j0 + u, nm - 1) * L.cnw[k]];
+#pragma unroll
+      for (int u = 0; u < CB_JC; ++u) {
+        const double w = j0 + u < nm ? pv[k][u] : 0.0;
+        s0 += w * c[min(j0 + u, nm - 1)];
+        s1 += w * c[nm + min(j0 + u, nm - 1)];
+      }
+    }
+    s0 *= chi;
+    s1 *= chi;
+    if (L.crot[k]) {
+      const double rx = (x - ccx * g.sx) * g.h * ca.invH;
+      const double ry = (y - ccy * g.sy) * g.h * ca.invH;
+      const double cr = c[2 * nm];
+      s0 += -chi * ry * cr;
+      s1 += chi * rx * cr;
+    }
+    z0 += s0;
+    z1 += s1;
+  }
+  if (mk.x) z0 = 0.0;
+  if (mk.y) z1 = 0.0;
+  if (act) reinterpret_cast<double2*>(a.z)[node] = make_double2(z0, z1);
   if (MODE == 0) return;
-  const double s_rz = block_sum<256>(d_rz, red);
-  const double s_zq = block_sum<256>(d_zq, red);
-  if (threadIdx.x == 0) {
+  double d_rz = 0.0, d_zq = 0.0;
+  if (act) {
+    d_rz = rv.x * z0 + rv.y * z1;
+    if (MODE == 1 && sc->flexible) d_zq = qv.x * z0 + qv.y * z1;
+  }
+  const double s_rz = block_sum<CB_NT>(d_rz, L.red);
+  const double s_zq = block_sum<CB_NT>(d_zq, L.red);
+  if (tid == 0) {
     a.part[bid] = s_rz;
     a.part[nblk + bid] = s_zq;
     if (MODE == 1 && bid == 0) sc->iter = sc->iter + 1;
@@ -664,12 +767,12 @@ __device__ __forceinline__ void combine_body(const CombineCall& a, int bid,
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(256) k_combine(CombineCall a) {
+__global__ void __launch_bounds__(CB_NT) k_combine(CombineCall a) {
   __shared__ CbLds L;
   combine_body<MODE>(a, blockIdx.x, gridDim.x, L);
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(CB_NT)
 k_combine_cg_batch(const CombineCall* __restrict__ tab, const int* __restrict__ start,
                    int nent) {
   __shared__ CbLds L;
@@ -763,22 +866,22 @@ void launch_coarse_gemv_batch(const GemvArgs* tab, const int* start, int nent,
 }
 
 int combine_blocks(const Geom& g) {
-  return (int)(((long long)g.nnx * g.nny + 255) / 256);
+  return (g.nx / g.sx) * (g.ny / g.sy) * cb_bands(g);
 }
 
 void launch_combine(int mode, const CombineCall& a, hipStream_t s) {
   const dim3 grid(combine_blocks(a.g));
   if (mode == 0)
-    hipLaunchKernelGGL(k_combine<0>, grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_combine<0>, grid, dim3(CB_NT), 0, s, a);
   else if (mode == 1)
-    hipLaunchKernelGGL(k_combine<1>, grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_combine<1>, grid, dim3(CB_NT), 0, s, a);
   else
-    hipLaunchKernelGGL(k_combine<2>, grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_combine<2>, grid, dim3(CB_NT), 0, s, a);
 }
 
 void launch_combine_cg_batch(const CombineCall* tab, const int* start, int nent,
                              int total, hipStream_t s) {
-  hipLaunchKernelGGL(k_combine_cg_batch, dim3(total), dim3(256), 0, s, tab, start, nent);
+  hipLaunchKernelGGL(k_combine_cg_batch, dim3(total), dim3(CB_NT), 0, s, tab, start, nent);
 }
 
 void launch_export_basis(const Geom& g, const CoarseNode* cn,

@@ -310,15 +310,19 @@ msp_status build_geometry(msp_handle* h) {
     if (s.nxb <= 0 || s.nyb <= 0)
       return fail(h, MSP_E_INVALID, "empty subdomain");
   }
-  // coverage of every free DOF
+  // coverage of every free DOF; the combination kernel gathers at most four
+  // local solutions per node
   {
     std::vector<uint8_t> cov((size_t)g.nnx * g.nny, 0);
     for (const SysDesc& s : h->subs)
       for (int y = s.y0; y < s.y0 + s.nyb; ++y)
-        for (int x = s.x0; x < s.x0 + s.nxb; ++x) cov[(size_t)y * g.nnx + x] = 1;
-    for (long long p = 0; p < (long long)g.nnx * g.nny; ++p)
+        for (int x = s.x0; x < s.x0 + s.nxb; ++x) cov[(size_t)y * g.nnx + x] += 1;
+    for (long long p = 0; p < (long long)g.nnx * g.nny; ++p) {
       if (!cov[p] && (!h->mask_h[2 * p] || !h->mask_h[2 * p + 1]))
         return fail(h, MSP_E_INVALID, "subdomains do not cover every free DOF (overlap too small)");
+      if (cov[p] > 4)
+        return fail(h, MSP_E_INVALID, "a node lies in more than four subdomains (need 2 * overlap <= sub_nel)");
+    }
   }
   // coarse neighbourhoods omega_l
   h->omegas.clear();
