@@ -342,11 +342,12 @@ def solve_only(torch, solvers, rho, f, reps):
 
 
 def level1_bytes(q):
-    """Algorithmic HBM bytes of one first-level launch: the factor records
-    it streams (inverse Schur block and couplings of every node row, read in
-    the forward sweep and, but for the last row, again in the backward
-    sweep, each subdomain in its selected precision), the local right-hand
-    sides gathered (FP64) and the local solutions written (FP64)."""
+    """Algorithmic HBM bytes of one first-level application (a forward and
+    a backward pass of the twisted sweep): the factor records it streams
+    (inverse Schur block and couplings of every node row, read once per
+    pass, the middle row's once per chain and pass, each subdomain in its
+    selected precision), the local right-hand sides gathered (FP64) and the
+    local solutions written (FP64)."""
     return q["level1_record_bytes"] + q["local_vec_entries"] * (8 + 8)
 
 
@@ -572,7 +573,8 @@ def main():
         "solve_only_solves_per_s": round(so_mixed, 3),
         "kernel_ms": {k: round(t / max(c, 1), 4) for k, (c, t) in kt.items()},
         "kernel_ms_per_step_total": {k: round(t, 3) for k, (c, t) in kt.items()},
-        "roofline": {"kernel": "level1_apply (mixed FP32/FP64 factor records)",
+        "roofline": {"kernel": "level1_apply: k_level1<false> + k_level1<true> "
+                               "(mixed FP32/FP64 factor records)",
                      "bound": "hbm", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -52,7 +52,8 @@ typedef enum {
  *  nu         Poisson ratio in (-1, 0.5)
  *  penal      SIMP exponent, >= 1
  *  sub_nel    coarse block edge S in elements per axis (must divide nel)
- *  overlap    delta: element layers added around each block (0 <= delta < S)
+ *  overlap    delta: element layers added around each block (0 <= delta < S,
+ *             and 2 delta <= S so that a node lies in at most four subdomains)
  *  sub_mode   0: subdomains are the blocks extended by delta (max-norm);
  *             1: subdomains are the coarse-vertex neighbourhoods of the
  *                coarse nodes that are not clamped (the paper's experiments)
