@@ -15,6 +15,22 @@ namespace msp {
 
 constexpr int MAXBS = 72;      // largest block row (DOFs) of a local system
 constexpr int MAXM = 32;       // largest eigen subspace block
+
+// Record of one node row of a first-level (elasticity) system with bs DOFs
+// per row: the inverse Schur block in 16-byte column groups, columns
+// zero-padded to a multiple of 4 (FP64 copies hold column pairs,
+// element (i, j) at (j/2)*2*bs + 2*i + j%2; FP32 copies column quads,
+// element (i, j) at (j/4)*4*bs + 4*i + j%4), then the couplings F (bs x 6).
+__host__ __device__ inline int l1_cols(int bs) { return (bs + 3) & ~3; }
+
+// Record of one node row of a heat pencil factor (bs nodes per row): the
+// inverse Schur block column-major (bs^2), the couplings F of the row with
+// the row before (bs x 3) and G with the row after (bs x 3), padded to an
+// even length so that every record starts on 16 bytes.
+__host__ __device__ inline int heat_rec(int bs) { return (bs * bs + 6 * bs + 1) & ~1; }
+__host__ __device__ inline long long l1_rec(int bs) {
+  return (long long)l1_cols(bs) * bs + 6LL * bs;
+}
 constexpr int RED_THREADS = 256;
 
 // One block-tridiagonal local system.

@@ -295,20 +295,40 @@ __device__ __forceinline__ void fac_schur(int bs, const double* P, double* W,
   }
 }
 
-// Record elements of one node row: S^{-1} (bs^2) and F (bs x 3 NDOF).
+// Records of one node row.  Heat pencils (NDOF = 1): heat_rec (S^{-1}
+// column-major, F (bs x 3), G (bs x 3)).  Elasticity (NDOF = 2): the
+// first-level layout of l1_rec (16-byte column groups, then F (bs x 6)).
 __host__ __device__ inline long long fac_rec(int ndof, int nxb) {
-  const long long bs = (long long)ndof * nxb;
-  return bs * bs + 3LL * ndof * bs;
+  const int bs = ndof * nxb;
+  return ndof == 2 ? l1_rec(bs) : (long long)heat_rec(bs);
+}
+__host__ __device__ inline long long fac_fpart(int ndof, int bs) {
+  return ndof == 2 ? (long long)l1_cols(bs) * bs : (long long)bs * bs;
 }
 
-// Inverse block of a record: column j contiguous.
+// Inverse block of a record (layout as in fac_rec; padding columns zero).
+template <int NDOF>
 __device__ __forceinline__ void fac_write_inverse(int bs, const double* S,
                                                   double* o64, float* o32) {
-  for (int idx = threadIdx.x; idx < bs * bs; idx += FT_NT) {
-    const int j = idx / bs, i = idx - (idx / bs) * bs;
-    const double v = S[i * LDSTR + j];
-    o64[idx] = v;
-    if (o32 != nullptr) o32[idx] = (float)v;
+  if (NDOF == 1) {
+    for (int idx = threadIdx.x; idx < bs * bs; idx += FT_NT) {
+      const int j = idx / bs, i = idx - (idx / bs) * bs;
+      o64[idx] = S[i * LDSTR + j];
+    }
+    return;
+  }
+  const int nc = l1_cols(bs);
+  for (int idx = threadIdx.x; idx < nc * bs; idx += FT_NT) {
+    const int jp = idx / (2 * bs), rem = idx - jp * (2 * bs);
+    const int i = rem >> 1, j = 2 * jp + (rem & 1);
+    o64[idx] = j < bs ? S[i * LDSTR + j] : 0.0;
+  }
+  if (o32 != nullptr) {
+    for (int idx = threadIdx.x; idx < nc * bs; idx += FT_NT) {
+      const int jq = idx / (4 * bs), rem = idx - jq * (4 * bs);
+      const int i = rem >> 2, j = 4 * jq + (rem & 3);
+      o32[idx] = j < bs ? (float)S[i * LDSTR + j] : 0.0f;
+    }
   }
 }
 
@@ -317,10 +337,11 @@ template <int NDOF>
 __device__ __forceinline__ void fac_write_coupling(int bs, bool coupled,
                                                    const FactorLds& L,
                                                    double* o64, float* o32) {
+  const long long fo = fac_fpart(NDOF, bs);
   for (int idx = threadIdx.x; idx < bs * 3 * NDOF; idx += FT_NT) {
     const double v = coupled ? L.Bv[idx] : 0.0;
-    o64[bs * bs + idx] = v;
-    if (o32 != nullptr) o32[bs * bs + idx] = (float)v;
+    o64[fo + idx] = v;
+    if (o32 != nullptr) o32[fo + idx] = (float)v;
   }
 }
 
@@ -369,8 +390,17 @@ __device__ double factor_chain(const Geom& g, const SysDesc& s, int row0,
     __syncthreads();
     gj_invert(S, bs, L.pv, err);
     const long long off = s.foff + (long long)(rec0 + j) * rec;
-    fac_write_inverse(bs, S, out64 + off, out32 ? out32 + off : nullptr);
+    fac_write_inverse<NDOF>(bs, S, out64 + off, out32 ? out32 + off : nullptr);
     fac_write_coupling<NDOF>(bs, j > 0, L, out64 + off, out32 ? out32 + off : nullptr);
+    if (NDOF == 1) {
+      // G: couplings with the next row of the chain (zero for the last)
+      __syncthreads();
+      const bool nxt = j + 1 < count;
+      if (nxt) fac_coupling<NDOF>(s.nxb, 1 + dir, L);
+      __syncthreads();
+      for (int idx = tid; idx < 3 * bs; idx += FT_NT)
+        out64[off + (long long)bs * bs + 3 * bs + idx] = nxt ? L.Bv[idx] : 0.0;
+    }
     for (int a = tid; a < bs; a += FT_NT) mloc = fmax(mloc, S[a * LDSTR + a] * L.ddiag[a]);
     __syncthreads();
     const int t = prev;
@@ -431,12 +461,14 @@ k_factor_twisted(Geom g, const SysDesc* __restrict__ systems, int nsys,
   if (threadIdx.x == 0) metric[nsys + blockIdx.x] = mm;
 }
 
-// Load the inverse block of a record into LDS (row stride LDSTR).
+// Load the inverse block of an elasticity record (FP64 column pairs) into
+// LDS (row stride LDSTR).
 __device__ __forceinline__ void fac_load_inverse(int bs, const double* __restrict__ o,
                                                  double* P) {
-  for (int idx = threadIdx.x; idx < bs * bs; idx += FT_NT) {
-    const int j = idx / bs, i = idx - (idx / bs) * bs;
-    P[i * LDSTR + j] = o[idx];
+  for (int idx = threadIdx.x; idx < l1_cols(bs) * bs; idx += FT_NT) {
+    const int jp = idx / (2 * bs), rem = idx - jp * (2 * bs);
+    const int i = rem >> 1, j = 2 * jp + (rem & 1);
+    if (j < bs) P[i * LDSTR + j] = o[idx];
   }
 }
 
@@ -487,8 +519,8 @@ k_factor_middle(Geom g, const SysDesc* __restrict__ systems, int nsys,
   fac_write_coupling<NDOF>(bs, m + 1 < s.nyb, L, out64 + obot, out32 ? out32 + obot : nullptr);
   __syncthreads();
   gj_invert(S, bs, L.pv, err);
-  fac_write_inverse(bs, S, out64 + otop, out32 ? out32 + otop : nullptr);
-  fac_write_inverse(bs, S, out64 + obot, out32 ? out32 + obot : nullptr);
+  fac_write_inverse<NDOF>(bs, S, out64 + otop, out32 ? out32 + otop : nullptr);
+  fac_write_inverse<NDOF>(bs, S, out64 + obot, out32 ? out32 + obot : nullptr);
   double mloc = 0.0;
   for (int a = tid; a < bs; a += FT_NT) mloc = fmax(mloc, S[a * LDSTR + a] * L.ddiag[a]);
   const double mm = fac_wg_max(mloc, L);
@@ -521,7 +553,7 @@ k_factor_middle(Geom g, const SysDesc* __restrict__ systems, int nsys,
 //    the finished position into v.
 // Two barriers per step.
 constexpr int L1_NS = 3;                   // column groups of the block GEMV
-constexpr int L1_GMAX = (MAXBS + L1_NS - 1) / L1_NS;   // columns per group
+constexpr int L1_GMAX = 4 * ((MAXBS / 4 + L1_NS - 1) / L1_NS);   // columns per group
 constexpr int L1_COMPUTE = 256;            // threads of the compute waves
 constexpr int L1_NLW = (AP_NT - L1_COMPUTE) / 64;   // loader waves
 constexpr int L1_CHUNK = 1024;             // bytes of one wave's DMA load
@@ -531,22 +563,22 @@ static_assert(L1_NS * MAXBS <= L1_COMPUTE, "GEMV threads exceed the compute wave
 // ring geometry of one subdomain: R slots of nch 1 KiB chunks; chunk q is
 // copied by loader wave q % L1_NLW
 struct L1Ring {
-  int rec;       // record elements (bs^2 + 6 bs)
+  int rec;       // record elements (l1_rec)
   int nch;       // chunks per record
   int slot;      // slot bytes
   int R;         // ring depth, 2..8
 };
 
-// LDS elements beside the ring: v (nb*bs), w (bs), partial sums
-// (2 step parities x L1_NS groups x MAXBS)
+// LDS elements beside the ring: v (nb*bs, rounded up to 4), w (l1_cols,
+// padding zero), partial sums P[parity][row][group] (2 x MAXBS x 4)
 __host__ __device__ inline int l1_vec_elems(int bs, int nb) {
-  return nb * bs + bs + 2 * L1_NS * MAXBS;
+  return ((nb * bs + 3) & ~3) + l1_cols(bs) + 2 * 4 * MAXBS;
 }
 
 template <typename T>
 __host__ __device__ inline L1Ring l1_ring(int bs, int nb) {
   L1Ring g;
-  g.rec = bs * bs + 6 * bs;
+  g.rec = (int)l1_rec(bs);
   g.nch = (g.rec * (int)sizeof(T) + L1_CHUNK - 1) / L1_CHUNK;
   g.slot = g.nch * L1_CHUNK;
   const int vbytes = l1_vec_elems(bs, nb) * (int)sizeof(T);
@@ -635,30 +667,47 @@ __device__ __forceinline__ void wait_vmcnt(int n) {
   }
 }
 
-// GEMV of one column group: sum over j < n of S[j*ld + i] * w[j], n <= NJ,
-// fully unrolled with every LDS read issued before the first use; columns
-// j >= n read a valid entry (column 0 of the group) and weigh it by 0.
-// Four accumulators in a fixed order.
+// 16 bytes of T: four floats or two doubles
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float4 type; static constexpr int n = 4; };
+template <> struct Vec16<double> { typedef double2 type; static constexpr int n = 2; };
+
+// GEMV of one column group of a record block in 16-byte column groups:
+// sum over j < n of S(i, j) * w[j] (n <= NJ, a multiple of the group
+// width), where S points at the group's first 16-byte column group and
+// column group u of row i sits at S + u*G*bs + G*i (G = 16 / sizeof(T)).
+// Fully unrolled, every LDS read issued before the first use; column
+// groups at or past n read group 0 and weigh it by 0.  Four accumulators,
+// column j into accumulator j % 4.
 template <typename T, int NJ>
-__device__ __forceinline__ T lds_gemv_group(const T* S, int ld, int i,
+__device__ __forceinline__ T lds_gemv_group(const T* S, int bs, int i,
                                             const T* w, int n) {
-  T s[NJ], x[NJ];
+  typedef typename Vec16<T>::type V;
+  constexpr int G = Vec16<T>::n;
+  constexpr int NU = NJ / G;
+  static_assert(NJ % 4 == 0, "column groups hold whole quads");
+  V s[NU], x[NU];
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    const int jc = j < n ? j : 0;
-    s[j] = S[jc * ld + i];
-    x[j] = w[jc];
+  for (int u = 0; u < NU; ++u) {
+    const int uc = u * G < n ? u : 0;
+    s[u] = *reinterpret_cast<const V*>(S + uc * G * bs + G * i);
+    x[u] = *reinterpret_cast<const V*>(w + uc * G);
   }
   T a[4] = {0, 0, 0, 0};
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) a[j & 3] += s[j] * (j < n ? x[j] : (T)0);
+  for (int u = 0; u < NU; ++u) {
+    const T m = u * G < n ? (T)1 : (T)0;
+    if constexpr (G == 4) {
+      a[0] += s[u].x * (m * x[u].x);
+      a[1] += s[u].y * (m * x[u].y);
+      a[2] += s[u].z * (m * x[u].z);
+      a[3] += s[u].w * (m * x[u].w);
+    } else {
+      a[(2 * u) & 3] += s[u].x * (m * x[u].x);
+      a[(2 * u + 1) & 3] += s[u].y * (m * x[u].y);
+    }
+  }
   return (a[0] + a[1]) + (a[2] + a[3]);
-}
-
-// block index used at sweep step c (forward steps 0..nb-1, then backward
-// steps nb..2nb-2 on blocks nb-2..0)
-__device__ __forceinline__ int l1_block_of_step(int c, int nb) {
-  return c < nb ? c : 2 * nb - 2 - c;
 }
 
 typedef __attribute__((address_space(3))) void lds_void;
@@ -709,7 +758,8 @@ __device__ void level1_half(const Geom& g, const SysDesc& s, int half,
   const int tid = threadIdx.x;
   const int bs = 2 * s.nxb;
   const int nb = s.nyb;
-  const int bs2 = bs * bs;
+  const int ncols = l1_cols(bs);
+  const int fo = ncols * bs;                 // F part of a record
   const int mid = (nb - 1) >> 1;
   const int L = half ? nb - mid : mid + 1;
   const int rec0 = half ? mid + 1 : 0;
@@ -726,19 +776,19 @@ __device__ void level1_half(const Geom& g, const SysDesc& s, int half,
     return;
   }
   T* v = reinterpret_cast<T*>(lds + R * ring.slot);
-  T* w = v + L * bs;
-  T* P = w + bs;                              // P[parity][group][MAXBS]
+  T* w = v + ((L * bs + 3) & ~3);             // 16-byte aligned
+  T* P = w + ncols;                           // P[parity][row][4]: group sums
   const bool loader = tid >= L1_COMPUTE;
   const int lw = __builtin_amdgcn_readfirstlane((tid - L1_COMPUTE) >> 6);
   const int lane = tid & 63;
   // loads this wave issues per record, and after the record it waits for
   const int cw = lw < ring.nch ? (ring.nch - lw + L1_NLW - 1) / L1_NLW : 0;
   const int younger = (R - 2) * cw;
-  // GEMV role: column group q, row i
-  const int cs = (bs + L1_NS - 1) / L1_NS;
+  // GEMV role: column group q (cs columns, whole quads), row i
+  const int cs = 4 * ((ncols / 4 + L1_NS - 1) / L1_NS);
   const int gq = tid / bs, gi = tid - (tid / bs) * bs;
   const int j0 = gq * cs;
-  const int jn = min(bs, j0 + cs) - j0;
+  const int jn = max(0, min(ncols, j0 + cs) - j0);
   const bool gemv = tid < L1_NS * bs;
   // phase-1 role: row entry tid, its node and component
   const int ia = tid >> 1, ca = tid & 1;
@@ -766,6 +816,7 @@ __device__ void level1_half(const Geom& g, const SysDesc& s, int half,
     const long long d = 2 * ((long long)(s.y0 + mid) * g.nnx + s.x0 + tid / 2) + (tid & 1);
     w[tid] = mask[d] ? (T)0 : (T)r[d] - ((T)gm[tid] + (T)gm[MAXBS + tid]);
   }
+  if (tid >= bs && tid < ncols) w[tid] = (T)0;   // padding columns
   if (loader) wait_vmcnt(younger);      // record of step 0 is in its slot
   l1_barrier();
 
@@ -774,15 +825,28 @@ __device__ void level1_half(const Geom& g, const SysDesc& s, int half,
   // backward steps subtract it from t_jp).  fin_load issues the LDS reads,
   // fin_value combines them, so that callers can issue all reads before
   // the first use (the compiler otherwise waits for each read in turn).
+  static_assert(L1_NS <= 4, "group sums of a row fill one 16-byte group");
   struct Fin {
-    T p[L1_NS];
+    T p[4];
     T y;
   };
   auto fin_load = [&](int jp, int pp, int col) -> Fin {
     Fin f;
-    const T* pr = P + pp * (L1_NS * MAXBS) + col;
-#pragma unroll
-    for (int q = 0; q < L1_NS; ++q) f.p[q] = pr[q * MAXBS];
+    const T* pr = P + pp * (4 * MAXBS) + 4 * col;
+    if constexpr (sizeof(T) == 4) {
+      const float4 q = *reinterpret_cast<const float4*>(pr);
+      f.p[0] = q.x;
+      f.p[1] = q.y;
+      f.p[2] = q.z;
+      f.p[3] = q.w;
+    } else {
+      const double2 q0 = *reinterpret_cast<const double2*>(pr);
+      const double2 q1 = *reinterpret_cast<const double2*>(pr + 2);
+      f.p[0] = q0.x;
+      f.p[1] = q0.y;
+      f.p[2] = q1.x;
+      f.p[3] = q1.y;
+    }
     f.y = v[jp * bs + col];
     return f;
   };
@@ -807,8 +871,8 @@ __device__ void level1_half(const Geom& g, const SysDesc& s, int half,
       // contributes nothing; backward: F_{j+1} (couplings of position j+1
       // with j, in the previous step's slot) read transposed, entries
       // outside the row masked
-      const T* F = !BWD ? reinterpret_cast<const T*>(lds + cur * ring.slot) + bs2 + tid * 6
-                        : reinterpret_cast<const T*>(lds + prev * ring.slot) + bs2;
+      const T* F = !BWD ? reinterpret_cast<const T*>(lds + cur * ring.slot) + fo + tid * 6
+                        : reinterpret_cast<const T*>(lds + prev * ring.slot) + fo;
       T f[6];
       Fin y[6];
       bool ok[6];
@@ -838,7 +902,7 @@ __device__ void level1_half(const Geom& g, const SysDesc& s, int half,
     if (gemv) {
       if (c > 0 && tid < bs) v[jp * bs + tid] = fin_value(fin_load(jp, pp, tid), pfwd);
       const T* S = reinterpret_cast<const T*>(lds + cur * ring.slot) + j0 * bs;
-      P[(c & 1) * (L1_NS * MAXBS) + gq * MAXBS + gi] =
+      P[(c & 1) * (4 * MAXBS) + 4 * gi + gq] =
           lds_gemv_group<T, L1_GMAX>(S, bs, gi, w + j0, jn);
     } else if (loader) {
       const int cn = c + R - 1;
@@ -861,7 +925,7 @@ __device__ void level1_half(const Geom& g, const SysDesc& s, int half,
   if (!BWD) {
     // g = F_{L-1} t_{L-2}, F_{L-1} from the middle row's record in HBM
     if (tid < bs) {
-      const T* F = base + (long long)(L - 1) * ring.rec + bs2 + tid * 6;
+      const T* F = base + (long long)(L - 1) * ring.rec + fo + tid * 6;
       T acc = 0;
 #pragma unroll
       for (int t = 0; t < 6; ++t) {
@@ -1296,22 +1360,27 @@ __device__ void ritz_vectors(const double* Y, double* X,
 // step c runs, every thread holds its share of step c+1's record and vector
 // row (Z forward, the forward Y backward) in registers; they are stored to
 // the other LDS slot at the end of the step, so the loads overlap the block
-// GEMM, which gives each thread two rows and four columns.
-constexpr int EG_PFR = (MAXBS * MAXBS + 3 * MAXBS + EG_NT - 1) / EG_NT;   // record regs
+// GEMM, which runs on the matrix cores.
+typedef double eg_d4 __attribute__((ext_vector_type(4)));
+constexpr int EG_NK = (MAXBS + 3) / 4;     // K steps of 4 over a block row
+static_assert(EG_NK % 2 == 0, "the block GEMM pairs its K steps");
+constexpr int EG_RR = 0;                   // remainder rows of the block GEMM on vector lanes
 constexpr int EG_PFZ = (MAXBS * MAXM + EG_NT - 1) / EG_NT;               // row regs
 constexpr int EG_RAW = 18176;              // doubles of the kernel's carved LDS
 
 // LDS doubles the sweep needs for bs, m (2 record slots, 2 vector rows,
 // the right-hand side and the result rows)
 __host__ __device__ inline int eig_sweep_doubles(int bs, int m) {
-  const int rec = bs * bs + 3 * bs;
+  const int rec = heat_rec(bs);
   return 2 * ((rec + 1) & ~1) + 4 * bs * m;
 }
 
 // the block size m fits the kernel for rows of bs nodes
 __host__ __device__ inline bool eig_fits(int bs, int m) {
-  return m >= 4 && m <= MAXM && bs <= MAXBS && eig_sweep_doubles(bs, m) <= EG_RAW &&
-         ((bs + 1) / 2) * ((m + 3) / 4) <= EG_NT && 2 * MAXM * 64 <= EG_RAW;
+  // (the block GEMM's operand reads reach up to 2 m + 32 doubles past the
+  // sweep buffers)
+  return m >= 4 && m <= MAXM && bs <= MAXBS &&
+         eig_sweep_doubles(bs, m) + 2 * m + 32 <= EG_RAW && 2 * MAXM * 64 <= EG_RAW;
 }
 
 // LDS-only workgroup barrier (the register prefetch stays in flight)
@@ -1374,16 +1443,12 @@ k_eig_sweep(Geom g, const SysDesc* __restrict__ systems,
   // sweep buffers in LDS, addressed by offsets into raw (so that every
   // access stays an LDS access): two record slots, two vector rows, the
   // right-hand side Wl and the result rows T ([a][j], stride m)
-  const int rec = bs * bs + 3 * bs;
-  const int recp = (rec + 1) & ~1;
+  const int rec = heat_rec(bs);              // even
+  const int recp = rec;
   const int bm = bs * m;
   const int o_z = 2 * recp, o_w = 2 * recp + 2 * bm, o_t = o_w + bm;
   const double* recs = Sinv + s.foff;
   const int nsteps = 2 * nb - 1;
-  // GEMM role: row pair gr, column group gc (four columns)
-  const int nrp = (bs + 1) / 2, ncg = (m + 3) / 4;
-  const int gr = tid % nrp, gc = tid / nrp;
-  const bool gact = gc < ncg;
   // vector-row role: entries q = tid + u * EG_NT, q = j * bs + a
   int qa[EG_PFZ], qj[EG_PFZ];
 #pragma unroll
@@ -1401,98 +1466,179 @@ k_eig_sweep(Geom g, const SysDesc* __restrict__ systems,
   for (int u = 0; u < EG_PFZ; ++u)
     if (qj[u] >= 0) raw[o_z + tid + u * EG_NT] = Z[(long long)qj[u] * n + qa[u]];
   __syncthreads();
+  // block GEMM roles: full 16-row tiles on the matrix cores (wave w takes
+  // tiles w, w + 8, ...); up to EG_RR remainder rows on vector lanes
+  // (threads tid < rows * m, one output each), else a zero-padded tile
+  const int nft = bs >> 4, rrow = bs - 16 * nft;
+  const bool rvalu = rrow <= EG_RR;
+  const int nrt = nft + (rvalu ? 0 : (rrow > 0 ? 1 : 0)), nct = (m + 15) >> 4;
+  const int nk = (bs + 3) >> 2;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const bool vr = rvalu && tid < rrow * m;
+  const int vri = 16 * nft + (vr ? tid / m : 0), vrj = vr ? tid - (tid / m) * m : 0;
   for (int c = 0; c < nsteps; ++c) {
     const bool fwd = c < nb;
     const int k = c < nb ? c : 2 * nb - 2 - c;
+    const int kp = c == 0 ? 0 : (c - 1 < nb ? c - 1 : 2 * nb - 1 - c);   // row of step c-1
     const int cur = c & 1;
     const int o_s = cur ? recp : 0, o_sn = cur ? 0 : recp;     // this / other slot
     const int o_zc = o_z + (cur ? bm : 0), o_zn = o_z + (cur ? 0 : bm);
-    if (c == nb - 1) __syncthreads();    // forward rows of Y visible to the
-                                         // backward prefetch below
-    // prefetch step c+1: record and vector row (Z forward, Y backward)
-    double pr[EG_PFR], pz[EG_PFZ];
+    if (c == nb - 1) __syncthreads();    // forward rows of Y stored so far
+                                         // complete and visible
+    // prefetch step c+1: the record straight into the other LDS slot
+    // (direct-to-LDS loads of 16 bytes a lane, 1 KiB a wave, clipped at the
+    // record's end; this step reads only its own record), and the vector
+    // row (Z forward, Y backward) into registers.  The first backward row,
+    // the forward result of the previous step, is still in LDS: phase A
+    // copies it.
+    double pz[EG_PFZ];
     const bool pf = c + 1 < nsteps;
+    const bool pfz = pf && c != nb - 1;
     if (pf) {
       const int k1 = (c + 1) < nb ? c + 1 : 2 * nb - 3 - c;
-      const double* rsrc = recs + (long long)k1 * rec;
-      // unconditional loads at clamped indices (entries past the end are
-      // not stored below)
+      const unsigned char* rsrc = reinterpret_cast<const unsigned char*>(recs + (long long)k1 * rec);
+      unsigned char* rdst = reinterpret_cast<unsigned char*>(raw + o_sn);
+      const int rbytes = 8 * rec;
+      for (int q = wave; q * 1024 < rbytes; q += EG_NT / 64) {
+        const int off = q * 1024 + 16 * lane;
+        if (off < rbytes)
+          __builtin_amdgcn_global_load_lds((const void*)(rsrc + off),
+                                           (lds_void*)(rdst + q * 1024), 16, 0, 0);
+      }
+      if (pfz) {
+        const double* vsrc = ((c + 1) < nb ? Z : Y) + (long long)k1 * bs;
 #pragma unroll
-      for (int u = 0; u < EG_PFR; ++u) pr[u] = rsrc[min(tid + u * EG_NT, rec - 1)];
-      const double* vsrc = ((c + 1) < nb ? Z : Y) + (long long)k1 * bs;
-#pragma unroll
-      for (int u = 0; u < EG_PFZ; ++u) pz[u] = vsrc[(long long)max(qj[u], 0) * n + qa[u]];
+        for (int u = 0; u < EG_PFZ; ++u) pz[u] = vsrc[(long long)max(qj[u], 0) * n + qa[u]];
+      }
     }
-    // phase A: right-hand side of the row (forward: F(k) of this record;
-    // backward: F(k+1) of the previous step's record, read transposed)
-    {
-      const int o_f = (fwd ? o_s : o_sn) + bs * bs;
+    // phase A: store the previous step's result row to Y; right-hand side
+    // of this row from this record's couplings with the previous step's
+    // row (forward: F(k), with row k-1; backward: G(k), with row k+1).
+    // All of a thread's reads come first (the writes go to the same LDS
+    // array).
+    auto phase_a = [&](auto u0c, auto u1c) {
+      constexpr int U0 = decltype(u0c)::value, U1 = decltype(u1c)::value;
+      const int o_f = o_s + bs * bs + (fwd ? 0 : 3 * bs);
+      double fa[U1 - U0][3], ta[U1 - U0][3], za[U1 - U0];
 #pragma unroll
-      for (int u = 0; u < EG_PFZ; ++u) {
-        const int j = qj[u], a = qa[u];
-        if (j < 0) continue;
-        double f[3], tv[3];
+      for (int u = U0; u < U1; ++u) {
+        const int j = max(qj[u], 0), a = qa[u];
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
           const int b = min(max(a + t - 1, 0), bs - 1);
-          const bool ok = (a + t - 1) >= 0 && (a + t - 1) < bs;
-          const double fv = fwd ? raw[o_f + a * 3 + t] : raw[o_f + b * 3 + (2 - t)];
-          f[t] = (ok && (!fwd || k > 0)) ? fv : 0.0;
-          tv[t] = raw[o_t + b * m + j];
+          fa[u - U0][t] = raw[o_f + a * 3 + t];
+          ta[u - U0][t] = raw[o_t + b * m + j];
         }
-        const double zv = raw[o_zc + tid + u * EG_NT];
-        double w = fwd ? zv : 0.0;
+        za[u - U0] = raw[o_zc + (qj[u] >= 0 ? tid + u * EG_NT : 0)];
+      }
 #pragma unroll
-        for (int t = 0; t < 3; ++t) w = fwd ? w - f[t] * tv[t] : w + f[t] * tv[t];
+      for (int u = U0; u < U1; ++u) {
+        const int j = qj[u], a = qa[u];
+        if (j < 0) continue;
+        double w = fwd ? za[u - U0] : 0.0;
+        if (c > 0) {
+          // (at step 0 the result rows hold nothing yet)
+          Y[(long long)j * n + kp * bs + a] = ta[u - U0][1];
+          if (c == nb - 1) raw[o_zn + tid + u * EG_NT] = ta[u - U0][1];
+#pragma unroll
+          for (int t = 0; t < 3; ++t) {
+            const bool ok = (a + t - 1) >= 0 && (a + t - 1) < bs;
+            const double f = ok ? fa[u - U0][t] : 0.0;
+            w = fwd ? w - f * ta[u - U0][t] : w + f * ta[u - U0][t];
+          }
+        }
         raw[o_w + a * m + j] = w;
       }
-    }
+    };
+    phase_a(std::integral_constant<int, 0>(), std::integral_constant<int, EG_PFZ / 2 + 1>());
+    if (qj[EG_PFZ / 2 + 1] >= 0)
+      phase_a(std::integral_constant<int, EG_PFZ / 2 + 1>(), std::integral_constant<int, EG_PFZ>());
     eg_barrier();
-    // phase B: rows of C^{-1}: T = S_k^{-1} Wl (backward: Y_k - that).
-    // Thread (row pair r, column group cg) forms rows 2r, 2r+1 and columns
-    // 4cg .. 4cg+3 (clamped at the block edge; the extra ones are dropped).
-    if (gact) {
-      double acc[2][4];
+    // phase B: rows of C^{-1}: T = S_k^{-1} Wl (backward: Y_k - that), into
+    // LDS.  Per FP64 MFMA 16x16x4, lane l supplies S(16R + l%16, b) and
+    // Wl(b, 16C + l%16) for b = 4K + l/16 (zero outside the block) and
+    // receives T(16R + l/16 + 4r, 16C + l%16) in register r.  Operand reads
+    // run EG_PD K steps ahead; two accumulators take alternate K steps.
+    for (int tl = wave; tl < nrt * nct; tl += EG_NT / 64) {
+      const int R = tl / nct, C = tl - (tl / nct) * nct;
+      const int ia = 16 * R + li, jb = 16 * C + li;
+      // Rows ia >= bs and columns jb >= m of the operands read neighbouring
+      // LDS data: they reach only output rows and columns that are
+      // dropped.  Only the last K step, whose b can pass the block, is
+      // masked.
+      const double* pa = raw + o_s + lk * bs + ia;
+      const double* pw = raw + o_w + lk * m + jb;
+      const int sa = 4 * bs, sw = 4 * m;
+      constexpr int EG_PD = 4;
+      double av[EG_PD], wv[EG_PD];
+      const int kl = max(nk - 2, 0);            // last unmasked K step
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc[a][u] = 0.0;
-      const int i0 = min(2 * gr, bs - 1), i1 = min(2 * gr + 1, bs - 1);
-      const int jc0 = min(4 * gc, m - 4);          // m >= 4 (host check)
-#pragma unroll 4
-      for (int b = 0; b < bs; ++b) {
-        const double s0 = raw[o_s + b * bs + i0], s1 = raw[o_s + b * bs + i1];
-        const double* wr = raw + o_w + b * m + jc0;
-        const double w0 = wr[0], w1 = wr[1], w2 = wr[2], w3 = wr[3];
-        acc[0][0] += s0 * w0; acc[0][1] += s0 * w1; acc[0][2] += s0 * w2; acc[0][3] += s0 * w3;
-        acc[1][0] += s1 * w0; acc[1][1] += s1 * w1; acc[1][2] += s1 * w2; acc[1][3] += s1 * w3;
+      for (int K = 0; K < EG_PD; ++K) {
+        const int Kc = min(K, kl);
+        av[K] = pa[Kc * sa];
+        wv[K] = pw[Kc * sw];
       }
+      eg_d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const int i = 2 * gr + a;
-        if (i >= bs) continue;
+      for (int K = 0; K < EG_NK; ++K) {
+        const double ae = av[K % EG_PD], we = wv[K % EG_PD];
+        if (K + EG_PD < EG_NK) {
+          const int Kc = min(K + EG_PD, kl);
+          av[K % EG_PD] = pa[Kc * sa];
+          wv[K % EG_PD] = pw[Kc * sw];
+        }
+        if (K < nk - 1) {
+          if (K & 1)
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ae, we, acc1, 0, 0, 0);
+          else
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ae, we, acc0, 0, 0, 0);
+        }
+      }
+      {
+        // last K step: b past the block reads as zero
+        const bool ok = 4 * (nk - 1) + lk < bs;
+        const double ae = ok ? pa[(nk - 1) * sa] : 0.0, we = ok ? pw[(nk - 1) * sw] : 0.0;
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ae, we, acc0, 0, 0, 0);
+      }
+      if (jb < m) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int j = jc0 + u;
-          if (j < 4 * gc) continue;               // column of the previous group
-          const double val = fwd ? acc[a][u] : raw[o_zc + j * bs + i] - acc[a][u];
-          raw[o_t + i * m + j] = val;
-          Y[(long long)j * n + k * bs + i] = val;
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * R + lk + 4 * r;
+          if (i < bs) {
+            const double t = acc0[r] + acc1[r];
+            raw[o_t + i * m + jb] = fwd ? t : raw[o_zc + jb * bs + i] - t;
+          }
         }
       }
     }
-    if (pf) {
-#pragma unroll
-      for (int u = 0; u < EG_PFR; ++u) {
-        const int q = tid + u * EG_NT;
-        if (q < rec) raw[o_sn + q] = pr[u];
+    if (vr) {
+      // remainder row vri, column vrj: four accumulators over b
+      double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+      int b = 0;
+      for (; b + 3 < bs; b += 4) {
+        c0 += raw[o_s + b * bs + vri] * raw[o_w + b * m + vrj];
+        c1 += raw[o_s + (b + 1) * bs + vri] * raw[o_w + (b + 1) * m + vrj];
+        c2 += raw[o_s + (b + 2) * bs + vri] * raw[o_w + (b + 2) * m + vrj];
+        c3 += raw[o_s + (b + 3) * bs + vri] * raw[o_w + (b + 3) * m + vrj];
       }
+      for (; b < bs; ++b) c0 += raw[o_s + b * bs + vri] * raw[o_w + b * m + vrj];
+      const double t = (c0 + c1) + (c2 + c3);
+      raw[o_t + vri * m + vrj] = fwd ? t : raw[o_zc + vrj * bs + vri] - t;
+    }
+    if (pfz) {
 #pragma unroll
       for (int u = 0; u < EG_PFZ; ++u)
         if (qj[u] >= 0) raw[o_zn + tid + u * EG_NT] = pz[u];
     }
+    // this wave's record copies have landed in LDS
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     eg_barrier();
   }
+  // the last step's result row (row 0)
+#pragma unroll
+  for (int u = 0; u < EG_PFZ; ++u)
+    if (qj[u] >= 0) Y[(long long)qj[u] * n + qa[u]] = raw[o_t + qa[u] * m + qj[u]];
   __syncthreads();
 }
 

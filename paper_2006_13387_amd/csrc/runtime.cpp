@@ -267,7 +267,7 @@ msp_status build_geometry(msp_handle* h) {
     const long long bs = 2LL * s.nxb;
     // records S^-1 | F of the twisted factorisation: node rows 0..m from the
     // top, nyb-1..m from the bottom (the middle row m twice)
-    foff += (long long)(s.nyb + 1) * (bs * bs + 6 * bs);
+    foff += (long long)(s.nyb + 1) * l1_rec((int)bs);
     voff += (long long)s.nyb * bs;
     h->subs.push_back(s);
     return (int)h->subs.size() - 1;
@@ -344,7 +344,7 @@ msp_status build_geometry(msp_handle* h) {
       s.ey1 = ey1;
       s.foff = foff;
       s.voff = voff;
-      foff += (long long)s.nyb * (s.nxb * s.nxb + 3 * s.nxb);   // records: S^-1 | F
+      foff += (long long)s.nyb * heat_rec(s.nxb);   // records: S^-1 | F | G
       voff += (long long)s.nxb * s.nyb;
       if (s.nxb > MAXBS)
         return fail(h, MSP_E_INVALID, "coarse neighbourhood row exceeds 72 nodes (sub_nel too large)");
@@ -2066,7 +2066,7 @@ extern "C" msp_status msp_query(msp_handle* h, int64_t* q) {
     // one application of the twisted sweep reads every row's record twice
     // (the middle row's once per chain) and each chain's middle coupling
     // once more
-    const long long ent = 2LL * s.nyb * (4LL * s.nxb * s.nxb + 12LL * s.nxb) + 24LL * s.nxb;
+    const long long ent = 2LL * s.nyb * l1_rec(2 * s.nxb) + 24LL * s.nxb;
     const bool f64 = !h->fp32 || (i < h->use64_h.size() ? h->use64_h[i] != 0 : true);
     l1_bytes += ent * (f64 ? 8 : 4);
   }
