@@ -91,9 +91,16 @@ namespace {
 // Tunables of the heat eigen setup.
 constexpr double kShift = 0.05;      // sigma = kShift / H^2 in C = A + sigma M
 constexpr int kEigExtra = 8;         // subspace block m = kmax + kEigExtra
+// Heat eigen iteration: at most kEigMaxIt shift-invert steps, a
+// Rayleigh-Ritz step every kEigRR of them; a neighbourhood stops when the
+// Ritz values that decide its selection (those below the threshold, at
+// most kmax, and the next one) change by less than kEigTol (relative)
+// between two Rayleigh-Ritz steps.  The Ritz values' error is second order
+// in the subspace error, so 1e-8 leaves the selected eigenvalues far more
+// accurate than the 1e-6 the coarse space needs.
 constexpr int kEigMaxIt = 48;
 constexpr int kEigRR = 4;
-constexpr double kEigTol = 1e-10;
+constexpr double kEigTol = 1e-8;
 constexpr double kPivotDrop = 1e-12; // scaled K_0 pivots at or below: dropped
 constexpr int kChunk = 16;           // PCG iterations between host checks
 constexpr int kMaxRestarts = 3;
