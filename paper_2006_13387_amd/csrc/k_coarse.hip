@@ -535,30 +535,58 @@ __device__ __forceinline__ void gemv_body(const GemvArgs& a, int bid, GvLds& L) 
   const double* __restrict__ cpart = a.cpart;
   double* cl = L.cl;
   if (a.sc != nullptr && block_read_done(a.sc, &L.shi)) return;
-  for (int j = threadIdx.x; j < nc; j += GV_NT) {
-    double t = 0.0;
+  // c = sum of the band partials (fixed order) into LDS, GV_CC columns per
+  // thread at a time with all their loads issued together
+  constexpr int GV_CC = 8;
+  for (int j0 = 0; j0 < nc; j0 += GV_CC * GV_NT) {
+    double v[GV_CC][RS_CH];
 #pragma unroll
-    for (int b = 0; b < RS_CH; ++b) t += cpart[(long long)b * ldc + j];
-    cl[j] = t;
+    for (int u = 0; u < GV_CC; ++u) {
+      const int j = min(j0 + threadIdx.x + u * GV_NT, nc - 1);
+#pragma unroll
+      for (int b = 0; b < RS_CH; ++b) v[u][b] = cpart[(long long)b * ldc + j];
+    }
+#pragma unroll
+    for (int u = 0; u < GV_CC; ++u) {
+      const int j = j0 + threadIdx.x + u * GV_NT;
+      double t = 0.0;
+#pragma unroll
+      for (int b = 0; b < RS_CH; ++b) t += v[u][b];
+      if (j < nc) cl[j] = t;
+    }
   }
   __syncthreads();
+  // the wave's GV_RPW rows streamed together, four columns a lane at a time
+  static_assert(GV_RPW == 2, "the row loop pairs two rows");
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-  for (int rr = 0; rr < GV_RPW; ++rr) {
-    const int row = bid * GV_ROWS + wave * GV_RPW + rr;
-    if (row >= nc) break;
-    const double* kr = K0 + (long long)row * ldk;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int j = lane;
-    for (; j + 192 < nc; j += 256) {
-      s0 += kr[j] * cl[j];
-      s1 += kr[j + 64] * cl[j + 64];
-      s2 += kr[j + 128] * cl[j + 128];
-      s3 += kr[j + 192] * cl[j + 192];
-    }
-    for (; j < nc; j += 64) s0 += kr[j] * cl[j];
-    const double s = wave_sum((s0 + s1) + (s2 + s3));
-    if (lane == 0) a.c0[row] = s;
+  const int r0 = bid * GV_ROWS + wave * GV_RPW, r1 = r0 + 1;
+  if (r0 >= nc) return;
+  const bool has1 = r1 < nc;
+  const double* k0 = K0 + (long long)r0 * ldk;
+  const double* k1 = K0 + (long long)(has1 ? r1 : r0) * ldk;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+  int j = lane;
+  for (; j + 192 < nc; j += 256) {
+    const double c0 = cl[j], c1 = cl[j + 64], c2 = cl[j + 128], c3 = cl[j + 192];
+    s0 += k0[j] * c0;
+    s1 += k0[j + 64] * c1;
+    s2 += k0[j + 128] * c2;
+    s3 += k0[j + 192] * c3;
+    t0 += k1[j] * c0;
+    t1 += k1[j + 64] * c1;
+    t2 += k1[j + 128] * c2;
+    t3 += k1[j + 192] * c3;
+  }
+  for (; j < nc; j += 64) {
+    s0 += k0[j] * cl[j];
+    t0 += k1[j] * cl[j];
+  }
+  const double sa = wave_sum((s0 + s1) + (s2 + s3));
+  const double sb = wave_sum((t0 + t1) + (t2 + t3));
+  if (lane == 0) {
+    a.c0[r0] = sa;
+    if (has1) a.c0[r1] = sb;
   }
 }
 
