@@ -104,6 +104,44 @@ def matvec_probe(torch, launches=20):
             "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "launches": int(c)}
 
 
+PROBE3_NEL = (384, 192, 192)
+FP64_PEAK_TFLOPS = 78.6
+
+
+def matvec3d_probe(torch, launches=10):
+    """Event-timed 3D (H8) stiffness product on PROBE3_NEL (43M DOFs), against
+    the FP64 ALU roof (the dense element product, 2 * 24 * 24 flops per
+    element) and the HBM roof (x read, y written, E, one clamp byte per
+    node)."""
+    import numpy as np
+    import inputs
+    import paper_2006_13387_amd as msp
+    desc = inputs.problem_desc(3, PROBE3_NEL, sub_nel=6, overlap=1)
+    fixed = inputs.clamp_face_mask(desc, axis=0, side=0)
+    rng = np.random.default_rng(8)
+    nel = int(np.prod(PROBE3_NEL))
+    s = msp.Solver(desc, fixed)
+    s.set_densities(torch.tensor(rng.random(nel), device="cuda"))
+    x = torch.randn(s.n, device="cuda", dtype=torch.float64)
+    for _ in range(2):
+        s.apply_K(x)
+    s.kernel_timing(enable=2)
+    for _ in range(launches):
+        s.apply_K(x)
+    c, t = s.kernel_timing(enable=0)["cg_matvec"]
+    s.close()
+    ms = t / max(c, 1)
+    nn = int(np.prod([v + 1 for v in PROBE3_NEL]))
+    flops = 2 * 24 * 24 * nel
+    b = 8 * 3 * nn * 2 + 8 * nel + nn
+    return {"mesh": f"{PROBE3_NEL[0]}x{PROBE3_NEL[1]}x{PROBE3_NEL[2]} H8 ({3 * nn} DOFs)",
+            "avg_launch_ms": round(ms, 5), "launches": int(c),
+            "flops_per_launch": flops, "achieved_TFLOPs": round(flops / (ms * 1e-3) / 1e12, 2),
+            "frac_fp64_peak": round(flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+            "bytes_per_launch": b, "achieved_GBs": round(b / (ms * 1e-3) / 1e9, 1),
+            "frac_hbm_peak": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 COUNTERS = os.path.join(ROOT, "profiles", "level1_apply_hbm_counters.json")
 LEVEL1_SOURCES = ("paper_2006_13387_amd/csrc/k_local.hip",
                   "paper_2006_13387_amd/csrc/dev.h",
@@ -595,6 +633,8 @@ def main():
     if not args.no_matvec_probe:
         log("[bench] matvec probe")
         out["matvec_probe"] = matvec_probe(torch)
+        log("[bench] 3D matvec probe")
+        out["matvec3d_probe"] = matvec3d_probe(torch)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         gi = [(e, i["iters"], i["n_coarse"]) for e, i in zip(contrasts, inf_mixed)]

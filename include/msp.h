@@ -45,7 +45,10 @@ typedef enum {
  * Section 2: coarse blocks D_i and overlapping subdomains D'_i; Section 4.1:
  * heat eigenproblem and its automatic threshold; Section 4.2: rotations).
  *
- *  dim        2 (bilinear Q1, plane stress) or 3 (trilinear H8)
+ *  dim        2 (bilinear Q1, plane stress) or 3 (trilinear H8, isotropic;
+ *             in 3D only the SIMP moduli and the stiffness product are
+ *             built, and the subdomain, eigen and precision fields are
+ *             ignored)
  *  nel        elements per axis (nel[2] ignored in 2D)
  *  h          element edge length
  *  E0, Emin   SIMP moduli: E_e = Emin + rho_e^penal (E0 - Emin), 0<Emin<=E0
@@ -102,7 +105,11 @@ typedef struct msp_handle msp_handle;
  * Create a solver for one mesh.  fixed_mask_host holds n = dim*(#nodes)
  * bytes, 1 = that displacement DOF is clamped to zero (Gamma_D).  The mask
  * is copied.  In 2D the block row of a subdomain (2 * nodes per row) and
- * of a neighbourhood (nodes per row) must not exceed 72.
+ * of a neighbourhood (nodes per row) must not exceed 72.  A 3D handle
+ * supports msp_set_densities, msp_apply_K, msp_vec_dot, msp_query and
+ * msp_kernel_timing; the calls that need the preconditioner (setup, solve,
+ * the level-1, coarse and preconditioner applies, the coarse queries, batch
+ * and serving) return MSP_E_INVALID for it.
  * Errors: MSP_E_INVALID (see the field ranges above), MSP_E_NOMEM.
  */
 msp_status msp_create(const msp_problem_desc* desc,
@@ -146,8 +153,10 @@ msp_status msp_solve(msp_handle* h, const double* f_dev, double* u_dev,
 
 /* ---- single steps of the hot path, for parity checks and profiling ---- */
 
-/* y = K_FF x (Section 1.1 discretisation): y = 0 at clamped DOFs, entries
- * of x at clamped DOFs are treated as 0.  Needs densities. */
+/* y = K_FF x (Section 1.1 discretisation, Q1 plane stress in 2D, H8 in
+ * 3D): y = 0 at clamped DOFs, entries of x at clamped DOFs are treated as
+ * 0.  x and y are device vectors of n = dim * #nodes doubles (interleaved
+ * DOFs) that must not alias.  Needs densities. */
 msp_status msp_apply_K(msp_handle* h, const double* x_dev, double* y_dev,
                        hipStream_t stream);
 

@@ -93,6 +93,7 @@ struct Geom {
   int sx, sy;          // coarse block edge S (elements)
   int ncx, ncy;        // coarse nodes per axis
   double h;
+  int nz, nnz;         // 3D: elements and nodes along z (2D: 1, 1)
 };
 
 // Arguments of one problem's PCG-iteration kernels.  A single solve passes

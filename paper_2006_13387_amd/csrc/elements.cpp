@@ -1,5 +1,6 @@
 // Element matrices of the bilinear (Q1) square element, evaluated on the
-// host by 2 x 2 Gauss quadrature (exact for these polynomial integrands).
+// host by 2 x 2 Gauss quadrature (exact for these polynomial integrands),
+// and the stiffness of the trilinear (H8) brick.
 //
 // Paper Section 1.1: C = E(x) C0 with C0 the plane-stress tensor of unit
 // modulus; the stiffness of element e is E_e times the unit-modulus matrix.
@@ -62,6 +63,58 @@ void q1_element_matrices(double nu, double h, double* Ke, double* Ae,
           Me[a * 4 + b] += w * N[a] * N[b];
         }
     }
+}
+
+// Ke[24*24]: unit-modulus stiffness of the trilinear (H8) brick element of
+// edge h by 2 x 2 x 2 Gauss quadrature (exact here), isotropic with the
+// Lame constants of E = 1: lambda = nu / ((1 + nu)(1 - 2 nu)),
+// mu = 1 / (2 (1 + nu)).  Vertex a = ax + 2 ay + 4 az, DOF 3a + c; strains
+// in the order xx, yy, zz, xy, yz, zx with engineering shears.
+void h8_element_stiffness(double nu, double h, double* Ke) {
+  const double g = 0.5 / std::sqrt(3.0);
+  const double pts[2] = {0.5 - g, 0.5 + g};
+  const double lam = nu / ((1.0 + nu) * (1.0 - 2.0 * nu)), mu = 0.5 / (1.0 + nu);
+  double D[6][6] = {};
+  for (int p = 0; p < 3; ++p) {
+    for (int q = 0; q < 3; ++q) D[p][q] = lam;
+    D[p][p] = lam + 2.0 * mu;
+    D[p + 3][p + 3] = mu;
+  }
+  for (int i = 0; i < 576; ++i) Ke[i] = 0.0;
+  for (int qz = 0; qz < 2; ++qz)
+    for (int qy = 0; qy < 2; ++qy)
+      for (int qx = 0; qx < 2; ++qx) {
+        const double xi[3] = {pts[qx], pts[qy], pts[qz]};
+        double B[6][24] = {};
+        for (int a = 0; a < 8; ++a) {
+          const int bit[3] = {a & 1, (a >> 1) & 1, a >> 2};
+          double f[3], dg[3];
+          for (int d = 0; d < 3; ++d) {
+            f[d] = bit[d] ? xi[d] : 1.0 - xi[d];
+            dg[d] = bit[d] ? 1.0 : -1.0;
+          }
+          const double dx = dg[0] * f[1] * f[2] / h;
+          const double dy = f[0] * dg[1] * f[2] / h;
+          const double dz = f[0] * f[1] * dg[2] / h;
+          B[0][3 * a] = dx;
+          B[1][3 * a + 1] = dy;
+          B[2][3 * a + 2] = dz;
+          B[3][3 * a] = dy;
+          B[3][3 * a + 1] = dx;
+          B[4][3 * a + 1] = dz;
+          B[4][3 * a + 2] = dy;
+          B[5][3 * a] = dz;
+          B[5][3 * a + 2] = dx;
+        }
+        const double w = 0.125 * h * h * h;     // weight * |J|
+        for (int i = 0; i < 24; ++i)
+          for (int j = 0; j < 24; ++j) {
+            double s = 0.0;
+            for (int p = 0; p < 6; ++p)
+              for (int q = 0; q < 6; ++q) s += B[p][i] * D[p][q] * B[q][j];
+            Ke[i * 24 + j] += w * s;
+          }
+      }
 }
 
 }  // namespace msp

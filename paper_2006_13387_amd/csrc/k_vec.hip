@@ -328,6 +328,93 @@ k_mask(long long n, const uint8_t* __restrict__ mask, double* __restrict__ x) {
 
 // ---------------------------------------------------------------- launchers
 
+// 3D (H8) stiffness product on the free DOFs: y = K(E) x with x's fixed
+// entries read as 0 and y = 0 at fixed DOFs (Section 1.1 in three
+// dimensions).  One thread per node, x the fastest axis.  For each of the
+// node's 27 neighbours the element matrix blocks of the elements that hold
+// both nodes act on the neighbour's three values; the sums are kept per
+// element and scaled by its modulus at the end.  Ke is the unit-modulus
+// element matrix (24 x 24, vertex a = ax + 2 ay + 4 az, DOF 3a + c), staged
+// in LDS and read at compile-time offsets (the same address for the whole
+// wave).  nmask: per node, bit c set when DOF c is fixed.
+__global__ void __launch_bounds__(256)
+k_matvec3d(Geom g, const double* __restrict__ Ke, const double* __restrict__ E,
+           const uint8_t* __restrict__ nmask, const double* __restrict__ x,
+           double* __restrict__ y) {
+  __shared__ double K[576];
+  for (int q = threadIdx.x; q < 576; q += 256) K[q] = Ke[q];
+  __syncthreads();
+  const long long nn = (long long)g.nnx * g.nny * g.nnz;
+  const long long node = min((long long)blockIdx.x * 256 + threadIdx.x, nn - 1);
+  const bool own = (long long)blockIdx.x * 256 + threadIdx.x < nn;
+  const int i = (int)(node % g.nnx);
+  const long long rr = node / g.nnx;
+  const int j = (int)(rr % g.nny), k = (int)(rr / g.nny);
+  // element e around the node: (i - 1 + ex, j - 1 + ey, k - 1 + ez)
+  double Ee[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int ei = i - 1 + (e & 1), ej = j - 1 + ((e >> 1) & 1), ek = k - 1 + (e >> 2);
+    const bool in = ei >= 0 && ei < g.nx && ej >= 0 && ej < g.ny && ek >= 0 && ek < g.nz;
+    Ee[e] = in ? E[((long long)ek * g.ny + ej) * g.nx + ei] : 0.0;
+  }
+  double acc[8][3];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) acc[e][0] = acc[e][1] = acc[e][2] = 0.0;
+  // neighbours (dx, dy, dz): dy, dz in uniform loops, dx unrolled
+#pragma unroll 1
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll 1
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int bj = j + dy, bk = k + dz;
+      const bool inyz = bj >= 0 && bj < g.nny && bk >= 0 && bk < g.nnz;
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int bi = i + dx;
+        const bool in = inyz && bi >= 0 && bi < g.nnx;
+        const long long nb = in ? ((long long)bk * g.nny + bj) * g.nnx + bi : node;
+        const unsigned mb = in ? nmask[nb] : 7u;
+        const double v0 = x[3 * nb], v1 = x[3 * nb + 1], v2 = x[3 * nb + 2];
+        const double x0 = (mb & 1u) ? 0.0 : v0;
+        const double x1 = (mb & 2u) ? 0.0 : v1;
+        const double x2 = (mb & 4u) ? 0.0 : v2;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
+          // the element holds the neighbour iff each offset lies in {e - 1, e}
+          if (dx < ex - 1 || dx > ex) continue;
+          if (dy < ey - 1 || dy > ey || dz < ez - 1 || dz > ez) continue;
+          const int a = (1 - ex) + 2 * (1 - ey) + 4 * (1 - ez);
+          const int b = (dx + 1 - ex) + 2 * (dy + 1 - ey) + 4 * (dz + 1 - ez);
+          const double* kr = K + 3 * a * 24 + 3 * b;
+          acc[e][0] += kr[0] * x0 + kr[1] * x1 + kr[2] * x2;
+          acc[e][1] += kr[24] * x0 + kr[25] * x1 + kr[26] * x2;
+          acc[e][2] += kr[48] * x0 + kr[49] * x1 + kr[50] * x2;
+        }
+      }
+    }
+  double y0 = 0.0, y1 = 0.0, y2 = 0.0;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    y0 += Ee[e] * acc[e][0];
+    y1 += Ee[e] * acc[e][1];
+    y2 += Ee[e] * acc[e][2];
+  }
+  if (!own) return;
+  const unsigned m = nmask[node];
+  y[3 * node] = (m & 1u) ? 0.0 : y0;
+  y[3 * node + 1] = (m & 2u) ? 0.0 : y1;
+  y[3 * node + 2] = (m & 4u) ? 0.0 : y2;
+}
+
+void launch_apply_K3(const Geom& g, const double* Ke, const double* E,
+                     const uint8_t* nmask, const double* x, double* y,
+                     hipStream_t s) {
+  const long long nn = (long long)g.nnx * g.nny * g.nnz;
+  hipLaunchKernelGGL(k_matvec3d, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s,
+                     g, Ke, E, nmask, x, y);
+}
+
 void launch_mask(long long n, const uint8_t* mask, double* x, hipStream_t s) {
   hipLaunchKernelGGL(k_mask, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                      n, mask, x);

@@ -19,6 +19,9 @@ namespace msp {
 void launch_simp(const double*, double*, int, double, double, double, int*,
                  hipStream_t);
 int matvec_blocks(const Geom&, int ty);
+void launch_apply_K3(const Geom&, const double*, const double*, const uint8_t*,
+                     const double*, double*, hipStream_t);
+void h8_element_stiffness(double nu, double h, double* Ke);
 void launch_apply_K(const Geom&, int ty, const double*, const double*,
                     const uint8_t*, const double*, double*, hipStream_t);
 MatvecArgs cg_matvec_args(const Geom&, int ty, const double*, const double*,
@@ -132,6 +135,8 @@ enum { KT_LEVEL1 = 0, KT_MATVEC = 1, KT_EIGEN = 2, KT_COMBINE = 3,
 
 struct msp_handle {
   msp_problem_desc desc;
+  int dim = 2;                     // 3: stiffness product only
+  uint8_t* d_nmask = nullptr;      // 3D: per node, bit c = DOF c fixed
   bool timing = false;
   int timing_mask = 0;
   KernelTimer kt[KT_COUNT];
@@ -475,7 +480,7 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
                   h->d_K0, h->d_sdiag, h->d_P, h->d_Lp, h->d_Rp, h->d_dropped,
                   h->d_c, h->d_c0, h->d_x, h->d_r, h->d_p0, h->d_p1, h->d_q,
                   h->d_z, h->d_tmp, h->d_sc, h->d_ahist, h->d_bhist,
-                  h->d_part, h->d_cnt, h->d_err, h->d_eig_state};
+                  h->d_part, h->d_cnt, h->d_err, h->d_eig_state, h->d_nmask};
   for (void* p : bufs) dfree(p);
   for (int k = 0; k < KT_COUNT; ++k)
     for (hipEvent_t e : h->kt[k].ev) (void)hipEventDestroy(e);
@@ -486,14 +491,85 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
   return MSP_OK;
 }
 
+// A 3D (H8) handle: the SIMP moduli and the stiffness product only; the
+// preconditioner and the solve are built for 2D meshes.
+static msp_status create_3d(const msp_problem_desc* d, const uint8_t* fixed,
+                            msp_handle** out) {
+  if (d->nel[0] <= 0 || d->nel[1] <= 0 || d->nel[2] <= 0)
+    return fail(nullptr, MSP_E_INVALID, "mesh sizes must be positive");
+  if (!(d->Emin > 0.0) || !(d->E0 >= d->Emin) || !std::isfinite(d->E0))
+    return fail(nullptr, MSP_E_INVALID, "need 0 < Emin <= E0");
+  if (!(d->nu > -1.0 && d->nu < 0.5))
+    return fail(nullptr, MSP_E_INVALID, "nu must lie in (-1, 0.5)");
+  if (!(d->penal >= 1.0)) return fail(nullptr, MSP_E_INVALID, "penal must be >= 1");
+  if (!(d->h > 0.0)) return fail(nullptr, MSP_E_INVALID, "h must be positive");
+  const long long nn = (long long)(d->nel[0] + 1) * (d->nel[1] + 1) * (d->nel[2] + 1);
+  if (nn > (1LL << 31) / 3)
+    return fail(nullptr, MSP_E_INVALID, "3D mesh too large");
+  msp_handle* h = new msp_handle();
+  h->desc = *d;
+  h->dim = 3;
+  Geom& g = h->g;
+  g.nx = d->nel[0];
+  g.ny = d->nel[1];
+  g.nz = d->nel[2];
+  g.nnx = g.nx + 1;
+  g.nny = g.ny + 1;
+  g.nnz = g.nz + 1;
+  g.sx = g.sy = 1;
+  g.ncx = g.ncy = 0;
+  g.h = d->h;
+  h->n_nodes = nn;
+  h->n_dofs = 3 * nn;
+  h->n_elems = (long long)g.nx * g.ny * g.nz;
+  h->mv_tuned = true;
+  h->mask_h.assign(fixed, fixed + h->n_dofs);
+  std::vector<uint8_t> nmask(nn);
+  for (long long p = 0; p < nn; ++p)
+    nmask[p] = (uint8_t)((fixed[3 * p] ? 1 : 0) | (fixed[3 * p + 1] ? 2 : 0) | (fixed[3 * p + 2] ? 4 : 0));
+  std::vector<double> Ke(576);
+  h8_element_stiffness(d->nu, d->h, Ke.data());
+  bool ok = true;
+  auto A = [&](hipError_t e) { if (e != hipSuccess) ok = false; };
+  A(dalloc(&h->d_elem, 576));
+  A(dalloc(&h->d_nmask, nn));
+  A(dalloc(&h->d_E, h->n_elems));
+  A(dalloc(&h->d_err, 4));
+  A(hipHostMalloc((void**)&h->h_int, 64 * sizeof(int)));
+  if (!ok) {
+    msp_destroy(h);
+    return fail(nullptr, MSP_E_NOMEM, "device allocation failed");
+  }
+  hipError_t e = hipSuccess;
+  auto C = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
+  C(hipMemcpy(h->d_elem, Ke.data(), 576 * sizeof(double), hipMemcpyHostToDevice));
+  C(hipMemcpy(h->d_nmask, nmask.data(), nn, hipMemcpyHostToDevice));
+  C(hipMemset(h->d_err, 0, 4 * sizeof(int)));
+  if (e != hipSuccess) {
+    std::string msg = std::string("device copy failed: ") + hipGetErrorString(e);
+    msp_destroy(h);
+    return fail(nullptr, MSP_E_DEVICE, msg);
+  }
+  *out = h;
+  return MSP_OK;
+}
+
+// Calls that need the preconditioner refuse 3D handles.
+static msp_status need_2d(msp_handle* h) {
+  if (h && h->dim != 2)
+    return fail(h, MSP_E_INVALID, "dim = 3: only the stiffness product is built for 3D meshes");
+  return MSP_OK;
+}
+
 extern "C" msp_status msp_create(const msp_problem_desc* d,
                                  const uint8_t* fixed_mask_host,
                                  msp_handle** out) {
   if (!d || !out || !fixed_mask_host)
     return fail(nullptr, MSP_E_INVALID, "null argument");
   *out = nullptr;
+  if (d->dim == 3) return create_3d(d, fixed_mask_host, out);
   if (d->dim != 2)
-    return fail(nullptr, MSP_E_INVALID, "only dim = 2 (Q1 plane stress) is built in this library");
+    return fail(nullptr, MSP_E_INVALID, "dim must be 2 or 3");
   if (d->nel[0] <= 0 || d->nel[1] <= 0 || d->sub_nel[0] <= 0 || d->sub_nel[1] <= 0)
     return fail(nullptr, MSP_E_INVALID, "mesh and block sizes must be positive");
   if (d->nel[0] % d->sub_nel[0] || d->nel[1] % d->sub_nel[1])
@@ -526,6 +602,8 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
   g.ncx = g.nx / g.sx + 1;
   g.ncy = g.ny / g.sy + 1;
   g.h = d->h;
+  g.nz = 1;
+  g.nnz = 1;
   h->n_nodes = (long long)g.nnx * g.nny;
   h->n_dofs = 2 * h->n_nodes;
   h->n_elems = (long long)g.nx * g.ny;
@@ -768,6 +846,7 @@ static msp_status ensure_coarse_buffers(msp_handle* h, size_t ncols,
 
 extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
   if (!h) return fail(h, MSP_E_INVALID, "null handle");
+  if (need_2d(h) != MSP_OK) return MSP_E_INVALID;
   if (!h->have_E) return fail(h, MSP_E_STATE, "msp_set_densities must come first");
   {
     const msp_status st = ensure_setup_buffers(h);
@@ -1030,7 +1109,10 @@ extern "C" msp_status msp_apply_K(msp_handle* h, const double* x, double* y,
   if (!h->have_E) return fail(h, MSP_E_STATE, "msp_set_densities must come first");
   if (x == y) return fail(h, MSP_E_INVALID, "x and y must not alias");
   const int tm = timer_begin(h, KT_MATVEC, s);
-  launch_apply_K(h->g, h->mv_ty, h->d_elem, h->d_E, h->d_mask, x, y, s);
+  if (h->dim == 3)
+    launch_apply_K3(h->g, h->d_elem, h->d_E, h->d_nmask, x, y, s);
+  else
+    launch_apply_K(h->g, h->mv_ty, h->d_elem, h->d_E, h->d_mask, x, y, s);
   timer_end(h, KT_MATVEC, tm, s);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(s));
@@ -1041,6 +1123,7 @@ extern "C" msp_status msp_apply_K(msp_handle* h, const double* x, double* y,
 static msp_status apply_parts(msp_handle* h, const double* r, double* z,
                               bool l1, bool coarse, hipStream_t s) {
   if (!r || !z) return fail(h, MSP_E_INVALID, "null argument");
+  if (need_2d(h) != MSP_OK) return MSP_E_INVALID;
   msp_status st = check_ready(h, s);
   if (st != MSP_OK) return st;
   enqueue_prec(h, 0, r, nullptr, z, l1, coarse, false, s);
@@ -1282,6 +1365,7 @@ extern "C" msp_status msp_solve(msp_handle* h, const double* f, double* u,
                                 int32_t maxit, hipStream_t s,
                                 msp_solve_info* info) {
   if (!h || !f || !u) return fail(h, MSP_E_INVALID, "null argument");
+  if (need_2d(h) != MSP_OK) return MSP_E_INVALID;
   if (nrhs < 1 || maxit < 1 || !(rtol > 0.0))
     return fail(h, MSP_E_INVALID, "need nrhs >= 1, maxit >= 1, rtol > 0");
   double t_setup = 0.0;
@@ -1485,6 +1569,7 @@ extern "C" msp_status msp_batch_solve(msp_batch* b, msp_handle* const* hs_in,
   std::vector<msp_handle*> hs(hs_in, hs_in + n);
   for (int e = 0; e < n; ++e) {
     if (!hs[e] || !f[e] || !u[e]) return bfail(b, MSP_E_INVALID, "null handle or vector in the batch");
+    if (hs[e]->dim != 2) return bfail(b, MSP_E_INVALID, "dim = 3: only the stiffness product is built for 3D meshes");
     for (int k = 0; k < e; ++k)
       if (hs[k] == hs[e]) return bfail(b, MSP_E_INVALID, "a handle appears twice in the batch");
     if (!hs[e]->have_E) return bfail(b, MSP_E_STATE, "msp_set_densities must come first");
@@ -1711,6 +1796,8 @@ extern "C" msp_status msp_server_add_run(msp_server* sv, const msp_problem_desc*
                                          int32_t* run_id) {
   if (!sv || !d || !fixed_mask_host || !run_id)
     return sfail(sv, MSP_E_INVALID, "null argument");
+  if (d->dim != 2)
+    return sfail(sv, MSP_E_INVALID, "runs must be 2D: the solve is built for 2D meshes");
   // validate by building the geometry once (no device memory is kept)
   msp_handle* probe = nullptr;
   msp_status st = msp_create(d, fixed_mask_host, &probe);
@@ -2005,6 +2092,7 @@ extern "C" msp_status msp_coarse_info(msp_handle* h, int32_t* n_modes,
                                       double* eigvals, int32_t* n_cnodes,
                                       int32_t* n_coarse, int32_t* cap_hits) {
   if (!h) return fail(h, MSP_E_INVALID, "null handle");
+  if (need_2d(h) != MSP_OK) return MSP_E_INVALID;
   if (!h->setup_ok) return fail(h, MSP_E_STATE, "no setup");
   const int kmax = h->desc.eig_kmax;
   for (size_t l = 0; l < h->cn_h.size(); ++l) {
@@ -2022,6 +2110,7 @@ extern "C" msp_status msp_coarse_info(msp_handle* h, int32_t* n_modes,
 extern "C" msp_status msp_coarse_basis(msp_handle* h, double* phi,
                                        hipStream_t s) {
   if (!h || !phi) return fail(h, MSP_E_INVALID, "null argument");
+  if (need_2d(h) != MSP_OK) return MSP_E_INVALID;
   if (!h->setup_ok) return fail(h, MSP_E_STATE, "no setup");
   launch_export_basis(h->g, h->d_cn, h->d_col_node, h->nc, h->d_mask, h->d_psi,
                       phi, h->invH, s);

@@ -61,7 +61,7 @@ def test_create_rejects_invalid_desc_without_touching_gpu():
                       ctypes.byref(h))
     assert st == -1
     assert b"multiple" in L.msp_last_error(None)
-    bad3 = inputs.problem_desc(3, (4, 4, 4), sub_nel=2, overlap=1)
+    bad3 = dict(inputs.problem_desc(3, (4, 4, 4), sub_nel=2, overlap=1), nel=(4, 4, 0))
     st = L.msp_create(ctypes.byref(msp.make_desc(bad3)),
                       ctypes.cast(mask, ctypes.c_void_p), ctypes.byref(h))
     assert st == -1
