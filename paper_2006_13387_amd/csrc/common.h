@@ -82,6 +82,7 @@ struct CombineArgs {
   int lsol_fp32;
   const CoarseNode* cnodes;
   const double* psi;
+  const float* psi32;        // FP32 copy of psi (FP32-local path) or null
   const double* c0;
   double invH;
   int use_l1, use_coarse;
@@ -154,6 +155,7 @@ struct RestrictArgs {
   const CoarseNode* cn;
   const uint8_t* mask;
   const double* psi;
+  const float* psi32;        // FP32 copy of psi (FP32-local path) or null
   const double* r;
   double* cpart;
   int ldc;

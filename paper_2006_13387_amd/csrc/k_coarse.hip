@@ -400,7 +400,14 @@ struct RsLds {
   int shi;
 };
 
+// the heat modes in the element type T: FP64, or the FP32 copy of the
+// FP32-local path (the same rounded values)
+template <typename T> __device__ __forceinline__ const T* psi_of(const double* p, const float* p32);
+template <> __device__ __forceinline__ const double* psi_of<double>(const double* p, const float*) { return p; }
+template <> __device__ __forceinline__ const float* psi_of<float>(const double*, const float* p32) { return p32; }
+
 // Workgroup bid = (coarse node, band): partial restriction of r.
+template <typename T>
 __device__ __forceinline__ void restrict_body(const RestrictArgs& a, int bid,
                                               RsLds& L) {
   const Geom& g = a.g;
@@ -423,7 +430,7 @@ __device__ __forceinline__ void restrict_body(const RestrictArgs& a, int bid,
   const int nw = cn.nxw * cn.nyw;
   const int r0w = (band * cn.nyw) / RS_CH, r1w = ((band + 1) * cn.nyw) / RS_CH;
   const int lo = r0w * cn.nxw, hi = r1w * cn.nxw;
-  const double* ps = a.psi + cn.psi_off;
+  const T* ps = psi_of<T>(a.psi, a.psi32) + cn.psi_off;
   // this thread's nodes of the band (past the band's end: its first node,
   // weighted 0)
   int locs[RS_NPT];
@@ -504,7 +511,10 @@ __device__ __forceinline__ void restrict_body(const RestrictArgs& a, int bid,
 
 __global__ void __launch_bounds__(RS_NT) k_restrict(RestrictArgs a) {
   __shared__ RsLds L;
-  restrict_body(a, blockIdx.x, L);
+  if (a.psi32 != nullptr)
+    restrict_body<float>(a, blockIdx.x, L);
+  else
+    restrict_body<double>(a, blockIdx.x, L);
 }
 
 __global__ void __launch_bounds__(RS_NT)
@@ -512,7 +522,10 @@ k_restrict_batch(const RestrictArgs* __restrict__ tab, const int* __restrict__ s
                  int nent) {
   __shared__ RsLds L;
   const int e = batch_entry(start, nent, blockIdx.x);
-  restrict_body(tab[e], blockIdx.x - start[e], L);
+  if (tab[e].psi32 != nullptr)
+    restrict_body<float>(tab[e], blockIdx.x - start[e], L);
+  else
+    restrict_body<double>(tab[e], blockIdx.x - start[e], L);
 }
 
 // c0 = K_0^+ c with c the sum of the restriction's band partials.  Rows of
@@ -636,7 +649,7 @@ __host__ __device__ inline int cb_bands(const Geom& g) {
   return (g.sy + 1 + cb_rows(g) - 1) / cb_rows(g);
 }
 
-template <int MODE>
+template <int MODE, typename T>
 __device__ __forceinline__ void combine_body(const CombineCall& a, int bid,
                                              int nblk, CbLds& L) {
   const Geom& g = a.g;
@@ -719,11 +732,12 @@ __device__ __forceinline__ void combine_body(const CombineCall& a, int bid,
   if (nh > 3) lv3 = ls[li3 >> 1];
   // coarse part: the first chunk of every corner's modes at this node
   double pv[4][CB_JC];
-  const double* pp[4];
+  const T* pp[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int nm = L.cnm[k];
-    pp[k] = ca.psi + L.cpsi[k] + (long long)(y - L.cy0[k]) * L.cnxw[k] + (x - L.cx0[k]);
+    pp[k] = psi_of<T>(ca.psi, ca.psi32) + L.cpsi[k] + (long long)(y - L.cy0[k]) * L.cnxw[k] +
+            (x - L.cx0[k]);
     if (nm > 0) {
 #pragma unroll
       for (int u = 0; u < CB_JC; ++u) pv[k][u] = pp[k][(long long)min(u, nm - 1) * L.cnw[k]];
@@ -797,7 +811,10 @@ __device__ __forceinline__ void combine_body(const CombineCall& a, int bid,
 template <int MODE>
 __global__ void __launch_bounds__(CB_NT) k_combine(CombineCall a) {
   __shared__ CbLds L;
-  combine_body<MODE>(a, blockIdx.x, gridDim.x, L);
+  if (a.ca.psi32 != nullptr)
+    combine_body<MODE, float>(a, blockIdx.x, gridDim.x, L);
+  else
+    combine_body<MODE, double>(a, blockIdx.x, gridDim.x, L);
 }
 
 __global__ void __launch_bounds__(CB_NT)
@@ -805,7 +822,10 @@ k_combine_cg_batch(const CombineCall* __restrict__ tab, const int* __restrict__ 
                    int nent) {
   __shared__ CbLds L;
   const int e = batch_entry(start, nent, blockIdx.x);
-  combine_body<1>(tab[e], blockIdx.x - start[e], start[e + 1] - start[e], L);
+  if (tab[e].ca.psi32 != nullptr)
+    combine_body<1, float>(tab[e], blockIdx.x - start[e], start[e + 1] - start[e], L);
+  else
+    combine_body<1, double>(tab[e], blockIdx.x - start[e], start[e + 1] - start[e], L);
 }
 
 // Dense export of the coarse basis (column-major n x Nc).

@@ -748,13 +748,16 @@ __device__ __forceinline__ void l1_barrier() {
 //    (the middle row by chain 0 only).
 // Step c of the sweep uses the record of position j(c) (forward j = c,
 // backward j = L-1-c).
-template <typename T, bool BWD>
+// gate: the CG stop test of the workgroup (may be null), run once the
+// first record copies are in flight so that the two latencies overlap;
+// when it says the solve is over the workgroup drains its copies and leaves.
+template <typename T, bool BWD, typename Gate>
 __device__ void level1_half(const Geom& g, const SysDesc& s, int half,
                             const uint8_t* __restrict__ mask,
                             const T* __restrict__ Sinv,
                             const double* __restrict__ r,
                             double* __restrict__ lsol, double* __restrict__ gm,
-                            unsigned char* lds) {
+                            unsigned char* lds, const Gate& gate) {
   const int tid = threadIdx.x;
   const int bs = 2 * s.nxb;
   const int nb = s.nyb;
@@ -772,6 +775,7 @@ __device__ void level1_half(const Geom& g, const SysDesc& s, int half,
   auto pos_of = [&](int c) { return BWD ? L - 1 - c : c; };
   if (!BWD && L == 1) {
     // no row before the middle on this side
+    if (gate()) return;
     for (int a = tid; a < bs; a += AP_NT) gm[half * MAXBS + a] = 0.0;
     return;
   }
@@ -799,6 +803,10 @@ __device__ void level1_half(const Geom& g, const SysDesc& s, int half,
       l1_dma<T>(base, ring.rec, pos_of(st), lds + (c % R) * ring.slot,
                 ring.nch, lw, lane);
     }
+  }
+  if (gate()) {
+    if (loader) wait_vmcnt(0);
+    return;
   }
   // local vector: forward, r at the chain's rows before the middle;
   // backward, the forward results t_j and the middle row's right-hand side
@@ -957,20 +965,18 @@ struct L1Shared {
 template <bool BWD>
 __device__ __forceinline__ void level1_item(const Level1Args& a, int vb,
                                             unsigned char* lds, L1Shared& L) {
-  if (a.sc != nullptr) {
-    if (!BWD && a.check) {
-      if (cg_check_done<AP_NT>(a.sc, a.part_upd, a.nb_upd, L.red, &L.shi, vb == 0)) return;
-    } else if (block_read_done(a.sc, &L.shi)) {
-      return;
-    }
-  }
+  auto gate = [&]() -> bool {
+    if (a.sc == nullptr) return false;
+    if (!BWD && a.check) return cg_check_done<AP_NT>(a.sc, a.part_upd, a.nb_upd, L.red, &L.shi, vb == 0);
+    return block_read_done(a.sc, &L.shi);
+  };
   const int bid = vb >> 1, half = vb & 1;
   const SysDesc s = a.sys[bid];
   double* gm = a.gmid + (long long)bid * 2 * MAXBS;
   if (a.S32 == nullptr || a.use64 == nullptr || a.use64[bid])
-    level1_half<double, BWD>(a.g, s, half, a.mask, a.S64, a.r, a.lsol, gm, lds);
+    level1_half<double, BWD>(a.g, s, half, a.mask, a.S64, a.r, a.lsol, gm, lds, gate);
   else
-    level1_half<float, BWD>(a.g, s, half, a.mask, a.S32, a.r, a.lsol, gm, lds);
+    level1_half<float, BWD>(a.g, s, half, a.mask, a.S32, a.r, a.lsol, gm, lds, gate);
 }
 
 // One pass (forward or backward) of the first-level solves: two workgroups
@@ -1736,8 +1742,9 @@ k_eig_count(const EigState* __restrict__ st, int nsys, int* __restrict__ count) 
 __global__ void __launch_bounds__(EG_NT)
 k_eig_select(const SysDesc* __restrict__ systems, const double* __restrict__ Xw,
              EigParams prm, const EigState* __restrict__ st,
-             double* __restrict__ psi_out, double* __restrict__ lam_out,
-             int* __restrict__ nsel_out, int* __restrict__ cap_out) {
+             double* __restrict__ psi_out, float* __restrict__ psi32_out,
+             double* __restrict__ lam_out, int* __restrict__ nsel_out,
+             int* __restrict__ cap_out) {
   __shared__ int nsel;
   const SysDesc s = systems[blockIdx.x];
   const int tid = threadIdx.x;
@@ -1755,8 +1762,20 @@ k_eig_select(const SysDesc* __restrict__ systems, const double* __restrict__ Xw,
       lam_out[(long long)blockIdx.x * prm.kmax + i] = (i < nsel) ? es.theta[i] : __builtin_nan("");
   }
   __syncthreads();
+  // with psi32_out the modes are rounded to FP32 and both copies hold the
+  // rounded values: the coarse space is the span of the rounded modes
   double* po = psi_out + s.voff * (long long)prm.kmax;
-  for (int idx = tid; idx < nsel * n; idx += EG_NT) po[idx] = X[idx];
+  float* po32 = psi32_out ? psi32_out + s.voff * (long long)prm.kmax : nullptr;
+  for (int idx = tid; idx < nsel * n; idx += EG_NT) {
+    const double x = X[idx];
+    if (po32 != nullptr) {
+      const float f = (float)x;
+      po32[idx] = f;
+      po[idx] = (double)f;
+    } else {
+      po[idx] = x;
+    }
+  }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1804,8 +1823,8 @@ void launch_heat_eigen(const Geom& g, const SysDesc* sys, int nsys,
                        const double* Me, const double* Sinv, double* X,
                        double* Y, double* Z, int m, int kmax, int maxit,
                        int rr_every, double lim, double tol, void* state,
-                       int* d_count, int* h_count, double* psi, double* lam,
-                       int* nsel, int* cap, int* err, hipStream_t s) {
+                       int* d_count, int* h_count, double* psi, float* psi32,
+                       double* lam, int* nsel, int* cap, int* err, hipStream_t s) {
   EigParams p{m, kmax, maxit, rr_every, lim, tol};
   EigState* st = static_cast<EigState*>(state);
   hipLaunchKernelGGL(k_eig_start, dim3(nsys), dim3(EG_NT), 0, s, g, sys, dflag, X, m, st);
@@ -1827,7 +1846,7 @@ void launch_heat_eigen(const Geom& g, const SysDesc* sys, int nsys,
     }
   }
   hipLaunchKernelGGL(k_eig_select, dim3(nsys), dim3(EG_NT), 0, s, sys, X, p, st,
-                     psi, lam, nsel, cap);
+                     psi, psi32, lam, nsel, cap);
 }
 
 }  // namespace msp

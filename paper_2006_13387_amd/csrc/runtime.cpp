@@ -55,8 +55,8 @@ bool level1_fits(int bs, int nb, bool fp32);
 void launch_heat_eigen(const Geom&, const SysDesc*, int, const double*,
                        const uint8_t*, const double*, const double*,
                        const double*, double*, double*, double*, int, int, int,
-                       int, double, double, void*, int*, int*, double*, double*,
-                       int*, int*, int*, hipStream_t);
+                       int, double, double, void*, int*, int*, double*, float*,
+                       double*, int*, int*, int*, hipStream_t);
 size_t eig_state_bytes();
 // k_coarse.hip
 
@@ -175,6 +175,7 @@ struct msp_handle {
   double* d_Som = nullptr;
   double *d_X = nullptr, *d_Y = nullptr, *d_Z = nullptr;
   double *d_psi = nullptr, *d_lam = nullptr;
+  float* d_psi32 = nullptr;        // FP32 copy of the heat modes (precision 1)
   void* d_eig_state = nullptr;     // per-neighbourhood subspace-iteration state
   int *d_nsel = nullptr, *d_cap = nullptr;
   CoarseNode* d_cn = nullptr;
@@ -475,7 +476,7 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
   void* bufs[] = {h->d_elem, h->d_mask, h->d_dflag, h->d_E, h->d_subs,
                   h->d_omegas, h->d_sub_grid, h->d_S64, h->d_S32, h->d_metric,
                   h->d_use64, h->d_lsol, h->d_gmid, h->d_Som,
-                  h->d_X, h->d_Y, h->d_Z, h->d_psi, h->d_lam, h->d_nsel,
+                  h->d_X, h->d_Y, h->d_Z, h->d_psi, h->d_psi32, h->d_lam, h->d_nsel,
                   h->d_cap, h->d_cn, h->d_col_node, h->d_pairs, h->d_W,
                   h->d_K0, h->d_sdiag, h->d_P, h->d_Lp, h->d_Rp, h->d_dropped,
                   h->d_c, h->d_c0, h->d_x, h->d_r, h->d_p0, h->d_p1, h->d_q,
@@ -785,6 +786,7 @@ static msp_status ensure_setup_buffers(msp_handle* h) {
   A(dalloc(&h->d_Y, h->om_vec * m));
   A(dalloc(&h->d_Z, h->om_vec * m));
   A(dalloc(&h->d_psi, h->om_vec * h->desc.eig_kmax));
+  if (h->fp32) A(dalloc(&h->d_psi32, h->om_vec * h->desc.eig_kmax));
   A(dalloc(&h->d_lam, h->omegas.size() * h->desc.eig_kmax));
   A(dalloc(&h->d_nsel, h->omegas.size()));
   A(dalloc(&h->d_cap, h->omegas.size()));
@@ -796,7 +798,8 @@ static msp_status ensure_setup_buffers(msp_handle* h) {
                      (void**)&h->d_use64, (void**)&h->d_lsol, (void**)&h->d_gmid,
                      (void**)&h->d_Som,
                      (void**)&h->d_X, (void**)&h->d_Y, (void**)&h->d_Z,
-                     (void**)&h->d_psi, (void**)&h->d_lam, (void**)&h->d_nsel,
+                     (void**)&h->d_psi, (void**)&h->d_psi32, (void**)&h->d_lam,
+                     (void**)&h->d_nsel,
                      (void**)&h->d_cap, (void**)&h->d_cn, &h->d_eig_state};
     for (void** b : bufs) {
       dfree(*b);
@@ -876,7 +879,7 @@ extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
                     Ae, Me, h->d_Som, h->d_X, h->d_Y, h->d_Z, m, kmax,
                     kEigMaxIt, kEigRR, h->desc.eig_tau / (h->H * h->H), kEigTol,
                     h->d_eig_state, (int*)h->d_cnt + 4, h->h_int + 8,
-                    h->d_psi, h->d_lam, h->d_nsel, h->d_cap, h->d_err, s);
+                    h->d_psi, h->d_psi32, h->d_lam, h->d_nsel, h->d_cap, h->d_err, s);
   timer_end(h, KT_EIGEN, tk, s);
   HIPCHK(h, hipGetLastError());
   const size_t nom = h->omegas.size();
@@ -987,6 +990,7 @@ static CombineArgs combine_args(msp_handle* h, bool l1, bool coarse) {
   ca.lsol_fp32 = 0;
   ca.cnodes = h->d_cn;
   ca.psi = h->d_psi;
+  ca.psi32 = h->d_psi32;
   ca.c0 = h->d_c0;
   ca.invH = h->invH;
   ca.use_l1 = l1 ? 1 : 0;
@@ -1021,6 +1025,7 @@ static RestrictArgs rs_args(msp_handle* h, const double* r, CGScalars* sc, int c
   a.cn = h->d_cn;
   a.mask = h->d_mask;
   a.psi = h->d_psi;
+  a.psi32 = h->d_psi32;
   a.r = r;
   a.cpart = h->d_c;
   a.ldc = h->ldk;
@@ -1086,8 +1091,10 @@ static void enqueue_prec(msp_handle* h, int mode, const double* r,
     timer_end(h, KT_LEVEL1, t, s);
   }
   if (coarse && h->nc > 0) {
+    // after the first level, which ran the convergence test and left its
+    // decision in the done word, the restriction only reads that word
     const int t = timer_begin(h, KT_RESTRICT, s);
-    launch_restrict(rs_args(h, r, sc, check), (int)h->cn_h.size(), s);
+    launch_restrict(rs_args(h, r, sc, l1 ? 0 : check), (int)h->cn_h.size(), s);
     timer_end(h, KT_RESTRICT, t, s);
     launch_coarse_gemv(gv_args(h, sc), s);
   }
@@ -1485,7 +1492,7 @@ static msp_status batch_tables(msp_batch* b, const std::vector<msp_handle*>& hs,
       up[c].push_back(up_args(h, c));
     }
     l1.push_back(l1_args(h, h->d_r, h->d_sc, 1));
-    rs.push_back(rs_args(h, h->d_r, h->d_sc, 1));
+    rs.push_back(rs_args(h, h->d_r, h->d_sc, 0));     // after the first level
     gv.push_back(gv_args(h, h->d_sc));
     cb.push_back(cb_args(h, true, true, h->d_r, h->d_q, h->d_z));
     const int nblk[6] = {matvec_blocks(h->g, h->mv_ty), update_blocks(h->n_dofs),
@@ -1696,6 +1703,7 @@ static long long handle_projected_bytes(const msp_handle* h) {
   long long b = 10 * nd * 8 + nd + nn + ne * 8;
   b += h->l1_entries * (8 + (h->fp32 ? 4 : 0)) + h->l1_vec * 8;
   b += h->om_entries * 8 + h->om_vec * (long long)h->eig_m * 8 * 3 + h->om_vec * kmax * 8;
+  if (h->fp32) b += h->om_vec * kmax * 4;      // FP32 heat modes
   b += 3 * ldk * ldk * 8 + 4 * ldk * 8;
   return b;
 }
