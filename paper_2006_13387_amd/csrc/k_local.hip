@@ -62,54 +62,61 @@ __device__ __forceinline__ bool is_fixed(const Geom& g,
 // after; during the inversion each of the 16 x 16 threads holds a 5 x 5
 // tile in registers (rows ti + 16u, columns tj + 16w), and only the pivot
 // row and column go through LDS, double-buffered by pivot parity so that
-// one barrier per pivot suffices.  pv: LDS scratch of 4 * MAXBS doubles.
+// one barrier per pivot suffices.  The pivot vectors span the whole tile
+// range (GJ_N entries, those at and beyond bs are zero), so that every
+// access to them is unconditional.  The owner of the next pivot forms its
+// reciprocal during the current update, off the barrier-to-barrier path.
+// pv: LDS scratch of GJ_PV doubles.
 constexpr int GJ_T = 5;                      // tile edge: 16 * 5 >= MAXBS
-static_assert(16 * GJ_T >= MAXBS, "Gauss-Jordan tiles do not cover a block");
+constexpr int GJ_N = 16 * GJ_T;              // padded pivot vector length
+constexpr int GJ_PV = 4 * GJ_N + 2;          // two row/column pairs, two reciprocals
+static_assert(GJ_N >= MAXBS, "Gauss-Jordan tiles do not cover a block");
 static_assert(GJ_T == 5, "gj_invert unrolls five tile rows of pivots");
 
 // One Gauss-Jordan pivot p = 16 PU + pt.  PU is a compile-time constant,
 // so the pivot's tile row and column are static register indices and only
-// the entries of that tile row / column need a select.
+// the entries of that tile row / column need a select.  On entry nv / inv
+// hold (on the pivot's owner, ti = tj = pt) the pivot and its reciprocal;
+// on exit the same for pivot p + 1.  A pivot that is not positive and
+// finite sets bad on its owner and is replaced by 1.
 template <int PU>
 __device__ __forceinline__ void gj_pivot_step(double (&a)[GJ_T][GJ_T], int p,
-                                              int pt, int ti, int tj, int bs,
-                                              double* pv, bool& bad) {
-  double* rowv = pv + (p & 1) * 2 * MAXBS;
-  double* colv = rowv + MAXBS;
-  // the owners publish the current pivot row and column
-  if (ti == pt) {
+                                              int pt, int ti, int tj,
+                                              double* pv, double& nv,
+                                              double& inv, bool& bad) {
+  double* rowv = pv + (p & 1) * 2 * GJ_N;
+  double* colv = rowv + GJ_N;
+  double* ipv = pv + 4 * GJ_N + (p & 1);
+  const bool prow = ti == pt, pcol = tj == pt;
+  // the owners publish the current pivot row and column, and its reciprocal
+  if (prow) {
 #pragma unroll
-    for (int w = 0; w < GJ_T; ++w) {
-      const int j = tj + 16 * w;
-      if (j < bs) rowv[j] = a[PU][w];
+    for (int w = 0; w < GJ_T; ++w) rowv[tj + 16 * w] = a[PU][w];
+    if (pcol) {
+      const bool ok = nv > 0.0 && finite(nv);
+      bad |= !ok;
+      *ipv = ok ? inv : 1.0;
     }
   }
-  if (tj == pt) {
+  if (pcol) {
 #pragma unroll
-    for (int u = 0; u < GJ_T; ++u) {
-      const int i = ti + 16 * u;
-      if (i < bs) colv[i] = a[u][PU];
-    }
+    for (int u = 0; u < GJ_T; ++u) colv[ti + 16 * u] = a[u][PU];
   }
   __syncthreads();
-  double piv = colv[p];
-  if (!(piv > 0.0) || !finite(piv)) {
-    bad = true;
-    piv = 1.0;
-  }
-  const double ip = 1.0 / piv;
+  const double ip = *ipv;
   double cv[GJ_T], rv[GJ_T];
 #pragma unroll
-  for (int u = 0; u < GJ_T; ++u) {
-    const int i = ti + 16 * u;
-    cv[u] = (i < bs) ? colv[i] : 0.0;
-  }
+  for (int u = 0; u < GJ_T; ++u) cv[u] = colv[ti + 16 * u];
 #pragma unroll
-  for (int w = 0; w < GJ_T; ++w) {
-    const int j = tj + 16 * w;
-    rv[w] = ((j < bs) ? rowv[j] : 0.0) * ip;
-  }
-  const bool prow = ti == pt, pcol = tj == pt;
+  for (int w = 0; w < GJ_T; ++w) rv[w] = rowv[tj + 16 * w] * ip;
+  // the entry of pivot p + 1 first: (PU, PU), or (PU + 1, PU + 1) after the
+  // last pivot of this tile row
+  constexpr int PN = PU + 1 < GJ_T ? PU + 1 : PU;
+  const bool wrap = pt == 15;
+  const double e_pp = a[PU][PU] - cv[PU] * rv[PU];
+  const double e_nn = a[PN][PN] - cv[PN] * rv[PN];
+  nv = wrap ? e_nn : e_pp;
+  inv = 1.0 / nv;
 #pragma unroll
   for (int u = 0; u < GJ_T; ++u)
 #pragma unroll
@@ -129,11 +136,12 @@ __device__ __forceinline__ void gj_pivot_step(double (&a)[GJ_T][GJ_T], int p,
 template <int PU>
 __device__ __forceinline__ void gj_pivot_tile(double (&a)[GJ_T][GJ_T], int ti,
                                               int tj, int bs, double* pv,
+                                              double& nv, double& inv,
                                               bool& bad) {
   for (int pt = 0; pt < 16; ++pt) {
     const int p = 16 * PU + pt;
     if (p >= bs) break;                       // uniform: bs is per system
-    gj_pivot_step<PU>(a, p, pt, ti, tj, bs, pv, bad);
+    gj_pivot_step<PU>(a, p, pt, ti, tj, pv, nv, inv, bad);
   }
 }
 
@@ -151,12 +159,13 @@ __device__ __forceinline__ void gj_invert(double* S, int bs, double* pv,
       a[u][w] = (i < bs && j < bs) ? S[i * LDSTR + j] : 0.0;
     }
   bool bad = false;
-  gj_pivot_tile<0>(a, ti, tj, bs, pv, bad);
-  gj_pivot_tile<1>(a, ti, tj, bs, pv, bad);
-  gj_pivot_tile<2>(a, ti, tj, bs, pv, bad);
-  gj_pivot_tile<3>(a, ti, tj, bs, pv, bad);
-  gj_pivot_tile<4>(a, ti, tj, bs, pv, bad);
-  if (bad && tid == 0) atomicOr(err, ERR_NOT_SPD);
+  double nv = a[0][0], inv = 1.0 / nv;
+  gj_pivot_tile<0>(a, ti, tj, bs, pv, nv, inv, bad);
+  gj_pivot_tile<1>(a, ti, tj, bs, pv, nv, inv, bad);
+  gj_pivot_tile<2>(a, ti, tj, bs, pv, nv, inv, bad);
+  gj_pivot_tile<3>(a, ti, tj, bs, pv, nv, inv, bad);
+  gj_pivot_tile<4>(a, ti, tj, bs, pv, nv, inv, bad);
+  if (bad) atomicOr(err, ERR_NOT_SPD);
 #pragma unroll
   for (int u = 0; u < GJ_T; ++u)
 #pragma unroll
@@ -195,7 +204,7 @@ __device__ __forceinline__ double coupling_l(const double (*er)[MAXBS + 2],
 struct FactorLds {
   double buf[3][MAXBS * LDSTR];
   double Bv[MAXBS * 6];
-  double pv[4 * MAXBS];
+  double pv[GJ_PV];
   double ddiag[MAXBS];
   double er[3][MAXBS + 2];
   uint8_t fr[3][MAXBS];
@@ -360,11 +369,14 @@ __device__ __forceinline__ double fac_wg_max(double v, FactorLds& L) {
 // Factorise one chain of node rows of system s: count rows starting at
 // node row row0 (relative to the box) in direction dir (+1 downwards in row
 // index, -1 upwards), each eliminating the previous row of the chain, with
-// chain position j's record at record index rec0 + j.  Returns this
-// thread's share of max_i (S^-1)_ii (D)_ii.
+// chain position j's record at record index rec0 + j.  Heat records also
+// hold G, the coupling with the next row of the chain; for the chain's last
+// row that is the row after it (the middle row of a twisted factorisation)
+// when tail is set, else zero.  Returns this thread's share of
+// max_i (S^-1)_ii (D)_ii.
 template <int NDOF>
 __device__ double factor_chain(const Geom& g, const SysDesc& s, int row0,
-                               int dir, int count, int rec0,
+                               int dir, int count, int rec0, bool tail,
                                const double* __restrict__ E,
                                const uint8_t* __restrict__ flag,
                                double* __restrict__ out64,
@@ -393,9 +405,9 @@ __device__ double factor_chain(const Geom& g, const SysDesc& s, int row0,
     fac_write_inverse<NDOF>(bs, S, out64 + off, out32 ? out32 + off : nullptr);
     fac_write_coupling<NDOF>(bs, j > 0, L, out64 + off, out32 ? out32 + off : nullptr);
     if (NDOF == 1) {
-      // G: couplings with the next row of the chain (zero for the last)
+      // G: couplings with the next row of the chain
       __syncthreads();
-      const bool nxt = j + 1 < count;
+      const bool nxt = j + 1 < count || tail;
       if (nxt) fac_coupling<NDOF>(s.nxb, 1 + dir, L);
       __syncthreads();
       for (int idx = tid; idx < 3 * bs; idx += FT_NT)
@@ -410,8 +422,10 @@ __device__ double factor_chain(const Geom& g, const SysDesc& s, int row0,
   return mloc;
 }
 
-// Factorise every system top-down: one workgroup per system, records of
-// rows 0..nyb-1 in order (the heat pencils of the coarse space).
+// Twisted factorisation, both outer parts: workgroup 2 i + h factorises
+// system i's chain h: h = 0 eliminates rows 0..m-1 top-down (records
+// 0..m-1), h = 1 rows nyb-1..m+1 bottom-up (records m+1..nyb-1), with
+// m = (nyb - 1) / 2 the middle row.
 //
 // out64 receives the FP64 records; out32 (may be null) a rounded FP32
 // copy.  metric (may be null) receives per system max_i (S_k^-1)_ii (D_k)_ii
@@ -419,28 +433,8 @@ __device__ double factor_chain(const Geom& g, const SysDesc& s, int row0,
 // contrast E0/Emin for DOFs of stiff islands that float in soft material,
 // whose rigid motions then have amplitudes ~E0/Emin.  FP32 rounding of such
 // values leaves spurious strains in the stiff phase, so the runtime keeps
-// FP64 blocks for systems whose metric exceeds a bound.
-template <int NDOF>
-__global__ void __launch_bounds__(FT_NT)
-k_factor(Geom g, const SysDesc* __restrict__ systems,
-         const double* __restrict__ E, const uint8_t* __restrict__ flag,
-         const double* __restrict__ Kel, double* __restrict__ out64,
-         float* __restrict__ out32, double* __restrict__ metric,
-         int* __restrict__ err) {
-  __shared__ FactorLds L;
-  const SysDesc s = systems[blockIdx.x];
-  for (int i = threadIdx.x; i < 16 * NDOF * NDOF; i += FT_NT) L.Kl[i] = Kel[i];
-  const double mloc = factor_chain<NDOF>(g, s, 0, 1, s.nyb, 0, E, flag, out64,
-                                         out32, err, L);
-  const double mm = fac_wg_max(mloc, L);
-  if (metric != nullptr && threadIdx.x == 0) metric[blockIdx.x] = mm;
-}
-
-// Twisted factorisation, both outer parts: workgroup 2 i + h factorises
-// system i's chain h: h = 0 eliminates rows 0..m-1 top-down (records
-// 0..m-1), h = 1 rows nyb-1..m+1 bottom-up (records m+1..nyb-1), with
-// m = (nyb - 1) / 2 the middle row.  Part metrics go to
-// metric[nsys + 2 i + h].
+// FP64 blocks for systems whose metric exceeds a bound.  Part metrics go to
+// metric[nsys + 2 i + h], the system's to metric[i] (k_factor_middle).
 template <int NDOF>
 __global__ void __launch_bounds__(FT_NT)
 k_factor_twisted(Geom g, const SysDesc* __restrict__ systems, int nsys,
@@ -454,17 +448,25 @@ k_factor_twisted(Geom g, const SysDesc* __restrict__ systems, int nsys,
   for (int i = threadIdx.x; i < 16 * NDOF * NDOF; i += FT_NT) L.Kl[i] = Kel[i];
   const int m = (s.nyb - 1) >> 1;
   const double mloc =
-      half == 0 ? factor_chain<NDOF>(g, s, 0, 1, m, 0, E, flag, out64, out32, err, L)
-                : factor_chain<NDOF>(g, s, s.nyb - 1, -1, s.nyb - 1 - m, m + 1, E,
-                                     flag, out64, out32, err, L);
+      half == 0 ? factor_chain<NDOF>(g, s, 0, 1, m, 0, true, E, flag, out64, out32, err, L)
+                : factor_chain<NDOF>(g, s, s.nyb - 1, -1, s.nyb - 1 - m, m + 1, true,
+                                     E, flag, out64, out32, err, L);
   const double mm = fac_wg_max(mloc, L);
-  if (threadIdx.x == 0) metric[nsys + blockIdx.x] = mm;
+  if (metric != nullptr && threadIdx.x == 0) metric[nsys + blockIdx.x] = mm;
 }
 
-// Load the inverse block of an elasticity record (FP64 column pairs) into
-// LDS (row stride LDSTR).
+// Load the inverse block of a record (layout as in fac_rec) into LDS (row
+// stride LDSTR).
+template <int NDOF>
 __device__ __forceinline__ void fac_load_inverse(int bs, const double* __restrict__ o,
                                                  double* P) {
+  if (NDOF == 1) {
+    for (int idx = threadIdx.x; idx < bs * bs; idx += FT_NT) {
+      const int j = idx / bs, i = idx - (idx / bs) * bs;
+      P[i * LDSTR + j] = o[idx];
+    }
+    return;
+  }
   for (int idx = threadIdx.x; idx < l1_cols(bs) * bs; idx += FT_NT) {
     const int jp = idx / (2 * bs), rem = idx - jp * (2 * bs);
     const int i = rem >> 1, j = 2 * jp + (rem & 1);
@@ -476,7 +478,8 @@ __device__ __forceinline__ void fac_load_inverse(int bs, const double* __restric
 // S_m = D_m - B S_{m-1}^{-1} B^T - C S'_{m+1}^{-1} C^T with B, C the
 // couplings of row m with rows m-1 and m+1, inverted.  Its inverse ends
 // both chains: record m (top chain, with F = B) and record nyb (bottom
-// chain, with F = C).  metric[i] = max over the system.
+// chain, with F = C).  metric[i] = max over the system (metric may be
+// null).  Heat records of the middle row get G = 0 (no row follows it).
 template <int NDOF>
 __global__ void __launch_bounds__(FT_NT)
 k_factor_middle(Geom g, const SysDesc* __restrict__ systems, int nsys,
@@ -500,7 +503,7 @@ k_factor_middle(Geom g, const SysDesc* __restrict__ systems, int nsys,
   // top part: row m-1 eliminated
   if (m > 0) {
     fac_coupling<NDOF>(s.nxb, 0, L);
-    fac_load_inverse(bs, out64 + s.foff + (long long)(m - 1) * rec, L.buf[1]);
+    fac_load_inverse<NDOF>(bs, out64 + s.foff + (long long)(m - 1) * rec, L.buf[1]);
     __syncthreads();
     fac_schur<NDOF>(bs, L.buf[1], L.buf[2], S, L);
     __syncthreads();
@@ -511,7 +514,7 @@ k_factor_middle(Geom g, const SysDesc* __restrict__ systems, int nsys,
   // record nyb-1)
   if (m + 1 < s.nyb) {
     fac_coupling<NDOF>(s.nxb, 2, L);
-    fac_load_inverse(bs, out64 + s.foff + (long long)(s.nyb - 1) * rec, L.buf[1]);
+    fac_load_inverse<NDOF>(bs, out64 + s.foff + (long long)(s.nyb - 1) * rec, L.buf[1]);
     __syncthreads();
     fac_schur<NDOF>(bs, L.buf[1], L.buf[2], S, L);
     __syncthreads();
@@ -521,10 +524,16 @@ k_factor_middle(Geom g, const SysDesc* __restrict__ systems, int nsys,
   gj_invert(S, bs, L.pv, err);
   fac_write_inverse<NDOF>(bs, S, out64 + otop, out32 ? out32 + otop : nullptr);
   fac_write_inverse<NDOF>(bs, S, out64 + obot, out32 ? out32 + obot : nullptr);
+  if (NDOF == 1) {
+    for (int idx = tid; idx < 3 * bs; idx += FT_NT) {
+      out64[otop + (long long)bs * bs + 3 * bs + idx] = 0.0;
+      out64[obot + (long long)bs * bs + 3 * bs + idx] = 0.0;
+    }
+  }
   double mloc = 0.0;
   for (int a = tid; a < bs; a += FT_NT) mloc = fmax(mloc, S[a * LDSTR + a] * L.ddiag[a]);
   const double mm = fac_wg_max(mloc, L);
-  if (tid == 0)
+  if (metric != nullptr && tid == 0)
     metric[blockIdx.x] = fmax(mm, fmax(metric[nsys + 2 * blockIdx.x],
                                        metric[nsys + 2 * blockIdx.x + 1]));
 }
@@ -1011,7 +1020,8 @@ k_level1_batch(const Level1Args* __restrict__ tab, const int* __restrict__ start
 // A = sum_e E_e int grad N grad N, M = sum_e E_e int N N over the elements
 // of omega_l (Neumann boundary, clamped nodes removed).  Shift-invert
 // block subspace iteration with C = A + sigma M (block-tridiagonal inverse
-// blocks from k_factor<1>), M-orthonormalisation by Cholesky QR applied
+// blocks from k_factor_twisted<1> and k_factor_middle<1>),
+// M-orthonormalisation by Cholesky QR applied
 // twice, and Rayleigh-Ritz with a parallel (round-robin) Jacobi solver for
 // the small projected matrix.  One workgroup per neighbourhood.
 
@@ -1050,7 +1060,8 @@ __device__ __forceinline__ double hash_unit(unsigned long long a) {
 }
 
 // out[j][node] = sum_e kappa_e (Kel in)[node] over omega's elements for the
-// first m columns; Dirichlet rows are 0.  One node per thread: its nine
+// first m columns and nodes n0 <= node < n1 (column stride n); Dirichlet
+// rows are 0.  One node per thread: its nine
 // neighbour weights are formed once from the (up to) four elements around
 // it, then the columns are done four at a time with all their loads issued
 // before the stores.
@@ -1059,8 +1070,9 @@ __device__ void omega_stencil(const Geom& g, const SysDesc& s,
                               const uint8_t* __restrict__ dflag,
                               const double* __restrict__ Kel4,
                               const double* __restrict__ in,
-                              double* __restrict__ out, int n, int m) {
-  for (int node = threadIdx.x; node < n; node += EG_NT) {
+                              double* __restrict__ out, int n, int m,
+                              int n0, int n1) {
+  for (int node = n0 + threadIdx.x; node < n1; node += EG_NT) {
     const int i = node % s.nxb, k = node / s.nxb;
     const int x = s.x0 + i, y = s.y0 + k;
     if (dflag[(long long)y * g.nnx + x]) {
@@ -1359,26 +1371,18 @@ __device__ void ritz_vectors(const double* Y, double* X,
   }
 }
 
-// Sweep of the shift-invert solve Y = C^{-1} Z by node rows: nb forward and
-// nb-1 backward steps, step c on row k(c) (as in the first-level apply).
-// Each row k has a record [S_k^{-1} (bs x bs, column-major) | F(k) (bs x
-// 3: couplings of row k with row k-1)] written by the factorisation.  While
-// step c runs, every thread holds its share of step c+1's record and vector
-// row (Z forward, the forward Y backward) in registers; they are stored to
-// the other LDS slot at the end of the step, so the loads overlap the block
-// GEMM, which runs on the matrix cores.
+// Shift-invert sweeps (k_eig_chain): block products S_k^{-1} Wl on the
+// FP64 matrix cores, K steps of 4 over a block row.
 typedef double eg_d4 __attribute__((ext_vector_type(4)));
 constexpr int EG_NK = (MAXBS + 3) / 4;     // K steps of 4 over a block row
 static_assert(EG_NK % 2 == 0, "the block GEMM pairs its K steps");
-constexpr int EG_RR = 0;                   // remainder rows of the block GEMM on vector lanes
 constexpr int EG_PFZ = (MAXBS * MAXM + EG_NT - 1) / EG_NT;               // row regs
 constexpr int EG_RAW = 18176;              // doubles of the kernel's carved LDS
 
 // LDS doubles the sweep needs for bs, m (2 record slots, 2 vector rows,
-// the right-hand side and the result rows)
+// the right-hand side, the result rows and one more coupling block)
 __host__ __device__ inline int eig_sweep_doubles(int bs, int m) {
-  const int rec = heat_rec(bs);
-  return 2 * ((rec + 1) & ~1) + 4 * bs * m;
+  return 2 * heat_rec(bs) + 4 * bs * m + 3 * bs;
 }
 
 // the block size m fits the kernel for rows of bs nodes
@@ -1428,33 +1432,71 @@ k_eig_start(Geom g, const SysDesc* __restrict__ systems,
   if (tid < MAXM) e.theta_old[tid] = 0.0;
 }
 
-// One shift-invert step of every neighbourhood still iterating:
-// Z = M X, then Y = C^{-1} Z by the row sweep.
+// One shift-invert step of every neighbourhood still iterating: Z = M X,
+// then Y = C^{-1} Z by node rows in the factorisation's twisted order.
+// Workgroup 2 l + h runs chain h of neighbourhood l (h = 0: rows 0..mid-1
+// top-down; h = 1: rows nb-1..mid+1 bottom-up; mid = (nb - 1) / 2).
+//   BWD = false: Z = M X on the chain's rows (h = 0 also on the middle
+//     row), then the chain's forward steps; every forward row goes to Y,
+//     the chain's last one also to its own Z row (Z rows mid-1 and mid+1
+//     are not read again before the next Z = M X).
+//   BWD = true: both workgroups solve the middle row from Z_mid and the
+//     two chain ends (h = 0 stores it), then run their chain backwards.
+// Record of row k: [S_k^{-1} (bs x bs, column-major) | F (bs x 3: coupling
+// with the previous row of its chain) | G (bs x 3: with the next row; for
+// a chain's last row, the middle row)]; the middle row has two records,
+// index mid (F: coupling with row mid-1) and index nb (F: with row mid+1).
+// Step c: phase A forms the right-hand side Wl from the previous step's
+// result rows T (LDS) and the record's coupling (forward Wl = Z_k - F T,
+// backward Wl = G T, middle Wl = Z_mid - F T_top - F' T_bottom) and
+// stores the previous T to Y; phase B computes T = S_k^{-1} Wl (forward,
+// middle) or T = Y_k - S_k^{-1} Wl (backward) on the matrix cores.  While
+// step c runs, the record of step c+1 is copied into the other LDS slot
+// (direct-to-LDS loads) and its vector row (Z forward, the forward Y
+// backward) is held in registers.
+template <bool BWD>
 __global__ void __launch_bounds__(EG_NT)
-k_eig_sweep(Geom g, const SysDesc* __restrict__ systems,
+k_eig_chain(Geom g, const SysDesc* __restrict__ systems,
             const double* __restrict__ E, const uint8_t* __restrict__ dflag,
             const double* __restrict__ Me, const double* __restrict__ Sinv,
             const double* __restrict__ Xw, double* __restrict__ Yw,
             double* __restrict__ Zw, int m, const EigState* __restrict__ st) {
   __shared__ __align__(16) double raw[EG_RAW];
-  if (st[blockIdx.x].done) return;
-  const SysDesc s = systems[blockIdx.x];
+  const int sys = blockIdx.x >> 1, h = blockIdx.x & 1;
+  if (st[sys].done) return;
+  const SysDesc s = systems[sys];
   const int tid = threadIdx.x;
   const int n = s.nxb * s.nyb;
   const int bs = s.nxb, nb = s.nyb;
+  const int mid = (nb - 1) >> 1;
+  const int len = h == 0 ? mid : nb - 1 - mid;          // rows of the chain
   const long long wo = s.voff * (long long)m;
   const double* X = Xw + wo;
   double* Y = Yw + wo;
   double* Z = Zw + wo;
+  if (!BWD) {
+    const int r0 = h == 0 ? 0 : mid + 1, r1 = h == 0 ? mid + 1 : nb;
+    omega_stencil(g, s, E, dflag, Me, X, Z, n, m, r0 * bs, r1 * bs);
+    __syncthreads();
+    if (len == 0) return;
+  }
+  // node row and record index of step c
+  auto row_of = [&](int c) {
+    return BWD ? (h == 0 ? mid - c : mid + c) : (h == 0 ? c : nb - 1 - c);
+  };
+  auto rec_of = [&](int c) {
+    return BWD ? (h == 0 ? mid - c : (c == 0 ? mid : nb - c))
+               : (h == 0 ? c : mid + 1 + c);
+  };
+  const int nsteps = BWD ? len + 1 : len;
   // sweep buffers in LDS, addressed by offsets into raw (so that every
   // access stays an LDS access): two record slots, two vector rows, the
-  // right-hand side Wl and the result rows T ([a][j], stride m)
+  // right-hand side Wl and the result rows T ([a][j], stride m), and the
+  // middle row's second coupling
   const int rec = heat_rec(bs);              // even
-  const int recp = rec;
   const int bm = bs * m;
-  const int o_z = 2 * recp, o_w = 2 * recp + 2 * bm, o_t = o_w + bm;
+  const int o_z = 2 * rec, o_w = o_z + 2 * bm, o_t = o_w + bm, o_fb = o_t + bm;
   const double* recs = Sinv + s.foff;
-  const int nsteps = 2 * nb - 1;
   // vector-row role: entries q = tid + u * EG_NT, q = j * bs + a
   int qa[EG_PFZ], qj[EG_PFZ];
 #pragma unroll
@@ -1463,47 +1505,51 @@ k_eig_sweep(Geom g, const SysDesc* __restrict__ systems,
     qj[u] = q < bm ? q / bs : -1;
     qa[u] = q < bm ? q - (q / bs) * bs : 0;
   }
-
-  omega_stencil(g, s, E, dflag, Me, X, Z, n, m);
-  __syncthreads();
-  // Y = C^{-1} Z
-  for (int q = tid; q < rec; q += EG_NT) raw[q] = recs[q];
+  {
+    const double* r0p = recs + (long long)rec_of(0) * rec;
+    for (int q = tid; q < rec; q += EG_NT) raw[q] = r0p[q];
+  }
 #pragma unroll
   for (int u = 0; u < EG_PFZ; ++u)
-    if (qj[u] >= 0) raw[o_z + tid + u * EG_NT] = Z[(long long)qj[u] * n + qa[u]];
+    if (qj[u] >= 0)
+      raw[o_z + tid + u * EG_NT] = Z[(long long)qj[u] * n + row_of(0) * bs + qa[u]];
+  if (BWD) {
+    // the chain ends (forward rows mid-1 and mid+1, zero where a chain is
+    // empty) as result rows, the bottom one in the other vector slot, and
+    // the coupling of the middle row with row mid+1
+    for (int q = tid; q < bm; q += EG_NT) {
+      const int j = q / bs, a = q - (q / bs) * bs;
+      raw[o_t + a * m + j] = mid > 0 ? Z[(long long)j * n + (mid - 1) * bs + a] : 0.0;
+      raw[o_z + bm + a * m + j] =
+          mid + 1 < nb ? Z[(long long)j * n + (mid + 1) * bs + a] : 0.0;
+    }
+    const double* fb = recs + (long long)nb * rec + bs * bs;
+    for (int q = tid; q < 3 * bs; q += EG_NT) raw[o_fb + q] = fb[q];
+  }
   __syncthreads();
-  // block GEMM roles: full 16-row tiles on the matrix cores (wave w takes
-  // tiles w, w + 8, ...); up to EG_RR remainder rows on vector lanes
-  // (threads tid < rows * m, one output each), else a zero-padded tile
-  const int nft = bs >> 4, rrow = bs - 16 * nft;
-  const bool rvalu = rrow <= EG_RR;
-  const int nrt = nft + (rvalu ? 0 : (rrow > 0 ? 1 : 0)), nct = (m + 15) >> 4;
+  // block GEMM roles: 16-row tiles on the matrix cores (wave w takes tiles
+  // w, w + 8, ...; the last tile row zero-padded)
+  const int nrt = (bs + 15) >> 4, nct = (m + 15) >> 4;
   const int nk = (bs + 3) >> 2;
   const int wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
-  const bool vr = rvalu && tid < rrow * m;
-  const int vri = 16 * nft + (vr ? tid / m : 0), vrj = vr ? tid - (tid / m) * m : 0;
   for (int c = 0; c < nsteps; ++c) {
-    const bool fwd = c < nb;
-    const int k = c < nb ? c : 2 * nb - 2 - c;
-    const int kp = c == 0 ? 0 : (c - 1 < nb ? c - 1 : 2 * nb - 1 - c);   // row of step c-1
+    const int kp = c > 0 ? row_of(c - 1) : 0;      // row of the previous step
     const int cur = c & 1;
-    const int o_s = cur ? recp : 0, o_sn = cur ? 0 : recp;     // this / other slot
+    const int o_s = cur ? rec : 0, o_sn = cur ? 0 : rec;       // this / other slot
     const int o_zc = o_z + (cur ? bm : 0), o_zn = o_z + (cur ? 0 : bm);
-    if (c == nb - 1) __syncthreads();    // forward rows of Y stored so far
-                                         // complete and visible
+    const bool mstep = BWD && c == 0;            // the middle row
+    const bool sub = BWD && c > 0;               // T = Y_k - S_k^{-1} Wl
+    const bool keep = c > 0 && !(BWD && c == 1 && h == 1);   // store the previous T
     // prefetch step c+1: the record straight into the other LDS slot
     // (direct-to-LDS loads of 16 bytes a lane, 1 KiB a wave, clipped at the
     // record's end; this step reads only its own record), and the vector
-    // row (Z forward, Y backward) into registers.  The first backward row,
-    // the forward result of the previous step, is still in LDS: phase A
-    // copies it.
+    // row into registers
     double pz[EG_PFZ];
     const bool pf = c + 1 < nsteps;
-    const bool pfz = pf && c != nb - 1;
     if (pf) {
-      const int k1 = (c + 1) < nb ? c + 1 : 2 * nb - 3 - c;
-      const unsigned char* rsrc = reinterpret_cast<const unsigned char*>(recs + (long long)k1 * rec);
+      const unsigned char* rsrc =
+          reinterpret_cast<const unsigned char*>(recs + (long long)rec_of(c + 1) * rec);
       unsigned char* rdst = reinterpret_cast<unsigned char*>(raw + o_sn);
       const int rbytes = 8 * rec;
       for (int q = wave; q * 1024 < rbytes; q += EG_NT / 64) {
@@ -1512,20 +1558,15 @@ k_eig_sweep(Geom g, const SysDesc* __restrict__ systems,
           __builtin_amdgcn_global_load_lds((const void*)(rsrc + off),
                                            (lds_void*)(rdst + q * 1024), 16, 0, 0);
       }
-      if (pfz) {
-        const double* vsrc = ((c + 1) < nb ? Z : Y) + (long long)k1 * bs;
+      const double* vsrc = (BWD ? Y : Z) + (long long)row_of(c + 1) * bs;
 #pragma unroll
-        for (int u = 0; u < EG_PFZ; ++u) pz[u] = vsrc[(long long)max(qj[u], 0) * n + qa[u]];
-      }
+      for (int u = 0; u < EG_PFZ; ++u) pz[u] = vsrc[(long long)max(qj[u], 0) * n + qa[u]];
     }
-    // phase A: store the previous step's result row to Y; right-hand side
-    // of this row from this record's couplings with the previous step's
-    // row (forward: F(k), with row k-1; backward: G(k), with row k+1).
-    // All of a thread's reads come first (the writes go to the same LDS
-    // array).
+    // phase A (all of a thread's reads come first: the writes go to the
+    // same LDS array)
     auto phase_a = [&](auto u0c, auto u1c) {
       constexpr int U0 = decltype(u0c)::value, U1 = decltype(u1c)::value;
-      const int o_f = o_s + bs * bs + (fwd ? 0 : 3 * bs);
+      const int o_f = o_s + bs * bs + (sub ? 3 * bs : 0);
       double fa[U1 - U0][3], ta[U1 - U0][3], za[U1 - U0];
 #pragma unroll
       for (int u = U0; u < U1; ++u) {
@@ -1542,16 +1583,15 @@ k_eig_sweep(Geom g, const SysDesc* __restrict__ systems,
       for (int u = U0; u < U1; ++u) {
         const int j = qj[u], a = qa[u];
         if (j < 0) continue;
-        double w = fwd ? za[u - U0] : 0.0;
-        if (c > 0) {
-          // (at step 0 the result rows hold nothing yet)
-          Y[(long long)j * n + kp * bs + a] = ta[u - U0][1];
-          if (c == nb - 1) raw[o_zn + tid + u * EG_NT] = ta[u - U0][1];
+        double w = sub ? 0.0 : za[u - U0];
+        if (keep) Y[(long long)j * n + kp * bs + a] = ta[u - U0][1];
+        if (c > 0 || mstep) {
+          // (at step 0 of a forward chain the result rows hold nothing)
 #pragma unroll
           for (int t = 0; t < 3; ++t) {
             const bool ok = (a + t - 1) >= 0 && (a + t - 1) < bs;
             const double f = ok ? fa[u - U0][t] : 0.0;
-            w = fwd ? w - f * ta[u - U0][t] : w + f * ta[u - U0][t];
+            w = sub ? w + f * ta[u - U0][t] : w - f * ta[u - U0][t];
           }
         }
         raw[o_w + a * m + j] = w;
@@ -1560,9 +1600,23 @@ k_eig_sweep(Geom g, const SysDesc* __restrict__ systems,
     phase_a(std::integral_constant<int, 0>(), std::integral_constant<int, EG_PFZ / 2 + 1>());
     if (qj[EG_PFZ / 2 + 1] >= 0)
       phase_a(std::integral_constant<int, EG_PFZ / 2 + 1>(), std::integral_constant<int, EG_PFZ>());
+    if (mstep) {
+      // the middle row's coupling with the bottom chain's end
+#pragma unroll
+      for (int u = 0; u < EG_PFZ; ++u) {
+        const int j = qj[u], a = qa[u];
+        if (j < 0) continue;
+        double w = raw[o_w + a * m + j];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const int b = a + t - 1;
+          if (b >= 0 && b < bs) w -= raw[o_fb + a * 3 + t] * raw[o_zn + b * m + j];
+        }
+        raw[o_w + a * m + j] = w;
+      }
+    }
     eg_barrier();
-    // phase B: rows of C^{-1}: T = S_k^{-1} Wl (backward: Y_k - that), into
-    // LDS.  Per FP64 MFMA 16x16x4, lane l supplies S(16R + l%16, b) and
+    // phase B: per FP64 MFMA 16x16x4, lane l supplies S(16R + l%16, b) and
     // Wl(b, 16C + l%16) for b = 4K + l/16 (zero outside the block) and
     // receives T(16R + l/16 + 4r, 16C + l%16) in register r.  Operand reads
     // run EG_PD K steps ahead; two accumulators take alternate K steps.
@@ -1613,26 +1667,12 @@ k_eig_sweep(Geom g, const SysDesc* __restrict__ systems,
           const int i = 16 * R + lk + 4 * r;
           if (i < bs) {
             const double t = acc0[r] + acc1[r];
-            raw[o_t + i * m + jb] = fwd ? t : raw[o_zc + jb * bs + i] - t;
+            raw[o_t + i * m + jb] = sub ? raw[o_zc + jb * bs + i] - t : t;
           }
         }
       }
     }
-    if (vr) {
-      // remainder row vri, column vrj: four accumulators over b
-      double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
-      int b = 0;
-      for (; b + 3 < bs; b += 4) {
-        c0 += raw[o_s + b * bs + vri] * raw[o_w + b * m + vrj];
-        c1 += raw[o_s + (b + 1) * bs + vri] * raw[o_w + (b + 1) * m + vrj];
-        c2 += raw[o_s + (b + 2) * bs + vri] * raw[o_w + (b + 2) * m + vrj];
-        c3 += raw[o_s + (b + 3) * bs + vri] * raw[o_w + (b + 3) * m + vrj];
-      }
-      for (; b < bs; ++b) c0 += raw[o_s + b * bs + vri] * raw[o_w + b * m + vrj];
-      const double t = (c0 + c1) + (c2 + c3);
-      raw[o_t + vri * m + vrj] = fwd ? t : raw[o_zc + vrj * bs + vri] - t;
-    }
-    if (pfz) {
+    if (pf) {
 #pragma unroll
       for (int u = 0; u < EG_PFZ; ++u)
         if (qj[u] >= 0) raw[o_zn + tid + u * EG_NT] = pz[u];
@@ -1641,11 +1681,17 @@ k_eig_sweep(Geom g, const SysDesc* __restrict__ systems,
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     eg_barrier();
   }
-  // the last step's result row (row 0)
+  // the last step's result rows (a forward chain's end also into its Z row)
+  const int kl = row_of(nsteps - 1);
+  const bool keep = !(BWD && nsteps == 1 && h == 1);
 #pragma unroll
   for (int u = 0; u < EG_PFZ; ++u)
-    if (qj[u] >= 0) Y[(long long)qj[u] * n + qa[u]] = raw[o_t + qa[u] * m + qj[u]];
-  __syncthreads();
+    if (qj[u] >= 0) {
+      const long long gi = (long long)qj[u] * n + kl * bs + qa[u];
+      const double v = raw[o_t + qa[u] * m + qj[u]];
+      if (keep) Y[gi] = v;
+      if (!BWD) Z[gi] = v;
+    }
 }
 
 // M-orthonormalise Y by Cholesky QR into X; with rr, orthonormalise again
@@ -1676,20 +1722,20 @@ k_eig_orth(Geom g, const SysDesc* __restrict__ systems,
   double* Y = Yw + wo;
   double* Z = Zw + wo;
   // pass 1: X = Y L^-T with L L^T = Y^T M Y
-  omega_stencil(g, s, E, dflag, Me, Y, Z, n, m);
+  omega_stencil(g, s, E, dflag, Me, Y, Z, n, m, 0, n);
   __syncthreads();
   gram(Y, Z, n, m, G, raw);
   chol_small(G, m, err);
   apply_linvT(Y, X, n, m, G);
   if (!rr) return;
   // pass 2 (in place)
-  omega_stencil(g, s, E, dflag, Me, X, Z, n, m);
+  omega_stencil(g, s, E, dflag, Me, X, Z, n, m, 0, n);
   __syncthreads();
   gram(X, Z, n, m, G, raw);
   chol_small(G, m, err);
   apply_linvT(X, X, n, m, G);
   // Rayleigh-Ritz with A
-  omega_stencil(g, s, E, dflag, Ae, X, Z, n, m);
+  omega_stencil(g, s, E, dflag, Ae, X, Z, n, m, 0, n);
   __syncthreads();
   gram(X, Z, n, m, G, raw);
   jacobi_small(G, V, m, rc, rs, rp, rq);
@@ -1794,8 +1840,12 @@ void launch_factor_heat(const Geom& g, const SysDesc* sys, int nsys,
                         const double* E, const uint8_t* dflag,
                         const double* Cel, double* out, int* err,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_factor<1>, dim3(nsys), dim3(FT_NT), 0, s, g, sys, E,
-                     dflag, Cel, out, (float*)nullptr, (double*)nullptr, err);
+  hipLaunchKernelGGL(k_factor_twisted<1>, dim3(2 * nsys), dim3(FT_NT), 0, s, g,
+                     sys, nsys, E, dflag, Cel, out, (float*)nullptr,
+                     (double*)nullptr, err);
+  hipLaunchKernelGGL(k_factor_middle<1>, dim3(nsys), dim3(FT_NT), 0, s, g, sys,
+                     nsys, E, dflag, Cel, out, (float*)nullptr, (double*)nullptr,
+                     err);
 }
 
 void launch_level1(const Level1Args& a, int nsys, hipStream_t s) {
@@ -1830,8 +1880,10 @@ void launch_heat_eigen(const Geom& g, const SysDesc* sys, int nsys,
   hipLaunchKernelGGL(k_eig_start, dim3(nsys), dim3(EG_NT), 0, s, g, sys, dflag, X, m, st);
   bool first_rr = true;
   for (int it = 0; it < maxit; ++it) {
-    hipLaunchKernelGGL(k_eig_sweep, dim3(nsys), dim3(EG_NT), 0, s, g, sys, E,
-                       dflag, Me, Sinv, X, Y, Z, m, st);
+    hipLaunchKernelGGL(k_eig_chain<false>, dim3(2 * nsys), dim3(EG_NT), 0, s, g,
+                       sys, E, dflag, Me, Sinv, X, Y, Z, m, st);
+    hipLaunchKernelGGL(k_eig_chain<true>, dim3(2 * nsys), dim3(EG_NT), 0, s, g,
+                       sys, E, dflag, Me, Sinv, X, Y, Z, m, st);
     const bool rr = ((it + 1) % rr_every == 0) || (it + 1 == maxit);
     hipLaunchKernelGGL(k_eig_orth, dim3(nsys), dim3(EG_NT), 0, s, g, sys, E,
                        dflag, Ae, Me, X, Y, Z, p, rr ? 1 : 0, first_rr ? 1 : 0,

@@ -357,7 +357,9 @@ msp_status build_geometry(msp_handle* h) {
       s.ey1 = ey1;
       s.foff = foff;
       s.voff = voff;
-      foff += (long long)s.nyb * heat_rec(s.nxb);   // records: S^-1 | F | G
+      // records S^-1 | F | G of the twisted factorisation: nyb rows, the
+      // middle row twice
+      foff += (long long)(s.nyb + 1) * heat_rec(s.nxb);
       voff += (long long)s.nxb * s.nyb;
       if (s.nxb > MAXBS)
         return fail(h, MSP_E_INVALID, "coarse neighbourhood row exceeds 72 nodes (sub_nel too large)");
