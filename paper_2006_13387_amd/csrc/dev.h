@@ -89,25 +89,41 @@ __device__ __forceinline__ int block_read_done(const CGScalars* sc, int* sh) {
 // workgroup sums the update kernel's partials of r.r in the same fixed
 // order; the leader (the problem's workgroup 0) records the outcome.
 // Returns true when the iteration is over (converged, iteration limit or
-// non-finite residual).
-template <int NT>
+// non-finite residual).  The done word, the counters and the partials are
+// read together (one memory latency); a workgroup that finds the solve
+// already over ignores the sum.  The counters are read before any leader
+// can advance them in this launch, so every workgroup decides alike.  Only
+// threads below NLD read partials (a workgroup whose other waves have
+// copies in flight keeps their memory counters to those copies).
+template <int NT, int NLD = NT>
 __device__ bool cg_check_done(CGScalars* sc, const double* part_upd, int nb_upd,
                               double* red, int* sh, bool leader) {
-  if (block_read_done(sc, sh)) return true;
-  const double rr = reduce_partials<NT>(part_upd, nb_upd, 1, red);
-  // the decision is taken by thread 0 and broadcast, so that it is uniform
-  // in the workgroup even if workgroup 0 updates the counters meanwhile
+  int d0 = DONE_RUNNING, it0 = 0, maxit = 0;
+  double tol2 = 0.0, ff = 0.0;
   if (threadIdx.x == 0) {
-    const int it1 = sc->iter + 1;
-    int d = DONE_RUNNING;
-    if (!finite(rr)) d = DONE_BREAKDOWN;
-    else if (rr <= sc->tol2 * sc->ff) d = DONE_CONVERGED;
-    else if (it1 >= sc->maxit) d = DONE_MAXIT;
-    if (d != DONE_RUNNING && leader) {
-      sc->rr = rr;
-      sc->iter = it1;
-      if (d == DONE_BREAKDOWN) sc->status = -5;
-      __hip_atomic_store(&sc->done, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    d0 = __hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    it0 = __hip_atomic_load(&sc->iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    maxit = sc->maxit;
+    tol2 = sc->tol2;
+    ff = sc->ff;
+  }
+  double s = 0.0;
+  if ((int)threadIdx.x < NLD)
+    for (int i = threadIdx.x; i < nb_upd; i += NLD) s += load_coherent(part_upd + i);
+  const double rr = block_sum<NT>(s, red);
+  if (threadIdx.x == 0) {
+    int d = d0;
+    if (d0 == DONE_RUNNING) {
+      const int it1 = it0 + 1;
+      if (!finite(rr)) d = DONE_BREAKDOWN;
+      else if (rr <= tol2 * ff) d = DONE_CONVERGED;
+      else if (it1 >= maxit) d = DONE_MAXIT;
+      if (d != DONE_RUNNING && leader) {
+        sc->rr = rr;
+        sc->iter = it1;
+        if (d == DONE_BREAKDOWN) sc->status = -5;
+        __hip_atomic_store(&sc->done, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
     *sh = d;
   }

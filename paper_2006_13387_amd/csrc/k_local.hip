@@ -566,6 +566,7 @@ constexpr int L1_GMAX = 4 * ((MAXBS / 4 + L1_NS - 1) / L1_NS);   // columns per 
 constexpr int L1_COMPUTE = 256;            // threads of the compute waves
 constexpr int L1_NLW = (AP_NT - L1_COMPUTE) / 64;   // loader waves
 constexpr int L1_CHUNK = 1024;             // bytes of one wave's DMA load
+constexpr int L1_VPT = 5;                  // local-vector entries a compute thread reads ahead
 constexpr int L1_LDS = 160 * 1024 - 256;   // LDS of the apply kernel
 static_assert(L1_NS * MAXBS <= L1_COMPUTE, "GEMV threads exceed the compute waves");
 
@@ -794,9 +795,8 @@ __device__ void level1_half(const Geom& g, const SysDesc& s, int half,
   const bool loader = tid >= L1_COMPUTE;
   const int lw = __builtin_amdgcn_readfirstlane((tid - L1_COMPUTE) >> 6);
   const int lane = tid & 63;
-  // loads this wave issues per record, and after the record it waits for
+  // loads this wave issues per record
   const int cw = lw < ring.nch ? (ring.nch - lw + L1_NLW - 1) / L1_NLW : 0;
-  const int younger = (R - 2) * cw;
   // GEMV role: column group q (cs columns, whole quads), row i
   const int cs = 4 * ((ncols / 4 + L1_NS - 1) / L1_NS);
   const int gq = tid / bs, gi = tid - (tid / bs) * bs;
@@ -806,35 +806,67 @@ __device__ void level1_half(const Geom& g, const SysDesc& s, int half,
   // phase-1 role: row entry tid, its node and component
   const int ia = tid >> 1, ca = tid & 1;
 
-  if (loader) {
-    for (int c = 0; c < R - 1; ++c) {
-      const int st = c < nsteps ? c : nsteps - 1;
-      l1_dma<T>(base, ring.rec, pos_of(st), lds + (c % R) * ring.slot,
-                ring.nch, lw, lane);
+  // Records are copied in step order, record n into slot n % R: the
+  // prologue issues the first R - 1, step c the record of step c + R - 1
+  // (none past the last step), so that after step c's issue the first
+  // min(c + R, nsteps) records are in flight or landed.
+  const int npro = min(R - 1, nsteps);
+  if (loader)
+    for (int n = 0; n < npro; ++n)
+      l1_dma<T>(base, ring.rec, pos_of(n), lds + n * ring.slot, ring.nch, lw, lane);
+  // local vector: forward, r at the chain's rows before the middle;
+  // backward, the forward results t_j and the middle row's right-hand side.
+  // The compute waves read the first L1_VPT entries each before the stop
+  // test, so that the two latencies overlap; the loader waves read nothing
+  // but records, so that their memory counters count only record copies.
+  const int nv = (L - 1) * bs;
+  auto v_load = [&](int idx) -> T {
+    const int j = idx / bs, a = idx - (idx / bs) * bs;
+    const int k = row_of(j);
+    if (!BWD) {
+      const long long d = 2 * ((long long)(s.y0 + k) * g.nnx + s.x0 + a / 2) + (a & 1);
+      const uint8_t mk = mask[d];
+      const T rv = (T)r[d];
+      return mk ? (T)0 : rv;
+    }
+    return (T)o[k * bs + a];
+  };
+  T vr[L1_VPT];
+  T wr = 0;
+  T fmid[6];                  // forward: F of the middle row, for g_h
+  if (!loader) {
+#pragma unroll
+    for (int u = 0; u < L1_VPT; ++u) {
+      const int idx = tid + u * L1_COMPUTE;
+      vr[u] = idx < nv ? v_load(idx) : (T)0;
+    }
+    if (BWD && tid < bs) {
+      const long long d = 2 * ((long long)(s.y0 + mid) * g.nnx + s.x0 + tid / 2) + (tid & 1);
+      const uint8_t mk = mask[d];
+      const T rv = (T)r[d], g0 = (T)gm[tid], g1 = (T)gm[MAXBS + tid];
+      wr = mk ? (T)0 : rv - (g0 + g1);
+    }
+    if (!BWD && tid < bs) {
+      const T* F = base + (long long)(L - 1) * ring.rec + fo + tid * 6;
+#pragma unroll
+      for (int t = 0; t < 6; ++t) fmid[t] = F[t];
     }
   }
   if (gate()) {
     if (loader) wait_vmcnt(0);
     return;
   }
-  // local vector: forward, r at the chain's rows before the middle;
-  // backward, the forward results t_j and the middle row's right-hand side
-  for (int idx = tid; idx < (L - 1) * bs; idx += AP_NT) {
-    const int j = idx / bs, a = idx - (idx / bs) * bs;
-    const int k = row_of(j);
-    if (!BWD) {
-      const long long d = 2 * ((long long)(s.y0 + k) * g.nnx + s.x0 + a / 2) + (a & 1);
-      v[idx] = mask[d] ? (T)0 : (T)r[d];
-    } else {
-      v[idx] = (T)o[k * bs + a];
+  if (!loader) {
+#pragma unroll
+    for (int u = 0; u < L1_VPT; ++u) {
+      const int idx = tid + u * L1_COMPUTE;
+      if (idx < nv) v[idx] = vr[u];
     }
-  }
-  if (BWD && tid < bs) {
-    const long long d = 2 * ((long long)(s.y0 + mid) * g.nnx + s.x0 + tid / 2) + (tid & 1);
-    w[tid] = mask[d] ? (T)0 : (T)r[d] - ((T)gm[tid] + (T)gm[MAXBS + tid]);
+    for (int idx = tid + L1_VPT * L1_COMPUTE; idx < nv; idx += L1_COMPUTE) v[idx] = v_load(idx);
+    if (BWD && tid < bs) w[tid] = wr;
   }
   if (tid >= bs && tid < ncols) w[tid] = (T)0;   // padding columns
-  if (loader) wait_vmcnt(younger);      // record of step 0 is in its slot
+  if (loader) wait_vmcnt((npro - 1) * cw);       // record of step 0 is in its slot
   l1_barrier();
 
   // Position jp, finished at the previous step (parity pp), at entry col:
@@ -913,25 +945,27 @@ __device__ void level1_half(const Geom& g, const SysDesc& s, int half,
     }
     l1_barrier();
     // phase 2: retire position jp into v (phase 1 may read t_jp there, so
-    // not before the barrier); partial block GEMV; loaders fetch the record
-    // of step c+R-1 into the slot freed by step c-1 and wait for the record
-    // of step c+1
+    // not before the barrier); partial block GEMV; loaders issue the next
+    // records (slots freed by steps up to c-1) and wait for the record of
+    // step c+1
     if (gemv) {
       if (c > 0 && tid < bs) v[jp * bs + tid] = fin_value(fin_load(jp, pp, tid), pfwd);
       const T* S = reinterpret_cast<const T*>(lds + cur * ring.slot) + j0 * bs;
       P[(c & 1) * (4 * MAXBS) + 4 * gi + gq] =
           lds_gemv_group<T, L1_GMAX>(S, bs, gi, w + j0, jn);
     } else if (loader) {
-      const int cn = c + R - 1;
-      const int st = cn < nsteps ? cn : nsteps - 1;
-      l1_dma<T>(base, ring.rec, pos_of(st), lds + prev * ring.slot, ring.nch,
-                lw, lane);
-      wait_vmcnt(younger);
+      if (c + R - 1 < nsteps)
+        l1_dma<T>(base, ring.rec, pos_of(c + R - 1), lds + prev * ring.slot,
+                  ring.nch, lw, lane);
+      // the record of step c+1 has landed once at most the copies of the
+      // records after it are in flight
+      if (c + 1 < nsteps) wait_vmcnt((min(c + R, nsteps) - (c + 2)) * cw);
     }
     l1_barrier();
   }
-  // retire the position of the last step; the loaders drain their last
-  // (unused) record loads so that no copy into LDS outlives this system
+  // retire the position of the last step (every record copy has been
+  // waited for; the loaders' wait is a guard that no copy into LDS outlives
+  // this system)
   {
     const int c = nsteps;
     const int jl = pos_of(c - 1);
@@ -940,15 +974,15 @@ __device__ void level1_half(const Geom& g, const SysDesc& s, int half,
   if (loader) wait_vmcnt(0);
   l1_barrier();
   if (!BWD) {
-    // g = F_{L-1} t_{L-2}, F_{L-1} from the middle row's record in HBM
+    // g = F_{L-1} t_{L-2}, F_{L-1} read from the middle row's record in
+    // the prologue
     if (tid < bs) {
-      const T* F = base + (long long)(L - 1) * ring.rec + fo + tid * 6;
       T acc = 0;
 #pragma unroll
       for (int t = 0; t < 6; ++t) {
         const int di = t / 2 - 1, cc = t & 1;
         const int a = 2 * (ia + di) + cc;
-        if (a >= 0 && a < bs) acc += F[t] * v[(L - 2) * bs + a];
+        if (a >= 0 && a < bs) acc += fmid[t] * v[(L - 2) * bs + a];
       }
       gm[half * MAXBS + tid] = (double)acc;
     }
@@ -976,7 +1010,8 @@ __device__ __forceinline__ void level1_item(const Level1Args& a, int vb,
                                             unsigned char* lds, L1Shared& L) {
   auto gate = [&]() -> bool {
     if (a.sc == nullptr) return false;
-    if (!BWD && a.check) return cg_check_done<AP_NT>(a.sc, a.part_upd, a.nb_upd, L.red, &L.shi, vb == 0);
+    if (!BWD && a.check)
+      return cg_check_done<AP_NT, L1_COMPUTE>(a.sc, a.part_upd, a.nb_upd, L.red, &L.shi, vb == 0);
     return block_read_done(a.sc, &L.shi);
   };
   const int bid = vb >> 1, half = vb & 1;
