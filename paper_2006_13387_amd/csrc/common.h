@@ -74,8 +74,7 @@ enum : int { ERR_NOT_SPD = 1, ERR_NONFINITE = 2, ERR_RANGE = 4,
 
 // Arguments of the kernel that forms z = M^{-1} r at every node.
 struct CombineArgs {
-  const SysDesc* sys;
-  const int* sub_grid;       // grid cell -> subdomain index or -1
+  const SysDesc* sys_grid;   // grid cell -> its subdomain (nxb = 0: none)
   int ngx, ngy;              // extent of that grid
   int sub_vertex;            // 1: grid = coarse nodes, 0: blocks
   const void* lsol;          // local solutions (double or float)
@@ -184,6 +183,7 @@ struct CombineCall {
   double* z;
   CGScalars* sc;
   double* part;
+  int flex;                  // flexible CG: also the partials of z.q
 };
 
 // Problem of workgroup b in a batched launch: the last e with start[e] <= b

@@ -40,6 +40,30 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
+// Two sums over the workgroup at once, each in block_sum's order; sh must
+// hold 2 (NT/64) doubles.  All threads get both results.
+template <int NT>
+__device__ __forceinline__ double2 block_sum2(double a, double b, double* sh) {
+  static_assert(NT % 64 == 0, "workgroup must be whole waves");
+  constexpr int W = NT / 64;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[w] = a;
+    sh[W + w] = b;
+  }
+  __syncthreads();
+  double ra = 0.0, rb = 0.0;
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    ra += sh[i];
+    rb += sh[W + i];
+  }
+  __syncthreads();
+  return make_double2(ra, rb);
+}
+
 __device__ __forceinline__ double load_coherent(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

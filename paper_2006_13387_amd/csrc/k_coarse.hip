@@ -536,6 +536,7 @@ constexpr int GV_NT = 256;
 constexpr int GV_RPW = 2;                               // rows per wave
 constexpr int GV_ROWS = (GV_NT / 64) * GV_RPW;          // rows per workgroup
 constexpr int GV_MAXC = 12288;
+constexpr int GV_U = 32;                                // row columns a lane loads at once
 
 struct GvLds {
   double cl[GV_MAXC];
@@ -547,18 +548,42 @@ __device__ __forceinline__ void gemv_body(const GemvArgs& a, int bid, GvLds& L) 
   const int ldk = a.ldk, nc = a.nc, ldc = a.ldc;
   const double* __restrict__ cpart = a.cpart;
   double* cl = L.cl;
-  if (a.sc != nullptr && block_read_done(a.sc, &L.shi)) return;
+  static_assert(GV_RPW == 2, "the row loop pairs two rows");
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r0 = bid * GV_ROWS + wave * GV_RPW, r1 = r0 + 1;
+  const bool has0 = r0 < nc, has1 = r1 < nc;
+  const double* k0 = K0 + (long long)(has0 ? r0 : 0) * ldk;
+  const double* k1 = K0 + (long long)(has1 ? r1 : (has0 ? r0 : 0)) * ldk;
+  // The wave's two rows (GV_U columns a lane at a time), the band partials
+  // of c and the done word all go out before the first use, so that for
+  // nc <= 64 GV_U the kernel waits for memory once.
+  double kv0[GV_U], kv1[GV_U];
+  auto load_rows = [&](int jb) {
+#pragma unroll
+    for (int u = 0; u < GV_U; ++u) {
+      const int j = jb + lane + 64 * u;
+      const bool ok = j < nc;
+      kv0[u] = ok ? k0[j] : 0.0;
+      kv1[u] = ok ? k1[j] : 0.0;
+    }
+  };
   // c = sum of the band partials (fixed order) into LDS, GV_CC columns per
   // thread at a time with all their loads issued together
   constexpr int GV_CC = 8;
-  for (int j0 = 0; j0 < nc; j0 += GV_CC * GV_NT) {
-    double v[GV_CC][RS_CH];
+  double v[GV_CC][RS_CH];
+  auto load_c = [&](int j0) {
 #pragma unroll
     for (int u = 0; u < GV_CC; ++u) {
-      const int j = min(j0 + threadIdx.x + u * GV_NT, nc - 1);
+      const int j = min(j0 + (int)threadIdx.x + u * GV_NT, nc - 1);
 #pragma unroll
       for (int b = 0; b < RS_CH; ++b) v[u][b] = cpart[(long long)b * ldc + j];
     }
+  };
+  load_rows(0);
+  load_c(0);
+  if (a.sc != nullptr && block_read_done(a.sc, &L.shi)) return;
+  for (int j0 = 0; j0 < nc; j0 += GV_CC * GV_NT) {
+    if (j0 > 0) load_c(j0);
 #pragma unroll
     for (int u = 0; u < GV_CC; ++u) {
       const int j = j0 + threadIdx.x + u * GV_NT;
@@ -569,34 +594,21 @@ __device__ __forceinline__ void gemv_body(const GemvArgs& a, int bid, GvLds& L) 
     }
   }
   __syncthreads();
-  // the wave's GV_RPW rows streamed together, four columns a lane at a time
-  static_assert(GV_RPW == 2, "the row loop pairs two rows");
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r0 = bid * GV_ROWS + wave * GV_RPW, r1 = r0 + 1;
-  if (r0 >= nc) return;
-  const bool has1 = r1 < nc;
-  const double* k0 = K0 + (long long)r0 * ldk;
-  const double* k1 = K0 + (long long)(has1 ? r1 : r0) * ldk;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
-  int j = lane;
-  for (; j + 192 < nc; j += 256) {
-    const double c0 = cl[j], c1 = cl[j + 64], c2 = cl[j + 128], c3 = cl[j + 192];
-    s0 += k0[j] * c0;
-    s1 += k0[j + 64] * c1;
-    s2 += k0[j + 128] * c2;
-    s3 += k0[j + 192] * c3;
-    t0 += k1[j] * c0;
-    t1 += k1[j + 64] * c1;
-    t2 += k1[j + 128] * c2;
-    t3 += k1[j + 192] * c3;
+  if (!has0) return;
+  // column j = jb + lane + 64 u into accumulator u % 4
+  double s[4] = {0.0, 0.0, 0.0, 0.0}, t[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int jb = 0; jb < nc; jb += 64 * GV_U) {
+    if (jb > 0) load_rows(jb);
+#pragma unroll
+    for (int u = 0; u < GV_U; ++u) {
+      const int j = jb + lane + 64 * u;
+      const double c = j < nc ? cl[j] : 0.0;
+      s[u & 3] += kv0[u] * c;
+      t[u & 3] += kv1[u] * c;
+    }
   }
-  for (; j < nc; j += 64) {
-    s0 += k0[j] * cl[j];
-    t0 += k1[j] * cl[j];
-  }
-  const double sa = wave_sum((s0 + s1) + (s2 + s3));
-  const double sb = wave_sum((t0 + t1) + (t2 + t3));
+  const double sa = wave_sum((s[0] + s[1]) + (s[2] + s[3]));
+  const double sb = wave_sum((t[0] + t[1]) + (t[2] + t[3]));
   if (lane == 0) {
     a.c0[r0] = sa;
     if (has1) a.c0[r1] = sb;
@@ -657,7 +669,6 @@ __device__ __forceinline__ void combine_body(const CombineCall& a, int bid,
   const uint8_t* __restrict__ mask = a.mask;
   CGScalars* sc = a.sc;
   const int tid = threadIdx.x;
-  if (MODE != 0 && block_read_done(sc, &L.shi)) return;
   const int ncellx = g.nx / g.sx, ncelly = g.ny / g.sy;
   const int nbands = cb_bands(g), rpb = cb_rows(g);
   const int cell = bid / nbands, band = bid - (bid / nbands) * nbands;
@@ -669,19 +680,22 @@ __device__ __forceinline__ void combine_body(const CombineCall& a, int bid,
   // idle threads stand on the cell's first node (valid addresses, no output)
   const int x = cx * g.sx + (act ? tx : 0), y = cy * g.sy + (act ? ty : 0);
   const long long node = (long long)y * g.nnx + x;
-  // stage the candidates (empty boxes / no modes where there are none)
+  // Every read that needs no staged value goes out at once: the done word,
+  // the candidates (empty boxes / no modes where there are none) and the
+  // node's mask, r and (flexible) q.
+  int dn = DONE_RUNNING;
+  if (MODE != 0 && tid == 0)
+    dn = __hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (tid < 9) {
     const int gy = cy - 1 + tid / 3, gx = cx - 1 + tid % 3;
-    int sid = -1;
-    if (ca.use_l1 && gx >= 0 && gx < ca.ngx && gy >= 0 && gy < ca.ngy)
-      sid = ca.sub_grid[gy * ca.ngx + gx];
     SysDesc sd{};
-    if (sid >= 0) sd = ca.sys[sid];
+    if (ca.use_l1 && gx >= 0 && gx < ca.ngx && gy >= 0 && gy < ca.ngy)
+      sd = ca.sys_grid[gy * ca.ngx + gx];
     L.sx0[tid] = sd.x0;
     L.sy0[tid] = sd.y0;
-    L.snx[tid] = sid >= 0 ? sd.nxb : 0;
-    L.sny[tid] = sid >= 0 ? sd.nyb : 0;
-    L.svoff[tid] = sid >= 0 ? sd.voff : 0;
+    L.snx[tid] = sd.nxb;
+    L.sny[tid] = sd.nyb;
+    L.svoff[tid] = sd.voff;
   } else if (tid >= 64 && tid < 68) {
     const int k = tid - 64;
     CoarseNode cn{};
@@ -696,14 +710,15 @@ __device__ __forceinline__ void combine_body(const CombineCall& a, int bid,
     L.ccol[k] = cn.col0;
     L.cpsi[k] = cn.psi_off;
   }
-  // loads that need no candidate
   uchar2 mk = reinterpret_cast<const uchar2*>(mask)[node];
   double2 rv = make_double2(0.0, 0.0), qv = make_double2(0.0, 0.0);
   if (MODE != 0) {
     rv = reinterpret_cast<const double2*>(a.r)[node];
-    if (MODE == 1 && sc->flexible) qv = reinterpret_cast<const double2*>(a.q)[node];
+    if (MODE == 1 && a.flex) qv = reinterpret_cast<const double2*>(a.q)[node];
   }
+  if (tid == 0) L.shi = dn;
   __syncthreads();
+  if (MODE != 0 && L.shi != DONE_RUNNING) return;
   for (int idx = tid; idx < 4 * CB_NCOL; idx += CB_NT) {
     const int k = idx / CB_NCOL, j = idx - (idx / CB_NCOL) * CB_NCOL;
     if (j < 2 * L.cnm[k] + L.crot[k]) L.c0[k][j] = ca.c0[L.ccol[k] + j];
@@ -731,7 +746,8 @@ __device__ __forceinline__ void combine_body(const CombineCall& a, int bid,
   if (nh > 2) lv2 = ls[li2 >> 1];
   if (nh > 3) lv3 = ls[li3 >> 1];
   // coarse part: the first chunk of every corner's modes at this node
-  double pv[4][CB_JC];
+  constexpr int JC = CB_JC;
+  T pv[4][JC];
   const T* pp[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -740,7 +756,7 @@ __device__ __forceinline__ void combine_body(const CombineCall& a, int bid,
             (x - L.cx0[k]);
     if (nm > 0) {
 #pragma unroll
-      for (int u = 0; u < CB_JC; ++u) pv[k][u] = pp[k][(long long)min(u, nm - 1) * L.cnw[k]];
+      for (int u = 0; u < JC; ++u) pv[k][u] = pp[k][(long long)min(u, nm - 1) * L.cnw[k]];
     }
   }
   __syncthreads();
@@ -762,17 +778,17 @@ __device__ __forceinline__ void combine_body(const CombineCall& a, int bid,
     const double* c = L.c0[k];
     double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-    for (int u = 0; u < CB_JC; ++u) {
+    for (int u = 0; u < JC; ++u) {
       const double w = u < nm ? pv[k][u] : 0.0;
       s0 += w * c[min(u, nm - 1)];
       s1 += w * c[nm + min(u, nm - 1)];
     }
-    for (int j0 = CB_JC; j0 < nm; j0 += CB_JC) {
+    for (int j0 = JC; j0 < nm; j0 += JC) {
 #pragma unroll
-      for (int u = 0; u < CB_JC; ++u)
+      for (int u = 0; u < JC; ++u)
         pv[k][u] = pp[k][(long long)min(j0 + u, nm - 1) * L.cnw[k]];
 #pragma unroll
-      for (int u = 0; u < CB_JC; ++u) {
+      for (int u = 0; u < JC; ++u) {
         const double w = j0 + u < nm ? pv[k][u] : 0.0;
         s0 += w * c[min(j0 + u, nm - 1)];
         s1 += w * c[nm + min(j0 + u, nm - 1)];
@@ -797,7 +813,7 @@ __device__ __forceinline__ void combine_body(const CombineCall& a, int bid,
   double d_rz = 0.0, d_zq = 0.0;
   if (act) {
     d_rz = rv.x * z0 + rv.y * z1;
-    if (MODE == 1 && sc->flexible) d_zq = qv.x * z0 + qv.y * z1;
+    if (MODE == 1 && a.flex) d_zq = qv.x * z0 + qv.y * z1;
   }
   const double s_rz = block_sum<CB_NT>(d_rz, L.red);
   const double s_zq = block_sum<CB_NT>(d_zq, L.red);

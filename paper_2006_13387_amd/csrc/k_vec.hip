@@ -39,7 +39,7 @@ struct MvLds {
   double2 xs[(MV_TYMAX + 2) * (MV_TX + 2)];
   double es[(MV_TYMAX + 1) * (MV_TX + 1)];
   double ks[64];
-  double red[MV_NT / 64 + 1];
+  double red[2 * (MV_NT / 64)];
   int shi;
   double beta;
 };
@@ -61,61 +61,100 @@ __device__ __forceinline__ void matvec_body(const MatvecArgs& a, int bx, int by,
                                             int gx, int gy, MvLds& L) {
   static_assert(TY % 4 == 0 && TY <= MV_TYMAX, "tile height");
   constexpr int RPT = TY / 4;                // rows per thread
+  constexpr int NXN = (TY + 2) * (MV_TX + 2);               // halo nodes
+  constexpr int NEN = (TY + 1) * (MV_TX + 1);               // moduli
+  constexpr int NXS = (NXN + MV_NT - 1) / MV_NT;            // per thread
+  constexpr int NES = (NEN + MV_NT - 1) / MV_NT;
   const Geom& g = a.g;
   const int tid = threadIdx.x;
+  const int bx0 = bx * MV_TX - 1;   // node x of xs column 0
+  const int by0 = by * TY - 1;
+  // Every read goes out before the first use (one memory latency): the
+  // tile's halo of the input (CG: z and p_old), the moduli, the element
+  // matrix and, CG, the done word, the scalars and the combine kernel's
+  // partials of r.z and z.q (the z.q half is used only when flexible).
+  int dn = DONE_RUNNING, it = 0, flex = 0, maxit = 0;
+  double alpha_o = 0.0, rz_o = 0.0;
+  double srz = 0.0, szq = 0.0;
+  if (MODE == MV_CG) {
+    if (tid == 0) {
+      dn = __hip_atomic_load(&a.sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      it = a.sc->iter;                       // not written by this kernel
+      flex = a.sc->flexible;
+      maxit = a.sc->maxit;
+      alpha_o = a.sc->alpha;
+      rz_o = a.sc->rz;
+    }
+    for (int k = tid; k < a.nb_comb; k += MV_NT) {
+      srz += load_coherent(a.part_comb + k);
+      szq += load_coherent(a.part_comb + a.nb_comb + k);
+    }
+  }
+  double2 xu[NXS], xp[NXS];
+  uchar2 xm[NXS];
+#pragma unroll
+  for (int k = 0; k < NXS; ++k) {
+    const int t = tid + k * MV_NT;
+    const int ii = t % (MV_TX + 2), jj = t / (MV_TX + 2);
+    const int x = bx0 + ii, y = by0 + jj;
+    xu[k] = xp[k] = make_double2(0.0, 0.0);
+    xm[k] = make_uchar2(1, 1);
+    if (t < NXN && x >= 0 && x < g.nnx && y >= 0 && y < g.nny) {
+      const long long node = (long long)y * g.nnx + x;
+      xu[k] = reinterpret_cast<const double2*>(a.xin)[node];
+      if (MODE == MV_CG) xp[k] = reinterpret_cast<const double2*>(a.pin)[node];
+      if (MODE == MV_APPLY) xm[k] = reinterpret_cast<const uchar2*>(a.mask)[node];
+    }
+  }
+  double ev[NES];
+#pragma unroll
+  for (int k = 0; k < NES; ++k) {
+    const int t = tid + k * MV_NT;
+    const int ii = t % (MV_TX + 1), jj = t / (MV_TX + 1);
+    const int ex = bx0 + ii, ey = by0 + jj;
+    ev[k] = (t < NEN && ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny)
+                ? a.E[(long long)ey * g.nx + ex] : 0.0;
+  }
+  const double kv = tid < 64 ? a.Ke[tid] : 0.0;
   double beta = 0.0;
   if (MODE == MV_CG) {
-    if (block_read_done(a.sc, &L.shi)) return;
-    const int it = a.sc->iter;               // not written by this kernel
-    if (it > 0) {
-      const double rz = reduce_partials<MV_NT>(a.part_comb, a.nb_comb, 1, L.red);
-      const double zq = a.sc->flexible ? reduce_partials<MV_NT>(a.part_comb + a.nb_comb, a.nb_comb, 1, L.red) : 0.0;
-      if (tid == 0) {
-        const double b = a.sc->flexible ? (-a.sc->alpha * zq / a.sc->rz) : (rz / a.sc->rz);
-        L.beta = b;
+    const double2 sums = block_sum2<MV_NT>(srz, szq, L.red);
+    if (tid == 0) {
+      bool stop = dn != DONE_RUNNING;
+      double b = 0.0;
+      if (!stop && it > 0) {
+        b = flex ? (-alpha_o * sums.y / rz_o) : (sums.x / rz_o);
         if (bx == 0 && by == 0) {
           a.sc->beta = b;
-          if (it <= a.sc->maxit) a.beta_hist[it - 1] = b;
+          if (it <= maxit) a.beta_hist[it - 1] = b;
           if (!finite(b)) {
             a.sc->status = -5;
             __hip_atomic_store(&a.sc->done, (int)DONE_BREAKDOWN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
         }
+        stop = !finite(b);
       }
-      __syncthreads();
-      beta = L.beta;
-      if (!finite(beta)) return;
+      L.beta = stop ? __builtin_nan("") : b;
+    }
+    __syncthreads();
+    beta = L.beta;
+    if (!finite(beta)) return;
+  }
+  if (tid < 64) L.ks[tid] = kv;
+#pragma unroll
+  for (int k = 0; k < NXS; ++k) {
+    const int t = tid + k * MV_NT;
+    if (t < NXN) {
+      double2 v = xu[k];
+      if (MODE == MV_CG) v = make_double2(xu[k].x + beta * xp[k].x, xu[k].y + beta * xp[k].y);
+      if (MODE == MV_APPLY) v = make_double2(xm[k].x ? 0.0 : xu[k].x, xm[k].y ? 0.0 : xu[k].y);
+      L.xs[t] = v;
     }
   }
-  const int bx0 = bx * MV_TX - 1;   // node x of xs column 0
-  const int by0 = by * TY - 1;
-  if (tid < 64) L.ks[tid] = a.Ke[tid];
-
-  for (int t = tid; t < (TY + 2) * (MV_TX + 2); t += MV_NT) {
-    const int ii = t % (MV_TX + 2), jj = t / (MV_TX + 2);
-    const int x = bx0 + ii, y = by0 + jj;
-    double2 v = make_double2(0.0, 0.0);
-    if (x >= 0 && x < g.nnx && y >= 0 && y < g.nny) {
-      const long long node = (long long)y * g.nnx + x;
-      const double2 u = reinterpret_cast<const double2*>(a.xin)[node];
-      if (MODE == MV_CG) {
-        const double2 po = reinterpret_cast<const double2*>(a.pin)[node];
-        v = make_double2(u.x + beta * po.x, u.y + beta * po.y);
-      } else if (MODE == MV_APPLY) {
-        const uchar2 m = reinterpret_cast<const uchar2*>(a.mask)[node];
-        v = make_double2(m.x ? 0.0 : u.x, m.y ? 0.0 : u.y);
-      } else {
-        v = u;
-      }
-    }
-    L.xs[t] = v;
-  }
-  for (int t = tid; t < (TY + 1) * (MV_TX + 1); t += MV_NT) {
-    const int ii = t % (MV_TX + 1), jj = t / (MV_TX + 1);
-    const int ex = bx0 + ii, ey = by0 + jj;
-    double v = 0.0;
-    if (ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny) v = a.E[(long long)ey * g.nx + ex];
-    L.es[t] = v;
+#pragma unroll
+  for (int k = 0; k < NES; ++k) {
+    const int t = tid + k * MV_NT;
+    if (t < NEN) L.es[t] = ev[k];
   }
   __syncthreads();
 
@@ -237,23 +276,38 @@ k_resid_finish(CGScalars* __restrict__ sc, const double* __restrict__ part,
 }
 
 struct UpLds {
-  double red[256 / 64 + 1];
-  int shi;
+  double red[2 * (256 / 64)];
   double alpha;
 };
 
 // x += alpha p ; r -= alpha q ; partial sums of r.r.  alpha = (r.z)/(p.q)
 // from the partials of the combine and stiffness kernels, summed by every
-// workgroup in the same order; workgroup 0 records alpha and r.z.
+// workgroup in the same order; workgroup 0 records alpha and r.z.  Every
+// read (the done word, both partial sets, this thread's entries) goes out
+// at once, so the kernel waits for memory once before its stores.
 __device__ __forceinline__ void update_body(const UpdateArgs& a, int bid, UpLds& L) {
-  if (block_read_done(a.sc, &L.shi)) return;
-  const double pq = reduce_partials<256>(a.part_mv, a.nb_mv, 1, L.red);
-  const double rz = reduce_partials<256>(a.part_comb, a.nb_comb, 1, L.red);
+  int d0 = DONE_RUNNING;
+  if (threadIdx.x == 0)
+    d0 = __hip_atomic_load(&a.sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  double spq = 0.0, srz = 0.0;
+  for (int k = threadIdx.x; k < a.nb_mv; k += 256) spq += load_coherent(a.part_mv + k);
+  for (int k = threadIdx.x; k < a.nb_comb; k += 256) srz += load_coherent(a.part_comb + k);
+  const long long i = (long long)bid * 256 + threadIdx.x;
+  const bool own = i < a.n2;
+  double2 xx = make_double2(0.0, 0.0), rr = xx, pp = xx, qq = xx;
+  if (own) {
+    xx = reinterpret_cast<double2*>(a.x)[i];
+    rr = reinterpret_cast<double2*>(a.r)[i];
+    pp = reinterpret_cast<const double2*>(a.p)[i];
+    qq = reinterpret_cast<const double2*>(a.q)[i];
+  }
+  const double2 sums = block_sum2<256>(spq, srz, L.red);
+  const double pq = sums.x, rz = sums.y;
   if (threadIdx.x == 0) {
     const bool bad = !(pq > 0.0) || !finite(pq) || !finite(rz);
     const double alpha = bad ? 0.0 : rz / pq;
-    L.alpha = bad ? __builtin_nan("") : alpha;
-    if (bid == 0) {
+    L.alpha = (bad || d0 != DONE_RUNNING) ? __builtin_nan("") : alpha;
+    if (bid == 0 && d0 == DONE_RUNNING) {
       const int it = a.sc->iter;
       a.sc->pq = pq;
       a.sc->alpha = alpha;
@@ -269,12 +323,7 @@ __device__ __forceinline__ void update_body(const UpdateArgs& a, int bid, UpLds&
   const double alpha = L.alpha;
   if (!finite(alpha)) return;
   double acc = 0.0;
-  const long long i = (long long)bid * 256 + threadIdx.x;
-  if (i < a.n2) {
-    double2 xx = reinterpret_cast<double2*>(a.x)[i];
-    double2 rr = reinterpret_cast<double2*>(a.r)[i];
-    const double2 pp = reinterpret_cast<const double2*>(a.p)[i];
-    const double2 qq = reinterpret_cast<const double2*>(a.q)[i];
+  if (own) {
     xx.x += alpha * pp.x;
     xx.y += alpha * pp.y;
     rr.x -= alpha * qq.x;

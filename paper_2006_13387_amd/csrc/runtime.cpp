@@ -161,7 +161,7 @@ struct msp_handle {
   uint8_t *d_mask = nullptr, *d_dflag = nullptr;
   double* d_E = nullptr;
   SysDesc *d_subs = nullptr, *d_omegas = nullptr;
-  int* d_sub_grid = nullptr;
+  SysDesc* d_sys_grid = nullptr;   // subdomain grid cell -> its system (nxb 0: none)
   double* d_S64 = nullptr;         // FP64 inverse blocks (always)
   float* d_S32 = nullptr;          // FP32 copy (precision 1)
   double* d_metric = nullptr;      // per-subdomain amplification metric
@@ -476,7 +476,7 @@ extern "C" const char* msp_last_error(const msp_handle* h) {
 extern "C" msp_status msp_destroy(msp_handle* h) {
   if (!h) return MSP_OK;
   void* bufs[] = {h->d_elem, h->d_mask, h->d_dflag, h->d_E, h->d_subs,
-                  h->d_omegas, h->d_sub_grid, h->d_S64, h->d_S32, h->d_metric,
+                  h->d_omegas, h->d_sys_grid, h->d_S64, h->d_S32, h->d_metric,
                   h->d_use64, h->d_lsol, h->d_gmid, h->d_Som,
                   h->d_X, h->d_Y, h->d_Z, h->d_psi, h->d_psi32, h->d_lam, h->d_nsel,
                   h->d_cap, h->d_cn, h->d_col_node, h->d_pairs, h->d_W,
@@ -648,7 +648,7 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
   A(dalloc(&h->d_E, h->n_elems));
   A(dalloc(&h->d_subs, h->subs.size()));
   A(dalloc(&h->d_omegas, h->omegas.size()));
-  A(dalloc(&h->d_sub_grid, h->sub_grid.size()));
+  A(dalloc(&h->d_sys_grid, h->sub_grid.size()));
   // the preconditioner's buffers are allocated by the first setup
   A(dalloc(&h->d_x, nd));
   A(dalloc(&h->d_r, nd));
@@ -689,7 +689,12 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
   C(hipMemcpy(h->d_dflag, dflag.data(), nn, hipMemcpyHostToDevice));
   C(hipMemcpy(h->d_subs, h->subs.data(), h->subs.size() * sizeof(SysDesc), hipMemcpyHostToDevice));
   C(hipMemcpy(h->d_omegas, h->omegas.data(), h->omegas.size() * sizeof(SysDesc), hipMemcpyHostToDevice));
-  C(hipMemcpy(h->d_sub_grid, h->sub_grid.data(), h->sub_grid.size() * sizeof(int), hipMemcpyHostToDevice));
+  {
+    std::vector<SysDesc> sg(h->sub_grid.size());
+    for (size_t i = 0; i < sg.size(); ++i)
+      if (h->sub_grid[i] >= 0) sg[i] = h->subs[h->sub_grid[i]];
+    C(hipMemcpy(h->d_sys_grid, sg.data(), sg.size() * sizeof(SysDesc), hipMemcpyHostToDevice));
+  }
   C(hipMemset(h->d_cnt, 0, 8 * sizeof(unsigned int)));
   C(hipMemset(h->d_err, 0, 4 * sizeof(int)));
   if (e != hipSuccess) {
@@ -983,8 +988,7 @@ extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
 
 static CombineArgs combine_args(msp_handle* h, bool l1, bool coarse) {
   CombineArgs ca;
-  ca.sys = h->d_subs;
-  ca.sub_grid = h->d_sub_grid;
+  ca.sys_grid = h->d_sys_grid;
   ca.ngx = h->ngx;
   ca.ngy = h->ngy;
   ca.sub_vertex = h->desc.sub_mode;
@@ -1062,6 +1066,7 @@ static CombineCall cb_args(msp_handle* h, bool l1, bool coarse, const double* r,
   a.z = z;
   a.sc = h->d_sc;
   a.part = h->part_comb;
+  a.flex = h->fp32 ? 1 : 0;           // as the CG scalars' flexible flag
   return a;
 }
 
