@@ -24,6 +24,7 @@ namespace msp {
 constexpr int FT_NT = 256;    // factorisation workgroup
 constexpr int AP_NT = 512;    // first-level apply workgroup
 constexpr int EG_NT = 512;    // eigen workgroup
+typedef double eg_d4 __attribute__((ext_vector_type(4)));   // FP64 MFMA accumulator
 constexpr int LDSTR = MAXBS + 1;   // LDS row stride of a dense block
 
 // K entry between DOF (xa,ya,ca) and DOF (xb,yb,cb): sum over the elements
@@ -1159,27 +1160,30 @@ __device__ void omega_stencil(const Geom& g, const SysDesc& s,
   }
 }
 
-// G = Y^T Z (m x m, symmetrised) into LDS G[MAXM*MAXM].  Chunks of
-// GR_NC nodes of Y and Z are staged in LDS (stage: 2*MAXM*GR_NC doubles;
-// the next chunk is loaded into registers while the current one is used).
-// Thread t = 32 sb + grp accumulates the 8 x 8 block sb of G over the
-// chunk nodes grp, grp + 32; the 32 partial blocks of a block are then
-// summed across the lanes (fixed butterfly order).
+// Part of G = Y^T Z (m x m) over nodes n0 <= node < n1 into out (global,
+// stride m, not symmetrised), on the FP64 matrix cores.  Chunks of GR_NC
+// nodes of Y and Z are staged in LDS (stage: GR_STAGE doubles, rows of
+// GR_LD doubles; the next chunk is loaded into registers while the current
+// one is used).  Wave w < 4 owns the 16 x 16 tile (w / 2, w % 2) of G
+// (m <= MAXM = 32): per FP64 MFMA 16x16x4, lane l supplies Y(16R + l%16,
+// t) and Z(16C + l%16, t) for the chunk node t = 4K + l/16 and receives
+// G(16R + l/16 + 4r, 16C + l%16) in register r.  Staged rows past m hold
+// stale values: they reach only the rows and columns of G that are
+// dropped.
 constexpr int GR_NC = 64;                       // nodes per chunk
+constexpr int GR_LD = GR_NC + 4;                // LDS row stride (banks)
+constexpr int GR_STAGE = 2 * MAXM * GR_LD;
 constexpr int GR_PF = (2 * MAXM * GR_NC + EG_NT - 1) / EG_NT;   // prefetch regs
-__device__ void gram(const double* __restrict__ Y, const double* __restrict__ Z,
-                     int n, int m, double* G, double* stage) {
-  static_assert(EG_NT == 512, "gram: 16 blocks of 32 lanes");
+static_assert(MAXM <= 32, "the Gram tiles cover 32 x 32");
+__device__ void gram_part(const double* __restrict__ Y, const double* __restrict__ Z,
+                          int n, int m, int n0, int n1, double* __restrict__ out,
+                          double* stage) {
+  static_assert(EG_NT >= 256, "gram: four waves own the tiles");
   const int tid = threadIdx.x;
-  const int sb = tid >> 5, grp = tid & 31;
-  const int nbk = (m + 7) / 8;                 // 8 x 8 blocks per dimension
-  const bool act = sb < nbk * nbk;
-  const int a0 = (sb / max(nbk, 1)) * 8, b0 = (sb % max(nbk, 1)) * 8;
-  double acc[8][8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i)
-#pragma unroll
-    for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int R = wave >> 1, C = wave & 1;
+  const bool act = wave < 4 && 16 * R < m && 16 * C < m;
   const int per = m * GR_NC;                   // doubles of Y (or Z) per chunk
   auto load = [&](int c0, double (&pf)[GR_PF]) {
 #pragma unroll
@@ -1187,69 +1191,139 @@ __device__ void gram(const double* __restrict__ Y, const double* __restrict__ Z,
       const int q = tid + u * EG_NT;           // q < per: Y, else Z
       const int qq = q < per ? q : q - per;
       const int j = qq / GR_NC, t = qq - (qq / GR_NC) * GR_NC;
-      const int node = min(c0 + t, n - 1);
+      const int node = min(c0 + t, n1 - 1);
       const double* src = q < per ? Y : Z;
-      pf[u] = (q < 2 * per && c0 + t < n && j < m) ? src[(long long)j * n + node] : 0.0;
+      pf[u] = (q < 2 * per && c0 + t < n1 && j < m) ? src[(long long)j * n + node] : 0.0;
     }
   };
+  eg_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  const double* ya = stage + (16 * R + li) * GR_LD + lk;
+  const double* zb = stage + MAXM * GR_LD + (16 * C + li) * GR_LD + lk;
   double pf[GR_PF];
-  load(0, pf);
-  for (int c0 = 0; c0 < n; c0 += GR_NC) {
+  load(n0, pf);
+  for (int c0 = n0; c0 < n1; c0 += GR_NC) {
     __syncthreads();                           // previous chunk consumed
 #pragma unroll
     for (int u = 0; u < GR_PF; ++u) {
       const int q = tid + u * EG_NT;
-      if (q < 2 * per) stage[q] = pf[u];
-    }
-    __syncthreads();
-    if (c0 + GR_NC < n) load(c0 + GR_NC, pf);
-    if (act) {
-      const double* ys = stage;
-      const double* zs = stage + per;
-#pragma unroll
-      for (int h = 0; h < GR_NC / 32; ++h) {
-        const int t = grp + 32 * h;
-        double yv[8], zv[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          yv[i] = (a0 + i < m) ? ys[(a0 + i) * GR_NC + t] : 0.0;
-          zv[i] = (b0 + i < m) ? zs[(b0 + i) * GR_NC + t] : 0.0;
-        }
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-#pragma unroll
-          for (int j = 0; j < 8; ++j) acc[i][j] += yv[i] * zv[j];
+      if (q < 2 * per) {
+        const int qq = q < per ? q : q - per;
+        const int j = qq / GR_NC, t = qq - (qq / GR_NC) * GR_NC;
+        stage[(q < per ? 0 : MAXM * GR_LD) + j * GR_LD + t] = pf[u];
       }
     }
-  }
+    __syncthreads();
+    if (c0 + GR_NC < n1) load(c0 + GR_NC, pf);
+    if (act) {
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      double v = acc[i][j];
-#pragma unroll
-      for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-      acc[i][j] = v;
-    }
-  __syncthreads();
-  if (act && grp == 0) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if (a0 + i < m && b0 + j < m) G[(a0 + i) * m + b0 + j] = acc[i][j];
-  }
-  __syncthreads();
-  // symmetrise
-  for (int e = tid; e < m * m; e += EG_NT) {
-    const int a = e / m, b = e - (e / m) * m;
-    if (a < b) {
-      const double v = 0.5 * (G[a * m + b] + G[b * m + a]);
-      G[a * m + b] = v;
-      G[b * m + a] = v;
+      for (int K = 0; K < GR_NC / 4; ++K)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[4 * K], zb[4 * K], acc, 0, 0, 0);
     }
   }
-  __syncthreads();
+  if (act) {
+    const int j = 16 * C + li;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * R + lk + 4 * r;
+      if (i < m && j < m) out[i * m + j] = acc[r];
+    }
+  }
+}
+
+// Part of G = Y^T (K Y) over nodes n0 <= node < n1 into out (stride m, not
+// symmetrised), K the pencil matrix of the element matrix Kel4 as in
+// omega_stencil (Dirichlet rows zero).  K Y is formed chunk by chunk
+// straight into the LDS stage, never stored: thread (wave w, lane t) forms
+// node c0 + t of the chunk for the columns w, w + 8, ... from the node's
+// nine neighbours (all its loads in one batch), then the Gram tiles
+// accumulate as in gram_part.
+__device__ void stencil_gram_part(const Geom& g, const SysDesc& s,
+                                  const double* __restrict__ E,
+                                  const uint8_t* __restrict__ dflag,
+                                  const double* __restrict__ Kel4,
+                                  const double* __restrict__ Y, int n, int m,
+                                  int n0, int n1, double* __restrict__ out,
+                                  double* stage) {
+  static_assert(EG_NT == 512 && GR_NC == 64, "eight waves of one chunk node each");
+  constexpr int NJ = MAXM / 8;                 // columns a thread forms
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int R = wave >> 1, C = wave & 1;
+  const bool act = wave < 4 && 16 * R < m && 16 * C < m;
+  const double* ya = stage + (16 * R + li) * GR_LD + lk;
+  const double* zb = stage + MAXM * GR_LD + (16 * C + li) * GR_LD + lk;
+  eg_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int c0 = n0; c0 < n1; c0 += GR_NC) {
+    const int node = c0 + lane;
+    const bool ok = node < n1;
+    const int nd = ok ? node : n0;
+    const int i = nd % s.nxb, k = nd / s.nxb;
+    const int x = s.x0 + i, y = s.y0 + k;
+    const bool dir = dflag[(long long)y * g.nnx + x] != 0;
+    double ke[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int ex = x - 1 + (e & 1), ey = y - 1 + (e >> 1);
+      const bool in = ex >= s.ex0 && ex < s.ex1 && ey >= s.ey0 && ey < s.ey1;
+      ke[e] = in ? E[(long long)ey * g.nx + ex] : 0.0;
+    }
+    int off9[9];
+    bool inb[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int ddx = t % 3 - 1, ddy = t / 3 - 1;
+      inb[t] = i + ddx >= 0 && i + ddx < s.nxb && k + ddy >= 0 && k + ddy < s.nyb;
+      off9[t] = inb[t] ? nd + ddy * s.nxb + ddx : nd;
+    }
+    double v[NJ][9];
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) {
+      const double* col = Y + (long long)min(wave + 8 * u, m - 1) * n;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) v[u][t] = col[off9[t]];
+    }
+    // w9[(dy+1)*3 + (dx+1)]: weight of neighbour (x+dx, y+dy)
+    double w9[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) w9[t] = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int ex_ = e & 1, ey_ = e >> 1;
+      const int va = (1 - ex_) + 2 * (1 - ey_);
+#pragma unroll
+      for (int vb = 0; vb < 4; ++vb) {
+        const int ddx = ex_ - 1 + (vb & 1), ddy = ey_ - 1 + (vb >> 1);
+        w9[(ddy + 1) * 3 + (ddx + 1)] += ke[e] * Kel4[va * 4 + vb];
+      }
+    }
+    __syncthreads();                           // previous chunk consumed
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) {
+      const int j = wave + 8 * u;
+      if (j < m) {
+        double z = 0.0;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) z += (inb[t] ? w9[t] : 0.0) * v[u][t];
+        stage[j * GR_LD + lane] = ok ? v[u][4] : 0.0;
+        stage[MAXM * GR_LD + j * GR_LD + lane] = (ok && !dir) ? z : 0.0;
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int K = 0; K < GR_NC / 4; ++K)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[4 * K], zb[4 * K], acc, 0, 0, 0);
+    }
+  }
+  if (act) {
+    const int j = 16 * C + li;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * R + lk + 4 * r;
+      if (i < m && j < m) out[i * m + j] = acc[r];
+    }
+  }
 }
 
 __device__ void chol_small(double* G, int m, int* __restrict__ err) {
@@ -1276,10 +1350,11 @@ __device__ void chol_small(double* G, int m, int* __restrict__ err) {
   __syncthreads();
 }
 
-// Y <- Y L^{-T} (each node's row of m values solved with L).
+// Y <- Y L^{-T} on nodes n0 <= node < n1 (each node's row of m values
+// solved with L).
 __device__ void apply_linvT(const double* Yin, double* Y, int n, int m,
-                            const double* L) {
-  for (int node = threadIdx.x; node < n; node += EG_NT) {
+                            const double* L, int n0, int n1) {
+  for (int node = n0 + threadIdx.x; node < n1; node += EG_NT) {
     double yv[MAXM];
 #pragma unroll
     for (int j = 0; j < MAXM; ++j)
@@ -1298,7 +1373,6 @@ __device__ void apply_linvT(const double* Yin, double* Y, int n, int m,
     for (int j = 0; j < MAXM; ++j)
       if (j < m) Y[(long long)j * n + node] = yv[j];
   }
-  __syncthreads();
 }
 
 // Jacobi eigenvalues of the symmetric m x m matrix A (LDS, stride m);
@@ -1385,12 +1459,11 @@ __device__ void jacobi_small(double* A, double* V, int m, double* rc,
   __syncthreads();
 }
 
-// X[:, c] = Y V[:, order[c]] (the Ritz vectors, ascending); one node per
-// thread.
-__device__ void ritz_vectors(const double* Y, double* X,
-                                          const double* V, const int* order,
-                                          int n, int m) {
-  for (int node = threadIdx.x; node < n; node += EG_NT) {
+// X[:, c] = Y V[:, order[c]] (the Ritz vectors, ascending) on nodes
+// n0 <= node < n1; one node per thread.
+__device__ void ritz_vectors(const double* Y, double* X, const double* V,
+                             const int* order, int n, int m, int n0, int n1) {
+  for (int node = n0 + threadIdx.x; node < n1; node += EG_NT) {
     double yv[MAXM];
 #pragma unroll
     for (int j = 0; j < MAXM; ++j)
@@ -1408,7 +1481,6 @@ __device__ void ritz_vectors(const double* Y, double* X,
 
 // Shift-invert sweeps (k_eig_chain): block products S_k^{-1} Wl on the
 // FP64 matrix cores, K steps of 4 over a block row.
-typedef double eg_d4 __attribute__((ext_vector_type(4)));
 constexpr int EG_NK = (MAXBS + 3) / 4;     // K steps of 4 over a block row
 static_assert(EG_NK % 2 == 0, "the block GEMM pairs its K steps");
 constexpr int EG_PFZ = (MAXBS * MAXM + EG_NT - 1) / EG_NT;               // row regs
@@ -1435,11 +1507,15 @@ __device__ __forceinline__ void eg_barrier() {
 
 // Per-neighbourhood state of the subspace iteration, kept in device memory
 // between the iteration's kernels.
+constexpr int EG_OB = 3;                   // row bands of a neighbourhood's streaming kernels
 struct EigState {
   int done;                  // converged (or failed): later launches skip it
-  int pad;
+  int conv;                  // the last Rayleigh-Ritz step converged
   double theta[MAXM];        // Ritz values of the last Rayleigh-Ritz step
   double theta_old[MAXM];
+  double gp[EG_OB][MAXM * MAXM];   // band parts of a Gram matrix
+  double L[MAXM * MAXM];     // Cholesky factor, or the Ritz rotation V
+  int order[MAXM];           // Ritz values ascending: their columns of V
 };
 
 size_t eig_state_bytes() { return sizeof(EigState); }
@@ -1463,7 +1539,10 @@ k_eig_start(Geom g, const SysDesc* __restrict__ systems,
     X[idx] = d ? 0.0 : hash_unit(key);
   }
   EigState& e = st[blockIdx.x];
-  if (tid == 0) e.done = 0;
+  if (tid == 0) {
+    e.done = 0;
+    e.conv = 0;
+  }
   if (tid < MAXM) e.theta_old[tid] = 0.0;
 }
 
@@ -1729,50 +1808,101 @@ k_eig_chain(Geom g, const SysDesc* __restrict__ systems,
     }
 }
 
-// M-orthonormalise Y by Cholesky QR into X; with rr, orthonormalise again
-// and replace X by the Ritz vectors of the pencil (A, M) on span(X),
-// ascending, then test convergence of the Ritz values that decide the
-// selection (those below the threshold, at most kmax, and the next one).
+// M-orthonormalisation of Y by Cholesky QR into X (twice at a
+// Rayleigh-Ritz step), and Rayleigh-Ritz with A on span(X): the Ritz
+// vectors replace X, ascending, and the Ritz values that decide the
+// selection (those below the threshold, at most kmax, and the next one)
+// are tested for convergence.  Streaming work runs in EG_OB row bands per
+// neighbourhood (workgroup EG_OB l + b), the small dense work in one
+// workgroup per neighbourhood:
+//   k_orth_gram   Z = M_e src on the band's rows, the band's part of src^T Z
+//   k_orth_chol   G = sum of the parts (band order), symmetrised; L L^T = G
+//   k_orth_linvT  dst = src L^{-T} on the band's rows
+//   k_orth_rr     G as above (A_e), Jacobi, Ritz values ascending, test
+//   k_orth_ritz   X = X V (columns in ascending Ritz order) on the band
+
+// node range [n0, n1) of band b (whole node rows)
+__device__ __forceinline__ void eig_band(const SysDesc& s, int b, int* n0, int* n1) {
+  *n0 = ((b * s.nyb) / EG_OB) * s.nxb;
+  *n1 = (((b + 1) * s.nyb) / EG_OB) * s.nxb;
+}
+
+// (at most 128 registers: two workgroups per CU)
+__global__ void __launch_bounds__(EG_NT, 4)
+k_orth_gram(Geom g, const SysDesc* __restrict__ systems,
+            const double* __restrict__ E, const uint8_t* __restrict__ dflag,
+            const double* __restrict__ Kel4, const double* __restrict__ Srcw,
+            double* __restrict__ Zw, int m, EigState* __restrict__ st) {
+  __shared__ __align__(16) double stage[GR_STAGE];
+  const int sys = blockIdx.x / EG_OB, b = blockIdx.x - (blockIdx.x / EG_OB) * EG_OB;
+  EigState& es = st[sys];
+  if (es.done) return;
+  const SysDesc s = systems[sys];
+  const int n = s.nxb * s.nyb;
+  const long long wo = s.voff * (long long)m;
+  int n0, n1;
+  eig_band(s, b, &n0, &n1);
+  (void)Zw;
+  stencil_gram_part(g, s, E, dflag, Kel4, Srcw + wo, n, m, n0, n1, es.gp[b], stage);
+}
+
+// G (LDS, stride m) = the sum of the band parts in band order, symmetrised
+__device__ void orth_gather(const EigState& es, int m, double* G) {
+  for (int e = threadIdx.x; e < m * m; e += EG_NT) {
+    double v = 0.0;
+#pragma unroll
+    for (int b = 0; b < EG_OB; ++b) v += es.gp[b][e];
+    G[e] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < m * m; e += EG_NT) {
+    const int a = e / m, c = e - (e / m) * m;
+    if (a < c) {
+      const double v = 0.5 * (G[a * m + c] + G[c * m + a]);
+      G[a * m + c] = v;
+      G[c * m + a] = v;
+    }
+  }
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(EG_NT)
-k_eig_orth(Geom g, const SysDesc* __restrict__ systems,
-           const double* __restrict__ E, const uint8_t* __restrict__ dflag,
-           const double* __restrict__ Ae, const double* __restrict__ Me,
-           double* __restrict__ Xw, double* __restrict__ Yw,
-           double* __restrict__ Zw, EigParams prm, int rr, int first_rr,
-           EigState* __restrict__ st, int* __restrict__ err) {
-  __shared__ __align__(16) double raw[2 * MAXM * 64];   // gram staging
+k_orth_chol(int m, EigState* __restrict__ st, int* __restrict__ err) {
+  __shared__ double G[MAXM * MAXM];
+  EigState& es = st[blockIdx.x];
+  if (es.done) return;
+  orth_gather(es, m, G);
+  chol_small(G, m, err);
+  for (int e = threadIdx.x; e < m * m; e += EG_NT) es.L[e] = G[e];
+}
+
+__global__ void __launch_bounds__(EG_NT)
+k_orth_linvT(const SysDesc* __restrict__ systems, const double* __restrict__ Srcw,
+             double* __restrict__ Dstw, int m, const EigState* __restrict__ st) {
+  __shared__ double L[MAXM * MAXM];
+  const int sys = blockIdx.x / EG_OB, b = blockIdx.x - (blockIdx.x / EG_OB) * EG_OB;
+  const EigState& es = st[sys];
+  if (es.done) return;
+  const SysDesc s = systems[sys];
+  const long long wo = s.voff * (long long)m;
+  for (int e = threadIdx.x; e < m * m; e += EG_NT) L[e] = es.L[e];
+  __syncthreads();
+  int n0, n1;
+  eig_band(s, b, &n0, &n1);
+  apply_linvT(Srcw + wo, Dstw + wo, s.nxb * s.nyb, m, L, n0, n1);
+}
+
+__global__ void __launch_bounds__(EG_NT)
+k_orth_rr(EigParams prm, int first_rr, EigState* __restrict__ st) {
   __shared__ double G[MAXM * MAXM];
   __shared__ double V[MAXM * MAXM];
   __shared__ double rc[MAXM], rs[MAXM];
   __shared__ int rp[MAXM], rq[MAXM], order[MAXM];
-  __shared__ int converged;
   EigState& es = st[blockIdx.x];
   if (es.done) return;
-  const SysDesc s = systems[blockIdx.x];
   const int tid = threadIdx.x;
-  const int n = s.nxb * s.nyb;
   const int m = prm.m;
-  const long long wo = s.voff * (long long)m;
-  double* X = Xw + wo;
-  double* Y = Yw + wo;
-  double* Z = Zw + wo;
-  // pass 1: X = Y L^-T with L L^T = Y^T M Y
-  omega_stencil(g, s, E, dflag, Me, Y, Z, n, m, 0, n);
-  __syncthreads();
-  gram(Y, Z, n, m, G, raw);
-  chol_small(G, m, err);
-  apply_linvT(Y, X, n, m, G);
-  if (!rr) return;
-  // pass 2 (in place)
-  omega_stencil(g, s, E, dflag, Me, X, Z, n, m, 0, n);
-  __syncthreads();
-  gram(X, Z, n, m, G, raw);
-  chol_small(G, m, err);
-  apply_linvT(X, X, n, m, G);
-  // Rayleigh-Ritz with A
-  omega_stencil(g, s, E, dflag, Ae, X, Z, n, m, 0, n);
-  __syncthreads();
-  gram(X, Z, n, m, G, raw);
+  orth_gather(es, m, G);
   jacobi_small(G, V, m, rc, rs, rp, rq);
   if (tid == 0) {
     for (int i = 0; i < m; ++i) order[i] = i;
@@ -1798,22 +1928,45 @@ k_eig_orth(Geom g, const SysDesc* __restrict__ systems,
       dmax = fmax(dmax, rel);
     }
     for (int i = 0; i < m; ++i) es.theta_old[i] = es.theta[i];
-    converged = (!first_rr && dmax < prm.tol) ? 1 : 0;
+    // k_eig_count turns this into done once the Ritz vectors are formed
+    es.conv = (!first_rr && dmax < prm.tol) ? 1 : 0;
   }
   __syncthreads();
-  // X = X V (columns sorted ascending), in place node by node
-  ritz_vectors(X, X, V, order, n, m);
-  if (tid == 0 && converged) es.done = 1;
+  for (int e = tid; e < m * m; e += EG_NT) es.L[e] = V[e];
+  if (tid < m) es.order[tid] = order[tid];
 }
 
-// Number of neighbourhoods still iterating, into *count (one workgroup).
+__global__ void __launch_bounds__(EG_NT)
+k_orth_ritz(const SysDesc* __restrict__ systems, double* __restrict__ Xw, int m,
+            const EigState* __restrict__ st) {
+  __shared__ double V[MAXM * MAXM];
+  __shared__ int order[MAXM];
+  const int sys = blockIdx.x / EG_OB, b = blockIdx.x - (blockIdx.x / EG_OB) * EG_OB;
+  const EigState& es = st[sys];
+  if (es.done) return;
+  const SysDesc s = systems[sys];
+  const long long wo = s.voff * (long long)m;
+  for (int e = threadIdx.x; e < m * m; e += EG_NT) V[e] = es.L[e];
+  if (threadIdx.x < m) order[threadIdx.x] = es.order[threadIdx.x];
+  __syncthreads();
+  int n0, n1;
+  eig_band(s, b, &n0, &n1);
+  ritz_vectors(Xw + wo, Xw + wo, V, order, s.nxb * s.nyb, m, n0, n1);
+}
+
+// After a Rayleigh-Ritz step: neighbourhoods whose Ritz values converged
+// stop iterating; the number still iterating goes to *count (one
+// workgroup).
 __global__ void __launch_bounds__(256)
-k_eig_count(const EigState* __restrict__ st, int nsys, int* __restrict__ count) {
+k_eig_count(EigState* __restrict__ st, int nsys, int* __restrict__ count) {
   __shared__ int c;
   if (threadIdx.x == 0) c = 0;
   __syncthreads();
   int mine = 0;
-  for (int i = threadIdx.x; i < nsys; i += 256) mine += st[i].done ? 0 : 1;
+  for (int i = threadIdx.x; i < nsys; i += 256) {
+    if (!st[i].done && st[i].conv) st[i].done = 1;
+    mine += st[i].done ? 0 : 1;
+  }
   if (mine) atomicAdd(&c, mine);
   __syncthreads();
   if (threadIdx.x == 0) *count = c;
@@ -1920,9 +2073,24 @@ void launch_heat_eigen(const Geom& g, const SysDesc* sys, int nsys,
     hipLaunchKernelGGL(k_eig_chain<true>, dim3(2 * nsys), dim3(EG_NT), 0, s, g,
                        sys, E, dflag, Me, Sinv, X, Y, Z, m, st);
     const bool rr = ((it + 1) % rr_every == 0) || (it + 1 == maxit);
-    hipLaunchKernelGGL(k_eig_orth, dim3(nsys), dim3(EG_NT), 0, s, g, sys, E,
-                       dflag, Ae, Me, X, Y, Z, p, rr ? 1 : 0, first_rr ? 1 : 0,
-                       st, err);
+    // X = Y L^{-T} with L L^T = Y^T M Y (in place with src = dst = X)
+    auto orth_pass = [&](const double* src, double* dst) {
+      hipLaunchKernelGGL(k_orth_gram, dim3(EG_OB * nsys), dim3(EG_NT), 0, s, g,
+                         sys, E, dflag, Me, src, Z, m, st);
+      hipLaunchKernelGGL(k_orth_chol, dim3(nsys), dim3(EG_NT), 0, s, m, st, err);
+      hipLaunchKernelGGL(k_orth_linvT, dim3(EG_OB * nsys), dim3(EG_NT), 0, s,
+                         sys, src, dst, m, st);
+    };
+    orth_pass(Y, X);
+    if (rr) {
+      orth_pass(X, X);
+      hipLaunchKernelGGL(k_orth_gram, dim3(EG_OB * nsys), dim3(EG_NT), 0, s, g,
+                         sys, E, dflag, Ae, X, Z, m, st);
+      hipLaunchKernelGGL(k_orth_rr, dim3(nsys), dim3(EG_NT), 0, s, p,
+                         first_rr ? 1 : 0, st);
+      hipLaunchKernelGGL(k_orth_ritz, dim3(EG_OB * nsys), dim3(EG_NT), 0, s, sys,
+                         X, m, st);
+    }
     if (rr) {
       first_rr = false;
       hipLaunchKernelGGL(k_eig_count, dim3(1), dim3(256), 0, s, st, nsys, d_count);
