@@ -1095,233 +1095,154 @@ __device__ __forceinline__ double hash_unit(unsigned long long a) {
   return (double)(a >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
-// out[j][node] = sum_e kappa_e (Kel in)[node] over omega's elements for the
-// first m columns and nodes n0 <= node < n1 (column stride n); Dirichlet
-// rows are 0.  One node per thread: its nine
-// neighbour weights are formed once from the (up to) four elements around
-// it, then the columns are done four at a time with all their loads issued
-// before the stores.
-__device__ void omega_stencil(const Geom& g, const SysDesc& s,
-                              const double* __restrict__ E,
-                              const uint8_t* __restrict__ dflag,
-                              const double* __restrict__ Kel4,
-                              const double* __restrict__ in,
-                              double* __restrict__ out, int n, int m,
-                              int n0, int n1) {
-  for (int node = n0 + threadIdx.x; node < n1; node += EG_NT) {
-    const int i = node % s.nxb, k = node / s.nxb;
-    const int x = s.x0 + i, y = s.y0 + k;
-    if (dflag[(long long)y * g.nnx + x]) {
-      for (int j = 0; j < m; ++j) out[(long long)j * n + node] = 0.0;
-      continue;
+// K Y on node rows r0 <= k < r1 of a neighbourhood, K = sum_e kappa_e Kel4
+// over the neighbourhood's elements (Kel4 the 4 x 4 element matrix, kappa_e
+// the modulus; Dirichlet rows zero), through a rolling window of three node
+// rows of Y in LDS: every Y value is read from memory once, and the reads
+// of row k+2 go out before row k is formed.  Per row k, with the product
+// row P_k (m x nxb) in LDS:
+//   GRAM:  out (m x m, stride m, not symmetrised) += Y_k^T P_k on the FP64
+//          matrix cores, wave w < 4 owning the 16 x 16 tile (w / 2, w % 2)
+//          (lane l supplies Y(16R + l%16, t), P(16C + l%16, t) for the
+//          row node t = 4K + l/16 and receives (16R + l/16 + 4r,
+//          16C + l%16) in register r; rows past m hold stale values that
+//          reach only dropped rows and columns);
+//   else:  P_k is stored to Zout (rows k of its m columns).
+// LDS (doubles, at win): three Y rows, P, three element-moduli rows, three
+// flag rows, Kel4 (SW_DOUBLES in all).
+constexpr int SW_RL = 74;                        // row stride (>= MAXBS + 1; banks)
+constexpr int SW_Z = 3 * MAXM * SW_RL;           // product row
+constexpr int SW_E = SW_Z + MAXM * SW_RL;        // moduli rows (columns x0-1 ..)
+constexpr int SW_F = SW_E + 3 * SW_RL;           // Dirichlet flags (1.0 / 0.0)
+constexpr int SW_K = SW_F + 3 * SW_RL;           // element matrix
+constexpr int SW_DOUBLES = SW_K + 16;
+constexpr int SW_PF = (MAXM * MAXBS + EG_NT - 1) / EG_NT;   // Y prefetch regs
+static_assert(MAXBS + 1 <= SW_RL, "a moduli row needs nxb + 1 entries");
+template <bool GRAM>
+__device__ void stencil_rows(const Geom& g, const SysDesc& s,
+                             const double* __restrict__ E,
+                             const uint8_t* __restrict__ dflag,
+                             const double* __restrict__ Kel4,
+                             const double* __restrict__ Y, int n, int m, int r0,
+                             int r1, double* __restrict__ out,
+                             double* __restrict__ Zout, double* win) {
+  const int tid = threadIdx.x;
+  const int nxb = s.nxb, nyb = s.nyb;
+  const int nrow = m * nxb;                    // Y values of a node row
+  const int kpad = (nxb + 3) & ~3;             // K extent of the Gram tiles
+  auto slot = [&](int kk) { return ((kk % 3) + 3) % 3; };
+  // one node row kk of Y, its flags and the moduli row below it (element
+  // row y0 + kk - 1), into registers / into the window
+  double py[SW_PF], pe, pf;
+  auto fetch = [&](int kk) {
+    const bool rin = kk >= 0 && kk < nyb;
+#pragma unroll
+    for (int u = 0; u < SW_PF; ++u) {
+      const int q = tid + u * EG_NT;
+      const int j = q / nxb, i = q - (q / nxb) * nxb;
+      py[u] = (rin && q < nrow) ? Y[(long long)j * n + kk * nxb + i] : 0.0;
     }
-    // w9[(dy+1)*3 + (dx+1)]: weight of neighbour (x+dx, y+dy)
-    double w9[9];
+    pe = 0.0;
+    pf = 0.0;
+    if (tid <= nxb) {
+      const int ex = s.x0 - 1 + tid, ey = s.y0 + kk - 1;
+      if (ex >= s.ex0 && ex < s.ex1 && ey >= s.ey0 && ey < s.ey1)
+        pe = E[(long long)ey * g.nx + ex];
+    }
+    if (tid < nxb && rin) pf = dflag[(long long)(s.y0 + kk) * g.nnx + s.x0 + tid] ? 1.0 : 0.0;
+  };
+  auto place = [&](int kk) {
+    double* yw = win + slot(kk) * MAXM * SW_RL;
 #pragma unroll
-    for (int t = 0; t < 9; ++t) w9[t] = 0.0;
+    for (int u = 0; u < SW_PF; ++u) {
+      const int q = tid + u * EG_NT;
+      if (q < nrow) {
+        const int j = q / nxb, i = q - (q / nxb) * nxb;
+        yw[j * SW_RL + i] = py[u];
+      }
+    }
+    if (tid <= nxb) win[SW_E + slot(kk) * SW_RL + tid] = pe;
+    if (tid < nxb) win[SW_F + slot(kk) * SW_RL + tid] = pf;
+  };
+  // Y and P padding columns nxb .. kpad-1 stay zero (the Gram's K padding)
+  for (int q = tid; q < 4 * MAXM * (kpad - nxb); q += EG_NT) {
+    const int r = q / (kpad - nxb), c = nxb + q % (kpad - nxb);
+    win[r * SW_RL + c] = 0.0;
+  }
+  if (tid < 16) win[SW_K + tid] = Kel4[tid];
+  fetch(r0 - 1);
+  place(r0 - 1);
+  fetch(r0);
+  place(r0);
+  fetch(r0 + 1);
+  place(r0 + 1);
+  __syncthreads();
+  // stencil role: node i, columns jg, jg + ng, ...
+  const int ng = EG_NT / nxb;
+  const int i = tid % nxb, jg = tid / nxb;
+  const bool st = jg < ng;
+  // Gram role
+  const int wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int R = wave >> 1, C = wave & 1;
+  const bool act = GRAM && wave < 4 && 16 * R < m && 16 * C < m;
+  eg_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  double* P = win + SW_Z;
+  for (int k = r0; k < r1; ++k) {
+    const bool pre = k + 2 <= r1;
+    if (pre) fetch(k + 2);
+    if (st) {
+      // weights of the nine neighbours from the four elements around the
+      // node (moduli rows k: above, k+1: below)
+      double w9[9];
 #pragma unroll
-    for (int ey_ = 0; ey_ < 2; ++ey_)
+      for (int t = 0; t < 9; ++t) w9[t] = 0.0;
 #pragma unroll
-      for (int ex_ = 0; ex_ < 2; ++ex_) {
-        const int ex = x - 1 + ex_, ey = y - 1 + ey_;
-        const bool ok = ex >= s.ex0 && ex < s.ex1 && ey >= s.ey0 && ey < s.ey1;
-        const double ke = ok ? E[(long long)ey * g.nx + ex] : 0.0;
+      for (int e = 0; e < 4; ++e) {
+        const int ex_ = e & 1, ey_ = e >> 1;
+        const double ke = win[SW_E + slot(k + ey_) * SW_RL + i + ex_];
         const int va = (1 - ex_) + 2 * (1 - ey_);
 #pragma unroll
         for (int vb = 0; vb < 4; ++vb) {
           const int ddx = ex_ - 1 + (vb & 1), ddy = ey_ - 1 + (vb >> 1);
-          w9[(ddy + 1) * 3 + (ddx + 1)] += ke * Kel4[va * 4 + vb];
+          w9[(ddy + 1) * 3 + (ddx + 1)] += ke * win[SW_K + va * 4 + vb];
         }
       }
-    int off9[9];
+      const bool dir = win[SW_F + slot(k) * SW_RL + i] != 0.0;
+      bool ok[9];
+      int ofs[9];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int ddx = t % 3 - 1, ddy = t / 3 - 1;
-      const bool in_box = i + ddx >= 0 && i + ddx < s.nxb && k + ddy >= 0 && k + ddy < s.nyb;
-      off9[t] = in_box ? node + ddy * s.nxb + ddx : node;
-      if (!in_box) w9[t] = 0.0;
-    }
-    for (int j0 = 0; j0 < m; j0 += 4) {
-      double v[4][9];
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const double* col = in + (long long)min(j0 + jj, m - 1) * n;
-#pragma unroll
-        for (int t = 0; t < 9; ++t) v[jj][t] = col[off9[t]];
+      for (int t = 0; t < 9; ++t) {
+        const int ddx = t % 3 - 1, ddy = t / 3 - 1;
+        ok[t] = i + ddx >= 0 && i + ddx < nxb && k + ddy >= 0 && k + ddy < nyb;
+        ofs[t] = slot(k + ddy) * MAXM * SW_RL + (ok[t] ? i + ddx : i);
       }
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        double acc = 0.0;
-#pragma unroll
-        for (int t = 0; t < 9; ++t) acc += w9[t] * v[jj][t];
-        if (j0 + jj < m) out[(long long)(j0 + jj) * n + node] = acc;
-      }
-    }
-  }
-}
-
-// Part of G = Y^T Z (m x m) over nodes n0 <= node < n1 into out (global,
-// stride m, not symmetrised), on the FP64 matrix cores.  Chunks of GR_NC
-// nodes of Y and Z are staged in LDS (stage: GR_STAGE doubles, rows of
-// GR_LD doubles; the next chunk is loaded into registers while the current
-// one is used).  Wave w < 4 owns the 16 x 16 tile (w / 2, w % 2) of G
-// (m <= MAXM = 32): per FP64 MFMA 16x16x4, lane l supplies Y(16R + l%16,
-// t) and Z(16C + l%16, t) for the chunk node t = 4K + l/16 and receives
-// G(16R + l/16 + 4r, 16C + l%16) in register r.  Staged rows past m hold
-// stale values: they reach only the rows and columns of G that are
-// dropped.
-constexpr int GR_NC = 64;                       // nodes per chunk
-constexpr int GR_LD = GR_NC + 4;                // LDS row stride (banks)
-constexpr int GR_STAGE = 2 * MAXM * GR_LD;
-constexpr int GR_PF = (2 * MAXM * GR_NC + EG_NT - 1) / EG_NT;   // prefetch regs
-static_assert(MAXM <= 32, "the Gram tiles cover 32 x 32");
-__device__ void gram_part(const double* __restrict__ Y, const double* __restrict__ Z,
-                          int n, int m, int n0, int n1, double* __restrict__ out,
-                          double* stage) {
-  static_assert(EG_NT >= 256, "gram: four waves own the tiles");
-  const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
-  const int li = lane & 15, lk = lane >> 4;
-  const int R = wave >> 1, C = wave & 1;
-  const bool act = wave < 4 && 16 * R < m && 16 * C < m;
-  const int per = m * GR_NC;                   // doubles of Y (or Z) per chunk
-  auto load = [&](int c0, double (&pf)[GR_PF]) {
-#pragma unroll
-    for (int u = 0; u < GR_PF; ++u) {
-      const int q = tid + u * EG_NT;           // q < per: Y, else Z
-      const int qq = q < per ? q : q - per;
-      const int j = qq / GR_NC, t = qq - (qq / GR_NC) * GR_NC;
-      const int node = min(c0 + t, n1 - 1);
-      const double* src = q < per ? Y : Z;
-      pf[u] = (q < 2 * per && c0 + t < n1 && j < m) ? src[(long long)j * n + node] : 0.0;
-    }
-  };
-  eg_d4 acc = {0.0, 0.0, 0.0, 0.0};
-  const double* ya = stage + (16 * R + li) * GR_LD + lk;
-  const double* zb = stage + MAXM * GR_LD + (16 * C + li) * GR_LD + lk;
-  double pf[GR_PF];
-  load(n0, pf);
-  for (int c0 = n0; c0 < n1; c0 += GR_NC) {
-    __syncthreads();                           // previous chunk consumed
-#pragma unroll
-    for (int u = 0; u < GR_PF; ++u) {
-      const int q = tid + u * EG_NT;
-      if (q < 2 * per) {
-        const int qq = q < per ? q : q - per;
-        const int j = qq / GR_NC, t = qq - (qq / GR_NC) * GR_NC;
-        stage[(q < per ? 0 : MAXM * GR_LD) + j * GR_LD + t] = pf[u];
-      }
-    }
-    __syncthreads();
-    if (c0 + GR_NC < n1) load(c0 + GR_NC, pf);
-    if (act) {
-#pragma unroll
-      for (int K = 0; K < GR_NC / 4; ++K)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[4 * K], zb[4 * K], acc, 0, 0, 0);
-    }
-  }
-  if (act) {
-    const int j = 16 * C + li;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = 16 * R + lk + 4 * r;
-      if (i < m && j < m) out[i * m + j] = acc[r];
-    }
-  }
-}
-
-// Part of G = Y^T (K Y) over nodes n0 <= node < n1 into out (stride m, not
-// symmetrised), K the pencil matrix of the element matrix Kel4 as in
-// omega_stencil (Dirichlet rows zero).  K Y is formed chunk by chunk
-// straight into the LDS stage, never stored: thread (wave w, lane t) forms
-// node c0 + t of the chunk for the columns w, w + 8, ... from the node's
-// nine neighbours (all its loads in one batch), then the Gram tiles
-// accumulate as in gram_part.
-__device__ void stencil_gram_part(const Geom& g, const SysDesc& s,
-                                  const double* __restrict__ E,
-                                  const uint8_t* __restrict__ dflag,
-                                  const double* __restrict__ Kel4,
-                                  const double* __restrict__ Y, int n, int m,
-                                  int n0, int n1, double* __restrict__ out,
-                                  double* stage) {
-  static_assert(EG_NT == 512 && GR_NC == 64, "eight waves of one chunk node each");
-  constexpr int NJ = MAXM / 8;                 // columns a thread forms
-  const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
-  const int li = lane & 15, lk = lane >> 4;
-  const int R = wave >> 1, C = wave & 1;
-  const bool act = wave < 4 && 16 * R < m && 16 * C < m;
-  const double* ya = stage + (16 * R + li) * GR_LD + lk;
-  const double* zb = stage + MAXM * GR_LD + (16 * C + li) * GR_LD + lk;
-  eg_d4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int c0 = n0; c0 < n1; c0 += GR_NC) {
-    const int node = c0 + lane;
-    const bool ok = node < n1;
-    const int nd = ok ? node : n0;
-    const int i = nd % s.nxb, k = nd / s.nxb;
-    const int x = s.x0 + i, y = s.y0 + k;
-    const bool dir = dflag[(long long)y * g.nnx + x] != 0;
-    double ke[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int ex = x - 1 + (e & 1), ey = y - 1 + (e >> 1);
-      const bool in = ex >= s.ex0 && ex < s.ex1 && ey >= s.ey0 && ey < s.ey1;
-      ke[e] = in ? E[(long long)ey * g.nx + ex] : 0.0;
-    }
-    int off9[9];
-    bool inb[9];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int ddx = t % 3 - 1, ddy = t / 3 - 1;
-      inb[t] = i + ddx >= 0 && i + ddx < s.nxb && k + ddy >= 0 && k + ddy < s.nyb;
-      off9[t] = inb[t] ? nd + ddy * s.nxb + ddx : nd;
-    }
-    double v[NJ][9];
-#pragma unroll
-    for (int u = 0; u < NJ; ++u) {
-      const double* col = Y + (long long)min(wave + 8 * u, m - 1) * n;
-#pragma unroll
-      for (int t = 0; t < 9; ++t) v[u][t] = col[off9[t]];
-    }
-    // w9[(dy+1)*3 + (dx+1)]: weight of neighbour (x+dx, y+dy)
-    double w9[9];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) w9[t] = 0.0;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int ex_ = e & 1, ey_ = e >> 1;
-      const int va = (1 - ex_) + 2 * (1 - ey_);
-#pragma unroll
-      for (int vb = 0; vb < 4; ++vb) {
-        const int ddx = ex_ - 1 + (vb & 1), ddy = ey_ - 1 + (vb >> 1);
-        w9[(ddy + 1) * 3 + (ddx + 1)] += ke[e] * Kel4[va * 4 + vb];
-      }
-    }
-    __syncthreads();                           // previous chunk consumed
-#pragma unroll
-    for (int u = 0; u < NJ; ++u) {
-      const int j = wave + 8 * u;
-      if (j < m) {
+      for (int j = jg; j < m; j += ng) {
         double z = 0.0;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) z += (inb[t] ? w9[t] : 0.0) * v[u][t];
-        stage[j * GR_LD + lane] = ok ? v[u][4] : 0.0;
-        stage[MAXM * GR_LD + j * GR_LD + lane] = (ok && !dir) ? z : 0.0;
+        for (int t = 0; t < 9; ++t) z += (ok[t] ? w9[t] : 0.0) * win[ofs[t] + j * SW_RL];
+        z = dir ? 0.0 : z;
+        if (GRAM) P[j * SW_RL + i] = z;
+        else Zout[(long long)j * n + k * nxb + i] = z;
       }
     }
-    __syncthreads();
+    __syncthreads();                           // P complete, row k-1 free
     if (act) {
-#pragma unroll
-      for (int K = 0; K < GR_NC / 4; ++K)
+      const double* ya = win + slot(k) * MAXM * SW_RL + (16 * R + li) * SW_RL + lk;
+      const double* zb = P + (16 * C + li) * SW_RL + lk;
+      for (int K = 0; K < kpad / 4; ++K)
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[4 * K], zb[4 * K], acc, 0, 0, 0);
     }
+    // (after the products, so that row k+2's reads had the longest time)
+    if (pre) place(k + 2);
+    __syncthreads();
   }
   if (act) {
     const int j = 16 * C + li;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = 16 * R + lk + 4 * r;
-      if (i < m && j < m) out[i * m + j] = acc[r];
+      const int ii = 16 * R + lk + 4 * r;
+      if (ii < m && j < m) out[ii * m + j] = acc[r];
     }
   }
 }
@@ -1485,6 +1406,7 @@ constexpr int EG_NK = (MAXBS + 3) / 4;     // K steps of 4 over a block row
 static_assert(EG_NK % 2 == 0, "the block GEMM pairs its K steps");
 constexpr int EG_PFZ = (MAXBS * MAXM + EG_NT - 1) / EG_NT;               // row regs
 constexpr int EG_RAW = 18176;              // doubles of the kernel's carved LDS
+static_assert(SW_DOUBLES <= EG_RAW, "the sweep's LDS holds the stencil window");
 
 // LDS doubles the sweep needs for bs, m (2 record slots, 2 vector rows,
 // the right-hand side, the result rows and one more coupling block)
@@ -1590,7 +1512,7 @@ k_eig_chain(Geom g, const SysDesc* __restrict__ systems,
   double* Z = Zw + wo;
   if (!BWD) {
     const int r0 = h == 0 ? 0 : mid + 1, r1 = h == 0 ? mid + 1 : nb;
-    omega_stencil(g, s, E, dflag, Me, X, Z, n, m, r0 * bs, r1 * bs);
+    stencil_rows<false>(g, s, E, dflag, Me, X, n, m, r0, r1, nullptr, Z, raw);
     __syncthreads();
     if (len == 0) return;
   }
@@ -1833,7 +1755,7 @@ k_orth_gram(Geom g, const SysDesc* __restrict__ systems,
             const double* __restrict__ E, const uint8_t* __restrict__ dflag,
             const double* __restrict__ Kel4, const double* __restrict__ Srcw,
             double* __restrict__ Zw, int m, EigState* __restrict__ st) {
-  __shared__ __align__(16) double stage[GR_STAGE];
+  __shared__ __align__(16) double win[SW_DOUBLES];
   const int sys = blockIdx.x / EG_OB, b = blockIdx.x - (blockIdx.x / EG_OB) * EG_OB;
   EigState& es = st[sys];
   if (es.done) return;
@@ -1843,7 +1765,8 @@ k_orth_gram(Geom g, const SysDesc* __restrict__ systems,
   int n0, n1;
   eig_band(s, b, &n0, &n1);
   (void)Zw;
-  stencil_gram_part(g, s, E, dflag, Kel4, Srcw + wo, n, m, n0, n1, es.gp[b], stage);
+  stencil_rows<true>(g, s, E, dflag, Kel4, Srcw + wo, n, m, n0 / s.nxb, n1 / s.nxb,
+                     es.gp[b], nullptr, win);
 }
 
 // G (LDS, stride m) = the sum of the band parts in band order, symmetrised
