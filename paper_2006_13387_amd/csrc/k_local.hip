@@ -16,6 +16,8 @@
 // per row and chain, so one solve reads about 2 * nyb * bs^2 stored values.
 // Clamped (Dirichlet) DOFs become identity rows with zero couplings, which
 // keeps the principal submatrix of the free DOFs exact.
+#include <algorithm>
+#include <vector>
 #include "common.h"
 #include "dev.h"
 
@@ -436,24 +438,31 @@ __device__ double factor_chain(const Geom& g, const SysDesc& s, int row0,
 // values leaves spurious strains in the stiff phase, so the runtime keeps
 // FP64 blocks for systems whose metric exceeds a bound.  Part metrics go to
 // metric[nsys + 2 i + h], the system's to metric[i] (k_factor_middle).
+//
+// Workgroups take their chains from pack (see chain_items).
 template <int NDOF>
 __global__ void __launch_bounds__(FT_NT)
 k_factor_twisted(Geom g, const SysDesc* __restrict__ systems, int nsys,
                  const double* __restrict__ E, const uint8_t* __restrict__ flag,
                  const double* __restrict__ Kel, double* __restrict__ out64,
                  float* __restrict__ out32, double* __restrict__ metric,
-                 int* __restrict__ err) {
+                 int* __restrict__ err, const int* __restrict__ pack) {
   __shared__ FactorLds L;
-  const int sys = blockIdx.x >> 1, half = blockIdx.x & 1;
-  const SysDesc s = systems[sys];
   for (int i = threadIdx.x; i < 16 * NDOF * NDOF; i += FT_NT) L.Kl[i] = Kel[i];
-  const int m = (s.nyb - 1) >> 1;
-  const double mloc =
-      half == 0 ? factor_chain<NDOF>(g, s, 0, 1, m, 0, true, E, flag, out64, out32, err, L)
-                : factor_chain<NDOF>(g, s, s.nyb - 1, -1, s.nyb - 1 - m, m + 1, true,
-                                     E, flag, out64, out32, err, L);
-  const double mm = fac_wg_max(mloc, L);
-  if (metric != nullptr && threadIdx.x == 0) metric[nsys + blockIdx.x] = mm;
+  const int q0 = pack[blockIdx.x], q1 = pack[blockIdx.x + 1];
+  for (int q = q0; q < q1; ++q) {
+    const int item = pack[gridDim.x + 1 + q];
+    const int sys = item >> 1, half = item & 1;
+    const SysDesc s = systems[sys];
+    const int m = (s.nyb - 1) >> 1;
+    __syncthreads();                          // (the previous chain's LDS)
+    const double mloc =
+        half == 0 ? factor_chain<NDOF>(g, s, 0, 1, m, 0, true, E, flag, out64, out32, err, L)
+                  : factor_chain<NDOF>(g, s, s.nyb - 1, -1, s.nyb - 1 - m, m + 1, true,
+                                       E, flag, out64, out32, err, L);
+    const double mm = fac_wg_max(mloc, L);
+    if (metric != nullptr && threadIdx.x == 0) metric[nsys + item] = mm;
+  }
 }
 
 // Load the inverse block of a record (layout as in fac_rec) into LDS (row
@@ -1491,14 +1500,15 @@ k_eig_start(Geom g, const SysDesc* __restrict__ systems,
 // (direct-to-LDS loads) and its vector row (Z forward, the forward Y
 // backward) is held in registers.
 template <bool BWD>
-__global__ void __launch_bounds__(EG_NT)
-k_eig_chain(Geom g, const SysDesc* __restrict__ systems,
-            const double* __restrict__ E, const uint8_t* __restrict__ dflag,
-            const double* __restrict__ Me, const double* __restrict__ Sinv,
-            const double* __restrict__ Xw, double* __restrict__ Yw,
-            double* __restrict__ Zw, int m, const EigState* __restrict__ st) {
-  __shared__ __align__(16) double raw[EG_RAW];
-  const int sys = blockIdx.x >> 1, h = blockIdx.x & 1;
+__device__ void eig_chain_item(const Geom& g, const SysDesc* __restrict__ systems,
+                               const double* __restrict__ E,
+                               const uint8_t* __restrict__ dflag,
+                               const double* __restrict__ Me,
+                               const double* __restrict__ Sinv,
+                               const double* __restrict__ Xw, double* __restrict__ Yw,
+                               double* __restrict__ Zw, int m,
+                               const EigState* __restrict__ st, int sys, int h,
+                               double* raw) {
   if (st[sys].done) return;
   const SysDesc s = systems[sys];
   const int tid = threadIdx.x;
@@ -1730,6 +1740,26 @@ k_eig_chain(Geom g, const SysDesc* __restrict__ systems,
     }
 }
 
+// Workgroups take their (neighbourhood, chain) items from pack (see
+// chain_items): one workgroup per CU covers every chain.
+template <bool BWD>
+__global__ void __launch_bounds__(EG_NT)
+k_eig_chain(Geom g, const SysDesc* __restrict__ systems,
+            const double* __restrict__ E, const uint8_t* __restrict__ dflag,
+            const double* __restrict__ Me, const double* __restrict__ Sinv,
+            const double* __restrict__ Xw, double* __restrict__ Yw,
+            double* __restrict__ Zw, int m, const EigState* __restrict__ st,
+            const int* __restrict__ pack) {
+  __shared__ __align__(16) double raw[EG_RAW];
+  const int q0 = pack[blockIdx.x], q1 = pack[blockIdx.x + 1];
+  for (int q = q0; q < q1; ++q) {
+    const int item = pack[gridDim.x + 1 + q];
+    eig_chain_item<BWD>(g, systems, E, dflag, Me, Sinv, Xw, Yw, Zw, m, st,
+                        item >> 1, item & 1, raw);
+    __syncthreads();
+  }
+}
+
 // M-orthonormalisation of Y by Cholesky QR into X (twice at a
 // Rayleigh-Ritz step), and Rayleigh-Ritz with A on span(X): the Ritz
 // vectors replace X, ascending, and the Ritz values that decide the
@@ -1937,12 +1967,57 @@ k_eig_select(const SysDesc* __restrict__ systems, const double* __restrict__ Xw,
 
 // ---------------------------------------------------------------- launchers
 
+// Work items of the twisted chain kernels: item 2 i + h is chain h of
+// system i (h = 0: node rows 0..m with the middle row m = (nyb - 1) / 2,
+// h = 1: rows nyb-1..m).  They are packed onto at most ncu workgroups,
+// longest first onto the least loaded one (cost: rows x (nxb^2 + 64^2), the
+// constant standing for a step's fixed latency), so that on a mesh whose
+// boundary systems are smaller, short chains share a workgroup and one
+// workgroup per CU covers all.  pack: per workgroup the first item's
+// position (P + 1 offsets), then the items; returns P.
+int chain_items(const std::vector<SysDesc>& sys, int ncu, std::vector<int>& pack) {
+  struct It {
+    double cost;
+    int item;
+  };
+  std::vector<It> its;
+  for (size_t i = 0; i < sys.size(); ++i) {
+    const int m = (sys[i].nyb - 1) / 2;
+    for (int h = 0; h < 2; ++h) {
+      const int rows = h == 0 ? m + 1 : sys[i].nyb - m;
+      its.push_back({(double)rows * ((double)sys[i].nxb * sys[i].nxb + 4096.0),
+                     (int)(2 * i + h)});
+    }
+  }
+  std::stable_sort(its.begin(), its.end(),
+                   [](const It& a, const It& b) { return a.cost > b.cost; });
+  const int P = std::max(1, std::min(ncu, (int)its.size()));
+  std::vector<double> load(P, 0.0);
+  std::vector<std::vector<int>> bins(P);
+  for (const It& it : its) {
+    int best = 0;
+    for (int b = 1; b < P; ++b)
+      if (load[b] < load[best]) best = b;
+    load[best] += it.cost;
+    bins[best].push_back(it.item);
+  }
+  pack.assign(P + 1 + its.size(), 0);
+  int q = 0;
+  for (int b = 0; b < P; ++b) {
+    pack[b] = q;
+    for (int it : bins[b]) pack[P + 1 + q++] = it;
+  }
+  pack[P] = q;
+  return P;
+}
+
 void launch_factor_elastic(const Geom& g, const SysDesc* sys, int nsys,
                            const double* E, const uint8_t* mask,
                            const double* Ke, double* out64, float* out32,
-                           double* metric, int* err, hipStream_t s) {
-  hipLaunchKernelGGL(k_factor_twisted<2>, dim3(2 * nsys), dim3(FT_NT), 0, s, g,
-                     sys, nsys, E, mask, Ke, out64, out32, metric, err);
+                           double* metric, int* err, const int* pack, int npack,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_factor_twisted<2>, dim3(npack), dim3(FT_NT), 0, s, g,
+                     sys, nsys, E, mask, Ke, out64, out32, metric, err, pack);
   hipLaunchKernelGGL(k_factor_middle<2>, dim3(nsys), dim3(FT_NT), 0, s, g, sys,
                      nsys, E, mask, Ke, out64, out32, metric, err);
 }
@@ -1950,10 +2025,10 @@ void launch_factor_elastic(const Geom& g, const SysDesc* sys, int nsys,
 void launch_factor_heat(const Geom& g, const SysDesc* sys, int nsys,
                         const double* E, const uint8_t* dflag,
                         const double* Cel, double* out, int* err,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_factor_twisted<1>, dim3(2 * nsys), dim3(FT_NT), 0, s, g,
+                        const int* pack, int npack, hipStream_t s) {
+  hipLaunchKernelGGL(k_factor_twisted<1>, dim3(npack), dim3(FT_NT), 0, s, g,
                      sys, nsys, E, dflag, Cel, out, (float*)nullptr,
-                     (double*)nullptr, err);
+                     (double*)nullptr, err, pack);
   hipLaunchKernelGGL(k_factor_middle<1>, dim3(nsys), dim3(FT_NT), 0, s, g, sys,
                      nsys, E, dflag, Cel, out, (float*)nullptr, (double*)nullptr,
                      err);
@@ -1985,16 +2060,17 @@ void launch_heat_eigen(const Geom& g, const SysDesc* sys, int nsys,
                        double* Y, double* Z, int m, int kmax, int maxit,
                        int rr_every, double lim, double tol, void* state,
                        int* d_count, int* h_count, double* psi, float* psi32,
-                       double* lam, int* nsel, int* cap, int* err, hipStream_t s) {
+                       double* lam, int* nsel, int* cap, int* err,
+                       const int* pack, int npack, hipStream_t s) {
   EigParams p{m, kmax, maxit, rr_every, lim, tol};
   EigState* st = static_cast<EigState*>(state);
   hipLaunchKernelGGL(k_eig_start, dim3(nsys), dim3(EG_NT), 0, s, g, sys, dflag, X, m, st);
   bool first_rr = true;
   for (int it = 0; it < maxit; ++it) {
-    hipLaunchKernelGGL(k_eig_chain<false>, dim3(2 * nsys), dim3(EG_NT), 0, s, g,
-                       sys, E, dflag, Me, Sinv, X, Y, Z, m, st);
-    hipLaunchKernelGGL(k_eig_chain<true>, dim3(2 * nsys), dim3(EG_NT), 0, s, g,
-                       sys, E, dflag, Me, Sinv, X, Y, Z, m, st);
+    hipLaunchKernelGGL(k_eig_chain<false>, dim3(npack), dim3(EG_NT), 0, s, g,
+                       sys, E, dflag, Me, Sinv, X, Y, Z, m, st, pack);
+    hipLaunchKernelGGL(k_eig_chain<true>, dim3(npack), dim3(EG_NT), 0, s, g,
+                       sys, E, dflag, Me, Sinv, X, Y, Z, m, st, pack);
     const bool rr = ((it + 1) % rr_every == 0) || (it + 1 == maxit);
     // X = Y L^{-T} with L L^T = Y^T M Y (in place with src = dst = X)
     auto orth_pass = [&](const double* src, double* dst) {

@@ -43,12 +43,13 @@ void launch_dot(long long, const double*, const double*, double*,
                 unsigned int*, double*, hipStream_t);
 void launch_mask(long long, const uint8_t*, double*, hipStream_t);
 // k_local.hip
+int chain_items(const std::vector<SysDesc>&, int ncu, std::vector<int>& pack);
 void launch_factor_elastic(const Geom&, const SysDesc*, int, const double*,
                            const uint8_t*, const double*, double*, float*,
-                           double*, int*, hipStream_t);
+                           double*, int*, const int*, int, hipStream_t);
 void launch_factor_heat(const Geom&, const SysDesc*, int, const double*,
                         const uint8_t*, const double*, double*, int*,
-                        hipStream_t);
+                        const int*, int, hipStream_t);
 void launch_level1(const Level1Args&, int nsys, hipStream_t);
 void launch_level1_batch(const Level1Args*, const int*, int, int, int, hipStream_t);
 bool level1_fits(int bs, int nb, bool fp32);
@@ -56,7 +57,7 @@ void launch_heat_eigen(const Geom&, const SysDesc*, int, const double*,
                        const uint8_t*, const double*, const double*,
                        const double*, double*, double*, double*, int, int, int,
                        int, double, double, void*, int*, int*, double*, float*,
-                       double*, int*, int*, int*, hipStream_t);
+                       double*, int*, int*, int*, const int*, int, hipStream_t);
 size_t eig_state_bytes();
 // k_coarse.hip
 
@@ -161,6 +162,11 @@ struct msp_handle {
   uint8_t *d_mask = nullptr, *d_dflag = nullptr;
   double* d_E = nullptr;
   SysDesc *d_subs = nullptr, *d_omegas = nullptr;
+  // chains of the twisted kernels packed onto workgroups (chain_items)
+  std::vector<int> sub_pack_h, om_pack_h;
+  int* d_sub_pack = nullptr;
+  int* d_om_pack = nullptr;
+  int sub_npack = 0, om_npack = 0;
   SysDesc* d_sys_grid = nullptr;   // subdomain grid cell -> its system (nxb 0: none)
   double* d_S64 = nullptr;         // FP64 inverse blocks (always)
   float* d_S32 = nullptr;          // FP32 copy (precision 1)
@@ -476,7 +482,7 @@ extern "C" const char* msp_last_error(const msp_handle* h) {
 extern "C" msp_status msp_destroy(msp_handle* h) {
   if (!h) return MSP_OK;
   void* bufs[] = {h->d_elem, h->d_mask, h->d_dflag, h->d_E, h->d_subs,
-                  h->d_omegas, h->d_sys_grid, h->d_S64, h->d_S32, h->d_metric,
+                  h->d_omegas, h->d_sys_grid, h->d_sub_pack, h->d_om_pack, h->d_S64, h->d_S32, h->d_metric,
                   h->d_use64, h->d_lsol, h->d_gmid, h->d_Som,
                   h->d_X, h->d_Y, h->d_Z, h->d_psi, h->d_psi32, h->d_lam, h->d_nsel,
                   h->d_cap, h->d_cn, h->d_col_node, h->d_pairs, h->d_W,
@@ -649,6 +655,17 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
   A(dalloc(&h->d_subs, h->subs.size()));
   A(dalloc(&h->d_omegas, h->omegas.size()));
   A(dalloc(&h->d_sys_grid, h->sub_grid.size()));
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        ncu <= 0)
+      ncu = 256;
+    h->sub_npack = chain_items(h->subs, ncu, h->sub_pack_h);
+    h->om_npack = chain_items(h->omegas, ncu, h->om_pack_h);
+  }
+  A(dalloc(&h->d_sub_pack, h->sub_pack_h.size()));
+  A(dalloc(&h->d_om_pack, h->om_pack_h.size()));
   // the preconditioner's buffers are allocated by the first setup
   A(dalloc(&h->d_x, nd));
   A(dalloc(&h->d_r, nd));
@@ -689,6 +706,8 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
   C(hipMemcpy(h->d_dflag, dflag.data(), nn, hipMemcpyHostToDevice));
   C(hipMemcpy(h->d_subs, h->subs.data(), h->subs.size() * sizeof(SysDesc), hipMemcpyHostToDevice));
   C(hipMemcpy(h->d_omegas, h->omegas.data(), h->omegas.size() * sizeof(SysDesc), hipMemcpyHostToDevice));
+  C(hipMemcpy(h->d_sub_pack, h->sub_pack_h.data(), h->sub_pack_h.size() * sizeof(int), hipMemcpyHostToDevice));
+  C(hipMemcpy(h->d_om_pack, h->om_pack_h.data(), h->om_pack_h.size() * sizeof(int), hipMemcpyHostToDevice));
   {
     std::vector<SysDesc> sg(h->sub_grid.size());
     for (size_t i = 0; i < sg.size(); ++i)
@@ -877,16 +896,17 @@ extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
   int tk = timer_begin(h, KT_FACTOR, s);
   launch_factor_elastic(g, h->d_subs, (int)h->subs.size(), h->d_E, h->d_mask,
                         Ke, h->d_S64, h->fp32 ? h->d_S32 : nullptr,
-                        h->d_metric, h->d_err, s);
+                        h->d_metric, h->d_err, h->d_sub_pack, h->sub_npack, s);
   timer_end(h, KT_FACTOR, tk, s);
   launch_factor_heat(g, h->d_omegas, (int)h->omegas.size(), h->d_E,
-                     h->d_dflag, Ce, h->d_Som, h->d_err, s);
+                     h->d_dflag, Ce, h->d_Som, h->d_err, h->d_om_pack, h->om_npack, s);
   tk = timer_begin(h, KT_EIGEN, s);
   launch_heat_eigen(g, h->d_omegas, (int)h->omegas.size(), h->d_E, h->d_dflag,
                     Ae, Me, h->d_Som, h->d_X, h->d_Y, h->d_Z, m, kmax,
                     kEigMaxIt, kEigRR, h->desc.eig_tau / (h->H * h->H), kEigTol,
                     h->d_eig_state, (int*)h->d_cnt + 4, h->h_int + 8,
-                    h->d_psi, h->d_psi32, h->d_lam, h->d_nsel, h->d_cap, h->d_err, s);
+                    h->d_psi, h->d_psi32, h->d_lam, h->d_nsel, h->d_cap, h->d_err,
+                    h->d_om_pack, h->om_npack, s);
   timer_end(h, KT_EIGEN, tk, s);
   HIPCHK(h, hipGetLastError());
   const size_t nom = h->omegas.size();
