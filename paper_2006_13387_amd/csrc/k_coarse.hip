@@ -96,16 +96,27 @@ k_coarse_kphi(Geom g, const CoarseNode* __restrict__ cnodes,
 
 // K_0 block of coarse nodes (l, l2): K0[a][b] = Phi_a^T W_b over the
 // intersection of omega_l and omega_l2.  One workgroup per ordered pair.
+// Chunks of K0_CH nodes (2 K0_CH DOFs) of the pair's columns are staged in
+// LDS (rows of K0_LD doubles), and the block accumulates on the FP64 matrix
+// cores: wave w owns the 16 x 16 tiles w, w + 4, ... of the (up to 4 x 4)
+// tile grid; per MFMA 16x16x4, lane l supplies Phi_a(16R + l%16, k) and
+// W_b(k, 16C + l%16) for the chunk DOF k = 4K + l/16 and receives
+// (16R + l/16 + 4r, 16C + l%16) in register r.  Staged rows past na / nbc
+// hold stale values that reach only dropped rows and columns.
 constexpr int K0_CH = 32;      // nodes per LDS chunk
+constexpr int K0_LD = 2 * K0_CH + 2;   // LDS row stride (banks)
 constexpr int MAXCOL = 2 * 24 + 1;
+constexpr int K0_TR = (MAXCOL + 15) / 16;   // tile rows (and columns)
+typedef double k0_d4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(CK_NT)
 k_coarse_k0(Geom g, const CoarseNode* __restrict__ cnodes,
             const int2* __restrict__ pairs, const uint8_t* __restrict__ mask,
             const double* __restrict__ psi, const double* __restrict__ W,
             double* __restrict__ K0, int ldk, double invH) {
-  __shared__ double pa[MAXCOL * K0_CH * 2];
-  __shared__ double wb[MAXCOL * K0_CH * 2];
+  static_assert(CK_NT == 256, "four waves share the tiles");
+  __shared__ double pa[16 * K0_TR * K0_LD];
+  __shared__ double wb[16 * K0_TR * K0_LD];
   const int2 pr = pairs[blockIdx.x];
   const CoarseNode A = cnodes[pr.x];
   const CoarseNode B = cnodes[pr.y];
@@ -117,9 +128,12 @@ k_coarse_k0(Geom g, const CoarseNode* __restrict__ cnodes,
   const int nxi = max(0, xhi - xlo), nyi = max(0, yhi - ylo);
   const int ni = nxi * nyi;
   const int nwB = B.nxw * B.nyw;
-  double acc[(MAXCOL * MAXCOL + CK_NT - 1) / CK_NT];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tra = (na + 15) >> 4, trb = (nbc + 15) >> 4;
+  k0_d4 acc[K0_TR];
 #pragma unroll
-  for (int e = 0; e < (MAXCOL * MAXCOL + CK_NT - 1) / CK_NT; ++e) acc[e] = 0.0;
+  for (int u = 0; u < K0_TR; ++u) acc[u] = {0.0, 0.0, 0.0, 0.0};
   for (int c0 = 0; c0 < ni; c0 += K0_CH) {
     const int cn = min(K0_CH, ni - c0);
     __syncthreads();
@@ -131,8 +145,8 @@ k_coarse_k0(Geom g, const CoarseNode* __restrict__ cnodes,
         const int x = xlo + q % nxi, y = ylo + q / nxi;
         v = phi_at(g, A, psi, mask, a, x, y, invH);
       }
-      pa[(a * K0_CH + t) * 2] = v.x;
-      pa[(a * K0_CH + t) * 2 + 1] = v.y;
+      pa[a * K0_LD + 2 * t] = v.x;
+      pa[a * K0_LD + 2 * t + 1] = v.y;
     }
     for (int idx = threadIdx.x; idx < nbc * K0_CH; idx += CK_NT) {
       const int b = idx / K0_CH, t = idx - b * K0_CH;
@@ -145,27 +159,34 @@ k_coarse_k0(Geom g, const CoarseNode* __restrict__ cnodes,
         vx = wcol[2 * loc];
         vy = wcol[2 * loc + 1];
       }
-      wb[(b * K0_CH + t) * 2] = vx;
-      wb[(b * K0_CH + t) * 2 + 1] = vy;
+      wb[b * K0_LD + 2 * t] = vx;
+      wb[b * K0_LD + 2 * t + 1] = vy;
     }
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < (MAXCOL * MAXCOL + CK_NT - 1) / CK_NT; ++e) {
-      const int idx = threadIdx.x + e * CK_NT;
-      if (idx < na * nbc) {
-        const int a = idx / nbc, b = idx - (idx / nbc) * nbc;
-        double s = 0.0;
-        for (int t = 0; t < 2 * K0_CH; ++t) s += pa[a * 2 * K0_CH + t] * wb[b * 2 * K0_CH + t];
-        acc[e] += s;
+    for (int u = 0; u < K0_TR; ++u) {
+      const int tl = wave + 4 * u;
+      const int R = tl / K0_TR, C = tl - (tl / K0_TR) * K0_TR;
+      if (R < tra && C < trb) {
+        const double* ap = pa + (16 * R + li) * K0_LD + lk;
+        const double* bp = wb + (16 * C + li) * K0_LD + lk;
+#pragma unroll
+        for (int K = 0; K < 2 * K0_CH / 4; ++K)
+          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[4 * K], bp[4 * K], acc[u], 0, 0, 0);
       }
     }
   }
 #pragma unroll
-  for (int e = 0; e < (MAXCOL * MAXCOL + CK_NT - 1) / CK_NT; ++e) {
-    const int idx = threadIdx.x + e * CK_NT;
-    if (idx < na * nbc) {
-      const int a = idx / nbc, b = idx - (idx / nbc) * nbc;
-      K0[(long long)(A.col0 + a) * ldk + (B.col0 + b)] = acc[e];
+  for (int u = 0; u < K0_TR; ++u) {
+    const int tl = wave + 4 * u;
+    const int R = tl / K0_TR, C = tl - (tl / K0_TR) * K0_TR;
+    if (R < tra && C < trb) {
+      const int b = 16 * C + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = 16 * R + lk + 4 * r;
+        if (a < na && b < nbc) K0[(long long)(A.col0 + a) * ldk + (B.col0 + b)] = acc[u][r];
+      }
     }
   }
 }
@@ -202,33 +223,49 @@ __global__ void k_k0_scale(double* __restrict__ K0, int ldk,
 // register tiles by 16 x 16 threads (rows ti + 16u, columns tj + 16w); PU is
 // a compile-time constant, so the pivot's tile row and column are static.
 // A pivot at or below tol (scaled matrix) is dropped: its row and column
-// become zero, the rest is unchanged (a generalised inverse).
+// become zero, the rest is unchanged (a generalised inverse).  The owner
+// of the next pivot forms its reciprocal during the current update and
+// publishes it with the pivot row (0 for a dropped pivot), off the
+// barrier-to-barrier path.  On entry nv / inv hold (on the pivot's owner,
+// ti = tj = pt) the pivot and its reciprocal; on exit those of pivot p+1.
 template <int PU>
 __device__ __forceinline__ void gjp_pivot(double (&a)[4][4], int pt, int ti,
                                           int tj, double tol, double* pv,
+                                          double& nv, double& inv,
                                           int* __restrict__ dropped) {
   const int p = 16 * PU + pt;
   double* rowv = pv + (p & 1) * 2 * GJB;
   double* colv = rowv + GJB;
-  if (ti == pt) {
+  double* ipv = pv + 4 * GJB + (p & 1);
+  const bool prow = ti == pt, pcol = tj == pt;
+  if (prow) {
 #pragma unroll
     for (int w = 0; w < 4; ++w) rowv[tj + 16 * w] = a[PU][w];
+    if (pcol) {
+      const bool dr = !(nv > tol) || !finite(nv);
+      if (dr) atomicAdd(dropped, 1);
+      *ipv = dr ? 0.0 : inv;
+    }
   }
-  if (tj == pt) {
+  if (pcol) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) colv[ti + 16 * u] = a[u][PU];
   }
   __syncthreads();
-  const double piv = colv[p];
-  const bool drop = !(piv > tol) || !finite(piv);
-  if (drop && threadIdx.x == 0) atomicAdd(dropped, 1);
-  const double ip = drop ? 0.0 : 1.0 / piv;
+  const double ip = *ipv;
+  const bool drop = ip == 0.0;
   double cv[4], rv[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) cv[u] = colv[ti + 16 * u];
 #pragma unroll
   for (int w = 0; w < 4; ++w) rv[w] = rowv[tj + 16 * w] * ip;
-  const bool prow = ti == pt, pcol = tj == pt;
+  // the entry of pivot p + 1 first: (PU, PU), or (PU + 1, PU + 1) after the
+  // last pivot of this tile row
+  constexpr int PN = PU + 1 < 4 ? PU + 1 : PU;
+  const double e_pp = a[PU][PU] - cv[PU] * rv[PU];
+  const double e_nn = a[PN][PN] - cv[PN] * rv[PN];
+  nv = pt == 15 ? e_nn : e_pp;
+  inv = 1.0 / nv;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -248,9 +285,9 @@ __device__ __forceinline__ void gjp_pivot(double (&a)[4][4], int pt, int ti,
 
 template <int PU>
 __device__ __forceinline__ void gjp_tile(double (&a)[4][4], int ti, int tj,
-                                         double tol, double* pv,
-                                         int* __restrict__ dropped) {
-  for (int pt = 0; pt < 16; ++pt) gjp_pivot<PU>(a, pt, ti, tj, tol, pv, dropped);
+                                         double tol, double* pv, double& nv,
+                                         double& inv, int* __restrict__ dropped) {
+  for (int pt = 0; pt < 16; ++pt) gjp_pivot<PU>(a, pt, ti, tj, tol, pv, nv, inv, dropped);
 }
 
 // P = GJ inverse (generalised) of the diagonal block kb of A.
@@ -258,7 +295,7 @@ __global__ void __launch_bounds__(CK_NT)
 k_gj_pivot(double* __restrict__ A, int ld, int kb, double* __restrict__ P,
            double tol, int* __restrict__ dropped) {
   static_assert(GJB == 64 && CK_NT == 256, "pivot tiling: 16 x 16 threads, 4 x 4 tiles");
-  __shared__ double pv[4 * GJB];
+  __shared__ double pv[4 * GJB + 2];
   const int tid = threadIdx.x;
   const int tj = tid & 15, ti = tid >> 4;
   const long long base = (long long)kb * GJB;
@@ -268,10 +305,11 @@ k_gj_pivot(double* __restrict__ A, int ld, int kb, double* __restrict__ P,
 #pragma unroll
     for (int w = 0; w < 4; ++w)
       a[u][w] = A[(base + ti + 16 * u) * ld + base + tj + 16 * w];
-  gjp_tile<0>(a, ti, tj, tol, pv, dropped);
-  gjp_tile<1>(a, ti, tj, tol, pv, dropped);
-  gjp_tile<2>(a, ti, tj, tol, pv, dropped);
-  gjp_tile<3>(a, ti, tj, tol, pv, dropped);
+  double nv = a[0][0], inv = 1.0 / nv;
+  gjp_tile<0>(a, ti, tj, tol, pv, nv, inv, dropped);
+  gjp_tile<1>(a, ti, tj, tol, pv, nv, inv, dropped);
+  gjp_tile<2>(a, ti, tj, tol, pv, nv, inv, dropped);
+  gjp_tile<3>(a, ti, tj, tol, pv, nv, inv, dropped);
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
