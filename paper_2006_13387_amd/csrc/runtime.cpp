@@ -103,7 +103,7 @@ constexpr int kEigExtra = 8;         // subspace block m = kmax + kEigExtra
 // in the subspace error, so 1e-8 leaves the selected eigenvalues far more
 // accurate than the 1e-6 the coarse space needs.
 constexpr int kEigMaxIt = 48;
-constexpr int kEigRR = 4;
+constexpr int kEigRR = 3;
 constexpr double kEigTol = 1e-8;
 constexpr double kPivotDrop = 1e-12; // scaled K_0 pivots at or below: dropped
 constexpr int kChunk = 16;           // PCG iterations between host checks
