@@ -17,11 +17,19 @@ constexpr int MAXBS = 72;      // largest block row (DOFs) of a local system
 constexpr int MAXM = 32;       // largest eigen subspace block
 
 // Record of one node row of a first-level (elasticity) system with bs DOFs
-// per row: the inverse Schur block in 16-byte column groups, columns
-// zero-padded to a multiple of 4 (FP64 copies hold column pairs,
-// element (i, j) at (j/2)*2*bs + 2*i + j%2; FP32 copies column quads,
-// element (i, j) at (j/4)*4*bs + 4*i + j%4), then the couplings F (bs x 6).
+// per row (bs even): the symmetric inverse Schur block in 16-byte column
+// groups, then the couplings F (bs x 6).
+//  * FP32 copies hold every column, zero-padded to a multiple of 4, in
+//    quads: element (i, j) at (j/4)*4*bs + 4*i + j%4; F at l1_cols(bs)*bs.
+//  * FP64 copies hold the lower part of each column pair p (columns 2p,
+//    2p+1, rows 2p..bs-1): element (i, j) with i >= 2(j/2) at
+//    l1_pair_off(bs, j/2) + 2*(i - 2*(j/2)) + j%2; the rest is read
+//    transposed.  F at l1_s64(bs).
+// Both use the record stride l1_rec(bs); an FP64 record's used part is
+// l1_s64(bs) + 6 bs.
 __host__ __device__ inline int l1_cols(int bs) { return (bs + 3) & ~3; }
+__host__ __device__ inline int l1_pair_off(int bs, int p) { return 2 * p * (bs - p + 1); }
+__host__ __device__ inline int l1_s64(int bs) { return l1_pair_off(bs, bs / 2); }
 
 // Record of one node row of a heat pencil factor (bs nodes per row): the
 // inverse Schur block column-major (bs^2), the couplings F of the row with

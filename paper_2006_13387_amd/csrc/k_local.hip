@@ -317,6 +317,10 @@ __host__ __device__ inline long long fac_rec(int ndof, int nxb) {
 __host__ __device__ inline long long fac_fpart(int ndof, int bs) {
   return ndof == 2 ? (long long)l1_cols(bs) * bs : (long long)bs * bs;
 }
+// the same for FP64 elasticity records (packed lower column pairs)
+__host__ __device__ inline long long fac_fpart64(int ndof, int bs) {
+  return ndof == 2 ? (long long)l1_s64(bs) : (long long)bs * bs;
+}
 
 // Inverse block of a record (layout as in fac_rec; padding columns zero).
 template <int NDOF>
@@ -330,10 +334,15 @@ __device__ __forceinline__ void fac_write_inverse(int bs, const double* S,
     return;
   }
   const int nc = l1_cols(bs);
-  for (int idx = threadIdx.x; idx < nc * bs; idx += FT_NT) {
-    const int jp = idx / (2 * bs), rem = idx - jp * (2 * bs);
-    const int i = rem >> 1, j = 2 * jp + (rem & 1);
-    o64[idx] = j < bs ? S[i * LDSTR + j] : 0.0;
+  // FP64: the symmetric part (X + X^T) / 2 of the computed inverse X (the
+  // exact inverse of a slightly perturbed block, so it stays positive
+  // definite where the raw lower triangle of an ill-conditioned X need not)
+  for (int p = 0; 2 * p < bs; ++p) {
+    const int off = l1_pair_off(bs, p);
+    for (int e = threadIdx.x; e < 2 * (bs - 2 * p); e += FT_NT) {
+      const int i = 2 * p + (e >> 1), j = 2 * p + (e & 1);
+      o64[off + e] = 0.5 * (S[i * LDSTR + j] + S[j * LDSTR + i]);
+    }
   }
   if (o32 != nullptr) {
     for (int idx = threadIdx.x; idx < nc * bs; idx += FT_NT) {
@@ -349,10 +358,10 @@ template <int NDOF>
 __device__ __forceinline__ void fac_write_coupling(int bs, bool coupled,
                                                    const FactorLds& L,
                                                    double* o64, float* o32) {
-  const long long fo = fac_fpart(NDOF, bs);
+  const long long fo = fac_fpart(NDOF, bs), fo64 = fac_fpart64(NDOF, bs);
   for (int idx = threadIdx.x; idx < bs * 3 * NDOF; idx += FT_NT) {
     const double v = coupled ? L.Bv[idx] : 0.0;
-    o64[fo + idx] = v;
+    o64[fo64 + idx] = v;
     if (o32 != nullptr) o32[fo + idx] = (float)v;
   }
 }
@@ -477,10 +486,16 @@ __device__ __forceinline__ void fac_load_inverse(int bs, const double* __restric
     }
     return;
   }
-  for (int idx = threadIdx.x; idx < l1_cols(bs) * bs; idx += FT_NT) {
-    const int jp = idx / (2 * bs), rem = idx - jp * (2 * bs);
-    const int i = rem >> 1, j = 2 * jp + (rem & 1);
-    if (j < bs) P[i * LDSTR + j] = o[idx];
+  // packed lower column pairs; the mirror entries written alike (the
+  // 2 x 2 diagonal blocks twice, with equal values)
+  for (int p = 0; 2 * p < bs; ++p) {
+    const int off = l1_pair_off(bs, p);
+    for (int e = threadIdx.x; e < 2 * (bs - 2 * p); e += FT_NT) {
+      const int i = 2 * p + (e >> 1), j = 2 * p + (e & 1);
+      const double v = o[off + e];
+      P[i * LDSTR + j] = v;
+      P[j * LDSTR + i] = v;
+    }
   }
 }
 
@@ -595,11 +610,17 @@ __host__ __device__ inline int l1_vec_elems(int bs, int nb) {
   return ((nb * bs + 3) & ~3) + l1_cols(bs) + 2 * 4 * MAXBS;
 }
 
+// elements of a record a pass reads (FP64: the packed block and F)
+template <typename T>
+__host__ __device__ inline int l1_used(int bs) {
+  return sizeof(T) == 8 ? l1_s64(bs) + 6 * bs : (int)l1_rec(bs);
+}
+
 template <typename T>
 __host__ __device__ inline L1Ring l1_ring(int bs, int nb) {
   L1Ring g;
   g.rec = (int)l1_rec(bs);
-  g.nch = (g.rec * (int)sizeof(T) + L1_CHUNK - 1) / L1_CHUNK;
+  g.nch = (l1_used<T>(bs) * (int)sizeof(T) + L1_CHUNK - 1) / L1_CHUNK;
   g.slot = g.nch * L1_CHUNK;
   const int vbytes = l1_vec_elems(bs, nb) * (int)sizeof(T);
   const int per_wave = (g.nch + L1_NLW - 1) / L1_NLW;
@@ -730,6 +751,41 @@ __device__ __forceinline__ T lds_gemv_group(const T* S, int bs, int i,
   return (a[0] + a[1]) + (a[2] + a[3]);
 }
 
+// The same over the FP64 packed layout (lower part of each column pair,
+// rows 2p..bs-1): for pair p = j0/2 + u, row i reads S(i, 2p) and
+// S(i, 2p+1) from row i of pair p when i >= 2p, else S(2p, i) and
+// S(2p+1, i) (component i%2) from rows 2p, 2p+1 of pair i/2.  Every lane
+// reads two doubles at addresses chosen by selects, so the two cases do not
+// diverge.  Pairs past the block (2p >= bs) weigh 0.
+template <int NJ>
+__device__ __forceinline__ double lds_gemv_sym(const double* S, int bs, int i,
+                                               const double* w, int j0, int n) {
+  constexpr int NU = NJ / 2;
+  static_assert(NJ % 4 == 0, "column groups hold whole quads");
+  const int q = i >> 1, comp = i & 1, ph = bs / 2 - 1;
+  const int uoff = l1_pair_off(bs, q) + comp;   // row 0 of pair i/2, component
+  double s0[NU], s1[NU];
+  double2 x[NU];
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int p = min(j0 / 2 + u, ph);
+    const bool lower = i >= 2 * p;
+    const int a0 = lower ? l1_pair_off(bs, p) + 2 * (i - 2 * p) : uoff + 2 * (2 * p - 2 * q);
+    const int a1 = lower ? a0 + 1 : a0 + 2;
+    s0[u] = S[a0];
+    s1[u] = S[a1];
+    x[u] = *reinterpret_cast<const double2*>(w + (2 * u < n ? j0 + 2 * u : 0));
+  }
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const double m = (2 * u < n && j0 + 2 * u < bs) ? 1.0 : 0.0;
+    a[(2 * u) & 3] += s0[u] * (m * x[u].x);
+    a[(2 * u + 1) & 3] += s1[u] * (m * x[u].y);
+  }
+  return (a[0] + a[1]) + (a[2] + a[3]);
+}
+
 typedef __attribute__((address_space(3))) void lds_void;
 
 // loader wave lw: DMA its chunks of the record of row k into the LDS slot
@@ -782,7 +838,7 @@ __device__ void level1_half(const Geom& g, const SysDesc& s, int half,
   const int bs = 2 * s.nxb;
   const int nb = s.nyb;
   const int ncols = l1_cols(bs);
-  const int fo = ncols * bs;                 // F part of a record
+  const int fo = sizeof(T) == 8 ? l1_s64(bs) : ncols * bs;   // F part of a record
   const int mid = (nb - 1) >> 1;
   const int L = half ? nb - mid : mid + 1;
   const int rec0 = half ? mid + 1 : 0;
@@ -960,9 +1016,13 @@ __device__ void level1_half(const Geom& g, const SysDesc& s, int half,
     // step c+1
     if (gemv) {
       if (c > 0 && tid < bs) v[jp * bs + tid] = fin_value(fin_load(jp, pp, tid), pfwd);
-      const T* S = reinterpret_cast<const T*>(lds + cur * ring.slot) + j0 * bs;
-      P[(c & 1) * (4 * MAXBS) + 4 * gi + gq] =
-          lds_gemv_group<T, L1_GMAX>(S, bs, gi, w + j0, jn);
+      const T* Sr = reinterpret_cast<const T*>(lds + cur * ring.slot);
+      if constexpr (sizeof(T) == 8)
+        P[(c & 1) * (4 * MAXBS) + 4 * gi + gq] =
+            lds_gemv_sym<L1_GMAX>(Sr, bs, gi, w, j0, jn);
+      else
+        P[(c & 1) * (4 * MAXBS) + 4 * gi + gq] =
+            lds_gemv_group<T, L1_GMAX>(Sr + j0 * bs, bs, gi, w + j0, jn);
     } else if (loader) {
       if (c + R - 1 < nsteps)
         l1_dma<T>(base, ring.rec, pos_of(c + R - 1), lds + prev * ring.slot,

@@ -2197,8 +2197,11 @@ extern "C" msp_status msp_query(msp_handle* h, int64_t* q) {
     // one application of the twisted sweep reads every row's record twice
     // (the middle row's once per chain) and each chain's middle coupling
     // once more
-    const long long ent = 2LL * s.nyb * l1_rec(2 * s.nxb) + 24LL * s.nxb;
+    // (FP64 records hold the packed lower column pairs of the block)
+    const int bs = 2 * s.nxb;
     const bool f64 = !h->fp32 || (i < h->use64_h.size() ? h->use64_h[i] != 0 : true);
+    const long long rec = f64 ? (long long)l1_s64(bs) + 6LL * bs : l1_rec(bs);
+    const long long ent = 2LL * s.nyb * rec + 24LL * s.nxb;
     l1_bytes += ent * (f64 ? 8 : 4);
   }
   q[6] = l1_bytes;
