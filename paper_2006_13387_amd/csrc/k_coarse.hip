@@ -430,7 +430,6 @@ constexpr int RS_CH = 4;       // bands of neighbourhood rows per coarse node
 constexpr int RS_NPT = 6;      // band nodes per thread (band <= RS_NT*RS_NPT)
 constexpr int RS_JC = 8;       // modes per load chunk
 constexpr int KMAXD = 24;
-static_assert(KMAXD % RS_JC == 0, "mode chunks must tile the mode cap");
 
 struct RsLds {
   double red[(2 * KMAXD + 1) * (RS_NT / 64)];
@@ -453,6 +452,8 @@ __device__ __forceinline__ void restrict_body(const RestrictArgs& a, int bid,
   const double* __restrict__ r = a.r;
   const double invH = a.invH;
   double* red = L.red;
+  // the coarse node's descriptor is read alongside the stop test
+  const CoarseNode cn = a.cn[bid / RS_CH];
   if (a.sc != nullptr) {
     if (a.check) {
       if (cg_check_done<RS_NT>(a.sc, a.part_upd, a.nb_upd, L.redc, &L.shi, bid == 0)) return;
@@ -460,7 +461,6 @@ __device__ __forceinline__ void restrict_body(const RestrictArgs& a, int bid,
       return;
     }
   }
-  const CoarseNode cn = a.cn[bid / RS_CH];
   const int band = bid % RS_CH;
   const int nm = cn.nmodes;
   const int ncol = 2 * nm + cn.nrot;
@@ -479,10 +479,11 @@ __device__ __forceinline__ void restrict_body(const RestrictArgs& a, int bid,
     okp[p] = loc < hi;
     locs[p] = okp[p] ? loc : lo;
   }
-  double pv[RS_JC][RS_NPT];
+  constexpr int JC = RS_JC;
+  T pv[JC][RS_NPT];       // in the element type: FP32 halves the registers
   auto load_chunk = [&](int j0) {
 #pragma unroll
-    for (int u = 0; u < RS_JC; ++u) {
+    for (int u = 0; u < JC; ++u) {
       const long long j = min(j0 + u, nm - 1);
 #pragma unroll
       for (int p = 0; p < RS_NPT; ++p) pv[u][p] = ps[j * nw + locs[p]];
@@ -507,26 +508,22 @@ __device__ __forceinline__ void restrict_body(const RestrictArgs& a, int bid,
   }
   const int w = threadIdx.x >> 6;
 #pragma unroll
-  for (int c = 0; c < KMAXD / RS_JC; ++c) {
-    const int j0 = c * RS_JC;
+  for (int c = 0; c < (KMAXD + JC - 1) / JC; ++c) {
+    const int j0 = c * JC;
     if (j0 >= nm) break;
     if (c > 0) load_chunk(j0);
-    double ax[RS_JC], ay[RS_JC];
 #pragma unroll
-    for (int u = 0; u < RS_JC; ++u) {
-      ax[u] = ay[u] = 0.0;
-#pragma unroll
-      for (int p = 0; p < RS_NPT; ++p) {
-        ax[u] += pv[u][p] * r0[p];
-        ay[u] += pv[u][p] * r1[p];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < RS_JC; ++u) {
+    for (int u = 0; u < JC; ++u) {
       const int j = j0 + u;
       if (j < nm) {
-        const double sx = wave_sum(ax[u]);
-        const double sy = wave_sum(ay[u]);
+        double ax = 0.0, ay = 0.0;
+#pragma unroll
+        for (int p = 0; p < RS_NPT; ++p) {
+          ax += (double)pv[u][p] * r0[p];
+          ay += (double)pv[u][p] * r1[p];
+        }
+        const double sx = wave_sum(ax);
+        const double sy = wave_sum(ay);
         if ((threadIdx.x & 63) == 0) {
           red[j * (RS_NT / 64) + w] = sx;
           red[(nm + j) * (RS_NT / 64) + w] = sy;
@@ -547,12 +544,12 @@ __device__ __forceinline__ void restrict_body(const RestrictArgs& a, int bid,
   }
 }
 
-__global__ void __launch_bounds__(RS_NT) k_restrict(RestrictArgs a) {
+// one kernel per element type, so that the FP32 one keeps few enough
+// registers for three workgroups per CU
+template <typename T>
+__global__ void __launch_bounds__(RS_NT, sizeof(T) == 4 ? 3 : 2) k_restrict(RestrictArgs a) {
   __shared__ RsLds L;
-  if (a.psi32 != nullptr)
-    restrict_body<float>(a, blockIdx.x, L);
-  else
-    restrict_body<double>(a, blockIdx.x, L);
+  restrict_body<T>(a, blockIdx.x, L);
 }
 
 __global__ void __launch_bounds__(RS_NT)
@@ -783,20 +780,31 @@ __device__ __forceinline__ void combine_body(const CombineCall& a, int bid,
   if (nh > 1) lv1 = ls[li1 >> 1];
   if (nh > 2) lv2 = ls[li2 >> 1];
   if (nh > 3) lv3 = ls[li3 >> 1];
-  // coarse part: the first chunk of every corner's modes at this node
+  // coarse part: every corner's modes at this node, one chunk of JC modes of
+  // all four corners at a time (the first chunk goes out with the loads above)
   constexpr int JC = CB_JC;
   T pv[4][JC];
   const T* pp[4];
+  int nmk[4];
+  auto load_chunk = [&](int j0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (j0 < nmk[k]) {
+#pragma unroll
+        for (int u = 0; u < JC; ++u)
+          pv[k][u] = pp[k][(long long)min(j0 + u, nmk[k] - 1) * L.cnw[k]];
+      }
+    }
+  };
+  int nmax = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int nm = L.cnm[k];
+    nmk[k] = L.cnm[k];
+    nmax = max(nmax, nmk[k]);
     pp[k] = psi_of<T>(ca.psi, ca.psi32) + L.cpsi[k] + (long long)(y - L.cy0[k]) * L.cnxw[k] +
             (x - L.cx0[k]);
-    if (nm > 0) {
-#pragma unroll
-      for (int u = 0; u < JC; ++u) pv[k][u] = pp[k][(long long)min(u, nm - 1) * L.cnw[k]];
-    }
   }
+  load_chunk(0);
   __syncthreads();
   double z0 = 0.0, z1 = 0.0;
   z0 += lv0.x;
@@ -807,42 +815,39 @@ __device__ __forceinline__ void combine_body(const CombineCall& a, int bid,
   z1 += lv2.y;
   z0 += lv3.x;
   z1 += lv3.y;
+  double s0[4] = {0.0, 0.0, 0.0, 0.0}, s1[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int j0 = 0; j0 < nmax; j0 += JC) {
+    if (j0 > 0) load_chunk(j0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int nm = nmk[k];
+      if (j0 >= nm) continue;
+      const double* c = L.c0[k];
+#pragma unroll
+      for (int u = 0; u < JC; ++u) {
+        const double w = j0 + u < nm ? pv[k][u] : 0.0;
+        s0[k] += w * c[min(j0 + u, nm - 1)];
+        s1[k] += w * c[nm + min(j0 + u, nm - 1)];
+      }
+    }
+  }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int nm = L.cnm[k];
+    const int nm = nmk[k];
     if (nm == 0) continue;
     const int ccx = cx + (k & 1), ccy = cy + (k >> 1);
     const double chi = chi_at(g, ccx, ccy, x, y);
     const double* c = L.c0[k];
-    double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-    for (int u = 0; u < JC; ++u) {
-      const double w = u < nm ? pv[k][u] : 0.0;
-      s0 += w * c[min(u, nm - 1)];
-      s1 += w * c[nm + min(u, nm - 1)];
-    }
-    for (int j0 = JC; j0 < nm; j0 += JC) {
-#pragma unroll
-      for (int u = 0; u < JC; ++u)
-        pv[k][u] = pp[k][(long long)min(j0 + u, nm - 1) * L.cnw[k]];
-#pragma unroll
-      for (int u = 0; u < JC; ++u) {
-        const double w = j0 + u < nm ? pv[k][u] : 0.0;
-        s0 += w * c[min(j0 + u, nm - 1)];
-        s1 += w * c[nm + min(j0 + u, nm - 1)];
-      }
-    }
-    s0 *= chi;
-    s1 *= chi;
+    double t0 = s0[k] * chi, t1 = s1[k] * chi;
     if (L.crot[k]) {
       const double rx = (x - ccx * g.sx) * g.h * ca.invH;
       const double ry = (y - ccy * g.sy) * g.h * ca.invH;
       const double cr = c[2 * nm];
-      s0 += -chi * ry * cr;
-      s1 += chi * rx * cr;
+      t0 += -chi * ry * cr;
+      t1 += chi * rx * cr;
     }
-    z0 += s0;
-    z1 += s1;
+    z0 += t0;
+    z1 += t1;
   }
   if (mk.x) z0 = 0.0;
   if (mk.y) z1 = 0.0;
@@ -943,7 +948,10 @@ void launch_k0_pinv(double* K0, int ldk, int nc, double* sdiag, double* P,
 }
 
 void launch_restrict(const RestrictArgs& a, int ncn, hipStream_t s) {
-  hipLaunchKernelGGL(k_restrict, dim3(ncn * RS_CH), dim3(RS_NT), 0, s, a);
+  if (a.psi32 != nullptr)
+    hipLaunchKernelGGL(k_restrict<float>, dim3(ncn * RS_CH), dim3(RS_NT), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_restrict<double>, dim3(ncn * RS_CH), dim3(RS_NT), 0, s, a);
 }
 
 void launch_restrict_batch(const RestrictArgs* tab, const int* start, int nent,
