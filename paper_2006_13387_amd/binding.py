@@ -16,6 +16,12 @@ LIB_PATH = os.path.join(HERE, "libmsp.so")
 
 MSP_OK = 0
 MSP_NOT_CONVERGED = 1
+MSP_E_INVALID = -1
+MSP_E_NOMEM = -2
+MSP_E_DEVICE = -3
+MSP_E_NOT_SPD = -4
+MSP_E_BREAKDOWN = -5
+MSP_E_STATE = -7
 STATUS_NAMES = {0: "MSP_OK", 1: "MSP_NOT_CONVERGED", -1: "MSP_E_INVALID",
                 -2: "MSP_E_NOMEM", -3: "MSP_E_DEVICE", -4: "MSP_E_NOT_SPD",
                 -5: "MSP_E_BREAKDOWN", -7: "MSP_E_STATE"}

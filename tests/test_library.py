@@ -65,3 +65,13 @@ def test_create_rejects_invalid_desc_without_touching_gpu():
     st = L.msp_create(ctypes.byref(msp.make_desc(bad3)),
                       ctypes.cast(mask, ctypes.c_void_p), ctypes.byref(h))
     assert st == -1
+
+
+def test_status_codes_match_header():
+    text = open(HEADER).read()
+    codes = dict((k, int(v)) for k, v in
+                 re.findall(r"\b(MSP_(?:OK|NOT_CONVERGED|E_[A-Z_]+))\s*=\s*(-?\d+)", text))
+    assert len(codes) == 8
+    for name, value in codes.items():
+        assert getattr(msp.binding, name) == value, name
+        assert msp.binding.STATUS_NAMES[value] == name
