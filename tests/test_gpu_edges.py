@@ -10,8 +10,8 @@
   iterations and u(0) = u(1) / Emin, the coarse dimension is identical.
 * The largest node row the first-level kernels take (36 nodes, 72 DOFs:
   70 x 70 elements, S = 35, overlap 1) and its 71-node coarse
-  neighbourhood rows; level-1 parity against the oracle and full solves
-  against a sparse direct solve.
+  neighbourhood rows; level-1, heat-mode and coarse-correction parity
+  against the oracle and full solves against a sparse direct solve.
 * The first row size refused (37 nodes): MSP_E_INVALID, no launch.
 """
 import numpy as np
@@ -119,8 +119,8 @@ def test_largest_row_level1_and_solve():
     p = _square(70, 35, 1, seed=91)
     assert _max_row_nodes(p) == 36                 # 72 DOFs per node row
     assert 2 * 35 + 1 <= 72                        # neighbourhood rows of 71 nodes
-    print(f"[edges] {p.name}: level-1 parity", flush=True)
-    h = dd.build_preconditioner(p.desc, p.rho, p.fixed, level="one")
+    print(f"[edges] {p.name}: level-1, heat-mode and coarse parity", flush=True)
+    h = dd.build_preconditioner(p.desc, p.rho, p.fixed)
     s = _solver(p)
     s.setup()
     rng = np.random.default_rng(8)
@@ -129,6 +129,24 @@ def test_largest_row_level1_and_solve():
     z = _host(s.apply_level1(_dev(r)))
     assert _rel(z[h.free], h.M.level1(r[h.free])) <= 1e-6
     assert np.all(z[p.fixed == 1] == 0.0)
+    # heat modes of every neighbourhood, the 71 x 71 one included.  A
+    # neighbourhood without clamped nodes has the eigenvalue 0 (constants);
+    # both solvers fix it only to rounding of the pencil's largest
+    # eigenvalue (order 10 at h = 1), so its absolute tolerance is 1e-13,
+    # far below the smallest nonzero selected eigenvalue (about 2e-6).
+    ci = s.coarse_info()
+    cs = h.coarse
+    H2 = dd.coarse_H(p.desc) ** 2
+    for l in range(len(cs.coarse_nodes)):
+        seen = cs.lam_seen[l][0] * H2
+        if np.any(np.abs(seen - p.desc["eig_tau"]) < 0.01 * p.desc["eig_tau"]):
+            continue
+        assert ci["n_modes"][l] == cs.n_modes[l, 0], l
+        ref = cs.eigvals[l][0]
+        assert np.allclose(ci["eigvals"][l][: len(ref)], ref, rtol=1e-6, atol=1e-13), l
+    assert ci["n_coarse"] == cs.Phi.shape[1]
+    zc = _host(s.apply_coarse(_dev(r)))
+    assert _rel(zc[h.free], h.M.coarse(r[h.free])) <= 1e-6
     ud = oracle.direct_solve(p.desc, p.rho, p.fixed, p.f)
     for precision in (0, 1):
         print(f"[edges] {p.name}: solve precision={precision}", flush=True)
