@@ -280,6 +280,8 @@ struct UpLds {
   double alpha;
 };
 
+constexpr int UP_NPT = 2;   // nodes per thread (fewer workgroups re-reducing the partials)
+
 // x += alpha p ; r -= alpha q ; partial sums of r.r.  alpha = (r.z)/(p.q)
 // from the partials of the combine and stiffness kernels, summed by every
 // workgroup in the same order; workgroup 0 records alpha and r.z.  Every
@@ -292,14 +294,20 @@ __device__ __forceinline__ void update_body(const UpdateArgs& a, int bid, UpLds&
   double spq = 0.0, srz = 0.0;
   for (int k = threadIdx.x; k < a.nb_mv; k += 256) spq += load_coherent(a.part_mv + k);
   for (int k = threadIdx.x; k < a.nb_comb; k += 256) srz += load_coherent(a.part_comb + k);
-  const long long i = (long long)bid * 256 + threadIdx.x;
-  const bool own = i < a.n2;
-  double2 xx = make_double2(0.0, 0.0), rr = xx, pp = xx, qq = xx;
-  if (own) {
-    xx = reinterpret_cast<double2*>(a.x)[i];
-    rr = reinterpret_cast<double2*>(a.r)[i];
-    pp = reinterpret_cast<const double2*>(a.p)[i];
-    qq = reinterpret_cast<const double2*>(a.q)[i];
+  long long i[UP_NPT];
+  bool own[UP_NPT];
+  double2 xx[UP_NPT], rr[UP_NPT], pp[UP_NPT], qq[UP_NPT];
+#pragma unroll
+  for (int k = 0; k < UP_NPT; ++k) {
+    i[k] = ((long long)bid * UP_NPT + k) * 256 + threadIdx.x;
+    own[k] = i[k] < a.n2;
+    xx[k] = rr[k] = pp[k] = qq[k] = make_double2(0.0, 0.0);
+    if (own[k]) {
+      xx[k] = reinterpret_cast<double2*>(a.x)[i[k]];
+      rr[k] = reinterpret_cast<double2*>(a.r)[i[k]];
+      pp[k] = reinterpret_cast<const double2*>(a.p)[i[k]];
+      qq[k] = reinterpret_cast<const double2*>(a.q)[i[k]];
+    }
   }
   const double2 sums = block_sum2<256>(spq, srz, L.red);
   const double pq = sums.x, rz = sums.y;
@@ -323,14 +331,16 @@ __device__ __forceinline__ void update_body(const UpdateArgs& a, int bid, UpLds&
   const double alpha = L.alpha;
   if (!finite(alpha)) return;
   double acc = 0.0;
-  if (own) {
-    xx.x += alpha * pp.x;
-    xx.y += alpha * pp.y;
-    rr.x -= alpha * qq.x;
-    rr.y -= alpha * qq.y;
-    reinterpret_cast<double2*>(a.x)[i] = xx;
-    reinterpret_cast<double2*>(a.r)[i] = rr;
-    acc = rr.x * rr.x + rr.y * rr.y;
+#pragma unroll
+  for (int k = 0; k < UP_NPT; ++k) {
+    if (!own[k]) continue;
+    xx[k].x += alpha * pp[k].x;
+    xx[k].y += alpha * pp[k].y;
+    rr[k].x -= alpha * qq[k].x;
+    rr[k].y -= alpha * qq[k].y;
+    reinterpret_cast<double2*>(a.x)[i[k]] = xx[k];
+    reinterpret_cast<double2*>(a.r)[i[k]] = rr[k];
+    acc += rr[k].x * rr[k].x + rr[k].y * rr[k].y;
   }
   const double s = block_sum<256>(acc, L.red);
   if (threadIdx.x == 0) a.part[bid] = s;
@@ -554,7 +564,7 @@ void launch_residual(const Geom& g, int ty, const double* Ke, const double* E,
                      matvec_blocks(g, ty), slot);
 }
 
-int update_blocks(long long n) { return (int)((n / 2 + 255) / 256); }
+int update_blocks(long long n) { return (int)((n / 2 + 256 * UP_NPT - 1) / (256 * UP_NPT)); }
 
 UpdateArgs update_args(long long n, double* x, double* r, const double* p,
                        const double* q, CGScalars* sc, double* alpha_hist,
