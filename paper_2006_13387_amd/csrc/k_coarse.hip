@@ -367,6 +367,16 @@ k_gj_update(double* __restrict__ A, int ld, int kb,
     }
     return;
   }
+  // this thread's 4 x 4 of A_ij, read now so that the read overlaps the
+  // staging and the product
+  const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+  double aij[4][4];
+  if (ib != kb) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) aij[a][b] = A[(ibase + tr + a) * ld + jbase + tc + b];
+  }
   // Ls = (ib == kb) ? P : Lp_i ; Rs = Rp_j
   for (int idx = tid; idx < GJB * GJB; idx += CK_NT) {
     const int i = idx / GJB, j = idx - i * GJB;
@@ -375,7 +385,6 @@ k_gj_update(double* __restrict__ A, int ld, int kb,
   }
   __syncthreads();
   // each thread: 4 rows x 4 cols of the tile
-  const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
   double acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -398,7 +407,7 @@ k_gj_update(double* __restrict__ A, int ld, int kb,
     for (int b = 0; b < 4; ++b) {
       double* dst = &A[(ibase + tr + a) * ld + jbase + tc + b];
       if (ib == kb) *dst = acc[a][b];              // P A_kj
-      else *dst = *dst - acc[a][b];                // A_ij - Lp_i A_kj
+      else *dst = aij[a][b] - acc[a][b];           // A_ij - Lp_i A_kj
     }
 }
 
