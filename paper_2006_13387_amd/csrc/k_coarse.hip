@@ -367,15 +367,20 @@ k_gj_update(double* __restrict__ A, int ld, int kb,
     }
     return;
   }
-  // this thread's 4 x 4 of A_ij, read now so that the read overlaps the
-  // staging and the product
-  const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+  // The product on FP64 matrix cores: wave w takes rows 16w..16w+15 of the
+  // tile and all four 16-column tiles; per MFMA 16x16x4, lane l supplies
+  // Ls(16w + l%16, 4K + l/16) and Rs(4K + l/16, 16C + l%16) and holds
+  // C(16w + l/16 + 4r, 16C + l%16) in register r.  This lane's entries of
+  // A_ij are read first so that the read overlaps the staging and the
+  // product.
+  const int wave = tid >> 6, li = tid & 15, lk = (tid & 63) >> 4;
   double aij[4][4];
   if (ib != kb) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int C = 0; C < 4; ++C)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) aij[a][b] = A[(ibase + tr + a) * ld + jbase + tc + b];
+      for (int r = 0; r < 4; ++r)
+        aij[C][r] = A[(ibase + 16 * wave + lk + 4 * r) * ld + jbase + 16 * C + li];
   }
   // Ls = (ib == kb) ? P : Lp_i ; Rs = Rp_j
   for (int idx = tid; idx < GJB * GJB; idx += CK_NT) {
@@ -384,30 +389,26 @@ k_gj_update(double* __restrict__ A, int ld, int kb,
     Rs[i * (GJB + 1) + j] = Rp[(long long)i * ld + jbase + j];
   }
   __syncthreads();
-  // each thread: 4 rows x 4 cols of the tile
-  double acc[4][4];
+  static_assert(GJB == 64 && CK_NT == 256, "four waves of 16-row strips");
+  k0_d4 acc[4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int C = 0; C < 4; ++C) acc[C] = {0.0, 0.0, 0.0, 0.0};
+  const double* la = Ls + (16 * wave + li) * (GJB + 1) + lk;
+  const double* rb = Rs + lk * (GJB + 1) + li;
+#pragma unroll 4
+  for (int K = 0; K < GJB / 4; ++K) {
+    const double av = la[4 * K];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-  for (int t = 0; t < GJB; ++t) {
-    double lv[4], rv[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) lv[a] = Ls[(tr + a) * (GJB + 1) + t];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) rv[b] = Rs[t * (GJB + 1) + tc + b];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] += lv[a] * rv[b];
+    for (int C = 0; C < 4; ++C)
+      acc[C] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, rb[4 * K * (GJB + 1) + 16 * C], acc[C], 0, 0, 0);
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int C = 0; C < 4; ++C)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      double* dst = &A[(ibase + tr + a) * ld + jbase + tc + b];
-      if (ib == kb) *dst = acc[a][b];              // P A_kj
-      else *dst = aij[a][b] - acc[a][b];           // A_ij - Lp_i A_kj
+    for (int r = 0; r < 4; ++r) {
+      double* dst = &A[(ibase + 16 * wave + lk + 4 * r) * ld + jbase + 16 * C + li];
+      if (ib == kb) *dst = acc[C][r];              // P A_kj
+      else *dst = aij[C][r] - acc[C][r];           // A_ij - Lp_i A_kj
     }
 }
 
