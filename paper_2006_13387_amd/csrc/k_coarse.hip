@@ -335,12 +335,26 @@ k_gj_panel(const double* __restrict__ A, int ld, int kb,
     Rp[(long long)i * ld + ibase + j] = A[(kbase + i) * ld + ibase + j];   // A_kj, j-block ib
   }
   __syncthreads();
-  for (int idx = tid; idx < GJB * GJB; idx += CK_NT) {
-    const int i = idx / GJB, j = idx - i * GJB;
-    double s = 0.0;
-    for (int t = 0; t < GJB; ++t) s += As[i * (GJB + 1) + t] * Ps[t * GJB + j];
-    Lp[(ibase + i) * GJB + j] = s;
+  // Lp_i on FP64 matrix cores, the operand and result layout of the tile
+  // update below: wave w, rows 16w..16w+15, all four 16-column tiles
+  const int wave = tid >> 6, li = tid & 15, lk = (tid & 63) >> 4;
+  k0_d4 acc[4];
+#pragma unroll
+  for (int C = 0; C < 4; ++C) acc[C] = {0.0, 0.0, 0.0, 0.0};
+  const double* la = As + (16 * wave + li) * (GJB + 1) + lk;
+  const double* pb = Ps + lk * GJB + li;
+#pragma unroll 4
+  for (int K = 0; K < GJB / 4; ++K) {
+    const double av = la[4 * K];
+#pragma unroll
+    for (int C = 0; C < 4; ++C)
+      acc[C] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, pb[4 * K * GJB + 16 * C], acc[C], 0, 0, 0);
   }
+#pragma unroll
+  for (int C = 0; C < 4; ++C)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      Lp[(ibase + 16 * wave + lk + 4 * r) * GJB + 16 * C + li] = acc[C][r];
 }
 
 // Tile update of block step k.  Grid (nblk, nblk) of 64 x 64 tiles.
