@@ -91,6 +91,11 @@ typedef struct {
   int32_t coarse_rank;     /* numerical rank of K_0                          */
   int32_t cap_hits;        /* neighbourhoods with more than kmax modes below  */
   int32_t fp64_subdomains; /* subdomains applied with FP64 inverse blocks     */
+  int32_t eig_unconverged; /* neighbourhoods whose heat eigen iteration hit
+                              its step limit before the Ritz values deciding
+                              the threshold settled (0 on a sound setup)     */
+  int32_t setup_reused;    /* 1: this solve ran with a setup built for
+                              earlier densities (lazy reuse, serving)       */
   double relres_true;      /* ||f - K u|| / ||f|| over free DOFs             */
   double relres_rec;       /* recursively updated residual at exit           */
   double compliance;       /* f^T u                                          */
@@ -150,6 +155,22 @@ msp_status msp_setup(msp_handle* h, hipStream_t stream);
 msp_status msp_solve(msp_handle* h, const double* f_dev, double* u_dev,
                      int32_t nrhs, int32_t warm, double rtol, int32_t maxit,
                      hipStream_t stream, msp_solve_info* info_host);
+
+/*
+ * Lazy reuse of the preconditioner across density updates (Section 1: the
+ * preconditioner is updated after a fixed number of optimisation steps, or
+ * once the iterations of the solver exceed a threshold).  With max_age > 0
+ * a setup built for earlier densities is kept for up to max_age further
+ * msp_set_densities calls: msp_solve (and the single-step applies, batches
+ * and serving) then run PCG on the new K(rho) preconditioned by the older
+ * setup, which is still symmetric positive definite, so the solution is
+ * that of the new system to rtol.  With iter_limit > 0, a solve on a reused
+ * setup that takes more than iter_limit iterations makes the next solve
+ * rebuild.  max_age = 0 (the default) rebuilds at every density change.
+ * msp_solve_info.setup_reused tells which solves ran on an older setup.
+ * Errors: MSP_E_INVALID for negative arguments.
+ */
+msp_status msp_set_reuse(msp_handle* h, int32_t max_age, int32_t iter_limit);
 
 /* ---- single steps of the hot path, for parity checks and profiling ---- */
 
@@ -289,8 +310,9 @@ msp_status msp_server_submit(msp_server* sv, int32_t run_id,
  * iterations for every solve in progress (a batched launch per iteration
  * kernel, as msp_batch_solve), while queued requests are admitted as slots
  * and memory allow, their densities and setup running on a second stream
- * at the same time; then finished solves move on (state -> adjoint ->
- * done).  n_completed receives the requests completed by this step.  Each
+ * at the same time (ordered after all work the caller queued on the stream
+ * before this call, so densities written there are seen); then finished
+ * solves move on (state -> adjoint -> done).  n_completed receives the requests completed by this step.  Each
  * solve's arithmetic is that of msp_solve on its run's handle with the
  * same warm start, whatever else is in progress.
  */
@@ -303,10 +325,18 @@ msp_status msp_server_step(msp_server* sv, hipStream_t stream,
 msp_status msp_server_result(msp_server* sv, int32_t ticket,
                              msp_solve_info* info2_host, double* latency_ms);
 
-/* 8 doubles: completed requests, p50 and p99 latency (ms), solves per
- * second (state and adjoint solves, first submission to last completion),
- * projected device bytes of resident runs, queued, active, chunks run. */
-msp_status msp_server_stats(const msp_server* sv, double* stats8_host);
+/* Lazy preconditioner reuse for every run of the server (msp_set_reuse's
+ * policy, applied to each run's handle; a run whose setup was evicted
+ * rebuilds).  The decision is taken when a request is admitted: its state
+ * and adjoint solves share one setup. */
+msp_status msp_server_set_reuse(msp_server* sv, int32_t max_age,
+                                int32_t iter_limit);
+
+/* Writes min(n, 10) doubles: completed requests, p50 and p99 latency (ms),
+ * solves per second (state and adjoint solves, first submission to last
+ * completion), projected device bytes of resident runs, queued, active,
+ * chunks run, setups built, setups reused. */
+msp_status msp_server_stats(const msp_server* sv, double* stats_host, int32_t n);
 
 #ifdef __cplusplus
 }

@@ -34,7 +34,7 @@ __all__ = [
     "clamp_all_mask", "point_load", "face_patch_load", "force_solid_disk",
     "connect_load_path",
     "config", "config_p", "batch_configs", "perturb", "perturb_seed",
-    "output_dof_load",
+    "output_dof_load", "probe_vector",
 ]
 
 
@@ -464,6 +464,14 @@ def output_dof_load(desc, rho, fixed, seed):
     f = np.zeros(n_dofs(desc))
     f[cand[int(rng.integers(len(cand)))]] = 1.0
     return f
+
+
+def probe_vector(fixed, seed):
+    """Seeded residual for single-step parity probes: standard normal on the
+    free DOFs, zero at clamped DOFs."""
+    r = np.random.default_rng(seed).standard_normal(len(fixed))
+    r[np.asarray(fixed) == 1] = 0.0
+    return r
 
 
 def perturb_seed(run, t):

@@ -43,6 +43,8 @@ class SolveInfo(ctypes.Structure):
                 ("n_coarse", ctypes.c_int32), ("coarse_rank", ctypes.c_int32),
                 ("cap_hits", ctypes.c_int32),
                 ("fp64_subdomains", ctypes.c_int32),
+                ("eig_unconverged", ctypes.c_int32),
+                ("setup_reused", ctypes.c_int32),
                 ("relres_true", ctypes.c_double),
                 ("relres_rec", ctypes.c_double),
                 ("compliance", ctypes.c_double), ("cond_est", ctypes.c_double),
@@ -61,7 +63,8 @@ EXPORTS = ["msp_create", "msp_destroy", "msp_last_error", "msp_set_densities",
            "msp_batch_last_error", "msp_batch_solve", "msp_batch_stats",
            "msp_server_create", "msp_server_destroy", "msp_server_last_error",
            "msp_server_add_run", "msp_server_submit", "msp_server_step",
-           "msp_server_result", "msp_server_stats"]
+           "msp_server_result", "msp_server_stats", "msp_set_reuse",
+           "msp_server_set_reuse"]
 
 KERNEL_NAMES = ["level1_apply", "cg_matvec", "heat_eigen", "combine",
                 "coarse_restrict", "local_factor"]
@@ -117,7 +120,9 @@ def load_library(path=LIB_PATH):
     L.msp_server_step.argtypes = [vp, vp, ctypes.POINTER(i32)]
     L.msp_server_result.argtypes = [vp, i32, ctypes.POINTER(SolveInfo),
                                     ctypes.POINTER(ctypes.c_double)]
-    L.msp_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.msp_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32]
+    L.msp_set_reuse.argtypes = [vp, i32, i32]
+    L.msp_server_set_reuse.argtypes = [vp, i32, i32]
     for name in EXPORTS:
         if name not in ("msp_last_error", "msp_batch_last_error",
                         "msp_server_last_error"):
@@ -202,6 +207,9 @@ class Solver:
 
     def setup(self):
         self._check(self.L.msp_setup(self.h, _stream()))
+
+    def set_reuse(self, max_age, iter_limit=0):
+        self._check(self.L.msp_set_reuse(self.h, int(max_age), int(iter_limit)))
 
     def solve(self, f, u=None, warm=False, rtol=1e-8, maxit=5000):
         import torch
@@ -400,11 +408,15 @@ class Server:
         self._keep.pop(ticket, None)
         return infos[0].as_dict(), infos[1].as_dict(), lat.value
 
+    def set_reuse(self, max_age, iter_limit=0):
+        self._check(self.L.msp_server_set_reuse(self.sv, int(max_age),
+                                                int(iter_limit)))
+
     def stats(self):
-        v = (ctypes.c_double * 8)()
-        self._check(self.L.msp_server_stats(self.sv, v))
+        v = (ctypes.c_double * 10)()
+        self._check(self.L.msp_server_stats(self.sv, v, 10))
         keys = ["completed", "p50_ms", "p99_ms", "solves_per_s", "hbm_bytes",
-                "queued", "active", "chunks"]
+                "queued", "active", "chunks", "setups_built", "setups_reused"]
         return dict(zip(keys, list(v)))
 
 

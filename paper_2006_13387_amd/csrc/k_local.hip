@@ -2114,18 +2114,22 @@ bool level1_fits(int bs, int nb, bool fp32) {
   return l1_fits<double>(bs, L) && (!fp32 || l1_fits<float>(bs, L));
 }
 
-void launch_heat_eigen(const Geom& g, const SysDesc* sys, int nsys,
-                       const double* E, const uint8_t* dflag, const double* Ae,
-                       const double* Me, const double* Sinv, double* X,
-                       double* Y, double* Z, int m, int kmax, int maxit,
-                       int rr_every, double lim, double tol, void* state,
-                       int* d_count, int* h_count, double* psi, float* psi32,
-                       double* lam, int* nsel, int* cap, int* err,
-                       const int* pack, int npack, hipStream_t s) {
+// Returns the number of neighbourhoods whose deciding Ritz values had not
+// settled when the iteration limit was reached (0 when all converged), or
+// -1 if a HIP call failed (the selection is then not launched).
+int launch_heat_eigen(const Geom& g, const SysDesc* sys, int nsys,
+                      const double* E, const uint8_t* dflag, const double* Ae,
+                      const double* Me, const double* Sinv, double* X,
+                      double* Y, double* Z, int m, int kmax, int maxit,
+                      int rr_every, double lim, double tol, void* state,
+                      int* d_count, int* h_count, double* psi, float* psi32,
+                      double* lam, int* nsel, int* cap, int* err,
+                      const int* pack, int npack, hipStream_t s) {
   EigParams p{m, kmax, maxit, rr_every, lim, tol};
   EigState* st = static_cast<EigState*>(state);
   hipLaunchKernelGGL(k_eig_start, dim3(nsys), dim3(EG_NT), 0, s, g, sys, dflag, X, m, st);
   bool first_rr = true;
+  int unconverged = nsys;
   for (int it = 0; it < maxit; ++it) {
     hipLaunchKernelGGL(k_eig_chain<false>, dim3(npack), dim3(EG_NT), 0, s, g,
                        sys, E, dflag, Me, Sinv, X, Y, Z, m, st, pack);
@@ -2153,14 +2157,18 @@ void launch_heat_eigen(const Geom& g, const SysDesc* sys, int nsys,
     if (rr) {
       first_rr = false;
       hipLaunchKernelGGL(k_eig_count, dim3(1), dim3(256), 0, s, st, nsys, d_count);
-      if (hipMemcpyAsync(h_count, d_count, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      if (hipGetLastError() != hipSuccess ||
+          hipMemcpyAsync(h_count, d_count, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
           hipStreamSynchronize(s) != hipSuccess)
-        break;
-      if (*h_count == 0) break;
+        return -1;
+      unconverged = *h_count;
+      if (unconverged == 0) break;
     }
   }
   hipLaunchKernelGGL(k_eig_select, dim3(nsys), dim3(EG_NT), 0, s, sys, X, p, st,
                      psi, psi32, lam, nsel, cap);
+  if (hipGetLastError() != hipSuccess) return -1;
+  return unconverged;
 }
 
 }  // namespace msp

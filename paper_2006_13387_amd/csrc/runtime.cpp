@@ -53,7 +53,7 @@ void launch_factor_heat(const Geom&, const SysDesc*, int, const double*,
 void launch_level1(const Level1Args&, int nsys, hipStream_t);
 void launch_level1_batch(const Level1Args*, const int*, int, int, int, hipStream_t);
 bool level1_fits(int bs, int nb, bool fp32);
-void launch_heat_eigen(const Geom&, const SysDesc*, int, const double*,
+int launch_heat_eigen(const Geom&, const SysDesc*, int, const double*,
                        const uint8_t*, const double*, const double*,
                        const double*, double*, double*, double*, int, int, int,
                        int, double, double, void*, int*, int*, double*, float*,
@@ -205,8 +205,7 @@ struct msp_handle {
          *part_res = nullptr;
   int nb_mv = 0, nb_upd = 0, nb_comb = 0;
   int nb_mv_max = 0;         // stiffness-product tiles of the smallest tile
-  int mv_ty = 8;             // node rows per stiffness-product tile
-  bool mv_tuned = false;
+  int mv_ty = 4;             // node rows per stiffness-product tile
   unsigned int* d_cnt = nullptr;   // counters of msp_vec_dot
   int* d_err = nullptr;
   // pinned host
@@ -215,7 +214,15 @@ struct msp_handle {
   double* h_dbl = nullptr;
 
   bool have_E = false, setup_ok = false;
+  // lazy reuse of the preconditioner (Section 1: update it after a fixed
+  // number of design steps, or once the solver's iterations exceed a
+  // threshold): densities generation now and at the last setup
+  long long dens_gen = 0, setup_gen = -1;
+  int reuse_max_age = 0;           // 0: every new density field rebuilds
+  int reuse_iter_limit = 0;        // 0: no iteration criterion
+  bool rebuild_due = false;        // a reused setup took too many iterations
   int nc = 0, ldk = 0, rank = 0, cap_hits = 0;
+  int eig_unconverged = 0;         // neighbourhoods stopped at the iteration limit
   std::vector<int> nsel_h;
   std::vector<double> lam_h;
   double t_setup_ms = 0.0;
@@ -531,7 +538,6 @@ static msp_status create_3d(const msp_problem_desc* d, const uint8_t* fixed,
   h->n_nodes = nn;
   h->n_dofs = 3 * nn;
   h->n_elems = (long long)g.nx * g.ny * g.nz;
-  h->mv_tuned = true;
   h->mask_h.assign(fixed, fixed + h->n_dofs);
   std::vector<uint8_t> nmask(nn);
   for (long long p = 0; p < nn; ++p)
@@ -561,6 +567,21 @@ static msp_status create_3d(const msp_problem_desc* d, const uint8_t* fixed,
   }
   *out = h;
   return MSP_OK;
+}
+
+// Stiffness-product tile height for this mesh: MSP_MV_TILE (4, 8 or 16)
+// if set, else the tallest tile that still gives at least four workgroups
+// per CU (4 when none does).  A function of the mesh alone, so every handle
+// of the same mesh (a served run rebuilt after eviction, a handle in a
+// batch) forms the p.q partial sums over the same tiles and gets the same
+// bits.  Taller tiles re-read fewer halo nodes and moduli.
+static int matvec_tile(const Geom& g) {
+  const char* env = std::getenv("MSP_MV_TILE");
+  if (env && (std::atoi(env) == 4 || std::atoi(env) == 8 || std::atoi(env) == 16))
+    return std::atoi(env);
+  if (matvec_blocks(g, 16) >= 4 * kNumCUs) return 16;
+  if (matvec_blocks(g, 8) >= 4 * kNumCUs) return 8;
+  return 4;
 }
 
 // Calls that need the preconditioner refuse 3D handles.
@@ -640,7 +661,7 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
   for (int i = 0; i < 16; ++i) h->Ce[i] = h->Ae[i] + sigma * h->Me[i];
 
   const long long nd = h->n_dofs, nn = h->n_nodes;
-  h->mv_ty = 8;                           // until the first densities
+  h->mv_ty = matvec_tile(g);
   h->nb_mv_max = matvec_blocks(g, 4);     // partial buffers fit any tile
   h->nb_mv = matvec_blocks(g, h->mv_ty);
   h->nb_upd = update_blocks(nd);
@@ -725,48 +746,6 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
   return MSP_OK;
 }
 
-// Stiffness-product tile height for this mesh: MSP_MV_TILE (4, 8 or 16)
-// if set, else the fastest over ten timed products of the tiles that still
-// give at least two workgroups per CU (4 always qualifies).  Once per
-// handle, at the first densities; every later product of the handle, alone
-// or batched, uses the same tile and therefore the same sums.
-static msp_status tune_matvec(msp_handle* h, hipStream_t s) {
-  int best = 8;
-  const char* env = std::getenv("MSP_MV_TILE");
-  if (env && (std::atoi(env) == 4 || std::atoi(env) == 8 || std::atoi(env) == 16)) {
-    best = std::atoi(env);
-  } else {
-    const long long nd = h->n_dofs;
-    HIPCHK(h, hipMemsetAsync(h->d_x, 0, nd * sizeof(double), s));
-    hipEvent_t e0, e1;
-    HIPCHK(h, hipEventCreate(&e0));
-    HIPCHK(h, hipEventCreate(&e1));
-    float best_ms = 0.f;
-    const int cand[3] = {4, 8, 16};
-    for (int c = 0; c < 3; ++c) {
-      if (cand[c] != 4 && matvec_blocks(h->g, cand[c]) < 2 * kNumCUs) continue;
-      launch_apply_K(h->g, cand[c], h->d_elem, h->d_E, h->d_mask, h->d_x, h->d_tmp, s);
-      HIPCHK(h, hipEventRecord(e0, s));
-      for (int r = 0; r < 10; ++r)
-        launch_apply_K(h->g, cand[c], h->d_elem, h->d_E, h->d_mask, h->d_x, h->d_tmp, s);
-      HIPCHK(h, hipEventRecord(e1, s));
-      HIPCHK(h, hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
-      if (c == 0 || ms < best_ms) {
-        best_ms = ms;
-        best = cand[c];
-      }
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-  }
-  h->mv_ty = best;
-  h->nb_mv = matvec_blocks(h->g, best);
-  h->mv_tuned = true;
-  return MSP_OK;
-}
-
 extern "C" msp_status msp_set_densities(msp_handle* h, const double* rho,
                                         hipStream_t s) {
   if (!h || !rho) return fail(h, MSP_E_INVALID, "null argument");
@@ -782,11 +761,40 @@ extern "C" msp_status msp_set_densities(msp_handle* h, const double* rho,
     return fail(h, MSP_E_INVALID, "densities must be finite and lie in [0, 1]");
   }
   h->have_E = true;
-  h->setup_ok = false;
-  if (!h->mv_tuned) {
-    const msp_status st = tune_matvec(h, s);
-    if (st != MSP_OK) return st;
-  }
+  ++h->dens_gen;
+  // without a reuse policy the setup belongs to the old densities only
+  if (h->reuse_max_age <= 0) h->setup_ok = false;
+  return MSP_OK;
+}
+
+// The setup was built for the current densities.
+static bool setup_fresh(const msp_handle* h) {
+  return h->setup_ok && h->setup_gen == h->dens_gen;
+}
+
+// A setup must be built before the next solve or apply: none exists, or it
+// belongs to older densities and the reuse policy does not cover them.
+static bool setup_needed(const msp_handle* h) {
+  if (!h->setup_ok) return true;
+  if (setup_fresh(h)) return false;
+  return h->rebuild_due || h->reuse_max_age <= 0 ||
+         h->dens_gen - h->setup_gen > h->reuse_max_age;
+}
+
+// After a solve: a reused setup that needed more iterations than the limit
+// is rebuilt before the next solve.
+static void reuse_note_iters(msp_handle* h, bool reused, int iters) {
+  if (reused && h->reuse_iter_limit > 0 && iters > h->reuse_iter_limit)
+    h->rebuild_due = true;
+}
+
+extern "C" msp_status msp_set_reuse(msp_handle* h, int32_t max_age,
+                                    int32_t iter_limit) {
+  if (!h) return fail(h, MSP_E_INVALID, "null handle");
+  if (max_age < 0 || iter_limit < 0)
+    return fail(h, MSP_E_INVALID, "max_age and iter_limit must be >= 0");
+  h->reuse_max_age = max_age;
+  h->reuse_iter_limit = iter_limit;
   return MSP_OK;
 }
 
@@ -901,13 +909,19 @@ extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
   launch_factor_heat(g, h->d_omegas, (int)h->omegas.size(), h->d_E,
                      h->d_dflag, Ce, h->d_Som, h->d_err, h->d_om_pack, h->om_npack, s);
   tk = timer_begin(h, KT_EIGEN, s);
-  launch_heat_eigen(g, h->d_omegas, (int)h->omegas.size(), h->d_E, h->d_dflag,
-                    Ae, Me, h->d_Som, h->d_X, h->d_Y, h->d_Z, m, kmax,
-                    kEigMaxIt, kEigRR, h->desc.eig_tau / (h->H * h->H), kEigTol,
-                    h->d_eig_state, (int*)h->d_cnt + 4, h->h_int + 8,
-                    h->d_psi, h->d_psi32, h->d_lam, h->d_nsel, h->d_cap, h->d_err,
-                    h->d_om_pack, h->om_npack, s);
+  const int unconv = launch_heat_eigen(
+      g, h->d_omegas, (int)h->omegas.size(), h->d_E, h->d_dflag, Ae, Me,
+      h->d_Som, h->d_X, h->d_Y, h->d_Z, m, kmax, kEigMaxIt, kEigRR,
+      h->desc.eig_tau / (h->H * h->H), kEigTol, h->d_eig_state,
+      (int*)h->d_cnt + 4, h->h_int + 8, h->d_psi, h->d_psi32, h->d_lam,
+      h->d_nsel, h->d_cap, h->d_err, h->d_om_pack, h->om_npack, s);
   timer_end(h, KT_EIGEN, tk, s);
+  if (unconv < 0) {
+    h->setup_ok = false;
+    const hipError_t e = hipGetLastError();
+    return fail(h, MSP_E_DEVICE, std::string("heat eigen iteration: ") + hipGetErrorString(e));
+  }
+  h->eig_unconverged = unconv;
   HIPCHK(h, hipGetLastError());
   const size_t nom = h->omegas.size();
   h->nsel_h.resize(nom);
@@ -1003,6 +1017,8 @@ extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
   h->t_setup_ms = ms;
   h->rank = h->ldk - h->h_int[1];
   h->setup_ok = true;
+  h->setup_gen = h->dens_gen;
+  h->rebuild_due = false;
   return MSP_OK;
 }
 
@@ -1133,7 +1149,7 @@ static void enqueue_prec(msp_handle* h, int mode, const double* r,
 static msp_status check_ready(msp_handle* h, hipStream_t s) {
   if (!h) return fail(h, MSP_E_INVALID, "null handle");
   if (!h->have_E) return fail(h, MSP_E_STATE, "msp_set_densities must come first");
-  if (!h->setup_ok) return msp_setup(h, s);
+  if (setup_needed(h)) return msp_setup(h, s);
   return MSP_OK;
 }
 
@@ -1341,6 +1357,7 @@ static msp_status run_end(SolveRun& R, hipStream_t s, msp_solve_info* info) {
     info->coarse_rank = h->rank;
     info->cap_hits = h->cap_hits;
     info->fp64_subdomains = h->n_fp64_subs;
+    info->eig_unconverged = h->eig_unconverged;
     info->relres_true = R.relres_true;
     info->relres_rec = R.relres_rec;
     info->compliance = R.comp;
@@ -1404,20 +1421,25 @@ extern "C" msp_status msp_solve(msp_handle* h, const double* f, double* u,
     return fail(h, MSP_E_INVALID, "need nrhs >= 1, maxit >= 1, rtol > 0");
   double t_setup = 0.0;
   if (!h->have_E) return fail(h, MSP_E_STATE, "msp_set_densities must come first");
-  if (!h->setup_ok) {
+  if (setup_needed(h)) {
     msp_status st = msp_setup(h, s);
     if (st != MSP_OK) return st;
     t_setup = h->t_setup_ms;
   }
+  const bool reused = !setup_fresh(h);
   msp_status last = MSP_OK;
+  msp_solve_info tmp{};
+  msp_solve_info* inf = info ? info : &tmp;
   for (int k = 0; k < nrhs; ++k) {
     msp_status st = solve_one(h, f + (long long)k * h->n_dofs,
                               u + (long long)k * h->n_dofs, warm, rtol, maxit,
-                              s, info);
+                              s, inf);
     if (st < 0) return st;
     if (st != MSP_OK) last = st;
+    reuse_note_iters(h, reused, inf->iters);
   }
-  if (info) info->t_setup_ms = t_setup;
+  inf->t_setup_ms = t_setup;
+  inf->setup_reused = reused ? 1 : 0;
   return last;
 }
 
@@ -1610,8 +1632,12 @@ extern "C" msp_status msp_batch_solve(msp_batch* b, msp_handle* const* hs_in,
   }
   // setups (those whose densities changed)
   std::vector<double> t_setup(n, 0.0);
+  std::vector<char> reused(n, 0);
   for (int e = 0; e < n; ++e) {
-    if (hs[e]->setup_ok) continue;
+    if (!setup_needed(hs[e])) {
+      reused[e] = setup_fresh(hs[e]) ? 0 : 1;
+      continue;
+    }
     const msp_status st = msp_setup(hs[e], s);
     if (st != MSP_OK) return bfail(b, st, std::string("setup of batch entry failed: ") + hs[e]->err);
     t_setup[e] = hs[e]->t_setup_ms;
@@ -1701,7 +1727,11 @@ extern "C" msp_status msp_batch_solve(msp_batch* b, msp_handle* const* hs_in,
   for (int e = 0; e < n; ++e) {
     msp_solve_info* inf = infos ? &infos[e] : nullptr;
     const msp_status se = run_end(R[e], s, inf);
-    if (inf) inf->t_setup_ms = t_setup[e];
+    if (inf) {
+      inf->t_setup_ms = t_setup[e];
+      inf->setup_reused = reused[e];
+    }
+    reuse_note_iters(hs[e], reused[e] != 0, R[e].total_iters);
     if (se < 0 && worst >= 0) worst = se;
     else if (se > 0 && worst == MSP_OK) worst = se;
   }
@@ -1745,6 +1775,7 @@ struct SvRun {
   long long bytes = 0;         // projected handle bytes
   long long last_use = 0;
   bool busy = false;           // a request of this run is admitted
+  bool reused = false;         // the admitted request runs on an older setup
 };
 
 struct SvReq {
@@ -1777,6 +1808,9 @@ struct msp_server {
   std::vector<double> lat_ms;
   long long solves = 0;
   double t_first = -1.0, t_last = 0.0;
+  int reuse_max_age = 0, reuse_iter_limit = 0;   // applied to every run's handle
+  long long setups_built = 0, setups_reused = 0;
+  hipEvent_t ev_step = nullptr;  // orders the setup stream after the caller's
   std::string err;
 };
 
@@ -1802,6 +1836,11 @@ extern "C" msp_status msp_server_create(int64_t hbm_budget_bytes, int32_t max_ac
     delete sv;
     return sfail(nullptr, MSP_E_DEVICE, "stream creation failed");
   }
+  if (hipEventCreateWithFlags(&sv->ev_step, hipEventDisableTiming) != hipSuccess) {
+    (void)hipStreamDestroy(sv->s_setup);
+    delete sv;
+    return sfail(nullptr, MSP_E_DEVICE, "event creation failed");
+  }
   *out = sv;
   return MSP_OK;
 }
@@ -1818,6 +1857,7 @@ extern "C" msp_status msp_server_destroy(msp_server* sv) {
   batch_free_tables(&sv->batch);
   sv->batch.gexec = nullptr;
   if (sv->s_setup) (void)hipStreamDestroy(sv->s_setup);
+  if (sv->ev_step) (void)hipEventDestroy(sv->ev_step);
   delete sv;
   return MSP_OK;
 }
@@ -1941,6 +1981,8 @@ static msp_status sv_admit(msp_server* sv) {
       if (!sv_make_room(sv, q.run)) break;          // wait for memory
       msp_status st = msp_create(&r.desc, r.mask.data(), &r.h);
       if (st != MSP_OK) return sfail(sv, st, g_static_err);
+      r.h->reuse_max_age = sv->reuse_max_age;
+      r.h->reuse_iter_limit = sv->reuse_iter_limit;
       if (!r.d_us) {
         const long long nd = r.h->n_dofs;
         if (dalloc(&r.d_us, nd) != hipSuccess || dalloc(&r.d_ua, nd) != hipSuccess)
@@ -1952,7 +1994,16 @@ static msp_status sv_admit(msp_server* sv) {
     sv->queue.erase(sv->queue.begin() + qi);
     sv->active.push_back(id);
     msp_status st = msp_set_densities(r.h, q.rho, sv->s_setup);
-    if (st == MSP_OK) st = msp_setup(r.h, sv->s_setup);
+    r.reused = false;
+    if (st == MSP_OK) {
+      if (setup_needed(r.h)) {
+        st = msp_setup(r.h, sv->s_setup);
+        ++sv->setups_built;
+      } else {
+        r.reused = true;
+        ++sv->setups_reused;
+      }
+    }
     if (st == MSP_OK) st = sv_start_solve(sv, q, false, sv->s_setup);
     if (st != MSP_OK) {
       q.status = st;
@@ -1968,7 +2019,9 @@ static void sv_solve_finished(msp_server* sv, SvReq& q, hipStream_t s) {
   const bool adjoint = q.phase == 3;
   msp_solve_info& inf = q.info[adjoint ? 1 : 0];
   const msp_status st = run_end(q.R, s, &inf);
-  inf.t_setup_ms = adjoint ? 0.0 : r.h->t_setup_ms;
+  inf.t_setup_ms = (adjoint || r.reused) ? 0.0 : r.h->t_setup_ms;
+  inf.setup_reused = r.reused ? 1 : 0;
+  reuse_note_iters(r.h, r.reused, inf.iters);
   if (st < 0) {
     q.status = st;
     q.phase = -1;
@@ -1999,6 +2052,11 @@ extern "C" msp_status msp_server_step(msp_server* sv, hipStream_t s,
                                       int32_t* n_completed) {
   if (!sv) return sfail(sv, MSP_E_INVALID, "null server");
   if (n_completed) *n_completed = 0;
+  // admissions read the caller's densities and loads on the setup stream:
+  // it starts after everything the caller queued on s before this call
+  if (hipEventRecord(sv->ev_step, s) != hipSuccess ||
+      hipStreamWaitEvent(sv->s_setup, sv->ev_step, 0) != hipSuccess)
+    return sfail(sv, MSP_E_DEVICE, "ordering the setup stream failed");
   // 1. one chunk of lockstep iterations for every solve that iterates
   std::vector<int> it_ids;
   std::vector<msp_handle*> hs;
@@ -2098,12 +2156,28 @@ extern "C" msp_status msp_server_result(msp_server* sv, int32_t ticket,
   return q.phase == 4 ? q.status : (q.status < 0 ? q.status : MSP_E_DEVICE);
 }
 
-// stats (8 doubles): completed requests, p50 and p99 latency (ms), solves/s
-// (state and adjoint solves completed per second of wall time from the
-// first submission to the last completion), projected HBM in use (bytes),
-// queued, active, batched chunks run.
-extern "C" msp_status msp_server_stats(const msp_server* sv, double* out8) {
-  if (!sv || !out8) return MSP_E_INVALID;
+// stats (up to 10 doubles): completed requests, p50 and p99 latency (ms),
+// solves/s (state and adjoint solves completed per second of wall time from
+// the first submission to the last completion), projected HBM in use
+// (bytes), queued, active, batched chunks run, setups built, setups reused.
+extern "C" msp_status msp_server_set_reuse(msp_server* sv, int32_t max_age,
+                                           int32_t iter_limit) {
+  if (!sv) return sfail(sv, MSP_E_INVALID, "null server");
+  if (max_age < 0 || iter_limit < 0)
+    return sfail(sv, MSP_E_INVALID, "max_age and iter_limit must be >= 0");
+  sv->reuse_max_age = max_age;
+  sv->reuse_iter_limit = iter_limit;
+  for (SvRun& r : sv->runs)
+    if (r.h) {
+      r.h->reuse_max_age = max_age;
+      r.h->reuse_iter_limit = iter_limit;
+    }
+  return MSP_OK;
+}
+
+extern "C" msp_status msp_server_stats(const msp_server* sv, double* out, int32_t n) {
+  if (!sv || !out || n < 0) return MSP_E_INVALID;
+  double out8[10];
   std::vector<double> l = sv->lat_ms;
   std::sort(l.begin(), l.end());
   auto pct = [&](double p) {
@@ -2120,6 +2194,9 @@ extern "C" msp_status msp_server_stats(const msp_server* sv, double* out8) {
   out8[5] = (double)sv->queue.size();
   out8[6] = (double)sv->active.size();
   out8[7] = (double)sv->batch.chunks;
+  out8[8] = (double)sv->setups_built;
+  out8[9] = (double)sv->setups_reused;
+  for (int i = 0; i < std::min(n, 10); ++i) out[i] = out8[i];
   return MSP_OK;
 }
 

@@ -11,6 +11,8 @@ import pytest
 import inputs
 import oracle
 
+from _checks import assert_entrywise
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
@@ -46,8 +48,8 @@ def test_matvec3d_parity(nel, seed):
     y = s.apply_K(_dev(x)).cpu().numpy()
     xm = np.where(fixed == 1, 0.0, x)
     yref = np.where(fixed == 1, 0.0, K @ xm)
-    rel = np.linalg.norm(y - yref) / np.linalg.norm(yref)
-    assert rel <= 1e-13, rel
+    # same terms in another order: per entry within 1e-13 (|K| |x|)_i
+    assert_entrywise(y, yref, 1e-13, abs(K) @ np.abs(xm), "3D K x")
     assert np.all(y[fixed == 1] == 0.0)
     s.close()
 

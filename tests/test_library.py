@@ -34,7 +34,43 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(msp.ProblemDesc) == 104
     assert msp.ProblemDesc.h.offset == 16
     assert msp.ProblemDesc.eig_tau.offset == 80
-    assert ctypes.sizeof(msp.SolveInfo) == 32 + 6 * 8
+    assert ctypes.sizeof(msp.SolveInfo) == 40 + 6 * 8
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """Every field offset and struct size of the binding equals what a C
+    compiler gives for include/msp.h."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None or not os.path.exists("/opt/rocm/include/hip/hip_runtime_api.h"):
+        pytest.skip("no C compiler or HIP headers")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "msp.h"',
+             'int main(void) {']
+    for cname, cls in (("msp_problem_desc", msp.ProblemDesc),
+                       ("msp_solve_info", msp.SolveInfo)):
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    res = subprocess.run([cc, "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                          "-I", "/opt/rocm/include", str(src), "-o", str(exe)],
+                         capture_output=True, text=True)
+    if res.returncode != 0:
+        pytest.skip("header does not compile as C here: " + res.stderr[:200])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    got = {}
+    for line in out.splitlines():
+        a, b, v = line.split()
+        got[(a, b)] = int(v)
+    for cname, cls in (("msp_problem_desc", msp.ProblemDesc),
+                       ("msp_solve_info", msp.SolveInfo)):
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
 
 
 def test_missing_library_fails_loudly(tmp_path):
