@@ -212,6 +212,27 @@ msp_status msp_coarse_basis(msp_handle* h, double* phi_dev, hipStream_t stream);
 msp_status msp_vec_dot(int64_t n, const double* x_dev, const double* y_dev,
                        hipStream_t stream, double* out_host);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that forbid hipMalloc): out_dev[0] = x . y over n
+ * doubles, the same kernel and grid as msp_vec_dot (so the same bits), but
+ * with its workgroup partials and ticket counter in a fixed library-owned
+ * device array (1,025 doubles per GPU, held until the process ends) instead
+ * of buffers allocated per call, and the result left in device memory
+ * (out_dev: one double, caller-owned).  Nothing is allocated and the call
+ * does not synchronise: the result is ready when the caller's stream
+ * reaches it.  Every call on a GPU shares that GPU's array, so calls that
+ * overlap on one GPU (different streams, or host threads) race; serialise
+ * them.  The first call on each device looks the array up (with that
+ * device current).
+ * Errors: MSP_E_INVALID (null pointer, n < 0, n > MSP_NOALLOC_DOT_MAX_N),
+ * MSP_E_DEVICE.  The text is in msp_last_error(NULL).
+ */
+#define MSP_NOALLOC_DOT_MAX_N (((int64_t)1) << 35)
+msp_status msp_vec_dot_noalloc(int64_t n, const double* x_dev,
+                               const double* y_dev, double* out_dev,
+                               hipStream_t stream);
+
 /* Sizes (12 int64): [0] n DOFs, [1] elements, [2] subdomains, [3] coarse
  * nodes, [4] coarse dimension after setup, [5] largest local system,
  * [6] bytes of first-level factor records (inverse Schur blocks and row

@@ -64,7 +64,7 @@ EXPORTS = ["msp_create", "msp_destroy", "msp_last_error", "msp_set_densities",
            "msp_server_create", "msp_server_destroy", "msp_server_last_error",
            "msp_server_add_run", "msp_server_submit", "msp_server_step",
            "msp_server_result", "msp_server_stats", "msp_set_reuse",
-           "msp_server_set_reuse"]
+           "msp_server_set_reuse", "msp_vec_dot_noalloc"]
 
 KERNEL_NAMES = ["level1_apply", "cg_matvec", "heat_eigen", "combine",
                 "coarse_restrict", "local_factor"]
@@ -99,6 +99,7 @@ def load_library(path=LIB_PATH):
     L.msp_coarse_basis.argtypes = [vp, vp, vp]
     L.msp_vec_dot.argtypes = [ctypes.c_int64, vp, vp, vp,
                               ctypes.POINTER(ctypes.c_double)]
+    L.msp_vec_dot_noalloc.argtypes = [ctypes.c_int64, vp, vp, vp, vp]
     L.msp_query.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     L.msp_kernel_timing.argtypes = [vp, i32, vp, vp, i32]
     L.msp_batch_create.argtypes = [ctypes.POINTER(vp)]
@@ -428,3 +429,13 @@ def vec_dot(x, y):
     if st != 0:
         raise MspError(st, L.msp_last_error(None).decode())
     return out.value
+
+
+def vec_dot_noalloc(x, y, out):
+    """out[0] = x . y through the entry point that allocates nothing; out is
+    a one-element float64 device tensor, written on the current stream."""
+    L = load_library()
+    st = L.msp_vec_dot_noalloc(x.numel(), _ptr(x), _ptr(y), _ptr(out), _stream())
+    if st != 0:
+        raise MspError(st, L.msp_last_error(None).decode())
+    return out

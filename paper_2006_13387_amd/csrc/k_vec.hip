@@ -595,10 +595,14 @@ void launch_update_batch(const UpdateArgs* tab, const int* start, int nent,
   hipLaunchKernelGGL(k_update_batch, dim3(total), dim3(256), 0, s, tab, start, nent);
 }
 
+// largest grid of the dot product: the partial buffer holds this many
+constexpr int kDotMaxBlocks = 1024;
+int dot_max_blocks() { return kDotMaxBlocks; }
+
 void launch_dot(long long n, const double* x, const double* y, double* part,
                 unsigned int* counter, double* out, hipStream_t s) {
   long long nb = (n + 255) / 256;
-  if (nb > 1024) nb = 1024;
+  if (nb > kDotMaxBlocks) nb = kDotMaxBlocks;
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL(k_dot, dim3((unsigned)nb), dim3(256), 0, s, n, x, y, part,
                      counter, out);

@@ -42,6 +42,7 @@ void launch_update_batch(const UpdateArgs*, const int*, int, int, hipStream_t);
 void launch_dot(long long, const double*, const double*, double*,
                 unsigned int*, double*, hipStream_t);
 void launch_mask(long long, const uint8_t*, double*, hipStream_t);
+int dot_max_blocks();
 // k_local.hip
 int chain_items(const std::vector<SysDesc>&, int ncu, std::vector<int>& pack);
 void launch_factor_elastic(const Geom&, const SysDesc*, int, const double*,
@@ -481,6 +482,13 @@ static void timer_flush(msp_handle* h) {
 }
 
 // --------------------------------------------------------------------- API
+
+namespace msp {
+// Error text of a call that has no handle (read by msp_last_error(NULL)).
+msp_status set_static_error(msp_status st, const std::string& msg) {
+  return fail(nullptr, st, msg);
+}
+}  // namespace msp
 
 extern "C" const char* msp_last_error(const msp_handle* h) {
   return h ? h->err.c_str() : g_static_err.c_str();
@@ -2237,7 +2245,7 @@ extern "C" msp_status msp_vec_dot(int64_t n, const double* x, const double* y,
   double* part = nullptr;
   unsigned int* cnt = nullptr;
   double* d_out = nullptr;
-  if (dalloc(&part, 1024) != hipSuccess || dalloc(&cnt, 1) != hipSuccess ||
+  if (dalloc(&part, dot_max_blocks()) != hipSuccess || dalloc(&cnt, 1) != hipSuccess ||
       dalloc(&d_out, 1) != hipSuccess) {
     dfree(part);
     dfree(cnt);
