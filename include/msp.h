@@ -207,6 +207,16 @@ msp_status msp_coarse_info(msp_handle* h, int32_t* n_modes_host,
  * phi_dev (caller allocates n*N_c doubles).  For checks on small meshes. */
 msp_status msp_coarse_basis(msp_handle* h, double* phi_dev, hipStream_t stream);
 
+/* Write a coarse matrix to out_dev (caller allocates ldk * ldk doubles,
+ * ldk = msp_query()[11]; row-major with leading dimension ldk, entries
+ * beyond N_c are padding): which = 0 the assembled K_0 = R_0 K R_0^T of the
+ * last setup (Section 2; recomputed from the stored K R_0^T columns),
+ * which = 1 the generalised inverse K_0^+ that the coarse solve applies.
+ * For checks of the coarse solve.  Errors: MSP_E_INVALID, MSP_E_STATE (no
+ * setup), MSP_E_DEVICE. */
+msp_status msp_coarse_matrix(msp_handle* h, int32_t which, double* out_dev,
+                             hipStream_t stream);
+
 /* out_host[0] = x . y over n doubles with the library's two-stage
  * wavefront reduction (the reduction used by the CG dot products). */
 msp_status msp_vec_dot(int64_t n, const double* x_dev, const double* y_dev,

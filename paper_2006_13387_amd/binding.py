@@ -64,7 +64,8 @@ EXPORTS = ["msp_create", "msp_destroy", "msp_last_error", "msp_set_densities",
            "msp_server_create", "msp_server_destroy", "msp_server_last_error",
            "msp_server_add_run", "msp_server_submit", "msp_server_step",
            "msp_server_result", "msp_server_stats", "msp_set_reuse",
-           "msp_server_set_reuse", "msp_vec_dot_noalloc"]
+           "msp_server_set_reuse", "msp_vec_dot_noalloc",
+           "msp_coarse_matrix"]
 
 KERNEL_NAMES = ["level1_apply", "cg_matvec", "heat_eigen", "combine",
                 "coarse_restrict", "local_factor"]
@@ -99,6 +100,7 @@ def load_library(path=LIB_PATH):
     L.msp_coarse_basis.argtypes = [vp, vp, vp]
     L.msp_vec_dot.argtypes = [ctypes.c_int64, vp, vp, vp,
                               ctypes.POINTER(ctypes.c_double)]
+    L.msp_coarse_matrix.argtypes = [vp, i32, vp, vp]
     L.msp_vec_dot_noalloc.argtypes = [ctypes.c_int64, vp, vp, vp, vp]
     L.msp_query.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     L.msp_kernel_timing.argtypes = [vp, i32, vp, vp, i32]
@@ -264,6 +266,17 @@ class Solver:
                           device="cuda")
         self._check(self.L.msp_coarse_basis(self.h, _ptr(phi), _stream()))
         return phi[:nc].T
+
+    def coarse_matrix(self, which):
+        """K_0 (which=0) or the generalised inverse the coarse solve applies
+        (which=1), N_c x N_c on the device."""
+        import torch
+        q = self.query()
+        ldk, nc = q["ldk"], q["n_coarse"]
+        out = torch.zeros((ldk, ldk), dtype=torch.float64, device="cuda")
+        self._check(self.L.msp_coarse_matrix(self.h, int(which), _ptr(out),
+                                             _stream()))
+        return out[:nc, :nc]
 
     def kernel_timing(self, enable=-1):
         """Launch counts and summed event times (ms) of the tracked kernels

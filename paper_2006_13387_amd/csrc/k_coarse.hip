@@ -9,7 +9,10 @@
 //
 // K_0 = R_0 K R_0^T is assembled from W = K Phi per column and the
 // products Phi_a^T W_b over overlapping neighbourhoods, scaled to unit
-// diagonal and inverted by blocked Gauss-Jordan with zero-pivot dropping.
+// diagonal and inverted by blocked Gauss-Jordan with zero-pivot dropping
+// (each block step: the pivot block by pivot-by-pivot Gauss-Jordan, the
+// block row and column by substitution with its L D L^T factors, the rest
+// by a rank-64 update on the FP64 matrix cores).
 // Dropping a (numerically) dependent direction gives a generalized inverse
 // G of K_0, and R_0^T G R_0 does not depend on which one: it is the
 // K-orthogonal projection onto the coarse space composed with K^{-1}.
@@ -192,13 +195,15 @@ k_coarse_k0(Geom g, const CoarseNode* __restrict__ cnodes,
 }
 
 // Symmetrise, scale to unit diagonal (s_j = 1/sqrt(K0_jj), 0 for empty
-// columns and padding).  One thread per entry.
+// columns, padding and the dependent column dep_col, -1 for none, so that
+// their pivots are dropped).  One thread per entry.
 __global__ void k_k0_scale_factors(const double* __restrict__ K0, int ldk,
-                                   int nc, double* __restrict__ sdiag) {
+                                   int nc, int dep_col,
+                                   double* __restrict__ sdiag) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= ldk) return;
   double s = 0.0;
-  if (j < nc) {
+  if (j < nc && j != dep_col) {
     const double d = K0[(long long)j * ldk + j];
     if (d > 0.0 && finite(d)) s = 1.0 / sqrt(d);
   }
@@ -232,7 +237,9 @@ template <int PU>
 __device__ __forceinline__ void gjp_pivot(double (&a)[4][4], int pt, int ti,
                                           int tj, double tol, double* pv,
                                           double& nv, double& inv,
-                                          int* __restrict__ dropped) {
+                                          int* __restrict__ dropped,
+                                          double* __restrict__ Lg,
+                                          double* __restrict__ Dg) {
   const int p = 16 * PU + pt;
   double* rowv = pv + (p & 1) * 2 * GJB;
   double* colv = rowv + GJB;
@@ -259,6 +266,16 @@ __device__ __forceinline__ void gjp_pivot(double (&a)[4][4], int pt, int ti,
   for (int u = 0; u < 4; ++u) cv[u] = colv[ti + 16 * u];
 #pragma unroll
   for (int w = 0; w < 4; ++w) rv[w] = rowv[tj + 16 * w] * ip;
+  // the block's L D L^T, kept for the panels: column p of the unit lower L
+  // is the pivot column below the pivot over the pivot (zero if dropped)
+  if (pcol) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int row = ti + 16 * u;
+      Lg[row * GJB + p] = row > p ? cv[u] * ip : 0.0;
+    }
+    if (prow) Dg[p] = ip;
+  }
   // the entry of pivot p + 1 first: (PU, PU), or (PU + 1, PU + 1) after the
   // last pivot of this tile row
   constexpr int PN = PU + 1 < 4 ? PU + 1 : PU;
@@ -286,19 +303,27 @@ __device__ __forceinline__ void gjp_pivot(double (&a)[4][4], int pt, int ti,
 template <int PU>
 __device__ __forceinline__ void gjp_tile(double (&a)[4][4], int ti, int tj,
                                          double tol, double* pv, double& nv,
-                                         double& inv, int* __restrict__ dropped) {
-  for (int pt = 0; pt < 16; ++pt) gjp_pivot<PU>(a, pt, ti, tj, tol, pv, nv, inv, dropped);
+                                         double& inv, int* __restrict__ dropped,
+                                         double* __restrict__ Lg,
+                                         double* __restrict__ Dg) {
+  for (int pt = 0; pt < 16; ++pt)
+    gjp_pivot<PU>(a, pt, ti, tj, tol, pv, nv, inv, dropped, Lg, Dg);
 }
 
-// P = GJ inverse (generalised) of the diagonal block kb of A.
+// Block step kb, first part: P = GJ inverse (generalised) of the diagonal
+// block, written over it, and the block's factors L D L^T (unit lower L
+// row-major in LD[0 .. 4095], 1/D in LD[4096 .. 4159], 0 for a dropped
+// pivot) for the panels.
 __global__ void __launch_bounds__(CK_NT)
-k_gj_pivot(double* __restrict__ A, int ld, int kb, double* __restrict__ P,
+k_gj_pivot(double* __restrict__ A, int ld, int kb, double* __restrict__ LD,
            double tol, int* __restrict__ dropped) {
   static_assert(GJB == 64 && CK_NT == 256, "pivot tiling: 16 x 16 threads, 4 x 4 tiles");
   __shared__ double pv[4 * GJB + 2];
   const int tid = threadIdx.x;
   const int tj = tid & 15, ti = tid >> 4;
   const long long base = (long long)kb * GJB;
+  double* Lg = LD;
+  double* Dg = LD + GJB * GJB;
   double a[4][4];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
@@ -306,107 +331,137 @@ k_gj_pivot(double* __restrict__ A, int ld, int kb, double* __restrict__ P,
     for (int w = 0; w < 4; ++w)
       a[u][w] = A[(base + ti + 16 * u) * ld + base + tj + 16 * w];
   double nv = a[0][0], inv = 1.0 / nv;
-  gjp_tile<0>(a, ti, tj, tol, pv, nv, inv, dropped);
-  gjp_tile<1>(a, ti, tj, tol, pv, nv, inv, dropped);
-  gjp_tile<2>(a, ti, tj, tol, pv, nv, inv, dropped);
-  gjp_tile<3>(a, ti, tj, tol, pv, nv, inv, dropped);
+  gjp_tile<0>(a, ti, tj, tol, pv, nv, inv, dropped, Lg, Dg);
+  gjp_tile<1>(a, ti, tj, tol, pv, nv, inv, dropped, Lg, Dg);
+  gjp_tile<2>(a, ti, tj, tol, pv, nv, inv, dropped, Lg, Dg);
+  gjp_tile<3>(a, ti, tj, tol, pv, nv, inv, dropped, Lg, Dg);
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int w = 0; w < 4; ++w)
-      P[(ti + 16 * u) * GJB + tj + 16 * w] = a[u][w];
+      A[(base + ti + 16 * u) * ld + base + tj + 16 * w] = a[u][w];
 }
 
-// Panels of block k: Lp_i = A_ik P (for every block row i != k) and
-// Rp_j = A_kj (copy).  Grid: nblk workgroups, block index = i (or j).
-__global__ void __launch_bounds__(CK_NT)
-k_gj_panel(const double* __restrict__ A, int ld, int kb,
-           const double* __restrict__ P, double* __restrict__ Lp,
+// Block step kb, second part, for every other block index ib: the block
+// column A_ik and the block row A_ki are transformed by substitution with
+// the pivot block's factors instead of by products with its explicit
+// inverse P = L^-T D^-1 L^-1.  Multiplying by an explicit P amplifies the
+// rounding of its entries by cond(A_kk), which reaches 1e8 in the soft
+// region of a high-contrast K_0; substitution repeats the arithmetic of
+// pivot-by-pivot Gauss-Jordan.  Lane v of wave 0 takes row v of A_ik, lane
+// v of wave 1 column v of A_ki (a 64-vector a, in registers):
+//   w = a L^-T (forward substitution), y = w D^-1, x = y L^-1 (backward);
+// then A_ik <- -x (rows), A_ki <- x^T (columns), and for the update
+// Lp_i = y (rows) and Rp_i = w^T (columns), so that
+// A_ij - A_ik P A_kj = A_ij - Lp_i Rp_j.
+constexpr int GJP_NT = 128;
+__global__ void __launch_bounds__(GJP_NT)
+k_gj_panel(double* __restrict__ A, int ld, int kb,
+           const double* __restrict__ LD, double* __restrict__ Lp,
            double* __restrict__ Rp) {
-  __shared__ double Ps[GJB * GJB];
-  __shared__ double As[GJB * (GJB + 1)];
+  __shared__ double Ls[GJB * GJB];
+  __shared__ double Di[GJB];
   const int ib = blockIdx.x;
+  if (ib == kb) return;
   const int tid = threadIdx.x;
+  for (int q = tid; q < GJB * GJB; q += GJP_NT) Ls[q] = LD[q];
+  if (tid < GJB) Di[tid] = LD[GJB * GJB + tid];
   const long long kbase = (long long)kb * GJB, ibase = (long long)ib * GJB;
-  for (int idx = tid; idx < GJB * GJB; idx += CK_NT) {
-    Ps[idx] = P[idx];
-    const int i = idx / GJB, j = idx - i * GJB;
-    As[i * (GJB + 1) + j] = A[(ibase + i) * ld + kbase + j];     // A_ik
-    Rp[(long long)i * ld + ibase + j] = A[(kbase + i) * ld + ibase + j];   // A_kj, j-block ib
+  const bool colv = tid < GJB;               // wave 0: rows of A_ik
+  const int v = tid & (GJB - 1);
+  double a[GJB];
+  if (colv) {
+    const double2* src = reinterpret_cast<const double2*>(A + (ibase + v) * ld + kbase);
+#pragma unroll
+    for (int t = 0; t < GJB / 2; ++t) {
+      const double2 q = src[t];
+      a[2 * t] = q.x;
+      a[2 * t + 1] = q.y;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < GJB; ++t) a[t] = A[(kbase + t) * ld + ibase + v];
   }
   __syncthreads();
-  // Lp_i on FP64 matrix cores, the operand and result layout of the tile
-  // update below: wave w, rows 16w..16w+15, all four 16-column tiles
+  // w = a L^-T: w_t = a_t - sum_{s<t} w_s L_ts, in pivot order
+#pragma unroll
+  for (int t = 1; t < GJB; ++t) {
+    double acc = a[t];
+#pragma unroll
+    for (int s = 0; s + 1 < t; s += 2) {
+      const double2 l = *reinterpret_cast<const double2*>(Ls + t * GJB + s);
+      acc = fma(-a[s], l.x, acc);
+      acc = fma(-a[s + 1], l.y, acc);
+    }
+    if (t & 1) acc = fma(-a[t - 1], Ls[t * GJB + t - 1], acc);
+    a[t] = acc;
+  }
+  if (!colv) {
+#pragma unroll
+    for (int t = 0; t < GJB; ++t) Rp[(long long)t * ld + ibase + v] = a[t];
+  }
+#pragma unroll
+  for (int t = 0; t < GJB; ++t) a[t] *= Di[t];
+  if (colv) {
+    double2* dst = reinterpret_cast<double2*>(Lp + (ibase + v) * GJB);
+#pragma unroll
+    for (int t = 0; t < GJB / 2; ++t) dst[t] = make_double2(a[2 * t], a[2 * t + 1]);
+  }
+  // x = y L^-1: x_s = y_s - sum_{t>s} x_t L_ts, right-looking from the last
+#pragma unroll
+  for (int t = GJB - 1; t > 0; --t) {
+    const double xt = a[t];
+#pragma unroll
+    for (int s = 0; s + 1 < t; s += 2) {
+      const double2 l = *reinterpret_cast<const double2*>(Ls + t * GJB + s);
+      a[s] = fma(-xt, l.x, a[s]);
+      a[s + 1] = fma(-xt, l.y, a[s + 1]);
+    }
+    if (t & 1) a[t - 1] = fma(-xt, Ls[t * GJB + t - 1], a[t - 1]);
+  }
+  if (colv) {
+    double2* dst = reinterpret_cast<double2*>(A + (ibase + v) * ld + kbase);
+#pragma unroll
+    for (int t = 0; t < GJB / 2; ++t) dst[t] = make_double2(-a[2 * t], -a[2 * t + 1]);
+  } else {
+#pragma unroll
+    for (int t = 0; t < GJB; ++t) A[(kbase + t) * ld + ibase + v] = a[t];
+  }
+}
+
+// Block step kb, last part: A_ij -= Lp_i Rp_j for the tiles outside block
+// row and column kb (those were written by the first two parts).  Grid
+// (nblk, nblk) of 64 x 64 tiles.
+__global__ void __launch_bounds__(CK_NT)
+k_gj_update(double* __restrict__ A, int ld, int kb,
+            const double* __restrict__ Lp, const double* __restrict__ Rp) {
+  __shared__ double Ls[GJB * (GJB + 1)];
+  __shared__ double Rs[GJB * (GJB + 1)];
+  const int ib = blockIdx.y, jb = blockIdx.x;
+  if (ib == kb || jb == kb) return;
+  const int tid = threadIdx.x;
+  const long long ibase = (long long)ib * GJB, jbase = (long long)jb * GJB;
+  // The product on FP64 matrix cores: wave w takes rows 16w..16w+15 of the
+  // tile and all four 16-column tiles; per MFMA 16x16x4, lane l supplies
+  // Ls(16w + l%16, 4K + l/16) and Rs(4K + l/16, 16C + l%16) and holds
+  // C(16w + l/16 + 4r, 16C + l%16) in register r.  The accumulators start
+  // from this lane's entries of A_ij and Ls holds -Lp_i, so the 64 pivots'
+  // terms are subtracted from A_ij in pivot order, four at a time (as the
+  // pivot-by-pivot elimination does) rather than summed first.
   const int wave = tid >> 6, li = tid & 15, lk = (tid & 63) >> 4;
   k0_d4 acc[4];
-#pragma unroll
-  for (int C = 0; C < 4; ++C) acc[C] = {0.0, 0.0, 0.0, 0.0};
-  const double* la = As + (16 * wave + li) * (GJB + 1) + lk;
-  const double* pb = Ps + lk * GJB + li;
-#pragma unroll 4
-  for (int K = 0; K < GJB / 4; ++K) {
-    const double av = la[4 * K];
-#pragma unroll
-    for (int C = 0; C < 4; ++C)
-      acc[C] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, pb[4 * K * GJB + 16 * C], acc[C], 0, 0, 0);
-  }
 #pragma unroll
   for (int C = 0; C < 4; ++C)
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      Lp[(ibase + 16 * wave + lk + 4 * r) * GJB + 16 * C + li] = acc[C][r];
-}
-
-// Tile update of block step k.  Grid (nblk, nblk) of 64 x 64 tiles.
-__global__ void __launch_bounds__(CK_NT)
-k_gj_update(double* __restrict__ A, int ld, int kb,
-            const double* __restrict__ P, const double* __restrict__ Lp,
-            const double* __restrict__ Rp) {
-  __shared__ double Ls[GJB * (GJB + 1)];
-  __shared__ double Rs[GJB * (GJB + 1)];
-  const int ib = blockIdx.y, jb = blockIdx.x;
-  const int tid = threadIdx.x;
-  const long long ibase = (long long)ib * GJB, jbase = (long long)jb * GJB;
-  if (ib == kb && jb == kb) {
-    for (int idx = tid; idx < GJB * GJB; idx += CK_NT) {
-      const int i = idx / GJB, j = idx - i * GJB;
-      A[(ibase + i) * ld + jbase + j] = P[idx];
-    }
-    return;
-  }
-  if (jb == kb) {
-    for (int idx = tid; idx < GJB * GJB; idx += CK_NT) {
-      const int i = idx / GJB, j = idx - i * GJB;
-      A[(ibase + i) * ld + jbase + j] = -Lp[(ibase + i) * GJB + j];
-    }
-    return;
-  }
-  // The product on FP64 matrix cores: wave w takes rows 16w..16w+15 of the
-  // tile and all four 16-column tiles; per MFMA 16x16x4, lane l supplies
-  // Ls(16w + l%16, 4K + l/16) and Rs(4K + l/16, 16C + l%16) and holds
-  // C(16w + l/16 + 4r, 16C + l%16) in register r.  This lane's entries of
-  // A_ij are read first so that the read overlaps the staging and the
-  // product.
-  const int wave = tid >> 6, li = tid & 15, lk = (tid & 63) >> 4;
-  double aij[4][4];
-  if (ib != kb) {
-#pragma unroll
-    for (int C = 0; C < 4; ++C)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        aij[C][r] = A[(ibase + 16 * wave + lk + 4 * r) * ld + jbase + 16 * C + li];
-  }
-  // Ls = (ib == kb) ? P : Lp_i ; Rs = Rp_j
+      acc[C][r] = A[(ibase + 16 * wave + lk + 4 * r) * ld + jbase + 16 * C + li];
   for (int idx = tid; idx < GJB * GJB; idx += CK_NT) {
     const int i = idx / GJB, j = idx - i * GJB;
-    Ls[i * (GJB + 1) + j] = (ib == kb) ? P[idx] : Lp[(ibase + i) * GJB + j];
+    Ls[i * (GJB + 1) + j] = -Lp[(ibase + i) * GJB + j];
     Rs[i * (GJB + 1) + j] = Rp[(long long)i * ld + jbase + j];
   }
   __syncthreads();
   static_assert(GJB == 64 && CK_NT == 256, "four waves of 16-row strips");
-  k0_d4 acc[4];
-#pragma unroll
-  for (int C = 0; C < 4; ++C) acc[C] = {0.0, 0.0, 0.0, 0.0};
   const double* la = Ls + (16 * wave + li) * (GJB + 1) + lk;
   const double* rb = Rs + lk * (GJB + 1) + li;
 #pragma unroll 4
@@ -419,11 +474,8 @@ k_gj_update(double* __restrict__ A, int ld, int kb,
 #pragma unroll
   for (int C = 0; C < 4; ++C)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      double* dst = &A[(ibase + 16 * wave + lk + 4 * r) * ld + jbase + 16 * C + li];
-      if (ib == kb) *dst = acc[C][r];              // P A_kj
-      else *dst = aij[C][r] - acc[C][r];           // A_ij - Lp_i A_kj
-    }
+    for (int r = 0; r < 4; ++r)
+      A[(ibase + 16 * wave + lk + 4 * r) * ld + jbase + 16 * C + li] = acc[C][r];
 }
 
 // K0p = S A S (undo the scaling), symmetrised.
@@ -950,11 +1002,11 @@ void launch_coarse_k0(const Geom& g, const CoarseNode* cn, const int2* pairs,
                      mask, psi, W, K0, ldk, invH);
 }
 
-void launch_k0_pinv(double* K0, int ldk, int nc, double* sdiag, double* P,
-                    double* Lp, double* Rp, double tol, int* dropped,
+void launch_k0_pinv(double* K0, int ldk, int nc, int dep_col, double* sdiag,
+                    double* P, double* Lp, double* Rp, double tol, int* dropped,
                     hipStream_t s) {
   hipLaunchKernelGGL(k_k0_scale_factors, dim3((ldk + 255) / 256), dim3(256), 0,
-                     s, K0, ldk, nc, sdiag);
+                     s, K0, ldk, nc, dep_col, sdiag);
   const long long n2 = (long long)ldk * ldk;
   hipLaunchKernelGGL(k_k0_scale, dim3((unsigned)((n2 + 255) / 256)), dim3(256),
                      0, s, K0, ldk, sdiag);
@@ -962,10 +1014,10 @@ void launch_k0_pinv(double* K0, int ldk, int nc, double* sdiag, double* P,
   for (int kb = 0; kb < nblk; ++kb) {
     hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(CK_NT), 0, s, K0, ldk, kb, P,
                        tol, dropped);
-    hipLaunchKernelGGL(k_gj_panel, dim3(nblk), dim3(CK_NT), 0, s, K0, ldk, kb,
+    hipLaunchKernelGGL(k_gj_panel, dim3(nblk), dim3(GJP_NT), 0, s, K0, ldk, kb,
                        P, Lp, Rp);
     hipLaunchKernelGGL(k_gj_update, dim3(nblk, nblk), dim3(CK_NT), 0, s, K0,
-                       ldk, kb, P, Lp, Rp);
+                       ldk, kb, Lp, Rp);
   }
   hipLaunchKernelGGL(k_k0_unscale, dim3((unsigned)((n2 + 255) / 256)),
                      dim3(256), 0, s, K0, ldk, sdiag);

@@ -68,7 +68,7 @@ void launch_coarse_kphi(const Geom&, const CoarseNode*, const int*, int,
 void launch_coarse_k0(const Geom&, const CoarseNode*, const int2*, int,
                       const uint8_t*, const double*, const double*, double*,
                       int, double, hipStream_t);
-void launch_k0_pinv(double*, int, int, double*, double*, double*, double*,
+void launch_k0_pinv(double*, int, int, int, double*, double*, double*, double*,
                     double, int*, hipStream_t);
 void launch_restrict(const RestrictArgs&, int ncn, hipStream_t);
 void launch_restrict_batch(const RestrictArgs*, const int*, int, int, hipStream_t);
@@ -106,7 +106,18 @@ constexpr int kEigExtra = 8;         // subspace block m = kmax + kEigExtra
 constexpr int kEigMaxIt = 48;
 constexpr int kEigRR = 3;
 constexpr double kEigTol = 1e-8;
-constexpr double kPivotDrop = 1e-12; // scaled K_0 pivots at or below: dropped
+// Pivots of the unit-diagonal K_0 at or below kPivotDrop are dropped (the
+// column is treated as dependent; dropping a genuine pivot would remove its
+// column from the coarse space, and the correction would stay the exact
+// Galerkin correction of the remaining columns).  The one dependency the
+// method itself creates, sum_l chi_l r_l = 0 when every coarse node carries
+// a rotation (the hats reproduce linear functions), is removed before the
+// elimination instead: in pivot order its last column's pivot is
+// (rounding of K_0) / v_n^2, with v_n that column's weight in the null
+// vector, which on the 512 x 256 cantilever at Emin 1e-9 (rounding about
+// 1.5e-12, v_n = 0.023) lands among the genuine pivots (about 1e-8; the
+// smallest nonzero eigenvalue of the scaled K_0 is 2.4e-9).
+constexpr double kPivotDrop = 1e-10;
 constexpr int kChunk = 16;           // PCG iterations between host checks
 constexpr int kMaxRestarts = 3;
 // FP32 inverse blocks are used for a subdomain only if its amplification
@@ -223,6 +234,7 @@ struct msp_handle {
   int reuse_iter_limit = 0;        // 0: no iteration criterion
   bool rebuild_due = false;        // a reused setup took too many iterations
   int nc = 0, ldk = 0, rank = 0, cap_hits = 0;
+  int npairs = 0, dep_col = -1;     // K_0 blocks; dependent column dropped (-1 none)
   int eig_unconverged = 0;         // neighbourhoods stopped at the iteration limit
   std::vector<int> nsel_h;
   std::vector<double> lam_h;
@@ -879,7 +891,7 @@ static msp_status ensure_coarse_buffers(msp_handle* h, size_t ncols,
     dfree(h->d_sdiag);
     dfree(h->d_Lp);
     dfree(h->d_Rp);
-    if (!h->d_P) HIPCHK(h, dalloc(&h->d_P, 64 * 64));
+    if (!h->d_P) HIPCHK(h, dalloc(&h->d_P, 64 * 64 + 64));   // pivot block L, 1/D
     HIPCHK(h, dalloc(&h->d_K0, (size_t)ldk * ldk));
     HIPCHK(h, dalloc(&h->d_sdiag, ldk));
     HIPCHK(h, dalloc(&h->d_Lp, (size_t)ldk * 64));
@@ -985,6 +997,11 @@ extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
     h->cap_hits += cap[c.sys];
   }
   h->nc = col;
+  // every coarse node carries a rotation: sum_l chi_l r_l = 0, so the last
+  // node's rotation column lies in the span of the others and is dropped
+  bool all_rot = rot && !h->cn_h.empty();
+  for (const CoarseNode& c : h->cn_h) all_rot = all_rot && c.nrot == 1;
+  const int dep_col = all_rot ? h->cn_h.back().col0 + 2 * h->cn_h.back().nmodes : -1;
   h->ldk = std::max(64, ((col + 63) / 64) * 64);
   if (h->ldk > 12288) {
     h->setup_ok = false;
@@ -1009,11 +1026,13 @@ extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
   launch_coarse_kphi(g, h->d_cn, h->d_col_node, col, Ke, h->d_E, h->d_mask,
                      h->d_psi, h->d_W, h->invH, s);
   HIPCHK(h, hipMemsetAsync(h->d_K0, 0, (size_t)h->ldk * h->ldk * sizeof(double), s));
+  h->npairs = (int)pairs.size();
+  h->dep_col = dep_col;
   launch_coarse_k0(g, h->d_cn, h->d_pairs, (int)pairs.size(), h->d_mask,
                    h->d_psi, h->d_W, h->d_K0, h->ldk, h->invH, s);
   HIPCHK(h, hipMemsetAsync(h->d_dropped, 0, sizeof(int), s));
-  launch_k0_pinv(h->d_K0, h->ldk, h->nc, h->d_sdiag, h->d_P, h->d_Lp, h->d_Rp,
-                 kPivotDrop, h->d_dropped, s);
+  launch_k0_pinv(h->d_K0, h->ldk, h->nc, dep_col, h->d_sdiag, h->d_P, h->d_Lp,
+                 h->d_Rp, kPivotDrop, h->d_dropped, s);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipMemcpyAsync(h->h_int + 1, h->d_dropped, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipEventRecord(e1, s));
@@ -2235,6 +2254,26 @@ extern "C" msp_status msp_coarse_basis(msp_handle* h, double* phi,
   launch_export_basis(h->g, h->d_cn, h->d_col_node, h->nc, h->d_mask, h->d_psi,
                       phi, h->invH, s);
   HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(s));
+  return MSP_OK;
+}
+
+extern "C" msp_status msp_coarse_matrix(msp_handle* h, int32_t which,
+                                        double* out, hipStream_t s) {
+  if (!h || !out || (which != 0 && which != 1))
+    return fail(h, MSP_E_INVALID, "bad argument");
+  if (need_2d(h) != MSP_OK) return MSP_E_INVALID;
+  if (!h->setup_ok) return fail(h, MSP_E_STATE, "no setup");
+  const size_t bytes = (size_t)h->ldk * h->ldk * sizeof(double);
+  if (which == 1) {
+    HIPCHK(h, hipMemcpyAsync(out, h->d_K0, bytes, hipMemcpyDeviceToDevice, s));
+  } else {
+    // the setup's K Phi columns are still held; redo the block products
+    HIPCHK(h, hipMemsetAsync(out, 0, bytes, s));
+    launch_coarse_k0(h->g, h->d_cn, h->d_pairs, h->npairs, h->d_mask,
+                     h->d_psi, h->d_W, out, h->ldk, h->invH, s);
+    HIPCHK(h, hipGetLastError());
+  }
   HIPCHK(h, hipStreamSynchronize(s));
   return MSP_OK;
 }
