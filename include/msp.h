@@ -267,6 +267,42 @@ msp_status msp_kernel_timing(msp_handle* h, int32_t enable,
                              int64_t* launches_host, double* total_ms_host,
                              int32_t n);
 
+/* ---- the design update around the state solve (Section 1) ---- */
+
+/*
+ * Gradient of an objective with respect to the element densities,
+ * Section 1's formula d g/d rho_e = -u^T (dK/d rho_e) u for the compliance
+ * f^T u, under the SIMP law of the handle:
+ *   dg_dev[e] = -p rho_e^(p-1) (E0 - Emin) lam_e^T K^_e u_e
+ * (K^_e the unit-modulus element matrix, u_e / lam_e the element's DOFs).
+ * lam_dev = NULL means lam = u (compliance); otherwise lam is the adjoint
+ * solution of K lam = l for an objective l^T u.  rho_dev, dg_dev: nel
+ * doubles; u_dev, lam_dev: n doubles.  2D and 3D handles.  dg_dev must not
+ * alias an input.  Errors: MSP_E_INVALID, MSP_E_DEVICE.
+ */
+msp_status msp_sensitivity(msp_handle* h, const double* rho_dev,
+                           const double* u_dev, const double* lam_dev,
+                           double* dg_dev, hipStream_t stream);
+
+/*
+ * One optimality-criteria density update (the method Section 1 names for
+ * the design step, after Bendsoe and Sigmund): with B_e = max(0, -dg_e)/Lam,
+ *   rho_new[e] = clamp(rho_e sqrt(B_e), max(0, rho_e - move),
+ *                      min(1, rho_e + move)),
+ * the multiplier Lam chosen on the device (a logarithmic bracketing pass,
+ * then passes that split the bracket 33-fold, to a relative width of
+ * 1e-13) so that sum_e rho_new[e] = volfrac * nel (equal element volumes).
+ * If even Lam = 2^75 leaves the volume above the target, Lam = 2^75.  No
+ * density filter.  rho_dev, dg_dev, rho_new_dev: nel doubles (rho_new_dev
+ * must not alias the inputs); *lam_host receives Lam (may be NULL).
+ * Errors: MSP_E_INVALID (volfrac or move outside (0, 1]), MSP_E_NOMEM,
+ * MSP_E_DEVICE, MSP_E_BREAKDOWN (the search did not converge).
+ */
+msp_status msp_oc_update(msp_handle* h, const double* rho_dev,
+                         const double* dg_dev, double volfrac, double move,
+                         double* rho_new_dev, double* lam_host,
+                         hipStream_t stream);
+
 /* ---- batches: the PCG solves of many problems in lockstep ---- */
 
 typedef struct msp_batch msp_batch;

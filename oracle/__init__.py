@@ -21,7 +21,9 @@ computes, plainly and slowly, in float64:
   and its rotation enrichment (Section 4.2);
 * the preconditioner M_EH+Rot, and M_EH without rotations (Section 4.3,
   Table 1);
-* PCG and the Lanczos condition estimate (Section 2 and Section 5).
+* PCG and the Lanczos condition estimate (Section 2 and Section 5);
+* the density gradient of the compliance (or of l^T u through an adjoint)
+  and one optimality-criteria design update (Section 1), in ``topopt``.
 
 Functions pinned by no independent check say "parity unpinned" in their
 docstring.  At the time of writing every function here has a pin in

@@ -65,7 +65,7 @@ EXPORTS = ["msp_create", "msp_destroy", "msp_last_error", "msp_set_densities",
            "msp_server_add_run", "msp_server_submit", "msp_server_step",
            "msp_server_result", "msp_server_stats", "msp_set_reuse",
            "msp_server_set_reuse", "msp_vec_dot_noalloc",
-           "msp_coarse_matrix"]
+           "msp_coarse_matrix", "msp_sensitivity", "msp_oc_update"]
 
 KERNEL_NAMES = ["level1_apply", "cg_matvec", "heat_eigen", "combine",
                 "coarse_restrict", "local_factor"]
@@ -101,6 +101,9 @@ def load_library(path=LIB_PATH):
     L.msp_vec_dot.argtypes = [ctypes.c_int64, vp, vp, vp,
                               ctypes.POINTER(ctypes.c_double)]
     L.msp_coarse_matrix.argtypes = [vp, i32, vp, vp]
+    L.msp_sensitivity.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.msp_oc_update.argtypes = [vp, vp, vp, dbl, dbl, vp,
+                                ctypes.POINTER(ctypes.c_double), vp]
     L.msp_vec_dot_noalloc.argtypes = [ctypes.c_int64, vp, vp, vp, vp]
     L.msp_query.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     L.msp_kernel_timing.argtypes = [vp, i32, vp, vp, i32]
@@ -277,6 +280,25 @@ class Solver:
         self._check(self.L.msp_coarse_matrix(self.h, int(which), _ptr(out),
                                              _stream()))
         return out[:nc, :nc]
+
+    def sensitivity(self, rho, u, lam=None):
+        """d g / d rho_e (compliance when lam is None), nel doubles."""
+        import torch
+        out = torch.empty_like(rho)
+        self._check(self.L.msp_sensitivity(
+            self.h, _ptr(rho), _ptr(u), None if lam is None else _ptr(lam),
+            _ptr(out), _stream()))
+        return out
+
+    def oc_update(self, rho, dg, volfrac, move=0.2):
+        """One optimality-criteria step; returns (rho_new, multiplier)."""
+        import torch
+        out = torch.empty_like(rho)
+        lam = ctypes.c_double()
+        self._check(self.L.msp_oc_update(self.h, _ptr(rho), _ptr(dg),
+                                         float(volfrac), float(move), _ptr(out),
+                                         ctypes.byref(lam), _stream()))
+        return out, lam.value
 
     def kernel_timing(self, enable=-1):
         """Launch counts and summed event times (ms) of the tracked kernels

@@ -20,8 +20,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmsp.so")
 
-SOURCES = ["k_vec.hip", "k_local.hip", "k_coarse.hip", "noalloc.hip",
-           "runtime.cpp", "elements.cpp"]
+SOURCES = ["k_vec.hip", "k_local.hip", "k_coarse.hip", "k_topo.hip",
+           "noalloc.hip", "runtime.cpp", "elements.cpp"]
 
 ARCH = os.environ.get("MSP_OFFLOAD_ARCH", "gfx950")
 # packed FP32 instructions are disabled for all device code
@@ -54,7 +54,7 @@ def build(verbose=True):
     """Compile every source and link libmsp.so; returns the library path."""
     with tempfile.TemporaryDirectory(prefix="msp_build_") as tmp:
         objs = [os.path.join(tmp, s + ".o") for s in SOURCES]
-        with concurrent.futures.ThreadPoolExecutor(max_workers=6) as ex:
+        with concurrent.futures.ThreadPoolExecutor(max_workers=7) as ex:
             futs = [ex.submit(_compile, s, o) for s, o in zip(SOURCES, objs)]
             for f in futs:
                 src, msgs = f.result()

@@ -60,6 +60,16 @@ int launch_heat_eigen(const Geom&, const SysDesc*, int, const double*,
                        int, double, double, void*, int*, int*, double*, float*,
                        double*, int*, int*, int*, const int*, int, hipStream_t);
 size_t eig_state_bytes();
+// k_topo.hip
+void launch_sensitivity(const Geom&, int, const double*, const double*,
+                        const double*, const double*, double, double, double*,
+                        hipStream_t);
+size_t oc_state_bytes();
+int oc_blocks(long long);
+int oc_candidates();
+void oc_result(const void*, double*, int*);
+void launch_oc(long long, const double*, const double*, double, double, double,
+               void*, double*, int, double*, hipStream_t);
 // k_coarse.hip
 
 void launch_coarse_kphi(const Geom&, const CoarseNode*, const int*, int,
@@ -235,6 +245,9 @@ struct msp_handle {
   bool rebuild_due = false;        // a reused setup took too many iterations
   int nc = 0, ldk = 0, rank = 0, cap_hits = 0;
   int npairs = 0, dep_col = -1;     // K_0 blocks; dependent column dropped (-1 none)
+  void* d_oc = nullptr;            // optimality-criteria search state
+  double* d_oc_part = nullptr;     // its per-workgroup volume partials
+  void* h_oc = nullptr;            // pinned host copy of the state
   int eig_unconverged = 0;         // neighbourhoods stopped at the iteration limit
   std::vector<int> nsel_h;
   std::vector<double> lam_h;
@@ -508,6 +521,9 @@ extern "C" const char* msp_last_error(const msp_handle* h) {
 
 extern "C" msp_status msp_destroy(msp_handle* h) {
   if (!h) return MSP_OK;
+  if (h->d_oc) (void)hipFree(h->d_oc);
+  if (h->d_oc_part) (void)hipFree(h->d_oc_part);
+  if (h->h_oc) (void)hipHostFree(h->h_oc);
   void* bufs[] = {h->d_elem, h->d_mask, h->d_dflag, h->d_E, h->d_subs,
                   h->d_omegas, h->d_sys_grid, h->d_sub_pack, h->d_om_pack, h->d_S64, h->d_S32, h->d_metric,
                   h->d_use64, h->d_lsol, h->d_gmid, h->d_Som,
@@ -1194,6 +1210,50 @@ extern "C" msp_status msp_apply_K(msp_handle* h, const double* x, double* y,
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(s));
   timer_flush(h);
+  return MSP_OK;
+}
+
+extern "C" msp_status msp_sensitivity(msp_handle* h, const double* rho,
+                                      const double* u, const double* lam,
+                                      double* dg, hipStream_t s) {
+  if (!h || !rho || !u || !dg) return fail(h, MSP_E_INVALID, "null argument");
+  if (dg == u || dg == rho || (lam && dg == lam))
+    return fail(h, MSP_E_INVALID, "dg must not alias the inputs");
+  const double scale = h->desc.penal * (h->desc.E0 - h->desc.Emin);
+  launch_sensitivity(h->g, h->dim, h->d_elem, rho, u, lam ? lam : u, scale,
+                     h->desc.penal - 1.0, dg, s);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(s));
+  return MSP_OK;
+}
+
+extern "C" msp_status msp_oc_update(msp_handle* h, const double* rho,
+                                    const double* dg, double volfrac,
+                                    double move, double* rho_new,
+                                    double* lam_host, hipStream_t s) {
+  if (!h || !rho || !dg || !rho_new) return fail(h, MSP_E_INVALID, "null argument");
+  if (!(volfrac > 0.0 && volfrac <= 1.0) || !(move > 0.0 && move <= 1.0))
+    return fail(h, MSP_E_INVALID, "volfrac and move must lie in (0, 1]");
+  if (rho_new == rho || rho_new == dg)
+    return fail(h, MSP_E_INVALID, "rho_new must not alias the inputs");
+  if (!h->d_oc) {
+    HIPCHK(h, hipMalloc(&h->d_oc, oc_state_bytes()));
+    HIPCHK(h, hipMalloc((void**)&h->d_oc_part,
+                        (size_t)oc_blocks(h->n_elems) * oc_candidates() * sizeof(double)));
+    HIPCHK(h, hipHostMalloc(&h->h_oc, oc_state_bytes(), 0));
+  }
+  constexpr int kOcPasses = 12;        // one bracketing pass, eleven narrowing
+  constexpr double kOcRelTol = 1e-13;
+  launch_oc(h->n_elems, rho, dg, move, volfrac * (double)h->n_elems, kOcRelTol,
+            h->d_oc, h->d_oc_part, kOcPasses, rho_new, s);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(h->h_oc, h->d_oc, oc_state_bytes(), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  double lam = 0.0;
+  int done = 0;
+  oc_result(h->h_oc, &lam, &done);
+  if (lam_host) *lam_host = lam;
+  if (!done) return fail(h, MSP_E_BREAKDOWN, "optimality-criteria multiplier search did not converge");
   return MSP_OK;
 }
 
