@@ -53,8 +53,10 @@ def parse():
                          "topopt: design loop (solve, gradient, OC step)")
     ap.add_argument("--topopt-steps", type=int, default=12)
     ap.add_argument("--topopt-emin", type=float, default=1e-6)
-    ap.add_argument("--reuse-age", type=int, default=4,
+    ap.add_argument("--reuse-age", type=int, default=1,
                     help="design steps a setup may be reused (topopt)")
+    ap.add_argument("--serve-reuse-age", type=int, default=0,
+                    help="requests a run's setup may be reused (serving)")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--serve-runs", type=int, default=32)
     ap.add_argument("--serve-requests", type=int, default=64)
@@ -270,8 +272,8 @@ def serving_workload(torch, args):
                      torch.tensor(p.f, device="cuda"), torch.tensor(fa, device="cuda")))
     arrivals = np.cumsum(rng.exponential(1.0 / args.serve_rate, len(reqs)))
     sv = msp.Server(250 << 30, 16)
-    if args.reuse_age > 0:
-        sv.set_reuse(args.reuse_age, 0)
+    if args.serve_reuse_age > 0:
+        sv.set_reuse(args.serve_reuse_age, 0)
     rid = [sv.add_run(p.desc, p.fixed) for p in runs]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -307,7 +309,7 @@ def serving_workload(torch, args):
         "wall_seconds": round(wall, 3),
         "requests_converged_to_1e-8": conv,
         "chunks": int(st["chunks"]),
-        "reuse_age": args.reuse_age,
+        "reuse_age": args.serve_reuse_age,
         "setups_built": int(st["setups_built"]),
         "setups_reused": int(st["setups_reused"]),
     }
@@ -320,8 +322,10 @@ def topopt_workload(torch, args):
     step), the density gradient and an optimality-criteria update (volume
     fraction 0.4, move 0.2), all on the device.  Run twice: rebuilding the
     preconditioner at every step, and reusing a setup for up to
-    --reuse-age steps unless a reused solve takes over 1.25x the iterations
-    of the solve right after a rebuild (Section 1's update strategy)."""
+    --reuse-age steps while a reused solve stays within the iterations of
+    the solve right after a rebuild plus the iterations one setup costs
+    (Section 1's update strategy; past that limit the solve rebuilds and
+    continues)."""
     import inputs
     import paper_2006_13387_amd as msp
     p = inputs.config(1, Emin=args.topopt_emin, precision=1)
@@ -343,8 +347,11 @@ def topopt_workload(torch, args):
         for t in range(args.topopt_steps):
             s.set_densities(rho)
             u, info = s.solve(f, u=u, warm=t > 0, rtol=1e-8)
-            if age > 0 and not info["setup_reused"]:
-                lim = int(1.25 * info["iters"]) + 1
+            if (age > 0 and not info["setup_reused"] and info["t_setup_ms"] > 0
+                    and (lim == 0 or info["iters"] <= lim)):
+                # a solve on its own fresh setup (not one stopped at the limit)
+                per_it = info["t_solve_ms"] / max(info["iters"], 1)
+                lim = info["iters"] + int(info["t_setup_ms"] / per_it) + 1
                 s.set_reuse(age, lim)
             iters.append(info["iters"])
             comps.append(info["compliance"])

@@ -164,10 +164,13 @@ msp_status msp_solve(msp_handle* h, const double* f_dev, double* u_dev,
  * msp_set_densities calls: msp_solve (and the single-step applies, batches
  * and serving) then run PCG on the new K(rho) preconditioned by the older
  * setup, which is still symmetric positive definite, so the solution is
- * that of the new system to rtol.  With iter_limit > 0, a solve on a reused
- * setup that takes more than iter_limit iterations makes the next solve
- * rebuild.  max_age = 0 (the default) rebuilds at every density change.
- * msp_solve_info.setup_reused tells which solves ran on an older setup.
+ * that of the new system to rtol.  With iter_limit > 0, msp_solve stops a
+ * solve on a reused setup after iter_limit iterations, rebuilds the setup
+ * for the current densities and continues from the iterate it reached
+ * (msp_solve_info.iters counts both parts; batches and serving instead make
+ * the next solve rebuild).  max_age = 0 (the default) rebuilds at every
+ * density change.  msp_solve_info.setup_reused tells which solves finished
+ * on an older setup.
  * Errors: MSP_E_INVALID for negative arguments.
  */
 msp_status msp_set_reuse(msp_handle* h, int32_t max_age, int32_t iter_limit);

@@ -1513,15 +1513,28 @@ extern "C" msp_status msp_solve(msp_handle* h, const double* f, double* u,
     if (st != MSP_OK) return st;
     t_setup = h->t_setup_ms;
   }
-  const bool reused = !setup_fresh(h);
+  bool reused = !setup_fresh(h);
   msp_status last = MSP_OK;
   msp_solve_info tmp{};
   msp_solve_info* inf = info ? info : &tmp;
   for (int k = 0; k < nrhs; ++k) {
-    msp_status st = solve_one(h, f + (long long)k * h->n_dofs,
-                              u + (long long)k * h->n_dofs, warm, rtol, maxit,
-                              s, inf);
+    double* uk = u + (long long)k * h->n_dofs;
+    const double* fk = f + (long long)k * h->n_dofs;
+    // on a reused setup with an iteration limit: stop at the limit, rebuild
+    // for the current densities and continue from the iterate reached
+    const int lim = (reused && h->reuse_iter_limit > 0) ? std::min(maxit, h->reuse_iter_limit) : maxit;
+    msp_status st = solve_one(h, fk, uk, warm, rtol, lim, s, inf);
     if (st < 0) return st;
+    if (st == MSP_NOT_CONVERGED && lim < maxit) {
+      const int done_iters = inf->iters;
+      msp_status ss = msp_setup(h, s);
+      if (ss != MSP_OK) return ss;
+      t_setup += h->t_setup_ms;
+      reused = false;
+      st = solve_one(h, fk, uk, 1, rtol, maxit - done_iters, s, inf);
+      if (st < 0) return st;
+      inf->iters += done_iters;
+    }
     if (st != MSP_OK) last = st;
     reuse_note_iters(h, reused, inf->iters);
   }
