@@ -110,7 +110,8 @@ struct Geom {
 // are problem e's workgroups).
 struct MatvecArgs {
   Geom g;
-  const double* Ke;
+  double ke[64];              // unit-modulus element matrix, read by every
+                             // lane from the arguments (scalar loads)
   const double* E;
   const uint8_t* mask;
   const double* xin;         // APPLY: x, CG: z, RESID: x

@@ -6,9 +6,15 @@
 // once and no atomics are needed.  A tile of 64 x TY nodes stages its
 // displacements (one-node halo) and the surrounding element moduli in LDS;
 // each thread then sums the contributions of the four elements that share
-// its node.  Rows of clamped DOFs are zero.  The tile height (4, 8 or 16
-// node rows, 256 threads) is chosen per mesh by a short timing at the first
-// densities: taller tiles re-read fewer halo nodes and moduli.
+// its node.  Rows of clamped DOFs are zero.  The tile height (4, 8, 16 or
+// 32 node rows, 256 threads) is a function of the mesh: taller tiles re-read
+// fewer halo nodes and moduli.  Tiles are ordered so that each XCD takes a
+// contiguous range of them (overlapping halos meet in its L2); the product
+// alone on large meshes runs in persistent workgroups that load the next
+// tile while computing the current one.  The element matrix comes in the
+// kernel arguments (scalar loads shared by the wave).
+#include <algorithm>
+
 #include "common.h"
 #include "dev.h"
 
@@ -16,7 +22,10 @@ namespace msp {
 
 constexpr int MV_TX = 64;        // nodes per tile row
 constexpr int MV_NT = 256;       // threads: tile rows are processed 4 at a time
-constexpr int MV_TYMAX = 16;     // tallest tile (rows of nodes)
+constexpr int MV_TYMAX = 16;     // tallest tile of the batched product
+constexpr int MV_TYBIG = 32;     // tallest tile of the single-problem product
+constexpr int NUM_XCD = 8;       // workgroups go round-robin to the chip's XCDs
+constexpr int kNumCUsVec = 256;  // compute units of the chip
 
 enum : int { MV_APPLY = 0, MV_CG = 1, MV_RESID = 2 };
 
@@ -34,15 +43,17 @@ k_simp(const double* __restrict__ rho, double* __restrict__ E, int n,
   E[i] = Emin + pow(r, penal) * (E0 - Emin);
 }
 
-// LDS of one stiffness-product tile (sized for the tallest tile)
-struct MvLds {
-  double2 xs[(MV_TYMAX + 2) * (MV_TX + 2)];
-  double es[(MV_TYMAX + 1) * (MV_TX + 1)];
-  double ks[64];
+// LDS of one stiffness-product tile of TYL node rows (or fewer)
+template <int TYL>
+struct MvLdsT {
+  double2 xs[(TYL + 2) * (MV_TX + 2)];
+  double es[(TYL + 1) * (MV_TX + 1)];
   double red[2 * (MV_NT / 64)];
   int shi;
   double beta;
 };
+typedef MvLdsT<MV_TYMAX> MvLds;
+
 
 // Tile (bx, by) of a gx x gy grid of 64 x TY node tiles.
 // MODE MV_APPLY : y = K x with x treated as 0 at clamped DOFs.
@@ -56,10 +67,11 @@ struct MvLds {
 //                 read p_old in their halos while this tile writes p_new.
 // MODE MV_RESID : r = f - K x (x is already 0 at clamped DOFs); partial
 //                 sums of r.r, f.f and f.x over free DOFs.
-template <int MODE, int TY>
+template <int MODE, int TY, typename LT>
 __device__ __forceinline__ void matvec_body(const MatvecArgs& a, int bx, int by,
-                                            int gx, int gy, MvLds& L) {
-  static_assert(TY % 4 == 0 && TY <= MV_TYMAX, "tile height");
+                                            int gx, int gy, LT& L) {
+  static_assert(TY % 4 == 0 && sizeof(L.xs) >= (TY + 2) * (MV_TX + 2) * sizeof(double2),
+                "tile height");
   constexpr int RPT = TY / 4;                // rows per thread
   constexpr int NXN = (TY + 2) * (MV_TX + 2);               // halo nodes
   constexpr int NEN = (TY + 1) * (MV_TX + 1);               // moduli
@@ -115,7 +127,6 @@ __device__ __forceinline__ void matvec_body(const MatvecArgs& a, int bx, int by,
     ev[k] = (t < NEN && ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny)
                 ? a.E[(long long)ey * g.nx + ex] : 0.0;
   }
-  const double kv = tid < 64 ? a.Ke[tid] : 0.0;
   double beta = 0.0;
   if (MODE == MV_CG) {
     const double2 sums = block_sum2<MV_NT>(srz, szq, L.red);
@@ -140,13 +151,12 @@ __device__ __forceinline__ void matvec_body(const MatvecArgs& a, int bx, int by,
     beta = L.beta;
     if (!finite(beta)) return;
   }
-  if (tid < 64) L.ks[tid] = kv;
 #pragma unroll
   for (int k = 0; k < NXS; ++k) {
     const int t = tid + k * MV_NT;
     if (t < NXN) {
       double2 v = xu[k];
-      if (MODE == MV_CG) v = make_double2(xu[k].x + beta * xp[k].x, xu[k].y + beta * xp[k].y);
+      if (MODE == MV_CG) v = make_double2(fma(beta, xp[k].x, xu[k].x), fma(beta, xp[k].y, xu[k].y));
       if (MODE == MV_APPLY) v = make_double2(xm[k].x ? 0.0 : xu[k].x, xm[k].y ? 0.0 : xu[k].y);
       L.xs[t] = v;
     }
@@ -176,11 +186,14 @@ __device__ __forceinline__ void matvec_body(const MatvecArgs& a, int bx, int by,
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           const double2 u = L.xs[(j + dy + (b >> 1)) * (MV_TX + 2) + (i + dx + (b & 1))];
-          s0 += L.ks[(2 * av) * 8 + 2 * b] * u.x + L.ks[(2 * av) * 8 + 2 * b + 1] * u.y;
-          s1 += L.ks[(2 * av + 1) * 8 + 2 * b] * u.x + L.ks[(2 * av + 1) * 8 + 2 * b + 1] * u.y;
+          // explicit FMAs: the single and the batched kernel round alike
+          s0 = fma(a.ke[(2 * av) * 8 + 2 * b], u.x, s0);
+          s0 = fma(a.ke[(2 * av) * 8 + 2 * b + 1], u.y, s0);
+          s1 = fma(a.ke[(2 * av + 1) * 8 + 2 * b], u.x, s1);
+          s1 = fma(a.ke[(2 * av + 1) * 8 + 2 * b + 1], u.y, s1);
         }
-        y0 += ee * s0;
-        y1 += ee * s1;
+        y0 = fma(ee, s0, y0);
+        y1 = fma(ee, s1, y1);
       }
     }
     if (own) {
@@ -194,16 +207,16 @@ __device__ __forceinline__ void matvec_body(const MatvecArgs& a, int bx, int by,
         const double2 pn = L.xs[(j + 1) * (MV_TX + 2) + (i + 1)];
         reinterpret_cast<double2*>(a.pout)[node] = pn;
         reinterpret_cast<double2*>(a.yout)[node] = make_double2(y0, y1);
-        d0 += pn.x * y0 + pn.y * y1;
+        d0 = fma(pn.y, y1, fma(pn.x, y0, d0));
       } else {
         const double2 ff = reinterpret_cast<const double2*>(a.f)[node];
         const double f0 = m.x ? 0.0 : ff.x, f1 = m.y ? 0.0 : ff.y;
         const double r0 = m.x ? 0.0 : f0 - y0, r1 = m.y ? 0.0 : f1 - y1;
         reinterpret_cast<double2*>(a.yout)[node] = make_double2(r0, r1);
         const double2 xx = L.xs[(j + 1) * (MV_TX + 2) + (i + 1)];
-        d0 += r0 * r0 + r1 * r1;
-        d1 += f0 * f0 + f1 * f1;
-        d2 += f0 * xx.x + f1 * xx.y;
+        d0 = fma(r1, r1, fma(r0, r0, d0));
+        d1 = fma(f1, f1, fma(f0, f0, d1));
+        d2 = fma(f1, xx.y, fma(f0, xx.x, d2));
       }
     }
   }
@@ -233,10 +246,131 @@ __device__ __forceinline__ void matvec_dispatch(const MatvecArgs& a, int bx,
   else matvec_body<MODE, 16>(a, bx, by, gx, gy, L);
 }
 
+// Tile of workgroup k of a 1D grid of nb tiles: the hardware hands
+// workgroups to the XCDs in turn (k % 8), so XCD x gets the contiguous
+// range of tiles x * nb/8 .. and neighbouring tiles, whose halos overlap,
+// meet in the same L2.
+__device__ __forceinline__ int xcd_tile(int k, int nb) {
+  const int q = nb / NUM_XCD, rem = nb - q * NUM_XCD;
+  const int x = k % NUM_XCD, slot = k / NUM_XCD;
+  return x * q + min(x, rem) + slot;
+}
+
 template <int MODE, int TY>
 __global__ void __launch_bounds__(MV_NT) k_matvec(MatvecArgs a) {
-  __shared__ MvLds L;
-  matvec_body<MODE, TY>(a, blockIdx.x, blockIdx.y, gridDim.x, gridDim.y, L);
+  __shared__ MvLdsT<TY> L;
+  const int gx = (a.g.nnx + MV_TX - 1) / MV_TX;
+  const int gy = (a.g.nny + TY - 1) / TY;
+  const int t = xcd_tile(blockIdx.x, gx * gy);
+  matvec_body<MODE, TY>(a, t % gx, t / gx, gx, gy, L);
+}
+
+// y = K x (x treated as 0 at clamped DOFs, y = 0 there) on meshes of many
+// tiles: persistent workgroups, eight groups of them, one per XCD, each
+// group walking the contiguous range of tiles of its XCD with the group's
+// stride (neighbouring tiles, whose halos overlap, meet in the same L2).
+// The next tile's x halo, clamp flags and moduli are loaded into registers
+// while the current tile is computed from LDS, so the loads of one tile
+// overlap the arithmetic of the previous one.
+template <int TY>
+__global__ void __launch_bounds__(MV_NT)
+k_matvec_apply_pf(MatvecArgs a) {
+  __shared__ MvLdsT<TY> L;
+  __shared__ uchar2 ms[(TY + 2) * (MV_TX + 2)];
+  constexpr int RPT = TY / 4;
+  constexpr int NXN = (TY + 2) * (MV_TX + 2);
+  constexpr int NEN = (TY + 1) * (MV_TX + 1);
+  constexpr int NXS = (NXN + MV_NT - 1) / MV_NT;
+  constexpr int NES = (NEN + MV_NT - 1) / MV_NT;
+  const Geom& g = a.g;
+  const int tid = threadIdx.x;
+  const int gx = (g.nnx + MV_TX - 1) / MV_TX, gy = (g.nny + TY - 1) / TY;
+  const int nt = gx * gy;
+  const int xcd = blockIdx.x % NUM_XCD, stride = gridDim.x / NUM_XCD;
+  const int q = nt / NUM_XCD, rem = nt - q * NUM_XCD;
+  const int t_end = xcd * q + min(xcd, rem) + q + (xcd < rem ? 1 : 0);
+  int t = xcd * q + min(xcd, rem) + blockIdx.x / NUM_XCD;
+  if (t >= t_end) return;
+  double2 xu[NXS];
+  uchar2 xm[NXS];
+  double ev[NES];
+  auto load = [&](int tile) {
+    const int bx0 = (tile % gx) * MV_TX - 1, by0 = (tile / gx) * TY - 1;
+#pragma unroll
+    for (int k = 0; k < NXS; ++k) {
+      const int u = tid + k * MV_NT;
+      const int x = bx0 + u % (MV_TX + 2), y = by0 + u / (MV_TX + 2);
+      xu[k] = make_double2(0.0, 0.0);
+      xm[k] = make_uchar2(1, 1);
+      if (u < NXN && x >= 0 && x < g.nnx && y >= 0 && y < g.nny) {
+        const long long node = (long long)y * g.nnx + x;
+        xu[k] = reinterpret_cast<const double2*>(a.xin)[node];
+        xm[k] = reinterpret_cast<const uchar2*>(a.mask)[node];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NES; ++k) {
+      const int u = tid + k * MV_NT;
+      const int ex = bx0 + u % (MV_TX + 1), ey = by0 + u / (MV_TX + 1);
+      ev[k] = (u < NEN && ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny)
+                  ? a.E[(long long)ey * g.nx + ex] : 0.0;
+    }
+  };
+  load(t);
+  for (;;) {
+#pragma unroll
+    for (int k = 0; k < NXS; ++k) {
+      const int u = tid + k * MV_NT;
+      if (u < NXN) {
+        L.xs[u] = make_double2(xm[k].x ? 0.0 : xu[k].x, xm[k].y ? 0.0 : xu[k].y);
+        ms[u] = xm[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NES; ++k) {
+      const int u = tid + k * MV_NT;
+      if (u < NEN) L.es[u] = ev[k];
+    }
+    __syncthreads();
+    const int bx = t % gx, by = t / gx;
+    const int tn = t + stride;
+    if (tn < t_end) load(tn);
+    const int i = tid % MV_TX;
+#pragma unroll
+    for (int rr = 0; rr < RPT; ++rr) {
+      const int j = tid / MV_TX + 4 * rr;
+      const int x = bx * MV_TX + i, y = by * TY + j;
+      double y0 = 0.0, y1 = 0.0;
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy) {
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+          const double ee = L.es[(j + dy) * (MV_TX + 1) + (i + dx)];
+          const int av = (1 - dx) + 2 * (1 - dy);
+          const double* ke = a.ke;
+          double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const double2 u = L.xs[(j + dy + (b >> 1)) * (MV_TX + 2) + (i + dx + (b & 1))];
+            s0 = fma(ke[(2 * av) * 8 + 2 * b], u.x, s0);
+            s0 = fma(ke[(2 * av) * 8 + 2 * b + 1], u.y, s0);
+            s1 = fma(ke[(2 * av + 1) * 8 + 2 * b], u.x, s1);
+            s1 = fma(ke[(2 * av + 1) * 8 + 2 * b + 1], u.y, s1);
+          }
+          y0 = fma(ee, s0, y0);
+          y1 = fma(ee, s1, y1);
+        }
+      }
+      if (x < g.nnx && y < g.nny) {
+        const uchar2 m = ms[(j + 1) * (MV_TX + 2) + (i + 1)];
+        reinterpret_cast<double2*>(a.yout)[(long long)y * g.nnx + x] =
+            make_double2(m.x ? 0.0 : y0, m.y ? 0.0 : y1);
+      }
+    }
+    __syncthreads();
+    if (tn >= t_end) break;
+    t = tn;
+  }
 }
 
 // The CG stiffness products of several problems in one launch.
@@ -485,21 +619,17 @@ void launch_simp(const double* rho, double* E, int n, double E0, double Emin,
                      E0, Emin, penal, err);
 }
 
-static dim3 mv_grid(const Geom& g, int ty) {
-  return dim3((g.nnx + MV_TX - 1) / MV_TX, (g.nny + ty - 1) / ty);
-}
-
 int matvec_blocks(const Geom& g, int ty) {
-  const dim3 gr = mv_grid(g, ty);
-  return gr.x * gr.y;
+  return ((g.nnx + MV_TX - 1) / MV_TX) * ((g.nny + ty - 1) / ty);
 }
 
 template <int MODE>
 static void launch_mv(const MatvecArgs& a, hipStream_t s) {
-  const dim3 gr = mv_grid(a.g, a.ty);
+  const dim3 gr(matvec_blocks(a.g, a.ty));
   if (a.ty == 4) hipLaunchKernelGGL((k_matvec<MODE, 4>), gr, dim3(MV_NT), 0, s, a);
   else if (a.ty == 8) hipLaunchKernelGGL((k_matvec<MODE, 8>), gr, dim3(MV_NT), 0, s, a);
-  else hipLaunchKernelGGL((k_matvec<MODE, 16>), gr, dim3(MV_NT), 0, s, a);
+  else if (a.ty == 16) hipLaunchKernelGGL((k_matvec<MODE, 16>), gr, dim3(MV_NT), 0, s, a);
+  else hipLaunchKernelGGL((k_matvec<MODE, MV_TYBIG>), gr, dim3(MV_NT), 0, s, a);
 }
 
 static MatvecArgs mv_args(const Geom& g, int ty, const double* Ke, const double* E,
@@ -507,7 +637,7 @@ static MatvecArgs mv_args(const Geom& g, int ty, const double* Ke, const double*
   MatvecArgs a{};
   a.g = g;
   a.ty = ty;
-  a.Ke = Ke;
+  for (int i = 0; i < 64; ++i) a.ke[i] = Ke[i];
   a.E = E;
   a.mask = mask;
   return a;
@@ -519,7 +649,20 @@ void launch_apply_K(const Geom& g, int ty, const double* Ke, const double* E,
   MatvecArgs a = mv_args(g, ty, Ke, E, mask);
   a.xin = x;
   a.yout = y;
-  launch_mv<MV_APPLY>(a, s);
+  const int nt = matvec_blocks(g, ty);
+  if (nt < 16 * kNumCUsVec || ty < 8) {
+    launch_mv<MV_APPLY>(a, s);
+    return;
+  }
+  // persistent: as many workgroups as fit on the chip at once (registers
+  // allow four per CU with 8-row tiles, three with taller ones), a multiple
+  // of the XCD count
+  const int per_cu = ty == 8 ? 4 : 3;
+  const int per_xcd = std::min((nt + NUM_XCD - 1) / NUM_XCD, per_cu * kNumCUsVec / NUM_XCD);
+  const dim3 gr(per_xcd * NUM_XCD);
+  if (ty == 8) hipLaunchKernelGGL(k_matvec_apply_pf<8>, gr, dim3(MV_NT), 0, s, a);
+  else if (ty == 16) hipLaunchKernelGGL(k_matvec_apply_pf<16>, gr, dim3(MV_NT), 0, s, a);
+  else hipLaunchKernelGGL(k_matvec_apply_pf<MV_TYBIG>, gr, dim3(MV_NT), 0, s, a);
 }
 
 MatvecArgs cg_matvec_args(const Geom& g, int ty, const double* Ke,

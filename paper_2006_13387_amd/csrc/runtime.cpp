@@ -605,16 +605,19 @@ static msp_status create_3d(const msp_problem_desc* d, const uint8_t* fixed,
   return MSP_OK;
 }
 
-// Stiffness-product tile height for this mesh: MSP_MV_TILE (4, 8 or 16)
-// if set, else the tallest tile that still gives at least four workgroups
-// per CU (4 when none does).  A function of the mesh alone, so every handle
-// of the same mesh (a served run rebuilt after eviction, a handle in a
-// batch) forms the p.q partial sums over the same tiles and gets the same
-// bits.  Taller tiles re-read fewer halo nodes and moduli.
+// Stiffness-product tile height for this mesh: MSP_MV_TILE (4, 8, 16 or
+// 32) if set, else the tallest tile up to 16 rows that still gives at least
+// four workgroups per CU (4 when none does; 32-row tiles measured slower).  A function of the mesh alone, so
+// every handle of the same mesh (a served run rebuilt after eviction, a
+// handle in a batch) forms the p.q partial sums over the same tiles and
+// gets the same bits.  Taller tiles re-read fewer halo nodes and moduli.
+// Batches take at most 16 (their kernel's LDS is sized for it).
 static int matvec_tile(const Geom& g) {
   const char* env = std::getenv("MSP_MV_TILE");
-  if (env && (std::atoi(env) == 4 || std::atoi(env) == 8 || std::atoi(env) == 16))
-    return std::atoi(env);
+  if (env) {
+    const int t = std::atoi(env);
+    if (t == 4 || t == 8 || t == 16 || t == 32) return t;
+  }
   if (matvec_blocks(g, 16) >= 4 * kNumCUs) return 16;
   if (matvec_blocks(g, 8) >= 4 * kNumCUs) return 8;
   return 4;
@@ -1153,7 +1156,7 @@ static CombineCall cb_args(msp_handle* h, bool l1, bool coarse, const double* r,
 static MatvecArgs mv_cg_args(msp_handle* h, int cur) {
   double* pold = cur ? h->d_p1 : h->d_p0;
   double* pnew = cur ? h->d_p0 : h->d_p1;
-  return cg_matvec_args(h->g, h->mv_ty, h->d_elem, h->d_E, h->d_mask, h->d_z,
+  return cg_matvec_args(h->g, h->mv_ty, h->Ke, h->d_E, h->d_mask, h->d_z,
                         pold, pnew, h->d_q, h->d_sc, h->part_mv, h->part_comb,
                         h->nb_comb, h->d_bhist);
 }
@@ -1205,7 +1208,7 @@ extern "C" msp_status msp_apply_K(msp_handle* h, const double* x, double* y,
   if (h->dim == 3)
     launch_apply_K3(h->g, h->d_elem, h->d_E, h->d_nmask, x, y, s);
   else
-    launch_apply_K(h->g, h->mv_ty, h->d_elem, h->d_E, h->d_mask, x, y, s);
+    launch_apply_K(h->g, h->mv_ty, h->Ke, h->d_E, h->d_mask, x, y, s);
   timer_end(h, KT_MATVEC, tm, s);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(s));
@@ -1338,7 +1341,7 @@ static msp_status seg_launch(SolveRun& R, hipStream_t s) {
   seg.maxit = std::max(1, R.maxit - R.total_iters);
   *h->h_sc = seg;
   HIPCHK(h, hipMemcpyAsync(h->d_sc, h->h_sc, sizeof(CGScalars), hipMemcpyHostToDevice, s));
-  launch_residual(h->g, h->mv_ty, h->d_elem, h->d_E, h->d_mask, h->d_x, R.f,
+  launch_residual(h->g, h->mv_ty, h->Ke, h->d_E, h->d_mask, h->d_x, R.f,
                   h->d_r, h->d_sc, h->part_res, 0, s);
   HIPCHK(h, hipMemsetAsync(h->d_p0, 0, h->n_dofs * sizeof(double), s));
   enqueue_prec(h, 2, h->d_r, nullptr, h->d_z, true, true, true, s);
@@ -1394,7 +1397,7 @@ static msp_status seg_finish(SolveRun& R, hipStream_t s, bool* restart) {
     R.finished = true;
     return MSP_OK;
   }
-  launch_residual(h->g, h->mv_ty, h->d_elem, h->d_E, h->d_mask, h->d_x, R.f,
+  launch_residual(h->g, h->mv_ty, h->Ke, h->d_E, h->d_mask, h->d_x, R.f,
                   h->d_tmp, h->d_sc, h->part_res, 1, s);
   HIPCHK(h, hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(CGScalars), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
@@ -1726,6 +1729,8 @@ extern "C" msp_status msp_batch_solve(msp_batch* b, msp_handle* const* hs_in,
   for (int e = 0; e < n; ++e) {
     if (!hs[e] || !f[e] || !u[e]) return bfail(b, MSP_E_INVALID, "null handle or vector in the batch");
     if (hs[e]->dim != 2) return bfail(b, MSP_E_INVALID, "dim = 3: only the stiffness product is built for 3D meshes");
+    if (hs[e]->mv_ty > 16)
+      return bfail(b, MSP_E_INVALID, "mesh too large for the batched stiffness product (tile height 32)");
     for (int k = 0; k < e; ++k)
       if (hs[k] == hs[e]) return bfail(b, MSP_E_INVALID, "a handle appears twice in the batch");
     if (!hs[e]->have_E) return bfail(b, MSP_E_STATE, "msp_set_densities must come first");
