@@ -236,6 +236,81 @@ def heat_modes(A, M, tau, H, kmax):
     return HeatModes(lam[sel], vec, lam, cap_hit)
 
 
+# --------------------------------------------------------------------------
+# the randomized approximation of the heat eigenproblems (Section 3, the
+# randomized algorithm, applied to the heat pencil as in Section 4.3)
+# --------------------------------------------------------------------------
+
+# Reading: the paper's local solves K u = f with zero-mean forcings f are
+# posed on the Neumann pencil's singular operator; here they use the
+# regularised operator A + SHIFT/H^2 M (1/40 of the threshold tau/H^2 = 2/H^2),
+# u = (A + sigma M)^{-1} M f, which samples the same low eigenspace (the
+# pencil's eigenvectors with weights 1 / (lambda + sigma)).  The forcings
+# keep zero M-mean, and the constant function (the heat operator's null
+# space, its analogue of the rigid-body modes) is added to the snapshots.
+RAND_SHIFT = 0.05
+
+_SM_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_SM_C1 = np.uint64(0xBF58476D1CE4E5B9)
+_SM_C2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(state):
+    """The output of the SplitMix64 generator (Steele, Lea and Flood,
+    "Fast splittable pseudorandom number generators", OOPSLA 2014) whose
+    state is ``state`` before the step: z = state + gamma, then the
+    variant-13 mix.  uint64 in, uint64 out (arithmetic mod 2^64)."""
+    with np.errstate(over="ignore"):
+        z = np.asarray(state, dtype=np.uint64) + _SM_GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _SM_C1
+        z = (z ^ (z >> np.uint64(27))) * _SM_C2
+    return z ^ (z >> np.uint64(31))
+
+
+def forcing_uniform(seed, l, j, p):
+    """Uniform forcing values in [-1, 1) for neighbourhood l, snapshot j and
+    box-local node positions p: the SplitMix64 output at state
+    key ^ (seed * gamma) with key = l * 2^40 + j * 2^24 + p, top 53 bits."""
+    p = np.asarray(p, dtype=np.uint64)
+    key = (np.uint64(l) << np.uint64(40)) | (np.uint64(j) << np.uint64(24)) | p
+    with np.errstate(over="ignore"):
+        z = splitmix64(key ^ (np.uint64(seed) * _SM_GAMMA))
+    return (z >> np.uint64(11)).astype(np.float64) * (2.0 / 9007199254740992.0) - 1.0
+
+
+def heat_modes_randomized(A, M, tau, H, kmax, nsnap, seed, l, pos):
+    """Approximate eigenpairs of A psi = lambda M psi by the randomized
+    algorithm of Section 3: nsnap zero-mean random forcings f_j on omega_l
+    (uniform, positions ``pos`` in omega's node box), local solutions u_j,
+    the space W = span{u_j} + span{1}, an M-orthonormal basis Q of W from the
+    eigendecomposition of its Gram matrix (the SVD of the snapshots in the M
+    inner product; directions below 1e-13 of the largest dropped), and the
+    reduced pencil Q^T A Q.  The Ritz values below tau / H^2 are selected,
+    ascending, at most kmax."""
+    n = A.shape[0]
+    if n == 0:
+        return HeatModes(np.zeros(0), np.zeros((0, 0)), np.zeros(0), False)
+    lim = tau / (H * H)
+    one = np.ones(n)
+    F = np.stack([forcing_uniform(seed, l, j, pos) for j in range(nsnap)], axis=1)
+    w = M @ one
+    F = F - np.outer(one, (w @ F) / (w @ one))          # 1^T M f_j = 0
+    C = (A + (RAND_SHIFT / (H * H)) * M).tocsc()
+    U = spla.splu(C).solve(np.asarray(M @ F))
+    U = np.hstack([U, one[:, None]])
+    G = U.T @ (M @ U)
+    g, V = np.linalg.eigh(0.5 * (G + G.T))
+    keep = g > 1e-13 * g[-1]
+    Q = (U @ V[:, keep]) / np.sqrt(g[keep])[None, :]
+    Ar = Q.T @ (A @ Q)
+    lam, phi = np.linalg.eigh(0.5 * (Ar + Ar.T))
+    vec = Q @ phi
+    below = np.nonzero(lam < lim)[0]
+    cap_hit = len(below) > kmax
+    sel = below[:kmax]
+    return HeatModes(lam[sel], vec[:, sel], lam, cap_hit)
+
+
 def _rotations(desc, c, node_flat):
     """Infinitesimal rotations about coarse node ``c`` scaled by 1/H, as a
     list of (n_nodes, dim) arrays (rigid body rotations of Section 2.1)."""
@@ -264,7 +339,9 @@ class CoarseSpace:
 
 
 def build_coarse_basis(desc, E, fixed, rot=None):
-    """R_0^T = [Phi_1 ... Phi_Nc] of M_EH(+Rot) (Sections 2.1, 4.1, 4.2).
+    """R_0^T = [Phi_1 ... Phi_Nc] of M_EH(+Rot) (Sections 2.1, 4.1, 4.2);
+    with desc["eig_random"] = M > 0 the heat eigenpairs are the randomized
+    approximations of Section 3 from M snapshots (M_EH+Rot;Rand).
 
     Column order: coarse nodes x-fastest; per node, for each component c the
     selected heat modes chi_l psi_j e_c in ascending eigenvalue order, then
@@ -294,7 +371,14 @@ def build_coarse_basis(desc, E, fixed, rot=None):
             key = tuple(dn.tolist())
             if key not in cache:
                 A, M, kept = heat_pencil(desc, E, c, dn)
-                cache[key] = (heat_modes(A, M, tau, H, kmax), kept)
+                if desc.get("eig_random", 0) > 0:
+                    pos = np.searchsorted(node_ids, kept)
+                    hm = heat_modes_randomized(A, M, tau, H, kmax,
+                                               desc["eig_random"],
+                                               desc.get("eig_seed", 0), li, pos)
+                else:
+                    hm = heat_modes(A, M, tau, H, kmax)
+                cache[key] = (hm, kept)
             hm, kept = cache[key]
             ev_l.append(hm.lam)
             seen_l.append(hm.lam_seen)
