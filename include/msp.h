@@ -68,6 +68,12 @@ typedef enum {
  *             except in subdomains whose amplification metric (see
  *             msp_solve_info.fp64_subdomains) shows stiff islands floating
  *             in soft material, which keep FP64 blocks
+ *  eig_random 0: heat eigenpairs by shift-invert subspace iteration to
+ *             convergence; M in 1..31: the randomized approximation of
+ *             Section 3 (M_EH+Rot;Rand) from M zero-mean random forcings,
+ *             their local solutions with A + 0.05/H^2 M and the constant
+ *             function, by Rayleigh-Ritz on that space
+ *  eig_seed   seed of the randomized forcings (SplitMix64, counter-based)
  */
 typedef struct {
   int32_t dim;
@@ -80,6 +86,8 @@ typedef struct {
   int32_t eig_kmax;
   int32_t rot_enrich;
   int32_t precision;
+  int32_t eig_random;
+  uint32_t eig_seed;
 } msp_problem_desc;
 
 typedef struct {

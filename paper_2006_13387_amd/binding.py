@@ -34,7 +34,8 @@ class ProblemDesc(ctypes.Structure):
                 ("penal", ctypes.c_double), ("sub_nel", ctypes.c_int32 * 3),
                 ("overlap", ctypes.c_int32), ("sub_mode", ctypes.c_int32),
                 ("eig_tau", ctypes.c_double), ("eig_kmax", ctypes.c_int32),
-                ("rot_enrich", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("rot_enrich", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("eig_random", ctypes.c_int32), ("eig_seed", ctypes.c_uint32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -169,6 +170,8 @@ def make_desc(d):
     pd.overlap, pd.sub_mode = d["overlap"], d["sub_mode"]
     pd.eig_tau, pd.eig_kmax = d["eig_tau"], d["eig_kmax"]
     pd.rot_enrich, pd.precision = d["rot_enrich"], d["precision"]
+    pd.eig_random = d.get("eig_random", 0)
+    pd.eig_seed = d.get("eig_seed", 0)
     return pd
 
 

@@ -1537,6 +1537,92 @@ k_eig_start(Geom g, const SysDesc* __restrict__ systems,
   if (tid < MAXM) e.theta_old[tid] = 0.0;
 }
 
+// Randomized setup (Section 3, applied to the heat pencils): X = nsnap
+// uniform forcings in [-1, 1) per neighbourhood, SplitMix64 outputs at the
+// state key ^ (seed * gamma), key = l * 2^40 + j * 2^24 + p (l the
+// neighbourhood, j the snapshot, p the node's index in the neighbourhood's
+// box, x fastest), zero on Dirichlet nodes, each shifted to zero M-mean over
+// the kept nodes: f_j -= (w . f_j) / (w . 1), w = M 1 (column sums of the
+// kept mass matrix).  Column nsnap (the last) is zero; it becomes the
+// constant function after the local solves.  Z's first column holds w.
+__global__ void __launch_bounds__(EG_NT)
+k_rand_start(Geom g, const SysDesc* __restrict__ systems,
+             const uint8_t* __restrict__ dflag, const double* __restrict__ E,
+             const double* __restrict__ Me, double* __restrict__ Xw,
+             double* __restrict__ Zw, int m, int nsnap, unsigned int seed,
+             EigState* __restrict__ st) {
+  __shared__ double red[EG_NT / 64 + 1];
+  __shared__ double me[16];
+  const SysDesc s = systems[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int n = s.nxb * s.nyb;
+  double* X = Xw + s.voff * (long long)m;
+  double* w = Zw + s.voff * (long long)m;
+  if (tid < 16) me[tid] = Me[tid];
+  __syncthreads();
+  double wsum = 0.0;
+  for (int node = tid; node < n; node += EG_NT) {
+    const int x = s.x0 + node % s.nxb, y = s.y0 + node / s.nxb;
+    double wi = 0.0;
+    if (!dflag[(long long)y * g.nnx + x]) {
+      for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+          const int ex = x - 1 + dx, ey = y - 1 + dy;
+          if (ex < s.ex0 || ex >= s.ex1 || ey < s.ey0 || ey >= s.ey1) continue;
+          const double kap = E[(long long)ey * g.nx + ex];
+          const int a = (1 - dx) + 2 * (1 - dy);
+          for (int b = 0; b < 4; ++b) {
+            const int bx = ex + (b & 1), by = ey + (b >> 1);
+            if (!dflag[(long long)by * g.nnx + bx]) wi += kap * me[4 * a + b];
+          }
+        }
+    }
+    w[node] = wi;
+    wsum += wi;
+  }
+  const double W = block_sum<EG_NT>(wsum, red);
+  const unsigned long long sg = (unsigned long long)seed * 0x9E3779B97F4A7C15ull;
+  for (int j = 0; j < m; ++j) {
+    double sj = 0.0;
+    for (int node = tid; node < n; node += EG_NT) {
+      const int x = s.x0 + node % s.nxb, y = s.y0 + node / s.nxb;
+      double f = 0.0;
+      if (j < nsnap && !dflag[(long long)y * g.nnx + x]) {
+        const unsigned long long key = ((unsigned long long)blockIdx.x << 40) |
+                                       ((unsigned long long)j << 24) |
+                                       (unsigned long long)node;
+        f = hash_unit(key ^ sg);
+      }
+      X[(long long)j * n + node] = f;
+      sj += w[node] * f;
+    }
+    const double mean = block_sum<EG_NT>(sj, red) / W;
+    for (int node = tid; node < n; node += EG_NT) {
+      const int x = s.x0 + node % s.nxb, y = s.y0 + node / s.nxb;
+      if (j < nsnap && !dflag[(long long)y * g.nnx + x]) X[(long long)j * n + node] -= mean;
+    }
+  }
+  EigState& e = st[blockIdx.x];
+  if (tid == 0) {
+    e.done = 0;
+    e.conv = 0;
+  }
+  if (tid < MAXM) e.theta_old[tid] = 0.0;
+}
+
+// Column m-1 of Y := the constant function on the kept nodes.
+__global__ void __launch_bounds__(EG_NT)
+k_rand_const(Geom g, const SysDesc* __restrict__ systems,
+             const uint8_t* __restrict__ dflag, double* __restrict__ Yw, int m) {
+  const SysDesc s = systems[blockIdx.x];
+  const int n = s.nxb * s.nyb;
+  double* Y = Yw + s.voff * (long long)m + (long long)(m - 1) * n;
+  for (int node = threadIdx.x; node < n; node += EG_NT) {
+    const int x = s.x0 + node % s.nxb, y = s.y0 + node / s.nxb;
+    Y[node] = dflag[(long long)y * g.nnx + x] ? 0.0 : 1.0;
+  }
+}
+
 // One shift-invert step of every neighbourhood still iterating: Z = M X,
 // then Y = C^{-1} Z by node rows in the factorisation's twisted order.
 // Workgroup 2 l + h runs chain h of neighbourhood l (h = 0: rows 0..mid-1
@@ -2124,9 +2210,38 @@ int launch_heat_eigen(const Geom& g, const SysDesc* sys, int nsys,
                       int rr_every, double lim, double tol, void* state,
                       int* d_count, int* h_count, double* psi, float* psi32,
                       double* lam, int* nsel, int* cap, int* err,
-                      const int* pack, int npack, hipStream_t s) {
+                      const int* pack, int npack, int nsnap,
+                      unsigned int seed, hipStream_t s) {
   EigParams p{m, kmax, maxit, rr_every, lim, tol};
   EigState* st = static_cast<EigState*>(state);
+  if (nsnap > 0) {
+    // randomized (Section 3): one pass of local solves on zero-mean random
+    // forcings, the constant function appended, an M-orthonormal basis of
+    // the snapshot space (Cholesky QR twice) and Rayleigh-Ritz on it
+    hipLaunchKernelGGL(k_rand_start, dim3(nsys), dim3(EG_NT), 0, s, g, sys, dflag,
+                       E, Me, X, Z, m, nsnap, seed, st);
+    hipLaunchKernelGGL(k_eig_chain<false>, dim3(npack), dim3(EG_NT), 0, s, g,
+                       sys, E, dflag, Me, Sinv, X, Y, Z, m, st, pack);
+    hipLaunchKernelGGL(k_eig_chain<true>, dim3(npack), dim3(EG_NT), 0, s, g,
+                       sys, E, dflag, Me, Sinv, X, Y, Z, m, st, pack);
+    hipLaunchKernelGGL(k_rand_const, dim3(nsys), dim3(EG_NT), 0, s, g, sys, dflag, Y, m);
+    for (int pass = 0; pass < 2; ++pass) {
+      hipLaunchKernelGGL(k_orth_gram, dim3(EG_OB * nsys), dim3(EG_NT), 0, s, g,
+                         sys, E, dflag, Me, pass ? X : Y, Z, m, st);
+      hipLaunchKernelGGL(k_orth_chol, dim3(nsys), dim3(EG_NT), 0, s, m, st, err);
+      hipLaunchKernelGGL(k_orth_linvT, dim3(EG_OB * nsys), dim3(EG_NT), 0, s,
+                         sys, pass ? X : Y, X, m, st);
+    }
+    hipLaunchKernelGGL(k_orth_gram, dim3(EG_OB * nsys), dim3(EG_NT), 0, s, g,
+                       sys, E, dflag, Ae, X, Z, m, st);
+    hipLaunchKernelGGL(k_orth_rr, dim3(nsys), dim3(EG_NT), 0, s, p, 1, st);
+    hipLaunchKernelGGL(k_orth_ritz, dim3(EG_OB * nsys), dim3(EG_NT), 0, s, sys,
+                       X, m, st);
+    hipLaunchKernelGGL(k_eig_select, dim3(nsys), dim3(EG_NT), 0, s, sys, X, p, st,
+                       psi, psi32, lam, nsel, cap);
+    if (hipGetLastError() != hipSuccess) return -1;
+    return 0;
+  }
   hipLaunchKernelGGL(k_eig_start, dim3(nsys), dim3(EG_NT), 0, s, g, sys, dflag, X, m, st);
   bool first_rr = true;
   int unconverged = nsys;

@@ -58,7 +58,8 @@ int launch_heat_eigen(const Geom&, const SysDesc*, int, const double*,
                        const uint8_t*, const double*, const double*,
                        const double*, double*, double*, double*, int, int, int,
                        int, double, double, void*, int*, int*, double*, float*,
-                       double*, int*, int*, int*, const int*, int, hipStream_t);
+                       double*, int*, int*, int*, const int*, int, int,
+                       unsigned int, hipStream_t);
 size_t eig_state_bytes();
 // k_topo.hip
 void launch_sensitivity(const Geom&, int, const double*, const double*,
@@ -424,7 +425,10 @@ msp_status build_geometry(msp_handle* h) {
   {
     int maxw = 1;
     for (const SysDesc& o : h->omegas) maxw = std::max(maxw, o.nxb);
-    int m = std::min(h->desc.eig_kmax + kEigExtra, MAXM);
+    // randomized: the snapshots and the constant function; else kmax plus
+    // guard vectors for the subspace iteration
+    int m = h->desc.eig_random > 0 ? h->desc.eig_random + 1
+                                   : std::min(h->desc.eig_kmax + kEigExtra, MAXM);
     while (m > h->desc.eig_kmax + 2 && !eig_fits_host(maxw, m)) --m;
     if (!eig_fits_host(maxw, m))
       return fail(h, MSP_E_INVALID, "eig_kmax too large for the coarse neighbourhood size");
@@ -652,6 +656,8 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
   if (!(d->penal >= 1.0)) return fail(nullptr, MSP_E_INVALID, "penal must be >= 1");
   if (!(d->h > 0.0)) return fail(nullptr, MSP_E_INVALID, "h must be positive");
   if (!(d->eig_tau > 0.0)) return fail(nullptr, MSP_E_INVALID, "eig_tau must be positive");
+  if (d->eig_random < 0 || d->eig_random > MAXM - 1)
+    return fail(nullptr, MSP_E_INVALID, "eig_random must lie in 0..31");
   if (d->eig_kmax < 1 || d->eig_kmax > 24)
     return fail(nullptr, MSP_E_INVALID, "eig_kmax must lie in 1..24");
   if (d->sub_mode != 0 && d->sub_mode != 1)
@@ -953,7 +959,8 @@ extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
       h->d_Som, h->d_X, h->d_Y, h->d_Z, m, kmax, kEigMaxIt, kEigRR,
       h->desc.eig_tau / (h->H * h->H), kEigTol, h->d_eig_state,
       (int*)h->d_cnt + 4, h->h_int + 8, h->d_psi, h->d_psi32, h->d_lam,
-      h->d_nsel, h->d_cap, h->d_err, h->d_om_pack, h->om_npack, s);
+      h->d_nsel, h->d_cap, h->d_err, h->d_om_pack, h->om_npack,
+      h->desc.eig_random, (unsigned int)h->desc.eig_seed, s);
   timer_end(h, KT_EIGEN, tk, s);
   if (unconv < 0) {
     h->setup_ok = false;

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     # msp_problem_desc: natural alignment as in C
-    assert ctypes.sizeof(msp.ProblemDesc) == 104
+    assert ctypes.sizeof(msp.ProblemDesc) == 112
     assert msp.ProblemDesc.h.offset == 16
     assert msp.ProblemDesc.eig_tau.offset == 80
     assert ctypes.sizeof(msp.SolveInfo) == 40 + 6 * 8
