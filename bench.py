@@ -426,13 +426,14 @@ def run_steps(torch, solvers, rho, f, nsteps, lat, infos):
         for s in solvers:
             t0 = time.perf_counter()
             s.set_densities(rho)
-            s.setup()
-            _, info = s.solve(f, rtol=1e-8)
+            _, info = s.solve(f, rtol=1e-8)     # builds the setup first
             torch.cuda.synchronize()
             lat.append(time.perf_counter() - t0)
             infos.append(info)
             if info["relres_true"] > 1e-8:
                 raise RuntimeError(f"solve missed relres 1e-8: {info}")
+            if info["setup_reused"] or not info["t_setup_ms"] > 0:
+                raise RuntimeError("a benchmark step must build its setup")
 
 
 def timed(torch, solvers, rho, f, steps):
@@ -626,6 +627,7 @@ def main():
                        "p99": round(1e3 * pct(lat_sorted, 0.99), 3)},
         "iterations": {f"{e:g}": i["iters"] for e, i in zip(contrasts, inf_mixed)},
         "coarse_dim": {f"{e:g}": i["n_coarse"] for e, i in zip(contrasts, inf_mixed)},
+        "setup_ms": {f"{e:g}": round(i["t_setup_ms"], 3) for e, i in zip(contrasts, inf_mixed)},
         "relres_true_max": max(i["relres_true"] for i in inf_mixed),
         "solve_only_solves_per_s": round(so_mixed, 3),
         "kernel_ms": {k: round(t / max(c, 1), 4) for k, (c, t) in kt.items()},
@@ -662,6 +664,7 @@ def main():
             "value": round(nsolves / t_rnd, 4),
             "iterations": {f"{e:g}": i["iters"] for e, i in zip(contrasts, inf_rnd)},
             "coarse_dim": {f"{e:g}": i["n_coarse"] for e, i in zip(contrasts, inf_rnd)},
+            "setup_ms": {f"{e:g}": round(i["t_setup_ms"], 3) for e, i in zip(contrasts, inf_rnd)},
             "latency_ms_p50": round(1e3 * statistics.median(lat_rnd), 3)}
         for s_ in rnd:
             s_.close()
