@@ -109,7 +109,30 @@ def matvec_probe(torch, launches=20):
     return {"mesh": f"{PROBE_NEL[0]}x{PROBE_NEL[1]} Q1 ({s.n} DOFs)",
             "bytes_per_launch": int(b), "avg_launch_ms": round(ms, 5),
             "achieved_GBs": round(gbs, 1),
-            "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "launches": int(c)}
+            "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "launches": int(c),
+            "copy_reference": copy_reference(torch, b)}
+
+
+def copy_reference(torch, nbytes, launches=10):
+    """A plain device copy moving the same number of bytes (half read, half
+    written; torch's copy kernel), event-timed: the attainable HBM rate for
+    a streaming kernel on this device, for comparison."""
+    n = int(nbytes) // 16
+    a = torch.ones(n, device="cuda", dtype=torch.float64)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(launches):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / launches
+    gbs = 16 * n / (ms * 1e-3) / 1e9
+    del a, b
+    return {"bytes": 16 * n, "avg_ms": round(ms, 5), "achieved_GBs": round(gbs, 1),
+            "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 PROBE3_NEL = (384, 192, 192)
@@ -183,6 +206,38 @@ def level1_traffic(launches_by_contrast):
     return sum(n * per[k] for k, n in launches_by_contrast.items()) / tot
 
 
+def level1_hbm_probe(torch, solvers, rounds=3):
+    """First-level applications taken in turn over the batch's problems
+    with at least 128 subdomains (whose applications fill the chip), so
+    that the records of one application were evicted from the 256 MB
+    last-level cache by the others' since it last ran: algorithmic bytes
+    over HIP-event time, read from HBM."""
+    big = [s for s in solvers if s.query()["n_subdomains"] >= 128]
+    if not big:
+        return None
+    rs = [torch.randn(s.n, device="cuda", dtype=torch.float64) for s in big]
+    for s, r in zip(big, rs):
+        s.apply_level1(r)
+        s.kernel_timing(enable=1)
+    for _ in range(rounds):
+        for s, r in zip(big, rs):
+            s.apply_level1(r)
+    torch.cuda.synchronize()
+    tot_b = tot_ms = 0.0
+    launches = 0
+    for s in big:
+        c, t = s.kernel_timing(enable=0)["level1_apply"]
+        tot_b += c * level1_bytes(s.query())
+        tot_ms += t
+        launches += c
+    gbs = tot_b / (tot_ms * 1e-3) / 1e9
+    return {"problems": len(big), "launches": int(launches),
+            "records_total_MB": round(sum(s.query()["level1_record_bytes"] for s in big) / 1e6, 1),
+            "bytes_per_launch": int(tot_b / max(launches, 1)),
+            "avg_launch_ms": round(tot_ms / max(launches, 1), 5),
+            "achieved_GBs": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def batch_workload(torch, args):
     """64 independent 2D cantilevers of uneven size (128x64 .. 768x384,
     config-1 style densities at Emin 1e-6, FP32 local solves): setups, then
@@ -236,6 +291,7 @@ def batch_workload(torch, args):
         "relres_true_max": max(i["relres_true"] for i in infos),
         "same_as_one_at_a_time": all(i["iters"] == j["iters"] for i, j in zip(infos, seq)),
         "batch_stats": b.stats(),
+        "level1_hbm": level1_hbm_probe(torch, solvers),
     }
     print(json.dumps(out), flush=True)
 
