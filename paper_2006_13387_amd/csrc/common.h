@@ -65,6 +65,23 @@ struct CoarseNode {
   long long w_off;     // offset of K Phi columns (ncols x 2*nxw*nyw)
 };
 
+// Per-matrix strides (doubles) of a batched Gauss-Jordan elimination: the
+// matrices, their pivot-block factors and their panels.
+struct GjStride {
+  long long a, ld, p;
+};
+
+// First-level subdomain of a 3D mesh: node box [x0, x0+nbx) x [y0, y0+nby)
+// x [z0, z0+nbz), n = 3 nbx nby nbz local DOFs (DOF 3 local_node + c,
+// local nodes x fastest), its dense inverse at moff (entries; leading
+// dimension ld, shared by all) and its local solution at voff.
+struct Sub3 {
+  int x0, y0, z0;
+  int nbx, nby, nbz;
+  int n, pad;
+  long long moff, voff;
+};
+
 // Device scalars of one PCG run.
 struct CGScalars {
   double rz, rz_old, pq, alpha, beta, rr, ff, zq, fx, rr0;

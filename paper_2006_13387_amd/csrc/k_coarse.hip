@@ -316,9 +316,11 @@ __device__ __forceinline__ void gjp_tile(double (&a)[4][4], int ti, int tj,
 // pivot) for the panels.
 __global__ void __launch_bounds__(CK_NT)
 k_gj_pivot(double* __restrict__ A, int ld, int kb, double* __restrict__ LD,
-           double tol, int* __restrict__ dropped) {
+           double tol, int* __restrict__ dropped, GjStride bs) {
   static_assert(GJB == 64 && CK_NT == 256, "pivot tiling: 16 x 16 threads, 4 x 4 tiles");
   __shared__ double pv[4 * GJB + 2];
+  A += blockIdx.z * bs.a;
+  LD += blockIdx.z * bs.ld;
   const int tid = threadIdx.x;
   const int tj = tid & 15, ti = tid >> 4;
   const long long base = (long long)kb * GJB;
@@ -358,11 +360,15 @@ constexpr int GJP_NT = 128;
 __global__ void __launch_bounds__(GJP_NT)
 k_gj_panel(double* __restrict__ A, int ld, int kb,
            const double* __restrict__ LD, double* __restrict__ Lp,
-           double* __restrict__ Rp) {
+           double* __restrict__ Rp, GjStride bs) {
   __shared__ double Ls[GJB * GJB];
   __shared__ double Di[GJB];
   const int ib = blockIdx.x;
   if (ib == kb) return;
+  A += blockIdx.z * bs.a;
+  LD += blockIdx.z * bs.ld;
+  Lp += blockIdx.z * bs.p;
+  Rp += blockIdx.z * bs.p;
   const int tid = threadIdx.x;
   for (int q = tid; q < GJB * GJB; q += GJP_NT) Ls[q] = LD[q];
   if (tid < GJB) Di[tid] = LD[GJB * GJB + tid];
@@ -434,11 +440,15 @@ k_gj_panel(double* __restrict__ A, int ld, int kb,
 // (nblk, nblk) of 64 x 64 tiles.
 __global__ void __launch_bounds__(CK_NT)
 k_gj_update(double* __restrict__ A, int ld, int kb,
-            const double* __restrict__ Lp, const double* __restrict__ Rp) {
+            const double* __restrict__ Lp, const double* __restrict__ Rp,
+            GjStride bs) {
   __shared__ double Ls[GJB * (GJB + 1)];
   __shared__ double Rs[GJB * (GJB + 1)];
   const int ib = blockIdx.y, jb = blockIdx.x;
   if (ib == kb || jb == kb) return;
+  A += blockIdx.z * bs.a;
+  Lp += blockIdx.z * bs.p;
+  Rp += blockIdx.z * bs.p;
   const int tid = threadIdx.x;
   const long long ibase = (long long)ib * GJB, jbase = (long long)jb * GJB;
   // The product on FP64 matrix cores: wave w takes rows 16w..16w+15 of the
@@ -1002,6 +1012,24 @@ void launch_coarse_k0(const Geom& g, const CoarseNode* cn, const int2* pairs,
                      mask, psi, W, K0, ldk, invH);
 }
 
+// The block steps of the Gauss-Jordan elimination on nmat matrices of
+// order ld (a multiple of 64) at once: matrix z at A + z bs.a, its pivot
+// factors at LD + z bs.ld (4160 doubles each), its panels at Lp + z bs.p and
+// Rp + z bs.p (64 ld doubles each).
+void launch_gj_steps(double* A, int ld, int nmat, GjStride bs, double* LD,
+                     double* Lp, double* Rp, double tol, int* dropped,
+                     hipStream_t s) {
+  const int nblk = ld / GJB;
+  for (int kb = 0; kb < nblk; ++kb) {
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1, 1, nmat), dim3(CK_NT), 0, s, A, ld,
+                       kb, LD, tol, dropped, bs);
+    hipLaunchKernelGGL(k_gj_panel, dim3(nblk, 1, nmat), dim3(GJP_NT), 0, s, A,
+                       ld, kb, LD, Lp, Rp, bs);
+    hipLaunchKernelGGL(k_gj_update, dim3(nblk, nblk, nmat), dim3(CK_NT), 0, s,
+                       A, ld, kb, Lp, Rp, bs);
+  }
+}
+
 void launch_k0_pinv(double* K0, int ldk, int nc, int dep_col, double* sdiag,
                     double* P, double* Lp, double* Rp, double tol, int* dropped,
                     hipStream_t s) {
@@ -1010,15 +1038,7 @@ void launch_k0_pinv(double* K0, int ldk, int nc, int dep_col, double* sdiag,
   const long long n2 = (long long)ldk * ldk;
   hipLaunchKernelGGL(k_k0_scale, dim3((unsigned)((n2 + 255) / 256)), dim3(256),
                      0, s, K0, ldk, sdiag);
-  const int nblk = ldk / GJB;
-  for (int kb = 0; kb < nblk; ++kb) {
-    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(CK_NT), 0, s, K0, ldk, kb, P,
-                       tol, dropped);
-    hipLaunchKernelGGL(k_gj_panel, dim3(nblk), dim3(GJP_NT), 0, s, K0, ldk, kb,
-                       P, Lp, Rp);
-    hipLaunchKernelGGL(k_gj_update, dim3(nblk, nblk), dim3(CK_NT), 0, s, K0,
-                       ldk, kb, Lp, Rp);
-  }
+  launch_gj_steps(K0, ldk, 1, GjStride{0, 0, 0}, P, Lp, Rp, tol, dropped, s);
   hipLaunchKernelGGL(k_k0_unscale, dim3((unsigned)((n2 + 255) / 256)),
                      dim3(256), 0, s, K0, ldk, sdiag);
 }

@@ -533,8 +533,10 @@ k_mask(long long n, const uint8_t* __restrict__ mask, double* __restrict__ x) {
 __global__ void __launch_bounds__(256)
 k_matvec3d(Geom g, const double* __restrict__ Ke, const double* __restrict__ E,
            const uint8_t* __restrict__ nmask, const double* __restrict__ x,
-           double* __restrict__ y) {
+           double* __restrict__ y, const CGScalars* __restrict__ sc) {
   __shared__ double K[576];
+  __shared__ int shd;
+  if (sc != nullptr && block_read_done(sc, &shd)) return;   // PCG run over
   for (int q = threadIdx.x; q < 576; q += 256) K[q] = Ke[q];
   __syncthreads();
   const long long nn = (long long)g.nnx * g.nny * g.nnz;
@@ -602,10 +604,10 @@ k_matvec3d(Geom g, const double* __restrict__ Ke, const double* __restrict__ E,
 
 void launch_apply_K3(const Geom& g, const double* Ke, const double* E,
                      const uint8_t* nmask, const double* x, double* y,
-                     hipStream_t s) {
+                     hipStream_t s, const CGScalars* sc) {
   const long long nn = (long long)g.nnx * g.nny * g.nnz;
   hipLaunchKernelGGL(k_matvec3d, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s,
-                     g, Ke, E, nmask, x, y);
+                     g, Ke, E, nmask, x, y, sc);
 }
 
 void launch_mask(long long n, const uint8_t* mask, double* x, hipStream_t s) {

@@ -20,7 +20,8 @@ void launch_simp(const double*, double*, int, double, double, double, int*,
                  hipStream_t);
 int matvec_blocks(const Geom&, int ty);
 void launch_apply_K3(const Geom&, const double*, const double*, const uint8_t*,
-                     const double*, double*, hipStream_t);
+                     const double*, double*, hipStream_t,
+                     const CGScalars* sc = nullptr);
 void h8_element_stiffness(double nu, double h, double* Ke);
 void launch_apply_K(const Geom&, int ty, const double*, const double*,
                     const uint8_t*, const double*, double*, hipStream_t);
@@ -98,6 +99,30 @@ void launch_export_basis(const Geom&, const CoarseNode*, const int*, int,
 // elements.cpp
 void q1_element_matrices(double nu, double h, double* Ke, double* Ae,
                          double* Me);
+// k_3d.hip
+int level1_3d_max_order();
+int vec3_blocks(long long);
+void launch_assemble3(const Geom&, const Sub3*, int, int, const double*,
+                      const double*, const uint8_t*, double*, hipStream_t);
+void launch_local_inverse3(double*, int, int, double*, double*, double*,
+                           double*, int*, float*, hipStream_t);
+void launch_level1_3d(const Geom&, const Sub3*, int, int, int, int, int, int,
+                      int, int, const double*, const float*, const uint8_t*,
+                      const double*, double*, double*, const CGScalars*,
+                      hipStream_t);
+void launch_cg3_resid(long long, const double*, const double*, const double*,
+                      const uint8_t*, double*, CGScalars*, double*,
+                      unsigned int*, int, hipStream_t);
+void launch_cg3_pq(long long, const double*, const double*, CGScalars*,
+                   double*, unsigned int*, double*, hipStream_t);
+void launch_cg3_update(long long, double*, double*, const double*,
+                       const double*, CGScalars*, double*, unsigned int*,
+                       hipStream_t);
+void launch_cg3_rz(long long, const double*, const double*, const double*,
+                   CGScalars*, double*, unsigned int*, double*, int,
+                   hipStream_t);
+void launch_cg3_p(long long, const double*, double*, const CGScalars*,
+                  hipStream_t);
 }  // namespace msp
 
 using namespace msp;
@@ -253,6 +278,16 @@ struct msp_handle {
   std::vector<int> nsel_h;
   std::vector<double> lam_h;
   double t_setup_ms = 0.0;
+  // 3D first level: dense inverses of the subdomain systems (ld3^2 entries
+  // each), FP64 and, on the mixed path, an FP32 copy
+  std::vector<Sub3> subs3;
+  Sub3* d_subs3 = nullptr;
+  int ld3 = 0, nbx3 = 0, nby3 = 0, nbz3 = 0;
+  long long l3_vec = 0;
+  double* d_A3 = nullptr;
+  float* d_A3f = nullptr;
+  double *d_LD3 = nullptr, *d_Lp3 = nullptr, *d_Rp3 = nullptr, *d_sd3 = nullptr;
+  unsigned int* d_tk3 = nullptr;   // ticket of the 3D PCG sums
 };
 
 namespace {
@@ -536,7 +571,9 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
                   h->d_K0, h->d_sdiag, h->d_P, h->d_Lp, h->d_Rp, h->d_dropped,
                   h->d_c, h->d_c0, h->d_x, h->d_r, h->d_p0, h->d_p1, h->d_q,
                   h->d_z, h->d_tmp, h->d_sc, h->d_ahist, h->d_bhist,
-                  h->d_part, h->d_cnt, h->d_err, h->d_eig_state, h->d_nmask};
+                  h->d_part, h->d_cnt, h->d_err, h->d_eig_state, h->d_nmask,
+                  h->d_subs3, h->d_A3, h->d_A3f, h->d_LD3, h->d_Lp3, h->d_Rp3,
+                  h->d_sd3, h->d_tk3};
   for (void* p : bufs) dfree(p);
   for (int k = 0; k < KT_COUNT; ++k)
     for (hipEvent_t e : h->kt[k].ev) (void)hipEventDestroy(e);
@@ -547,8 +584,9 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
   return MSP_OK;
 }
 
-// A 3D (H8) handle: the SIMP moduli and the stiffness product only; the
-// preconditioner and the solve are built for 2D meshes.
+// A 3D (H8) handle: the SIMP moduli, the stiffness product and the
+// gradient; the first-level preconditioner and the solve are built by the
+// first setup (its subdomain geometry is checked there).
 static msp_status create_3d(const msp_problem_desc* d, const uint8_t* fixed,
                             msp_handle** out) {
   if (d->nel[0] <= 0 || d->nel[1] <= 0 || d->nel[2] <= 0)
@@ -565,6 +603,7 @@ static msp_status create_3d(const msp_problem_desc* d, const uint8_t* fixed,
   msp_handle* h = new msp_handle();
   h->desc = *d;
   h->dim = 3;
+  h->fp32 = d->precision == 1;
   Geom& g = h->g;
   g.nx = d->nel[0];
   g.ny = d->nel[1];
@@ -926,9 +965,182 @@ static msp_status ensure_coarse_buffers(msp_handle* h, size_t ncols,
   return MSP_OK;
 }
 
+// ---- 3D first level ---------------------------------------------------
+
+// Subdomain boxes of a 3D mesh (blocks of sub_nel elements extended by the
+// overlap, as in 2D), their dense-matrix layout and the solve's buffers;
+// once per handle.
+static msp_status ensure_3d_buffers(msp_handle* h) {
+  if (h->d_A3 != nullptr) return MSP_OK;
+  const msp_problem_desc& d = h->desc;
+  const Geom& g = h->g;
+  if (d.eig_kmax != 0 || d.rot_enrich != 0)
+    return fail(h, MSP_E_INVALID, "dim = 3: the coarse space is not built; "
+                                  "set eig_kmax = 0 and rot_enrich = 0 (first level only)");
+  if (d.sub_mode != 0)
+    return fail(h, MSP_E_INVALID, "dim = 3: only box subdomains (sub_mode 0)");
+  const int nel[3] = {g.nx, g.ny, g.nz};
+  int nb[3];
+  for (int a = 0; a < 3; ++a) {
+    if (d.sub_nel[a] <= 0 || nel[a] % d.sub_nel[a])
+      return fail(h, MSP_E_INVALID, "nel must be a multiple of sub_nel (3D)");
+    if (d.overlap < 0 || d.overlap >= d.sub_nel[a])
+      return fail(h, MSP_E_INVALID, "overlap must satisfy 0 <= overlap < sub_nel");
+    nb[a] = nel[a] / d.sub_nel[a];
+  }
+  h->nbx3 = nb[0];
+  h->nby3 = nb[1];
+  h->nbz3 = nb[2];
+  h->subs3.clear();
+  int maxn = 0;
+  long long voff = 0;
+  for (int bz = 0; bz < nb[2]; ++bz)
+    for (int by = 0; by < nb[1]; ++by)
+      for (int bx = 0; bx < nb[0]; ++bx) {
+        const int b[3] = {bx, by, bz};
+        int lo[3], hi[3];
+        for (int a = 0; a < 3; ++a)
+          node_range(std::max(0, b[a] * d.sub_nel[a] - d.overlap),
+                     std::min(nel[a], (b[a] + 1) * d.sub_nel[a] + d.overlap),
+                     nel[a], &lo[a], &hi[a]);
+        Sub3 sb{};
+        sb.x0 = lo[0];
+        sb.y0 = lo[1];
+        sb.z0 = lo[2];
+        sb.nbx = hi[0] - lo[0] + 1;
+        sb.nby = hi[1] - lo[1] + 1;
+        sb.nbz = hi[2] - lo[2] + 1;
+        if (sb.nbx <= 0 || sb.nby <= 0 || sb.nbz <= 0)
+          return fail(h, MSP_E_INVALID, "empty subdomain");
+        sb.n = 3 * sb.nbx * sb.nby * sb.nbz;
+        sb.voff = voff;
+        voff += sb.n;
+        maxn = std::max(maxn, sb.n);
+        h->subs3.push_back(sb);
+      }
+  if (maxn > level1_3d_max_order())
+    return fail(h, MSP_E_INVALID, "3D subdomain exceeds 2048 DOFs (reduce sub_nel + 2*overlap)");
+  {
+    std::vector<uint8_t> cov((size_t)h->n_nodes, 0);
+    for (const Sub3& sb : h->subs3)
+      for (int z = sb.z0; z < sb.z0 + sb.nbz; ++z)
+        for (int y = sb.y0; y < sb.y0 + sb.nby; ++y)
+          for (int x = sb.x0; x < sb.x0 + sb.nbx; ++x)
+            cov[((size_t)z * g.nny + y) * g.nnx + x] = 1;
+    for (long long p = 0; p < h->n_nodes; ++p)
+      if (!cov[p] && (!h->mask_h[3 * p] || !h->mask_h[3 * p + 1] || !h->mask_h[3 * p + 2]))
+        return fail(h, MSP_E_INVALID, "subdomains do not cover every free DOF (overlap too small)");
+  }
+  const int ld = (maxn + 63) / 64 * 64;
+  h->ld3 = ld;
+  const long long ms = (long long)ld * ld;
+  for (size_t i = 0; i < h->subs3.size(); ++i) h->subs3[i].moff = (long long)i * ms;
+  h->l3_vec = voff;
+  const long long nsub = (long long)h->subs3.size();
+  const long long nd = h->n_dofs;
+  bool ok = true;
+  auto A = [&](hipError_t e) { if (e != hipSuccess) ok = false; };
+  A(dalloc(&h->d_subs3, nsub));
+  A(dalloc(&h->d_A3, nsub * ms));
+  if (h->fp32) A(dalloc(&h->d_A3f, nsub * ms));
+  A(dalloc(&h->d_LD3, nsub * 64 * 65));
+  A(dalloc(&h->d_Lp3, nsub * 64 * ld));
+  A(dalloc(&h->d_Rp3, nsub * 64 * ld));
+  A(dalloc(&h->d_sd3, nsub * ld));
+  A(dalloc(&h->d_lsol, voff));
+  A(dalloc(&h->d_tk3, 4));
+  if (!h->d_mask) A(dalloc(&h->d_mask, nd));
+  if (!h->d_x) {
+    A(dalloc(&h->d_x, nd));
+    A(dalloc(&h->d_r, nd));
+    A(dalloc(&h->d_p0, nd));
+    A(dalloc(&h->d_q, nd));
+    A(dalloc(&h->d_z, nd));
+    A(dalloc(&h->d_tmp, nd));
+    A(dalloc(&h->d_sc, 1));
+    A(dalloc(&h->d_part, 3 * vec3_blocks(nd) + 64));
+    A(dalloc(&h->d_dropped, 1));
+    A(hipHostMalloc((void**)&h->h_sc, sizeof(CGScalars)));
+    A(hipHostMalloc((void**)&h->h_dbl, 64 * sizeof(double)));
+  }
+  hipError_t e = hipSuccess;
+  auto C = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
+  if (ok) {
+    C(hipMemcpy(h->d_subs3, h->subs3.data(), nsub * sizeof(Sub3), hipMemcpyHostToDevice));
+    C(hipMemcpy(h->d_mask, h->mask_h.data(), nd, hipMemcpyHostToDevice));
+    C(hipMemset(h->d_tk3, 0, 4 * sizeof(unsigned int)));
+  }
+  if (!ok || e != hipSuccess) {
+    void** bufs[] = {(void**)&h->d_subs3, (void**)&h->d_A3, (void**)&h->d_A3f,
+                     (void**)&h->d_LD3, (void**)&h->d_Lp3, (void**)&h->d_Rp3,
+                     (void**)&h->d_sd3, (void**)&h->d_lsol, (void**)&h->d_tk3};
+    for (void** b : bufs) {
+      dfree(*b);
+      *b = nullptr;
+    }
+    return fail(h, ok ? MSP_E_DEVICE : MSP_E_NOMEM,
+                "device allocation of the 3D first level failed");
+  }
+  return MSP_OK;
+}
+
+// z = sum_i R_i^T K_i^{-1} R_i r on a 3D handle (sc: skip when the PCG run
+// is over).
+static void level1_3d(msp_handle* h, const double* r, double* z,
+                      const CGScalars* sc, hipStream_t s) {
+  const int t = timer_begin(h, KT_LEVEL1, s);
+  launch_level1_3d(h->g, h->d_subs3, (int)h->subs3.size(), h->ld3, h->nbx3,
+                   h->nby3, h->nbz3, h->desc.sub_nel[0], h->desc.sub_nel[1],
+                   h->desc.sub_nel[2], h->d_A3, h->fp32 ? h->d_A3f : nullptr,
+                   h->d_mask, r, h->d_lsol, z, sc, s);
+  timer_end(h, KT_LEVEL1, t, s);
+}
+
+// Setup of the 3D first level: gather every K_i densely, invert them all
+// at once, round to FP32 on the mixed path.
+static msp_status setup_3d(msp_handle* h, hipStream_t s) {
+  if (!h->have_E) return fail(h, MSP_E_STATE, "msp_set_densities must come first");
+  msp_status st = ensure_3d_buffers(h);
+  if (st != MSP_OK) return st;
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  HIPCHK(h, hipEventRecord(e0, s));
+  const int nsub = (int)h->subs3.size();
+  const long long ms = (long long)h->ld3 * h->ld3;
+  const int tk = timer_begin(h, KT_FACTOR, s);
+  HIPCHK(h, hipMemsetAsync(h->d_A3, 0, (size_t)nsub * ms * sizeof(double), s));
+  launch_assemble3(h->g, h->d_subs3, nsub, h->ld3, h->d_elem, h->d_E, h->d_mask,
+                   h->d_A3, s);
+  HIPCHK(h, hipMemsetAsync(h->d_dropped, 0, sizeof(int), s));
+  launch_local_inverse3(h->d_A3, h->ld3, nsub, h->d_sd3, h->d_LD3, h->d_Lp3,
+                        h->d_Rp3, h->d_dropped, h->fp32 ? h->d_A3f : nullptr, s);
+  timer_end(h, KT_FACTOR, tk, s);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(h->h_int + 1, h->d_dropped, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipEventRecord(e1, s));
+  HIPCHK(h, hipEventSynchronize(e1));
+  float msf = 0.f;
+  HIPCHK(h, hipEventElapsedTime(&msf, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  timer_flush(h);
+  if (h->h_int[1] != 0) {
+    h->setup_ok = false;
+    return fail(h, MSP_E_NOT_SPD, "a 3D local system has a non-positive pivot");
+  }
+  h->t_setup_ms = msf;
+  h->nc = 0;
+  h->rank = 0;
+  h->setup_ok = true;
+  h->setup_gen = h->dens_gen;
+  h->rebuild_due = false;
+  return MSP_OK;
+}
+
 extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
   if (!h) return fail(h, MSP_E_INVALID, "null handle");
-  if (need_2d(h) != MSP_OK) return MSP_E_INVALID;
+  if (h->dim == 3) return setup_3d(h, s);
   if (!h->have_E) return fail(h, MSP_E_STATE, "msp_set_densities must come first");
   {
     const msp_status st = ensure_setup_buffers(h);
@@ -1270,10 +1482,15 @@ extern "C" msp_status msp_oc_update(msp_handle* h, const double* rho,
 static msp_status apply_parts(msp_handle* h, const double* r, double* z,
                               bool l1, bool coarse, hipStream_t s) {
   if (!r || !z) return fail(h, MSP_E_INVALID, "null argument");
-  if (need_2d(h) != MSP_OK) return MSP_E_INVALID;
   msp_status st = check_ready(h, s);
   if (st != MSP_OK) return st;
-  enqueue_prec(h, 0, r, nullptr, z, l1, coarse, false, s);
+  if (h->dim == 3) {
+    // no coarse space in 3D: its part is zero
+    if (l1) level1_3d(h, r, z, nullptr, s);
+    else HIPCHK(h, hipMemsetAsync(z, 0, h->n_dofs * sizeof(double), s));
+  } else {
+    enqueue_prec(h, 0, r, nullptr, z, l1, coarse, false, s);
+  }
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(s));
   timer_flush(h);
@@ -1478,10 +1695,127 @@ static void chunk_single(msp_handle* h, hipStream_t s) {
   }
 }
 
+// ---- 3D PCG (first-level preconditioner) ---------------------------------
+
+// Fresh segment of a 3D run: r = f - K x, ||f||, z = M^{-1} r, r.z, p = z.
+static msp_status seg3_launch(SolveRun& R, hipStream_t s) {
+  msp_handle* h = R.h;
+  const long long n = h->n_dofs;
+  CGScalars seg = R.init;
+  seg.maxit = std::max(1, R.maxit - R.total_iters);
+  *h->h_sc = seg;
+  HIPCHK(h, hipMemcpyAsync(h->d_sc, h->h_sc, sizeof(CGScalars), hipMemcpyHostToDevice, s));
+  launch_apply_K3(h->g, h->d_elem, h->d_E, h->d_nmask, h->d_x, h->d_q, s);
+  launch_cg3_resid(n, R.f, h->d_q, h->d_x, h->d_mask, h->d_r, h->d_sc, h->d_part,
+                   h->d_tk3, 0, s);
+  level1_3d(h, h->d_r, h->d_z, nullptr, s);
+  launch_cg3_rz(n, h->d_r, h->d_z, h->d_q, h->d_sc, h->d_part, h->d_tk3,
+                h->d_bhist, 1, s);
+  HIPCHK(h, hipMemsetAsync(h->d_p0, 0, n * sizeof(double), s));
+  launch_cg3_p(n, h->d_z, h->d_p0, h->d_sc, s);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(CGScalars), hipMemcpyDeviceToHost, s));
+  return MSP_OK;
+}
+
+// kChunk iterations: q = K p, alpha, x and r, the stop test, z = M^{-1} r,
+// beta, p = z + beta p (every kernel returns at once after the stop).
+static void chunk3(msp_handle* h, hipStream_t s) {
+  const long long n = h->n_dofs;
+  for (int it = 0; it < kChunk; ++it) {
+    const int tm = timer_begin(h, KT_MATVEC, s);
+    launch_apply_K3(h->g, h->d_elem, h->d_E, h->d_nmask, h->d_p0, h->d_q, s, h->d_sc);
+    timer_end(h, KT_MATVEC, tm, s);
+    launch_cg3_pq(n, h->d_p0, h->d_q, h->d_sc, h->d_part, h->d_tk3, h->d_ahist, s);
+    launch_cg3_update(n, h->d_x, h->d_r, h->d_p0, h->d_q, h->d_sc, h->d_part,
+                      h->d_tk3, s);
+    level1_3d(h, h->d_r, h->d_z, h->d_sc, s);
+    launch_cg3_rz(n, h->d_r, h->d_z, h->d_q, h->d_sc, h->d_part, h->d_tk3,
+                  h->d_bhist, 0, s);
+    launch_cg3_p(n, h->d_z, h->d_p0, h->d_sc, s);
+  }
+}
+
+// End of a 3D segment: as seg_finish, with the 3D true residual.
+static msp_status seg3_finish(SolveRun& R, hipStream_t s, bool* restart) {
+  msp_handle* h = R.h;
+  *restart = false;
+  const CGScalars fin = *h->h_sc;
+  R.seg_iters = fin.iter;
+  R.total_iters += fin.iter;
+  R.relres_rec = fin.ff > 0 ? std::sqrt(fin.rr / fin.ff) : 0.0;
+  if (fin.iter > 0) {
+    R.ah.resize(fin.iter);
+    R.bh.resize(fin.iter);
+    HIPCHK(h, hipMemcpyAsync(R.ah.data(), h->d_ahist, fin.iter * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(R.bh.data(), h->d_bhist, fin.iter * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  if (fin.done == DONE_BREAKDOWN) {
+    HIPCHK(h, hipStreamSynchronize(s));
+    R.status = MSP_E_BREAKDOWN;
+    R.finished = true;
+    return MSP_OK;
+  }
+  if (fin.ff == 0.0) {
+    HIPCHK(h, hipStreamSynchronize(s));
+    R.relres_true = 0.0;
+    R.comp = 0.0;
+    R.finished = true;
+    return MSP_OK;
+  }
+  launch_apply_K3(h->g, h->d_elem, h->d_E, h->d_nmask, h->d_x, h->d_q, s);
+  launch_cg3_resid(h->n_dofs, R.f, h->d_q, h->d_x, h->d_mask, h->d_tmp, h->d_sc,
+                   h->d_part, h->d_tk3, 1, s);
+  HIPCHK(h, hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(CGScalars), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  R.relres_true = std::sqrt(h->h_sc->rr0 / h->h_sc->ff);
+  R.comp = h->h_sc->fx;
+  if (R.relres_true <= R.rtol) {
+    R.finished = true;
+  } else if (fin.done == DONE_MAXIT || R.total_iters >= R.maxit || R.restarts >= kMaxRestarts) {
+    R.status = MSP_NOT_CONVERGED;
+    R.finished = true;
+  } else {
+    ++R.restarts;
+    *restart = true;
+  }
+  return MSP_OK;
+}
+
+static msp_status solve_one_3d(msp_handle* h, const double* f, double* u,
+                               int warm, double rtol, int maxit, hipStream_t s,
+                               msp_solve_info* info) {
+  SolveRun R;
+  R.h = h;
+  R.f = f;
+  R.u = u;
+  R.rtol = rtol;
+  R.maxit = maxit;
+  msp_status st = run_begin(R, warm, s);
+  if (st != MSP_OK) return st;
+  while (!R.finished) {
+    if ((st = seg3_launch(R, s)) != MSP_OK) return st;
+    HIPCHK(h, hipStreamSynchronize(s));
+    if ((st = seg_started(R, s)) != MSP_OK) return st;
+    while (R.iterating) {
+      chunk3(h, s);
+      HIPCHK(h, hipGetLastError());
+      HIPCHK(h, hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(CGScalars), hipMemcpyDeviceToHost, s));
+      HIPCHK(h, hipStreamSynchronize(s));
+      timer_flush(h);
+      if (h->h_sc->done) break;
+    }
+    bool restart = false;
+    if ((st = seg3_finish(R, s, &restart)) != MSP_OK) return st;
+  }
+  return run_end(R, s, info);
+}
+
 static msp_status solve_one(msp_handle* h, const double* f, double* u,
                             int warm, double rtol, int maxit, hipStream_t s,
                             msp_solve_info* info) {
   static_assert(kChunk % 2 == 0, "chunks keep the p parity");
+  if (h->dim == 3) return solve_one_3d(h, f, u, warm, rtol, maxit, s, info);
   SolveRun R;
   R.h = h;
   R.f = f;
@@ -1513,7 +1847,6 @@ extern "C" msp_status msp_solve(msp_handle* h, const double* f, double* u,
                                 int32_t maxit, hipStream_t s,
                                 msp_solve_info* info) {
   if (!h || !f || !u) return fail(h, MSP_E_INVALID, "null argument");
-  if (need_2d(h) != MSP_OK) return MSP_E_INVALID;
   if (nrhs < 1 || maxit < 1 || !(rtol > 0.0))
     return fail(h, MSP_E_INVALID, "need nrhs >= 1, maxit >= 1, rtol > 0");
   double t_setup = 0.0;
@@ -2392,6 +2725,25 @@ extern "C" msp_status msp_vec_dot(int64_t n, const double* x, const double* y,
 
 extern "C" msp_status msp_query(msp_handle* h, int64_t* q) {
   if (!h || !q) return fail(h, MSP_E_INVALID, "null argument");
+  if (h->dim == 3) {
+    // first level: the dense inverses as the application reads them (n
+    // rows of n entries, rounded up to whole 16-byte loads)
+    const int vb = h->fp32 ? 4 : 8, nv = 16 / vb;
+    long long maxn = 0, l1 = 0;
+    for (const Sub3& sb : h->subs3) {
+      maxn = std::max<long long>(maxn, sb.n);
+      l1 += (long long)sb.n * ((sb.n + nv - 1) / nv * nv) * vb;
+    }
+    for (int k = 0; k < 12; ++k) q[k] = 0;
+    q[0] = h->n_dofs;
+    q[1] = h->n_elems;
+    q[2] = (int64_t)h->subs3.size();
+    q[5] = maxn;
+    q[6] = l1;
+    q[8] = h->l3_vec;
+    q[11] = h->ld3;
+    return MSP_OK;
+  }
   long long maxsys = 0;
   for (const SysDesc& s : h->subs) maxsys = std::max(maxsys, 2LL * s.nxb * s.nyb);
   q[0] = h->n_dofs;

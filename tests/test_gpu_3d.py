@@ -1,5 +1,6 @@
-"""GPU parity of the 3D (H8) stiffness product, the part of the hot path
-built for 3D meshes (Section 1.1 discretisation in three dimensions).
+"""GPU parity of the 3D (H8) stiffness product (Section 1.1 discretisation
+in three dimensions); the 3D first level and solve are in
+test_gpu_3d_solve.py.
 
 The reference is the oracle's assembled K(E) = sum_e E_e P_e^T K^_e P_e
 with the trilinear element matrix by 2x2x2 Gauss quadrature, restricted to
@@ -78,11 +79,13 @@ def test_matvec3d_unclamped_rigid_motions():
     s.close()
 
 
-def test_3d_handle_refuses_the_solve():
+def test_3d_handle_refuses_the_coarse_space():
+    # the 3D preconditioner is the first level only: a description that
+    # asks for heat modes or rotations is refused at setup
     desc, rho, fixed = _case((4, 3, 2), 31)
     msp = _msp()
     s = msp.Solver(desc, fixed)
     s.set_densities(_dev(rho))
-    with pytest.raises(Exception, match="stiffness product"):
+    with pytest.raises(Exception, match="coarse space is not built"):
         s.setup()
     s.close()

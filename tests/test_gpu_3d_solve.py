@@ -1,0 +1,147 @@
+"""GPU parity of the 3D (H8) solve with the first-level Schwarz
+preconditioner (Section 2: z = sum_i R_i^T K_i^{-1} R_i r over the
+overlapping subdomains; the paper's one-level method), through the C ABI.
+
+The GPU inverts every K_i densely (batched Gauss-Jordan on the unit-diagonal
+scaled matrix) and applies the inverses as matrix-vector products; the
+oracle factors each K_i by sparse LU.  Tolerances:
+- first level, FP64 inverses: per entry 1e-9 of max |z| at Emin 1e-3, 1e-6
+  at Emin 1e-6 (the forward error of an inverse grows with cond(K_i), as in
+  2D); FP32 inverses: 1e-3 of max |z| (FP32 rounding of the inverse);
+- solves: true relres <= 1e-8; u within 1e-6 of max |u| of a sparse direct
+  solve, entry by entry; compliance 1e-6; iterations within 10% and the
+  Lanczos condition estimate within 5% of the oracle's one-level PCG.
+"""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from oracle import dd
+
+from _checks import assert_entrywise
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _msp():
+    import paper_2006_13387_amd as msp
+    msp.load_library()
+    return msp
+
+
+def _dev(a):
+    return torch.tensor(np.asarray(a, dtype=np.float64), device="cuda")
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+def _case(nel, seed, Emin=1e-6, sub=6, overlap=1, precision=0):
+    """A 3D cantilever: random densities with 30% void, the x = 0 face
+    clamped, a unit downward load spread over the x = nx face."""
+    desc = inputs.problem_desc(3, nel, sub_nel=sub, overlap=overlap, Emin=Emin,
+                               eig_kmax=0, rot_enrich=0, precision=precision)
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.0, 1.0, inputs.n_elems(desc))
+    rho[rng.uniform(size=rho.size) < 0.3] = 0.0
+    fixed = inputs.clamp_face_mask(desc, axis=0, side=0)
+    ny, nz = nel[1], nel[2]
+    f = inputs.face_patch_load(desc, max(0, ny // 2 - 1), ny // 2 + 1, 1, -1.0)
+    f[fixed == 1] = 0.0
+    return desc, rho, fixed, f
+
+
+CASES = [((18, 12, 12), 41), ((12, 6, 18), 42), ((6, 6, 6), 43)]
+
+
+@pytest.mark.parametrize("nel,seed", CASES)
+@pytest.mark.parametrize("precision,Emin,tol", [(0, 1e-3, 1e-9), (0, 1e-6, 1e-6),
+                                                (1, 1e-6, 1e-3)])
+def test_level1_3d_entrywise(nel, seed, precision, Emin, tol):
+    desc, rho, fixed, _ = _case(nel, seed, Emin=Emin, precision=precision)
+    print(f"[3d level1] nel={nel} precision={precision} Emin={Emin}", flush=True)
+    msp = _msp()
+    s = msp.Solver(desc, fixed)
+    s.set_densities(_dev(rho))
+    s.setup()
+    hier = dd.build_preconditioner(desc, rho, fixed, level="one")
+    r = np.random.default_rng(seed + 7).standard_normal(len(fixed))
+    r[fixed == 1] = 0.0
+    z = _host(s.apply_level1(_dev(r)))
+    zref = np.zeros(len(fixed))
+    zref[hier.free] = hier.M.level1(r[hier.free])
+    assert np.all(z[fixed == 1] == 0.0)
+    assert_entrywise(z, zref, tol, np.max(np.abs(zref)), "3D first level")
+    # no coarse space: the coarse part is zero, the preconditioner is the
+    # first level
+    assert np.all(_host(s.apply_coarse(_dev(r))) == 0.0)
+    assert np.array_equal(_host(s.apply_prec(_dev(r))), z)
+    q = s.query()
+    assert q["n_subdomains"] == len(hier.sub_idx)
+    s.close()
+
+
+@pytest.mark.parametrize("nel,seed", CASES[:2])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_3d_against_direct_and_oracle(nel, seed, precision):
+    desc, rho, fixed, f = _case(nel, seed, precision=precision)
+    print(f"[3d solve] nel={nel} precision={precision}", flush=True)
+    msp = _msp()
+    s = msp.Solver(desc, fixed)
+    s.set_densities(_dev(rho))
+    u, info = s.solve(_dev(f), rtol=1e-8)
+    u = _host(u)
+    ud = oracle.direct_solve(desc, rho, fixed, f)
+    _, info_o, _ = oracle.solve(desc, rho, fixed, f, level="one")
+    print(f"  iters gpu {info['iters']} oracle {info_o.iters}, cond gpu "
+          f"{info['cond_est']:.4g} oracle {info_o.cond_est:.4g}, relres "
+          f"{info['relres_true']:.2e}", flush=True)
+    assert info["status"] == 0 and info["relres_true"] <= 1e-8
+    assert np.all(u[fixed == 1] == 0.0)
+    assert_entrywise(u, ud, 1e-6, np.max(np.abs(ud)), "u")
+    c_ref = float(f @ ud)
+    assert abs(info["compliance"] - c_ref) <= 1e-6 * abs(c_ref)
+    assert info["n_coarse"] == 0
+    assert abs(info["iters"] - info_o.iters) <= max(2, 0.1 * info_o.iters)
+    assert abs(info["cond_est"] - info_o.cond_est) <= 0.05 * info_o.cond_est
+    s.close()
+
+
+def test_solve_3d_warm_start_and_zero_load():
+    desc, rho, fixed, f = _case((12, 6, 6), 44)
+    msp = _msp()
+    s = msp.Solver(desc, fixed)
+    s.set_densities(_dev(rho))
+    u, info = s.solve(_dev(f), rtol=1e-8)
+    assert info["status"] == 0
+    # warm start from the solution: no iteration
+    u2, info2 = s.solve(_dev(f), u=u.clone(), warm=True, rtol=1e-8)
+    assert info2["iters"] == 0 and info2["relres_true"] <= 1e-8
+    # zero load: u exactly 0
+    z0, info0 = s.solve(_dev(np.zeros_like(f)), rtol=1e-8)
+    assert info0["iters"] == 0 and np.all(_host(z0) == 0.0)
+    # the same solve twice: the same bits
+    u3, _ = s.solve(_dev(f), rtol=1e-8)
+    assert torch.equal(u, u3)
+    s.close()
+
+
+def test_3d_geometry_checks():
+    msp = _msp()
+    # subdomains wider than the first-level kernel allows (8^3 nodes + overlap)
+    desc, rho, fixed, _ = _case((16, 8, 8), 45, sub=8, overlap=2)
+    s = msp.Solver(desc, fixed)
+    s.set_densities(_dev(rho))
+    with pytest.raises(Exception, match="2048 DOFs"):
+        s.setup()
+    s.close()
+    # no overlap: the nodes on block faces belong to no subdomain
+    desc, rho, fixed, _ = _case((12, 6, 6), 46, overlap=0)
+    s = msp.Solver(desc, fixed)
+    s.set_densities(_dev(rho))
+    with pytest.raises(Exception, match="cover"):
+        s.setup()
+    s.close()
