@@ -46,9 +46,9 @@ typedef enum {
  * heat eigenproblem and its automatic threshold; Section 4.2: rotations).
  *
  *  dim        2 (bilinear Q1, plane stress) or 3 (trilinear H8, isotropic;
- *             in 3D only the SIMP moduli and the stiffness product are
- *             built, and the subdomain, eigen and precision fields are
- *             ignored)
+ *             in 3D the preconditioner is the first level only: eig_kmax
+ *             and rot_enrich must be 0 and sub_mode 0, and sub_nel,
+ *             overlap and precision apply as in 2D)
  *  nel        elements per axis (nel[2] ignored in 2D)
  *  h          element edge length
  *  E0, Emin   SIMP moduli: E_e = Emin + rho_e^penal (E0 - Emin), 0<Emin<=E0
@@ -119,10 +119,11 @@ typedef struct msp_handle msp_handle;
  * bytes, 1 = that displacement DOF is clamped to zero (Gamma_D).  The mask
  * is copied.  In 2D the block row of a subdomain (2 * nodes per row) and
  * of a neighbourhood (nodes per row) must not exceed 72.  A 3D handle
- * supports msp_set_densities, msp_apply_K, msp_vec_dot, msp_query and
- * msp_kernel_timing; the calls that need the preconditioner (setup, solve,
- * the level-1, coarse and preconditioner applies, the coarse queries, batch
- * and serving) return MSP_E_INVALID for it.
+ * supports every single-problem call with the first-level preconditioner
+ * (Section 2 without the coarse term): a subdomain may hold at most 2,048
+ * DOFs (7^3 nodes for S = 6 and one overlap layer); its geometry is
+ * checked by the first msp_setup.  The coarse queries, batches and serving
+ * return MSP_E_INVALID for a 3D handle; msp_apply_coarse gives z = 0.
  * Errors: MSP_E_INVALID (see the field ranges above), MSP_E_NOMEM.
  */
 msp_status msp_create(const msp_problem_desc* desc,
@@ -147,13 +148,17 @@ msp_status msp_set_densities(msp_handle* h, const double* rho_dev,
  * local factors of K_i = R_i K R_i^T, heat eigenpairs on every coarse
  * neighbourhood with the threshold, coarse basis and K_0^+.  One
  * device-to-host read of the selected mode counts.  MSP_E_NOT_SPD if a
- * local pivot is not positive.
+ * local pivot is not positive.  3D: the dense inverse of every K_i
+ * (FP64, and an FP32 copy when precision = 1), held by the handle
+ * (about 12 ld^2 bytes per subdomain, ld the largest local order rounded
+ * up to 64); MSP_E_INVALID if the description asks for a coarse space or
+ * the subdomains are too large or do not cover the free DOFs.
  */
 msp_status msp_setup(msp_handle* h, hipStream_t stream);
 
 /*
- * Solve K_FF u = f by PCG with M_EH+Rot (or M_EH) to ||f - K u|| <=
- * rtol ||f|| over the free DOFs (Section 2; Section 5 for the stopping
+ * Solve K_FF u = f by PCG with M_EH+Rot (M_EH; in 3D the first level) to
+ * ||f - K u|| <= rtol ||f|| over the free DOFs (Section 2; Section 5 for the stopping
  * test and the Lanczos estimate).  f_dev and u_dev hold nrhs right-hand
  * sides of n doubles each, one after another; with warm != 0 u_dev holds
  * the initial guesses.  Entries of f at clamped DOFs are ignored and u is

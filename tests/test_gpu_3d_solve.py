@@ -145,3 +145,43 @@ def test_3d_geometry_checks():
     with pytest.raises(Exception, match="cover"):
         s.setup()
     s.close()
+
+
+def test_config2_full_size_level1_and_solve():
+    """The 96 x 48 x 48 workload (698,691 DOFs, 1,024 subdomains of up to
+    1,029 DOFs) in the launch configuration the benchmark times: the first
+    level per entry against the oracle's sparse LU at both precisions, and
+    the one-level solves to relres 1e-8 (the oracle's one-level PCG needs
+    about 12,000 iterations here, too many to run beside the test): the
+    true residual, the compliance against u^T K u from the stiffness
+    product, and the two precisions' displacements against each other."""
+    p = inputs.config(2)
+    msp = _msp()
+    desc0 = dict(p.desc, eig_kmax=0, rot_enrich=0)
+    print("[3d config2] oracle first level", flush=True)
+    hier = dd.build_preconditioner(desc0, p.rho, p.fixed, level="one")
+    r = np.random.default_rng(2002).standard_normal(len(p.fixed))
+    r[p.fixed == 1] = 0.0
+    zref = np.zeros(len(p.fixed))
+    zref[hier.free] = hier.M.level1(r[hier.free])
+    del hier
+    us = {}
+    for prec, tol in ((1, 1e-3), (0, 1e-6)):
+        print(f"[3d config2] precision {prec}", flush=True)
+        s = msp.Solver(dict(desc0, precision=prec), p.fixed)
+        s.set_densities(_dev(p.rho))
+        s.setup()
+        z = _host(s.apply_level1(_dev(r)))
+        assert_entrywise(z, zref, tol, np.max(np.abs(zref)), f"config-2 first level ({prec})")
+        f = _dev(p.f)
+        u, info = s.solve(f, rtol=1e-8, maxit=20000)
+        Ku = _host(s.apply_K(u))
+        uh = _host(u)
+        print(f"  iters {info['iters']} relres {info['relres_true']:.2e} "
+              f"cond {info['cond_est']:.4g}", flush=True)
+        assert info["status"] == 0 and info["relres_true"] <= 1e-8
+        uKu = float(uh @ Ku)
+        assert abs(info["compliance"] - uKu) <= 1e-6 * abs(uKu)
+        us[prec] = uh
+        s.close()
+    assert_entrywise(us[1], us[0], 1e-6, np.max(np.abs(us[0])), "FP32 against FP64 path")
