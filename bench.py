@@ -490,7 +490,10 @@ def topopt_workload(torch, args):
 
 
 def kernel_probe(torch):
-    """Launch only the kernels whose HBM counters are collected."""
+    """Launch only the kernels whose HBM counters are collected: 10
+    first-level applications per contrast on the 512 x 256 cantilever, 13
+    stiffness products on the 8192 x 4096 probe, 5 first-level
+    applications on the 96 x 48 x 48 workload, 5 plain 1 GiB copies."""
     import inputs
     import paper_2006_13387_amd as msp
     l1 = {}
@@ -506,6 +509,19 @@ def kernel_probe(torch):
         l1[f"{e:g}"] = int(level1_bytes(s.query()))
         s.close()
     mv = matvec_probe(torch, launches=10)
+    # 3D first level on the 96 x 48 x 48 workload (FP32 inverses, 4.4 GB):
+    # 5 applications
+    p3 = inputs.config(2)
+    s3 = msp.Solver(dict(p3.desc, eig_kmax=0, rot_enrich=0), p3.fixed)
+    s3.set_densities(torch.tensor(p3.rho, device="cuda"))
+    s3.setup()
+    r3 = torch.randn(s3.n, device="cuda", dtype=torch.float64)
+    for _ in range(5):
+        s3.apply_level1(r3)
+    torch.cuda.synchronize()
+    q3 = s3.query()
+    l1_3d = int(q3["level1_record_bytes"] + q3["local_vec_entries"] * 16)
+    s3.close()
     nbytes = 1 << 30
     a = torch.empty(nbytes // 8, device="cuda", dtype=torch.float64).fill_(1.0)
     b = torch.empty_like(a)
@@ -513,6 +529,7 @@ def kernel_probe(torch):
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"level1_bytes_per_launch": l1,
+                      "level1_3d_bytes_per_launch": l1_3d,
                       "matvec_bytes_per_launch": mv["bytes_per_launch"],
                       "copy_bytes_read": nbytes, "copy_bytes_written": nbytes}))
 
