@@ -82,6 +82,35 @@ struct Sub3 {
   long long moff, voff;
 };
 
+// Coarse node of a 3D mesh and its neighbourhood omega_l: closed node box
+// [x0, x0+nbx) x [y0, y0+nby) x [z0, z0+nbz).  The heat pencil's factor is
+// block tridiagonal by node planes of constant z (np = nbx nby nodes, padded
+// to the shared order ldp): plane k's inverse Schur block at goff + k ldp^2
+// (row-major, symmetric), the subspace block at xoff (row k ldp + a of the
+// in-plane node a, m values a row).  After the setup: nmodes selected heat
+// modes psi_j at psi_off (box node b = k np + a, value b nmodes + j), the
+// node's columns from col0 (mode j of component c at col0 + c nmodes + j,
+// rotation k at col0 + 3 nmodes + k) and their K Phi at woff (3 values per
+// box node a column).
+struct Nbh3 {
+  int cx, cy, cz;
+  int x0, y0, z0;
+  int nbx, nby, nbz;
+  int np;
+  int nmodes, nrot, col0, pad;
+  long long goff, xoff, psi_off, woff;
+};
+
+// Coarse part of the 3D preconditioner as the node-centric kernels see it.
+struct Coarse3 {
+  const Nbh3* nb;            // coarse nodes, x fastest
+  int ncx, ncy, ncz;
+  int S0, S1, S2;            // coarse block edge (elements)
+  double invH;               // 1 / H (rotation scale)
+  const double* psi;
+  const double* c0;          // K_0^+ R_0 r (null: no coarse part)
+};
+
 // Device scalars of one PCG run.
 struct CGScalars {
   double rz, rz_old, pq, alpha, beta, rr, ff, zq, fx, rr0;

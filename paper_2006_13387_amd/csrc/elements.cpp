@@ -117,4 +117,24 @@ void h8_element_stiffness(double nu, double h, double* Ke) {
       }
 }
 
+
+// Ae[8*8], Me[8*8]: scalar stiffness int grad N . grad N and consistent mass
+// int N N of the trilinear brick of edge h (the 3D heat pencil of Section
+// 4.1, unit coefficient).  Both are tensor products of the linear element's
+// 1D matrices k1 = [1 -1; -1 1] / h and m1 = h [2 1; 1 2] / 6:
+// Ae = k1 x m1 x m1 + m1 x k1 x m1 + m1 x m1 x k1, Me = m1 x m1 x m1.
+void h8_heat_element(double h, double* Ae, double* Me) {
+  const double k1[2][2] = {{1.0 / h, -1.0 / h}, {-1.0 / h, 1.0 / h}};
+  const double m1[2][2] = {{h / 3.0, h / 6.0}, {h / 6.0, h / 3.0}};
+  for (int a = 0; a < 8; ++a)
+    for (int b = 0; b < 8; ++b) {
+      const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
+      const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
+      Ae[a * 8 + b] = k1[ax][bx] * m1[ay][by] * m1[az][bz] +
+                      m1[ax][bx] * k1[ay][by] * m1[az][bz] +
+                      m1[ax][bx] * m1[ay][by] * k1[az][bz];
+      Me[a * 8 + b] = m1[ax][bx] * m1[ay][by] * m1[az][bz];
+    }
+}
+
 }  // namespace msp

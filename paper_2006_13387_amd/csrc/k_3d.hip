@@ -202,15 +202,63 @@ k3_level1(Geom g, const Sub3* __restrict__ subs, int ld, const T* __restrict__ A
   }
 }
 
+// z at node (X, Y, Z) += sum over the (at most 8) coarse nodes whose hat is
+// nonzero there of their columns times c0.
+__device__ __forceinline__ double3 coarse3_prolong(const Geom& g, const Coarse3& cc,
+                                                   int X, int Y, int Z) {
+  double3 z = make_double3(0.0, 0.0, 0.0);
+  for (int cz = Z / cc.S2; cz <= min(Z / cc.S2 + 1, cc.ncz - 1); ++cz) {
+    const int dz = Z - cz * cc.S2;
+    const double hz = 1.0 - fabs((double)dz) / cc.S2;
+    if (!(hz > 0.0)) continue;
+    for (int cy = Y / cc.S1; cy <= min(Y / cc.S1 + 1, cc.ncy - 1); ++cy) {
+      const int dy = Y - cy * cc.S1;
+      const double hy = 1.0 - fabs((double)dy) / cc.S1;
+      if (!(hy > 0.0)) continue;
+      for (int cx = X / cc.S0; cx <= min(X / cc.S0 + 1, cc.ncx - 1); ++cx) {
+        const int dx = X - cx * cc.S0;
+        const double hx = 1.0 - fabs((double)dx) / cc.S0;
+        if (!(hx > 0.0)) continue;
+        const Nbh3& w = cc.nb[((long long)cz * cc.ncy + cy) * cc.ncx + cx];
+        const int nm = w.nmodes;
+        if (3 * nm + w.nrot == 0) continue;
+        const double chi = hx * hy * hz;
+        const double* cw = cc.c0 + w.col0;
+        const long long b = ((long long)(Z - w.z0) * w.nby + (Y - w.y0)) * w.nbx + (X - w.x0);
+        const double* ps = cc.psi + w.psi_off + b * nm;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int j = 0; j < nm; ++j) {
+          const double p = ps[j];
+          s0 = fma(p, cw[j], s0);
+          s1 = fma(p, cw[nm + j], s1);
+          s2 = fma(p, cw[2 * nm + j], s2);
+        }
+        if (w.nrot) {
+          const double x = dx * g.h * cc.invH, y = dy * g.h * cc.invH, zz = dz * g.h * cc.invH;
+          const double a0 = cw[3 * nm], a1 = cw[3 * nm + 1], a2 = cw[3 * nm + 2];
+          s0 += zz * a1 - y * a2;
+          s1 += -zz * a0 + x * a2;
+          s2 += y * a0 - x * a1;
+        }
+        z.x = fma(chi, s0, z.x);
+        z.y = fma(chi, s1, z.y);
+        z.z = fma(chi, s2, z.z);
+      }
+    }
+  }
+  return z;
+}
+
 // Part 2: z at every node = sum of the local solutions of the subdomains
 // whose boxes hold the node, in ascending subdomain order (at most two
-// blocks per axis hold a node when the overlap is below the block edge);
-// zero at fixed DOFs.
+// blocks per axis hold a node when the overlap is below the block edge),
+// plus the coarse part R_0^T c0 when cc.c0 is set; zero at fixed DOFs.
+// use_l1 = 0 leaves the first level out (the coarse part alone).
 __global__ void __launch_bounds__(T3_NT)
 k3_level1_sum(Geom g, const Sub3* __restrict__ subs, int nbx, int nby, int nbz,
               int S0, int S1, int S2, const uint8_t* __restrict__ mask,
               const double* __restrict__ lsol, double* __restrict__ z,
-              const CGScalars* __restrict__ sc) {
+              const CGScalars* __restrict__ sc, int use_l1, Coarse3 cc) {
   __shared__ int shd;
   if (sc != nullptr && block_read_done(sc, &shd)) return;
   const long long nn = (long long)g.nnx * g.nny * g.nnz;
@@ -220,6 +268,7 @@ k3_level1_sum(Geom g, const Sub3* __restrict__ subs, int nbx, int nby, int nbz,
   const long long rr = node / g.nnx;
   const int Y = (int)(rr % g.nny), Z = (int)(rr / g.nny);
   double z0 = 0.0, z1 = 0.0, z2 = 0.0;
+  if (use_l1)
   for (int bz = max(0, Z / S2 - 1); bz <= min(nbz - 1, Z / S2 + 1); ++bz)
     for (int by = max(0, Y / S1 - 1); by <= min(nby - 1, Y / S1 + 1); ++by)
       for (int bx = max(0, X / S0 - 1); bx <= min(nbx - 1, X / S0 + 1); ++bx) {
@@ -231,6 +280,12 @@ k3_level1_sum(Geom g, const Sub3* __restrict__ subs, int nbx, int nby, int nbz,
         z1 += l[1];
         z2 += l[2];
       }
+  if (cc.c0 != nullptr) {
+    const double3 zc = coarse3_prolong(g, cc, X, Y, Z);
+    z0 += zc.x;
+    z1 += zc.y;
+    z2 += zc.z;
+  }
   const uint8_t* m = mask + 3 * node;
   z[3 * node] = m[0] ? 0.0 : z0;
   z[3 * node + 1] = m[1] ? 0.0 : z1;
@@ -429,14 +484,14 @@ void launch_assemble3(const Geom& g, const Sub3* subs, int nsub, int ld,
 void launch_gj_steps(double*, int, int, GjStride, double*, double*, double*,
                      double, int*, hipStream_t);
 
-// In place: A_i <- K_i^{-1} for every subdomain (scaled to unit diagonal,
-// batched Gauss-Jordan, unscaled; FP32 copy into A32 when given).  LD,
-// Lp and Rp hold 4160, 64 ld and 64 ld doubles per subdomain.
-void launch_local_inverse3(double* A, int ld, int nsub, double* sdiag,
-                           double* LD, double* Lp, double* Rp, int* dropped,
-                           float* A32, hipStream_t s) {
-  const long long ms = (long long)ld * ld;
-  const unsigned nbe = (unsigned)((ms + T3_NT - 1) / T3_NT);
+// In place: A_i <- A_i^{-1} for the nsub matrices at stride ms (scaled to
+// unit diagonal, batched Gauss-Jordan, unscaled and symmetrised; FP32 copy
+// into A32 when given).  LD, Lp and Rp hold 4160, 64 ld and 64 ld doubles
+// per matrix.
+void launch_local_inverse3_strided(double* A, int ld, int nsub, long long ms,
+                                   double* sdiag, double* LD, double* Lp, double* Rp,
+                                   int* dropped, float* A32, hipStream_t s) {
+  const unsigned nbe = (unsigned)(((long long)ld * ld + T3_NT - 1) / T3_NT);
   hipLaunchKernelGGL(k3_scale_factors, dim3((ld + T3_NT - 1) / T3_NT, nsub),
                      dim3(T3_NT), 0, s, A, ld, ms, sdiag);
   hipLaunchKernelGGL(k3_scale, dim3(nbe, nsub), dim3(T3_NT), 0, s, A, ld, ms, sdiag);
@@ -448,13 +503,22 @@ void launch_local_inverse3(double* A, int ld, int nsub, double* sdiag,
                      sdiag, A32);
 }
 
+void launch_local_inverse3(double* A, int ld, int nsub, double* sdiag,
+                           double* LD, double* Lp, double* Rp, int* dropped,
+                           float* A32, hipStream_t s) {
+  launch_local_inverse3_strided(A, ld, nsub, (long long)ld * ld, sdiag, LD, Lp, Rp,
+                                dropped, A32, s);
+}
+
 void launch_level1_3d(const Geom& g, const Sub3* subs, int nsub, int ld,
                       int nbx, int nby, int nbz, int S0, int S1, int S2,
                       const double* A64, const float* A32, const uint8_t* mask,
                       const double* r, double* lsol, double* z,
-                      const CGScalars* sc, hipStream_t s) {
+                      const CGScalars* sc, int use_l1, const Coarse3& cc,
+                      hipStream_t s) {
   const dim3 gr(ld / 64, nsub);
-  if (A32 != nullptr)
+  if (!use_l1) {
+  } else if (A32 != nullptr)
     hipLaunchKernelGGL(k3_level1<float>, gr, dim3(T3_NT), 0, s, g, subs, ld, A32,
                        mask, r, lsol, sc);
   else
@@ -463,7 +527,7 @@ void launch_level1_3d(const Geom& g, const Sub3* subs, int nsub, int ld,
   const long long nn = (long long)g.nnx * g.nny * g.nnz;
   hipLaunchKernelGGL(k3_level1_sum, dim3((unsigned)((nn + T3_NT - 1) / T3_NT)),
                      dim3(T3_NT), 0, s, g, subs, nbx, nby, nbz, S0, S1, S2, mask,
-                     lsol, z, sc);
+                     lsol, z, sc, use_l1, cc);
 }
 
 void launch_cg3_resid(long long n, const double* f, const double* y, const double* x,

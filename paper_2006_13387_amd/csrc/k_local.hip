@@ -20,6 +20,7 @@
 #include <vector>
 #include "common.h"
 #include "dev.h"
+#include "small_dense.h"
 
 namespace msp {
 
@@ -1155,14 +1156,6 @@ __device__ __forceinline__ double eig_dot(const double* S, int ld, int i,
   return (a0 + a1) + (a2 + a3);
 }
 
-__device__ __forceinline__ double hash_unit(unsigned long long a) {
-  // splitmix64 finaliser -> uniform in [-1, 1)
-  a += 0x9E3779B97F4A7C15ull;
-  a = (a ^ (a >> 30)) * 0xBF58476D1CE4E5B9ull;
-  a = (a ^ (a >> 27)) * 0x94D049BB133111EBull;
-  a ^= a >> 31;
-  return (double)(a >> 11) * (2.0 / 9007199254740992.0) - 1.0;
-}
 
 // K Y on node rows r0 <= k < r1 of a neighbourhood, K = sum_e kappa_e Kel4
 // over the neighbourhood's elements (Kel4 the 4 x 4 element matrix, kappa_e
@@ -1316,29 +1309,6 @@ __device__ void stencil_rows(const Geom& g, const SysDesc& s,
   }
 }
 
-__device__ void chol_small(double* G, int m, int* __restrict__ err) {
-  const int tid = threadIdx.x;
-  for (int p = 0; p < m; ++p) {
-    __syncthreads();
-    double d = G[p * m + p];
-    if (!(d > 0.0) || !finite(d)) {
-      if (tid == 0) atomicOr(err, ERR_EIG);
-      d = 1e-300;
-    }
-    const double piv = sqrt(d);
-    __syncthreads();
-    for (int i = tid; i < m; i += EG_NT) {
-      if (i == p) G[p * m + p] = piv;
-      else if (i > p) G[i * m + p] /= piv;
-    }
-    __syncthreads();
-    for (int idx = tid; idx < m * m; idx += EG_NT) {
-      const int i = idx / m, j = idx - (idx / m) * m;
-      if (i > p && j > p && j <= i) G[i * m + j] -= G[i * m + p] * G[j * m + p];
-    }
-  }
-  __syncthreads();
-}
 
 // Y <- Y L^{-T} on nodes n0 <= node < n1 (each node's row of m values
 // solved with L).
@@ -1365,89 +1335,6 @@ __device__ void apply_linvT(const double* Yin, double* Y, int n, int m,
   }
 }
 
-// Jacobi eigenvalues of the symmetric m x m matrix A (LDS, stride m);
-// V (LDS, stride m) receives the eigenvectors as columns.  Parallel
-// round-robin ordering: m/2 disjoint rotations per round.
-__device__ void jacobi_small(double* A, double* V, int m, double* rc,
-                             double* rs, int* rp, int* rq) {
-  const int tid = threadIdx.x;
-  const int me = (m + 1) & ~1;            // even number of players
-  for (int idx = tid; idx < m * m; idx += EG_NT) {
-    const int i = idx / m, j = idx - (idx / m) * m;
-    V[idx] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  __shared__ double jred[EG_NT / 64 + 1];
-  for (int sweep = 0; sweep < 30; ++sweep) {
-    // convergence test: off-diagonal and diagonal squares, summed by the
-    // whole workgroup (fixed order)
-    double o = 0.0, d = 0.0;
-    for (int idx = tid; idx < m * m; idx += EG_NT) {
-      const int i = idx / m, j = idx - (idx / m) * m;
-      const double a = A[idx];
-      if (i == j) d += a * a; else o += a * a;
-    }
-    const double offn = block_sum<EG_NT>(o, jred);
-    const double diagn = block_sum<EG_NT>(d, jred);
-    if (offn <= 1e-30 * diagn || offn == 0.0) break;
-    for (int r = 0; r < me - 1; ++r) {
-      if (tid < me / 2) {
-        int p, q;
-        if (tid == 0) {
-          p = 0;
-          q = 1 + (r % (me - 1));
-        } else {
-          p = 1 + (r + tid) % (me - 1);
-          q = 1 + (r - tid + me - 1) % (me - 1);
-        }
-        if (p > q) { const int t = p; p = q; q = t; }
-        double c = 1.0, sn = 0.0;
-        if (q < m) {
-          const double apq = A[p * m + q];
-          if (fabs(apq) > 1e-300) {
-            const double th = (A[q * m + q] - A[p * m + p]) / (2.0 * apq);
-            const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            sn = t * c;
-          }
-        }
-        rc[tid] = c;
-        rs[tid] = sn;
-        rp[tid] = p;
-        rq[tid] = q;
-      }
-      __syncthreads();
-      // rows: A <- J^T A
-      for (int idx = tid; idx < (me / 2) * m; idx += EG_NT) {
-        const int pr = idx / m, col = idx - (idx / m) * m;
-        const int p = rp[pr], q = rq[pr];
-        if (q < m) {
-          const double c = rc[pr], sn = rs[pr];
-          const double ap = A[p * m + col], aq = A[q * m + col];
-          A[p * m + col] = c * ap - sn * aq;
-          A[q * m + col] = sn * ap + c * aq;
-        }
-      }
-      __syncthreads();
-      // columns: A <- A J, V <- V J
-      for (int idx = tid; idx < (me / 2) * m; idx += EG_NT) {
-        const int pr = idx / m, row = idx - (idx / m) * m;
-        const int p = rp[pr], q = rq[pr];
-        if (q < m) {
-          const double c = rc[pr], sn = rs[pr];
-          const double ap = A[row * m + p], aq = A[row * m + q];
-          A[row * m + p] = c * ap - sn * aq;
-          A[row * m + q] = sn * ap + c * aq;
-          const double vp = V[row * m + p], vq = V[row * m + q];
-          V[row * m + p] = c * vp - sn * vq;
-          V[row * m + q] = sn * vp + c * vq;
-        }
-      }
-      __syncthreads();
-    }
-  }
-  __syncthreads();
-}
 
 // X[:, c] = Y V[:, order[c]] (the Ritz vectors, ascending) on nodes
 // n0 <= node < n1; one node per thread.
@@ -1971,7 +1858,7 @@ k_orth_chol(int m, EigState* __restrict__ st, int* __restrict__ err) {
   EigState& es = st[blockIdx.x];
   if (es.done) return;
   orth_gather(es, m, G);
-  chol_small(G, m, err);
+  chol_small<EG_NT>(G, m, err);
   for (int e = threadIdx.x; e < m * m; e += EG_NT) es.L[e] = G[e];
 }
 
@@ -2002,7 +1889,7 @@ k_orth_rr(EigParams prm, int first_rr, EigState* __restrict__ st) {
   const int tid = threadIdx.x;
   const int m = prm.m;
   orth_gather(es, m, G);
-  jacobi_small(G, V, m, rc, rs, rp, rq);
+  jacobi_small<EG_NT>(G, V, m, rc, rs, rp, rq);
   if (tid == 0) {
     for (int i = 0; i < m; ++i) order[i] = i;
     for (int i = 1; i < m; ++i) {       // insertion sort by eigenvalue

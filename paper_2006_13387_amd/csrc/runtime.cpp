@@ -80,8 +80,8 @@ void launch_coarse_kphi(const Geom&, const CoarseNode*, const int*, int,
 void launch_coarse_k0(const Geom&, const CoarseNode*, const int2*, int,
                       const uint8_t*, const double*, const double*, double*,
                       int, double, hipStream_t);
-void launch_k0_pinv(double*, int, int, int, double*, double*, double*, double*,
-                    double, int*, hipStream_t);
+void launch_k0_pinv(double*, int, int, int, int, double*, double*, double*,
+                    double*, double, int*, hipStream_t);
 void launch_restrict(const RestrictArgs&, int ncn, hipStream_t);
 void launch_restrict_batch(const RestrictArgs*, const int*, int, int, hipStream_t);
 int restrict_bands();
@@ -108,8 +108,42 @@ void launch_local_inverse3(double*, int, int, double*, double*, double*,
                            double*, int*, float*, hipStream_t);
 void launch_level1_3d(const Geom&, const Sub3*, int, int, int, int, int, int,
                       int, int, const double*, const float*, const uint8_t*,
-                      const double*, double*, double*, const CGScalars*,
+                      const double*, double*, double*, const CGScalars*, int,
+                      const Coarse3&, hipStream_t);
+void h8_heat_element(double h, double* Ae, double* Me);
+// k_coarse3d.hip
+size_t eig3_state_bytes();
+int eig3_block(int kmax);
+int coarse3_max_plane();
+int coarse3_max_cols();
+void launch_heat3_factor(const Geom&, const Nbh3*, int, int, int, const double*,
+                         const uint8_t*, const double*, double, double*, double*,
+                         double*, double*, double*, int*, hipStream_t);
+void launch_heat3_start(const Geom&, const Nbh3*, int, int, int, int,
+                        const uint8_t*, double*, void*, hipStream_t);
+void launch_heat3_step(int, const Geom&, const Nbh3*, int, int, int, const double*,
+                       const uint8_t*, const double*, double, const double*,
+                       double*, double*, double*, double*, void*, int, double,
+                       double, int, int*, hipStream_t);
+void launch_heat3_count(void*, int, int, int*, hipStream_t);
+void launch_heat3_select(const void*, int, int, int, double, int*, int*, double*,
+                         hipStream_t);
+void launch_heat3_psi(int, const Nbh3*, int, int, int, const double*, double*,
                       hipStream_t);
+void launch_coarse3_kphi(const Geom&, const Nbh3*, const int*, int, int, int, int,
+                         int, double, const double*, const double*, const uint8_t*,
+                         const double*, double*, hipStream_t);
+void launch_coarse3_k0(const Geom&, const Nbh3*, const int2*, int, int, int, int,
+                       double, const uint8_t*, const double*, const double*,
+                       double*, int, hipStream_t);
+void launch_coarse3_export(const Geom&, const Nbh3*, const int*, int, int, int, int,
+                           double, const uint8_t*, const double*, double*,
+                           hipStream_t);
+void launch_coarse3_restrict(const Geom&, const Nbh3*, int, int, int, int, double,
+                             const uint8_t*, const double*, const double*, double*,
+                             const CGScalars*, hipStream_t);
+void launch_coarse3_gemv(const double*, int, int, const double*, double*,
+                         const CGScalars*, hipStream_t);
 void launch_cg3_resid(long long, const double*, const double*, const double*,
                       const uint8_t*, double*, CGScalars*, double*,
                       unsigned int*, int, hipStream_t);
@@ -140,6 +174,9 @@ constexpr int kEigExtra = 8;         // subspace block m = kmax + kEigExtra
 // in the subspace error, so 1e-8 leaves the selected eigenvalues far more
 // accurate than the 1e-6 the coarse space needs.
 constexpr int kEigMaxIt = 48;
+constexpr int kEig3MaxIt = 40;       // 3D: sweeps, each with Rayleigh-Ritz
+constexpr int kEig3Passes = 3;       // 3D: consecutive converged steps to stop
+constexpr int kMaxCoarse3 = 32768;   // largest padded 3D K_0 order
 constexpr int kEigRR = 3;
 constexpr double kEigTol = 1e-8;
 // Pivots of the unit-diagonal K_0 at or below kPivotDrop are dropped (the
@@ -288,6 +325,21 @@ struct msp_handle {
   float* d_A3f = nullptr;
   double *d_LD3 = nullptr, *d_Lp3 = nullptr, *d_Rp3 = nullptr, *d_sd3 = nullptr;
   unsigned int* d_tk3 = nullptr;   // ticket of the 3D PCG sums
+  // 3D coarse space: the coarse nodes with their neighbourhoods, the
+  // plane-blocked factors of the heat pencils (pmax3 planes of ldp3^2 per
+  // neighbourhood), the subspace blocks (m3 columns), the modes, K Phi and
+  // (shared with 2D) K_0
+  std::vector<Nbh3> nb3_h;
+  Nbh3* d_nb3 = nullptr;
+  int ncx3 = 0, ncy3 = 0, ncz3 = 0, pmax3 = 0, ldp3 = 0, m3 = 0;
+  double* d_G3 = nullptr;
+  double *d_X3 = nullptr, *d_Y3 = nullptr, *d_T3 = nullptr, *d_U3 = nullptr;
+  void* d_est3 = nullptr;
+  double *d_hsd3 = nullptr, *d_hLD3 = nullptr, *d_hLp3 = nullptr, *d_hRp3 = nullptr;
+  double* d_hel3 = nullptr;        // heat element matrices A^ | M^ (8 x 8 each)
+  double* d_psi3 = nullptr;
+  size_t psi3_cap = 0;
+  int ndep3 = 0;                   // dependent rotation columns dropped from K_0
 };
 
 namespace {
@@ -573,7 +625,9 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
                   h->d_z, h->d_tmp, h->d_sc, h->d_ahist, h->d_bhist,
                   h->d_part, h->d_cnt, h->d_err, h->d_eig_state, h->d_nmask,
                   h->d_subs3, h->d_A3, h->d_A3f, h->d_LD3, h->d_Lp3, h->d_Rp3,
-                  h->d_sd3, h->d_tk3};
+                  h->d_sd3, h->d_tk3, h->d_nb3, h->d_G3, h->d_X3, h->d_Y3,
+                  h->d_T3, h->d_U3, h->d_est3, h->d_hsd3, h->d_hLD3, h->d_hLp3,
+                  h->d_hRp3, h->d_hel3, h->d_psi3};
   for (void* p : bufs) dfree(p);
   for (int k = 0; k < KT_COUNT; ++k)
     for (hipEvent_t e : h->kt[k].ev) (void)hipEventDestroy(e);
@@ -664,13 +718,6 @@ static int matvec_tile(const Geom& g) {
   if (matvec_blocks(g, 16) >= 4 * kNumCUs) return 16;
   if (matvec_blocks(g, 8) >= 4 * kNumCUs) return 8;
   return 4;
-}
-
-// Calls that need the preconditioner refuse 3D handles.
-static msp_status need_2d(msp_handle* h) {
-  if (h && h->dim != 2)
-    return fail(h, MSP_E_INVALID, "dim = 3: only the stiffness product is built for 3D meshes");
-  return MSP_OK;
 }
 
 extern "C" msp_status msp_create(const msp_problem_desc* d,
@@ -974,9 +1021,12 @@ static msp_status ensure_3d_buffers(msp_handle* h) {
   if (h->d_A3 != nullptr) return MSP_OK;
   const msp_problem_desc& d = h->desc;
   const Geom& g = h->g;
-  if (d.eig_kmax != 0 || d.rot_enrich != 0)
-    return fail(h, MSP_E_INVALID, "dim = 3: the coarse space is not built; "
-                                  "set eig_kmax = 0 and rot_enrich = 0 (first level only)");
+  if (d.eig_kmax < 0 || d.eig_kmax > 24)
+    return fail(h, MSP_E_INVALID, "eig_kmax must lie in 0..24 (0: first level only)");
+  if (d.eig_kmax > 0 && !(d.eig_tau > 0.0))
+    return fail(h, MSP_E_INVALID, "eig_tau must be positive");
+  if (d.eig_random != 0)
+    return fail(h, MSP_E_INVALID, "dim = 3: the randomized heat setup is built for 2D meshes only");
   if (d.sub_mode != 0)
     return fail(h, MSP_E_INVALID, "dim = 3: only box subdomains (sub_mode 0)");
   const int nel[3] = {g.nx, g.ny, g.nz};
@@ -1084,20 +1134,261 @@ static msp_status ensure_3d_buffers(msp_handle* h) {
   return MSP_OK;
 }
 
-// z = sum_i R_i^T K_i^{-1} R_i r on a 3D handle (sc: skip when the PCG run
-// is over).
-static void level1_3d(msp_handle* h, const double* r, double* z,
-                      const CGScalars* sc, hipStream_t s) {
+// z = M^{-1} r on a 3D handle: the first level sum_i R_i^T K_i^{-1} R_i r
+// (l1) plus the coarse term R_0^T K_0^+ R_0 r (coarse, when the setup built
+// a coarse space); sc: skip when the PCG run is over.
+static void prec_3d(msp_handle* h, const double* r, double* z,
+                    const CGScalars* sc, bool l1, bool coarse, hipStream_t s) {
+  const msp_problem_desc& d = h->desc;
+  Coarse3 cc{};
+  if (coarse && h->nc > 0) {
+    const int tr = timer_begin(h, KT_RESTRICT, s);
+    launch_coarse3_restrict(h->g, h->d_nb3, (int)h->nb3_h.size(), d.sub_nel[0],
+                            d.sub_nel[1], d.sub_nel[2], h->invH, h->d_nmask,
+                            h->d_psi3, r, h->d_c, sc, s);
+    launch_coarse3_gemv(h->d_K0, h->ldk, h->nc, h->d_c, h->d_c0, sc, s);
+    timer_end(h, KT_RESTRICT, tr, s);
+    cc.nb = h->d_nb3;
+    cc.ncx = h->ncx3;
+    cc.ncy = h->ncy3;
+    cc.ncz = h->ncz3;
+    cc.S0 = d.sub_nel[0];
+    cc.S1 = d.sub_nel[1];
+    cc.S2 = d.sub_nel[2];
+    cc.invH = h->invH;
+    cc.psi = h->d_psi3;
+    cc.c0 = h->d_c0;
+  }
   const int t = timer_begin(h, KT_LEVEL1, s);
   launch_level1_3d(h->g, h->d_subs3, (int)h->subs3.size(), h->ld3, h->nbx3,
-                   h->nby3, h->nbz3, h->desc.sub_nel[0], h->desc.sub_nel[1],
-                   h->desc.sub_nel[2], h->d_A3, h->fp32 ? h->d_A3f : nullptr,
-                   h->d_mask, r, h->d_lsol, z, sc, s);
+                   h->nby3, h->nbz3, d.sub_nel[0], d.sub_nel[1], d.sub_nel[2],
+                   h->d_A3, h->fp32 ? h->d_A3f : nullptr, h->d_mask, r, h->d_lsol,
+                   z, sc, l1 ? 1 : 0, cc, s);
   timer_end(h, KT_LEVEL1, t, s);
 }
 
+// Coarse nodes of a 3D mesh (the block corners, x fastest) with the node
+// boxes of their neighbourhoods omega_l = supp chi_l (Section 4.1), the
+// plane layout of the heat factors and the eigen iteration's buffers; once
+// per handle.
+static msp_status ensure_coarse3(msp_handle* h) {
+  if (h->d_nb3 != nullptr) return MSP_OK;
+  const msp_problem_desc& d = h->desc;
+  const Geom& g = h->g;
+  const int S[3] = {d.sub_nel[0], d.sub_nel[1], d.sub_nel[2]};
+  const int nel[3] = {g.nx, g.ny, g.nz};
+  for (long long p = 0; p < h->n_nodes; ++p) {
+    const int f = (h->mask_h[3 * p] ? 1 : 0) + (h->mask_h[3 * p + 1] ? 1 : 0) +
+                  (h->mask_h[3 * p + 2] ? 1 : 0);
+    if (f != 0 && f != 3)
+      return fail(h, MSP_E_INVALID, "dim = 3 with a coarse space: every node must be "
+                                    "clamped in all three components or in none");
+  }
+  const int ncx = nel[0] / S[0] + 1, ncy = nel[1] / S[1] + 1, ncz = nel[2] / S[2] + 1;
+  h->nb3_h.clear();
+  int pmax = 0, maxnp = 0;
+  for (int cz = 0; cz < ncz; ++cz)
+    for (int cy = 0; cy < ncy; ++cy)
+      for (int cx = 0; cx < ncx; ++cx) {
+        const int c[3] = {cx, cy, cz};
+        int lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+          lo[a] = std::max(0, (c[a] - 1) * S[a]);
+          hi[a] = std::min(nel[a], (c[a] + 1) * S[a]);
+        }
+        Nbh3 w{};
+        w.cx = cx;
+        w.cy = cy;
+        w.cz = cz;
+        w.x0 = lo[0];
+        w.y0 = lo[1];
+        w.z0 = lo[2];
+        w.nbx = hi[0] - lo[0] + 1;
+        w.nby = hi[1] - lo[1] + 1;
+        w.nbz = hi[2] - lo[2] + 1;
+        w.np = w.nbx * w.nby;
+        pmax = std::max(pmax, w.nbz);
+        maxnp = std::max(maxnp, w.np);
+        h->nb3_h.push_back(w);
+      }
+  const int ldp = (maxnp + 63) / 64 * 64;
+  if (ldp > coarse3_max_plane())
+    return fail(h, MSP_E_INVALID, "dim = 3: a neighbourhood's node plane exceeds 256 nodes "
+                                  "(reduce sub_nel)");
+  const int m = eig3_block(d.eig_kmax);
+  const long long nnb = (long long)h->nb3_h.size();
+  const long long ldp2 = (long long)ldp * ldp;
+  for (long long l = 0; l < nnb; ++l) {
+    h->nb3_h[l].goff = l * pmax * ldp2;
+    h->nb3_h[l].xoff = l * pmax * ldp * m;
+  }
+  h->ncx3 = ncx;
+  h->ncy3 = ncy;
+  h->ncz3 = ncz;
+  h->pmax3 = pmax;
+  h->ldp3 = ldp;
+  h->m3 = m;
+  h->H = std::max(S[0], std::max(S[1], S[2])) * d.h;
+  h->invH = 1.0 / h->H;
+  const long long nx = nnb * pmax * ldp * m;
+  bool ok = true;
+  auto A = [&](hipError_t e) { if (e != hipSuccess) ok = false; };
+  A(dalloc(&h->d_nb3, nnb));
+  A(dalloc(&h->d_G3, nnb * pmax * ldp2));
+  A(dalloc(&h->d_X3, nx));
+  A(dalloc(&h->d_Y3, nx));
+  A(dalloc(&h->d_T3, nx));
+  A(dalloc(&h->d_U3, nx));
+  A(dalloc((char**)&h->d_est3, nnb * (long long)eig3_state_bytes()));
+  A(dalloc(&h->d_hsd3, nnb * ldp));
+  A(dalloc(&h->d_hLD3, nnb * 64 * 65));
+  A(dalloc(&h->d_hLp3, nnb * 64 * ldp));
+  A(dalloc(&h->d_hRp3, nnb * 64 * ldp));
+  A(dalloc(&h->d_hel3, 128));
+  A(dalloc(&h->d_nsel, nnb));
+  A(dalloc(&h->d_cap, nnb));
+  A(dalloc(&h->d_lam, nnb * std::max(1, d.eig_kmax)));
+  if (!ok) return fail(h, MSP_E_NOMEM, "device allocation of the 3D coarse space failed");
+  double hel[128];
+  h8_heat_element(d.h, hel, hel + 64);
+  HIPCHK(h, hipMemcpy(h->d_hel3, hel, sizeof(hel), hipMemcpyHostToDevice));
+  return MSP_OK;
+}
+
+// The 3D coarse space from the current moduli (Sections 4.1-4.3): heat
+// factors by planes, the subspace iteration to convergence, the threshold,
+// then the columns, K Phi, K_0 and its generalised inverse.
+static msp_status setup_coarse3(msp_handle* h, hipStream_t s) {
+  msp_status st = ensure_coarse3(h);
+  if (st != MSP_OK) return st;
+  const Geom& g = h->g;
+  const msp_problem_desc& d = h->desc;
+  const int nnb = (int)h->nb3_h.size();
+  const int kmax = d.eig_kmax, m = h->m3, pmax = h->pmax3, ldp = h->ldp3;
+  const int S0 = d.sub_nel[0], S1 = d.sub_nel[1], S2 = d.sub_nel[2];
+  const double sigma = kShift / (h->H * h->H);
+  const double lim = d.eig_tau / (h->H * h->H);
+  for (Nbh3& w : h->nb3_h) {
+    w.nmodes = 0;
+    w.nrot = 0;
+    w.col0 = 0;
+    w.psi_off = 0;
+    w.woff = 0;
+  }
+  HIPCHK(h, hipMemcpyAsync(h->d_nb3, h->nb3_h.data(), nnb * sizeof(Nbh3), hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemsetAsync(h->d_err, 0, 4 * sizeof(int), s));
+  HIPCHK(h, hipMemsetAsync(h->d_dropped, 0, sizeof(int), s));
+  const int tk = timer_begin(h, KT_EIGEN, s);
+  launch_heat3_factor(g, h->d_nb3, nnb, pmax, ldp, h->d_E, h->d_nmask, h->d_hel3, sigma,
+                      h->d_G3, h->d_hsd3, h->d_hLD3, h->d_hLp3, h->d_hRp3, h->d_dropped, s);
+  launch_heat3_start(g, h->d_nb3, nnb, pmax, ldp, m, h->d_nmask, h->d_X3, h->d_est3, s);
+  int unconv = nnb;
+  for (int it = 0; it < kEig3MaxIt; ++it) {
+    launch_heat3_step(m, g, h->d_nb3, nnb, pmax, ldp, h->d_E, h->d_nmask, h->d_hel3,
+                      sigma, h->d_G3, h->d_X3, h->d_Y3, h->d_T3, h->d_U3, h->d_est3,
+                      kmax, lim, kEigTol, it == 0 ? 1 : 0, h->d_err, s);
+    if (it % 2 == 1 || it + 1 == kEig3MaxIt) {
+      launch_heat3_count(h->d_est3, nnb, kEig3Passes, h->d_err + 2, s);
+      HIPCHK(h, hipGetLastError());
+      HIPCHK(h, hipMemcpyAsync(h->h_int + 8, h->d_err + 2, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(h, hipStreamSynchronize(s));
+      unconv = h->h_int[8];
+      if (unconv == 0) break;
+    }
+  }
+  launch_heat3_select(h->d_est3, nnb, m, kmax, lim, h->d_nsel, h->d_cap, h->d_lam, s);
+  timer_end(h, KT_EIGEN, tk, s);
+  HIPCHK(h, hipGetLastError());
+  h->nsel_h.resize(nnb);
+  std::vector<int> cap(nnb);
+  h->lam_h.resize((size_t)nnb * kmax);
+  HIPCHK(h, hipMemcpyAsync(h->h_int, h->d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(h->h_int + 1, h->d_dropped, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  timer_flush(h);
+  if (h->h_int[1] != 0)
+    return fail(h, MSP_E_NOT_SPD, "a 3D heat pencil's plane factor lost positive definiteness");
+  if (h->h_int[0] & ERR_EIG)
+    return fail(h, MSP_E_NOT_SPD, "3D heat eigen setup lost positive definiteness of the subspace Gram matrix");
+  HIPCHK(h, hipMemcpy(h->nsel_h.data(), h->d_nsel, nnb * sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(h, hipMemcpy(cap.data(), h->d_cap, nnb * sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(h, hipMemcpy(h->lam_h.data(), h->d_lam, (size_t)nnb * kmax * sizeof(double), hipMemcpyDeviceToHost));
+  h->eig_unconverged = unconv;
+  // columns: per coarse node the modes of each component, then 3 rotations
+  const bool rot = d.rot_enrich != 0;
+  int col = 0;
+  long long poff = 0, woff = 0;
+  std::vector<int> col_node;
+  h->cap_hits = 0;
+  for (int l = 0; l < nnb; ++l) {
+    Nbh3& w = h->nb3_h[l];
+    const long long nbox = (long long)w.nbz * w.np;
+    w.nmodes = h->nsel_h[l];
+    w.nrot = (rot && w.nmodes >= 1) ? 3 : 0;
+    w.col0 = col;
+    w.psi_off = poff;
+    w.woff = woff;
+    const int ncol = 3 * w.nmodes + w.nrot;
+    for (int j = 0; j < ncol; ++j) col_node.push_back(l);
+    col += ncol;
+    poff += nbox * w.nmodes;
+    woff += (long long)ncol * nbox * 3;
+    h->cap_hits += cap[l];
+  }
+  h->nc = col;
+  // every coarse node carries its rotations: sum_l chi_l r_l = 0 for each
+  // of the three, so the last node's rotation columns are dropped
+  bool all_rot = rot && nnb > 0;
+  for (const Nbh3& w : h->nb3_h) all_rot = all_rot && w.nrot == 3;
+  h->dep_col = all_rot ? h->nb3_h.back().col0 + 3 * h->nb3_h.back().nmodes : -1;
+  h->ndep3 = all_rot ? 3 : 0;
+  h->ldk = std::max(64, ((col + 63) / 64) * 64);
+  if (h->ldk > kMaxCoarse3)
+    return fail(h, MSP_E_INVALID, "3D coarse dimension exceeds 32768 (reduce eig_kmax)");
+  std::vector<int2> pairs;
+  for (int l = 0; l < nnb; ++l)
+    for (int l2 = 0; l2 < nnb; ++l2) {
+      const Nbh3 &a = h->nb3_h[l], &b = h->nb3_h[l2];
+      if (std::abs(a.cx - b.cx) <= 1 && std::abs(a.cy - b.cy) <= 1 &&
+          std::abs(a.cz - b.cz) <= 1 && 3 * a.nmodes + a.nrot > 0 && 3 * b.nmodes + b.nrot > 0)
+        pairs.push_back(make_int2(l, l2));
+    }
+  st = ensure_coarse_buffers(h, col_node.size(), pairs.size(),
+                             (size_t)std::max<long long>(woff, 1), h->ldk);
+  if (st != MSP_OK) return st;
+  if ((size_t)std::max<long long>(poff, 1) > h->psi3_cap) {
+    dfree(h->d_psi3);
+    h->d_psi3 = nullptr;
+    h->psi3_cap = 0;
+    HIPCHK(h, dalloc(&h->d_psi3, (size_t)std::max<long long>(poff, 1)));
+    h->psi3_cap = (size_t)std::max<long long>(poff, 1);
+  }
+  HIPCHK(h, hipMemcpyAsync(h->d_nb3, h->nb3_h.data(), nnb * sizeof(Nbh3), hipMemcpyHostToDevice, s));
+  if (!col_node.empty())
+    HIPCHK(h, hipMemcpyAsync(h->d_col_node, col_node.data(), col_node.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  if (!pairs.empty())
+    HIPCHK(h, hipMemcpyAsync(h->d_pairs, pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+  h->npairs = (int)pairs.size();
+  launch_heat3_psi(m, h->d_nb3, nnb, pmax, ldp, h->d_X3, h->d_psi3, s);
+  launch_coarse3_kphi(g, h->d_nb3, h->d_col_node, col, pmax, S0, S1, S2, h->invH,
+                      h->d_elem, h->d_E, h->d_nmask, h->d_psi3, h->d_W, s);
+  HIPCHK(h, hipMemsetAsync(h->d_K0, 0, (size_t)h->ldk * h->ldk * sizeof(double), s));
+  launch_coarse3_k0(g, h->d_nb3, h->d_pairs, h->npairs, S0, S1, S2, h->invH, h->d_nmask,
+                    h->d_psi3, h->d_W, h->d_K0, h->ldk, s);
+  HIPCHK(h, hipMemsetAsync(h->d_dropped, 0, sizeof(int), s));
+  launch_k0_pinv(h->d_K0, h->ldk, h->nc, h->dep_col, h->ndep3, h->d_sdiag, h->d_P,
+                 h->d_Lp, h->d_Rp, kPivotDrop, h->d_dropped, s);
+  HIPCHK(h, hipMemsetAsync(h->d_c, 0, (size_t)h->ldk * sizeof(double), s));
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(h->h_int + 1, h->d_dropped, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  h->rank = h->ldk - h->h_int[1];
+  return MSP_OK;
+}
+
 // Setup of the 3D first level: gather every K_i densely, invert them all
-// at once, round to FP32 on the mixed path.
+// at once, round to FP32 on the mixed path; then the coarse space when
+// eig_kmax > 0.
 static msp_status setup_3d(msp_handle* h, hipStream_t s) {
   if (!h->have_E) return fail(h, MSP_E_STATE, "msp_set_densities must come first");
   msp_status st = ensure_3d_buffers(h);
@@ -1122,16 +1413,35 @@ static msp_status setup_3d(msp_handle* h, hipStream_t s) {
   HIPCHK(h, hipEventSynchronize(e1));
   float msf = 0.f;
   HIPCHK(h, hipEventElapsedTime(&msf, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   timer_flush(h);
   if (h->h_int[1] != 0) {
     h->setup_ok = false;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     return fail(h, MSP_E_NOT_SPD, "a 3D local system has a non-positive pivot");
   }
-  h->t_setup_ms = msf;
   h->nc = 0;
   h->rank = 0;
+  h->cap_hits = 0;
+  h->eig_unconverged = 0;
+  if (h->desc.eig_kmax > 0) {
+    HIPCHK(h, hipEventRecord(e0, s));
+    st = setup_coarse3(h, s);
+    if (st != MSP_OK) {
+      h->setup_ok = false;
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return st;
+    }
+    HIPCHK(h, hipEventRecord(e1, s));
+    HIPCHK(h, hipEventSynchronize(e1));
+    float msc = 0.f;
+    HIPCHK(h, hipEventElapsedTime(&msc, e0, e1));
+    msf += msc;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->t_setup_ms = msf;
   h->setup_ok = true;
   h->setup_gen = h->dens_gen;
   h->rebuild_due = false;
@@ -1269,8 +1579,8 @@ extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
   launch_coarse_k0(g, h->d_cn, h->d_pairs, (int)pairs.size(), h->d_mask,
                    h->d_psi, h->d_W, h->d_K0, h->ldk, h->invH, s);
   HIPCHK(h, hipMemsetAsync(h->d_dropped, 0, sizeof(int), s));
-  launch_k0_pinv(h->d_K0, h->ldk, h->nc, dep_col, h->d_sdiag, h->d_P, h->d_Lp,
-                 h->d_Rp, kPivotDrop, h->d_dropped, s);
+  launch_k0_pinv(h->d_K0, h->ldk, h->nc, dep_col, dep_col >= 0 ? 1 : 0, h->d_sdiag,
+                 h->d_P, h->d_Lp, h->d_Rp, kPivotDrop, h->d_dropped, s);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipMemcpyAsync(h->h_int + 1, h->d_dropped, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipEventRecord(e1, s));
@@ -1485,9 +1795,7 @@ static msp_status apply_parts(msp_handle* h, const double* r, double* z,
   msp_status st = check_ready(h, s);
   if (st != MSP_OK) return st;
   if (h->dim == 3) {
-    // no coarse space in 3D: its part is zero
-    if (l1) level1_3d(h, r, z, nullptr, s);
-    else HIPCHK(h, hipMemsetAsync(z, 0, h->n_dofs * sizeof(double), s));
+    prec_3d(h, r, z, nullptr, l1, coarse, s);
   } else {
     enqueue_prec(h, 0, r, nullptr, z, l1, coarse, false, s);
   }
@@ -1695,7 +2003,7 @@ static void chunk_single(msp_handle* h, hipStream_t s) {
   }
 }
 
-// ---- 3D PCG (first-level preconditioner) ---------------------------------
+// ---- 3D PCG (two-level preconditioner; first level alone at eig_kmax = 0) --
 
 // Fresh segment of a 3D run: r = f - K x, ||f||, z = M^{-1} r, r.z, p = z.
 static msp_status seg3_launch(SolveRun& R, hipStream_t s) {
@@ -1708,7 +2016,7 @@ static msp_status seg3_launch(SolveRun& R, hipStream_t s) {
   launch_apply_K3(h->g, h->d_elem, h->d_E, h->d_nmask, h->d_x, h->d_q, s);
   launch_cg3_resid(n, R.f, h->d_q, h->d_x, h->d_mask, h->d_r, h->d_sc, h->d_part,
                    h->d_tk3, 0, s);
-  level1_3d(h, h->d_r, h->d_z, nullptr, s);
+  prec_3d(h, h->d_r, h->d_z, nullptr, true, true, s);
   launch_cg3_rz(n, h->d_r, h->d_z, h->d_q, h->d_sc, h->d_part, h->d_tk3,
                 h->d_bhist, 1, s);
   HIPCHK(h, hipMemsetAsync(h->d_p0, 0, n * sizeof(double), s));
@@ -1729,7 +2037,7 @@ static void chunk3(msp_handle* h, hipStream_t s) {
     launch_cg3_pq(n, h->d_p0, h->d_q, h->d_sc, h->d_part, h->d_tk3, h->d_ahist, s);
     launch_cg3_update(n, h->d_x, h->d_r, h->d_p0, h->d_q, h->d_sc, h->d_part,
                       h->d_tk3, s);
-    level1_3d(h, h->d_r, h->d_z, h->d_sc, s);
+    prec_3d(h, h->d_r, h->d_z, h->d_sc, true, true, s);
     launch_cg3_rz(n, h->d_r, h->d_z, h->d_q, h->d_sc, h->d_part, h->d_tk3,
                   h->d_bhist, 0, s);
     launch_cg3_p(n, h->d_z, h->d_p0, h->d_sc, s);
@@ -2649,9 +2957,20 @@ extern "C" msp_status msp_coarse_info(msp_handle* h, int32_t* n_modes,
                                       double* eigvals, int32_t* n_cnodes,
                                       int32_t* n_coarse, int32_t* cap_hits) {
   if (!h) return fail(h, MSP_E_INVALID, "null handle");
-  if (need_2d(h) != MSP_OK) return MSP_E_INVALID;
   if (!h->setup_ok) return fail(h, MSP_E_STATE, "no setup");
   const int kmax = h->desc.eig_kmax;
+  if (h->dim == 3) {
+    const size_t nnb = h->desc.eig_kmax > 0 ? h->nb3_h.size() : 0;
+    for (size_t l = 0; l < nnb; ++l) {
+      if (n_modes) n_modes[l] = h->nsel_h[l];
+      if (eigvals)
+        for (int j = 0; j < kmax; ++j) eigvals[l * kmax + j] = h->lam_h[l * kmax + j];
+    }
+    if (n_cnodes) *n_cnodes = (int32_t)nnb;
+    if (n_coarse) *n_coarse = h->nc;
+    if (cap_hits) *cap_hits = h->cap_hits;
+    return MSP_OK;
+  }
   for (size_t l = 0; l < h->cn_h.size(); ++l) {
     const int sys = h->cn_h[l].sys;
     if (n_modes) n_modes[l] = h->nsel_h[sys];
@@ -2667,8 +2986,16 @@ extern "C" msp_status msp_coarse_info(msp_handle* h, int32_t* n_modes,
 extern "C" msp_status msp_coarse_basis(msp_handle* h, double* phi,
                                        hipStream_t s) {
   if (!h || !phi) return fail(h, MSP_E_INVALID, "null argument");
-  if (need_2d(h) != MSP_OK) return MSP_E_INVALID;
   if (!h->setup_ok) return fail(h, MSP_E_STATE, "no setup");
+  if (h->dim == 3) {
+    const msp_problem_desc& d = h->desc;
+    launch_coarse3_export(h->g, h->d_nb3, h->d_col_node, h->nc, d.sub_nel[0],
+                          d.sub_nel[1], d.sub_nel[2], h->invH, h->d_nmask, h->d_psi3,
+                          phi, s);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipStreamSynchronize(s));
+    return MSP_OK;
+  }
   launch_export_basis(h->g, h->d_cn, h->d_col_node, h->nc, h->d_mask, h->d_psi,
                       phi, h->invH, s);
   HIPCHK(h, hipGetLastError());
@@ -2680,11 +3007,17 @@ extern "C" msp_status msp_coarse_matrix(msp_handle* h, int32_t which,
                                         double* out, hipStream_t s) {
   if (!h || !out || (which != 0 && which != 1))
     return fail(h, MSP_E_INVALID, "bad argument");
-  if (need_2d(h) != MSP_OK) return MSP_E_INVALID;
   if (!h->setup_ok) return fail(h, MSP_E_STATE, "no setup");
+  if (h->nc == 0) return fail(h, MSP_E_STATE, "the setup built no coarse space");
   const size_t bytes = (size_t)h->ldk * h->ldk * sizeof(double);
   if (which == 1) {
     HIPCHK(h, hipMemcpyAsync(out, h->d_K0, bytes, hipMemcpyDeviceToDevice, s));
+  } else if (h->dim == 3) {
+    const msp_problem_desc& d = h->desc;
+    HIPCHK(h, hipMemsetAsync(out, 0, bytes, s));
+    launch_coarse3_k0(h->g, h->d_nb3, h->d_pairs, h->npairs, d.sub_nel[0], d.sub_nel[1],
+                      d.sub_nel[2], h->invH, h->d_nmask, h->d_psi3, h->d_W, out, h->ldk, s);
+    HIPCHK(h, hipGetLastError());
   } else {
     // the setup's K Phi columns are still held; redo the block products
     HIPCHK(h, hipMemsetAsync(out, 0, bytes, s));
@@ -2741,7 +3074,19 @@ extern "C" msp_status msp_query(msp_handle* h, int64_t* q) {
     q[5] = maxn;
     q[6] = l1;
     q[8] = h->l3_vec;
-    q[11] = h->ld3;
+    if (h->desc.eig_kmax > 0 && !h->nb3_h.empty()) {
+      long long psi = 0, om = 0;
+      for (const Nbh3& w : h->nb3_h) {
+        psi += (long long)w.nmodes * w.nbz * w.np * 8;
+        om += (long long)w.nbz * w.np;
+      }
+      q[3] = (int64_t)h->nb3_h.size();
+      q[4] = h->nc;
+      q[7] = psi;
+      q[9] = om;
+      q[10] = (long long)h->nb3_h.size() * h->pmax3 * h->ldp3 * h->ldp3 * 8;
+      q[11] = h->nc > 0 ? h->ldk : 0;
+    }
     return MSP_OK;
   }
   long long maxsys = 0;
