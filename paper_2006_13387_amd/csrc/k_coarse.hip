@@ -195,15 +195,17 @@ k_coarse_k0(Geom g, const CoarseNode* __restrict__ cnodes,
 }
 
 // Symmetrise, scale to unit diagonal (s_j = 1/sqrt(K0_jj), 0 for empty
-// columns, padding and the ndep dependent columns from dep_col, so that
-// their pivots are dropped).  One thread per entry.
+// columns, padding, the ndep dependent columns from dep_col and the columns
+// flagged in drop (when given), so that their pivots are dropped).  One
+// thread per entry.
 __global__ void k_k0_scale_factors(const double* __restrict__ K0, int ldk,
                                    int nc, int dep_col, int ndep,
+                                   const uint8_t* __restrict__ drop,
                                    double* __restrict__ sdiag) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= ldk) return;
   double s = 0.0;
-  if (j < nc && (j < dep_col || j >= dep_col + ndep)) {
+  if (j < nc && (j < dep_col || j >= dep_col + ndep) && !(drop != nullptr && drop[j])) {
     const double d = K0[(long long)j * ldk + j];
     if (d > 0.0 && finite(d)) s = 1.0 / sqrt(d);
   }
@@ -1031,10 +1033,10 @@ void launch_gj_steps(double* A, int ld, int nmat, GjStride bs, double* LD,
 }
 
 void launch_k0_pinv(double* K0, int ldk, int nc, int dep_col, int ndep,
-                    double* sdiag, double* P, double* Lp, double* Rp, double tol,
-                    int* dropped, hipStream_t s) {
+                    const uint8_t* drop, double* sdiag, double* P, double* Lp,
+                    double* Rp, double tol, int* dropped, hipStream_t s) {
   hipLaunchKernelGGL(k_k0_scale_factors, dim3((ldk + 255) / 256), dim3(256), 0,
-                     s, K0, ldk, nc, dep_col, ndep, sdiag);
+                     s, K0, ldk, nc, dep_col, ndep, drop, sdiag);
   const long long n2 = (long long)ldk * ldk;
   hipLaunchKernelGGL(k_k0_scale, dim3((unsigned)((n2 + 255) / 256)), dim3(256),
                      0, s, K0, ldk, sdiag);

@@ -80,8 +80,8 @@ void launch_coarse_kphi(const Geom&, const CoarseNode*, const int*, int,
 void launch_coarse_k0(const Geom&, const CoarseNode*, const int2*, int,
                       const uint8_t*, const double*, const double*, double*,
                       int, double, hipStream_t);
-void launch_k0_pinv(double*, int, int, int, int, double*, double*, double*,
-                    double*, double, int*, hipStream_t);
+void launch_k0_pinv(double*, int, int, int, int, const uint8_t*, double*, double*,
+                    double*, double*, double, int*, hipStream_t);
 void launch_restrict(const RestrictArgs&, int ncn, hipStream_t);
 void launch_restrict_batch(const RestrictArgs*, const int*, int, int, hipStream_t);
 int restrict_bands();
@@ -340,6 +340,8 @@ struct msp_handle {
   double* d_psi3 = nullptr;
   size_t psi3_cap = 0;
   int ndep3 = 0;                   // dependent rotation columns dropped from K_0
+  uint8_t* d_drop3 = nullptr;      // per K_0 column: 1 = dropped as dependent
+  size_t drop3_cap = 0;
 };
 
 namespace {
@@ -627,7 +629,7 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
                   h->d_subs3, h->d_A3, h->d_A3f, h->d_LD3, h->d_Lp3, h->d_Rp3,
                   h->d_sd3, h->d_tk3, h->d_nb3, h->d_G3, h->d_X3, h->d_Y3,
                   h->d_T3, h->d_U3, h->d_est3, h->d_hsd3, h->d_hLD3, h->d_hLp3,
-                  h->d_hRp3, h->d_hel3, h->d_psi3};
+                  h->d_hRp3, h->d_hel3, h->d_psi3, h->d_drop3};
   for (void* p : bufs) dfree(p);
   for (int k = 0; k < KT_COUNT; ++k)
     for (hipEvent_t e : h->kt[k].ev) (void)hipEventDestroy(e);
@@ -1336,12 +1338,36 @@ static msp_status setup_coarse3(msp_handle* h, hipStream_t s) {
     h->cap_hits += cap[l];
   }
   h->nc = col;
-  // every coarse node carries its rotations: sum_l chi_l r_l = 0 for each
-  // of the three, so the last node's rotation columns are dropped
-  bool all_rot = rot && nnb > 0;
-  for (const Nbh3& w : h->nb3_h) all_rot = all_rot && w.nrot == 3;
-  h->dep_col = all_rot ? h->nb3_h.back().col0 + 3 * h->nb3_h.back().nmodes : -1;
-  h->ndep3 = all_rot ? 3 : 0;
+  // Dependent rotation columns.  The rotation about axis a does not involve
+  // the coordinate along a, and the hats of a plane of coarse nodes
+  // perpendicular to a reproduce linear functions in the other two
+  // coordinates, so sum over such a plane of chi_l r_{a,l} = 0 whenever
+  // every node of the plane carries its rotations: one dependency per such
+  // plane (they also imply the global identities).  The last node's
+  // rotation about a in each such plane is dropped.
+  std::vector<uint8_t> drop(col > 0 ? col : 1, 0);
+  h->ndep3 = 0;
+  if (rot) {
+    const int nca[3] = {h->ncx3, h->ncy3, h->ncz3};
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < nca[a]; ++c) {
+        bool all = true;
+        int last = -1;
+        for (int l = 0; l < nnb; ++l) {
+          const Nbh3& w = h->nb3_h[l];
+          const int cc = a == 0 ? w.cx : (a == 1 ? w.cy : w.cz);
+          if (cc != c) continue;
+          all = all && w.nrot == 3;
+          last = l;
+        }
+        if (all && last >= 0) {
+          const Nbh3& w = h->nb3_h[last];
+          drop[w.col0 + 3 * w.nmodes + a] = 1;
+          ++h->ndep3;
+        }
+      }
+  }
+  h->dep_col = -1;
   h->ldk = std::max(64, ((col + 63) / 64) * 64);
   if (h->ldk > kMaxCoarse3)
     return fail(h, MSP_E_INVALID, "3D coarse dimension exceeds 32768 (reduce eig_kmax)");
@@ -1356,6 +1382,13 @@ static msp_status setup_coarse3(msp_handle* h, hipStream_t s) {
   st = ensure_coarse_buffers(h, col_node.size(), pairs.size(),
                              (size_t)std::max<long long>(woff, 1), h->ldk);
   if (st != MSP_OK) return st;
+  if ((size_t)h->ldk > h->drop3_cap) {
+    dfree(h->d_drop3);
+    h->d_drop3 = nullptr;
+    h->drop3_cap = 0;
+    HIPCHK(h, dalloc(&h->d_drop3, (size_t)h->ldk));
+    h->drop3_cap = (size_t)h->ldk;
+  }
   if ((size_t)std::max<long long>(poff, 1) > h->psi3_cap) {
     dfree(h->d_psi3);
     h->d_psi3 = nullptr;
@@ -1376,7 +1409,8 @@ static msp_status setup_coarse3(msp_handle* h, hipStream_t s) {
   launch_coarse3_k0(g, h->d_nb3, h->d_pairs, h->npairs, S0, S1, S2, h->invH, h->d_nmask,
                     h->d_psi3, h->d_W, h->d_K0, h->ldk, s);
   HIPCHK(h, hipMemsetAsync(h->d_dropped, 0, sizeof(int), s));
-  launch_k0_pinv(h->d_K0, h->ldk, h->nc, h->dep_col, h->ndep3, h->d_sdiag, h->d_P,
+  HIPCHK(h, hipMemcpyAsync(h->d_drop3, drop.data(), drop.size(), hipMemcpyHostToDevice, s));
+  launch_k0_pinv(h->d_K0, h->ldk, h->nc, -1, 0, h->d_drop3, h->d_sdiag, h->d_P,
                  h->d_Lp, h->d_Rp, kPivotDrop, h->d_dropped, s);
   HIPCHK(h, hipMemsetAsync(h->d_c, 0, (size_t)h->ldk * sizeof(double), s));
   HIPCHK(h, hipGetLastError());
@@ -1579,8 +1613,8 @@ extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
   launch_coarse_k0(g, h->d_cn, h->d_pairs, (int)pairs.size(), h->d_mask,
                    h->d_psi, h->d_W, h->d_K0, h->ldk, h->invH, s);
   HIPCHK(h, hipMemsetAsync(h->d_dropped, 0, sizeof(int), s));
-  launch_k0_pinv(h->d_K0, h->ldk, h->nc, dep_col, dep_col >= 0 ? 1 : 0, h->d_sdiag,
-                 h->d_P, h->d_Lp, h->d_Rp, kPivotDrop, h->d_dropped, s);
+  launch_k0_pinv(h->d_K0, h->ldk, h->nc, dep_col, dep_col >= 0 ? 1 : 0, nullptr,
+                 h->d_sdiag, h->d_P, h->d_Lp, h->d_Rp, kPivotDrop, h->d_dropped, s);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipMemcpyAsync(h->h_int + 1, h->d_dropped, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipEventRecord(e1, s));
