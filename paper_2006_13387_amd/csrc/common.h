@@ -90,14 +90,15 @@ struct Sub3 {
 // in-plane node a, m values a row).  After the setup: nmodes selected heat
 // modes psi_j at psi_off (box node b = k np + a, value b nmodes + j), the
 // node's columns from col0 (mode j of component c at col0 + c nmodes + j,
-// rotation k at col0 + 3 nmodes + k) and their K Phi at woff (3 values per
+// rotation k at col0 + 3 nmodes + k; in K_0, whose columns are grouped by
+// slabs of coarse nodes, from kcol0) and their K Phi at woff (3 values per
 // box node a column).
 struct Nbh3 {
   int cx, cy, cz;
   int x0, y0, z0;
   int nbx, nby, nbz;
   int np;
-  int nmodes, nrot, col0, pad;
+  int nmodes, nrot, col0, kcol0;
   long long goff, xoff, psi_off, woff;
 };
 
@@ -108,7 +109,7 @@ struct Coarse3 {
   int S0, S1, S2;            // coarse block edge (elements)
   double invH;               // 1 / H (rotation scale)
   const double* psi;
-  const double* c0;          // K_0^+ R_0 r (null: no coarse part)
+  const double* c0;          // K_0^+ R_0 r in K_0's column order (null: no coarse part)
 };
 
 // Device scalars of one PCG run.

@@ -26,7 +26,9 @@ namespace msp {
 
 constexpr int T3_NT = 256;
 constexpr int LD3_MAX = 2048;     // largest local order (LDS of the apply)
-constexpr int V3_MAXB = 1024;     // workgroups of the vector kernels
+// workgroups of the vector kernels: one per CU (each workgroup takes its
+// ticket with one atomic on a shared counter, and those serialise)
+constexpr int V3_MAXB = 256;
 
 // ---------------------------------------------------------------------
 // Dense local matrices.  Thread per local row DOF q = 3 a + c (node a of
@@ -223,7 +225,7 @@ __device__ __forceinline__ double3 coarse3_prolong(const Geom& g, const Coarse3&
         const int nm = w.nmodes;
         if (3 * nm + w.nrot == 0) continue;
         const double chi = hx * hy * hz;
-        const double* cw = cc.c0 + w.col0;
+        const double* cw = cc.c0 + w.kcol0;
         const long long b = ((long long)(Z - w.z0) * w.nby + (Y - w.y0)) * w.nbx + (X - w.x0);
         const double* ps = cc.psi + w.psi_off + b * nm;
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;

@@ -16,6 +16,7 @@
 // Dropping a (numerically) dependent direction gives a generalized inverse
 // G of K_0, and R_0^T G R_0 does not depend on which one: it is the
 // K-orthogonal projection onto the coarse space composed with K^{-1}.
+#include <algorithm>
 #include "common.h"
 #include "dev.h"
 
@@ -360,12 +361,12 @@ k_gj_pivot(double* __restrict__ A, int ld, int kb, double* __restrict__ LD,
 // A_ij - A_ik P A_kj = A_ij - Lp_i Rp_j.
 constexpr int GJP_NT = 128;
 __global__ void __launch_bounds__(GJP_NT)
-k_gj_panel(double* __restrict__ A, int ld, int kb,
+k_gj_panel(double* __restrict__ A, int ld, int kb, int b0,
            const double* __restrict__ LD, double* __restrict__ Lp,
            double* __restrict__ Rp, GjStride bs) {
   __shared__ double Ls[GJB * GJB];
   __shared__ double Di[GJB];
-  const int ib = blockIdx.x;
+  const int ib = b0 + blockIdx.x;
   if (ib == kb) return;
   A += blockIdx.z * bs.a;
   LD += blockIdx.z * bs.ld;
@@ -439,14 +440,14 @@ k_gj_panel(double* __restrict__ A, int ld, int kb,
 
 // Block step kb, last part: A_ij -= Lp_i Rp_j for the tiles outside block
 // row and column kb (those were written by the first two parts).  Grid
-// (nblk, nblk) of 64 x 64 tiles.
+// (nblk, nblk) of 64 x 64 tiles from block b0 (0: the whole matrix).
 __global__ void __launch_bounds__(CK_NT)
-k_gj_update(double* __restrict__ A, int ld, int kb,
+k_gj_update(double* __restrict__ A, int ld, int kb, int b0,
             const double* __restrict__ Lp, const double* __restrict__ Rp,
             GjStride bs) {
   __shared__ double Ls[GJB * (GJB + 1)];
   __shared__ double Rs[GJB * (GJB + 1)];
-  const int ib = blockIdx.y, jb = blockIdx.x;
+  const int ib = b0 + blockIdx.y, jb = b0 + blockIdx.x;
   if (ib == kb || jb == kb) return;
   A += blockIdx.z * bs.a;
   Lp += blockIdx.z * bs.p;
@@ -1026,9 +1027,35 @@ void launch_gj_steps(double* A, int ld, int nmat, GjStride bs, double* LD,
     hipLaunchKernelGGL(k_gj_pivot, dim3(1, 1, nmat), dim3(CK_NT), 0, s, A, ld,
                        kb, LD, tol, dropped, bs);
     hipLaunchKernelGGL(k_gj_panel, dim3(nblk, 1, nmat), dim3(GJP_NT), 0, s, A,
-                       ld, kb, LD, Lp, Rp, bs);
+                       ld, kb, 0, LD, Lp, Rp, bs);
     hipLaunchKernelGGL(k_gj_update, dim3(nblk, nblk, nmat), dim3(CK_NT), 0, s,
-                       A, ld, kb, Lp, Rp, bs);
+                       A, ld, kb, 0, Lp, Rp, bs);
+  }
+}
+
+// Block LDL^T of a block-tridiagonal matrix (slab k: blocks [sb[k],
+// sb[k+1]) of 64 columns) by windowed Gauss-Jordan: slab k's pivot blocks
+// are eliminated with the panel and update steps restricted to the window
+// of slabs k and k+1.  Afterwards slab k's diagonal block holds the
+// (generalised) inverse G_k of its Schur complement S_k, the block right of
+// it G_k C_k and the block below it -C_k^T G_k (C_k the coupling of slab k
+// with slab k+1), and slab k+1's diagonal block has received
+// -C_k^T G_k C_k.
+void launch_gj_slabs(double* A, int ld, const int* sb, int nslab, double* LD,
+                     double* Lp, double* Rp, double tol, int* dropped,
+                     hipStream_t s) {
+  const GjStride bs{0, 0, 0};
+  for (int k = 0; k < nslab; ++k) {
+    const int w0 = sb[k], w1 = sb[std::min(k + 2, nslab)];
+    const int nw = w1 - w0;
+    for (int kb = sb[k]; kb < sb[k + 1]; ++kb) {
+      hipLaunchKernelGGL(k_gj_pivot, dim3(1, 1, 1), dim3(CK_NT), 0, s, A, ld, kb, LD,
+                         tol, dropped, bs);
+      hipLaunchKernelGGL(k_gj_panel, dim3(nw, 1, 1), dim3(GJP_NT), 0, s, A, ld, kb,
+                         w0, LD, Lp, Rp, bs);
+      hipLaunchKernelGGL(k_gj_update, dim3(nw, nw, 1), dim3(CK_NT), 0, s, A, ld, kb,
+                         w0, Lp, Rp, bs);
+    }
   }
 }
 
@@ -1043,6 +1070,24 @@ void launch_k0_pinv(double* K0, int ldk, int nc, int dep_col, int ndep,
   launch_gj_steps(K0, ldk, 1, GjStride{0, 0, 0}, P, Lp, Rp, tol, dropped, s);
   hipLaunchKernelGGL(k_k0_unscale, dim3((unsigned)((n2 + 255) / 256)),
                      dim3(256), 0, s, K0, ldk, sdiag);
+}
+
+void launch_gj_slabs(double*, int, const int*, int, double*, double*, double*, double,
+                     int*, hipStream_t);
+
+// Scaled block LDL^T of a block-tridiagonal K_0 (3D, slabs of coarse
+// nodes): unit-diagonal scaling (zero for padding, empty and flagged
+// columns), then the windowed Gauss-Jordan over the slabs; the factors stay
+// scaled (the solve applies sdiag on both sides).
+void launch_k0_slab_factor(double* K0, int ldk, const int* sb, int nslab,
+                           const uint8_t* drop, double* sdiag, double* P, double* Lp,
+                           double* Rp, double tol, int* dropped, hipStream_t s) {
+  hipLaunchKernelGGL(k_k0_scale_factors, dim3((ldk + 255) / 256), dim3(256), 0,
+                     s, K0, ldk, ldk, -1, 0, drop, sdiag);
+  const long long n2 = (long long)ldk * ldk;
+  hipLaunchKernelGGL(k_k0_scale, dim3((unsigned)((n2 + 255) / 256)), dim3(256),
+                     0, s, K0, ldk, sdiag);
+  launch_gj_slabs(K0, ldk, sb, nslab, P, Lp, Rp, tol, dropped, s);
 }
 
 void launch_restrict(const RestrictArgs& a, int ncn, hipStream_t s) {

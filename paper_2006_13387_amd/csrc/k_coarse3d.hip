@@ -741,14 +741,15 @@ k3c_kphi(Geom g, const Nbh3* __restrict__ nbs, const int* __restrict__ col_node,
 
 // K_0 block of the coarse-node pair (A, B): K_0(a, b) = sum over the
 // overlap of the two boxes of phi_a . W_b, the overlap's nodes taken in
-// chunks of K0C staged in LDS.  One workgroup per pair.
+// chunks of K0C staged in LDS, written in K_0's slab column order (compact
+// = 1: the plain column numbering col0).  One workgroup per pair.
 constexpr int K0C = 16;
 constexpr int K0_ACC = (C3_MAXCOL * C3_MAXCOL + C3_NT - 1) / C3_NT;
 __global__ void __launch_bounds__(C3_NT)
 k3c_k0(Geom g, const Nbh3* __restrict__ nbs, const int2* __restrict__ pairs,
        int S0, int S1, int S2, double invH, const uint8_t* __restrict__ nmask,
        const double* __restrict__ psi, const double* __restrict__ Wk,
-       double* __restrict__ K0, int ldk) {
+       double* __restrict__ K0, int ldk, int compact) {
   __shared__ double PA[C3_MAXCOL * 3 * K0C], WB[C3_MAXCOL * 3 * K0C];
   const int2 pr = pairs[blockIdx.x];
   const Nbh3 A = nbs[pr.x], B = nbs[pr.y];
@@ -815,7 +816,8 @@ k3c_k0(Geom g, const Nbh3* __restrict__ nbs, const int2* __restrict__ pairs,
     const int e = tid + u * C3_NT;
     if (e < nent) {
       const int qa = e / nb, qb = e - qa * nb;
-      K0[(long long)(A.col0 + qa) * ldk + B.col0 + qb] = acc[u];
+      const int ra = compact ? A.col0 : A.kcol0, rb = compact ? B.col0 : B.kcol0;
+      K0[(long long)(ra + qa) * ldk + rb + qb] = acc[u];
     }
   }
 }
@@ -845,9 +847,9 @@ k3c_export(Geom g, const Nbh3* __restrict__ nbs, const int* __restrict__ col_nod
 // ---------------------------------------------------------------------
 // Coarse apply
 
-// c = R_0 r: one workgroup per coarse node, its columns' sums over the box
-// (per-thread partials over a fixed node stride, then the workgroup sum in
-// fixed order); up to 16 modes a pass.
+// c = R_0 r (in K_0's slab column order): one workgroup per coarse node,
+// its columns' sums over the box (per-thread partials over a fixed node
+// stride, then the workgroup sum in fixed order); up to 16 modes a pass.
 __global__ void __launch_bounds__(C3_NT)
 k3c_restrict(Geom g, const Nbh3* __restrict__ nbs, int S0, int S1, int S2,
              double invH, const uint8_t* __restrict__ nmask,
@@ -909,43 +911,61 @@ k3c_restrict(Geom g, const Nbh3* __restrict__ nbs, int S0, int S1, int S2,
       const int u = tid;
       if (u < 48) {
         const int comp = u / 16, j = u - 16 * comp;
-        if (j < nj) c[w.col0 + comp * nm + j0 + j] = s;
+        if (j < nj) c[w.kcol0 + comp * nm + j0 + j] = s;
       } else if (rot) {
-        c[w.col0 + 3 * nm + (u - 48)] = s;
+        c[w.kcol0 + 3 * nm + (u - 48)] = s;
       }
     }
     __syncthreads();
   }
 }
 
-// c0 = K_0^+ c (rows of the padded inverse, 16-byte loads; c holds zeros
-// past N_c).  Workgroup = 4 waves, each two rows.
+// One step of the slab solve with K_0's block LDL^T (the windowed
+// Gauss-Jordan factors of the scaled K_0 = S K S, S = diag(sd)):
+//   out_i = sd_i bias_i + sum_{j in [a0, a1)} F_ij xa_j - sum_{j in [b0, b1)} F_ij xb_j
+// for the rows i of one slab, and outs_i = sd_i out_i when outs is set.
+// Forward, slab k: bias = c, a = slab k-1 with xa = w (F = -C^T G there),
+// out = w.  Backward: a = slab k with xa = w (F = G_k), b = slab k+1 with
+// xb = y (F = G_k C_k), out = y, outs = c0 = S y.  Each wave takes two rows
+// with 16-byte loads.
 __global__ void __launch_bounds__(256)
-k3c_gemv(const double* __restrict__ K0, int ldk, int nc, const double* __restrict__ c,
-         double* __restrict__ c0, const CGScalars* __restrict__ sc) {
+k3c_slab_step(const double* __restrict__ F, int ldk, int r0, int r1,
+              const double* __restrict__ bias, const double* __restrict__ sd,
+              int a0, int a1, const double* __restrict__ xa, int b0, int b1,
+              const double* __restrict__ xb, double* __restrict__ out,
+              double* __restrict__ outs, const CGScalars* __restrict__ sc) {
   __shared__ int shd;
   if (sc != nullptr && block_read_done(sc, &shd)) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r0 = blockIdx.x * 8 + 2 * wave;
-  if (r0 >= nc) return;
-  const int r1 = min(r0 + 1, nc - 1);
-  const double2* k0 = reinterpret_cast<const double2*>(K0 + (long long)r0 * ldk);
-  const double2* k1 = reinterpret_cast<const double2*>(K0 + (long long)r1 * ldk);
-  const double2* cv = reinterpret_cast<const double2*>(c);
-  double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
-  const int nv = ldk / 2;
-#pragma unroll 4
-  for (int j = lane; j < nv; j += 64) {
-    const double2 x = cv[j], p = k0[j], q = k1[j];
-    a0 = fma(p.x, x.x, a0);
-    a1 = fma(p.y, x.y, a1);
-    b0 = fma(q.x, x.x, b0);
-    b1 = fma(q.y, x.y, b1);
+  const int i0 = r0 + blockIdx.x * 8 + 2 * wave;
+  if (i0 >= r1) return;
+  const int i1 = min(i0 + 1, r1 - 1);
+  const double* f0 = F + (long long)i0 * ldk;
+  const double* f1 = F + (long long)i1 * ldk;
+  double s0 = 0.0, s1 = 0.0, t0 = 0.0, t1 = 0.0;
+  // column ranges are whole 64-column blocks: 16-byte loads stay aligned
+  for (int j = a0 + 2 * lane; j < a1; j += 128) {
+    const double2 x = *reinterpret_cast<const double2*>(xa + j);
+    const double2 p = *reinterpret_cast<const double2*>(f0 + j);
+    const double2 q = *reinterpret_cast<const double2*>(f1 + j);
+    s0 = fma(p.x, x.x, fma(p.y, x.y, s0));
+    s1 = fma(q.x, x.x, fma(q.y, x.y, s1));
   }
-  const double s0 = wave_sum(a0 + a1), s1 = wave_sum(b0 + b1);
-  if (lane == 0) {
-    c0[r0] = s0;
-    if (r0 + 1 < nc) c0[r0 + 1] = s1;
+  for (int j = b0 + 2 * lane; j < b1; j += 128) {
+    const double2 x = *reinterpret_cast<const double2*>(xb + j);
+    const double2 p = *reinterpret_cast<const double2*>(f0 + j);
+    const double2 q = *reinterpret_cast<const double2*>(f1 + j);
+    t0 = fma(p.x, x.x, fma(p.y, x.y, t0));
+    t1 = fma(q.x, x.x, fma(q.y, x.y, t1));
+  }
+  const double u0 = wave_sum(s0) - wave_sum(t0);
+  const double u1 = wave_sum(s1) - wave_sum(t1);
+  if (lane < 2 && (lane == 0 || i0 + 1 < r1)) {
+    const int i = lane == 0 ? i0 : i0 + 1;
+    double v = lane == 0 ? u0 : u1;
+    if (bias != nullptr) v += sd[i] * bias[i];
+    out[i] = v;
+    if (outs != nullptr) outs[i] = sd[i] * v;
   }
 }
 
@@ -1052,10 +1072,10 @@ void launch_coarse3_kphi(const Geom& g, const Nbh3* nbs, const int* col_node, in
 void launch_coarse3_k0(const Geom& g, const Nbh3* nbs, const int2* pairs, int npairs,
                        int S0, int S1, int S2, double invH, const uint8_t* nmask,
                        const double* psi, const double* W, double* K0, int ldk,
-                       hipStream_t s) {
+                       int compact, hipStream_t s) {
   if (npairs <= 0) return;
   hipLaunchKernelGGL(k3c_k0, dim3(npairs), dim3(C3_NT), 0, s, g, nbs, pairs, S0, S1,
-                     S2, invH, nmask, psi, W, K0, ldk);
+                     S2, invH, nmask, psi, W, K0, ldk, compact);
 }
 
 void launch_coarse3_export(const Geom& g, const Nbh3* nbs, const int* col_node,
@@ -1077,11 +1097,26 @@ void launch_coarse3_restrict(const Geom& g, const Nbh3* nbs, int nnb, int S0, in
                      invH, nmask, psi, r, c, sc);
 }
 
-void launch_coarse3_gemv(const double* K0, int ldk, int nc, const double* c,
-                         double* c0, const CGScalars* sc, hipStream_t s) {
-  if (nc <= 0) return;
-  hipLaunchKernelGGL(k3c_gemv, dim3((nc + 7) / 8), dim3(256), 0, s, K0, ldk, nc, c,
-                     c0, sc);
+// c0 = K_0^+ c by the slab factors (sb: slab k spans the 64-column blocks
+// [sb[k], sb[k+1])): forward over the slabs into w, backward into y and
+// c0 = S y.
+void launch_coarse3_solve(const double* F, int ldk, const int* sb, int nslab,
+                          const double* sd, const double* c, double* w, double* y,
+                          double* c0, const CGScalars* sc, hipStream_t s) {
+  for (int k = 0; k < nslab; ++k) {
+    const int r0 = 64 * sb[k], r1 = 64 * sb[k + 1];
+    const int a0 = k > 0 ? 64 * sb[k - 1] : r0, a1 = k > 0 ? r0 : r0;
+    hipLaunchKernelGGL(k3c_slab_step, dim3((r1 - r0 + 7) / 8), dim3(256), 0, s, F, ldk,
+                       r0, r1, c, sd, a0, a1, w, 0, 0, (const double*)nullptr, w,
+                       (double*)nullptr, sc);
+  }
+  for (int k = nslab - 1; k >= 0; --k) {
+    const int r0 = 64 * sb[k], r1 = 64 * sb[k + 1];
+    const int b0 = r1, b1 = k + 1 < nslab ? 64 * sb[k + 2] : r1;
+    hipLaunchKernelGGL(k3c_slab_step, dim3((r1 - r0 + 7) / 8), dim3(256), 0, s, F, ldk,
+                       r0, r1, (const double*)nullptr, sd, r0, r1, w, b0, b1, y, y, c0,
+                       sc);
+  }
 }
 
 }  // namespace msp

@@ -135,15 +135,18 @@ void launch_coarse3_kphi(const Geom&, const Nbh3*, const int*, int, int, int, in
                          const double*, double*, hipStream_t);
 void launch_coarse3_k0(const Geom&, const Nbh3*, const int2*, int, int, int, int,
                        double, const uint8_t*, const double*, const double*,
-                       double*, int, hipStream_t);
+                       double*, int, int, hipStream_t);
 void launch_coarse3_export(const Geom&, const Nbh3*, const int*, int, int, int, int,
                            double, const uint8_t*, const double*, double*,
                            hipStream_t);
 void launch_coarse3_restrict(const Geom&, const Nbh3*, int, int, int, int, double,
                              const uint8_t*, const double*, const double*, double*,
                              const CGScalars*, hipStream_t);
-void launch_coarse3_gemv(const double*, int, int, const double*, double*,
-                         const CGScalars*, hipStream_t);
+void launch_coarse3_solve(const double*, int, const int*, int, const double*,
+                          const double*, double*, double*, double*, const CGScalars*,
+                          hipStream_t);
+void launch_k0_slab_factor(double*, int, const int*, int, const uint8_t*, double*,
+                           double*, double*, double*, double, int*, hipStream_t);
 void launch_cg3_resid(long long, const double*, const double*, const double*,
                       const uint8_t*, double*, CGScalars*, double*,
                       unsigned int*, int, hipStream_t);
@@ -342,6 +345,8 @@ struct msp_handle {
   int ndep3 = 0;                   // dependent rotation columns dropped from K_0
   uint8_t* d_drop3 = nullptr;      // per K_0 column: 1 = dropped as dependent
   size_t drop3_cap = 0;
+  std::vector<int> sb3;            // K_0 slab k: 64-column blocks [sb3[k], sb3[k+1])
+  double *d_w3 = nullptr, *d_y3 = nullptr;   // the slab solve's two sweeps
 };
 
 namespace {
@@ -629,7 +634,7 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
                   h->d_subs3, h->d_A3, h->d_A3f, h->d_LD3, h->d_Lp3, h->d_Rp3,
                   h->d_sd3, h->d_tk3, h->d_nb3, h->d_G3, h->d_X3, h->d_Y3,
                   h->d_T3, h->d_U3, h->d_est3, h->d_hsd3, h->d_hLD3, h->d_hLp3,
-                  h->d_hRp3, h->d_hel3, h->d_psi3, h->d_drop3};
+                  h->d_hRp3, h->d_hel3, h->d_psi3, h->d_drop3, h->d_w3, h->d_y3};
   for (void* p : bufs) dfree(p);
   for (int k = 0; k < KT_COUNT; ++k)
     for (hipEvent_t e : h->kt[k].ev) (void)hipEventDestroy(e);
@@ -1148,7 +1153,8 @@ static void prec_3d(msp_handle* h, const double* r, double* z,
     launch_coarse3_restrict(h->g, h->d_nb3, (int)h->nb3_h.size(), d.sub_nel[0],
                             d.sub_nel[1], d.sub_nel[2], h->invH, h->d_nmask,
                             h->d_psi3, r, h->d_c, sc, s);
-    launch_coarse3_gemv(h->d_K0, h->ldk, h->nc, h->d_c, h->d_c0, sc, s);
+    launch_coarse3_solve(h->d_K0, h->ldk, h->sb3.data(), (int)h->sb3.size() - 1,
+                         h->d_sdiag, h->d_c, h->d_w3, h->d_y3, h->d_c0, sc, s);
     timer_end(h, KT_RESTRICT, tr, s);
     cc.nb = h->d_nb3;
     cc.ncx = h->ncx3;
@@ -1338,6 +1344,27 @@ static msp_status setup_coarse3(msp_handle* h, hipStream_t s) {
     h->cap_hits += cap[l];
   }
   h->nc = col;
+  // K_0's columns grouped by slabs of coarse nodes with the same cx (K_0 is
+  // block tridiagonal in them: a coarse node's box meets only those of the
+  // slabs next to its own), each slab padded to whole 64-column blocks;
+  // slabs without columns are left out.
+  h->sb3.assign(1, 0);
+  {
+    int kc = 0;
+    for (int cx = 0; cx < h->ncx3; ++cx) {
+      const int k0 = kc;
+      for (int l = 0; l < nnb; ++l) {
+        Nbh3& w = h->nb3_h[l];
+        if (w.cx != cx) continue;
+        w.kcol0 = kc;
+        kc += 3 * w.nmodes + w.nrot;
+      }
+      if (kc > k0) {
+        kc = (kc + 63) / 64 * 64;
+        h->sb3.push_back(kc / 64);
+      }
+    }
+  }
   // Dependent rotation columns.  The rotation about axis a does not involve
   // the coordinate along a, and the hats of a plane of coarse nodes
   // perpendicular to a reproduce linear functions in the other two
@@ -1345,7 +1372,7 @@ static msp_status setup_coarse3(msp_handle* h, hipStream_t s) {
   // every node of the plane carries its rotations: one dependency per such
   // plane (they also imply the global identities).  The last node's
   // rotation about a in each such plane is dropped.
-  std::vector<uint8_t> drop(col > 0 ? col : 1, 0);
+  std::vector<uint8_t> drop((size_t)std::max(64, 64 * h->sb3.back()), 0);
   h->ndep3 = 0;
   if (rot) {
     const int nca[3] = {h->ncx3, h->ncy3, h->ncz3};
@@ -1362,13 +1389,13 @@ static msp_status setup_coarse3(msp_handle* h, hipStream_t s) {
         }
         if (all && last >= 0) {
           const Nbh3& w = h->nb3_h[last];
-          drop[w.col0 + 3 * w.nmodes + a] = 1;
+          drop[w.kcol0 + 3 * w.nmodes + a] = 1;
           ++h->ndep3;
         }
       }
   }
   h->dep_col = -1;
-  h->ldk = std::max(64, ((col + 63) / 64) * 64);
+  h->ldk = std::max(64, 64 * h->sb3.back());
   if (h->ldk > kMaxCoarse3)
     return fail(h, MSP_E_INVALID, "3D coarse dimension exceeds 32768 (reduce eig_kmax)");
   std::vector<int2> pairs;
@@ -1383,10 +1410,15 @@ static msp_status setup_coarse3(msp_handle* h, hipStream_t s) {
                              (size_t)std::max<long long>(woff, 1), h->ldk);
   if (st != MSP_OK) return st;
   if ((size_t)h->ldk > h->drop3_cap) {
-    dfree(h->d_drop3);
-    h->d_drop3 = nullptr;
+    void** bufs[] = {(void**)&h->d_drop3, (void**)&h->d_w3, (void**)&h->d_y3};
+    for (void** b : bufs) {
+      dfree(*b);
+      *b = nullptr;
+    }
     h->drop3_cap = 0;
     HIPCHK(h, dalloc(&h->d_drop3, (size_t)h->ldk));
+    HIPCHK(h, dalloc(&h->d_w3, (size_t)h->ldk));
+    HIPCHK(h, dalloc(&h->d_y3, (size_t)h->ldk));
     h->drop3_cap = (size_t)h->ldk;
   }
   if ((size_t)std::max<long long>(poff, 1) > h->psi3_cap) {
@@ -1407,11 +1439,12 @@ static msp_status setup_coarse3(msp_handle* h, hipStream_t s) {
                       h->d_elem, h->d_E, h->d_nmask, h->d_psi3, h->d_W, s);
   HIPCHK(h, hipMemsetAsync(h->d_K0, 0, (size_t)h->ldk * h->ldk * sizeof(double), s));
   launch_coarse3_k0(g, h->d_nb3, h->d_pairs, h->npairs, S0, S1, S2, h->invH, h->d_nmask,
-                    h->d_psi3, h->d_W, h->d_K0, h->ldk, s);
+                    h->d_psi3, h->d_W, h->d_K0, h->ldk, 0, s);
   HIPCHK(h, hipMemsetAsync(h->d_dropped, 0, sizeof(int), s));
   HIPCHK(h, hipMemcpyAsync(h->d_drop3, drop.data(), drop.size(), hipMemcpyHostToDevice, s));
-  launch_k0_pinv(h->d_K0, h->ldk, h->nc, -1, 0, h->d_drop3, h->d_sdiag, h->d_P,
-                 h->d_Lp, h->d_Rp, kPivotDrop, h->d_dropped, s);
+  launch_k0_slab_factor(h->d_K0, h->ldk, h->sb3.data(), (int)h->sb3.size() - 1,
+                        h->d_drop3, h->d_sdiag, h->d_P, h->d_Lp, h->d_Rp, kPivotDrop,
+                        h->d_dropped, s);
   HIPCHK(h, hipMemsetAsync(h->d_c, 0, (size_t)h->ldk * sizeof(double), s));
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipMemcpyAsync(h->h_int + 1, h->d_dropped, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -3044,14 +3077,17 @@ extern "C" msp_status msp_coarse_matrix(msp_handle* h, int32_t which,
   if (!h->setup_ok) return fail(h, MSP_E_STATE, "no setup");
   if (h->nc == 0) return fail(h, MSP_E_STATE, "the setup built no coarse space");
   const size_t bytes = (size_t)h->ldk * h->ldk * sizeof(double);
-  if (which == 1) {
-    HIPCHK(h, hipMemcpyAsync(out, h->d_K0, bytes, hipMemcpyDeviceToDevice, s));
-  } else if (h->dim == 3) {
+  if (h->dim == 3) {
+    if (which == 1)
+      return fail(h, MSP_E_INVALID, "dim = 3: K_0 is kept as slab factors, not as an explicit inverse");
     const msp_problem_desc& d = h->desc;
     HIPCHK(h, hipMemsetAsync(out, 0, bytes, s));
     launch_coarse3_k0(h->g, h->d_nb3, h->d_pairs, h->npairs, d.sub_nel[0], d.sub_nel[1],
-                      d.sub_nel[2], h->invH, h->d_nmask, h->d_psi3, h->d_W, out, h->ldk, s);
+                      d.sub_nel[2], h->invH, h->d_nmask, h->d_psi3, h->d_W, out, h->ldk,
+                      1, s);
     HIPCHK(h, hipGetLastError());
+  } else if (which == 1) {
+    HIPCHK(h, hipMemcpyAsync(out, h->d_K0, bytes, hipMemcpyDeviceToDevice, s));
   } else {
     // the setup's K Phi columns are still held; redo the block products
     HIPCHK(h, hipMemsetAsync(out, 0, bytes, s));

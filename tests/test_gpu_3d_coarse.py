@@ -211,3 +211,71 @@ def test_coarse3_cap_and_no_rotations():
     zref[h0.free] = h0.M.coarse(r[h0.free])
     assert_entrywise(z, zref, 1e-6, np.max(np.abs(zref)), "M_EH coarse correction")
     s.close()
+
+
+def test_config2_two_level_against_goldens():
+    """The 96 x 48 x 48 workload (698,691 DOFs, 1,377 coarse nodes, kmax 16)
+    against the oracle's values written by
+    tests/golden/make_cantilever3d_goldens.py: every neighbourhood's mode
+    count and eigenvalues, N_c, the pseudo-inverse's rank, the coarse
+    correction and M^{-1} r at 16,384 sampled DOFs, and the PCG run
+    (iterations within 10%, condition estimate within 5%, compliance 1e-6)
+    on the FP64 path; the FP32-local path to relres 1e-8 with at most 20%
+    more iterations."""
+    import json
+    import os
+    gdir = os.path.join(os.path.dirname(__file__), "golden")
+    with open(os.path.join(gdir, "cantilever3d_golden.json")) as fh:
+        gold = json.load(fh)
+    probe = np.load(os.path.join(gdir, "cantilever3d_probe.npz"))
+    p = inputs.config(2, precision=0)
+    msp = _msp()
+    H2 = dd.coarse_H(p.desc) ** 2
+    tau = p.desc["eig_tau"]
+    rho = _dev(p.rho)
+    f = _dev(p.f)
+    for prec in (0, 1):
+        print(f"[3d config2] precision {prec}", flush=True)
+        s = msp.Solver(dict(p.desc, precision=prec), p.fixed)
+        s.set_densities(rho)
+        s.setup()
+        ci = s.coarse_info()
+        assert ci["n_coarse"] == gold["n_coarse"]
+        assert ci["cap_hits"] * 3 == gold["cap_hits"]
+        compared = 0
+        for l, node in enumerate(gold["nodes"]):
+            lam = np.asarray(node["eigvals"])
+            near = list(lam * H2) + ([node["first_rejected"] * H2]
+                                     if node["first_rejected"] is not None else [])
+            if np.any(np.abs(np.asarray(near) - tau) < 0.01 * tau):
+                continue
+            assert ci["n_modes"][l] == node["n_modes"], (l, ci["n_modes"][l], node)
+            got = ci["eigvals"][l][: len(lam)]
+            assert np.allclose(got, lam, rtol=1e-6, atol=1e-12 / H2), (l, got, lam)
+            compared += 1
+        print(f"  {compared} of {len(gold['nodes'])} neighbourhoods compared", flush=True)
+        assert compared >= 0.9 * len(gold["nodes"])
+        r = _dev(inputs.probe_vector(p.fixed, gold["probe_seed"]))
+        idx = probe["idx"]
+        zc = _host(s.apply_coarse(r))[idx]
+        assert_entrywise(zc, probe["z_coarse"], 1e-6, gold["probe"]["coarse_zmax"],
+                         "config-2 coarse correction")
+        if prec == 0:
+            zp = _host(s.apply_prec(r))[idx]
+            assert_entrywise(zp, probe["z_prec"], 1e-6, gold["probe"]["prec_zmax"],
+                             "config-2 M^-1 r")
+        u, info = s.solve(f, rtol=1e-8, maxit=5000)
+        g = gold["pcg"]
+        print(f"  iters {info['iters']} (oracle {g['iters']}), cond {info['cond_est']:.5g} "
+              f"(oracle {g['cond']:.5g}), rank {info['coarse_rank']} (oracle "
+              f"{gold['coarse_rank']}), relres {info['relres_true']:.2e}", flush=True)
+        assert info["status"] == 0 and info["relres_true"] <= 1e-8
+        assert info["eig_unconverged"] == 0
+        assert info["coarse_rank"] == gold["coarse_rank"]
+        assert abs(info["compliance"] - g["compliance"]) <= 1e-6 * abs(g["compliance"])
+        if prec == 0:
+            assert abs(info["iters"] - g["iters"]) <= max(2, 0.1 * g["iters"])
+            assert abs(info["cond_est"] - g["cond"]) <= 0.05 * g["cond"]
+        else:
+            assert info["iters"] <= 1.2 * g["iters"] + 2
+        s.close()
