@@ -46,9 +46,11 @@ typedef enum {
  * heat eigenproblem and its automatic threshold; Section 4.2: rotations).
  *
  *  dim        2 (bilinear Q1, plane stress) or 3 (trilinear H8, isotropic;
- *             in 3D the preconditioner is the first level only: eig_kmax
- *             and rot_enrich must be 0 and sub_mode 0, and sub_nel,
- *             overlap and precision apply as in 2D)
+ *             in 3D sub_mode must be 0 and eig_random 0; eig_kmax = 0
+ *             gives the first level alone (the paper's one-level method),
+ *             eig_kmax in 1..24 the coarse space with three rotations per
+ *             coarse node (Section 4.2) when rot_enrich is set; a node
+ *             must then be clamped in all three components or in none)
  *  nel        elements per axis (nel[2] ignored in 2D)
  *  h          element edge length
  *  E0, Emin   SIMP moduli: E_e = Emin + rho_e^penal (E0 - Emin), 0<Emin<=E0
@@ -119,11 +121,12 @@ typedef struct msp_handle msp_handle;
  * bytes, 1 = that displacement DOF is clamped to zero (Gamma_D).  The mask
  * is copied.  In 2D the block row of a subdomain (2 * nodes per row) and
  * of a neighbourhood (nodes per row) must not exceed 72.  A 3D handle
- * supports every single-problem call with the first-level preconditioner
- * (Section 2 without the coarse term): a subdomain may hold at most 2,048
- * DOFs (7^3 nodes for S = 6 and one overlap layer); its geometry is
- * checked by the first msp_setup.  The coarse queries, batches and serving
- * return MSP_E_INVALID for a 3D handle; msp_apply_coarse gives z = 0.
+ * supports every single-problem call: a subdomain may hold at most 2,048
+ * DOFs (7^3 nodes for S = 6 and one overlap layer) and a neighbourhood's
+ * node plane (constant z) at most 256 nodes (S <= 7 in x and y); the
+ * geometry is checked by the first msp_setup.  Batches and serving return
+ * MSP_E_INVALID for a 3D handle; without a coarse space msp_apply_coarse
+ * gives z = 0.
  * Errors: MSP_E_INVALID (see the field ranges above), MSP_E_NOMEM.
  */
 msp_status msp_create(const msp_problem_desc* desc,
@@ -151,13 +154,21 @@ msp_status msp_set_densities(msp_handle* h, const double* rho_dev,
  * local pivot is not positive.  3D: the dense inverse of every K_i
  * (FP64, and an FP32 copy when precision = 1), held by the handle
  * (about 12 ld^2 bytes per subdomain, ld the largest local order rounded
- * up to 64); MSP_E_INVALID if the description asks for a coarse space or
- * the subdomains are too large or do not cover the free DOFs.
+ * up to 64); with eig_kmax > 0 the heat pencils of all coarse
+ * neighbourhoods factored by node planes (8 ldp^2 bytes a plane, ldp the
+ * largest plane rounded up to 64) and solved by subspace iteration, and
+ * K_0 held as block LDL^T factors by slabs of coarse nodes (columns
+ * that are linearly dependent by construction, one rotation per plane of
+ * coarse nodes that all carry rotations, are dropped).  MSP_E_INVALID if
+ * the subdomains or planes are too large, the subdomains do not cover the
+ * free DOFs, a node is clamped in only some components, or N_c exceeds
+ * 32,768.
  */
 msp_status msp_setup(msp_handle* h, hipStream_t stream);
 
 /*
- * Solve K_FF u = f by PCG with M_EH+Rot (M_EH; in 3D the first level) to
+ * Solve K_FF u = f by PCG with M_EH+Rot (M_EH; the first level alone when
+ * eig_kmax = 0 in 3D) to
  * ||f - K u|| <= rtol ||f|| over the free DOFs (Section 2; Section 5 for the stopping
  * test and the Lanczos estimate).  f_dev and u_dev hold nrhs right-hand
  * sides of n doubles each, one after another; with warm != 0 u_dev holds
@@ -227,9 +238,10 @@ msp_status msp_coarse_basis(msp_handle* h, double* phi_dev, hipStream_t stream);
  * ldk = msp_query()[11]; row-major with leading dimension ldk, entries
  * beyond N_c are padding): which = 0 the assembled K_0 = R_0 K R_0^T of the
  * last setup (Section 2; recomputed from the stored K R_0^T columns),
- * which = 1 the generalised inverse K_0^+ that the coarse solve applies.
- * For checks of the coarse solve.  Errors: MSP_E_INVALID, MSP_E_STATE (no
- * setup), MSP_E_DEVICE. */
+ * which = 1 the generalised inverse K_0^+ that the coarse solve applies
+ * (2D only: a 3D handle keeps K_0 as slab factors and returns
+ * MSP_E_INVALID).  For checks of the coarse solve.  Errors: MSP_E_INVALID,
+ * MSP_E_STATE (no setup, or no coarse space), MSP_E_DEVICE. */
 msp_status msp_coarse_matrix(msp_handle* h, int32_t which, double* out_dev,
                              hipStream_t stream);
 

@@ -2443,7 +2443,7 @@ extern "C" msp_status msp_batch_solve(msp_batch* b, msp_handle* const* hs_in,
   std::vector<msp_handle*> hs(hs_in, hs_in + n);
   for (int e = 0; e < n; ++e) {
     if (!hs[e] || !f[e] || !u[e]) return bfail(b, MSP_E_INVALID, "null handle or vector in the batch");
-    if (hs[e]->dim != 2) return bfail(b, MSP_E_INVALID, "dim = 3: only the stiffness product is built for 3D meshes");
+    if (hs[e]->dim != 2) return bfail(b, MSP_E_INVALID, "dim = 3: batches take 2D problems only");
     if (hs[e]->mv_ty > 16)
       return bfail(b, MSP_E_INVALID, "mesh too large for the batched stiffness product (tile height 32)");
     for (int k = 0; k < e; ++k)
@@ -2692,7 +2692,7 @@ extern "C" msp_status msp_server_add_run(msp_server* sv, const msp_problem_desc*
   if (!sv || !d || !fixed_mask_host || !run_id)
     return sfail(sv, MSP_E_INVALID, "null argument");
   if (d->dim != 2)
-    return sfail(sv, MSP_E_INVALID, "runs must be 2D: the solve is built for 2D meshes");
+    return sfail(sv, MSP_E_INVALID, "runs must be 2D: serving batches 2D problems only");
   // validate by building the geometry once (no device memory is kept)
   msp_handle* probe = nullptr;
   msp_status st = msp_create(d, fixed_mask_host, &probe);
