@@ -76,6 +76,15 @@ typedef enum {
  *             their local solutions with A + 0.05/H^2 M and the constant
  *             function, by Rayleigh-Ritz on that space
  *  eig_seed   seed of the randomized forcings (SplitMix64, counter-based)
+ *  coarse_kind 0: the heat coarse space (M_EH, M_EH+Rot; Section 4);
+ *             1: M_EE (Section 2.1, 2D only): per coarse neighbourhood the
+ *                lowest eigenpairs of the local elasticity pencil
+ *                -div sigma(psi) = lambda E psi times chi_l, 3 per
+ *                high-stiffness region of the neighbourhood (the regions
+ *                counted by the heat threshold; at most 24 modes a
+ *                neighbourhood); 2: M_EE with twice as many modes.
+ *                M_EE keeps its coarse operator dense (n x N_c), for the
+ *                paper's small examples; batches and serving refuse it.
  */
 typedef struct {
   int32_t dim;
@@ -90,6 +99,7 @@ typedef struct {
   int32_t precision;
   int32_t eig_random;
   uint32_t eig_seed;
+  int32_t coarse_kind;
 } msp_problem_desc;
 
 typedef struct {

@@ -44,7 +44,8 @@ __all__ = [
 
 def problem_desc(dim, nel, *, sub_nel, overlap, h=1.0, E0=1.0, Emin=1e-6,
                  nu=0.3, penal=3.0, sub_mode=0, eig_tau=2.0, eig_kmax=6,
-                 rot_enrich=1, precision=0, eig_random=0, eig_seed=0):
+                 rot_enrich=1, precision=0, eig_random=0, eig_seed=0,
+                 coarse_kind=0):
     """Return a plain dict describing a problem.
 
     ``sub_nel`` is the coarse block edge S in elements, ``overlap`` the number
@@ -55,6 +56,8 @@ def problem_desc(dim, nel, *, sub_nel, overlap, h=1.0, E0=1.0, Emin=1e-6,
     0 = FP64 local solves, 1 = FP32 local solves inside the FP64 outer CG.
     ``eig_random`` > 0 approximates the heat eigenpairs by the randomized
     method from that many snapshots (M_EH+Rot;Rand), drawn with ``eig_seed``.
+    ``coarse_kind`` 0 = heat coarse space, 1 = M_EE (elasticity pencils),
+    2 = M_EE with twice as many modes.
     """
     nel = tuple(int(v) for v in nel)
     sub = (sub_nel,) * dim if np.isscalar(sub_nel) else tuple(int(v) for v in sub_nel)
@@ -65,7 +68,8 @@ def problem_desc(dim, nel, *, sub_nel, overlap, h=1.0, E0=1.0, Emin=1e-6,
                 sub_nel=sub, overlap=int(overlap), sub_mode=int(sub_mode),
                 eig_tau=float(eig_tau), eig_kmax=int(eig_kmax),
                 rot_enrich=int(rot_enrich), precision=int(precision),
-                eig_random=int(eig_random), eig_seed=int(eig_seed))
+                eig_random=int(eig_random), eig_seed=int(eig_seed),
+                coarse_kind=int(coarse_kind))
 
 
 def n_nodes(desc):

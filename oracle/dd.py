@@ -34,7 +34,8 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .fem import assemble_scalar, assemble_stiffness, heat_element, simp_modulus
+from .fem import (assemble_scalar, assemble_stiffness, elasticity_element,
+                  heat_element, simp_modulus)
 
 # omega with at most this many nodes is solved with a dense LAPACK eigh
 DENSE_EIG_MAX = 1600
@@ -420,6 +421,138 @@ def build_coarse_basis(desc, E, fixed, rot=None):
 
 
 # --------------------------------------------------------------------------
+# M_EE: the coarse space of local elasticity eigenproblems (Section 2.1)
+# --------------------------------------------------------------------------
+
+def elasticity_pencil(desc, E, c, fixed):
+    """(K_l, M_l, DOF ids) of the elasticity pencil on omega_l (Section 2.1:
+    -div sigma(psi) = lambda E psi, homogeneous Neumann on the boundary of
+    omega_l, Dirichlet on its clamped part).
+
+    K_l = sum_e E_e K^_e and M_l = sum_e E_e (M^_e on every displacement
+    component) over the elements of omega_l; clamped DOFs are removed.
+    Returned DOF ids are global (dim * node + component), in omega's
+    x-fastest node order.
+    """
+    dim = desc["dim"]
+    nel = desc["nel"]
+    ebox, nbox = neighbourhood(desc, c)
+    Ke = elasticity_element(dim, desc["nu"], desc["h"])
+    _, Ms = heat_element(dim, desc["h"])
+    nv = 2 ** dim
+    Me = np.zeros((dim * nv, dim * nv))
+    for comp in range(dim):
+        Me[comp::dim, comp::dim] = Ms
+    node_ids, _ = _node_ids_of_box(desc, nbox)
+    shape = [hi - lo + 1 for lo, hi in nbox]
+    eaxes = [np.arange(lo, hi) for lo, hi in ebox]
+    g = np.meshgrid(*eaxes, indexing="ij")
+    ecoord = [np.ascontiguousarray(a.transpose()).ravel() for a in g]
+    estride = [1]
+    for d in range(dim - 1):
+        estride.append(estride[-1] * nel[d])
+    eid = sum(ecoord[d] * estride[d] for d in range(dim))
+    lstride = [1]
+    for d in range(dim - 1):
+        lstride.append(lstride[-1] * shape[d])
+    lbase = sum((ecoord[d] - nbox[d][0]) * lstride[d] for d in range(dim))
+    loc = np.empty((len(eid), dim * nv), dtype=np.int64)
+    for a in range(nv):
+        ln = lbase + sum(((a >> d) & 1) * lstride[d] for d in range(dim))
+        for comp in range(dim):
+            loc[:, dim * a + comp] = dim * ln + comp
+    kappa = np.asarray(E)[eid]
+    n = dim * len(node_ids)
+    K = assemble_scalar(loc, kappa, Ke, n)
+    M = assemble_scalar(loc, kappa, Me, n)
+    dofs = (dim * node_ids[:, None] + np.arange(dim)[None, :]).ravel()
+    idx = np.nonzero(np.asarray(fixed)[dofs] == 0)[0]
+    return K[idx][:, idx].tocsc(), M[idx][:, idx].tocsc(), dofs[idx]
+
+
+def elasticity_modes(K, M, count, H):
+    """The ``count`` lowest eigenpairs of K psi = lambda M psi, ascending,
+    M-orthonormal (LAPACK for small pencils, ARPACK shift-invert about a
+    point just below zero otherwise); also returns the next eigenvalue."""
+    n = K.shape[0]
+    if count == 0 or n == 0:
+        return np.zeros(0), np.zeros((n, 0)), np.zeros(0)
+    if n <= DENSE_EIG_MAX:
+        lam, vec = sla.eigh(K.toarray(), M.toarray())
+    else:
+        k = min(count + 1, n - 1)
+        rng = np.random.default_rng(12345)
+        lam, vec = spla.eigsh(K, k=k, M=M, sigma=-1e-3 / (H * H), which="LM", tol=0.0,
+                              v0=rng.standard_normal(n), maxiter=100000)
+        order = np.argsort(lam)
+        lam, vec = lam[order], vec[:, order]
+    sel = min(count, n)
+    v = vec[:, :sel]
+    G = v.T @ (M @ v)
+    L = np.linalg.cholesky(0.5 * (G + G.T))
+    v = np.linalg.solve(L, v.T).T
+    return lam[:sel], v, lam[: sel + 1]
+
+
+def build_coarse_basis_ee(desc, E, fixed):
+    """R_0^T of M_EE (Section 2.1): per coarse node the lowest eigenpairs of
+    the elasticity pencil on omega_l times chi_l.
+
+    Reading of the mode count: the paper selects, by hand, the rigid-body
+    modes of each disconnected high-stiffness region of omega_l (d(d+1)/2
+    per region); the number of such regions is what the heat threshold of
+    Section 4.1 counts on the same neighbourhood, so n_l = d(d+1)/2 times
+    the heat modes selected there (desc["coarse_kind"] = 2: twice that, the
+    "twice many eigenvectors" rows of the tables).  Column order: coarse
+    nodes x-fastest, per node its modes in ascending eigenvalue order.
+    """
+    dim = desc["dim"]
+    H = coarse_H(desc)
+    tau, kmax = desc["eig_tau"], desc["eig_kmax"]
+    mult = 2 if desc.get("coarse_kind", 1) == 2 else 1
+    per_region = dim * (dim + 1) // 2
+    n = len(fixed)
+    fixed = np.asarray(fixed)
+    nodes = coarse_node_grid(desc)
+    rows, cols, vals = [], [], []
+    n_modes = np.zeros((len(nodes), dim), dtype=np.int64)
+    eigvals, seen = [], []
+    cap_hits = 0
+    col = 0
+    for li, c in enumerate(nodes):
+        _, nbox = neighbourhood(desc, c)
+        node_ids, flat = _node_ids_of_box(desc, nbox)
+        chi = partition_of_unity(desc, c, flat)
+        dn = node_ids[fixed[dim * node_ids] == 1]
+        A, Mh, _ = heat_pencil(desc, E, c, dn)
+        hm = heat_modes(A, Mh, tau, H, kmax)
+        cap_hits += int(hm.cap_hit)
+        count = mult * per_region * len(hm.lam)
+        K, M, dofs = elasticity_pencil(desc, E, c, fixed)
+        lam, vec, lam_seen = elasticity_modes(K, M, count, H)
+        n_modes[li, :] = len(lam)
+        eigvals.append([lam] * dim)
+        seen.append([lam_seen] * dim)
+        pos = {int(g): i for i, g in enumerate(node_ids)}
+        chi_d = chi[np.array([pos[int(d) // dim] for d in dofs], dtype=np.int64)]
+        for j in range(vec.shape[1]):
+            v = chi_d * vec[:, j]
+            nz = v != 0.0
+            rows.append(dofs[nz])
+            cols.append(np.full(int(nz.sum()), col))
+            vals.append(v[nz])
+            col += 1
+    if col:
+        Phi = sp.csc_matrix((np.concatenate(vals),
+                             (np.concatenate(rows), np.concatenate(cols))),
+                            shape=(n, col))
+    else:
+        Phi = sp.csc_matrix((n, 0))
+    return CoarseSpace(Phi, n_modes, np.zeros(len(nodes), np.int64), eigvals, seen,
+                       cap_hits, nodes)
+
+
+# --------------------------------------------------------------------------
 # the preconditioner
 # --------------------------------------------------------------------------
 
@@ -536,7 +669,8 @@ def subdomain_free_indices(desc, fixed, boxes):
 
 
 def build_preconditioner(desc, rho, fixed, level="both", rot=None):
-    """Assemble K(rho) and build M_EH+Rot (rot=1) or M_EH (rot=0)."""
+    """Assemble K(rho) and build M_EH+Rot (rot=1) or M_EH (rot=0), or M_EE
+    when desc["coarse_kind"] is 1 or 2."""
     fixed = np.asarray(fixed, dtype=np.uint8)
     E = simp_modulus(rho, desc["E0"], desc["Emin"], desc["penal"])
     K = assemble_stiffness(desc, E)
@@ -544,7 +678,9 @@ def build_preconditioner(desc, rho, fixed, level="both", rot=None):
     K_FF = K[free][:, free].tocsr()
     boxes = subdomain_node_boxes(desc, fixed)
     sub_idx = subdomain_free_indices(desc, fixed, boxes)
-    if level in ("both", "coarse"):
+    if level in ("both", "coarse") and desc.get("coarse_kind", 0) in (1, 2):
+        cs = build_coarse_basis_ee(desc, E, fixed)
+    elif level in ("both", "coarse"):
         cs = build_coarse_basis(desc, E, fixed, rot)
     else:
         cs = CoarseSpace(sp.csc_matrix((len(fixed), 0)),

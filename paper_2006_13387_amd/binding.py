@@ -35,7 +35,8 @@ class ProblemDesc(ctypes.Structure):
                 ("overlap", ctypes.c_int32), ("sub_mode", ctypes.c_int32),
                 ("eig_tau", ctypes.c_double), ("eig_kmax", ctypes.c_int32),
                 ("rot_enrich", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("eig_random", ctypes.c_int32), ("eig_seed", ctypes.c_uint32)]
+                ("eig_random", ctypes.c_int32), ("eig_seed", ctypes.c_uint32),
+                ("coarse_kind", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -172,6 +173,7 @@ def make_desc(d):
     pd.rot_enrich, pd.precision = d["rot_enrich"], d["precision"]
     pd.eig_random = d.get("eig_random", 0)
     pd.eig_seed = d.get("eig_seed", 0)
+    pd.coarse_kind = d.get("coarse_kind", 0)
     return pd
 
 

@@ -21,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmsp.so")
 
 SOURCES = ["k_vec.hip", "k_local.hip", "k_coarse.hip", "k_topo.hip", "k_3d.hip",
-           "k_coarse3d.hip",
+           "k_coarse3d.hip", "k_ee2d.hip",
            "noalloc.hip", "runtime.cpp", "elements.cpp"]
 
 ARCH = os.environ.get("MSP_OFFLOAD_ARCH", "gfx950")

@@ -240,6 +240,7 @@ struct CombineCall {
   CGScalars* sc;
   double* part;
   int flex;                  // flexible CG: also the partials of z.q
+  const double* zadd;        // added to z at free DOFs when set (M_EE's coarse part)
 };
 
 // Problem of workgroup b in a batched launch: the last e with start[e] <= b

@@ -938,6 +938,11 @@ __device__ __forceinline__ void combine_body(const CombineCall& a, int bid,
     z0 += t0;
     z1 += t1;
   }
+  if (act && a.zadd != nullptr) {
+    const double2 za = reinterpret_cast<const double2*>(a.zadd)[node];
+    z0 += za.x;
+    z1 += za.y;
+  }
   if (mk.x) z0 = 0.0;
   if (mk.y) z1 = 0.0;
   if (act) reinterpret_cast<double2*>(a.z)[node] = make_double2(z0, z1);

@@ -29,6 +29,7 @@
 #include "common.h"
 #include "dev.h"
 #include "small_dense.h"
+#include "plane_eig.h"
 
 namespace msp {
 
@@ -37,14 +38,6 @@ constexpr int C3_MAXP = 256;   // largest padded plane order
 constexpr int HS_NT = 512;     // sweep, Gram and Rayleigh-Ritz workgroups
 constexpr int SC_CB = 16;      // columns of a Schur-complement workgroup
 constexpr int C3_MAXCOL = 3 * 24 + 3;   // columns of one coarse node (kmax <= 24)
-
-// Per-neighbourhood state of the subspace iteration (device memory).
-struct Eig3State {
-  int done, conv;
-  double theta[MAXM], theta_old[MAXM];
-  double GA[MAXM * MAXM], GM[MAXM * MAXM];
-  double V[MAXM * MAXM];      // Ritz coefficients, columns in ascending order
-};
 
 size_t eig3_state_bytes() { return sizeof(Eig3State); }
 
@@ -489,11 +482,12 @@ k3h_gram(const Nbh3* __restrict__ nbs, int ldp, const double* __restrict__ Yw,
 // of C = L^{-1} GA L^{-T} give the Ritz values and the coefficients
 // V = L^{-T} Q (columns in ascending order, M-orthonormal Ritz vectors
 // Y V).  Convergence test as in the 2D iteration: the Ritz values below
-// the threshold (at most kmax) and the next one change by less than tol
-// (relative) since the previous step; conv counts the consecutive steps
-// that passed it.  One workgroup per neighbourhood.
+// the threshold lim (at most kmax) and the next one change by less than
+// tol relative to |theta| + scale (scale = lim for the heat pencils)
+// since the previous step; conv counts the consecutive steps that passed
+// it.  One workgroup per neighbourhood.
 __global__ void __launch_bounds__(HS_NT)
-k3h_rr(int m, int kmax, double lim, double tol, int first,
+k3h_rr(int m, int kmax, double lim, double scale, double tol, int first,
        Eig3State* __restrict__ st, int* __restrict__ err) {
   __shared__ double GA[MAXM * MAXM], L[MAXM * MAXM], W[MAXM * MAXM], Q[MAXM * MAXM];
   __shared__ double rc[MAXM], rs[MAXM];
@@ -562,7 +556,7 @@ k3h_rr(int m, int kmax, double lim, double tol, int first,
     const int nchk = min(m - 1, min(nbelow, kmax) + 1);
     double dmax = 0.0;
     for (int i = 0; i < nchk; ++i)
-      dmax = fmax(dmax, fabs(es.theta[i] - es.theta_old[i]) / (fabs(es.theta[i]) + lim));
+      dmax = fmax(dmax, fabs(es.theta[i] - es.theta_old[i]) / (fabs(es.theta[i]) + scale));
     for (int i = 0; i < m; ++i) es.theta_old[i] = es.theta[i];
     es.conv = (!first && dmax < tol) ? es.conv + 1 : 0;
   }
@@ -1018,8 +1012,8 @@ static void heat3_step_m(const Geom& g, const Nbh3* nbs, int nnb, int pmax, int 
   hipLaunchKernelGGL((k3h_stencil<M, true>), dim3(pmax, nnb), dim3(C3_NT), 0, s, g,
                      nbs, ldp, E, nmask, hel, Y, T, U, st);
   hipLaunchKernelGGL((k3h_gram<M>), dim3(nnb), dim3(HS_NT), 0, s, nbs, ldp, Y, T, U, st);
-  hipLaunchKernelGGL(k3h_rr, dim3(nnb), dim3(HS_NT), 0, s, M, kmax, lim, tol, first,
-                     st, err);
+  hipLaunchKernelGGL(k3h_rr, dim3(nnb), dim3(HS_NT), 0, s, M, kmax, lim, lim, tol,
+                     first, st, err);
   hipLaunchKernelGGL((k3h_ritz<M>), dim3(pmax, nnb), dim3(C3_NT), 0, s, nbs, ldp, Y,
                      X, st);
 }
@@ -1036,6 +1030,68 @@ void launch_heat3_step(int m, const Geom& g, const Nbh3* nbs, int nnb, int pmax,
     case 24: heat3_step_m<24>(g, nbs, nnb, pmax, ldp, E, nmask, hel, sigma, G, X, Y, T, U, es, kmax, lim, tol, first, err, s); break;
     default: heat3_step_m<32>(g, nbs, nnb, pmax, ldp, E, nmask, hel, sigma, G, X, Y, T, U, es, kmax, lim, tol, first, err, s); break;
   }
+}
+
+// The Rayleigh-Ritz part of a sweep on row-blocked pencils of any kind:
+// Gram matrices of Y with A Y (in T) and M Y (in U), the small
+// eigenproblem, X = Y V.
+template <int M>
+static void plane_rr_m(const Nbh3* nbs, int nnb, int pmax, int ldp, const double* Y,
+                       const double* T, const double* U, double* X, Eig3State* st,
+                       int kmax, double lim, double scale, double tol, int first,
+                       int* err, hipStream_t s) {
+  hipLaunchKernelGGL((k3h_gram<M>), dim3(nnb), dim3(HS_NT), 0, s, nbs, ldp, Y, T, U, st);
+  hipLaunchKernelGGL(k3h_rr, dim3(nnb), dim3(HS_NT), 0, s, M, kmax, lim, scale, tol,
+                     first, st, err);
+  hipLaunchKernelGGL((k3h_ritz<M>), dim3(pmax, nnb), dim3(C3_NT), 0, s, nbs, ldp, Y,
+                     X, st);
+}
+
+void launch_plane_rr(int m, const Nbh3* nbs, int nnb, int pmax, int ldp, const double* Y,
+                     const double* T, const double* U, double* X, void* st, int kmax,
+                     double lim, double scale, double tol, int first, int* err,
+                     hipStream_t s) {
+  Eig3State* es = (Eig3State*)st;
+  switch (m) {
+    case 8: plane_rr_m<8>(nbs, nnb, pmax, ldp, Y, T, U, X, es, kmax, lim, scale, tol, first, err, s); break;
+    case 16: plane_rr_m<16>(nbs, nnb, pmax, ldp, Y, T, U, X, es, kmax, lim, scale, tol, first, err, s); break;
+    case 24: plane_rr_m<24>(nbs, nnb, pmax, ldp, Y, T, U, X, es, kmax, lim, scale, tol, first, err, s); break;
+    default: plane_rr_m<32>(nbs, nnb, pmax, ldp, Y, T, U, X, es, kmax, lim, scale, tol, first, err, s); break;
+  }
+}
+
+// State reset for a new subspace iteration (the start block is the
+// caller's).
+__global__ void k3h_reset(Eig3State* __restrict__ st, int n) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= n) return;
+  st[l].done = 0;
+  st[l].conv = 0;
+  for (int i = 0; i < MAXM; ++i) st[l].theta_old[i] = 0.0;
+}
+
+void launch_plane_reset(void* st, int nnb, hipStream_t s) {
+  hipLaunchKernelGGL(k3h_reset, dim3((nnb + 127) / 128), dim3(128), 0, s,
+                     (Eig3State*)st, nnb);
+}
+
+// Selection by count: want[l] lowest Ritz values (at most m), their
+// values into lam (kmax_out per neighbourhood, NaN past the count).
+__global__ void k3h_select_count(const Eig3State* __restrict__ st, int n, int m,
+                                 const int* __restrict__ want, int kmax_out,
+                                 int* __restrict__ nsel, double* __restrict__ lam) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= n) return;
+  const int ns = min(want[l], m);
+  nsel[l] = ns;
+  for (int i = 0; i < kmax_out; ++i)
+    lam[(long long)l * kmax_out + i] = i < ns ? st[l].theta[i] : __builtin_nan("");
+}
+
+void launch_plane_select_count(const void* st, int nnb, int m, const int* want,
+                               int kmax_out, int* nsel, double* lam, hipStream_t s) {
+  hipLaunchKernelGGL(k3h_select_count, dim3((nnb + 127) / 128), dim3(128), 0, s,
+                     (const Eig3State*)st, nnb, m, want, kmax_out, nsel, lam);
 }
 
 void launch_heat3_count(void* st, int nnb, int need, int* count, hipStream_t s) {

@@ -142,6 +142,31 @@ void launch_coarse3_export(const Geom&, const Nbh3*, const int*, int, int, int, 
 void launch_coarse3_restrict(const Geom&, const Nbh3*, int, int, int, int, double,
                              const uint8_t*, const double*, const double*, double*,
                              const CGScalars*, hipStream_t);
+void launch_plane_rr(int, const Nbh3*, int, int, int, const double*, const double*,
+                     const double*, double*, void*, int, double, double, double, int,
+                     int*, hipStream_t);
+void launch_plane_reset(void*, int, hipStream_t);
+void launch_plane_select_count(const void*, int, int, const int*, int, int*, double*,
+                               hipStream_t);
+// k_ee2d.hip
+int ee2_max_row();
+void launch_ee2_factor(const Geom&, const Nbh3*, int, int, int, const double*,
+                       const uint8_t*, const double*, const double*, double, double*,
+                       double*, double*, double*, double*, int*, hipStream_t);
+void launch_ee2_start(const Geom&, const Nbh3*, int, int, int, int, const uint8_t*,
+                      double*, hipStream_t);
+void launch_ee2_products(int, const Geom&, const Nbh3*, int, int, int, const double*,
+                         const uint8_t*, const double*, const double*, double,
+                         const double*, const double*, double*, double*, double*,
+                         const void*, hipStream_t);
+void launch_ee2_basis(const Geom&, const Nbh3*, const int*, int, const uint8_t*,
+                      const double*, double*, hipStream_t);
+void launch_ee2_k0(const double*, const double*, long long, int, double*, int,
+                   hipStream_t);
+void launch_ee2_restrict(const double*, long long, int, const double*, double*,
+                         const CGScalars*, hipStream_t);
+void launch_ee2_prolong(const double*, long long, int, const double*, double*,
+                        const CGScalars*, hipStream_t);
 void launch_coarse3_solve(const double*, int, const int*, int, const double*,
                           const double*, double*, double*, double*, const CGScalars*,
                           hipStream_t);
@@ -179,6 +204,10 @@ constexpr int kEigExtra = 8;         // subspace block m = kmax + kEigExtra
 constexpr int kEigMaxIt = 48;
 constexpr int kEig3MaxIt = 40;       // 3D: sweeps, each with Rayleigh-Ritz
 constexpr int kEig3Passes = 3;       // 3D: consecutive converged steps to stop
+// M_EE: its counts can cut the spectrum where the next eigenvalue is only
+// some tens of percent above the last one kept, so the vectors converge
+// slower than the values; the values are held to a tighter change
+constexpr double kEigTolEE = 1e-12;
 constexpr int kMaxCoarse3 = 32768;   // largest padded 3D K_0 order
 constexpr int kEigRR = 3;
 constexpr double kEigTol = 1e-8;
@@ -347,6 +376,26 @@ struct msp_handle {
   size_t drop3_cap = 0;
   std::vector<int> sb3;            // K_0 slab k: 64-column blocks [sb3[k], sb3[k+1])
   double *d_w3 = nullptr, *d_y3 = nullptr;   // the slab solve's two sweeps
+  // M_EE (2D, coarse_kind 1 or 2): the coarse neighbourhoods as row-blocked
+  // elasticity pencils (rows of 2 nxw unknowns padded to ldpe), their
+  // factors, subspace blocks and state; the modes, the dense basis Phi and
+  // K Phi (n x N_c, column-major) and the prolongation's output
+  bool ee = false;
+  std::vector<Nbh3> nbe_h;
+  Nbh3* d_nbe = nullptr;
+  int pmaxe = 0, ldpe = 0;
+  double *d_Ge = nullptr, *d_Xe = nullptr, *d_Ye = nullptr, *d_Te = nullptr,
+         *d_Ue = nullptr;
+  void* d_este = nullptr;
+  double *d_hsde = nullptr, *d_hLDe = nullptr, *d_hLpe = nullptr, *d_hRpe = nullptr;
+  int *d_wante = nullptr, *d_nsele = nullptr;
+  double* d_lame = nullptr;
+  double* d_psie = nullptr;
+  size_t psie_cap = 0;
+  double *d_Phi = nullptr, *d_KPhi = nullptr, *d_zadd = nullptr;
+  size_t phi_cap = 0;
+  std::vector<int> ee_nsel_h;
+  std::vector<double> ee_lam_h;
 };
 
 namespace {
@@ -634,7 +683,10 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
                   h->d_subs3, h->d_A3, h->d_A3f, h->d_LD3, h->d_Lp3, h->d_Rp3,
                   h->d_sd3, h->d_tk3, h->d_nb3, h->d_G3, h->d_X3, h->d_Y3,
                   h->d_T3, h->d_U3, h->d_est3, h->d_hsd3, h->d_hLD3, h->d_hLp3,
-                  h->d_hRp3, h->d_hel3, h->d_psi3, h->d_drop3, h->d_w3, h->d_y3};
+                  h->d_hRp3, h->d_hel3, h->d_psi3, h->d_drop3, h->d_w3, h->d_y3,
+                  h->d_nbe, h->d_Ge, h->d_Xe, h->d_Ye, h->d_Te, h->d_Ue, h->d_este,
+                  h->d_hsde, h->d_hLDe, h->d_hLpe, h->d_hRpe, h->d_wante, h->d_nsele,
+                  h->d_lame, h->d_psie, h->d_Phi, h->d_KPhi, h->d_zadd};
   for (void* p : bufs) dfree(p);
   for (int k = 0; k < KT_COUNT; ++k)
     for (hipEvent_t e : h->kt[k].ev) (void)hipEventDestroy(e);
@@ -658,6 +710,8 @@ static msp_status create_3d(const msp_problem_desc* d, const uint8_t* fixed,
     return fail(nullptr, MSP_E_INVALID, "nu must lie in (-1, 0.5)");
   if (!(d->penal >= 1.0)) return fail(nullptr, MSP_E_INVALID, "penal must be >= 1");
   if (!(d->h > 0.0)) return fail(nullptr, MSP_E_INVALID, "h must be positive");
+  if (d->coarse_kind != 0)
+    return fail(nullptr, MSP_E_INVALID, "dim = 3: only the heat coarse space (coarse_kind 0)");
   const long long nn = (long long)(d->nel[0] + 1) * (d->nel[1] + 1) * (d->nel[2] + 1);
   if (nn > (1LL << 31) / 3)
     return fail(nullptr, MSP_E_INVALID, "3D mesh too large");
@@ -757,9 +811,14 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
     return fail(nullptr, MSP_E_INVALID, "sub_mode must be 0 or 1");
   if (d->precision != 0 && d->precision != 1)
     return fail(nullptr, MSP_E_INVALID, "precision must be 0 or 1");
+  if (d->coarse_kind < 0 || d->coarse_kind > 2)
+    return fail(nullptr, MSP_E_INVALID, "coarse_kind must be 0, 1 or 2");
+  if (d->coarse_kind != 0 && d->eig_random != 0)
+    return fail(nullptr, MSP_E_INVALID, "M_EE takes the exact eigenpairs (eig_random = 0)");
 
   msp_handle* h = new msp_handle();
   h->desc = *d;
+  h->ee = d->coarse_kind != 0;
   Geom& g = h->g;
   g.nx = d->nel[0];
   g.ny = d->nel[1];
@@ -1515,6 +1574,188 @@ static msp_status setup_3d(msp_handle* h, hipStream_t s) {
   return MSP_OK;
 }
 
+// M_EE (Section 2.1) from this setup's heat counts: per coarse node 3 (6
+// for coarse_kind 2) elasticity modes for each mode the heat threshold
+// selected on the same neighbourhood, by shift-invert subspace iteration on
+// the row-blocked pencils; then the dense basis, K Phi, K_0 and its
+// generalised inverse.
+static msp_status setup_ee(msp_handle* h, const std::vector<int>& cap, hipStream_t s) {
+  const Geom& g = h->g;
+  const msp_problem_desc& d = h->desc;
+  const int ncn = (int)h->cn_h.size();
+  const int mult = d.coarse_kind == 2 ? 2 : 1;
+  std::vector<int> want(ncn);
+  int maxw = 0;
+  h->cap_hits = 0;
+  for (int l = 0; l < ncn; ++l) {
+    want[l] = 3 * mult * h->nsel_h[h->cn_h[l].sys];
+    maxw = std::max(maxw, want[l]);
+    h->cap_hits += cap[h->cn_h[l].sys];
+  }
+  if (maxw > 24)
+    return fail(h, MSP_E_INVALID, "M_EE: more than 24 modes in a neighbourhood (reduce eig_kmax)");
+  const int m = std::max(8, ((maxw + 8 + 7) / 8) * 8);
+  if (h->d_nbe == nullptr) {
+    h->nbe_h.assign(ncn, Nbh3{});
+    int pmax = 0, maxnp = 0;
+    for (int l = 0; l < ncn; ++l) {
+      const CoarseNode& c = h->cn_h[l];
+      Nbh3& w = h->nbe_h[l];
+      w.cx = c.cx;
+      w.cy = c.cy;
+      w.x0 = c.x0;
+      w.y0 = c.y0;
+      w.nbx = c.nxw;
+      w.nby = 1;
+      w.nbz = c.nyw;
+      w.np = 2 * c.nxw;
+      pmax = std::max(pmax, w.nbz);
+      maxnp = std::max(maxnp, w.np);
+    }
+    const int ldp = (maxnp + 63) / 64 * 64;
+    if (ldp > ee2_max_row())
+      return fail(h, MSP_E_INVALID, "M_EE: a neighbourhood row exceeds 128 nodes");
+    const long long ldp2 = (long long)ldp * ldp;
+    for (int l = 0; l < ncn; ++l) h->nbe_h[l].goff = (long long)l * pmax * ldp2;
+    h->pmaxe = pmax;
+    h->ldpe = ldp;
+    const long long nx = (long long)ncn * pmax * ldp * MAXM;
+    bool ok = true;
+    auto A = [&](hipError_t e) { if (e != hipSuccess) ok = false; };
+    A(dalloc(&h->d_nbe, ncn));
+    A(dalloc(&h->d_Ge, (long long)ncn * pmax * ldp2));
+    A(dalloc(&h->d_Xe, nx));
+    A(dalloc(&h->d_Ye, nx));
+    A(dalloc(&h->d_Te, nx));
+    A(dalloc(&h->d_Ue, nx));
+    A(dalloc((char**)&h->d_este, (long long)ncn * (long long)eig3_state_bytes()));
+    A(dalloc(&h->d_hsde, (long long)ncn * ldp));
+    A(dalloc(&h->d_hLDe, (long long)ncn * 64 * 65));
+    A(dalloc(&h->d_hLpe, (long long)ncn * 64 * ldp));
+    A(dalloc(&h->d_hRpe, (long long)ncn * 64 * ldp));
+    A(dalloc(&h->d_wante, ncn));
+    A(dalloc(&h->d_nsele, ncn));
+    A(dalloc(&h->d_lame, (long long)ncn * d.eig_kmax));
+    A(dalloc(&h->d_zadd, h->n_dofs));
+    if (!ok) return fail(h, MSP_E_NOMEM, "device allocation of the M_EE setup failed");
+  }
+  const int pmax = h->pmaxe, ldp = h->ldpe;
+  for (int l = 0; l < ncn; ++l) {
+    Nbh3& w = h->nbe_h[l];
+    w.xoff = (long long)l * pmax * ldp * m;
+    w.nmodes = 0;
+    w.col0 = 0;
+    w.psi_off = 0;
+  }
+  HIPCHK(h, hipMemcpyAsync(h->d_nbe, h->nbe_h.data(), ncn * sizeof(Nbh3), hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(h->d_wante, want.data(), ncn * sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemsetAsync(h->d_err, 0, 4 * sizeof(int), s));
+  HIPCHK(h, hipMemsetAsync(h->d_dropped, 0, sizeof(int), s));
+  const double sigma = kShift / (h->H * h->H);
+  const double* Ke = h->d_elem;
+  const double* Ms = h->d_elem + 80;
+  const int tk = timer_begin(h, KT_EIGEN, s);
+  launch_ee2_factor(g, h->d_nbe, ncn, pmax, ldp, h->d_E, h->d_mask, Ke, Ms, sigma, h->d_Ge,
+                    h->d_hsde, h->d_hLDe, h->d_hLpe, h->d_hRpe, h->d_dropped, s);
+  launch_plane_reset(h->d_este, ncn, s);
+  launch_ee2_start(g, h->d_nbe, ncn, pmax, ldp, m, h->d_mask, h->d_Xe, s);
+  int unconv = ncn;
+  for (int it = 0; it < kEig3MaxIt; ++it) {
+    launch_ee2_products(m, g, h->d_nbe, ncn, pmax, ldp, h->d_E, h->d_mask, Ke, Ms, sigma,
+                        h->d_Ge, h->d_Xe, h->d_Ye, h->d_Te, h->d_Ue, h->d_este, s);
+    // selection by count: the test watches the first maxw + 1 Ritz values,
+    // their changes relative to |theta| + tau / H^2 (the heat threshold's
+    // scale, the same units)
+    launch_plane_rr(m, h->d_nbe, ncn, pmax, ldp, h->d_Ye, h->d_Te, h->d_Ue, h->d_Xe,
+                    h->d_este, maxw, 1e300, d.eig_tau / (h->H * h->H), kEigTolEE,
+                    it == 0 ? 1 : 0, h->d_err, s);
+    if (it % 2 == 1 || it + 1 == kEig3MaxIt) {
+      launch_heat3_count(h->d_este, ncn, kEig3Passes, h->d_err + 2, s);
+      HIPCHK(h, hipGetLastError());
+      HIPCHK(h, hipMemcpyAsync(h->h_int + 8, h->d_err + 2, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(h, hipStreamSynchronize(s));
+      unconv = h->h_int[8];
+      if (unconv == 0) break;
+    }
+  }
+  launch_plane_select_count(h->d_este, ncn, m, h->d_wante, d.eig_kmax, h->d_nsele,
+                            h->d_lame, s);
+  timer_end(h, KT_EIGEN, tk, s);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(h->h_int, h->d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(h->h_int + 1, h->d_dropped, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  timer_flush(h);
+  if (h->h_int[1] != 0)
+    return fail(h, MSP_E_NOT_SPD, "an elasticity pencil's row factor lost positive definiteness");
+  if (h->h_int[0] & ERR_EIG)
+    return fail(h, MSP_E_NOT_SPD, "M_EE eigen setup lost positive definiteness of the subspace Gram matrix");
+  h->ee_nsel_h.resize(ncn);
+  h->ee_lam_h.resize((size_t)ncn * d.eig_kmax);
+  HIPCHK(h, hipMemcpy(h->ee_nsel_h.data(), h->d_nsele, ncn * sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(h, hipMemcpy(h->ee_lam_h.data(), h->d_lame, (size_t)ncn * d.eig_kmax * sizeof(double),
+                      hipMemcpyDeviceToHost));
+  h->eig_unconverged = unconv;
+  int col = 0;
+  long long poff = 0;
+  std::vector<int> col_node;
+  for (int l = 0; l < ncn; ++l) {
+    Nbh3& w = h->nbe_h[l];
+    w.nmodes = h->ee_nsel_h[l];
+    w.col0 = col;
+    w.psi_off = poff;
+    for (int j = 0; j < w.nmodes; ++j) col_node.push_back(l);
+    col += w.nmodes;
+    poff += (long long)w.nbz * w.np * w.nmodes;
+  }
+  h->nc = col;
+  h->dep_col = -1;
+  h->ldk = std::max(64, ((col + 63) / 64) * 64);
+  const long long n = h->n_dofs;
+  if ((long long)col * n > (1LL << 30))
+    return fail(h, MSP_E_INVALID, "M_EE keeps its basis dense: n x N_c exceeds 2^30 entries");
+  msp_status st = ensure_coarse_buffers(h, col_node.size(), 0, 1, h->ldk);
+  if (st != MSP_OK) return st;
+  const size_t pne = (size_t)std::max<long long>(poff, 1);
+  if (pne > h->psie_cap) {
+    dfree(h->d_psie);
+    h->d_psie = nullptr;
+    h->psie_cap = 0;
+    HIPCHK(h, dalloc(&h->d_psie, pne));
+    h->psie_cap = pne;
+  }
+  const size_t nphi = (size_t)std::max<long long>((long long)col * n, 1);
+  if (nphi > h->phi_cap) {
+    dfree(h->d_Phi);
+    dfree(h->d_KPhi);
+    h->d_Phi = h->d_KPhi = nullptr;
+    h->phi_cap = 0;
+    HIPCHK(h, dalloc(&h->d_Phi, nphi));
+    HIPCHK(h, dalloc(&h->d_KPhi, nphi));
+    h->phi_cap = nphi;
+  }
+  HIPCHK(h, hipMemcpyAsync(h->d_nbe, h->nbe_h.data(), ncn * sizeof(Nbh3), hipMemcpyHostToDevice, s));
+  if (!col_node.empty())
+    HIPCHK(h, hipMemcpyAsync(h->d_col_node, col_node.data(), col_node.size() * sizeof(int),
+                             hipMemcpyHostToDevice, s));
+  launch_heat3_psi(m, h->d_nbe, ncn, pmax, ldp, h->d_Xe, h->d_psie, s);
+  launch_ee2_basis(g, h->d_nbe, h->d_col_node, col, h->d_mask, h->d_psie, h->d_Phi, s);
+  for (int c = 0; c < col; ++c)
+    launch_apply_K(g, h->mv_ty, h->Ke, h->d_E, h->d_mask, h->d_Phi + (long long)c * n,
+                   h->d_KPhi + (long long)c * n, s);
+  HIPCHK(h, hipMemsetAsync(h->d_K0, 0, (size_t)h->ldk * h->ldk * sizeof(double), s));
+  launch_ee2_k0(h->d_Phi, h->d_KPhi, n, col, h->d_K0, h->ldk, s);
+  HIPCHK(h, hipMemsetAsync(h->d_dropped, 0, sizeof(int), s));
+  launch_k0_pinv(h->d_K0, h->ldk, col, -1, 0, nullptr, h->d_sdiag, h->d_P, h->d_Lp,
+                 h->d_Rp, kPivotDrop, h->d_dropped, s);
+  HIPCHK(h, hipMemsetAsync(h->d_c, 0, (size_t)restrict_bands() * h->ldk * sizeof(double), s));
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemcpyAsync(h->h_int + 1, h->d_dropped, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  h->rank = h->ldk - h->h_int[1];
+  return MSP_OK;
+}
+
 extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
   if (!h) return fail(h, MSP_E_INVALID, "null handle");
   if (h->dim == 3) return setup_3d(h, s);
@@ -1590,6 +1831,26 @@ extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
   if (kerr & ERR_EIG) {
     h->setup_ok = false;
     return fail(h, MSP_E_NOT_SPD, "heat eigen setup lost positive definiteness of the subspace Gram matrix");
+  }
+  if (h->ee) {
+    const msp_status st = setup_ee(h, cap, s);
+    if (st != MSP_OK) {
+      h->setup_ok = false;
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return st;
+    }
+    HIPCHK(h, hipEventRecord(e1, s));
+    HIPCHK(h, hipEventSynchronize(e1));
+    float mse = 0.f;
+    HIPCHK(h, hipEventElapsedTime(&mse, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->t_setup_ms = mse;
+    h->setup_ok = true;
+    h->setup_gen = h->dens_gen;
+    h->rebuild_due = false;
+    return MSP_OK;
   }
   // coarse column layout
   const int rot = h->desc.rot_enrich ? 1 : 0;
@@ -1775,7 +2036,16 @@ static void enqueue_prec(msp_handle* h, int mode, const double* r,
     launch_level1(l1_args(h, r, sc, check), (int)h->subs.size(), s);
     timer_end(h, KT_LEVEL1, t, s);
   }
-  if (coarse && h->nc > 0) {
+  const bool ee = coarse && h->nc > 0 && h->ee;
+  if (ee) {
+    // M_EE: c = Phi^T r into the first partial band, c0 = K_0^+ c, and
+    // Phi c0 for the combination to add
+    const int t = timer_begin(h, KT_RESTRICT, s);
+    launch_ee2_restrict(h->d_Phi, h->n_dofs, h->nc, r, h->d_c, sc, s);
+    timer_end(h, KT_RESTRICT, t, s);
+    launch_coarse_gemv(gv_args(h, sc), s);
+    launch_ee2_prolong(h->d_Phi, h->n_dofs, h->nc, h->d_c0, h->d_zadd, sc, s);
+  } else if (coarse && h->nc > 0) {
     // after the first level, which ran the convergence test and left its
     // decision in the done word, the restriction only reads that word
     const int t = timer_begin(h, KT_RESTRICT, s);
@@ -1784,7 +2054,9 @@ static void enqueue_prec(msp_handle* h, int mode, const double* r,
     launch_coarse_gemv(gv_args(h, sc), s);
   }
   const int t = timer_begin(h, KT_COMBINE, s);
-  launch_combine(mode, cb_args(h, l1, coarse, r, q, z), s);
+  CombineCall cc = cb_args(h, l1, coarse && !h->ee, r, q, z);
+  if (ee) cc.zadd = h->d_zadd;
+  launch_combine(mode, cc, s);
   timer_end(h, KT_COMBINE, t, s);
 }
 
@@ -2444,6 +2716,7 @@ extern "C" msp_status msp_batch_solve(msp_batch* b, msp_handle* const* hs_in,
   for (int e = 0; e < n; ++e) {
     if (!hs[e] || !f[e] || !u[e]) return bfail(b, MSP_E_INVALID, "null handle or vector in the batch");
     if (hs[e]->dim != 2) return bfail(b, MSP_E_INVALID, "dim = 3: batches take 2D problems only");
+    if (hs[e]->ee) return bfail(b, MSP_E_INVALID, "batches take the heat coarse space only (coarse_kind 0)");
     if (hs[e]->mv_ty > 16)
       return bfail(b, MSP_E_INVALID, "mesh too large for the batched stiffness product (tile height 32)");
     for (int k = 0; k < e; ++k)
@@ -2693,6 +2966,8 @@ extern "C" msp_status msp_server_add_run(msp_server* sv, const msp_problem_desc*
     return sfail(sv, MSP_E_INVALID, "null argument");
   if (d->dim != 2)
     return sfail(sv, MSP_E_INVALID, "runs must be 2D: serving batches 2D problems only");
+  if (d->coarse_kind != 0)
+    return sfail(sv, MSP_E_INVALID, "serving takes the heat coarse space only (coarse_kind 0)");
   // validate by building the geometry once (no device memory is kept)
   msp_handle* probe = nullptr;
   msp_status st = msp_create(d, fixed_mask_host, &probe);
@@ -3038,6 +3313,17 @@ extern "C" msp_status msp_coarse_info(msp_handle* h, int32_t* n_modes,
     if (cap_hits) *cap_hits = h->cap_hits;
     return MSP_OK;
   }
+  if (h->ee) {
+    for (size_t l = 0; l < h->cn_h.size(); ++l) {
+      if (n_modes) n_modes[l] = h->ee_nsel_h[l];
+      if (eigvals)
+        for (int j = 0; j < kmax; ++j) eigvals[l * kmax + j] = h->ee_lam_h[l * kmax + j];
+    }
+    if (n_cnodes) *n_cnodes = (int32_t)h->cn_h.size();
+    if (n_coarse) *n_coarse = h->nc;
+    if (cap_hits) *cap_hits = h->cap_hits;
+    return MSP_OK;
+  }
   for (size_t l = 0; l < h->cn_h.size(); ++l) {
     const int sys = h->cn_h[l].sys;
     if (n_modes) n_modes[l] = h->nsel_h[sys];
@@ -3060,6 +3346,13 @@ extern "C" msp_status msp_coarse_basis(msp_handle* h, double* phi,
                           d.sub_nel[1], d.sub_nel[2], h->invH, h->d_nmask, h->d_psi3,
                           phi, s);
     HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipStreamSynchronize(s));
+    return MSP_OK;
+  }
+  if (h->ee) {
+    if (h->nc > 0)
+      HIPCHK(h, hipMemcpyAsync(phi, h->d_Phi, (size_t)h->nc * h->n_dofs * sizeof(double),
+                               hipMemcpyDeviceToDevice, s));
     HIPCHK(h, hipStreamSynchronize(s));
     return MSP_OK;
   }
@@ -3088,6 +3381,10 @@ extern "C" msp_status msp_coarse_matrix(msp_handle* h, int32_t which,
     HIPCHK(h, hipGetLastError());
   } else if (which == 1) {
     HIPCHK(h, hipMemcpyAsync(out, h->d_K0, bytes, hipMemcpyDeviceToDevice, s));
+  } else if (h->ee) {
+    HIPCHK(h, hipMemsetAsync(out, 0, bytes, s));
+    launch_ee2_k0(h->d_Phi, h->d_KPhi, h->n_dofs, h->nc, out, h->ldk, s);
+    HIPCHK(h, hipGetLastError());
   } else {
     // the setup's K Phi columns are still held; redo the block products
     HIPCHK(h, hipMemsetAsync(out, 0, bytes, s));
