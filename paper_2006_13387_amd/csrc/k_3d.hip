@@ -4,15 +4,15 @@
 // DOFs of D'_i; Section 1.1 for the trilinear brick element).
 //
 // A 3D subdomain of S = 6 elements and one overlap layer holds up to 7^3
-// nodes, 1,029 DOFs, and its node planes couple 147 DOFs each: too wide for
-// the block-tridiagonal records of the 2D path.  Each K_i is instead
-// gathered as a dense matrix, scaled to unit diagonal and inverted in place
-// by the blocked Gauss-Jordan elimination of the coarse solve, batched over
-// all subdomains (its update runs on the FP64 matrix cores).  The inverse
-// is kept in FP64, or rounded to FP32 for the mixed path, and applied as
-// one matrix-vector product per subdomain: the application streams every
-// inverse once, so it is bound by HBM bandwidth.  The local solutions are
-// summed per node in a fixed subdomain order (no atomics).
+// nodes, 1,029 DOFs, in 7 node planes of 147 DOFs: too wide for the
+// 72-DOF block rows of the 2D records.  K_i is factored block-
+// tridiagonally by those planes: each plane's Schur complement is assembled
+// from E and inverted by the blocked Gauss-Jordan elimination of the coarse
+// solve, batched over all subdomains (its update runs on the FP64 matrix
+// cores).  The inverse blocks are kept in FP64, and rounded to FP32 for
+// the mixed path; the application is a forward and a backward sweep over
+// a subdomain's planes in one workgroup.  The local solutions are summed
+// per node in a fixed subdomain order (no atomics).
 //
 // The PCG kernels keep their scalars on the device (CGScalars); every
 // kernel returns at once when the run is marked done, so a chunk of
@@ -25,75 +25,10 @@
 namespace msp {
 
 constexpr int T3_NT = 256;
-constexpr int LD3_MAX = 2048;     // largest local order (LDS of the apply)
+constexpr int LD3_MAX = 2048;     // largest local order (the box vector in LDS)
 // workgroups of the vector kernels: one per CU (each workgroup takes its
 // ticket with one atomic on a shared counter, and those serialise)
 constexpr int V3_MAXB = 256;
-
-// ---------------------------------------------------------------------
-// Dense local matrices.  Thread per local row DOF q = 3 a + c (node a of
-// the box): for each of the 27 neighbours b of a inside the box and each
-// component d, entry (q, 3 b + d) = sum over the elements holding both
-// nodes of E_e K^_e(3 va + c, 3 vb + d) (va, vb the nodes' vertices in e).
-// Rows and columns of fixed DOFs are those of the identity, as are the
-// padding rows n .. ld-1 (so the inverse restricted to the free DOFs is
-// K_i^{-1}).  The pool must be zero on entry.
-__global__ void __launch_bounds__(T3_NT)
-k3_assemble(Geom g, const Sub3* __restrict__ subs, int ld,
-            const double* __restrict__ Ke, const double* __restrict__ E,
-            const uint8_t* __restrict__ mask, double* __restrict__ A) {
-  __shared__ double K[576];
-  for (int q = threadIdx.x; q < 576; q += T3_NT) K[q] = Ke[q];
-  __syncthreads();
-  const Sub3 s = subs[blockIdx.y];
-  const int q = blockIdx.x * T3_NT + threadIdx.x;
-  if (q >= ld) return;
-  double* row = A + s.moff + (long long)q * ld;
-  if (q >= s.n) {
-    row[q] = 1.0;
-    return;
-  }
-  const int a = q / 3, c = q - 3 * (q / 3);
-  const int lx = a % s.nbx, ly = (a / s.nbx) % s.nby, lz = a / (s.nbx * s.nby);
-  const int ax = s.x0 + lx, ay = s.y0 + ly, az = s.z0 + lz;
-  const long long anode = ((long long)az * g.nny + ay) * g.nnx + ax;
-  if (mask[3 * anode + c]) {
-    row[q] = 1.0;
-    return;
-  }
-  // moduli of the eight elements around a: element (ax - sx, ay - sy, az - sz)
-  double Ee[8];
-#pragma unroll
-  for (int v = 0; v < 8; ++v) {
-    const int ex = ax - (v & 1), ey = ay - ((v >> 1) & 1), ez = az - (v >> 2);
-    const bool in = ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny && ez >= 0 && ez < g.nz;
-    Ee[v] = in ? E[((long long)ez * g.ny + ey) * g.nx + ex] : 0.0;
-  }
-  for (int dz = -1; dz <= 1; ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int bx = lx + dx, by = ly + dy, bz = lz + dz;
-        if (bx < 0 || bx >= s.nbx || by < 0 || by >= s.nby || bz < 0 || bz >= s.nbz) continue;
-        const int b = (bz * s.nby + by) * s.nbx + bx;
-        const long long bnode = anode + ((long long)dz * g.nny + dy) * g.nnx + dx;
-        double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-#pragma unroll
-        for (int v = 0; v < 8; ++v) {
-          const int sx = v & 1, sy = (v >> 1) & 1, sz = v >> 2;
-          const int ox = sx + dx, oy = sy + dy, oz = sz + dz;   // b's vertex offsets in e
-          if (ox < 0 || ox > 1 || oy < 0 || oy > 1 || oz < 0 || oz > 1) continue;
-          const int vb = ox + 2 * oy + 4 * oz;
-          const double* kr = K + (3 * v + c) * 24 + 3 * vb;
-          v0 += Ee[v] * kr[0];
-          v1 += Ee[v] * kr[1];
-          v2 += Ee[v] * kr[2];
-        }
-        const uint8_t* mb = mask + 3 * bnode;
-        row[3 * b] = mb[0] ? 0.0 : v0;
-        row[3 * b + 1] = mb[1] ? 0.0 : v1;
-        row[3 * b + 2] = mb[2] ? 0.0 : v2;
-      }
-}
 
 // s_j = 1 / sqrt(A_jj) (0 for a non-positive or non-finite diagonal, whose
 // pivot is then dropped and reported).
@@ -117,7 +52,8 @@ k3_scale(double* __restrict__ A, int ld, long long mstride,
 }
 
 // Undo the scaling of the inverse, symmetrised: B_ij = (A_ij + A_ji)/2 s_i
-// s_j, in place (FP64) or into the FP32 pool.
+// s_j, in place (FP64), and rounded into the FP32 pool when given.  The
+// thread of (i, j), j >= i, owns both entries of the pair.
 __global__ void __launch_bounds__(T3_NT)
 k3_unscale(double* __restrict__ A, int ld, long long mstride,
            const double* __restrict__ sdiag, float* __restrict__ A32) {
@@ -126,81 +62,13 @@ k3_unscale(double* __restrict__ A, int ld, long long mstride,
   const int i = (int)(idx / ld), j = (int)(idx - (long long)(idx / ld) * ld);
   double* M = A + blockIdx.y * mstride;
   const double* sd = sdiag + (long long)blockIdx.y * ld;
+  if (j < i) return;
   const double v = 0.5 * (M[(long long)i * ld + j] + M[(long long)j * ld + i]) * sd[i] * sd[j];
+  M[(long long)i * ld + j] = v;
+  M[(long long)j * ld + i] = v;
   if (A32 != nullptr) {
-    A32[blockIdx.y * mstride + idx] = (float)v;
-  } else if (j >= i) {
-    M[(long long)i * ld + j] = v;
-    M[(long long)j * ld + i] = v;
-  }
-}
-
-// ---------------------------------------------------------------------
-// First-level application, part 1: lsol_i = K_i^{-1} r_i.  Workgroup =
-// (64-row block, subdomain); r_i is gathered into LDS (zero at fixed DOFs
-// and past n), then each wave takes 16 rows, four at a time, the lanes
-// striding along the rows with 16-byte loads (FP64 sums).
-template <typename T> struct Vec3T;
-template <> struct Vec3T<float> { typedef float4 type; static constexpr int n = 4; };
-template <> struct Vec3T<double> { typedef double2 type; static constexpr int n = 2; };
-
-__device__ __forceinline__ double vdot(const float4& a, const double* x) {
-  return (double)a.x * x[0] + (double)a.y * x[1] + (double)a.z * x[2] + (double)a.w * x[3];
-}
-__device__ __forceinline__ double vdot(const double2& a, const double* x) {
-  return a.x * x[0] + a.y * x[1];
-}
-
-template <typename T>
-__global__ void __launch_bounds__(T3_NT)
-k3_level1(Geom g, const Sub3* __restrict__ subs, int ld, const T* __restrict__ A,
-          const uint8_t* __restrict__ mask, const double* __restrict__ r,
-          double* __restrict__ lsol, const CGScalars* __restrict__ sc) {
-  typedef typename Vec3T<T>::type V;
-  constexpr int NV = Vec3T<T>::n;
-  __shared__ double rl[LD3_MAX];
-  __shared__ int shd;
-  if (sc != nullptr && block_read_done(sc, &shd)) return;
-  const Sub3 s = subs[blockIdx.y];
-  const int row0 = blockIdx.x * 64;
-  if (row0 >= s.n) return;
-  const int ncol = (s.n + NV - 1) / NV * NV;
-  for (int q = threadIdx.x; q < ncol; q += T3_NT) {
-    double v = 0.0;
-    if (q < s.n) {
-      const int a = q / 3, c = q - 3 * (q / 3);
-      const int lx = a % s.nbx, ly = (a / s.nbx) % s.nby, lz = a / (s.nbx * s.nby);
-      const long long node = ((long long)(s.z0 + lz) * g.nny + s.y0 + ly) * g.nnx + s.x0 + lx;
-      v = mask[3 * node + c] ? 0.0 : r[3 * node + c];
-    }
-    rl[q] = v;
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int nvec = ncol / NV;
-  const T* M = A + s.moff;
-#pragma unroll 1
-  for (int g4 = 0; g4 < 4; ++g4) {
-    const int i0 = row0 + 16 * w + 4 * g4;
-    if (i0 >= s.n) break;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const V* rows[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      rows[k] = reinterpret_cast<const V*>(M + (long long)min(i0 + k, s.n - 1) * ld);
-    for (int cv = lane; cv < nvec; cv += 64) {
-      V v[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) v[k] = rows[k][cv];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) acc[k] += vdot(v[k], rl + NV * cv);
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) acc[k] = wave_sum(acc[k]);
-    if (lane < 4 && i0 + lane < s.n) {
-      const double o = lane == 0 ? acc[0] : lane == 1 ? acc[1] : lane == 2 ? acc[2] : acc[3];
-      lsol[s.voff + i0 + lane] = o;
-    }
+    A32[blockIdx.y * mstride + (long long)i * ld + j] = (float)v;
+    A32[blockIdx.y * mstride + (long long)j * ld + i] = (float)v;
   }
 }
 
@@ -251,7 +119,8 @@ __device__ __forceinline__ double3 coarse3_prolong(const Geom& g, const Coarse3&
   return z;
 }
 
-// Part 2: z at every node = sum of the local solutions of the subdomains
+// ---------------------------------------------------------------------
+// First-level summation: z at every node = sum of the local solutions of the subdomains
 // whose boxes hold the node, in ascending subdomain order (at most two
 // blocks per axis hold a node when the overlap is below the block edge),
 // plus the coarse part R_0^T c0 when cc.c0 is set; zero at fixed DOFs.
@@ -292,6 +161,274 @@ k3_level1_sum(Geom g, const Sub3* __restrict__ subs, int nbx, int nby, int nbz,
   z[3 * node] = m[0] ? 0.0 : z0;
   z[3 * node + 1] = m[1] ? 0.0 : z1;
   z[3 * node + 2] = m[2] ? 0.0 : z2;
+}
+
+// ---------------------------------------------------------------------
+// First level by node planes.  K_i is block tridiagonal in the planes of
+// constant z of its box (np = 3 nbx nby unknowns a plane, DOF 3 a + c of the
+// in-plane node a, padded to the shared order ldp); its block LDL^T keeps
+// the inverse Schur block G_k of every plane (row-major, symmetric), formed
+// plane after plane: S_k = D_k - C_k^T G_{k-1} C_k from E (k3s_schur), then
+// inverted by the batched Gauss-Jordan elimination.  The application is a
+// forward and a backward sweep over the planes, each step a product with
+// G_k and the couplings recomputed from E.  Fixed DOFs are identity rows.
+
+// Coupling of DOF (X, Y, Z, ca) with (X + dx, Y + dy, Z + dz, cb) in K:
+// the elements of the mesh holding both nodes (K_i is the principal
+// submatrix of K, so elements outside the box count).
+__device__ __forceinline__ double k3_coef(const Geom& g, const double* __restrict__ E,
+                                          const double* Ke, int X, int Y, int Z,
+                                          int dx, int dy, int dz, int ca, int cb) {
+  double v = 0.0;
+#pragma unroll
+  for (int sz = 0; sz < 2; ++sz) {
+    const int oz = sz + dz, ez = Z - sz;
+    if (oz < 0 || oz > 1 || ez < 0 || ez >= g.nz) continue;
+#pragma unroll
+    for (int sy = 0; sy < 2; ++sy) {
+      const int oy = sy + dy, ey = Y - sy;
+      if (oy < 0 || oy > 1 || ey < 0 || ey >= g.ny) continue;
+#pragma unroll
+      for (int sx = 0; sx < 2; ++sx) {
+        const int ox = sx + dx, ex = X - sx;
+        if (ox < 0 || ox > 1 || ex < 0 || ex >= g.nx) continue;
+        const int va = sx + 2 * sy + 4 * sz, vb = ox + 2 * oy + 4 * oz;
+        v += E[((long long)ez * g.ny + ey) * g.nx + ex] * Ke[(3 * va + ca) * 24 + 3 * vb + cb];
+      }
+    }
+  }
+  return v;
+}
+
+__device__ __forceinline__ bool k3_fixed(const Geom& g, const uint8_t* __restrict__ mask,
+                                         int X, int Y, int Z, int c) {
+  return mask[3 * (((long long)Z * g.nny + Y) * g.nnx + X) + c] != 0;
+}
+
+constexpr int K3S_CB = 16;     // columns of a Schur-complement workgroup
+constexpr int K3S_MAXP = 256;  // largest padded plane order
+
+// Plane k of every subdomain: S_k = D_k - C_k^T G_{k-1} C_k into slot k
+// (this workgroup's K3S_CB columns as rows), identity on padding, fixed DOFs
+// and the slots of subdomains with fewer planes.  Grid (ldp / K3S_CB,
+// subdomains); thread a forms row a.
+__global__ void __launch_bounds__(T3_NT)
+k3s_schur(Geom g, const Sub3* __restrict__ subs, int k, int ldp,
+          const double* __restrict__ Ke_g, const double* __restrict__ E,
+          const uint8_t* __restrict__ mask, double* __restrict__ G) {
+  __shared__ double Ke[576];
+  __shared__ double T[K3S_MAXP * K3S_CB];
+  __shared__ double Cb[K3S_CB * 27];
+  __shared__ int Jb[K3S_CB * 27];
+  const Sub3 sb = subs[blockIdx.y];
+  const int tid = threadIdx.x;
+  for (int q = tid; q < 576; q += T3_NT) Ke[q] = Ke_g[q];
+  const long long ldp2 = (long long)ldp * ldp;
+  double* Sk = G + sb.moff + k * ldp2;
+  const int b0 = blockIdx.x * K3S_CB;
+  if (k >= sb.nbz) {
+    for (int idx = tid; idx < K3S_CB * ldp; idx += T3_NT) {
+      const int t = idx / ldp, a = idx - t * ldp;
+      Sk[(long long)(b0 + t) * ldp + a] = (a == b0 + t) ? 1.0 : 0.0;
+    }
+    return;
+  }
+  __syncthreads();
+  const int np = 3 * sb.nbx * sb.nby;
+  const int Z = sb.z0 + k;
+  // couplings of column b with the 27 DOFs of its 9 neighbours in plane k-1
+  if (k > 0) {
+    for (int idx = tid; idx < K3S_CB * 27; idx += T3_NT) {
+      const int t = idx / 27, q = idx - 27 * (idx / 27);
+      const int b = b0 + t;
+      const int nq = q / 3, cj = q - 3 * (q / 3);
+      const int dx = nq % 3 - 1, dy = nq / 3 - 1;
+      double c = 0.0;
+      int j = -1;
+      if (b < np) {
+        const int bn = b / 3, cb = b - 3 * (b / 3);
+        const int bx = bn % sb.nbx, by = bn / sb.nbx;
+        const int jx = bx + dx, jy = by + dy;
+        if (jx >= 0 && jx < sb.nbx && jy >= 0 && jy < sb.nby) {
+          j = 3 * (jy * sb.nbx + jx) + cj;
+          const int X = sb.x0 + bx, Y = sb.y0 + by;
+          if (!k3_fixed(g, mask, X, Y, Z, cb) && !k3_fixed(g, mask, X + dx, Y + dy, Z - 1, cj))
+            c = k3_coef(g, E, Ke, X, Y, Z, dx, dy, -1, cb, cj);
+        }
+      }
+      Cb[idx] = c;
+      Jb[idx] = j;
+    }
+  }
+  __syncthreads();
+  if (k > 0 && tid < ldp) {
+    const double* Gp = Sk - ldp2;
+    for (int t = 0; t < K3S_CB; ++t) {
+      double acc = 0.0;
+      for (int q = 0; q < 27; ++q) {
+        const int j = Jb[t * 27 + q];
+        const double c = Cb[t * 27 + q];
+        if (j >= 0 && c != 0.0) acc += Gp[(long long)j * ldp + tid] * c;
+      }
+      T[tid * K3S_CB + t] = acc;
+    }
+  }
+  __syncthreads();
+  const int a = tid;
+  if (a >= ldp) return;
+  const bool arow = a < np;
+  const int an = a / 3, ca = a - 3 * (a / 3);
+  const int ax = arow ? an % sb.nbx : 0, ay = arow ? an / sb.nbx : 0;
+  const bool rem = !arow || k3_fixed(g, mask, sb.x0 + ax, sb.y0 + ay, Z, ca);
+  const int X = sb.x0 + ax, Y = sb.y0 + ay;
+  for (int t = 0; t < K3S_CB; ++t) {
+    const int b = b0 + t;
+    double v;
+    if (rem || b >= np) {
+      v = (a == b) ? 1.0 : 0.0;
+    } else {
+      const int bn = b / 3, cb = b - 3 * (b / 3);
+      const int dx = bn % sb.nbx - ax, dy = bn / sb.nbx - ay;
+      v = 0.0;
+      if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 &&
+          !k3_fixed(g, mask, X + dx, Y + dy, Z, cb))
+        v = k3_coef(g, E, Ke, X, Y, Z, dx, dy, 0, ca, cb);
+      if (k > 0) {
+        for (int q = 0; q < 27; ++q) {
+          const int nq = q / 3, ci = q - 3 * (q / 3);
+          const int ix = ax + nq % 3 - 1, iy = ay + nq / 3 - 1;
+          if (ix < 0 || ix >= sb.nbx || iy < 0 || iy >= sb.nby) continue;
+          if (k3_fixed(g, mask, sb.x0 + ix, sb.y0 + iy, Z - 1, ci)) continue;
+          const double c = k3_coef(g, E, Ke, X, Y, Z, nq % 3 - 1, nq / 3 - 1, -1, ca, ci);
+          v -= c * T[(3 * (iy * sb.nbx + ix) + ci) * K3S_CB + t];
+        }
+      }
+    }
+    Sk[(long long)b * ldp + a] = v;
+  }
+}
+
+// Per subdomain and plane: max over the plane's free DOFs of
+// (S_k^-1)_ii K_ii, about 1 where the DOF is held by stiff material and up
+// to the contrast for stiff islands floating in soft material (whose rigid
+// motions FP32 inverse blocks cannot carry, as in 2D).  Grid (planes,
+// subdomains).
+__global__ void __launch_bounds__(K3S_MAXP)
+k3s_metric(Geom g, const Sub3* __restrict__ subs, int ldp, const double* __restrict__ G,
+           const double* __restrict__ Ke_g, const double* __restrict__ E,
+           const uint8_t* __restrict__ mask, double* __restrict__ metric) {
+  __shared__ double Ke[576];
+  __shared__ double red[K3S_MAXP / 64];
+  const Sub3 sb = subs[blockIdx.y];
+  const int k = blockIdx.x, a = threadIdx.x;
+  for (int q = a; q < 576; q += K3S_MAXP) Ke[q] = Ke_g[q];
+  __syncthreads();
+  const int np = 3 * sb.nbx * sb.nby;
+  double v = 0.0;
+  if (k < sb.nbz && a < np) {
+    const int an = a / 3, c = a - 3 * (a / 3);
+    const int X = sb.x0 + an % sb.nbx, Y = sb.y0 + an / sb.nbx, Z = sb.z0 + k;
+    if (!k3_fixed(g, mask, X, Y, Z, c)) {
+      const double gi = G[sb.moff + (long long)k * ldp * ldp + (long long)a * ldp + a];
+      v = fabs(gi) * k3_coef(g, E, Ke, X, Y, Z, 0, 0, 0, c, c);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  if ((a & 63) == 0) red[a >> 6] = v;
+  __syncthreads();
+  if (a == 0) {
+    double m = red[0];
+    for (int w = 1; w < K3S_MAXP / 64; ++w) m = fmax(m, red[w]);
+    metric[(long long)blockIdx.y * gridDim.x + k] = m;
+  }
+}
+
+// z_i = K_i^{-1} r_i by the plane factors: one workgroup per subdomain,
+// the box vector in LDS (r, then y, then x), thread (i, h) forms row i of
+// each plane's product over half h of the inner index (G_k symmetric: row
+// kk read along i), the halves added through LDS.  The blocks are read in
+// FP32 (G32) unless the subdomain is flagged in use64 or G32 is null.
+constexpr int K3S_NT = 512;
+__global__ void __launch_bounds__(K3S_NT)
+k3s_apply(Geom g, const Sub3* __restrict__ subs, int ldp, const double* __restrict__ G64,
+          const float* __restrict__ G32, const uint8_t* __restrict__ use64,
+          const double* __restrict__ Ke_g, const double* __restrict__ E,
+          const uint8_t* __restrict__ mask, const double* __restrict__ r,
+          double* __restrict__ lsol, const CGScalars* __restrict__ sc) {
+  __shared__ double Ke[576];
+  __shared__ double xl[LD3_MAX];
+  __shared__ double rh[K3S_MAXP];
+  __shared__ double ph[K3S_MAXP];
+  __shared__ int shd;
+  if (sc != nullptr && block_read_done(sc, &shd)) return;
+  const Sub3 sb = subs[blockIdx.x];
+  const bool f32 = G32 != nullptr && !(use64 != nullptr && use64[blockIdx.x]);
+  const int tid = threadIdx.x;
+  for (int q = tid; q < 576; q += K3S_NT) Ke[q] = Ke_g[q];
+  const int np = 3 * sb.nbx * sb.nby;
+  for (int q = tid; q < sb.n; q += K3S_NT) {
+    const int a = q / 3, c = q - 3 * (q / 3);
+    const int lx = a % sb.nbx, ly = (a / sb.nbx) % sb.nby, lz = a / (sb.nbx * sb.nby);
+    const long long node = ((long long)(sb.z0 + lz) * g.nny + sb.y0 + ly) * g.nnx + sb.x0 + lx;
+    xl[q] = mask[3 * node + c] ? 0.0 : r[3 * node + c];
+  }
+  __syncthreads();
+  const int i = tid & (K3S_MAXP - 1), hh = tid / K3S_MAXP;
+  const int half = (np + 1) / 2, kk0 = hh * half, kk1 = min(np, kk0 + half);
+  const long long ldp2 = (long long)ldp * ldp;
+  const int an = tid / 3, ca = tid - 3 * (tid / 3);
+  const int ax = tid < np ? an % sb.nbx : 0, ay = tid < np ? an / sb.nbx : 0;
+  // sum over the 27 DOFs of the 9 neighbours in plane k + dz of the coupling
+  // times the box vector there
+  auto couple = [&](int k, int dz) -> double {
+    const int X = sb.x0 + ax, Y = sb.y0 + ay, Z = sb.z0 + k;
+    if (k3_fixed(g, mask, X, Y, Z, ca)) return 0.0;
+    const double* xp = xl + (k + dz) * np;
+    double s = 0.0;
+    for (int q = 0; q < 27; ++q) {
+      const int nq = q / 3, cj = q - 3 * (q / 3);
+      const int dx = nq % 3 - 1, dy = nq / 3 - 1;
+      const int jx = ax + dx, jy = ay + dy;
+      if (jx < 0 || jx >= sb.nbx || jy < 0 || jy >= sb.nby) continue;
+      if (k3_fixed(g, mask, X + dx, Y + dy, Z + dz, cj)) continue;
+      s = fma(k3_coef(g, E, Ke, X, Y, Z, dx, dy, dz, ca, cj), xp[3 * (jy * sb.nbx + jx) + cj], s);
+    }
+    return s;
+  };
+  auto gemv = [&](int k) -> double {
+    double acc = 0.0;
+    if (i < np) {
+      if (f32) {
+        const float* Gk = G32 + sb.moff + k * ldp2 + i;
+#pragma unroll 4
+        for (int kk = kk0; kk < kk1; ++kk) acc = fma((double)Gk[(long long)kk * ldp], rh[kk], acc);
+      } else {
+        const double* Gk = G64 + sb.moff + k * ldp2 + i;
+#pragma unroll 4
+        for (int kk = kk0; kk < kk1; ++kk) acc = fma(Gk[(long long)kk * ldp], rh[kk], acc);
+      }
+    }
+    return acc;
+  };
+  for (int k = 0; k < sb.nbz; ++k) {
+    if (tid < np) rh[tid] = xl[k * np + tid] - (k > 0 ? couple(k, -1) : 0.0);
+    __syncthreads();
+    const double acc = gemv(k);
+    if (hh == 1 && i < np) ph[i] = acc;
+    __syncthreads();
+    if (hh == 0 && i < np) xl[k * np + i] = acc + ph[i];
+    __syncthreads();
+  }
+  for (int k = sb.nbz - 2; k >= 0; --k) {
+    if (tid < np) rh[tid] = couple(k, 1);
+    __syncthreads();
+    const double acc = gemv(k);
+    if (hh == 1 && i < np) ph[i] = acc;
+    __syncthreads();
+    if (hh == 0 && i < np) xl[k * np + i] -= acc + ph[i];
+    __syncthreads();
+  }
+  for (int q = tid; q < sb.n; q += K3S_NT) lsol[sb.voff + q] = xl[q];
 }
 
 // ---------------------------------------------------------------------
@@ -476,13 +613,6 @@ int vec3_blocks(long long n) {
   return (int)(b < 1 ? 1 : (b > V3_MAXB ? V3_MAXB : b));
 }
 
-void launch_assemble3(const Geom& g, const Sub3* subs, int nsub, int ld,
-                      const double* Ke, const double* E, const uint8_t* mask,
-                      double* A, hipStream_t s) {
-  hipLaunchKernelGGL(k3_assemble, dim3((ld + T3_NT - 1) / T3_NT, nsub), dim3(T3_NT),
-                     0, s, g, subs, ld, Ke, E, mask, A);
-}
-
 void launch_gj_steps(double*, int, int, GjStride, double*, double*, double*,
                      double, int*, hipStream_t);
 
@@ -505,27 +635,41 @@ void launch_local_inverse3_strided(double* A, int ld, int nsub, long long ms,
                      sdiag, A32);
 }
 
-void launch_local_inverse3(double* A, int ld, int nsub, double* sdiag,
-                           double* LD, double* Lp, double* Rp, int* dropped,
-                           float* A32, hipStream_t s) {
-  launch_local_inverse3_strided(A, ld, nsub, (long long)ld * ld, sdiag, LD, Lp, Rp,
-                                dropped, A32, s);
+// Plane factors of every K_i: Schur complement and its inverse, plane by
+// plane (FP32 copies into G32 when given, same layout).  G, G32: pmax
+// slots of ldp^2 per subdomain (Sub3.moff).
+void launch_level1_planes(const Geom& g, const Sub3* subs, int nsub, int pmax, int ldp,
+                          const double* Ke, const double* E, const uint8_t* mask,
+                          double* G, float* G32, double* sdiag, double* LD, double* Lp,
+                          double* Rp, int* dropped, hipStream_t s) {
+  const long long ldp2 = (long long)ldp * ldp;
+  for (int k = 0; k < pmax; ++k) {
+    hipLaunchKernelGGL(k3s_schur, dim3(ldp / K3S_CB, nsub), dim3(T3_NT), 0, s, g, subs, k,
+                       ldp, Ke, E, mask, G);
+    launch_local_inverse3_strided(G + k * ldp2, ldp, nsub, pmax * ldp2, sdiag, LD, Lp, Rp,
+                                  dropped, G32 ? G32 + k * ldp2 : nullptr, s);
+  }
+}
+
+int level1_planes_max() { return K3S_MAXP; }
+
+void launch_level1_metric(const Geom& g, const Sub3* subs, int nsub, int pmax, int ldp,
+                          const double* G, const double* Ke, const double* E,
+                          const uint8_t* mask, double* metric, hipStream_t s) {
+  hipLaunchKernelGGL(k3s_metric, dim3(pmax, nsub), dim3(K3S_MAXP), 0, s, g, subs, ldp, G,
+                     Ke, E, mask, metric);
 }
 
 void launch_level1_3d(const Geom& g, const Sub3* subs, int nsub, int ld,
                       int nbx, int nby, int nbz, int S0, int S1, int S2,
-                      const double* A64, const float* A32, const uint8_t* mask,
+                      const double* A64, const float* A32, const uint8_t* use64,
+                      const double* Ke, const double* E, const uint8_t* mask,
                       const double* r, double* lsol, double* z,
                       const CGScalars* sc, int use_l1, const Coarse3& cc,
                       hipStream_t s) {
-  const dim3 gr(ld / 64, nsub);
-  if (!use_l1) {
-  } else if (A32 != nullptr)
-    hipLaunchKernelGGL(k3_level1<float>, gr, dim3(T3_NT), 0, s, g, subs, ld, A32,
-                       mask, r, lsol, sc);
-  else
-    hipLaunchKernelGGL(k3_level1<double>, gr, dim3(T3_NT), 0, s, g, subs, ld, A64,
-                       mask, r, lsol, sc);
+  if (use_l1)
+    hipLaunchKernelGGL(k3s_apply, dim3(nsub), dim3(K3S_NT), 0, s, g, subs, ld, A64, A32,
+                       use64, Ke, E, mask, r, lsol, sc);
   const long long nn = (long long)g.nnx * g.nny * g.nnz;
   hipLaunchKernelGGL(k3_level1_sum, dim3((unsigned)((nn + T3_NT - 1) / T3_NT)),
                      dim3(T3_NT), 0, s, g, subs, nbx, nby, nbz, S0, S1, S2, mask,

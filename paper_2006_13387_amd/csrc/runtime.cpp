@@ -102,14 +102,18 @@ void q1_element_matrices(double nu, double h, double* Ke, double* Ae,
 // k_3d.hip
 int level1_3d_max_order();
 int vec3_blocks(long long);
-void launch_assemble3(const Geom&, const Sub3*, int, int, const double*,
-                      const double*, const uint8_t*, double*, hipStream_t);
-void launch_local_inverse3(double*, int, int, double*, double*, double*,
-                           double*, int*, float*, hipStream_t);
 void launch_level1_3d(const Geom&, const Sub3*, int, int, int, int, int, int,
                       int, int, const double*, const float*, const uint8_t*,
-                      const double*, double*, double*, const CGScalars*, int,
-                      const Coarse3&, hipStream_t);
+                      const double*, const double*, const uint8_t*, const double*,
+                      double*, double*, const CGScalars*, int, const Coarse3&,
+                      hipStream_t);
+void launch_level1_metric(const Geom&, const Sub3*, int, int, int, const double*,
+                          const double*, const double*, const uint8_t*, double*,
+                          hipStream_t);
+void launch_level1_planes(const Geom&, const Sub3*, int, int, int, const double*,
+                          const double*, const uint8_t*, double*, float*, double*,
+                          double*, double*, double*, int*, hipStream_t);
+int level1_planes_max();
 void h8_heat_element(double h, double* Ae, double* Me);
 // k_coarse3d.hip
 size_t eig3_state_bytes();
@@ -357,6 +361,9 @@ struct msp_handle {
   float* d_A3f = nullptr;
   double *d_LD3 = nullptr, *d_Lp3 = nullptr, *d_Rp3 = nullptr, *d_sd3 = nullptr;
   unsigned int* d_tk3 = nullptr;   // ticket of the 3D PCG sums
+  int pmax3l = 0;                  // planes of the largest 3D subdomain
+  double* d_met3 = nullptr;        // per (subdomain, plane): the FP32 amplification metric
+  uint8_t* d_use3 = nullptr;       // per subdomain: 1 = apply the FP64 blocks
   // 3D coarse space: the coarse nodes with their neighbourhoods, the
   // plane-blocked factors of the heat pencils (pmax3 planes of ldp3^2 per
   // neighbourhood), the subspace blocks (m3 columns), the modes, K Phi and
@@ -681,7 +688,7 @@ extern "C" msp_status msp_destroy(msp_handle* h) {
                   h->d_z, h->d_tmp, h->d_sc, h->d_ahist, h->d_bhist,
                   h->d_part, h->d_cnt, h->d_err, h->d_eig_state, h->d_nmask,
                   h->d_subs3, h->d_A3, h->d_A3f, h->d_LD3, h->d_Lp3, h->d_Rp3,
-                  h->d_sd3, h->d_tk3, h->d_nb3, h->d_G3, h->d_X3, h->d_Y3,
+                  h->d_sd3, h->d_tk3, h->d_met3, h->d_use3, h->d_nb3, h->d_G3, h->d_X3, h->d_Y3,
                   h->d_T3, h->d_U3, h->d_est3, h->d_hsd3, h->d_hLD3, h->d_hLp3,
                   h->d_hRp3, h->d_hel3, h->d_psi3, h->d_drop3, h->d_w3, h->d_y3,
                   h->d_nbe, h->d_Ge, h->d_Xe, h->d_Ye, h->d_Te, h->d_Ue, h->d_este,
@@ -1136,6 +1143,13 @@ static msp_status ensure_3d_buffers(msp_handle* h) {
       }
   if (maxn > level1_3d_max_order())
     return fail(h, MSP_E_INVALID, "3D subdomain exceeds 2048 DOFs (reduce sub_nel + 2*overlap)");
+  int pmax = 0, maxnp = 0;
+  for (const Sub3& sb : h->subs3) {
+    pmax = std::max(pmax, sb.nbz);
+    maxnp = std::max(maxnp, 3 * sb.nbx * sb.nby);
+  }
+  if (maxnp > level1_planes_max())
+    return fail(h, MSP_E_INVALID, "3D subdomain plane exceeds 256 DOFs (reduce sub_nel + 2*overlap)");
   {
     std::vector<uint8_t> cov((size_t)h->n_nodes, 0);
     for (const Sub3& sb : h->subs3)
@@ -1147,9 +1161,12 @@ static msp_status ensure_3d_buffers(msp_handle* h) {
       if (!cov[p] && (!h->mask_h[3 * p] || !h->mask_h[3 * p + 1] || !h->mask_h[3 * p + 2]))
         return fail(h, MSP_E_INVALID, "subdomains do not cover every free DOF (overlap too small)");
   }
-  const int ld = (maxn + 63) / 64 * 64;
+  // plane factors: pmax slots of ld^2 per subdomain, ld the largest plane
+  // (3 nbx nby DOFs) rounded up to whole 64-blocks
+  const int ld = (maxnp + 63) / 64 * 64;
   h->ld3 = ld;
-  const long long ms = (long long)ld * ld;
+  h->pmax3l = pmax;
+  const long long ms = (long long)pmax * ld * ld;
   for (size_t i = 0; i < h->subs3.size(); ++i) h->subs3[i].moff = (long long)i * ms;
   h->l3_vec = voff;
   const long long nsub = (long long)h->subs3.size();
@@ -1163,6 +1180,8 @@ static msp_status ensure_3d_buffers(msp_handle* h) {
   A(dalloc(&h->d_Lp3, nsub * 64 * ld));
   A(dalloc(&h->d_Rp3, nsub * 64 * ld));
   A(dalloc(&h->d_sd3, nsub * ld));
+  A(dalloc(&h->d_met3, nsub * pmax));
+  A(dalloc(&h->d_use3, nsub));
   A(dalloc(&h->d_lsol, voff));
   A(dalloc(&h->d_tk3, 4));
   if (!h->d_mask) A(dalloc(&h->d_mask, nd));
@@ -1229,8 +1248,8 @@ static void prec_3d(msp_handle* h, const double* r, double* z,
   const int t = timer_begin(h, KT_LEVEL1, s);
   launch_level1_3d(h->g, h->d_subs3, (int)h->subs3.size(), h->ld3, h->nbx3,
                    h->nby3, h->nbz3, d.sub_nel[0], d.sub_nel[1], d.sub_nel[2],
-                   h->d_A3, h->fp32 ? h->d_A3f : nullptr, h->d_mask, r, h->d_lsol,
-                   z, sc, l1 ? 1 : 0, cc, s);
+                   h->d_A3, h->fp32 ? h->d_A3f : nullptr, h->d_use3, h->d_elem, h->d_E,
+                   h->d_mask, r, h->d_lsol, z, sc, l1 ? 1 : 0, cc, s);
   timer_end(h, KT_LEVEL1, t, s);
 }
 
@@ -1524,14 +1543,31 @@ static msp_status setup_3d(msp_handle* h, hipStream_t s) {
   HIPCHK(h, hipEventCreate(&e1));
   HIPCHK(h, hipEventRecord(e0, s));
   const int nsub = (int)h->subs3.size();
-  const long long ms = (long long)h->ld3 * h->ld3;
   const int tk = timer_begin(h, KT_FACTOR, s);
-  HIPCHK(h, hipMemsetAsync(h->d_A3, 0, (size_t)nsub * ms * sizeof(double), s));
-  launch_assemble3(h->g, h->d_subs3, nsub, h->ld3, h->d_elem, h->d_E, h->d_mask,
-                   h->d_A3, s);
   HIPCHK(h, hipMemsetAsync(h->d_dropped, 0, sizeof(int), s));
-  launch_local_inverse3(h->d_A3, h->ld3, nsub, h->d_sd3, h->d_LD3, h->d_Lp3,
-                        h->d_Rp3, h->d_dropped, h->fp32 ? h->d_A3f : nullptr, s);
+  launch_level1_planes(h->g, h->d_subs3, nsub, h->pmax3l, h->ld3, h->d_elem, h->d_E,
+                       h->d_mask, h->d_A3, h->fp32 ? h->d_A3f : nullptr, h->d_sd3,
+                       h->d_LD3, h->d_Lp3, h->d_Rp3, h->d_dropped, s);
+  // the FP32 blocks of subdomains whose metric exceeds the bound are not
+  // used (the FP64 ones are applied there)
+  h->n_fp64_subs = nsub;
+  h->use64_h.assign(nsub, 1);
+  if (h->fp32) {
+    launch_level1_metric(h->g, h->d_subs3, nsub, h->pmax3l, h->ld3, h->d_A3, h->d_elem,
+                         h->d_E, h->d_mask, h->d_met3, s);
+    std::vector<double> met((size_t)nsub * h->pmax3l);
+    HIPCHK(h, hipMemcpyAsync(met.data(), h->d_met3, met.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    h->n_fp64_subs = 0;
+    for (int i = 0; i < nsub; ++i) {
+      double m = 0.0;
+      for (int k = 0; k < h->pmax3l; ++k) m = std::max(m, met[(size_t)i * h->pmax3l + k]);
+      h->use64_h[i] = (!(m <= h->fp32_metric_max)) ? 1 : 0;
+      h->n_fp64_subs += h->use64_h[i];
+    }
+    HIPCHK(h, hipMemcpyAsync(h->d_use3, h->use64_h.data(), nsub, hipMemcpyHostToDevice, s));
+  }
   timer_end(h, KT_FACTOR, tk, s);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipMemcpyAsync(h->h_int + 1, h->d_dropped, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -3426,13 +3462,16 @@ extern "C" msp_status msp_vec_dot(int64_t n, const double* x, const double* y,
 extern "C" msp_status msp_query(msp_handle* h, int64_t* q) {
   if (!h || !q) return fail(h, MSP_E_INVALID, "null argument");
   if (h->dim == 3) {
-    // first level: the dense inverses as the application reads them (n
-    // rows of n entries, rounded up to whole 16-byte loads)
-    const int vb = h->fp32 ? 4 : 8, nv = 16 / vb;
+    // first level: the plane factors as the application reads them (the
+    // forward sweep every plane's np x np inverse block, the backward sweep
+    // all but the last)
     long long maxn = 0, l1 = 0;
-    for (const Sub3& sb : h->subs3) {
+    for (size_t i = 0; i < h->subs3.size(); ++i) {
+      const Sub3& sb = h->subs3[i];
+      const int vb = (h->fp32 && !(i < h->use64_h.size() && h->use64_h[i])) ? 4 : 8;
       maxn = std::max<long long>(maxn, sb.n);
-      l1 += (long long)sb.n * ((sb.n + nv - 1) / nv * nv) * vb;
+      const long long np = 3LL * sb.nbx * sb.nby;
+      l1 += (2LL * sb.nbz - 1) * np * np * vb;
     }
     for (int k = 0; k < 12; ++k) q[k] = 0;
     q[0] = h->n_dofs;

@@ -79,13 +79,26 @@ def test_matvec3d_unclamped_rigid_motions():
     s.close()
 
 
-def test_3d_handle_refuses_the_coarse_space():
-    # the 3D preconditioner is the first level only: a description that
-    # asks for heat modes or rotations is refused at setup
-    desc, rho, fixed = _case((4, 3, 2), 31)
+def test_3d_coarse_space_refusals():
+    """The 3D coarse space needs whole-node clamps (its heat pencils remove
+    clamped nodes), takes the exact heat eigenpairs and the heat coarse
+    space only."""
     msp = _msp()
-    s = msp.Solver(desc, fixed)
+    desc = inputs.problem_desc(3, (12, 6, 6), sub_nel=6, overlap=1, eig_kmax=6)
+    rng = np.random.default_rng(32)
+    rho = rng.uniform(0.0, 1.0, inputs.n_elems(desc))
+    fixed = inputs.clamp_face_mask(desc, axis=0, side=0)
+    part = fixed.copy()
+    node = int(np.nonzero(fixed[0::3])[0][0])
+    part[3 * node + 1] = 0          # a node clamped in x only
+    s = msp.Solver(desc, part)
     s.set_densities(_dev(rho))
-    with pytest.raises(Exception, match="coarse space is not built"):
+    with pytest.raises(Exception, match="all three components"):
         s.setup()
     s.close()
+    with pytest.raises(Exception, match="randomized heat setup"):
+        s = msp.Solver(dict(desc, eig_random=5), fixed)
+        s.set_densities(_dev(rho))
+        s.setup()
+    with pytest.raises(Exception, match="heat coarse space"):
+        msp.Solver(dict(desc, coarse_kind=1), fixed)
