@@ -207,6 +207,50 @@ __device__ __forceinline__ bool k3_fixed(const Geom& g, const uint8_t* __restric
 
 constexpr int K3S_CB = 16;     // columns of a Schur-complement workgroup
 constexpr int K3S_MAXP = 256;  // largest padded plane order
+constexpr int K3S_MAXE = 1024; // largest element box (nbx+1)(nby+1)(nbz+1) staged in LDS
+
+// k3_coef with the moduli of the subdomain's element box staged in LDS:
+// El[(lz (nby+1) + ly) (nbx+1) + lx] for element (x0-1+lx, y0-1+ly, z0-1+lz)
+// (zero outside the mesh), X, Y, Z global node coordinates of the box.
+__device__ __forceinline__ double k3_coef_l(const Sub3& sb, const double* El, const double* Ke,
+                                            int X, int Y, int Z, int dx, int dy, int dz,
+                                            int ca, int cb) {
+  const int ex1 = sb.nbx + 1, ey1 = sb.nby + 1;
+  double v = 0.0;
+#pragma unroll
+  for (int sz = 0; sz < 2; ++sz) {
+    const int oz = sz + dz;
+    if (oz < 0 || oz > 1) continue;
+    const int lz = Z - sz - sb.z0 + 1;
+#pragma unroll
+    for (int sy = 0; sy < 2; ++sy) {
+      const int oy = sy + dy;
+      if (oy < 0 || oy > 1) continue;
+      const int ly = Y - sy - sb.y0 + 1;
+#pragma unroll
+      for (int sx = 0; sx < 2; ++sx) {
+        const int ox = sx + dx;
+        if (ox < 0 || ox > 1) continue;
+        const int lx = X - sx - sb.x0 + 1;
+        const int va = sx + 2 * sy + 4 * sz, vb = ox + 2 * oy + 4 * oz;
+        v += El[(lz * ey1 + ly) * ex1 + lx] * Ke[(3 * va + ca) * 24 + 3 * vb + cb];
+      }
+    }
+  }
+  return v;
+}
+
+// stage the moduli of the box's elements (and the layer around it) in LDS
+__device__ __forceinline__ void k3_stage_E(const Geom& g, const Sub3& sb,
+                                           const double* __restrict__ E, double* El, int nt) {
+  const int ex1 = sb.nbx + 1, ey1 = sb.nby + 1, ez1 = sb.nbz + 1;
+  for (int q = threadIdx.x; q < ex1 * ey1 * ez1; q += nt) {
+    const int lx = q % ex1, ly = (q / ex1) % ey1, lz = q / (ex1 * ey1);
+    const int ex = sb.x0 - 1 + lx, ey = sb.y0 - 1 + ly, ez = sb.z0 - 1 + lz;
+    const bool in = ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny && ez >= 0 && ez < g.nz;
+    El[q] = in ? E[((long long)ez * g.ny + ey) * g.nx + ex] : 0.0;
+  }
+}
 
 // Plane k of every subdomain: S_k = D_k - C_k^T G_{k-1} C_k into slot k
 // (this workgroup's K3S_CB columns as rows), identity on padding, fixed DOFs
@@ -217,6 +261,7 @@ k3s_schur(Geom g, const Sub3* __restrict__ subs, int k, int ldp,
           const double* __restrict__ Ke_g, const double* __restrict__ E,
           const uint8_t* __restrict__ mask, double* __restrict__ G) {
   __shared__ double Ke[576];
+  __shared__ double El[K3S_MAXE];
   __shared__ double T[K3S_MAXP * K3S_CB];
   __shared__ double Cb[K3S_CB * 27];
   __shared__ int Jb[K3S_CB * 27];
@@ -233,6 +278,7 @@ k3s_schur(Geom g, const Sub3* __restrict__ subs, int k, int ldp,
     }
     return;
   }
+  k3_stage_E(g, sb, E, El, T3_NT);
   __syncthreads();
   const int np = 3 * sb.nbx * sb.nby;
   const int Z = sb.z0 + k;
@@ -253,7 +299,7 @@ k3s_schur(Geom g, const Sub3* __restrict__ subs, int k, int ldp,
           j = 3 * (jy * sb.nbx + jx) + cj;
           const int X = sb.x0 + bx, Y = sb.y0 + by;
           if (!k3_fixed(g, mask, X, Y, Z, cb) && !k3_fixed(g, mask, X + dx, Y + dy, Z - 1, cj))
-            c = k3_coef(g, E, Ke, X, Y, Z, dx, dy, -1, cb, cj);
+            c = k3_coef_l(sb, El, Ke, X, Y, Z, dx, dy, -1, cb, cj);
         }
       }
       Cb[idx] = c;
@@ -292,14 +338,14 @@ k3s_schur(Geom g, const Sub3* __restrict__ subs, int k, int ldp,
       v = 0.0;
       if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 &&
           !k3_fixed(g, mask, X + dx, Y + dy, Z, cb))
-        v = k3_coef(g, E, Ke, X, Y, Z, dx, dy, 0, ca, cb);
+        v = k3_coef_l(sb, El, Ke, X, Y, Z, dx, dy, 0, ca, cb);
       if (k > 0) {
         for (int q = 0; q < 27; ++q) {
           const int nq = q / 3, ci = q - 3 * (q / 3);
           const int ix = ax + nq % 3 - 1, iy = ay + nq / 3 - 1;
           if (ix < 0 || ix >= sb.nbx || iy < 0 || iy >= sb.nby) continue;
           if (k3_fixed(g, mask, sb.x0 + ix, sb.y0 + iy, Z - 1, ci)) continue;
-          const double c = k3_coef(g, E, Ke, X, Y, Z, nq % 3 - 1, nq / 3 - 1, -1, ca, ci);
+          const double c = k3_coef_l(sb, El, Ke, X, Y, Z, nq % 3 - 1, nq / 3 - 1, -1, ca, ci);
           v -= c * T[(3 * (iy * sb.nbx + ix) + ci) * K3S_CB + t];
         }
       }
@@ -356,6 +402,7 @@ k3s_apply(Geom g, const Sub3* __restrict__ subs, int ldp, const double* __restri
           const uint8_t* __restrict__ mask, const double* __restrict__ r,
           double* __restrict__ lsol, const CGScalars* __restrict__ sc) {
   __shared__ double Ke[576];
+  __shared__ double El[K3S_MAXE];
   __shared__ double xl[LD3_MAX];
   __shared__ double rh[K3S_MAXP];
   __shared__ double ph[K3S_MAXP];
@@ -365,6 +412,7 @@ k3s_apply(Geom g, const Sub3* __restrict__ subs, int ldp, const double* __restri
   const bool f32 = G32 != nullptr && !(use64 != nullptr && use64[blockIdx.x]);
   const int tid = threadIdx.x;
   for (int q = tid; q < 576; q += K3S_NT) Ke[q] = Ke_g[q];
+  k3_stage_E(g, sb, E, El, K3S_NT);
   const int np = 3 * sb.nbx * sb.nby;
   for (int q = tid; q < sb.n; q += K3S_NT) {
     const int a = q / 3, c = q - 3 * (q / 3);
@@ -391,7 +439,7 @@ k3s_apply(Geom g, const Sub3* __restrict__ subs, int ldp, const double* __restri
       const int jx = ax + dx, jy = ay + dy;
       if (jx < 0 || jx >= sb.nbx || jy < 0 || jy >= sb.nby) continue;
       if (k3_fixed(g, mask, X + dx, Y + dy, Z + dz, cj)) continue;
-      s = fma(k3_coef(g, E, Ke, X, Y, Z, dx, dy, dz, ca, cj), xp[3 * (jy * sb.nbx + jx) + cj], s);
+      s = fma(k3_coef_l(sb, El, Ke, X, Y, Z, dx, dy, dz, ca, cj), xp[3 * (jy * sb.nbx + jx) + cj], s);
     }
     return s;
   };

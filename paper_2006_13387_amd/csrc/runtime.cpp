@@ -1150,6 +1150,9 @@ static msp_status ensure_3d_buffers(msp_handle* h) {
   }
   if (maxnp > level1_planes_max())
     return fail(h, MSP_E_INVALID, "3D subdomain plane exceeds 256 DOFs (reduce sub_nel + 2*overlap)");
+  for (const Sub3& sb : h->subs3)
+    if ((sb.nbx + 1) * (sb.nby + 1) * (sb.nbz + 1) > 1024)
+      return fail(h, MSP_E_INVALID, "3D subdomain box exceeds 1024 elements with its surrounding layer");
   {
     std::vector<uint8_t> cov((size_t)h->n_nodes, 0);
     for (const Sub3& sb : h->subs3)
