@@ -298,7 +298,9 @@ k3h_stencil(Geom g, const Nbh3* __restrict__ nbs, int ldp,
 // neighbourhood.  Thread (i, h) forms row i of the product of G_k with the
 // right-hand side held in LDS over half h of the inner index; G_k is
 // symmetric, so its row kk is read along i and a wave's loads are
-// contiguous.  The halves are added through LDS.
+// contiguous.  The halves are added through LDS.  The two row blocks R
+// and P (ldp x M each) are dynamic LDS sized by the plane order, so that
+// two workgroups fit a CU at ldp = 192, M = 24.
 template <int M>
 __global__ void __launch_bounds__(HS_NT)
 k3h_sweep(Geom g, const Nbh3* __restrict__ nbs, int ldp,
@@ -307,8 +309,9 @@ k3h_sweep(Geom g, const Nbh3* __restrict__ nbs, int ldp,
           const double* __restrict__ G, const double* __restrict__ B,
           double* __restrict__ Yw, const Eig3State* __restrict__ st) {
   __shared__ double el[64];
-  __shared__ double R[C3_MAXP * M];
-  __shared__ double P[C3_MAXP * M];
+  extern __shared__ double sweep_lds[];
+  double* R = sweep_lds;
+  double* P = sweep_lds + ldp * M;
   if (st[blockIdx.x].done) return;
   const Nbh3 w = nbs[blockIdx.x];
   const int tid = threadIdx.x;
@@ -1007,7 +1010,15 @@ static void heat3_step_m(const Geom& g, const Nbh3* nbs, int nnb, int pmax, int 
   // T = M X; Y = (A + sigma M)^{-1} T; T = A Y, U = M Y; Gram; RR; X = Y V
   hipLaunchKernelGGL((k3h_stencil<M, false>), dim3(pmax, nnb), dim3(C3_NT), 0, s, g,
                      nbs, ldp, E, nmask, hel, X, nullptr, T, st);
-  hipLaunchKernelGGL((k3h_sweep<M>), dim3(nnb), dim3(HS_NT), 0, s, g, nbs, ldp, E,
+  const size_t lds = 2ull * ldp * M * sizeof(double);
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k3h_sweep<M>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(2ull * C3_MAXP * M * sizeof(double)));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k3h_sweep<M>), dim3(nnb), dim3(HS_NT), lds, s, g, nbs, ldp, E,
                      nmask, hel, sigma, G, T, Y, st);
   hipLaunchKernelGGL((k3h_stencil<M, true>), dim3(pmax, nnb), dim3(C3_NT), 0, s, g,
                      nbs, ldp, E, nmask, hel, Y, T, U, st);
