@@ -215,7 +215,7 @@ def solve3d_workload(torch):
     and one on the FP64 path, each the full setup (first-level inverses,
     heat eigenproblems, coarse basis, K_0 and its generalised inverse) and
     the PCG to relres 1e-8; the first-level application and the coarse
-    restriction with its K_0^+ product are event-timed."""
+    restriction with the slab solve of K_0 are event-timed."""
     import inputs
     import numpy as np
     import paper_2006_13387_amd as msp
@@ -256,17 +256,16 @@ def solve3d_workload(torch):
             l1_ms = t / max(c, 1)
             gbs = l1_b / (l1_ms * 1e-3) / 1e9
             cr, tr = kt["coarse_restrict"]
-            rec["level1_roofline"] = {"kernel": "k3_level1<float> + k3_level1_sum",
+            rec["level1_roofline"] = {"kernel": "k3s_apply (FP32 plane factors) + k3_level1_sum",
                                       "bound": "hbm", "bytes_per_launch": int(l1_b),
                                       "avg_launch_ms": round(l1_ms, 5),
                                       "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                                       "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                                       "launches": int(c)}
-            # restriction + K_0^+ c: the padded generalised inverse is read once
-            k0_b = 8 * q["ldk"] * q["ldk"]
-            rec["coarse_apply"] = {"kernels": "k3c_restrict + k3c_gemv",
-                                   "avg_launch_ms": round(tr / max(cr, 1), 5),
-                                   "k0_inverse_bytes": int(k0_b)}
+            # restriction + the slab solve with K_0's block LDL^T factors
+            rec["coarse_apply"] = {"kernels": "k3c_restrict + k3c_slab_step (forward and "
+                                              "backward over the slabs of coarse nodes)",
+                                   "avg_launch_ms": round(tr / max(cr, 1), 5)}
             out["fp32_local"] = rec
         else:
             out["fp64"] = rec
@@ -530,7 +529,7 @@ def kernel_probe(torch):
         l1[f"{e:g}"] = int(level1_bytes(s.query()))
         s.close()
     mv = matvec_probe(torch, launches=10)
-    # 3D first level on the 96 x 48 x 48 workload (FP32 inverses, 4.4 GB):
+    # 3D first level on the 96 x 48 x 48 workload (FP32 plane factors):
     # 5 applications
     p3 = inputs.config(2)
     s3 = msp.Solver(dict(p3.desc, eig_kmax=0, rot_enrich=0), p3.fixed)
