@@ -494,6 +494,52 @@ def elasticity_modes(K, M, count, H):
     return lam[:sel], v, lam[: sel + 1]
 
 
+def elasticity_modes_randomized(K, M, count, H, nsnap, seed, l, pos, R):
+    """The randomized algorithm of Section 3 on the elasticity pencil
+    (M_EE;Rand): nsnap uniform random forcings f_j (values at the box-local
+    DOF positions ``pos``), each made free of net force (zero M-weighted mean
+    of every displacement component: f_j M-orthogonal to the translations,
+    the first dim columns of R), local solutions u_j of the shifted pencil,
+    the space W = span{u_j} + span{R} (R the rigid-body motions on the
+    pencil's DOFs), an M-orthonormal basis Q of W (directions below 1e-13
+    of the largest dropped), the reduced pencil Q^T K Q, and its ``count``
+    lowest Ritz pairs, ascending; also returns the next Ritz value."""
+    n = K.shape[0]
+    if count == 0 or n == 0:
+        return np.zeros(0), np.zeros((n, 0)), np.zeros(0)
+    dim = 2 if R.shape[1] == 3 else 3       # R: 3 motions in 2D, 6 in 3D
+    F = np.stack([forcing_uniform(seed, l, j, pos) for j in range(nsnap)], axis=1)
+    T = R[:, :dim]
+    MT = M @ T
+    F = F - T @ np.linalg.solve(T.T @ MT, MT.T @ F)
+    C = (K + (RAND_SHIFT / (H * H)) * M).tocsc()
+    U = spla.splu(C).solve(np.asarray(M @ F))
+    U = np.hstack([U, R])
+    G = U.T @ (M @ U)
+    g, V = np.linalg.eigh(0.5 * (G + G.T))
+    keep = g > 1e-13 * g[-1]
+    Q = (U @ V[:, keep]) / np.sqrt(g[keep])[None, :]
+    Kr = Q.T @ (K @ Q)
+    lam, phi = np.linalg.eigh(0.5 * (Kr + Kr.T))
+    vec = Q @ phi
+    sel = min(count, len(lam))
+    return lam[:sel], vec[:, :sel], lam[:sel + 1]
+
+
+def rigid_body_motions(desc, c, node_flat, dofs, node_pos):
+    """The rigid-body motions on the DOFs ``dofs`` (global ids dim * node +
+    component) of omega_l: the dim translations, then the infinitesimal
+    rotations about coarse node ``c`` scaled by 1/H; ``node_pos`` maps each
+    DOF to its node's index in the box arrays ``node_flat``."""
+    dim = desc["dim"]
+    comp = np.asarray(dofs) % dim
+    rows = np.asarray(node_pos)
+    cols = [(comp == d).astype(np.float64) for d in range(dim)]
+    for r in _rotations(desc, c, node_flat):
+        cols.append(r[rows, comp])
+    return np.stack(cols, axis=1)
+
+
 def build_coarse_basis_ee(desc, E, fixed):
     """R_0^T of M_EE (Section 2.1): per coarse node the lowest eigenpairs of
     the elasticity pencil on omega_l times chi_l.
@@ -503,8 +549,11 @@ def build_coarse_basis_ee(desc, E, fixed):
     per region); the number of such regions is what the heat threshold of
     Section 4.1 counts on the same neighbourhood, so n_l = d(d+1)/2 times
     the heat modes selected there (desc["coarse_kind"] = 2: twice that, the
-    "twice many eigenvectors" rows of the tables).  Column order: coarse
-    nodes x-fastest, per node its modes in ascending eigenvalue order.
+    "twice many eigenvectors" rows of the tables).  With desc["eig_random"]
+    = M > 0 the elasticity eigenpairs are the randomized approximations of
+    Section 3 from M snapshots and the rigid-body motions (M_EE;Rand); the
+    heat count stays exact.  Column order: coarse nodes x-fastest, per node
+    its modes in ascending eigenvalue order.
     """
     dim = desc["dim"]
     H = coarse_H(desc)
@@ -529,11 +578,18 @@ def build_coarse_basis_ee(desc, E, fixed):
         cap_hits += int(hm.cap_hit)
         count = mult * per_region * len(hm.lam)
         K, M, dofs = elasticity_pencil(desc, E, c, fixed)
-        lam, vec, lam_seen = elasticity_modes(K, M, count, H)
+        pos = {int(g): i for i, g in enumerate(node_ids)}
+        if desc.get("eig_random", 0) > 0:
+            npos = np.array([pos[int(d) // dim] for d in dofs], dtype=np.int64)
+            R = rigid_body_motions(desc, c, flat, dofs, npos)
+            lam, vec, lam_seen = elasticity_modes_randomized(
+                K, M, count, H, desc["eig_random"], desc.get("eig_seed", 0), li,
+                dim * npos + dofs % dim, R)
+        else:
+            lam, vec, lam_seen = elasticity_modes(K, M, count, H)
         n_modes[li, :] = len(lam)
         eigvals.append([lam] * dim)
         seen.append([lam_seen] * dim)
-        pos = {int(g): i for i, g in enumerate(node_ids)}
         chi_d = chi[np.array([pos[int(d) // dim] for d in dofs], dtype=np.int64)]
         for j in range(vec.shape[1]):
             v = chi_d * vec[:, j]
