@@ -494,6 +494,15 @@ def elasticity_modes(K, M, count, H):
     return lam[:sel], v, lam[: sel + 1]
 
 
+def _m_orthonormal(U, M):
+    """An M-orthonormal basis of span(U) from the eigendecomposition of the
+    Gram matrix U^T M U (directions below 1e-13 of the largest dropped)."""
+    G = U.T @ (M @ U)
+    g, V = np.linalg.eigh(0.5 * (G + G.T))
+    keep = g > 1e-13 * g[-1]
+    return (U @ V[:, keep]) / np.sqrt(g[keep])[None, :]
+
+
 def elasticity_modes_randomized(K, M, count, H, nsnap, seed, l, pos, R):
     """The randomized algorithm of Section 3 on the elasticity pencil
     (M_EE;Rand): nsnap uniform random forcings f_j (values at the box-local
@@ -501,9 +510,10 @@ def elasticity_modes_randomized(K, M, count, H, nsnap, seed, l, pos, R):
     of every displacement component: f_j M-orthogonal to the translations,
     the first dim columns of R), local solutions u_j of the shifted pencil,
     the space W = span{u_j} + span{R} (R the rigid-body motions on the
-    pencil's DOFs), an M-orthonormal basis Q of W (directions below 1e-13
-    of the largest dropped), the reduced pencil Q^T K Q, and its ``count``
-    lowest Ritz pairs, ascending; also returns the next Ritz value."""
+    pencil's DOFs) with the basis Section 3 describes (the singular
+    directions of the snapshot matrix, enriched with the rigid-body
+    motions), the reduced pencil Q^T K Q, and its ``count`` lowest Ritz
+    pairs, ascending; also returns the next Ritz value."""
     n = K.shape[0]
     if count == 0 or n == 0:
         return np.zeros(0), np.zeros((n, 0)), np.zeros(0)
@@ -514,11 +524,13 @@ def elasticity_modes_randomized(K, M, count, H, nsnap, seed, l, pos, R):
     F = F - T @ np.linalg.solve(T.T @ MT, MT.T @ F)
     C = (K + (RAND_SHIFT / (H * H)) * M).tocsc()
     U = spla.splu(C).solve(np.asarray(M @ F))
-    U = np.hstack([U, R])
-    G = U.T @ (M @ U)
-    g, V = np.linalg.eigh(0.5 * (G + G.T))
-    keep = g > 1e-13 * g[-1]
-    Q = (U @ V[:, keep]) / np.sqrt(g[keep])[None, :]
+    # the SVD of the snapshot matrix (in the M inner product): its
+    # M-orthonormal left singular directions, those below 1e-13 of the
+    # largest dropped; then enriched with the rigid-body motions (each of
+    # unit M-norm) and orthonormalised once more
+    Qs = _m_orthonormal(U, M)
+    Rn = R / np.sqrt(np.einsum("ij,ij->j", R, M @ R))[None, :]
+    Q = _m_orthonormal(np.hstack([Qs, Rn]), M)
     Kr = Q.T @ (K @ Q)
     lam, phi = np.linalg.eigh(0.5 * (Kr + Kr.T))
     vec = Q @ phi

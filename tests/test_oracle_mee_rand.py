@@ -8,7 +8,8 @@ to the elasticity pencils of Section 2.1; Table 1, M_EE;Rand):
   (Poincare separation) and equal them when the snapshots and motions span
   the whole space; on a floating neighbourhood the three lowest Ritz
   values are the exact zero eigenvalues and their vectors span the
-  rigid-body motions;
+  rigid-body motions, also at contrast 1e6, where the snapshots are
+  dominated by a few near-rigid modes of stiff bars in void;
 * Table 2 (contrast 1): with 10 and 15 snapshots the coarse dimension is
   the paper's 243, the iteration count lies between the exact M_EE's and
   the paper's 20, and the condition estimate within the band the exact
@@ -85,3 +86,30 @@ def test_table2_mee_randomized_rows():
         assert h.coarse.Phi.shape[1] == 243
         assert exact.iters <= info.iters <= 20
         assert 0.75 * 9.4 <= info.cond_est <= 1.5 * 9.4
+
+
+def test_rigid_body_motions_survive_high_contrast():
+    # a floating neighbourhood of the 64 x 32 cantilever at Emin 1e-6 (the
+    # free right end, stiff bars in void): the snapshots are dominated by a
+    # few near-rigid modes of the bars, yet the three exact zeros of the
+    # rigid-body motions must stay among the Ritz values, and the Ritz
+    # values still bound the exact eigenvalues from above
+    c0 = inputs.config(0)
+    desc = c0.desc
+    E = oracle.simp_modulus(c0.rho, desc["E0"], desc["Emin"], desc["penal"])
+    nodes = dd.coarse_node_grid(desc)
+    li = 4
+    c = nodes[li]
+    K, M, dofs = dd.elasticity_pencil(desc, E, c, c0.fixed)
+    assert len(dofs) == 2 * (desc["sub_nel"][0] + 1) * (desc["sub_nel"][1] + 1)
+    _, nbox = dd.neighbourhood(desc, c)
+    ids, flat = dd._node_ids_of_box(desc, nbox)
+    pos = {int(g): i for i, g in enumerate(ids)}
+    npos = np.array([pos[int(d) // 2] for d in dofs], dtype=np.int64)
+    R = dd.rigid_body_motions(desc, c, flat, dofs, npos)
+    lam_ex = sla.eigh(K.toarray(), M.toarray(), eigvals_only=True)
+    lam, _, seen = dd.elasticity_modes_randomized(K, M, 6, dd.coarse_H(desc), 12, 3, li,
+                                                  2 * npos + dofs % 2, R)
+    assert np.all(np.abs(lam[:3]) <= 1e-12 * lam_ex[-1])
+    assert lam[3] > 1e3 * np.max(np.abs(lam[:3]))
+    assert np.all(seen >= lam_ex[:len(seen)] - 1e-12 * lam_ex[-1])
