@@ -74,7 +74,11 @@ typedef enum {
  *             convergence; M in 1..31: the randomized approximation of
  *             Section 3 (M_EH+Rot;Rand) from M zero-mean random forcings,
  *             their local solutions with A + 0.05/H^2 M and the constant
- *             function, by Rayleigh-Ritz on that space
+ *             function, by Rayleigh-Ritz on that space.  With coarse_kind
+ *             1 or 2 (M in 1..29) it applies to the elasticity pencils
+ *             instead (M_EE;Rand): M random forcings free of net force,
+ *             their solutions with K + 0.05/H^2 M, the rigid-body motions
+ *             added, one Rayleigh-Ritz step; the heat count stays exact
  *  eig_seed   seed of the randomized forcings (SplitMix64, counter-based)
  *  coarse_kind 0: the heat coarse space (M_EH, M_EH+Rot; Section 4);
  *             1: M_EE (Section 2.1, 2D only): per coarse neighbourhood the

@@ -1046,13 +1046,15 @@ void launch_heat3_step(int m, const Geom& g, const Nbh3* nbs, int nnb, int pmax,
 // The Rayleigh-Ritz part of a sweep on row-blocked pencils of any kind:
 // Gram matrices of Y with A Y (in T) and M Y (in U), the small
 // eigenproblem, X = Y V.
+// The first mrr columns take part in the small eigenproblem (mrr < M: the
+// rest are zero and their coefficients must be zero too).
 template <int M>
 static void plane_rr_m(const Nbh3* nbs, int nnb, int pmax, int ldp, const double* Y,
                        const double* T, const double* U, double* X, Eig3State* st,
                        int kmax, double lim, double scale, double tol, int first,
-                       int* err, hipStream_t s) {
+                       int* err, hipStream_t s, int mrr = M) {
   hipLaunchKernelGGL((k3h_gram<M>), dim3(nnb), dim3(HS_NT), 0, s, nbs, ldp, Y, T, U, st);
-  hipLaunchKernelGGL(k3h_rr, dim3(nnb), dim3(HS_NT), 0, s, M, kmax, lim, scale, tol,
+  hipLaunchKernelGGL(k3h_rr, dim3(nnb), dim3(HS_NT), 0, s, mrr, kmax, lim, scale, tol,
                      first, st, err);
   hipLaunchKernelGGL((k3h_ritz<M>), dim3(pmax, nnb), dim3(C3_NT), 0, s, nbs, ldp, Y,
                      X, st);
@@ -1068,6 +1070,22 @@ void launch_plane_rr(int m, const Nbh3* nbs, int nnb, int pmax, int ldp, const d
     case 16: plane_rr_m<16>(nbs, nnb, pmax, ldp, Y, T, U, X, es, kmax, lim, scale, tol, first, err, s); break;
     case 24: plane_rr_m<24>(nbs, nnb, pmax, ldp, Y, T, U, X, es, kmax, lim, scale, tol, first, err, s); break;
     default: plane_rr_m<32>(nbs, nnb, pmax, ldp, Y, T, U, X, es, kmax, lim, scale, tol, first, err, s); break;
+  }
+}
+
+// One Rayleigh-Ritz step on the first mrr of m stored columns (the
+// randomized setup: snapshots and rigid-body motions, zero columns after
+// them, zero coefficients there from the start kernel).
+void launch_plane_rr_live(int m, int mrr, const Nbh3* nbs, int nnb, int pmax, int ldp,
+                          const double* Y, const double* T, const double* U, double* X,
+                          void* st, int kmax, double lim, double scale, int* err,
+                          hipStream_t s) {
+  Eig3State* es = (Eig3State*)st;
+  switch (m) {
+    case 8: plane_rr_m<8>(nbs, nnb, pmax, ldp, Y, T, U, X, es, kmax, lim, scale, 0.0, 1, err, s, mrr); break;
+    case 16: plane_rr_m<16>(nbs, nnb, pmax, ldp, Y, T, U, X, es, kmax, lim, scale, 0.0, 1, err, s, mrr); break;
+    case 24: plane_rr_m<24>(nbs, nnb, pmax, ldp, Y, T, U, X, es, kmax, lim, scale, 0.0, 1, err, s, mrr); break;
+    default: plane_rr_m<32>(nbs, nnb, pmax, ldp, Y, T, U, X, es, kmax, lim, scale, 0.0, 1, err, s, mrr); break;
   }
 }
 

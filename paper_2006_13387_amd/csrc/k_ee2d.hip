@@ -195,6 +195,114 @@ k2e_start(Geom g, const Nbh3* __restrict__ nbs, int ldp, int m,
   }
 }
 
+// Randomized start (Section 3 on the elasticity pencil, M_EE;Rand): columns
+// 0..nsnap-1 uniform forcings in [-1, 1) (SplitMix64 output at the state
+// key ^ (seed * gamma), key = l 2^40 + j 2^24 + u: l the neighbourhood, j
+// the snapshot, u = 2 (box node, x fastest) + component the unknown's index
+// in the box), zero on clamped DOFs, each made free of net force: per
+// component c, f_j -= (w_c . f_j) / (w_c . 1_c) with w_c = M 1_c over the
+// free DOFs; columns nsnap..nsnap+2 the rigid-body motions (the two
+// translations, the rotation about the coarse node scaled by 1/H), zero on
+// clamped DOFs; the remaining columns and the padding zero.  Also zeroes
+// the Rayleigh-Ritz coefficients, so that the columns past the live ones
+// stay zero.  T's first column holds w as scratch.  One workgroup per
+// neighbourhood.
+__global__ void __launch_bounds__(E2_NT)
+k2e_rand_start(Geom g, const Nbh3* __restrict__ nbs, int pmax, int ldp, int m, int nsnap,
+               unsigned int seed, double invH, const double* __restrict__ E,
+               const uint8_t* __restrict__ mask, const double* __restrict__ Ke_g,
+               const double* __restrict__ Ms_g, double* __restrict__ X,
+               double* __restrict__ T, Eig3State* __restrict__ st) {
+  __shared__ double Ke[64], Ms[16];
+  __shared__ double red[2 * (E2_NT / 64)];
+  const Nbh3 w = nbs[blockIdx.x];
+  const int tid = threadIdx.x;
+  if (tid < 64) Ke[tid] = Ke_g[tid];
+  if (tid < 16) Ms[tid] = Ms_g[tid];
+  Eig3State& es = st[blockIdx.x];
+  for (int e = tid; e < MAXM * MAXM; e += E2_NT) es.V[e] = 0.0;
+  for (int idx = tid; idx < pmax * ldp; idx += E2_NT) {
+    const int k = idx / ldp, a = idx - (idx / ldp) * ldp;
+    double* row = X + w.xoff + (long long)idx * m;
+    if (k < w.nbz && a < w.np) {
+      for (int c = nsnap + 3; c < m; ++c) row[c] = 0.0;
+    } else {
+      for (int c = 0; c < m; ++c) row[c] = 0.0;
+    }
+  }
+  __syncthreads();
+  const int nu = w.nbz * w.np;
+  double w0 = 0.0, w1 = 0.0;
+  for (int u = tid; u < nu; u += E2_NT) {
+    const int k = u / w.np, a = u - (u / w.np) * w.np;
+    const int ax = a >> 1, ca = a & 1;
+    const int Xn = w.x0 + ax, Yn = w.y0 + k;
+    const bool live = !e2_fixed(g, mask, Xn, Yn, ca);
+    double wi = 0.0;
+    if (live) {
+      for (int dy = -1; dy <= 1; ++dy) {
+        if (k + dy < 0 || k + dy >= w.nbz) continue;
+        for (int dx = -1; dx <= 1; ++dx) {
+          if (ax + dx < 0 || ax + dx >= w.nbx) continue;
+          if (e2_fixed(g, mask, Xn + dx, Yn + dy, ca)) continue;
+          double cK, cM;
+          (void)e2_coef(g, w, E, Ke, Ms, 0.0, Xn, Yn, dx, dy, ca, ca, &cK, &cM);
+          wi += cM;
+        }
+      }
+    }
+    double* row = X + w.xoff + ((long long)k * ldp + a) * m;
+    T[w.xoff + ((long long)k * ldp + a) * m] = wi;
+    if (ca) w1 += wi; else w0 += wi;
+    const double rx = (double)(Xn - w.cx * g.sx) * g.h * invH;
+    const double ry = (double)(Yn - w.cy * g.sy) * g.h * invH;
+    row[nsnap] = (live && ca == 0) ? 1.0 : 0.0;
+    row[nsnap + 1] = (live && ca == 1) ? 1.0 : 0.0;
+    row[nsnap + 2] = live ? (ca == 0 ? -ry : rx) : 0.0;
+  }
+  const double2 W = block_sum2<E2_NT>(w0, w1, red);
+  const unsigned long long sg = (unsigned long long)seed * 0x9E3779B97F4A7C15ull;
+  for (int j = 0; j < nsnap; ++j) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int u = tid; u < nu; u += E2_NT) {
+      const int k = u / w.np, a = u - (u / w.np) * w.np;
+      const int ca = a & 1;
+      const long long o = w.xoff + ((long long)k * ldp + a) * m;
+      double f = 0.0;
+      if (!e2_fixed(g, mask, w.x0 + (a >> 1), w.y0 + k, ca)) {
+        const unsigned long long key = ((unsigned long long)blockIdx.x << 40) |
+                                       ((unsigned long long)j << 24) |
+                                       (unsigned long long)u;
+        f = hash_unit(key ^ sg);
+      }
+      X[o + j] = f;
+      const double wf = T[o] * f;
+      if (ca) s1 += wf; else s0 += wf;
+    }
+    const double2 S = block_sum2<E2_NT>(s0, s1, red);
+    const double m0 = W.x > 0.0 ? S.x / W.x : 0.0;
+    const double m1 = W.y > 0.0 ? S.y / W.y : 0.0;
+    for (int u = tid; u < nu; u += E2_NT) {
+      const int k = u / w.np, a = u - (u / w.np) * w.np;
+      const int ca = a & 1;
+      if (e2_fixed(g, mask, w.x0 + (a >> 1), w.y0 + k, ca)) continue;
+      X[w.xoff + ((long long)k * ldp + a) * m + j] -= ca ? m1 : m0;
+    }
+  }
+}
+
+// Y's columns [c0, c1) := X's on every row of the box (rows past the
+// neighbourhood included).  Grid (rows, neighbourhoods).
+__global__ void __launch_bounds__(E2_NT)
+k2e_copy_cols(const Nbh3* __restrict__ nbs, int ldp, int m, int c0, int c1,
+              const double* __restrict__ X, double* __restrict__ Y) {
+  const Nbh3 w = nbs[blockIdx.y];
+  const int a = threadIdx.x;
+  if (a >= ldp) return;
+  const long long o = w.xoff + ((long long)blockIdx.x * ldp + a) * m;
+  for (int c = c0; c < c1; ++c) Y[o + c] = X[o + c];
+}
+
 // OutM = M Y, and with BOTH also OutK = K Y, on row k of every unfinished
 // neighbourhood (the 9 neighbouring nodes, both components; clamped DOFs:
 // zero rows).
@@ -516,6 +624,43 @@ void launch_ee2_products(int m, const Geom& g, const Nbh3* nbs, int nnb, int pma
     case 16: ee2_products_m<16>(g, nbs, nnb, pmax, ldp, E, mask, Ke, Ms, sigma, G, X, Y, T, U, es, s); break;
     case 24: ee2_products_m<24>(g, nbs, nnb, pmax, ldp, E, mask, Ke, Ms, sigma, G, X, Y, T, U, es, s); break;
     default: ee2_products_m<32>(g, nbs, nnb, pmax, ldp, E, mask, Ke, Ms, sigma, G, X, Y, T, U, es, s); break;
+  }
+}
+
+// The randomized setup's products: the start block (forcings made free of
+// net force, the rigid-body motions), T = M X, Y = (K + sigma M)^{-1} T on
+// every column, the motions copied back over their solved columns (W =
+// span{u_j} + span{rigid-body motions}), then T = K Y and U = M Y for the
+// Rayleigh-Ritz step on the nsnap + 3 live columns.
+template <int M>
+static void ee2_rand_m(const Geom& g, const Nbh3* nbs, int nnb, int pmax, int ldp,
+                       int nsnap, unsigned int seed, double invH, const double* E,
+                       const uint8_t* mask, const double* Ke, const double* Ms,
+                       double sigma, const double* G, double* X, double* Y, double* T,
+                       double* U, Eig3State* st, hipStream_t s) {
+  hipLaunchKernelGGL(k2e_rand_start, dim3(nnb), dim3(E2_NT), 0, s, g, nbs, pmax, ldp, M,
+                     nsnap, seed, invH, E, mask, Ke, Ms, X, T, st);
+  hipLaunchKernelGGL((k2e_stencil<M, false>), dim3(pmax, nnb), dim3(E2_NT), 0, s, g, nbs,
+                     ldp, E, mask, Ke, Ms, X, (double*)nullptr, T, st);
+  hipLaunchKernelGGL((k2e_sweep<M>), dim3(nnb), dim3(E2_SW), 0, s, g, nbs, ldp, E, mask,
+                     Ke, Ms, sigma, G, T, Y, st);
+  hipLaunchKernelGGL(k2e_copy_cols, dim3(pmax, nnb), dim3(E2_NT), 0, s, nbs, ldp, M,
+                     nsnap, nsnap + 3, X, Y);
+  hipLaunchKernelGGL((k2e_stencil<M, true>), dim3(pmax, nnb), dim3(E2_NT), 0, s, g, nbs,
+                     ldp, E, mask, Ke, Ms, Y, T, U, st);
+}
+
+void launch_ee2_rand(int m, int nsnap, unsigned int seed, double invH, const Geom& g,
+                     const Nbh3* nbs, int nnb, int pmax, int ldp, const double* E,
+                     const uint8_t* mask, const double* Ke, const double* Ms, double sigma,
+                     const double* G, double* X, double* Y, double* T, double* U, void* st,
+                     hipStream_t s) {
+  Eig3State* es = (Eig3State*)st;
+  switch (m) {
+    case 8: ee2_rand_m<8>(g, nbs, nnb, pmax, ldp, nsnap, seed, invH, E, mask, Ke, Ms, sigma, G, X, Y, T, U, es, s); break;
+    case 16: ee2_rand_m<16>(g, nbs, nnb, pmax, ldp, nsnap, seed, invH, E, mask, Ke, Ms, sigma, G, X, Y, T, U, es, s); break;
+    case 24: ee2_rand_m<24>(g, nbs, nnb, pmax, ldp, nsnap, seed, invH, E, mask, Ke, Ms, sigma, G, X, Y, T, U, es, s); break;
+    default: ee2_rand_m<32>(g, nbs, nnb, pmax, ldp, nsnap, seed, invH, E, mask, Ke, Ms, sigma, G, X, Y, T, U, es, s); break;
   }
 }
 

@@ -149,6 +149,9 @@ void launch_coarse3_restrict(const Geom&, const Nbh3*, int, int, int, int, doubl
 void launch_plane_rr(int, const Nbh3*, int, int, int, const double*, const double*,
                      const double*, double*, void*, int, double, double, double, int,
                      int*, hipStream_t);
+void launch_plane_rr_live(int, int, const Nbh3*, int, int, int, const double*,
+                          const double*, const double*, double*, void*, int, double,
+                          double, int*, hipStream_t);
 void launch_plane_reset(void*, int, hipStream_t);
 void launch_plane_select_count(const void*, int, int, const int*, int, int*, double*,
                                hipStream_t);
@@ -163,6 +166,10 @@ void launch_ee2_products(int, const Geom&, const Nbh3*, int, int, int, const dou
                          const uint8_t*, const double*, const double*, double,
                          const double*, const double*, double*, double*, double*,
                          const void*, hipStream_t);
+void launch_ee2_rand(int, int, unsigned int, double, const Geom&, const Nbh3*, int, int,
+                     int, const double*, const uint8_t*, const double*, const double*,
+                     double, const double*, double*, double*, double*, double*, void*,
+                     hipStream_t);
 void launch_ee2_basis(const Geom&, const Nbh3*, const int*, int, const uint8_t*,
                       const double*, double*, hipStream_t);
 void launch_ee2_k0(const double*, const double*, long long, int, double*, int,
@@ -577,7 +584,7 @@ msp_status build_geometry(msp_handle* h) {
     for (const SysDesc& o : h->omegas) maxw = std::max(maxw, o.nxb);
     // randomized: the snapshots and the constant function; else kmax plus
     // guard vectors for the subspace iteration
-    int m = h->desc.eig_random > 0 ? h->desc.eig_random + 1
+    int m = (h->desc.eig_random > 0 && h->desc.coarse_kind == 0) ? h->desc.eig_random + 1
                                    : std::min(h->desc.eig_kmax + kEigExtra, MAXM);
     while (m > h->desc.eig_kmax + 2 && !eig_fits_host(maxw, m)) --m;
     if (!eig_fits_host(maxw, m))
@@ -820,8 +827,9 @@ extern "C" msp_status msp_create(const msp_problem_desc* d,
     return fail(nullptr, MSP_E_INVALID, "precision must be 0 or 1");
   if (d->coarse_kind < 0 || d->coarse_kind > 2)
     return fail(nullptr, MSP_E_INVALID, "coarse_kind must be 0, 1 or 2");
-  if (d->coarse_kind != 0 && d->eig_random != 0)
-    return fail(nullptr, MSP_E_INVALID, "M_EE takes the exact eigenpairs (eig_random = 0)");
+  if (d->coarse_kind != 0 && d->eig_random > MAXM - 3)
+    return fail(nullptr, MSP_E_INVALID,
+                "M_EE;Rand: eig_random must lie in 0..29 (snapshots and three rigid-body motions)");
 
   msp_handle* h = new msp_handle();
   h->desc = *d;
@@ -1633,7 +1641,11 @@ static msp_status setup_ee(msp_handle* h, const std::vector<int>& cap, hipStream
   }
   if (maxw > 24)
     return fail(h, MSP_E_INVALID, "M_EE: more than 24 modes in a neighbourhood (reduce eig_kmax)");
-  const int m = std::max(8, ((maxw + 8 + 7) / 8) * 8);
+  // randomized (M_EE;Rand): the snapshots and the three rigid-body motions
+  // are the live columns; else the wanted modes plus guard vectors
+  const int nsnap = d.eig_random;
+  const int mlive = nsnap > 0 ? nsnap + 3 : 0;
+  const int m = nsnap > 0 ? ((mlive + 7) / 8) * 8 : std::max(8, ((maxw + 8 + 7) / 8) * 8);
   if (h->d_nbe == nullptr) {
     h->nbe_h.assign(ncn, Nbh3{});
     int pmax = 0, maxnp = 0;
@@ -1697,9 +1709,20 @@ static msp_status setup_ee(msp_handle* h, const std::vector<int>& cap, hipStream
   launch_ee2_factor(g, h->d_nbe, ncn, pmax, ldp, h->d_E, h->d_mask, Ke, Ms, sigma, h->d_Ge,
                     h->d_hsde, h->d_hLDe, h->d_hLpe, h->d_hRpe, h->d_dropped, s);
   launch_plane_reset(h->d_este, ncn, s);
-  launch_ee2_start(g, h->d_nbe, ncn, pmax, ldp, m, h->d_mask, h->d_Xe, s);
   int unconv = ncn;
-  for (int it = 0; it < kEig3MaxIt; ++it) {
+  if (nsnap > 0) {
+    // Section 3: one solve per snapshot, one Rayleigh-Ritz step
+    launch_ee2_rand(m, nsnap, (unsigned int)d.eig_seed, 1.0 / h->H, g, h->d_nbe, ncn, pmax,
+                    ldp, h->d_E, h->d_mask, Ke, Ms, sigma, h->d_Ge, h->d_Xe, h->d_Ye,
+                    h->d_Te, h->d_Ue, h->d_este, s);
+    launch_plane_rr_live(m, mlive, h->d_nbe, ncn, pmax, ldp, h->d_Ye, h->d_Te, h->d_Ue,
+                         h->d_Xe, h->d_este, maxw, 1e300, d.eig_tau / (h->H * h->H),
+                         h->d_err, s);
+    unconv = 0;
+  } else {
+    launch_ee2_start(g, h->d_nbe, ncn, pmax, ldp, m, h->d_mask, h->d_Xe, s);
+  }
+  for (int it = 0; nsnap == 0 && it < kEig3MaxIt; ++it) {
     launch_ee2_products(m, g, h->d_nbe, ncn, pmax, ldp, h->d_E, h->d_mask, Ke, Ms, sigma,
                         h->d_Ge, h->d_Xe, h->d_Ye, h->d_Te, h->d_Ue, h->d_este, s);
     // selection by count: the test watches the first maxw + 1 Ritz values,
@@ -1717,8 +1740,8 @@ static msp_status setup_ee(msp_handle* h, const std::vector<int>& cap, hipStream
       if (unconv == 0) break;
     }
   }
-  launch_plane_select_count(h->d_este, ncn, m, h->d_wante, d.eig_kmax, h->d_nsele,
-                            h->d_lame, s);
+  launch_plane_select_count(h->d_este, ncn, nsnap > 0 ? mlive : m, h->d_wante, d.eig_kmax,
+                            h->d_nsele, h->d_lame, s);
   timer_end(h, KT_EIGEN, tk, s);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipMemcpyAsync(h->h_int, h->d_err, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1829,7 +1852,7 @@ extern "C" msp_status msp_setup(msp_handle* h, hipStream_t s) {
       h->desc.eig_tau / (h->H * h->H), kEigTol, h->d_eig_state,
       (int*)h->d_cnt + 4, h->h_int + 8, h->d_psi, h->d_psi32, h->d_lam,
       h->d_nsel, h->d_cap, h->d_err, h->d_om_pack, h->om_npack,
-      h->desc.eig_random, (unsigned int)h->desc.eig_seed, s);
+      h->desc.coarse_kind == 0 ? h->desc.eig_random : 0, (unsigned int)h->desc.eig_seed, s);
   timer_end(h, KT_EIGEN, tk, s);
   if (unconv < 0) {
     h->setup_ok = false;
