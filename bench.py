@@ -366,21 +366,27 @@ def batch_workload(torch, args):
 
 
 def serving_workload(torch, args):
-    """Poisson stream of state + adjoint requests from concurrent 2D runs
-    (256x128 .. 1024x512 Q1, Emin 1e-6 / 1e-9, FP32 local solves): each
-    request perturbs its run's densities (setup rebuilt) and warm-starts
-    from the run's previous solutions."""
+    """Poisson stream of state + adjoint requests from concurrent runs, 2D
+    (256x128 .. 1024x512 Q1) and, for a quarter of them, 3D (48x24x24 ..
+    96x48x48 H8), Emin 1e-6 / 1e-9, FP32 local solves: each request
+    perturbs its run's densities (setup rebuilt) and warm-starts from the
+    run's previous solutions."""
     import numpy as np
     import inputs
     import paper_2006_13387_amd as msp
     rng = np.random.default_rng(4)
     sizes = ((256, 128), (512, 256), (768, 384), (1024, 512))
+    sizes3 = ((48, 24, 24), (72, 36, 36), (96, 48, 48))
     runs = []
     t0 = time.perf_counter()
     for r in range(args.serve_runs):
-        nel = sizes[int(rng.integers(len(sizes)))]
         emin = (1e-6, 1e-9)[int(rng.integers(2))]
-        runs.append(inputs.scaled_cantilever_2d(nel, 4000 + r, Emin=emin, precision=1))
+        if r % 4 == 3:
+            nel = sizes3[int(rng.integers(len(sizes3)))]
+            runs.append(inputs.scaled_cantilever_3d(nel, 4000 + r, Emin=emin, precision=1))
+        else:
+            nel = sizes[int(rng.integers(len(sizes)))]
+            runs.append(inputs.scaled_cantilever_2d(nel, 4000 + r, Emin=emin, precision=1))
     log(f"[serve] {len(runs)} runs generated in {time.perf_counter() - t0:.1f} s")
     # requests: run r's t-th request perturbs its densities
     order = [int(rng.integers(len(runs))) for _ in range(args.serve_requests)]
@@ -426,7 +432,9 @@ def serving_workload(torch, args):
         "value": round(st["solves_per_s"], 3), "unit": "solves/s",
         "n_gpus": 1, "higher_is_better": True, "dtype": "f64 (FP32 local inverses)",
         "data": "synthetic",
-        "config": {"workload": f"{len(runs)} 2D runs (256x128..1024x512 Q1, Emin 1e-6/1e-9), "
+        "config": {"workload": f"{len(runs)} runs ({sum(p.desc['dim'] == 3 for p in runs)} "
+                               "of them 3D 48x24x24..96x48x48 H8, the rest 2D "
+                               "256x128..1024x512 Q1; Emin 1e-6/1e-9), "
                                f"{len(reqs)} requests, Poisson {args.serve_rate:g}/s, "
                                "perturbed densities (amplitude 0.05), warm starts",
                    "max_active": 16, "hbm_budget_gib": 250},

@@ -385,10 +385,12 @@ typedef struct msp_server msp_server;
 
 /*
  * A request loop for many topology-optimisation runs.  A run is a mesh with
- * its clamped DOFs; its handle (setup) and its last state and adjoint
- * solutions stay resident while the projected device memory of all resident
- * runs fits hbm_budget_bytes (idle runs' setups are evicted least recently
- * used first; their warm-start vectors stay).  At most max_active requests
+ * its clamped DOFs (2D, or 3D with the heat coarse space); its handle
+ * (setup) and its last state and adjoint solutions stay resident while the
+ * projected device memory of all resident runs fits hbm_budget_bytes (idle
+ * runs' setups are evicted least recently used first; their warm-start
+ * vectors stay).  A run's projection is raised to the device bytes its
+ * handle was measured to hold once admitted.  At most max_active requests
  * are in progress.  The serving layer is not in the paper; the solves are.
  */
 msp_status msp_server_create(int64_t hbm_budget_bytes, int32_t max_active,
@@ -396,7 +398,8 @@ msp_status msp_server_create(int64_t hbm_budget_bytes, int32_t max_active,
 msp_status msp_server_destroy(msp_server* sv);
 const char* msp_server_last_error(const msp_server* sv);
 
-/* Register a run (validated like msp_create; no device memory yet). */
+/* Register a run (validated like msp_create and, in 3D, like msp_setup's
+ * buffer layout; no device memory is kept). */
 msp_status msp_server_add_run(msp_server* sv, const msp_problem_desc* desc,
                               const uint8_t* fixed_mask_host, int32_t* run_id);
 
@@ -416,8 +419,9 @@ msp_status msp_server_submit(msp_server* sv, int32_t run_id,
 
 /*
  * One scheduling step on the caller's stream: one chunk of 16 lockstep PCG
- * iterations for every solve in progress (a batched launch per iteration
- * kernel, as msp_batch_solve), while queued requests are admitted as slots
+ * iterations for every 2D solve in progress (a batched launch per iteration
+ * kernel, as msp_batch_solve) and 16 iterations of each 3D solve in
+ * progress, while queued requests are admitted as slots
  * and memory allow, their densities and setup running on a second stream
  * at the same time (ordered after all work the caller queued on the stream
  * before this call, so densities written there are seen); then finished

@@ -426,6 +426,16 @@ def scaled_cantilever_2d(nel, seed, *, sub=32, overlap=2, Emin=1e-6,
                           precision=precision)
 
 
+def scaled_cantilever_3d(nel, seed, *, sub=6, overlap=1, Emin=1e-6, precision=1):
+    """A config-2 style 3D cantilever of another size (used by serving):
+    rods scaled with the volume."""
+    nx, ny, nz = nel
+    nr = max(1, int(round(100 * (nx * ny * nz) / (96 * 48 * 48))))
+    return _cantilever_3d(f"cantilever3d_{nx}x{ny}x{nz}", nel, seed, ell=6, vf=0.3,
+                          nrods=nr, widths=(1, 2), sub=sub, overlap=overlap, Emin=Emin,
+                          precision=precision)
+
+
 def batch_configs(count=64, seed=3, sizes=((128, 64), (256, 128), (512, 256),
                                            (768, 384)), Emin=1e-6,
                   precision=1):

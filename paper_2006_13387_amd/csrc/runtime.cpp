@@ -8,7 +8,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -429,15 +431,41 @@ msp_status fail(msp_handle* h, msp_status st, const std::string& msg) {
                   std::string(#call " failed: ") + hipGetErrorString(e_)); \
   } while (0)
 
+// Device bytes held by the library's allocations (the server's measure of
+// a run's footprint).
+static std::mutex g_alloc_mu;
+static std::unordered_map<void*, size_t> g_alloc_size;
+static long long g_dev_bytes = 0;
+
+static long long dev_bytes_in_use() {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  return g_dev_bytes;
+}
+
 template <typename T>
 hipError_t dalloc(T** p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
-  return hipMalloc((void**)p, count * sizeof(T));
+  const hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e == hipSuccess) {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc_size[(void*)*p] = count * sizeof(T);
+    g_dev_bytes += (long long)(count * sizeof(T));
+  }
+  return e;
 }
 
 void dfree(void* p) {
-  if (p) (void)hipFree(p);
+  if (!p) return;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    auto it = g_alloc_size.find(p);
+    if (it != g_alloc_size.end()) {
+      g_dev_bytes -= (long long)it->second;
+      g_alloc_size.erase(it);
+    }
+  }
+  (void)hipFree(p);
 }
 
 // Subdomain node box along one axis for element range [e_lo, e_hi):
@@ -2927,7 +2955,8 @@ struct SvRun {
   double* d_us = nullptr;      // last state solution (warm start)
   double* d_ua = nullptr;      // last adjoint solution
   bool have_us = false, have_ua = false;
-  long long bytes = 0;         // projected handle bytes
+  long long bytes = 0;         // projected handle bytes (raised to what was measured)
+  long long held = 0;          // device bytes the live handle allocated so far
   long long last_use = 0;
   bool busy = false;           // a request of this run is admitted
   bool reused = false;         // the admitted request runs on an older setup
@@ -3026,18 +3055,33 @@ extern "C" msp_status msp_server_add_run(msp_server* sv, const msp_problem_desc*
                                          int32_t* run_id) {
   if (!sv || !d || !fixed_mask_host || !run_id)
     return sfail(sv, MSP_E_INVALID, "null argument");
-  if (d->dim != 2)
-    return sfail(sv, MSP_E_INVALID, "runs must be 2D: serving batches 2D problems only");
+  if (d->dim != 2 && d->dim != 3)
+    return sfail(sv, MSP_E_INVALID, "runs must be 2D or 3D");
   if (d->coarse_kind != 0)
     return sfail(sv, MSP_E_INVALID, "serving takes the heat coarse space only (coarse_kind 0)");
   // validate by building the geometry once (no device memory is kept)
   msp_handle* probe = nullptr;
+  const long long b0 = dev_bytes_in_use();
   msp_status st = msp_create(d, fixed_mask_host, &probe);
   if (st != MSP_OK) return sfail(sv, st, g_static_err);
   SvRun r;
   r.desc = *d;
   r.mask.assign(fixed_mask_host, fixed_mask_host + probe->n_dofs);
-  r.bytes = handle_projected_bytes(probe) + 2 * probe->n_dofs * 8;
+  if (d->dim == 3) {
+    // 3D: the first level's buffers and the coarse eigen buffers as the
+    // probe allocates them, plus a quarter for the coarse operator's slab
+    // factors (each admission raises the projection to what it measured)
+    st = ensure_3d_buffers(probe);
+    if (st == MSP_OK && d->eig_kmax > 0) st = ensure_coarse3(probe);
+    if (st != MSP_OK) {
+      const std::string msg = probe->err;
+      msp_destroy(probe);
+      return sfail(sv, st, msg);
+    }
+    r.bytes = (dev_bytes_in_use() - b0) * 5 / 4 + 2 * probe->n_dofs * 8;
+  } else {
+    r.bytes = handle_projected_bytes(probe) + 2 * probe->n_dofs * 8;
+  }
   msp_destroy(probe);
   sv->runs.push_back(std::move(r));
   *run_id = (int32_t)sv->runs.size() - 1;
@@ -3114,7 +3158,7 @@ static msp_status sv_start_solve(msp_server* sv, SvReq& q, bool adjoint, hipStre
   q.R.rtol = q.rtol;
   q.R.maxit = q.maxit;
   msp_status st = run_begin(q.R, adjoint ? r.have_ua : r.have_us, s);
-  if (st == MSP_OK) st = seg_launch(q.R, s);
+  if (st == MSP_OK) st = r.h->dim == 3 ? seg3_launch(q.R, s) : seg_launch(q.R, s);
   if (st == MSP_OK && hipStreamSynchronize(s) != hipSuccess) st = MSP_E_DEVICE;
   if (st == MSP_OK) st = seg_started(q.R, s);
   q.phase = adjoint ? 3 : 2;
@@ -3134,10 +3178,13 @@ static msp_status sv_admit(msp_server* sv) {
       ++qi;
       continue;
     }
+    long long b0 = dev_bytes_in_use();
     if (!r.h) {
       if (!sv_make_room(sv, q.run)) break;          // wait for memory
+      b0 = dev_bytes_in_use();                      // after the evictions
       msp_status st = msp_create(&r.desc, r.mask.data(), &r.h);
       if (st != MSP_OK) return sfail(sv, st, g_static_err);
+      r.held = 0;
       r.h->reuse_max_age = sv->reuse_max_age;
       r.h->reuse_iter_limit = sv->reuse_iter_limit;
       if (!r.d_us) {
@@ -3161,6 +3208,8 @@ static msp_status sv_admit(msp_server* sv) {
         ++sv->setups_reused;
       }
     }
+    r.held += dev_bytes_in_use() - b0;
+    r.bytes = std::max(r.bytes, r.held);
     if (st == MSP_OK) st = sv_start_solve(sv, q, false, sv->s_setup);
     if (st != MSP_OK) {
       q.status = st;
@@ -3214,14 +3263,19 @@ extern "C" msp_status msp_server_step(msp_server* sv, hipStream_t s,
   if (hipEventRecord(sv->ev_step, s) != hipSuccess ||
       hipStreamWaitEvent(sv->s_setup, sv->ev_step, 0) != hipSuccess)
     return sfail(sv, MSP_E_DEVICE, "ordering the setup stream failed");
-  // 1. one chunk of lockstep iterations for every solve that iterates
-  std::vector<int> it_ids;
+  // 1. one chunk of lockstep iterations for every 2D solve that iterates,
+  //    then one chunk of each 3D solve's own iterations
+  std::vector<int> it_ids, it3;
   std::vector<msp_handle*> hs;
   for (int id : sv->active) {
     SvReq& q = sv->reqs[id];
     if ((q.phase == 2 || q.phase == 3) && !q.R.finished && q.R.iterating) {
-      it_ids.push_back(id);
-      hs.push_back(q.R.h);
+      if (q.R.h->dim == 3) {
+        it3.push_back(id);
+      } else {
+        it_ids.push_back(id);
+        hs.push_back(q.R.h);
+      }
     }
   }
   if (!hs.empty()) {
@@ -3238,6 +3292,12 @@ extern "C" msp_status msp_server_step(msp_server* sv, hipStream_t s,
       (void)hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(CGScalars), hipMemcpyDeviceToHost, s);
     }
   }
+  for (int id : it3) {
+    msp_handle* h = sv->reqs[id].R.h;
+    chunk3(h, s);
+    (void)hipMemcpyAsync(h->h_sc, h->d_sc, sizeof(CGScalars), hipMemcpyDeviceToHost, s);
+  }
+  it_ids.insert(it_ids.end(), it3.begin(), it3.end());
   // 2. admissions: their setups run on the setup stream while the chunk
   //    runs on s
   msp_status st = sv_admit(sv);
@@ -3254,8 +3314,9 @@ extern "C" msp_status msp_server_step(msp_server* sv, hipStream_t s,
     for (int guard = 0; guard < 8; ++guard) {
       if (!(q.phase == 2 || q.phase == 3) || q.R.iterating) break;
       bool restart = false;
+      const bool d3 = q.R.h->dim == 3;
       if (!q.R.finished) {
-        st = seg_finish(q.R, s, &restart);
+        st = d3 ? seg3_finish(q.R, s, &restart) : seg_finish(q.R, s, &restart);
         if (st != MSP_OK) {
           q.status = st;
           q.phase = -1;
@@ -3263,7 +3324,7 @@ extern "C" msp_status msp_server_step(msp_server* sv, hipStream_t s,
         }
       }
       if (restart) {
-        st = seg_launch(q.R, s);
+        st = d3 ? seg3_launch(q.R, s) : seg_launch(q.R, s);
         if (st == MSP_OK && hipStreamSynchronize(s) != hipSuccess) st = MSP_E_DEVICE;
         if (st == MSP_OK) st = seg_started(q.R, s);
         if (st != MSP_OK) {

@@ -201,3 +201,56 @@ def test_serving_latency_stats():
     assert st["completed"] == 4
     assert 0 < st["p50_ms"] <= st["p99_ms"]
     assert st["solves_per_s"] > 0
+
+
+def _runs_mixed():
+    # config 4's mix in small: a 2D run beside two 3D (H8) runs
+    return [inputs.scaled_cantilever_2d((64, 32), 4001, sub=16, precision=1),
+            inputs.scaled_cantilever_3d((24, 12, 12), 4101),
+            inputs.scaled_cantilever_3d((36, 12, 12), 4102)]
+
+
+def test_serving_2d_and_3d_runs_equal_msp_solve():
+    """2D and 3D runs served together: each 3D solve iterates on its own
+    handle between the 2D batch chunks. Every served state and adjoint
+    solution equals msp_solve's on a fresh handle with the same densities
+    and warm starts, bit for bit, also under a budget that holds one run's
+    setup at a time (evictions); the 3D state solutions match the oracle's
+    direct solve to 1e-6 (2-norm and entry by entry)."""
+    msp = _msp()
+    runs = _runs_mixed()
+    nreq = 2
+    reqs = [_requests(p, r, nreq) for r, p in enumerate(runs)]
+    order = [(r, t) for t in range(nreq) for r in range(len(runs))]
+    print("[serve3d] mixed server", flush=True)
+    served = _serve(msp.Server(1 << 40, 3), runs, reqs, order)
+    for r, p in enumerate(runs):
+        s = msp.Solver(p.desc, p.fixed)
+        us_prev = ua_prev = None
+        for t in range(nreq):
+            rho, fs, fa = reqs[r][t]
+            s.set_densities(rho)
+            us, ist = s.solve(fs, u=None if t == 0 else us_prev.clone(), warm=t > 0)
+            ua, iad = s.solve(fa, u=None if t == 0 else ua_prev.clone(), warm=t > 0)
+            um, am, (i0, i1, _) = served[(r, t)]
+            print(f"[serve3d] run {r} ({p.desc['dim']}D) req {t}: iters {ist['iters']}/"
+                  f"{iad['iters']} served {i0['iters']}/{i1['iters']} relres "
+                  f"{i0['relres_true']:.1e}/{i1['relres_true']:.1e}", flush=True)
+            assert torch.equal(um, us), (r, t)
+            assert torch.equal(am, ua), (r, t)
+            assert ist["iters"] == i0["iters"] and iad["iters"] == i1["iters"]
+            assert i0["status"] == 0 and i1["status"] == 0, (i0, i1)
+            assert i0["relres_true"] <= 1e-8 and i1["relres_true"] <= 1e-8
+            if p.desc["dim"] == 3:
+                ud = oracle.direct_solve(p.desc, rho.cpu().numpy(), p.fixed, fs.cpu().numpy())
+                u = um.cpu().numpy()
+                assert np.linalg.norm(u - ud) <= 1e-6 * np.linalg.norm(ud), (r, t)
+                assert_entrywise(u, ud, 1e-6, np.max(np.abs(ud)), f"served 3D u run {r} req {t}")
+            us_prev, ua_prev = us, ua
+        s.close()
+    one = max(_projected(runs))
+    print(f"[serve3d] tight budget {one * 1.2:.3e} bytes", flush=True)
+    tight = _serve(msp.Server(int(one * 1.2), 3), runs, reqs, order)
+    for key in served:
+        assert torch.equal(tight[key][0], served[key][0]), key
+        assert torch.equal(tight[key][1], served[key][1]), key
