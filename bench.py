@@ -328,7 +328,9 @@ def batch_workload(torch, args):
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     b = msp.Batch()
-    b.solve(solvers, fs, use_graph=True)           # warm-up, graph capture
+    b.solve(solvers, fs, use_graph=True)           # warm-up: autotuning, graph capture
+    if not b.tuning()["tuned"]:
+        b.solve(solvers, fs, use_graph=True)
     res = {}
     for name, graph in (("batched_graph", True), ("batched_eager", False)):
         torch.cuda.synchronize()
@@ -336,6 +338,16 @@ def batch_workload(torch, args):
         us, infos = b.solve(solvers, fs, use_graph=graph)
         torch.cuda.synchronize()
         res[name] = time.perf_counter() - t0
+    # the fixed launch shape (16 iterations a chunk, items problem by problem)
+    bf = msp.Batch()
+    bf.set_autotune(False)
+    bf.solve(solvers, fs, use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bf.solve(solvers, fs, use_graph=True)
+    torch.cuda.synchronize()
+    res["batched_graph_untuned_shape"] = time.perf_counter() - t0
+    bf.close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     seq = [s.solve(f)[1] for s, f in zip(solvers, fs)]
@@ -360,6 +372,7 @@ def batch_workload(torch, args):
         "relres_true_max": max(i["relres_true"] for i in infos),
         "same_as_one_at_a_time": all(i["iters"] == j["iters"] for i, j in zip(infos, seq)),
         "batch_stats": b.stats(),
+        "autotuner": b.tuning(),
         "level1_hbm": level1_hbm_probe(torch, solvers),
     }
     print(json.dumps(out), flush=True)

@@ -362,9 +362,15 @@ const char* msp_batch_last_error(const msp_batch* b);
  * changed.  Every PCG iteration then launches each iteration kernel once
  * for all problems still iterating (the first-level solves of all of them
  * in one persistent launch of one workgroup per CU); with use_graph != 0 a
- * chunk of 16 iterations is captured once as a HIP graph and replayed.
- * Each problem's arithmetic is that of msp_solve on its handle, so every
- * result is bitwise the one it would have alone.  infos_host (may be NULL)
+ * chunk of iterations is captured once as a HIP graph and replayed.  The
+ * launch shape (iterations per chunk: 8, 16 or 32; the first-level items
+ * problem by problem or largest systems first) is picked by an autotuner:
+ * the first chunks run on a new set of handles measure each candidate
+ * twice, in a mirrored order, as wall time per iteration per active DOF
+ * (carried over to the next solves until complete), and the fastest is
+ * kept for that set.  Each problem's arithmetic is that of msp_solve on its
+ * handle whatever the shape, so every result is bitwise the one it would
+ * have alone.  infos_host (may be NULL)
  * receives n statistics records.  A negative status of any entry makes the
  * call return an error; MSP_NOT_CONVERGED if some entry did not converge.
  */
@@ -374,10 +380,23 @@ msp_status msp_batch_solve(msp_batch* b, msp_handle* const* handles,
                            int32_t maxit, int32_t use_graph, hipStream_t stream,
                            msp_solve_info* infos_host);
 
-/* Chunks of 16 lockstep iterations run by this batch context, and how many
+/* Chunks of lockstep iterations run by this batch context, and how many
  * of them were graph replays. */
 msp_status msp_batch_stats(const msp_batch* b, int64_t* chunks,
                            int64_t* graph_chunks);
+
+/* Switch the launch-shape autotuner on (default) or off (off: 16 iterations
+ * per chunk, items problem by problem). */
+msp_status msp_batch_set_autotune(msp_batch* b, int32_t on);
+
+/* The current launch shape (chunk: iterations per chunk; order: 1 when the
+ * first-level items go largest systems first), whether it is the tuned
+ * choice for the last set of handles (tuned = 1), and the measured cost of
+ * each of the 6 candidates (ms per iteration per active DOF; 0: not yet
+ * measured), candidates in the order (16, 8, 32 iterations) x (problem
+ * order, largest first).  cost_host may be NULL. */
+msp_status msp_batch_tuning(const msp_batch* b, int32_t* chunk, int32_t* order,
+                            int32_t* tuned, double* cost_host);
 
 /* ---- serving: continuous batching of state and adjoint solves ---- */
 

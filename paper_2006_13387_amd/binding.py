@@ -63,6 +63,7 @@ EXPORTS = ["msp_create", "msp_destroy", "msp_last_error", "msp_set_densities",
            "msp_coarse_basis", "msp_vec_dot", "msp_query",
            "msp_kernel_timing", "msp_batch_create", "msp_batch_destroy",
            "msp_batch_last_error", "msp_batch_solve", "msp_batch_stats",
+           "msp_batch_set_autotune", "msp_batch_tuning",
            "msp_server_create", "msp_server_destroy", "msp_server_last_error",
            "msp_server_add_run", "msp_server_submit", "msp_server_step",
            "msp_server_result", "msp_server_stats", "msp_set_reuse",
@@ -117,6 +118,9 @@ def load_library(path=LIB_PATH):
                                   ctypes.POINTER(SolveInfo)]
     L.msp_batch_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(ctypes.c_int64)]
+    L.msp_batch_set_autotune.argtypes = [vp, i32]
+    L.msp_batch_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                   ctypes.POINTER(i32), vp]
     L.msp_server_create.argtypes = [ctypes.c_int64, i32, ctypes.POINTER(vp)]
     L.msp_server_destroy.argtypes = [vp]
     L.msp_server_last_error.argtypes = [vp]
@@ -377,6 +381,21 @@ class Batch:
         c, g = ctypes.c_int64(), ctypes.c_int64()
         self.L.msp_batch_stats(self.b, ctypes.byref(c), ctypes.byref(g))
         return {"chunks": c.value, "graph_chunks": g.value}
+
+    def set_autotune(self, on):
+        st = self.L.msp_batch_set_autotune(self.b, 1 if on else 0)
+        if st != 0:
+            raise MspError(st, self.L.msp_batch_last_error(self.b).decode())
+
+    def tuning(self):
+        """The launch shape the autotuner chose (or is measuring) and the
+        measured cost of each candidate."""
+        ch, od, tu = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        cost = np.zeros(6)
+        self.L.msp_batch_tuning(self.b, ctypes.byref(ch), ctypes.byref(od), ctypes.byref(tu),
+                                cost.ctypes.data_as(ctypes.c_void_p))
+        return {"chunk": ch.value, "largest_first": od.value, "tuned": bool(tu.value),
+                "cost_ms_per_iter_dof": cost.tolist()}
 
 
 class Server:

@@ -1105,17 +1105,19 @@ __global__ void __launch_bounds__(AP_NT) k_level1(Level1Args a) {
 
 // One pass of the first-level solves of several problems in one persistent
 // launch: workgroup w takes items w, w + grid, w + 2 grid, ... of the
-// concatenated list (problem by problem, two per system), so a grid of one
-// per CU covers any batch.
+// concatenated list (problem by problem, two per system), or of that list
+// permuted by `order` when given (an item's result does not depend on the
+// workgroup that computes it), so a grid of one per CU covers any batch.
 template <bool BWD>
 __global__ void __launch_bounds__(AP_NT)
 k_level1_batch(const Level1Args* __restrict__ tab, const int* __restrict__ start,
-               int nent, int total) {
+               int nent, int total, const int* __restrict__ order) {
   __shared__ __align__(1024) unsigned char lds[L1_LDS];
   __shared__ L1Shared L;
   for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
-    const int e = batch_entry(start, nent, vb);
-    level1_item<BWD>(tab[e], vb - start[e], lds, L);
+    const int item = order != nullptr ? order[vb] : vb;
+    const int e = batch_entry(start, nent, item);
+    level1_item<BWD>(tab[e], item - start[e], lds, L);
     __syncthreads();
   }
 }
@@ -2073,11 +2075,11 @@ void launch_level1(const Level1Args& a, int nsys, hipStream_t s) {
 }
 
 void launch_level1_batch(const Level1Args* tab, const int* start, int nent,
-                         int total, int grid, hipStream_t s) {
+                         int total, int grid, const int* order, hipStream_t s) {
   hipLaunchKernelGGL(k_level1_batch<false>, dim3(grid), dim3(AP_NT), 0, s, tab,
-                     start, nent, total);
+                     start, nent, total, order);
   hipLaunchKernelGGL(k_level1_batch<true>, dim3(grid), dim3(AP_NT), 0, s, tab,
-                     start, nent, total);
+                     start, nent, total, order);
 }
 
 bool eig_fits_host(int bs, int m) { return eig_fits(bs, m); }

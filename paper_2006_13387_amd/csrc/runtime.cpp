@@ -55,7 +55,8 @@ void launch_factor_heat(const Geom&, const SysDesc*, int, const double*,
                         const uint8_t*, const double*, double*, int*,
                         const int*, int, hipStream_t);
 void launch_level1(const Level1Args&, int nsys, hipStream_t);
-void launch_level1_batch(const Level1Args*, const int*, int, int, int, hipStream_t);
+void launch_level1_batch(const Level1Args*, const int*, int, int, int, const int*,
+                         hipStream_t);
 bool level1_fits(int bs, int nb, bool fp32);
 int launch_heat_eigen(const Geom&, const SysDesc*, int, const double*,
                        const uint8_t*, const double*, const double*,
@@ -237,6 +238,7 @@ constexpr double kEigTol = 1e-8;
 // smallest nonzero eigenvalue of the scaled K_0 is 2.4e-9).
 constexpr double kPivotDrop = 1e-10;
 constexpr int kChunk = 16;           // PCG iterations between host checks
+constexpr int kTuneCand = 6;         // batch autotuner: launch-shape candidates
 constexpr int kMaxRestarts = 3;
 // FP32 inverse blocks are used for a subdomain only if its amplification
 // metric max_i (S_k^-1)_ii (D_k)_ii stays at or below this bound (see
@@ -2637,12 +2639,31 @@ struct msp_batch {
   int* d_start = nullptr;                 // 6 prefix tables of cap + 1 ints
   int tot[6] = {0, 0, 0, 0, 0, 0};
   int n = 0;
-  hipGraphExec_t gexec = nullptr;         // captured chunk of kChunk iterations
+  hipGraphExec_t gexec = nullptr;         // captured chunk of `chunk` iterations
   std::vector<unsigned char> gkey;        // tables the graph was captured with
   long long chunks = 0, graph_chunks = 0;
+  // launch shape of the iterations, picked by the autotuner: PCG iterations
+  // per chunk (host check) and the order of the first-level items in the
+  // persistent launch (0: problem by problem; 1: largest systems first)
+  int chunk = kChunk;
+  int order_on = 0;
+  int* d_order = nullptr;                 // first-level item permutation
+  int order_cap = 0;
+  int autotune = 1;
+  std::vector<unsigned char> tuned_key;   // tables the choice was made for
+  std::vector<unsigned char> tuning_key;  // tables being measured
+  double tune_cost[kTuneCand] = {};       // per-iteration cost per candidate
+  int tune_cnt[kTuneCand] = {};
+  int tune_step = 0;
 };
 
 enum { BT_MV = 0, BT_UP, BT_L1, BT_RS, BT_GV, BT_CB };
+
+// Autotuner candidates (chunk length, first-level item order), measured in
+// a mirrored sequence so that a drift of the per-chunk work (problems
+// finishing) weighs on every candidate alike.
+static const int kTuneChunk[kTuneCand] = {16, 8, 32, 16, 8, 32};
+static const int kTuneOrder[kTuneCand] = {0, 0, 0, 1, 1, 1};
 
 static msp_status bfail(msp_batch* b, msp_status st, const std::string& msg) {
   if (b) b->err = msg;
@@ -2652,8 +2673,10 @@ static msp_status bfail(msp_batch* b, msp_status st, const std::string& msg) {
 
 static void batch_free_tables(msp_batch* b) {
   void* bufs[] = {b->d_mv[0], b->d_mv[1], b->d_up[0], b->d_up[1], b->d_l1,
-                  b->d_rs, b->d_gv, b->d_cb, b->d_start};
+                  b->d_rs, b->d_gv, b->d_cb, b->d_start, b->d_order};
   for (void* p : bufs) dfree(p);
+  b->d_order = nullptr;
+  b->order_cap = 0;
   b->d_mv[0] = b->d_mv[1] = nullptr;
   b->d_up[0] = b->d_up[1] = nullptr;
   b->d_l1 = nullptr;
@@ -2733,6 +2756,33 @@ static msp_status batch_tables(msp_batch* b, const std::vector<msp_handle*>& hs,
   }
   for (int k = 0; k < 6; ++k) b->tot[k] = start[k * (b->cap + 1) + n];
   b->n = n;
+  // first-level items by decreasing system size (nodes times row length),
+  // ties in list order: the persistent launch then deals the largest items
+  // out first
+  std::vector<int> order(std::max(1, b->tot[BT_L1]));
+  {
+    std::vector<long long> cost(b->tot[BT_L1]);
+    int k = 0;
+    for (int e = 0; e < n; ++e)
+      for (size_t i = 0; i < hs[e]->subs.size(); ++i) {
+        const SysDesc& sd = hs[e]->subs[i];
+        const long long c = (long long)sd.nyb * sd.nxb * sd.nxb;
+        cost[k] = c;
+        cost[k + 1] = c;
+        k += 2;
+      }
+    for (int i = 0; i < b->tot[BT_L1]; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.begin() + b->tot[BT_L1],
+                     [&](int a, int c) { return cost[a] > cost[c]; });
+  }
+  if ((int)order.size() > b->order_cap) {
+    dfree(b->d_order);
+    b->d_order = nullptr;
+    b->order_cap = 0;
+    if (dalloc(&b->d_order, order.size()) != hipSuccess)
+      return bfail(b, MSP_E_NOMEM, "device allocation of the batch tables failed");
+    b->order_cap = (int)order.size();
+  }
   auto up_copy = [&](void* d, const void* hsrc, size_t bytes) {
     return hipMemcpyAsync(d, hsrc, bytes, hipMemcpyHostToDevice, s);
   };
@@ -2747,6 +2797,7 @@ static msp_status batch_tables(msp_batch* b, const std::vector<msp_handle*>& hs,
   C(up_copy(b->d_gv, gv.data(), n * sizeof(GemvArgs)));
   C(up_copy(b->d_cb, cb.data(), n * sizeof(CombineCall)));
   C(up_copy(b->d_start, start.data(), start.size() * sizeof(int)));
+  C(up_copy(b->d_order, order.data(), order.size() * sizeof(int)));
   C(hipStreamSynchronize(s));               // host tables go out of scope
   if (e != hipSuccess) return bfail(b, MSP_E_DEVICE, std::string("batch table upload failed: ") + hipGetErrorString(e));
   // the graph depends on the table contents and the grid sizes
@@ -2757,8 +2808,8 @@ static msp_status batch_tables(msp_batch* b, const std::vector<msp_handle*>& hs,
   };
   add(&n, sizeof(n));
   add(b->tot, sizeof(b->tot));
-  const void* ptrs[9] = {b->d_mv[0], b->d_mv[1], b->d_up[0], b->d_up[1], b->d_l1,
-                         b->d_rs, b->d_gv, b->d_cb, b->d_start};
+  const void* ptrs[10] = {b->d_mv[0], b->d_mv[1], b->d_up[0], b->d_up[1], b->d_l1,
+                          b->d_rs, b->d_gv, b->d_cb, b->d_start, b->d_order};
   add(ptrs, sizeof(ptrs));
   for (int c = 0; c < 2; ++c) {
     add(mv[c].data(), n * sizeof(MatvecArgs));
@@ -2771,19 +2822,20 @@ static msp_status batch_tables(msp_batch* b, const std::vector<msp_handle*>& hs,
   return MSP_OK;
 }
 
-// kChunk lockstep iterations of every problem of the batch: each kernel is
-// launched once for all problems (problems whose segment is done return at
-// once); the first-level solves of all problems in one persistent launch of
-// one workgroup per CU.
+// b->chunk (even) lockstep iterations of every problem of the batch: each
+// kernel is launched once for all problems (problems whose segment is done
+// return at once); the first-level solves of all problems in one persistent
+// launch of one workgroup per CU, items in the tuned order.
 static void chunk_batch(msp_batch* b, hipStream_t s) {
   const int cp = b->cap + 1;
   const int* st = b->d_start;
   const int l1_grid = std::max(1, std::min(b->tot[BT_L1], kNumCUs));
-  for (int it = 0; it < kChunk; ++it) {
+  const int* order = b->order_on ? b->d_order : nullptr;
+  for (int it = 0; it < b->chunk; ++it) {
     const int cur = it & 1;
     launch_cg_matvec_batch(b->d_mv[cur], st + BT_MV * cp, b->n, b->tot[BT_MV], s);
     launch_update_batch(b->d_up[cur], st + BT_UP * cp, b->n, b->tot[BT_UP], s);
-    launch_level1_batch(b->d_l1, st + BT_L1 * cp, b->n, b->tot[BT_L1], l1_grid, s);
+    launch_level1_batch(b->d_l1, st + BT_L1 * cp, b->n, b->tot[BT_L1], l1_grid, order, s);
     if (b->tot[BT_RS] > 0) {
       launch_restrict_batch(b->d_rs, st + BT_RS * cp, b->n, b->tot[BT_RS], s);
       launch_coarse_gemv_batch(b->d_gv, st + BT_GV * cp, b->n, b->tot[BT_GV], s);
@@ -2843,32 +2895,49 @@ extern "C" msp_status msp_batch_solve(msp_batch* b, msp_handle* const* hs_in,
   if (hipStreamSynchronize(s) != hipSuccess) return bfail(b, MSP_E_DEVICE, "stream synchronisation failed");
   for (int e = 0; e < n; ++e)
     if ((st = seg_started(R[e], s)) != MSP_OK) return bfail(b, st, hs[e]->err);
-  // capture one chunk when asked for and the tables changed
-  bool graph_ready = false;
-  if (use_graph) {
-    if (b->gexec && b->gkey == key) {
-      graph_ready = true;
-    } else {
-      if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-      b->gexec = nullptr;
-      hipStream_t cs;
-      hipGraph_t gr = nullptr;
-      if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess) {
-        bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
-        if (ok) chunk_batch(b, cs);
-        ok = (hipStreamEndCapture(cs, &gr) == hipSuccess) && ok && gr != nullptr;
-        if (ok) ok = hipGraphInstantiate(&b->gexec, gr, nullptr, nullptr, 0) == hipSuccess;
-        if (gr) (void)hipGraphDestroy(gr);
-        (void)hipStreamDestroy(cs);
-        if (ok) {
-          b->gkey = key;
-          graph_ready = true;
-        } else {
-          b->gexec = nullptr;
-        }
-      }
+  // autotuning: a new table layout starts a measurement of the candidates
+  // (carried over to the next solves with the same layout until each was
+  // measured twice); the choice changes no result, only the launch shape
+  if (b->autotune && b->tuned_key != key && b->tuning_key != key) {
+    b->tuning_key = key;
+    b->tune_step = 0;
+    for (int c = 0; c < kTuneCand; ++c) {
+      b->tune_cost[c] = 0.0;
+      b->tune_cnt[c] = 0;
     }
   }
+  auto tuning = [&]() {
+    return b->autotune && b->tuned_key != key && b->tuning_key == key &&
+           b->tune_step < 2 * kTuneCand;
+  };
+  // capture one chunk of the chosen shape when asked for and the tables or
+  // the shape changed
+  bool graph_ready = false;
+  auto capture = [&]() {
+    std::vector<unsigned char> gk = key;
+    const int shape[2] = {b->chunk, b->order_on};
+    const unsigned char* sp = (const unsigned char*)shape;
+    gk.insert(gk.end(), sp, sp + sizeof(shape));
+    if (b->gexec && b->gkey == gk) return true;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+    hipStream_t cs;
+    hipGraph_t gr = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return false;
+    bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) chunk_batch(b, cs);
+    ok = (hipStreamEndCapture(cs, &gr) == hipSuccess) && ok && gr != nullptr;
+    if (ok) ok = hipGraphInstantiate(&b->gexec, gr, nullptr, nullptr, 0) == hipSuccess;
+    if (gr) (void)hipGraphDestroy(gr);
+    (void)hipStreamDestroy(cs);
+    if (!ok) {
+      b->gexec = nullptr;
+      return false;
+    }
+    b->gkey = gk;
+    return true;
+  };
+  bool graph_tried = false;
   for (;;) {
     bool any = false;
     for (int e = 0; e < n; ++e) any = any || (!R[e].finished && R[e].iterating);
@@ -2889,7 +2958,24 @@ extern "C" msp_status msp_batch_solve(msp_batch* b, msp_handle* const* hs_in,
       if (!more) break;
       continue;
     }
-    if (graph_ready) {
+    // a measured chunk takes its candidate's shape (plain launches; the
+    // cost is wall time per iteration per active DOF, host check included)
+    const bool meas = tuning();
+    int cand = -1;
+    double work = 0.0;
+    if (meas) {
+      const int k = b->tune_step;
+      cand = k < kTuneCand ? k : 2 * kTuneCand - 1 - k;
+      b->chunk = kTuneChunk[cand];
+      b->order_on = kTuneOrder[cand];
+      for (int e = 0; e < n; ++e)
+        if (!R[e].finished && R[e].iterating) work += (double)hs[e]->n_dofs;
+    } else if (use_graph && !graph_tried) {
+      graph_ready = capture();
+      graph_tried = true;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    if (graph_ready && !meas) {
       if (hipGraphLaunch(b->gexec, s) != hipSuccess) return bfail(b, MSP_E_DEVICE, "graph launch failed");
       ++b->graph_chunks;
     } else {
@@ -2901,6 +2987,20 @@ extern "C" msp_status msp_batch_solve(msp_batch* b, msp_handle* const* hs_in,
       if (!R[e].finished && R[e].iterating)
         (void)hipMemcpyAsync(hs[e]->h_sc, hs[e]->d_sc, sizeof(CGScalars), hipMemcpyDeviceToHost, s);
     if (hipStreamSynchronize(s) != hipSuccess) return bfail(b, MSP_E_DEVICE, "stream synchronisation failed");
+    if (meas) {
+      const double ms = std::chrono::duration<double, std::milli>(
+                            std::chrono::steady_clock::now() - t0).count();
+      b->tune_cost[cand] += ms / ((double)b->chunk * std::max(work, 1.0));
+      ++b->tune_cnt[cand];
+      if (++b->tune_step == 2 * kTuneCand) {
+        int best = 0;
+        for (int c = 1; c < kTuneCand; ++c)
+          if (b->tune_cost[c] / b->tune_cnt[c] < b->tune_cost[best] / b->tune_cnt[best]) best = c;
+        b->chunk = kTuneChunk[best];
+        b->order_on = kTuneOrder[best];
+        b->tuned_key = key;
+      }
+    }
     for (int e = 0; e < n; ++e) {
       if (R[e].finished || !R[e].iterating || !hs[e]->h_sc->done) continue;
       R[e].iterating = false;               // segment over: finished below
@@ -2920,6 +3020,30 @@ extern "C" msp_status msp_batch_solve(msp_batch* b, msp_handle* const* hs_in,
   }
   if (worst < 0) return bfail(b, worst, "a batch entry failed (see its msp_solve_info.status)");
   return worst;
+}
+
+extern "C" msp_status msp_batch_set_autotune(msp_batch* b, int32_t on) {
+  if (!b) return bfail(b, MSP_E_INVALID, "null batch");
+  b->autotune = on ? 1 : 0;
+  if (!on) {
+    b->chunk = kChunk;
+    b->order_on = 0;
+    b->tuned_key.clear();
+    b->tuning_key.clear();
+  }
+  return MSP_OK;
+}
+
+extern "C" msp_status msp_batch_tuning(const msp_batch* b, int32_t* chunk, int32_t* order,
+                                       int32_t* tuned, double* cost) {
+  if (!b) return bfail(nullptr, MSP_E_INVALID, "null batch");
+  if (chunk) *chunk = b->chunk;
+  if (order) *order = b->order_on;
+  if (tuned) *tuned = (!b->tuned_key.empty() && b->tuned_key == b->tuning_key) ? 1 : 0;
+  if (cost)
+    for (int c = 0; c < kTuneCand; ++c)
+      cost[c] = b->tune_cnt[c] > 0 ? b->tune_cost[c] / b->tune_cnt[c] : 0.0;
+  return MSP_OK;
 }
 
 extern "C" msp_status msp_batch_stats(const msp_batch* b, int64_t* chunks,

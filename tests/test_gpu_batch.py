@@ -56,6 +56,7 @@ def test_batch_matches_alone_bitwise_eager_and_graph():
               f"relres={info['relres_true']:.2e} restarts={info['restarts']}", flush=True)
         alone.append((u.clone(), info))
     b = msp.Batch()
+    b.set_autotune(False)                  # the fixed shape: 16 iterations a chunk
     for use_graph in (False, True, True):
         us, infos = b.solve(solvers, fs, rtol=1e-8, use_graph=use_graph)
         torch.cuda.synchronize()
@@ -95,6 +96,40 @@ def test_batch_warm_start_and_rejects_duplicates():
         assert i["relres_true"] <= 1e-8
     with pytest.raises(msp.MspError):
         b.solve([solvers[0], solvers[0]], [fs[0], fs[0]])
+    b.close()
+    for s in solvers:
+        s.close()
+
+
+def test_batch_autotuner_changes_no_bits():
+    """The launch-shape autotuner (iterations per chunk, first-level item
+    order) measures its candidates on the first solves of a set of handles
+    and then keeps the fastest: every solve, during and after the tuning,
+    with and without graphs, gives the bits the problems get alone."""
+    msp = _msp()
+    ps = _problems()
+    solvers = _solvers(ps)
+    fs = [torch.tensor(p.f, device="cuda") for p in ps]
+    alone = [s.solve(f, rtol=1e-8)[0].clone() for s, f in zip(solvers, fs)]
+    b = msp.Batch()
+    rounds = 0
+    while not b.tuning()["tuned"] and rounds < 12:
+        us, _ = b.solve(solvers, fs, rtol=1e-8, use_graph=True)
+        for e, u in enumerate(us):
+            assert torch.equal(u, alone[e]), (rounds, e)
+        rounds += 1
+    t = b.tuning()
+    print(f"[batch] tuned after {rounds} solves: {t}", flush=True)
+    assert t["tuned"]
+    assert t["chunk"] in (8, 16, 32) and t["largest_first"] in (0, 1)
+    assert all(c > 0 for c in t["cost_ms_per_iter_dof"])
+    g0 = b.stats()["graph_chunks"]
+    for _ in range(2):
+        us, _ = b.solve(solvers, fs, rtol=1e-8, use_graph=True)
+        for e, u in enumerate(us):
+            assert torch.equal(u, alone[e]), e
+    assert b.stats()["graph_chunks"] > g0      # the tuned shape is captured
+    assert b.tuning()["chunk"] == t["chunk"]
     b.close()
     for s in solvers:
         s.close()
