@@ -923,8 +923,12 @@ k3c_restrict(Geom g, const Nbh3* __restrict__ nbs, int S0, int S1, int S2,
 // for the rows i of one slab, and outs_i = sd_i out_i when outs is set.
 // Forward, slab k: bias = c, a = slab k-1 with xa = w (F = -C^T G there),
 // out = w.  Backward: a = slab k with xa = w (F = G_k), b = slab k+1 with
-// xb = y (F = G_k C_k), out = y, outs = c0 = S y.  Each wave takes two rows
-// with 16-byte loads.
+// xb = y (F = G_k C_k), out = y, outs = c0 = S y.  Each wave takes one row
+// with 16-byte loads, unrolled so that a lane's loads of the row (about
+// nine of each range) are in flight together: a step costs about one
+// memory latency, and four rows a workgroup put about 270 workgroups on the
+// chip for a slab of 1,088 rows.
+constexpr int SLAB_ROWS = 4;
 __global__ void __launch_bounds__(256)
 k3c_slab_step(const double* __restrict__ F, int ldk, int r0, int r1,
               const double* __restrict__ bias, const double* __restrict__ sd,
@@ -934,32 +938,26 @@ k3c_slab_step(const double* __restrict__ F, int ldk, int r0, int r1,
   __shared__ int shd;
   if (sc != nullptr && block_read_done(sc, &shd)) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i0 = r0 + blockIdx.x * 8 + 2 * wave;
-  if (i0 >= r1) return;
-  const int i1 = min(i0 + 1, r1 - 1);
-  const double* f0 = F + (long long)i0 * ldk;
-  const double* f1 = F + (long long)i1 * ldk;
-  double s0 = 0.0, s1 = 0.0, t0 = 0.0, t1 = 0.0;
+  const int i = r0 + blockIdx.x * SLAB_ROWS + wave;
+  if (i >= r1) return;
+  const double* f = F + (long long)i * ldk;
+  double s = 0.0, t = 0.0;
   // column ranges are whole 64-column blocks: 16-byte loads stay aligned
+#pragma unroll 8
   for (int j = a0 + 2 * lane; j < a1; j += 128) {
     const double2 x = *reinterpret_cast<const double2*>(xa + j);
-    const double2 p = *reinterpret_cast<const double2*>(f0 + j);
-    const double2 q = *reinterpret_cast<const double2*>(f1 + j);
-    s0 = fma(p.x, x.x, fma(p.y, x.y, s0));
-    s1 = fma(q.x, x.x, fma(q.y, x.y, s1));
+    const double2 p = *reinterpret_cast<const double2*>(f + j);
+    s = fma(p.x, x.x, fma(p.y, x.y, s));
   }
+#pragma unroll 8
   for (int j = b0 + 2 * lane; j < b1; j += 128) {
     const double2 x = *reinterpret_cast<const double2*>(xb + j);
-    const double2 p = *reinterpret_cast<const double2*>(f0 + j);
-    const double2 q = *reinterpret_cast<const double2*>(f1 + j);
-    t0 = fma(p.x, x.x, fma(p.y, x.y, t0));
-    t1 = fma(q.x, x.x, fma(q.y, x.y, t1));
+    const double2 p = *reinterpret_cast<const double2*>(f + j);
+    t = fma(p.x, x.x, fma(p.y, x.y, t));
   }
-  const double u0 = wave_sum(s0) - wave_sum(t0);
-  const double u1 = wave_sum(s1) - wave_sum(t1);
-  if (lane < 2 && (lane == 0 || i0 + 1 < r1)) {
-    const int i = lane == 0 ? i0 : i0 + 1;
-    double v = lane == 0 ? u0 : u1;
+  const double u = wave_sum(s) - wave_sum(t);
+  if (lane == 0) {
+    double v = u;
     if (bias != nullptr) v += sd[i] * bias[i];
     out[i] = v;
     if (outs != nullptr) outs[i] = sd[i] * v;
@@ -1191,16 +1189,16 @@ void launch_coarse3_solve(const double* F, int ldk, const int* sb, int nslab,
   for (int k = 0; k < nslab; ++k) {
     const int r0 = 64 * sb[k], r1 = 64 * sb[k + 1];
     const int a0 = k > 0 ? 64 * sb[k - 1] : r0, a1 = k > 0 ? r0 : r0;
-    hipLaunchKernelGGL(k3c_slab_step, dim3((r1 - r0 + 7) / 8), dim3(256), 0, s, F, ldk,
-                       r0, r1, c, sd, a0, a1, w, 0, 0, (const double*)nullptr, w,
+    hipLaunchKernelGGL(k3c_slab_step, dim3((r1 - r0 + SLAB_ROWS - 1) / SLAB_ROWS), dim3(256),
+                       0, s, F, ldk, r0, r1, c, sd, a0, a1, w, 0, 0, (const double*)nullptr, w,
                        (double*)nullptr, sc);
   }
   for (int k = nslab - 1; k >= 0; --k) {
     const int r0 = 64 * sb[k], r1 = 64 * sb[k + 1];
     const int b0 = r1, b1 = k + 1 < nslab ? 64 * sb[k + 2] : r1;
-    hipLaunchKernelGGL(k3c_slab_step, dim3((r1 - r0 + 7) / 8), dim3(256), 0, s, F, ldk,
-                       r0, r1, (const double*)nullptr, sd, r0, r1, w, b0, b1, y, y, c0,
-                       sc);
+    hipLaunchKernelGGL(k3c_slab_step, dim3((r1 - r0 + SLAB_ROWS - 1) / SLAB_ROWS), dim3(256),
+                       0, s, F, ldk, r0, r1, (const double*)nullptr, sd, r0, r1, w, b0, b1, y,
+                       y, c0, sc);
   }
 }
 
