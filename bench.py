@@ -275,6 +275,50 @@ def solve3d_workload(torch):
             **out}
 
 
+# Table 2 of the paper (contrast 1): iterations, condition and coarse
+# dimension as printed there, beside each method's run here (the paper's
+# Poisson ratio, forces and random draws are not known exactly)
+TABLE2_PAPER = {
+    "M_EE": (14, 4.6, 243), "M_EE twice": (15, 5.0, 486),
+    "M_EH": (15, 5.2, 243), "M_EH+Rot": (14, 4.6, 243),
+    "M_EH+Rot;Rand 10": (24, 13.8, 243), "M_EH+Rot;Rand 15": (25, 15.6, 243),
+    "M_EE;Rand 10": (20, 9.4, 243), "M_EE;Rand 15": (20, 9.4, 243)}
+
+
+def table2_workload(torch):
+    """The methods of the paper's Table 2 on its 100 x 100 example at
+    contrast 1 (FP64 path, PCG to 1e-6): per method the iterations, the
+    condition estimate, N_c and the setup and solve times of a warm run."""
+    import inputs
+    import paper_2006_13387_amd as msp
+    p = inputs.config_p()
+    variants = {
+        "M_EE": dict(coarse_kind=1), "M_EE twice": dict(coarse_kind=2),
+        "M_EH": dict(rot_enrich=0), "M_EH+Rot": {},
+        "M_EH+Rot;Rand 10": dict(eig_random=10, eig_seed=1),
+        "M_EH+Rot;Rand 15": dict(eig_random=15, eig_seed=1),
+        "M_EE;Rand 10": dict(coarse_kind=1, eig_random=10, eig_seed=1),
+        "M_EE;Rand 15": dict(coarse_kind=1, eig_random=15, eig_seed=1)}
+    rho = torch.tensor(p.rho, device="cuda")
+    f = torch.tensor(p.f, device="cuda")
+    out = {}
+    for name, extra in variants.items():
+        s = msp.Solver(dict(p.desc, **extra), p.fixed)
+        s.set_densities(rho)
+        s.solve(f, rtol=p.tol)                    # warm-up
+        s.set_densities(rho)
+        _, info = s.solve(f, rtol=p.tol)
+        s.close()
+        it, cond, nc = TABLE2_PAPER[name]
+        out[name] = {"iterations": info["iters"], "cond_est": round(info["cond_est"], 2),
+                     "n_coarse": info["n_coarse"], "setup_ms": round(info["t_setup_ms"], 2),
+                     "solve_ms": round(info["t_solve_ms"], 2),
+                     "paper": {"iterations": it, "condition": cond, "coarse_dim": nc}}
+    return {"workload": "square2d_100x100, 10x10 coarse blocks, vertex neighbourhoods, "
+                        "every edge clamped, contrast 1, PCG to 1e-6, FP64 path",
+            "methods": out}
+
+
 def level1_hbm_probe(torch, solvers, rounds=3):
     """First-level applications taken in turn over the batch's problems
     with at least 128 subdomains (whose applications fill the chip), so
@@ -831,6 +875,9 @@ def main():
             "latency_ms_p50": round(1e3 * statistics.median(lat_rnd), 3)}
         for s_ in rnd:
             s_.close()
+    if not args.quick:
+        log("[bench] the paper's Table 2 methods")
+        out["paper_table2"] = table2_workload(torch)
     if not args.quick and not args.no_3d:
         log("[bench] 3D two-level solve")
         out["solve3d"] = solve3d_workload(torch)
