@@ -395,6 +395,9 @@ k3s_metric(Geom g, const Sub3* __restrict__ subs, int ldp, const double* __restr
 // kk read along i), the halves added through LDS.  The blocks are read in
 // FP32 (G32) unless the subdomain is flagged in use64 or G32 is null.
 constexpr int K3S_NT = 512;
+constexpr int K3S_G = 8;       // inner-index groups of the FP32 plane product
+constexpr int K3S_LB = 6;     // 16-byte loads of a group in flight together
+static_assert(K3S_MAXP / 4 * K3S_G <= K3S_NT, "every row quad needs its K3S_G lanes");
 __global__ void __launch_bounds__(K3S_NT)
 k3s_apply(Geom g, const Sub3* __restrict__ subs, int ldp, const double* __restrict__ G64,
           const float* __restrict__ G32, const uint8_t* __restrict__ use64,
@@ -458,22 +461,76 @@ k3s_apply(Geom g, const Sub3* __restrict__ subs, int ldp, const double* __restri
     }
     return acc;
   };
+  // FP32 blocks: thread (q, g) forms rows 4q..4q+3 over group g of the
+  // inner index (K3S_G groups of adjacent lanes, summed by a butterfly in a
+  // fixed order); the group's 16-byte loads of a plane go out in batches of
+  // K3S_LB, all of a batch before any of its values is used, so a plane
+  // costs a memory latency or two instead of one per few inner indices.
+  const int gq = tid / K3S_G, gg = tid & (K3S_G - 1);
+  const int gc = (np + K3S_G - 1) / K3S_G;
+  const int gkb = gg * gc, gke = min(np, gkb + gc);
+  auto gemv32 = [&](int k) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    const bool rowq = 4 * gq < np;
+    const float* Gk = G32 + sb.moff + k * ldp2 + 4 * min(gq, (ldp - 4) / 4);
+    for (int b = gkb; b < gke; b += K3S_LB) {
+      float4 v[K3S_LB];
+#pragma unroll
+      for (int u = 0; u < K3S_LB; ++u) {
+        const int kk = min(b + u, gke - 1);
+        v[u] = *reinterpret_cast<const float4*>(Gk + (long long)kk * ldp);
+      }
+#pragma unroll
+      for (int u = 0; u < K3S_LB; ++u) {
+        const double x = (b + u < gke) ? rh[min(b + u, gke - 1)] : 0.0;
+        a0 = fma((double)v[u].x, x, a0);
+        a1 = fma((double)v[u].y, x, a1);
+        a2 = fma((double)v[u].z, x, a2);
+        a3 = fma((double)v[u].w, x, a3);
+      }
+    }
+#pragma unroll
+    for (int o = 1; o < K3S_G; o <<= 1) {
+      a0 += __shfl_xor(a0, o, 64);
+      a1 += __shfl_xor(a1, o, 64);
+      a2 += __shfl_xor(a2, o, 64);
+      a3 += __shfl_xor(a3, o, 64);
+    }
+    if (gg == 0 && rowq) {
+      ph[4 * gq] = a0;
+      if (4 * gq + 1 < np) ph[4 * gq + 1] = a1;
+      if (4 * gq + 2 < np) ph[4 * gq + 2] = a2;
+      if (4 * gq + 3 < np) ph[4 * gq + 3] = a3;
+    }
+  };
   for (int k = 0; k < sb.nbz; ++k) {
     if (tid < np) rh[tid] = xl[k * np + tid] - (k > 0 ? couple(k, -1) : 0.0);
     __syncthreads();
-    const double acc = gemv(k);
-    if (hh == 1 && i < np) ph[i] = acc;
-    __syncthreads();
-    if (hh == 0 && i < np) xl[k * np + i] = acc + ph[i];
+    if (f32) {
+      gemv32(k);
+      __syncthreads();
+      if (tid < np) xl[k * np + tid] = ph[tid];
+    } else {
+      const double acc = gemv(k);
+      if (hh == 1 && i < np) ph[i] = acc;
+      __syncthreads();
+      if (hh == 0 && i < np) xl[k * np + i] = acc + ph[i];
+    }
     __syncthreads();
   }
   for (int k = sb.nbz - 2; k >= 0; --k) {
     if (tid < np) rh[tid] = couple(k, 1);
     __syncthreads();
-    const double acc = gemv(k);
-    if (hh == 1 && i < np) ph[i] = acc;
-    __syncthreads();
-    if (hh == 0 && i < np) xl[k * np + i] -= acc + ph[i];
+    if (f32) {
+      gemv32(k);
+      __syncthreads();
+      if (tid < np) xl[k * np + tid] -= ph[tid];
+    } else {
+      const double acc = gemv(k);
+      if (hh == 1 && i < np) ph[i] = acc;
+      __syncthreads();
+      if (hh == 0 && i < np) xl[k * np + i] -= acc + ph[i];
+    }
     __syncthreads();
   }
   for (int q = tid; q < sb.n; q += K3S_NT) lsol[sb.voff + q] = xl[q];
