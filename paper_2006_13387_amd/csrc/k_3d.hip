@@ -390,13 +390,15 @@ k3s_metric(Geom g, const Sub3* __restrict__ subs, int ldp, const double* __restr
 }
 
 // z_i = K_i^{-1} r_i by the plane factors: one workgroup per subdomain,
-// the box vector in LDS (r, then y, then x), thread (i, h) forms row i of
-// each plane's product over half h of the inner index (G_k symmetric: row
-// kk read along i), the halves added through LDS.  The blocks are read in
-// FP32 (G32) unless the subdomain is flagged in use64 or G32 is null.
+// the box vector in LDS (r, then y, then x); each plane's product by groups
+// of lanes over the inner index (G_k symmetric: row kk read along the
+// rows), below.  The blocks are read in FP32 (G32) unless the subdomain is
+// flagged in use64 or G32 is null.
 constexpr int K3S_NT = 512;
 constexpr int K3S_G = 8;       // inner-index groups of the FP32 plane product
-constexpr int K3S_LB = 6;     // 16-byte loads of a group in flight together
+constexpr int K3S_LB = 8;     // 16-byte loads of a group in flight together
+constexpr int K3S_G64 = 4;     // inner-index groups of the FP64 plane product
+static_assert(K3S_MAXP / 2 * K3S_G64 <= K3S_NT, "every row pair needs its K3S_G64 lanes");
 static_assert(K3S_MAXP / 4 * K3S_G <= K3S_NT, "every row quad needs its K3S_G lanes");
 __global__ void __launch_bounds__(K3S_NT)
 k3s_apply(Geom g, const Sub3* __restrict__ subs, int ldp, const double* __restrict__ G64,
@@ -424,8 +426,6 @@ k3s_apply(Geom g, const Sub3* __restrict__ subs, int ldp, const double* __restri
     xl[q] = mask[3 * node + c] ? 0.0 : r[3 * node + c];
   }
   __syncthreads();
-  const int i = tid & (K3S_MAXP - 1), hh = tid / K3S_MAXP;
-  const int half = (np + 1) / 2, kk0 = hh * half, kk1 = min(np, kk0 + half);
   const long long ldp2 = (long long)ldp * ldp;
   const int an = tid / 3, ca = tid - 3 * (tid / 3);
   const int ax = tid < np ? an % sb.nbx : 0, ay = tid < np ? an / sb.nbx : 0;
@@ -445,21 +445,6 @@ k3s_apply(Geom g, const Sub3* __restrict__ subs, int ldp, const double* __restri
       s = fma(k3_coef_l(sb, El, Ke, X, Y, Z, dx, dy, dz, ca, cj), xp[3 * (jy * sb.nbx + jx) + cj], s);
     }
     return s;
-  };
-  auto gemv = [&](int k) -> double {
-    double acc = 0.0;
-    if (i < np) {
-      if (f32) {
-        const float* Gk = G32 + sb.moff + k * ldp2 + i;
-#pragma unroll 4
-        for (int kk = kk0; kk < kk1; ++kk) acc = fma((double)Gk[(long long)kk * ldp], rh[kk], acc);
-      } else {
-        const double* Gk = G64 + sb.moff + k * ldp2 + i;
-#pragma unroll 4
-        for (int kk = kk0; kk < kk1; ++kk) acc = fma(Gk[(long long)kk * ldp], rh[kk], acc);
-      }
-    }
-    return acc;
   };
   // FP32 blocks: thread (q, g) forms rows 4q..4q+3 over group g of the
   // inner index (K3S_G groups of adjacent lanes, summed by a butterfly in a
@@ -503,34 +488,55 @@ k3s_apply(Geom g, const Sub3* __restrict__ subs, int ldp, const double* __restri
       if (4 * gq + 3 < np) ph[4 * gq + 3] = a3;
     }
   };
+  // FP64 blocks alike: thread (pair, g) forms rows 2 pair, 2 pair + 1 over
+  // group g of K3S_G64 groups, 16-byte loads in batches of K3S_LB
+  const int hq = tid / K3S_G64, hg = tid & (K3S_G64 - 1);
+  const int hc = (np + K3S_G64 - 1) / K3S_G64;
+  const int hkb = hg * hc, hke = min(np, hkb + hc);
+  auto gemv64 = [&](int k) {
+    double a0 = 0.0, a1 = 0.0;
+    const bool rowp = 2 * hq < np;
+    const double* Gk = G64 + sb.moff + k * ldp2 + 2 * min(hq, (ldp - 2) / 2);
+    for (int b = hkb; b < hke; b += K3S_LB) {
+      double2 v[K3S_LB];
+#pragma unroll
+      for (int u = 0; u < K3S_LB; ++u) {
+        const int kk = min(b + u, hke - 1);
+        v[u] = *reinterpret_cast<const double2*>(Gk + (long long)kk * ldp);
+      }
+#pragma unroll
+      for (int u = 0; u < K3S_LB; ++u) {
+        const double x = (b + u < hke) ? rh[min(b + u, hke - 1)] : 0.0;
+        a0 = fma(v[u].x, x, a0);
+        a1 = fma(v[u].y, x, a1);
+      }
+    }
+#pragma unroll
+    for (int o = 1; o < K3S_G64; o <<= 1) {
+      a0 += __shfl_xor(a0, o, 64);
+      a1 += __shfl_xor(a1, o, 64);
+    }
+    if (hg == 0 && rowp) {
+      ph[2 * hq] = a0;
+      if (2 * hq + 1 < np) ph[2 * hq + 1] = a1;
+    }
+  };
   for (int k = 0; k < sb.nbz; ++k) {
     if (tid < np) rh[tid] = xl[k * np + tid] - (k > 0 ? couple(k, -1) : 0.0);
     __syncthreads();
-    if (f32) {
-      gemv32(k);
-      __syncthreads();
-      if (tid < np) xl[k * np + tid] = ph[tid];
-    } else {
-      const double acc = gemv(k);
-      if (hh == 1 && i < np) ph[i] = acc;
-      __syncthreads();
-      if (hh == 0 && i < np) xl[k * np + i] = acc + ph[i];
-    }
+    if (f32) gemv32(k);
+    else gemv64(k);
+    __syncthreads();
+    if (tid < np) xl[k * np + tid] = ph[tid];
     __syncthreads();
   }
   for (int k = sb.nbz - 2; k >= 0; --k) {
     if (tid < np) rh[tid] = couple(k, 1);
     __syncthreads();
-    if (f32) {
-      gemv32(k);
-      __syncthreads();
-      if (tid < np) xl[k * np + tid] -= ph[tid];
-    } else {
-      const double acc = gemv(k);
-      if (hh == 1 && i < np) ph[i] = acc;
-      __syncthreads();
-      if (hh == 0 && i < np) xl[k * np + i] -= acc + ph[i];
-    }
+    if (f32) gemv32(k);
+    else gemv64(k);
+    __syncthreads();
+    if (tid < np) xl[k * np + tid] -= ph[tid];
     __syncthreads();
   }
   for (int q = tid; q < sb.n; q += K3S_NT) lsol[sb.voff + q] = xl[q];
