@@ -411,6 +411,7 @@ k3s_apply(Geom g, const Sub3* __restrict__ subs, int ldp, const double* __restri
   __shared__ double xl[LD3_MAX];
   __shared__ double rh[K3S_MAXP];
   __shared__ double ph[K3S_MAXP];
+  __shared__ uint8_t fl[LD3_MAX];
   __shared__ int shd;
   if (sc != nullptr && block_read_done(sc, &shd)) return;
   const Sub3 sb = subs[blockIdx.x];
@@ -423,7 +424,9 @@ k3s_apply(Geom g, const Sub3* __restrict__ subs, int ldp, const double* __restri
     const int a = q / 3, c = q - 3 * (q / 3);
     const int lx = a % sb.nbx, ly = (a / sb.nbx) % sb.nby, lz = a / (sb.nbx * sb.nby);
     const long long node = ((long long)(sb.z0 + lz) * g.nny + sb.y0 + ly) * g.nnx + sb.x0 + lx;
-    xl[q] = mask[3 * node + c] ? 0.0 : r[3 * node + c];
+    const uint8_t mq = mask[3 * node + c];
+    fl[q] = mq;
+    xl[q] = mq ? 0.0 : r[3 * node + c];
   }
   __syncthreads();
   const long long ldp2 = (long long)ldp * ldp;
@@ -431,17 +434,21 @@ k3s_apply(Geom g, const Sub3* __restrict__ subs, int ldp, const double* __restri
   const int ax = tid < np ? an % sb.nbx : 0, ay = tid < np ? an / sb.nbx : 0;
   // sum over the 27 DOFs of the 9 neighbours in plane k + dz of the coupling
   // times the box vector there
+  // The box vector is zero at clamped DOFs from the start and stays zero
+  // (their rows and columns of the plane factors are the identity's), so
+  // clamped neighbours add exactly nothing and need no test; only the
+  // thread's own DOF is checked, from the clamp flags staged in LDS.
   auto couple = [&](int k, int dz) -> double {
+    if (fl[k * np + tid]) return 0.0;
     const int X = sb.x0 + ax, Y = sb.y0 + ay, Z = sb.z0 + k;
-    if (k3_fixed(g, mask, X, Y, Z, ca)) return 0.0;
     const double* xp = xl + (k + dz) * np;
     double s = 0.0;
+#pragma unroll
     for (int q = 0; q < 27; ++q) {
       const int nq = q / 3, cj = q - 3 * (q / 3);
       const int dx = nq % 3 - 1, dy = nq / 3 - 1;
       const int jx = ax + dx, jy = ay + dy;
       if (jx < 0 || jx >= sb.nbx || jy < 0 || jy >= sb.nby) continue;
-      if (k3_fixed(g, mask, X + dx, Y + dy, Z + dz, cj)) continue;
       s = fma(k3_coef_l(sb, El, Ke, X, Y, Z, dx, dy, dz, ca, cj), xp[3 * (jy * sb.nbx + jx) + cj], s);
     }
     return s;
