@@ -259,14 +259,18 @@ k3h_stencil(Geom g, const Nbh3* __restrict__ nbs, int ldp,
     live = !nmask[node_id(g, w.x0 + ax, w.y0 + ay, w.z0 + k)];
   }
   if (live) {
+    // the vectors are zero at clamped nodes (so a clamped neighbour adds
+    // exactly nothing and is not tested)
     const int X = w.x0 + ax, Y = w.y0 + ay, Z = w.z0 + k;
+#pragma unroll
     for (int dz = -1; dz <= 1; ++dz) {
       if (k + dz < 0 || k + dz >= w.nbz) continue;
+#pragma unroll
       for (int dy = -1; dy <= 1; ++dy) {
         if (ay + dy < 0 || ay + dy >= w.nby) continue;
+#pragma unroll
         for (int dx = -1; dx <= 1; ++dx) {
           if (ax + dx < 0 || ax + dx >= w.nbx) continue;
-          if (nmask[node_id(g, X + dx, Y + dy, Z + dz)]) continue;
           // the mass coupling, and the stiffness one into cA
           double cA = 0.0;
           const double cM = pair_coef(g, w, E, el + 64, BOTH ? el : nullptr,
@@ -339,16 +343,21 @@ k3h_sweep(Geom g, const Nbh3* __restrict__ nbs, int ldp,
       for (int c = 0; c < M; ++c) acc[c] = fma(gv, rr[c], acc[c]);
     }
   };
-  // the coupling of row tid with its 9 neighbours in plane k + dz
+  // the coupling of row tid (not clamped) with its 9 neighbours in plane
+  // k + dz.  The right-hand sides are zero at clamped nodes and G_k's rows
+  // and columns there are the identity's, so the vectors stay zero there:
+  // a clamped neighbour adds exactly nothing and is not tested.
   auto couple = [&](int k, int dz, int q, int* nb_) -> double {
     const int dx = q % 3 - 1, dy = q / 3 - 1;
     const int jx = ax + dx, jy = ay + dy;
     *nb_ = -1;
     if (jx < 0 || jx >= w.nbx || jy < 0 || jy >= w.nby) return 0.0;
     const int X = w.x0 + ax, Y = w.y0 + ay, Z = w.z0 + k;
-    if (nmask[node_id(g, X, Y, Z)] || nmask[node_id(g, X + dx, Y + dy, Z + dz)]) return 0.0;
     *nb_ = jy * w.nbx + jx;
     return pair_coef(g, w, E, el, nullptr, nullptr, X, Y, Z, dx, dy, dz);
+  };
+  auto clamped = [&](int k) -> bool {
+    return nmask[node_id(g, w.x0 + ax, w.y0 + ay, w.z0 + k)] != 0;
   };
   double acc[M];
   for (int k = 0; k < w.nbz; ++k) {
@@ -357,7 +366,8 @@ k3h_sweep(Geom g, const Nbh3* __restrict__ nbs, int ldp,
       const double* br = B + w.xoff + ((long long)k * ldp + tid) * M;
 #pragma unroll
       for (int c = 0; c < M; ++c) r[c] = tid < np ? br[c] : 0.0;
-      if (k > 0 && tid < np) {
+      if (k > 0 && tid < np && !clamped(k)) {
+#pragma unroll
         for (int q = 0; q < 9; ++q) {
           int j;
           const double cf = couple(k, -1, q, &j);
@@ -393,7 +403,8 @@ k3h_sweep(Geom g, const Nbh3* __restrict__ nbs, int ldp,
       double v[M];
 #pragma unroll
       for (int c = 0; c < M; ++c) v[c] = 0.0;
-      if (tid < np) {
+      if (tid < np && !clamped(k)) {
+#pragma unroll
         for (int q = 0; q < 9; ++q) {
           int j;
           const double cf = couple(k, 1, q, &j);
