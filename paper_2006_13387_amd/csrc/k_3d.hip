@@ -52,23 +52,47 @@ k3_scale(double* __restrict__ A, int ld, long long mstride,
 }
 
 // Undo the scaling of the inverse, symmetrised: B_ij = (A_ij + A_ji)/2 s_i
-// s_j, in place (FP64), and rounded into the FP32 pool when given.  The
-// thread of (i, j), j >= i, owns both entries of the pair.
-__global__ void __launch_bounds__(T3_NT)
+// s_j, in place (FP64), and rounded into the FP32 pool when given.  One
+// workgroup per pair of mirror tiles (US_T x US_T, the upper triangle's
+// tiles in row order): both tiles staged in LDS, then written row-wise.
+constexpr int US_T = 32;
+__global__ void __launch_bounds__(256)
 k3_unscale(double* __restrict__ A, int ld, long long mstride,
            const double* __restrict__ sdiag, float* __restrict__ A32) {
-  const long long idx = (long long)blockIdx.x * T3_NT + threadIdx.x;
-  if (idx >= (long long)ld * ld) return;
-  const int i = (int)(idx / ld), j = (int)(idx - (long long)(idx / ld) * ld);
+  __shared__ double t1[US_T][US_T + 1], t2[US_T][US_T + 1];
+  const int nt = ld / US_T;
+  int p = blockIdx.x, I = 0;
+  while (p >= nt - I) {       // tile pair (I, J), I <= J, row by row
+    p -= nt - I;
+    ++I;
+  }
+  const int J = I + p;
   double* M = A + blockIdx.y * mstride;
+  float* M32 = A32 != nullptr ? A32 + blockIdx.y * mstride : nullptr;
   const double* sd = sdiag + (long long)blockIdx.y * ld;
-  if (j < i) return;
-  const double v = 0.5 * (M[(long long)i * ld + j] + M[(long long)j * ld + i]) * sd[i] * sd[j];
-  M[(long long)i * ld + j] = v;
-  M[(long long)j * ld + i] = v;
-  if (A32 != nullptr) {
-    A32[blockIdx.y * mstride + (long long)i * ld + j] = (float)v;
-    A32[blockIdx.y * mstride + (long long)j * ld + i] = (float)v;
+  const int tx = threadIdx.x & (US_T - 1), ty = threadIdx.x / US_T;
+  for (int r = ty; r < US_T; r += 256 / US_T) {
+    t1[r][tx] = M[(long long)(I * US_T + r) * ld + J * US_T + tx];
+    t2[r][tx] = M[(long long)(J * US_T + r) * ld + I * US_T + tx];
+  }
+  __syncthreads();
+  // entry (i, j) from the symmetric pair A(lo, hi) + A(hi, lo), scaled by
+  // sd_lo then sd_hi (lo = min(i, j)), so both halves get the same bits
+  auto put = [&](int i, int j, double a_lohi, double a_hilo) {
+    const int lo = min(i, j), hi = max(i, j);
+    const double v = 0.5 * (a_lohi + a_hilo) * sd[lo] * sd[hi];
+    M[(long long)i * ld + j] = v;
+    if (M32 != nullptr) M32[(long long)i * ld + j] = (float)v;
+  };
+  for (int r = ty; r < US_T; r += 256 / US_T) {
+    const int i = I * US_T + r, j = J * US_T + tx;
+    if (i <= j) put(i, j, t1[r][tx], t2[tx][r]);     // A(i, j), A(j, i)
+    else put(i, j, t2[tx][r], t1[r][tx]);            // diagonal tile, i > j
+    if (I != J) {
+      // the mirror tile, row J*US_T + r, column I*US_T + tx
+      const int mi = J * US_T + r, mj = I * US_T + tx;
+      put(mi, mj, t1[tx][r], t2[r][tx]);
+    }
   }
 }
 
@@ -749,7 +773,8 @@ void launch_local_inverse3_strided(double* A, int ld, int nsub, long long ms,
   // reported as a failed setup
   launch_gj_steps(A, ld, nsub, GjStride{ms, 64LL * 65, 64LL * ld}, LD, Lp, Rp,
                   0.0, dropped, s);
-  hipLaunchKernelGGL(k3_unscale, dim3(nbe, nsub), dim3(T3_NT), 0, s, A, ld, ms,
+  const int nt = ld / US_T;
+  hipLaunchKernelGGL(k3_unscale, dim3(nt * (nt + 1) / 2, nsub), dim3(256), 0, s, A, ld, ms,
                      sdiag, A32);
 }
 
