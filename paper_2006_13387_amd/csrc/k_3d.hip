@@ -351,6 +351,20 @@ k3s_schur(Geom g, const Sub3* __restrict__ subs, int k, int ldp,
   const int ax = arow ? an % sb.nbx : 0, ay = arow ? an / sb.nbx : 0;
   const bool rem = !arow || k3_fixed(g, mask, sb.x0 + ax, sb.y0 + ay, Z, ca);
   const int X = sb.x0 + ax, Y = sb.y0 + ay;
+  // row a's couplings with the 27 DOFs of its neighbours in plane k-1,
+  // formed once for all columns.  T is zero at clamped DOFs (their C
+  // entries are zero and G_{k-1} is the identity there), so they need no
+  // test here.
+  double cq[27];
+  int iq[27];
+#pragma unroll
+  for (int q = 0; q < 27; ++q) {
+    const int nq = q / 3, ci = q - 3 * (q / 3);
+    const int ix = ax + nq % 3 - 1, iy = ay + nq / 3 - 1;
+    const bool ok = k > 0 && !rem && ix >= 0 && ix < sb.nbx && iy >= 0 && iy < sb.nby;
+    iq[q] = ok ? 3 * (iy * sb.nbx + ix) + ci : 0;
+    cq[q] = ok ? k3_coef_l(sb, El, Ke, X, Y, Z, nq % 3 - 1, nq / 3 - 1, -1, ca, ci) : 0.0;
+  }
   for (int t = 0; t < K3S_CB; ++t) {
     const int b = b0 + t;
     double v;
@@ -364,14 +378,8 @@ k3s_schur(Geom g, const Sub3* __restrict__ subs, int k, int ldp,
           !k3_fixed(g, mask, X + dx, Y + dy, Z, cb))
         v = k3_coef_l(sb, El, Ke, X, Y, Z, dx, dy, 0, ca, cb);
       if (k > 0) {
-        for (int q = 0; q < 27; ++q) {
-          const int nq = q / 3, ci = q - 3 * (q / 3);
-          const int ix = ax + nq % 3 - 1, iy = ay + nq / 3 - 1;
-          if (ix < 0 || ix >= sb.nbx || iy < 0 || iy >= sb.nby) continue;
-          if (k3_fixed(g, mask, sb.x0 + ix, sb.y0 + iy, Z - 1, ci)) continue;
-          const double c = k3_coef_l(sb, El, Ke, X, Y, Z, nq % 3 - 1, nq / 3 - 1, -1, ca, ci);
-          v -= c * T[(3 * (iy * sb.nbx + ix) + ci) * K3S_CB + t];
-        }
+#pragma unroll
+        for (int q = 0; q < 27; ++q) v -= cq[q] * T[iq[q] * K3S_CB + t];
       }
     }
     Sk[(long long)b * ldp + a] = v;
