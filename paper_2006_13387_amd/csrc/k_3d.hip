@@ -497,7 +497,7 @@ k3s_apply(Geom g, const Sub3* __restrict__ subs, int ldp, const double* __restri
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     const bool rowq = 4 * gq < np;
     const float* Gk = G32 + sb.moff + k * ldp2 + 4 * min(gq, (ldp - 4) / 4);
-    for (int b = gkb; b < gke; b += K3S_LB) {
+    for (int b = gkb; rowq && b < gke; b += K3S_LB) {
       float4 v[K3S_LB];
 #pragma unroll
       for (int u = 0; u < K3S_LB; ++u) {
@@ -536,7 +536,7 @@ k3s_apply(Geom g, const Sub3* __restrict__ subs, int ldp, const double* __restri
     double a0 = 0.0, a1 = 0.0;
     const bool rowp = 2 * hq < np;
     const double* Gk = G64 + sb.moff + k * ldp2 + 2 * min(hq, (ldp - 2) / 2);
-    for (int b = hkb; b < hke; b += K3S_LB) {
+    for (int b = hkb; rowp && b < hke; b += K3S_LB) {
       double2 v[K3S_LB];
 #pragma unroll
       for (int u = 0; u < K3S_LB; ++u) {
