@@ -322,8 +322,10 @@ k3h_sweep(Geom g, const Nbh3* __restrict__ nbs, int ldp,
   const int i = tid & (C3_MAXP - 1), hh = tid / C3_MAXP;
   if (tid < 64) el[tid] = hel[tid] + sigma * hel[64 + tid];
   const long long ldp2 = (long long)ldp * ldp;
-  const int half = ldp / 2, kk0 = hh * half;
   const int np = w.np;
+  // rows and inner indices past the plane's nodes are padding (identity
+  // rows of G_k on zero right-hand sides): neither half reads them
+  const int half = (np + 1) / 2, kk0 = hh * half, kk1 = min(np, kk0 + half);
   int ax = 0, ay = 0;
   if (tid < np) {
     ax = tid % w.nbx;
@@ -333,10 +335,10 @@ k3h_sweep(Geom g, const Nbh3* __restrict__ nbs, int ldp,
   auto gemm = [&](int k, double (&acc)[M]) {
 #pragma unroll
     for (int c = 0; c < M; ++c) acc[c] = 0.0;
-    if (i >= ldp) return;
+    if (i >= np) return;
     const double* Gk = G + w.goff + k * ldp2 + i;
 #pragma unroll 4
-    for (int kk = kk0; kk < kk0 + half; ++kk) {
+    for (int kk = kk0; kk < kk1; ++kk) {
       const double gv = Gk[(long long)kk * ldp];
       const double* rr = R + kk * M;
 #pragma unroll
