@@ -382,17 +382,19 @@ k2e_sweep(Geom g, const Nbh3* __restrict__ nbs, int ldp,
   if (tid < 64) Ke[tid] = Ke_g[tid];
   if (tid < 16) Ms[tid] = Ms_g[tid];
   const long long ldp2 = (long long)ldp * ldp;
-  const int half = ldp / 2, kk0 = hh * half;
   const int np = w.np;
+  // rows and inner indices past the row's unknowns are padding (identity
+  // rows of G_k on zero right-hand sides): neither half reads them
+  const int half = (np + 1) / 2, kk0 = hh * half, kk1 = min(np, kk0 + half);
   const int ax = tid >> 1, ca = tid & 1;
   __syncthreads();
   auto gemm = [&](int k, double (&acc)[M]) {
 #pragma unroll
     for (int c = 0; c < M; ++c) acc[c] = 0.0;
-    if (i >= ldp) return;
+    if (i >= np) return;
     const double* Gk = G + w.goff + k * ldp2 + i;
 #pragma unroll 4
-    for (int kk = kk0; kk < kk0 + half; ++kk) {
+    for (int kk = kk0; kk < kk1; ++kk) {
       const double gv = Gk[(long long)kk * ldp];
       const double* rr = R + kk * M;
 #pragma unroll
