@@ -887,10 +887,13 @@ k3c_restrict(Geom g, const Nbh3* __restrict__ nbs, int S0, int S1, int S2,
                          (1.0 - fabs((double)rz_) / S2);
       if (!(chi > 0.0)) continue;
       const long long node = node_id(g, w.x0 + a % w.nbx, w.y0 + a / w.nbx, w.z0 + k);
+      // the mask, r and the modes are loaded together (no load waits for
+      // the mask), the clamped components dropped afterwards
       const int mb = nmask[node];
-      const double r0 = (mb & 1) ? 0.0 : chi * r[3 * node];
-      const double r1 = (mb & 2) ? 0.0 : chi * r[3 * node + 1];
-      const double r2 = (mb & 4) ? 0.0 : chi * r[3 * node + 2];
+      const double rv0 = r[3 * node], rv1 = r[3 * node + 1], rv2 = r[3 * node + 2];
+      const double r0 = (mb & 1) ? 0.0 : chi * rv0;
+      const double r1 = (mb & 2) ? 0.0 : chi * rv1;
+      const double r2 = (mb & 4) ? 0.0 : chi * rv2;
       const double* ps = psi + w.psi_off + (long long)b * nm + j0;
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
