@@ -305,6 +305,7 @@ k3h_stencil(Geom g, const Nbh3* __restrict__ nbs, int ldp,
 // contiguous.  The halves are added through LDS.  The two row blocks R
 // and P (ldp x M each) are dynamic LDS sized by the plane order, so that
 // two workgroups fit a CU at ldp = 192, M = 24.
+constexpr int SW_LB = 8;       // loads of a sweep product batch
 template <int M>
 __global__ void __launch_bounds__(HS_NT)
 k3h_sweep(Geom g, const Nbh3* __restrict__ nbs, int ldp,
@@ -337,12 +338,20 @@ k3h_sweep(Geom g, const Nbh3* __restrict__ nbs, int ldp,
     for (int c = 0; c < M; ++c) acc[c] = 0.0;
     if (i >= np) return;
     const double* Gk = G + w.goff + k * ldp2 + i;
-#pragma unroll 4
-    for (int kk = kk0; kk < kk1; ++kk) {
-      const double gv = Gk[(long long)kk * ldp];
-      const double* rr = R + kk * M;
+    // the column's loads in batches of SW_LB, all of a batch issued before
+    // any is used (a plain loop waits for each few in turn)
+    for (int kb = kk0; kb < kk1; kb += SW_LB) {
+      double gv[SW_LB];
 #pragma unroll
-      for (int c = 0; c < M; ++c) acc[c] = fma(gv, rr[c], acc[c]);
+      for (int u = 0; u < SW_LB; ++u) gv[u] = Gk[(long long)min(kb + u, kk1 - 1) * ldp];
+#pragma unroll
+      for (int u = 0; u < SW_LB; ++u) {
+        if (kb + u < kk1) {
+          const double* rr = R + (kb + u) * M;
+#pragma unroll
+          for (int c = 0; c < M; ++c) acc[c] = fma(gv[u], rr[c], acc[c]);
+        }
+      }
     }
   };
   // the coupling of row tid (not clamped) with its 9 neighbours in plane
