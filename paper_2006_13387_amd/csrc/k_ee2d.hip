@@ -27,6 +27,7 @@ constexpr int E2_NT = 256;     // row kernels: a thread per unknown of a row
 constexpr int E2_MAXP = 256;   // largest padded row order
 constexpr int E2_SW = 512;     // sweep workgroup
 constexpr int E2_CB = 16;      // columns of a Schur-complement workgroup
+constexpr int E2_LB = 8;       // loads of a sweep product batch
 
 // Coupling of unknown (X, Y, ca) with (X + dx, Y + dy, cb) in
 // Ke + sigma (Me on each component) (unit-square element matrices: Ke 8 x 8
@@ -393,12 +394,19 @@ k2e_sweep(Geom g, const Nbh3* __restrict__ nbs, int ldp,
     for (int c = 0; c < M; ++c) acc[c] = 0.0;
     if (i >= np) return;
     const double* Gk = G + w.goff + k * ldp2 + i;
-#pragma unroll 4
-    for (int kk = kk0; kk < kk1; ++kk) {
-      const double gv = Gk[(long long)kk * ldp];
-      const double* rr = R + kk * M;
+    // the column's loads in batches of E2_LB, all of a batch issued first
+    for (int kb = kk0; kb < kk1; kb += E2_LB) {
+      double gv[E2_LB];
 #pragma unroll
-      for (int c = 0; c < M; ++c) acc[c] = fma(gv, rr[c], acc[c]);
+      for (int u = 0; u < E2_LB; ++u) gv[u] = Gk[(long long)min(kb + u, kk1 - 1) * ldp];
+#pragma unroll
+      for (int u = 0; u < E2_LB; ++u) {
+        if (kb + u < kk1) {
+          const double* rr = R + (kb + u) * M;
+#pragma unroll
+          for (int c = 0; c < M; ++c) acc[c] = fma(gv[u], rr[c], acc[c]);
+        }
+      }
     }
   };
   // coupling of unknown tid (row k) with unknown q of the three nodes in
