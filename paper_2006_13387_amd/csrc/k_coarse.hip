@@ -213,16 +213,44 @@ __global__ void k_k0_scale_factors(const double* __restrict__ K0, int ldk,
   sdiag[j] = s;
 }
 
-__global__ void k_k0_scale(double* __restrict__ K0, int ldk,
-                           const double* __restrict__ sdiag) {
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long n2 = (long long)ldk * ldk;
-  if (idx >= n2) return;
-  const int i = (int)(idx / ldk), j = (int)(idx - (idx / ldk) * ldk);
-  if (j < i) return;
-  const double v = 0.5 * (K0[(long long)i * ldk + j] + K0[(long long)j * ldk + i]) * sdiag[i] * sdiag[j];
-  K0[(long long)i * ldk + j] = v;
-  K0[(long long)j * ldk + i] = v;
+// K0 <- S ((K0 + K0^T) / 2) S, S = diag(sdiag), in place: one workgroup per
+// pair of mirror tiles (K0T_T x K0T_T, the upper triangle's tiles in row
+// order), both staged in LDS and written row-wise; entry (i, j) is
+// 0.5 (K0_lo,hi + K0_hi,lo) s_lo s_hi (lo = min(i, j)), so the two halves
+// get the same bits.  Used for the scaling and for undoing it.
+constexpr int K0T_T = 32;
+__global__ void __launch_bounds__(256)
+k_k0_scale(double* __restrict__ K0, int ldk, const double* __restrict__ sdiag) {
+  __shared__ double t1[K0T_T][K0T_T + 1], t2[K0T_T][K0T_T + 1];
+  const int nt = ldk / K0T_T;
+  long long p = blockIdx.x;
+  int I = 0;
+  while (p >= nt - I) {
+    p -= nt - I;
+    ++I;
+  }
+  const int J = I + (int)p;
+  const int tx = threadIdx.x & (K0T_T - 1), ty = threadIdx.x / K0T_T;
+  for (int r = ty; r < K0T_T; r += 256 / K0T_T) {
+    t1[r][tx] = K0[(long long)(I * K0T_T + r) * ldk + J * K0T_T + tx];
+    t2[r][tx] = K0[(long long)(J * K0T_T + r) * ldk + I * K0T_T + tx];
+  }
+  __syncthreads();
+  auto put = [&](int i, int j, double a_lohi, double a_hilo) {
+    const int lo = min(i, j), hi = max(i, j);
+    K0[(long long)i * ldk + j] = 0.5 * (a_lohi + a_hilo) * sdiag[lo] * sdiag[hi];
+  };
+  for (int r = ty; r < K0T_T; r += 256 / K0T_T) {
+    const int i = I * K0T_T + r, j = J * K0T_T + tx;
+    if (i <= j) put(i, j, t1[r][tx], t2[tx][r]);
+    else put(i, j, t2[tx][r], t1[r][tx]);
+    if (I != J) put(J * K0T_T + r, I * K0T_T + tx, t1[tx][r], t2[r][tx]);
+  }
+}
+
+static unsigned k0_scale_grid(int ldk) {
+  const long long nt = ldk / K0T_T;
+  return (unsigned)(nt * (nt + 1) / 2);
 }
 
 // Blocked Gauss-Jordan on the scaled K_0, block k: invert the 64 x 64
@@ -491,18 +519,6 @@ k_gj_update(double* __restrict__ A, int ld, int kb, int b0,
       A[(ibase + 16 * wave + lk + 4 * r) * ld + jbase + 16 * C + li] = acc[C][r];
 }
 
-// K0p = S A S (undo the scaling), symmetrised.
-__global__ void k_k0_unscale(double* __restrict__ K0, int ldk,
-                             const double* __restrict__ sdiag) {
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long n2 = (long long)ldk * ldk;
-  if (idx >= n2) return;
-  const int i = (int)(idx / ldk), j = (int)(idx - (idx / ldk) * ldk);
-  if (j < i) return;
-  const double v = 0.5 * (K0[(long long)i * ldk + j] + K0[(long long)j * ldk + i]) * sdiag[i] * sdiag[j];
-  K0[(long long)i * ldk + j] = v;
-  K0[(long long)j * ldk + i] = v;
-}
 
 // ---------------------------------------------------------------------
 // Restriction c = R_0 r: RS_CH workgroups per coarse node, each over a
@@ -1069,12 +1085,10 @@ void launch_k0_pinv(double* K0, int ldk, int nc, int dep_col, int ndep,
                     double* Rp, double tol, int* dropped, hipStream_t s) {
   hipLaunchKernelGGL(k_k0_scale_factors, dim3((ldk + 255) / 256), dim3(256), 0,
                      s, K0, ldk, nc, dep_col, ndep, drop, sdiag);
-  const long long n2 = (long long)ldk * ldk;
-  hipLaunchKernelGGL(k_k0_scale, dim3((unsigned)((n2 + 255) / 256)), dim3(256),
-                     0, s, K0, ldk, sdiag);
+  hipLaunchKernelGGL(k_k0_scale, dim3(k0_scale_grid(ldk)), dim3(256), 0, s, K0, ldk, sdiag);
   launch_gj_steps(K0, ldk, 1, GjStride{0, 0, 0}, P, Lp, Rp, tol, dropped, s);
-  hipLaunchKernelGGL(k_k0_unscale, dim3((unsigned)((n2 + 255) / 256)),
-                     dim3(256), 0, s, K0, ldk, sdiag);
+  // undo the scaling: the same symmetric product with S
+  hipLaunchKernelGGL(k_k0_scale, dim3(k0_scale_grid(ldk)), dim3(256), 0, s, K0, ldk, sdiag);
 }
 
 void launch_gj_slabs(double*, int, const int*, int, double*, double*, double*, double,
@@ -1089,9 +1103,7 @@ void launch_k0_slab_factor(double* K0, int ldk, const int* sb, int nslab,
                            double* Rp, double tol, int* dropped, hipStream_t s) {
   hipLaunchKernelGGL(k_k0_scale_factors, dim3((ldk + 255) / 256), dim3(256), 0,
                      s, K0, ldk, ldk, -1, 0, drop, sdiag);
-  const long long n2 = (long long)ldk * ldk;
-  hipLaunchKernelGGL(k_k0_scale, dim3((unsigned)((n2 + 255) / 256)), dim3(256),
-                     0, s, K0, ldk, sdiag);
+  hipLaunchKernelGGL(k_k0_scale, dim3(k0_scale_grid(ldk)), dim3(256), 0, s, K0, ldk, sdiag);
   launch_gj_slabs(K0, ldk, sb, nslab, P, Lp, Rp, tol, dropped, s);
 }
 
