@@ -333,12 +333,15 @@ k3s_schur(Geom g, const Sub3* __restrict__ subs, int k, int ldp,
   __syncthreads();
   if (k > 0 && tid < ldp) {
     const double* Gp = Sk - ldp2;
+    // every load of a column issued at once (an absent coupling reads row
+    // 0 and weighs it by 0, which adds exactly nothing)
     for (int t = 0; t < K3S_CB; ++t) {
       double acc = 0.0;
+#pragma unroll
       for (int q = 0; q < 27; ++q) {
         const int j = Jb[t * 27 + q];
-        const double c = Cb[t * 27 + q];
-        if (j >= 0 && c != 0.0) acc += Gp[(long long)j * ldp + tid] * c;
+        const double c = j >= 0 ? Cb[t * 27 + q] : 0.0;
+        acc = fma(Gp[(long long)max(j, 0) * ldp + tid], c, acc);
       }
       T[tid * K3S_CB + t] = acc;
     }

@@ -135,13 +135,15 @@ k3h_schur(Geom g, const Nbh3* __restrict__ nbs, int k, int ldp,
   // T(i, t) = sum_q G_{k-1}(i, j_q) C(j_q, b_t)  (G symmetric: row j_q at i)
   if (k > 0 && tid < ldp) {
     const double* Gp = Sk - ldp2;
+    // every load of a column issued at once (an absent coupling reads row
+    // 0 and weighs it by 0, which adds exactly nothing)
     for (int t = 0; t < SC_CB; ++t) {
       double s = 0.0;
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
         const int j = Jb[t * 9 + q];
-        const double c = Cb[t * 9 + q];
-        if (j >= 0 && c != 0.0) s += Gp[(long long)j * ldp + tid] * c;
+        const double c = j >= 0 ? Cb[t * 9 + q] : 0.0;
+        s = fma(Gp[(long long)max(j, 0) * ldp + tid], c, s);
       }
       T[tid * SC_CB + t] = s;
     }
