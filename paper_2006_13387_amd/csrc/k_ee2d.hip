@@ -118,13 +118,15 @@ k2e_schur(Geom g, const Nbh3* __restrict__ nbs, int k, int ldp,
   __syncthreads();
   if (k > 0 && tid < ldp) {
     const double* Gp = Sk - ldp2;
+    // every load of a column issued at once (an absent coupling reads row
+    // 0 and weighs it by 0, which adds exactly nothing)
     for (int t = 0; t < E2_CB; ++t) {
       double s = 0.0;
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
         const int j = Jb[t * 6 + q];
-        const double c = Cb[t * 6 + q];
-        if (j >= 0 && c != 0.0) s += Gp[(long long)j * ldp + tid] * c;
+        const double c = j >= 0 ? Cb[t * 6 + q] : 0.0;
+        s = fma(Gp[(long long)max(j, 0) * ldp + tid], c, s);
       }
       T[tid * E2_CB + t] = s;
     }
